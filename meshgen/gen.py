@@ -1,0 +1,306 @@
+"""Seeded point sets and their Delaunay triangulations as half-edge arrays.
+
+Layout of a triangulation (shared by every consumer):
+  xy      float64 [V, 2]   vertex coordinates
+  origin  int32   [H]      origin vertex of half-edge h; triangle t owns h = 3t, 3t+1, 3t+2 (CCW)
+  next    int32   [H]      next[3t+i] = 3t + (i+1) % 3
+  twin    int32   [H]      opposite half-edge of the same edge, -1 on the hull
+
+Point recipe common to every workload: draw FP64 points with numpy's PCG64
+generator, snap them to the lattice of multiples of 2^-28 in [0, 1] (so the
+triangulator's predicates are exact in integer arithmetic), drop exact
+duplicates keeping the first occurrence, number the vertices in Morton order
+of their lattice coordinates, triangulate, then rotate each triangle to start
+at its smallest vertex id and sort triangles by their first two vertex ids.
+The resulting arrays depend only on the point set (for points in general
+position the Delaunay triangulation is unique).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+import threading
+from dataclasses import dataclass, field
+
+import numpy as np
+
+LATTICE_BITS = 28
+_SCALE = float(1 << LATTICE_BITS)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "delaunay.cpp")
+_LIB = os.path.join(_HERE, "libmeshgen.so")
+_lib = None
+_lib_lock = threading.Lock()
+
+
+def build_native(force: bool = False) -> str:
+    """Compile the native triangulator (g++, host only)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _native():
+    global _lib
+    with _lib_lock:
+        if _lib is None:
+            if not os.path.exists(_LIB):
+                build_native()
+            lib = ctypes.CDLL(_LIB)
+            lib.mg_delaunay_run.restype = ctypes.c_void_p
+            lib.mg_delaunay_run.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                            ctypes.POINTER(ctypes.c_int64),
+                                            ctypes.POINTER(ctypes.c_int32)]
+            lib.mg_delaunay_fetch.restype = None
+            lib.mg_delaunay_fetch.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+            lib.mg_delaunay_free.restype = None
+            lib.mg_delaunay_free.argtypes = [ctypes.c_void_p]
+            _lib = lib
+    return _lib
+
+
+@dataclass
+class Mesh:
+    xy: np.ndarray          # float64 [V, 2]
+    origin: np.ndarray      # int32 [H]
+    twin: np.ndarray        # int32 [H]
+    next: np.ndarray        # int32 [H]
+    lattice: np.ndarray | None = None   # int64 [V, 2] lattice coordinates (None for hand meshes)
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_vertices(self) -> int:
+        return int(self.xy.shape[0])
+
+    @property
+    def n_halfedges(self) -> int:
+        return int(self.origin.shape[0])
+
+    @property
+    def n_tri(self) -> int:
+        return self.n_halfedges // 3
+
+    def nbytes(self) -> int:
+        return self.xy.nbytes + self.origin.nbytes + self.twin.nbytes + self.next.nbytes
+
+
+def _grouped_next(n_he: int) -> np.ndarray:
+    h = np.arange(n_he, dtype=np.int64)
+    return (h - h % 3 + (h + 1) % 3).astype(np.int32)
+
+
+def _part1by1(x: np.ndarray) -> np.ndarray:
+    x = x.astype(np.uint64) & np.uint64(0xFFFFFFFF)
+    x = (x | (x << np.uint64(16))) & np.uint64(0x0000FFFF0000FFFF)
+    x = (x | (x << np.uint64(8))) & np.uint64(0x00FF00FF00FF00FF)
+    x = (x | (x << np.uint64(4))) & np.uint64(0x0F0F0F0F0F0F0F0F)
+    x = (x | (x << np.uint64(2))) & np.uint64(0x3333333333333333)
+    x = (x | (x << np.uint64(1))) & np.uint64(0x5555555555555555)
+    return x
+
+
+def snap(points: np.ndarray) -> np.ndarray:
+    """FP64 points in [0,1]^2 -> int64 lattice coordinates in [0, 2^28]."""
+    q = np.rint(np.asarray(points, dtype=np.float64) * _SCALE)
+    return np.clip(q, 0, _SCALE).astype(np.int64)
+
+
+def mesh_from_points(points: np.ndarray, meta: dict | None = None) -> Mesh:
+    """Snap, deduplicate, Morton-number and Delaunay-triangulate a point set."""
+    lat = snap(points)
+    code = (_part1by1(lat[:, 0]) << np.uint64(1)) | _part1by1(lat[:, 1])
+    order = np.argsort(code, kind="stable")
+    code_s = code[order]
+    keep = np.ones(order.shape[0], dtype=bool)
+    keep[1:] = code_s[1:] != code_s[:-1]
+    lat = np.ascontiguousarray(lat[order[keep]])
+    n = lat.shape[0]
+    X = np.ascontiguousarray(lat[:, 0])
+    Y = np.ascontiguousarray(lat[:, 1])
+    lib = _native()
+    ntri = ctypes.c_int64(0)
+    status = ctypes.c_int32(0)
+    h = lib.mg_delaunay_run(n, X.ctypes.data, Y.ctypes.data, ctypes.byref(ntri), ctypes.byref(status))
+    if status.value != 0 or not h:
+        raise RuntimeError(f"triangulation failed (status {status.value}, {n} points)")
+    T = ntri.value
+    origin = np.empty(3 * T, dtype=np.int32)
+    twin = np.empty(3 * T, dtype=np.int32)
+    lib.mg_delaunay_fetch(h, origin.ctypes.data, twin.ctypes.data)
+    lib.mg_delaunay_free(h)
+    xy = lat.astype(np.float64) / _SCALE
+    m = dict(meta or {})
+    m.update(n_points_drawn=int(points.shape[0]), n_duplicates=int(points.shape[0] - n))
+    return Mesh(xy=xy, origin=origin, twin=twin, next=_grouped_next(3 * T), lattice=lat, meta=m)
+
+
+def mesh_from_triangles(xy, tris, check_ccw: bool = True) -> Mesh:
+    """Hand-built mesh: triangles given as vertex triples, kept in the given
+    order and rotation (so half-edge indices are exactly 3t+i)."""
+    xy = np.asarray(xy, dtype=np.float64).reshape(-1, 2)
+    tris = np.asarray(tris, dtype=np.int64).reshape(-1, 3)
+    T = tris.shape[0]
+    V = xy.shape[0]
+    origin = tris.reshape(-1).astype(np.int32)
+    nxt = _grouped_next(3 * T)
+    a = origin.astype(np.int64)
+    b = origin[nxt].astype(np.int64)
+    key = a * V + b
+    rkey = b * V + a
+    if np.unique(key).shape[0] != key.shape[0]:
+        raise ValueError("a directed edge occurs twice (non-manifold or inconsistent orientation)")
+    srt = np.argsort(key)
+    pos = np.searchsorted(key[srt], rkey)
+    pos = np.minimum(pos, key.shape[0] - 1)
+    hit = key[srt][pos] == rkey
+    twin = np.where(hit, srt[pos], -1).astype(np.int32)
+    mesh = Mesh(xy=xy, origin=origin, twin=twin, next=nxt, lattice=None, meta={})
+    if check_ccw:
+        p0, p1, p2 = xy[tris[:, 0]], xy[tris[:, 1]], xy[tris[:, 2]]
+        o = (p1[:, 0] - p0[:, 0]) * (p2[:, 1] - p0[:, 1]) - (p1[:, 1] - p0[:, 1]) * (p2[:, 0] - p0[:, 0])
+        if np.any(o <= 0):
+            raise ValueError("triangles must be counter-clockwise")
+    return mesh
+
+
+# --------------------------------------------------------------------------
+# Workload recipes (all seeded)
+# --------------------------------------------------------------------------
+
+def _uniform(rng, n):
+    return rng.random((n, 2))
+
+
+def _clusters(rng, n, k, sigma):
+    centres = rng.random((k, 2))
+    per = [n // k + (1 if i < n % k else 0) for i in range(k)]
+    parts = [rng.normal(centres[i], sigma, size=(per[i], 2)) for i in range(k)]
+    return np.clip(np.concatenate(parts, axis=0), 0.0, 1.0)
+
+
+def config_points(name: str) -> np.ndarray:
+    """Point sets of the single-mesh workloads.
+
+    uniform10k : 10,000 points uniform in [0,1]^2 (seed 1)
+    mixed1m    : 500,000 uniform + 8 Gaussian clusters of 62,500 (sigma 0.02),
+                 clipped to the square (seed 2)
+    grid10m    : 3163 x 3163 jittered grid, jitter uniform +-0.45 cell (seed 3)
+    Small variants for tests: uniform<N> (seed 1), mixed<N> (seed 2, same recipe
+    scaled), grid<g>x (g x g jittered grid, seed 3).
+    """
+    if name.startswith("uniform"):
+        n = _parse_count(name[len("uniform"):])
+        return _uniform(np.random.default_rng(1), n)
+    if name.startswith("mixed"):
+        n = _parse_count(name[len("mixed"):])
+        rng = np.random.default_rng(2)
+        u = _uniform(rng, n // 2)
+        c = _clusters(rng, n - n // 2, 8, 0.02)
+        return np.concatenate([u, c], axis=0)
+    if name.startswith("grid"):
+        spec = name[len("grid"):]
+        g = 3163 if spec == "10m" else int(spec.rstrip("x"))
+        rng = np.random.default_rng(3)
+        jit = rng.uniform(-0.45, 0.45, size=(g * g, 2))
+        j, i = np.divmod(np.arange(g * g, dtype=np.float64), g)
+        x = (i + 0.5 + jit[:, 0]) / g
+        y = (j + 0.5 + jit[:, 1]) / g
+        return np.stack([x, y], axis=1)
+    raise KeyError(name)
+
+
+def _parse_count(s: str) -> int:
+    s = s.lower()
+    mult = 1
+    if s.endswith("k"):
+        mult, s = 1000, s[:-1]
+    elif s.endswith("m"):
+        mult, s = 1000000, s[:-1]
+    return int(float(s) * mult)
+
+
+def config_mesh(name: str) -> Mesh:
+    pts = config_points(name)
+    return mesh_from_points(pts, meta={"workload": name})
+
+
+def batch_sizes(n_meshes: int = 2000, lo: float = 3.0, hi: float = 6.0, seed: int = 4) -> np.ndarray:
+    """Point counts of the batched workload: round(10^U(lo, hi)) (seed 4)."""
+    rng = np.random.default_rng(seed)
+    return np.rint(10.0 ** rng.uniform(lo, hi, size=n_meshes)).astype(np.int64)
+
+
+def batch_points(m: int, n: int) -> np.ndarray:
+    """Points of mesh m of the batched workload (seed 40000 + m)."""
+    return _uniform(np.random.default_rng(40_000 + m), int(n))
+
+
+def serve_requests(n_requests: int, rate: float, seed: int = 5, lo: float = 3.0,
+                   hi: float = math.log10(2e6)):
+    """Request stream of the serving workload: Poisson arrivals at `rate` per
+    second, sizes round(10^U(lo, hi)), each request uniform or 4-cluster
+    Gaussian (sigma 0.05) with probability 1/2. Returns a list of
+    (arrival_time_s, n_points, kind, seed)."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate, size=n_requests)
+    sizes = np.rint(10.0 ** rng.uniform(lo, hi, size=n_requests)).astype(np.int64)
+    kinds = rng.integers(0, 2, size=n_requests)
+    t = np.cumsum(gaps) - gaps[0]
+    return [(float(t[j]), int(sizes[j]), "cluster" if kinds[j] else "uniform", 50_000 + j)
+            for j in range(n_requests)]
+
+
+def request_points(n: int, kind: str, seed: int) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    if kind == "uniform":
+        return _uniform(rng, n)
+    return _clusters(rng, n, 4, 0.05)
+
+
+# --------------------------------------------------------------------------
+# Validation of the half-edge layout
+# --------------------------------------------------------------------------
+
+def validate(mesh: Mesh) -> dict:
+    """Check the layout contract; raises ValueError on the first violation.
+    Returns counts (T, h = hull edges, referenced vertices)."""
+    H = mesh.n_halfedges
+    V = mesh.n_vertices
+    if H % 3:
+        raise ValueError("n_halfedges % 3 != 0")
+    T = H // 3
+    if not np.array_equal(mesh.next, _grouped_next(H)):
+        raise ValueError("next is not grouped per triangle")
+    o = mesh.origin.astype(np.int64)
+    if o.size and (o.min() < 0 or o.max() >= V):
+        raise ValueError("origin out of range")
+    tw = mesh.twin.astype(np.int64)
+    if tw.size and (tw.min() < -1 or tw.max() >= H):
+        raise ValueError("twin out of range")
+    inner = np.nonzero(tw >= 0)[0]
+    if not np.array_equal(tw[tw[inner]], inner):
+        raise ValueError("twin is not an involution")
+    if np.any(tw[inner] == inner):
+        raise ValueError("twin maps a half-edge to itself")
+    nx = mesh.next.astype(np.int64)
+    if not np.array_equal(o[tw[inner]], o[nx[inner]]):
+        raise ValueError("twin endpoints do not match")
+    tri = o.reshape(T, 3)
+    if mesh.lattice is not None:
+        P = mesh.lattice
+        a, b, c = P[tri[:, 0]], P[tri[:, 1]], P[tri[:, 2]]
+        orient = (b[:, 0] - a[:, 0]) * (c[:, 1] - a[:, 1]) - (b[:, 1] - a[:, 1]) * (c[:, 0] - a[:, 0])
+    else:
+        P = mesh.xy
+        a, b, c = P[tri[:, 0]], P[tri[:, 1]], P[tri[:, 2]]
+        orient = (b[:, 0] - a[:, 0]) * (c[:, 1] - a[:, 1]) - (b[:, 1] - a[:, 1]) * (c[:, 0] - a[:, 0])
+    if np.any(orient <= 0):
+        raise ValueError("a triangle is not counter-clockwise")
+    h = int(np.count_nonzero(tw < 0))
+    nref = int(np.unique(o).shape[0])
+    return {"T": T, "hull_edges": h, "referenced_vertices": nref}

@@ -1,0 +1,165 @@
+"""Throughput benchmark of the terminal-edge-region mesher on one MI355X.
+
+One step = label -> build -> repair (polylla_mesh) over the resident 10M-point
+jittered-grid Delaunay mesh (inputs in HBM before timing starts, outputs at
+worst-case capacity). Prints ONE JSON line on stdout; progress goes to stderr.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload grid10m]
+                  [--no-cpu] [--calib-copy-mb M]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "triangles/sec (label+build+repair) at 10M pts; batched vs per-mesh launch; p99"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(kernel: str, n: dict) -> int:
+    """Compulsory bytes of one launch: every array element the kernel must
+    read or write, counted once (see the data-layout section of the design doc)."""
+    V, T, R, F, S, Sp = n["V"], n["T"], n["R"], n["F"], n["S"], n["Sp"]
+    table = {
+        # origin 12T + xy 16V read, Max 1T + vtx clear 1V written
+        "k_longest": 13 * T + 17 * V,
+        # twin 12T + Max 1T read, labels 3T + 1T and the seed list 4R written
+        "k_label": 17 * T + 4 * R,
+        # labels 3T + twin 12T + origin 12T + seed list 4R read; staged cycles
+        # 4Sp and five per-polygon words 20R written
+        "k_walk": 27 * T + 24 * R + 4 * Sp,
+        # staged cycles 4S + per-polygon words 28R read; verts 4S + offsets 4F written
+        "k_emit": 8 * S + 28 * R + 4 * F,
+        # two per-polygon counts read, two offsets written
+        "k_scan_polys": 16 * R,
+    }
+    return table.get(kernel, 0)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="grid10m")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); multi-GPU runs are not "
+              "part of this build: meshes shard without communication, see DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from meshgen.gen import config_mesh
+    from paper_2204_05438_amd import lib
+
+    t0 = time.time()
+    mesh = config_mesh(args.workload)
+    log(f"generated {args.workload}: {mesh.n_vertices} vertices, {mesh.n_tri} triangles in {time.time() - t0:.1f}s")
+
+    dev = torch.device("cuda:0")
+    ctx = lib.Context(0)
+    tri = lib.Tri.from_mesh(mesh, device=dev)
+    labels = lib.Labels.empty(tri)
+    out = lib.Polys.empty(tri, with_start=True)
+    ctx.reserve(tri.n_halfedges, tri.n_vertices)
+    torch.cuda.synchronize()
+    log("inputs resident on the device")
+
+    if args.calib_copy_mb:
+        nb = args.calib_copy_mb << 20
+        src = torch.empty(nb // 4, dtype=torch.int32, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy of {args.calib_copy_mb} MiB done")
+
+    for _ in range(args.warmup):
+        ctx.mesh(tri, labels, out)
+    ctx.status()
+    stats = ctx.stats()
+    F, S = (int(x) for x in out.counts.tolist())
+    log(f"warmup done: {stats}, F={F}, S={S}")
+
+    stream = torch.cuda.current_stream()
+    ctx.profile(True)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        ctx.mesh(tri, labels, out)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms_total = ev0.elapsed_time(ev1)
+    ctx.status()
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    ms_step = ms_total / args.steps
+    T = mesh.n_tri
+    value = T / (ms_step / 1e3)
+    log(f"{args.steps} steps: {ms_step:.3f} ms/step, {value:.4g} triangles/s")
+    for k, (ms, nlaunch) in sorted(prof.items(), key=lambda kv: -kv[1][0]):
+        log(f"  {k:14s} {ms / max(nlaunch, 1) * 1e3:10.1f} us/launch  ({nlaunch} launches)")
+
+    counts = {"V": mesh.n_vertices, "T": T, "R": stats["seeds"], "F": F, "S": S, "Sp": T + 2 * stats["seeds"]}
+    dominant = max(prof.items(), key=lambda kv: kv[1][0])[0]
+    dom_ms = prof[dominant][0] / prof[dominant][1]
+    dom_bytes = algorithmic_bytes(dominant, counts)
+    achieved = dom_bytes / (dom_ms / 1e3) / 1e9 if dom_bytes else 0.0
+    roofline = {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "avg_launch_us": round(dom_ms * 1e3, 1), "algorithmic_bytes": dom_bytes}
+    per_kernel = {k: {"us_per_launch": round(ms / n * 1e3, 1),
+                      "algorithmic_GBps": round(algorithmic_bytes(k, counts) / (ms / n / 1e3) / 1e9, 1)}
+                  for k, (ms, n) in prof.items()}
+
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        log("timing the CPU oracle on the same mesh (1 thread)")
+        c0 = time.perf_counter()
+        ref = oracle.oracle_on(mesh)
+        c1 = time.perf_counter()
+        cpu = {"value": round(T / (c1 - c0), 1), "unit": "triangles/s", "cores": 1, "kind": "oracle",
+               "sample": f"the full {args.workload} mesh ({T} triangles), one run, label+build+repair",
+               "seconds": round(c1 - c0, 2)}
+        # the timed GPU output is the oracle's output
+        off, verts, _ = (x.cpu().numpy() for x in out.trimmed())
+        cpu["gpu_output_identical"] = bool(np.array_equal(off, ref["offsets"]) and
+                                           np.array_equal(verts, ref["verts"]))
+        log(f"oracle: {c1 - c0:.1f}s, identical output: {cpu['gpu_output_identical']}")
+
+    line = {
+        "metric": METRIC, "value": round(value, 1), "unit": "triangles/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64+i32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: jittered 3163x3163 grid in [0,1]^2 (seed 3), Delaunay, "
+                               f"{mesh.n_vertices} vertices, {T} triangles, one mesh per step",
+                   "polygons": F, "seeds": stats["seeds"], "general_path": stats["general_path"],
+                   "tips": stats["tips"], "splits": stats["splits"]},
+        "roofline": roofline,
+        "kernels": per_kernel,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,181 @@
+/*
+ * polylla.h -- C ABI of the MI355X (gfx950) terminal-edge-region polygonal
+ * mesher: label -> build -> repair, after Salinas, Ojeda, Hitschfeld and
+ * Ortiz-Bernardin, "GPU parallel algorithm for the generation of polygonal
+ * meshes based on terminal-edge regions" (SIAM IMR 2022, arXiv 2204.05438).
+ *
+ * Conventions for every call below
+ * ---------------------------------
+ *  - Pointers inside polylla_tri / polylla_labels / polylla_polys are DEVICE
+ *    pointers owned by the caller; the library never frees or reallocates them.
+ *  - Calls enqueue work on `stream` and return without waiting. Host-side
+ *    argument errors are returned immediately; errors found by the kernels
+ *    (bad indices, exhausted capacity) are recorded in the context and read
+ *    with polylla_status(), which waits for the stream.
+ *  - Device scratch is owned by the context and grows on demand (hipMalloc on
+ *    the first call at a larger size; see polylla_reserve()). Calls sharing a
+ *    context must be ordered on one stream; use one context per stream.
+ *  - Output is deterministic: the same input gives byte-identical output.
+ *
+ * Input triangulation (the paper's Vertex, Triangle and Neighbor arrays, in
+ * half-edge form; section "Data structure")
+ * ----------------------------------------------------------------------
+ *  half-edge h belongs to triangle t = h / 3 and runs from origin[h] to
+ *  origin[next[h]]; next[3t+i] == 3t + (i+1) % 3 (grouped layout; the hot path
+ *  relies on it and does not read `next`, polylla_validate() checks it);
+ *  triangles are counter-clockwise; twin[h] is the opposite half-edge of the
+ *  same edge, -1 on the boundary. n_halfedges must be a multiple of 3 and below
+ *  2^31; vertex ids below 2^31.
+ *
+ * Labels (Label phase, Algorithm 2; Reparation phase, Algorithm 4)
+ * ----------------------------------------------------------------
+ *  he[h]  bit 1 LONGEST  : h is the longest edge of its triangle. Squared
+ *                           lengths in IEEE binary64 without contraction; equal
+ *                           lengths are ordered by the edge key min(h, twin[h])
+ *                           (h on the boundary), smaller key wins.
+ *         bit 2 FRONTIER : boundary edge, or longest edge of neither triangle,
+ *                           or an edge opened by the repair.
+ *         bit 4 TERMINAL : longest edge of both triangles, or a boundary edge
+ *                           that is the longest edge of its triangle.
+ *         bit 8 BORDER   : twin[h] == -1.
+ *         bit 16 BARRIER : frontier edge whose two half-edges lie on the same
+ *                           polygon before repair (set by build / repair / mesh).
+ *         bit 32 REPAIRED: frontier edge opened by the repair.
+ *  tri[t] bit 1 SEED     : t is the lower-index triangle of a terminal edge (or
+ *                           the triangle of a boundary terminal edge).
+ *  vtx[v] bit 1 TIP      : v is a barrier-edge tip before repair.
+ *
+ * Polygons (the paper's Mesh and Position arrays, as CSR)
+ * -------------------------------------------------------
+ *  polygon p has vertices verts[offsets[p] .. offsets[p+1]), counter-clockwise,
+ *  rotated to its lexicographically smallest vertex sequence (so it starts at
+ *  its smallest vertex id). start[p] is the half-edge leaving verts[offsets[p]]
+ *  along the cycle. Polygons are listed in increasing seed-triangle order; the
+ *  pieces of a repaired polygon take its place, ordered by their (first,
+ *  second) vertex. counts[0] = number of polygons F, counts[1] = sum of their
+ *  lengths (= n_tri + 2F). cap_polys >= n_tri and cap_verts >= 3 * n_tri are
+ *  always enough; smaller capacities are checked on the device (ECAPACITY).
+ *
+ * Repair reading (Algorithm 4 leaves it open): the tips of a polygon are
+ * handled in increasing vertex id. At tip v with barrier half-edge c0 (leaving
+ * v) and degree d, the edge opened is c_{floor(d/2)} where c_{j+1} =
+ * next[twin[c_j]] (clockwise about v). A tip whose vertex already lies on an
+ * edge opened for a smaller tip is no longer a tip and is skipped.
+ */
+#ifndef POLYLLA_H
+#define POLYLLA_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* return codes */
+#define POLYLLA_OK 0
+#define POLYLLA_EINVAL (-1)    /* null pointer, negative size, size limit exceeded */
+#define POLYLLA_ELAYOUT (-2)   /* n_halfedges % 3 != 0 or next not grouped */
+#define POLYLLA_ETOPO (-3)     /* index out of range, twin not an involution (device) */
+#define POLYLLA_ECAPACITY (-4) /* output capacity too small (device) */
+#define POLYLLA_ENOMEM (-5)    /* scratch allocation failed */
+#define POLYLLA_EHIP (-6)      /* a HIP runtime call failed */
+#define POLYLLA_EDEGEN (-7)    /* walk bound exceeded: input not a valid triangulation */
+#define POLYLLA_EINTERNAL (-8) /* a device-wide scan did not complete (library bug) */
+
+/* label bits */
+#define POLYLLA_LONGEST 1u
+#define POLYLLA_FRONTIER 2u
+#define POLYLLA_TERMINAL 4u
+#define POLYLLA_BORDER 8u
+#define POLYLLA_BARRIER 16u
+#define POLYLLA_REPAIRED 32u
+#define POLYLLA_SEED 1u
+#define POLYLLA_TIP 1u
+
+typedef struct polylla_ctx polylla_ctx;
+
+typedef struct {
+  int64_t n_vertices;
+  int64_t n_halfedges;
+  const double *xy;       /* [2 * n_vertices], x0 y0 x1 y1 ... */
+  const int32_t *twin;    /* [n_halfedges], -1 on the boundary */
+  const int32_t *next;    /* [n_halfedges], grouped (see above); may be NULL except for polylla_validate */
+  const int32_t *origin;  /* [n_halfedges] */
+} polylla_tri;
+
+typedef struct {
+  uint8_t *he;   /* [n_halfedges] */
+  uint8_t *tri;  /* [n_halfedges / 3] */
+  uint8_t *vtx;  /* [n_vertices] */
+} polylla_labels;
+
+typedef struct {
+  int32_t *offsets;   /* [cap_polys + 1] */
+  int32_t *verts;     /* [cap_verts] */
+  int32_t *start;     /* [cap_polys]; may be NULL for polylla_mesh outputs */
+  int64_t *counts;    /* [2] device: F, sum of lengths */
+  int64_t cap_polys;
+  int64_t cap_verts;
+} polylla_polys;
+
+/* Create a context bound to HIP device `device`. */
+int polylla_ctx_create(polylla_ctx **out, int device);
+/* Release a context and its scratch (waits for the device). */
+void polylla_ctx_destroy(polylla_ctx *ctx);
+/* Pre-allocate scratch for meshes up to n_halfedges / n_vertices (optional). */
+int polylla_reserve(polylla_ctx *ctx, int64_t n_halfedges, int64_t n_vertices);
+
+/* Label phase (Algorithm 2: LabelMax, LabelSeed, LabelFrontier): writes
+ * LONGEST, FRONTIER, TERMINAL, BORDER for every half-edge, SEED for every
+ * triangle and clears vtx. BARRIER, REPAIRED and TIP are left clear. */
+int polylla_label(polylla_ctx *ctx, const polylla_tri *tri, polylla_labels *labels, hipStream_t stream);
+
+/* Traversal phase (Algorithm 3 with PolyConstruction): one polygon per seed,
+ * before repair. Reads the labels written by polylla_label; adds BARRIER and
+ * TIP. `out->start` must not be NULL (polylla_repair needs it). */
+int polylla_build(polylla_ctx *ctx, const polylla_tri *tri, polylla_labels *labels,
+                  polylla_polys *out, hipStream_t stream);
+
+/* Reparation phase (Algorithm 4, run until no barrier-edge tip remains):
+ * `in` must be the output of polylla_build on the same labels, which must not
+ * have been repaired before. Adds FRONTIER | REPAIRED on the opened edges.
+ * `in` and `out` must not overlap. */
+int polylla_repair(polylla_ctx *ctx, const polylla_tri *tri, polylla_labels *labels,
+                   const polylla_polys *in, polylla_polys *out, hipStream_t stream);
+
+/* Algorithm 1 in one call: label, build and repair. `labels` may be NULL
+ * (then labels live in context scratch). Same result as the three calls. */
+int polylla_mesh(polylla_ctx *ctx, const polylla_tri *tri, polylla_labels *labels,
+                 polylla_polys *out, hipStream_t stream);
+
+/* Full input check on the device (layout of next, index ranges, twin
+ * involution and endpoints). Waits for the stream; returns the first error. */
+int polylla_validate(polylla_ctx *ctx, const polylla_tri *tri, hipStream_t stream);
+
+/* Waits for `stream` and returns the first device-side error recorded by the
+ * context since the previous polylla_status call (then clears it). */
+int polylla_status(polylla_ctx *ctx, hipStream_t stream);
+
+/* Diagnostics of the last build / repair / mesh call, after polylla_status:
+ * out[0] seeds, out[1] polygons routed to the general path, out[2] tips,
+ * out[3] opened edges. Returns the number of values written (<= n). */
+int polylla_stats(polylla_ctx *ctx, int64_t *out, int n);
+
+/* Per-kernel GPU timing with HIP events, for benchmarks (off by default).
+ * polylla_profile(ctx, 1) clears earlier records and records an event pair on
+ * the call's stream around every kernel launched by later calls (up to 8192
+ * launches); polylla_profile(ctx, 0) stops recording. polylla_profile_read
+ * waits for the device and fills, for up to n kernels, the kernel name
+ * (NUL-terminated, 32 bytes per entry in `names`), the summed milliseconds and
+ * the number of launches; it returns the number of kernels written. */
+int polylla_profile(polylla_ctx *ctx, int enable);
+int polylla_profile_read(polylla_ctx *ctx, char *names, double *ms, int64_t *launches, int n);
+
+const char *polylla_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* POLYLLA_H */

@@ -1,0 +1,445 @@
+// Host side of libpolylla: contexts, scratch, argument checks and the kernel
+// sequence of every entry point declared in include/polylla.h.
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "common.h"
+
+namespace polylla {
+
+__global__ void k_reset(Counters*, uint64_t*, int64_t, const int64_t*);
+__global__ void k_longest(int64_t, int64_t, const double*, const int32_t*, const int32_t*, uint8_t*, uint8_t*,
+                          Counters*);
+template <bool COMPUTE>
+__global__ void k_label(int64_t, const int32_t*, const uint8_t*, uint8_t*, uint8_t*, int32_t*, uint64_t*,
+                        Counters*, bool);
+template <bool FROM_SEEDS>
+__global__ void k_walk(const int32_t*, int32_t, const int32_t*, const int32_t*, const uint8_t*, int32_t*, int64_t,
+                       PolyState, int32_t*, Counters*);
+template <bool REPAIR>
+__global__ void k_general(const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*, uint8_t*,
+                          uint8_t*, int32_t*, int64_t, int32_t*, int64_t, PolyState, const int32_t*, Counters*);
+__global__ void k_scan_polys(PolyState, int32_t*, int32_t*, uint64_t*, int32_t*, int64_t*, int64_t, int64_t,
+                             Counters*);
+__global__ void k_emit(PolyState, const int32_t*, const int32_t*, const int32_t*, const int32_t*, int32_t*,
+                       int32_t*, int32_t*, int64_t, int64_t, Counters*);
+__global__ void k_validate(int64_t, int64_t, const int32_t*, const int32_t*, const int32_t*, Counters*);
+
+}  // namespace polylla
+
+using namespace polylla;
+
+struct polylla_ctx {
+  int device = 0;
+  Counters* cnt = nullptr;
+  int64_t cap_t = 0;  // triangles
+  int64_t cap_v = 0;  // vertices
+  uint8_t* lg = nullptr;
+  int32_t* seeds = nullptr;
+  int32_t* deferred = nullptr;
+  int32_t* poly_arrays = nullptr;  // 7 arrays of cap_t ints
+  int32_t* stage = nullptr;
+  int64_t stage_cap = 0;
+  int32_t* arena = nullptr;
+  int64_t arena_cap = 0;
+  uint64_t* status = nullptr;
+  int64_t n_status = 0;
+  uint8_t* he_s = nullptr;
+  uint8_t* tri_s = nullptr;
+  uint8_t* vtx_s = nullptr;
+  Counters last{};
+  // event profiling
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  struct Rec {
+    int kernel;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+};
+
+namespace {
+
+constexpr int64_t kTile = 1024;
+constexpr size_t kMaxProfiled = 8192;
+
+enum KernelId { KR_RESET, KR_LONGEST, KR_LABEL, KR_COMPACT, KR_WALK, KR_GENERAL, KR_SCAN, KR_EMIT, KR_VALIDATE, KR_N };
+const char* kKernelNames[KR_N] = {"k_reset", "k_longest", "k_label", "k_compact_seeds", "k_walk",
+                                  "k_general", "k_scan_polys", "k_emit", "k_validate"};
+
+// Event pair around one kernel launch when profiling is on.
+struct Prof {
+  polylla_ctx* c;
+  hipStream_t s;
+  int id;
+  hipEvent_t b = nullptr;
+  Prof(polylla_ctx* c_, hipStream_t s_, int id_) : c(c_), s(s_), id(id_) {
+    if (!c->prof || c->recs.size() >= kMaxProfiled || c->ev_pool.size() < 2 * (c->recs.size() + 1)) return;
+    hipEvent_t a = c->ev_pool[2 * c->recs.size()];
+    b = c->ev_pool[2 * c->recs.size() + 1];
+    (void)hipEventRecord(a, s);
+    c->recs.push_back({id, a, b});
+  }
+  ~Prof() {
+    if (b) (void)hipEventRecord(b, s);
+  }
+};
+
+template <typename T>
+int dalloc(T** p, int64_t n) {
+  *p = nullptr;
+  if (n <= 0) n = 1;
+  if (hipMalloc((void**)p, sizeof(T) * (size_t)n) != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return POLYLLA_ENOMEM;
+  }
+  return POLYLLA_OK;
+}
+
+template <typename T>
+void dfree(T** p) {
+  if (*p) (void)hipFree(*p);
+  *p = nullptr;
+}
+
+void free_scratch(polylla_ctx* c) {
+  dfree(&c->lg);
+  dfree(&c->seeds);
+  dfree(&c->deferred);
+  dfree(&c->poly_arrays);
+  dfree(&c->stage);
+  dfree(&c->arena);
+  dfree(&c->status);
+  dfree(&c->he_s);
+  dfree(&c->tri_s);
+  dfree(&c->vtx_s);
+  c->cap_t = c->cap_v = 0;
+}
+
+int ensure(polylla_ctx* c, int64_t nt, int64_t nv) {
+  if (nt <= c->cap_t && nv <= c->cap_v && c->lg) return POLYLLA_OK;
+  int64_t T = std::max(nt, c->cap_t), V = std::max(nv, c->cap_v);
+  if (hipSetDevice(c->device) != hipSuccess) return POLYLLA_EHIP;
+  (void)hipDeviceSynchronize();
+  free_scratch(c);
+  T = std::max<int64_t>(T, 1024);
+  V = std::max<int64_t>(V, 1024);
+  int rc = POLYLLA_OK;
+  const int64_t ntiles = (T + kTile - 1) / kTile + 1;
+  c->stage_cap = 3 * T + 64;
+  c->arena_cap = 6 * T + 4096;
+  c->n_status = 2 * ntiles;
+  if ((rc = dalloc(&c->lg, T)) || (rc = dalloc(&c->seeds, T)) || (rc = dalloc(&c->deferred, T)) ||
+      (rc = dalloc(&c->poly_arrays, 7 * T)) || (rc = dalloc(&c->stage, c->stage_cap)) ||
+      (rc = dalloc(&c->arena, c->arena_cap)) || (rc = dalloc(&c->status, c->n_status)) ||
+      (rc = dalloc(&c->he_s, 3 * T)) || (rc = dalloc(&c->tri_s, T)) || (rc = dalloc(&c->vtx_s, V))) {
+    free_scratch(c);
+    return rc;
+  }
+  c->cap_t = T;
+  c->cap_v = V;
+  return POLYLLA_OK;
+}
+
+PolyState poly_state(polylla_ctx* c) {
+  PolyState ps;
+  int32_t* b = c->poly_arrays;
+  ps.pstart = b;
+  ps.plen = b + c->cap_t;
+  ps.ppieces = b + 2 * c->cap_t;
+  ps.prec = b + 3 * c->cap_t;
+  ps.pstage = b + 4 * c->cap_t;
+  return ps;
+}
+int32_t* poly_off(polylla_ctx* c) { return c->poly_arrays + 5 * c->cap_t; }
+int32_t* vert_off(polylla_ctx* c) { return c->poly_arrays + 6 * c->cap_t; }
+
+int check_tri(const polylla_tri* t) {
+  if (!t) return POLYLLA_EINVAL;
+  if (t->n_vertices < 0 || t->n_halfedges < 0) return POLYLLA_EINVAL;
+  if (t->n_halfedges % 3) return POLYLLA_ELAYOUT;
+  if (t->n_halfedges >= ((int64_t)1 << 31) - 64 || t->n_vertices >= ((int64_t)1 << 31)) return POLYLLA_EINVAL;
+  if (t->n_halfedges > 0 && (!t->xy || !t->twin || !t->origin)) return POLYLLA_EINVAL;
+  return POLYLLA_OK;
+}
+
+int check_polys(const polylla_polys* p, bool need_start) {
+  if (!p || !p->offsets || !p->counts) return POLYLLA_EINVAL;
+  if (p->cap_polys < 0 || p->cap_verts < 0) return POLYLLA_EINVAL;
+  if (p->cap_verts > 0 && !p->verts) return POLYLLA_EINVAL;
+  if (need_start && !p->start) return POLYLLA_EINVAL;
+  return POLYLLA_OK;
+}
+
+int launched() { return hipGetLastError() == hipSuccess ? POLYLLA_OK : POLYLLA_EHIP; }
+
+int grid_for(int64_t n, int64_t per_block, int64_t cap) {
+  int64_t g = (n + per_block - 1) / per_block;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(g, cap));
+}
+
+void reset(polylla_ctx* c, hipStream_t s, const int64_t* n_from) {
+  Prof p(c, s, KR_RESET);
+  hipLaunchKernelGGL(k_reset, dim3(grid_for(c->n_status, 256, 4096)), dim3(256), 0, s, c->cnt, c->status,
+                     c->n_status, n_from);
+}
+
+int run_label(polylla_ctx* c, const polylla_tri* t, uint8_t* he, uint8_t* tri, uint8_t* vtx, hipStream_t s) {
+  const int64_t T = t->n_halfedges / 3;
+  {
+    Prof p(c, s, KR_LONGEST);
+    hipLaunchKernelGGL(k_longest, dim3(grid_for(std::max(T, t->n_vertices), 256, 1 << 20)), dim3(256), 0, s, T,
+                       t->n_vertices, t->xy, t->origin, t->twin, c->lg, vtx, c->cnt);
+  }
+  if (T > 0) {
+    Prof p(c, s, KR_LABEL);
+    // 16-byte loads of twin and 4-byte label stores need aligned arrays
+    const bool vec = ((uintptr_t)t->twin % 16 == 0) && ((uintptr_t)he % 4 == 0) && ((uintptr_t)tri % 4 == 0);
+    hipLaunchKernelGGL(k_label<true>, dim3((T + kTile - 1) / kTile), dim3(256), 0, s, T, t->twin, c->lg, he, tri,
+                       c->seeds, c->status, c->cnt, vec);
+  }
+  return launched();
+}
+
+// Walk + general path + scan + emit over the list `list` of seeds (from_seeds)
+// or start half-edges; n (device) polygons already in cnt->n_seeds.
+int run_build(polylla_ctx* c, const polylla_tri* t, const int32_t* list, bool from_seeds, bool repair,
+              uint8_t* he, uint8_t* vtx, polylla_polys* out, hipStream_t s) {
+  const int64_t T = t->n_halfedges / 3;
+  const int32_t nhe = (int32_t)t->n_halfedges;
+  PolyState ps = poly_state(c);
+  {
+    Prof p(c, s, KR_WALK);
+    const int gw = grid_for(T, 1024, 1 << 16);
+    if (from_seeds)
+      hipLaunchKernelGGL(k_walk<true>, dim3(gw), dim3(256), 0, s, list, nhe, t->twin, t->origin, he, c->stage,
+                         c->stage_cap, ps, c->deferred, c->cnt);
+    else
+      hipLaunchKernelGGL(k_walk<false>, dim3(gw), dim3(256), 0, s, list, nhe, t->twin, t->origin, he, c->stage,
+                         c->stage_cap, ps, c->deferred, c->cnt);
+  }
+  {
+    Prof p(c, s, KR_GENERAL);
+    const int gg = 2048;
+    if (repair)
+      hipLaunchKernelGGL(k_general<true>, dim3(gg), dim3(64), 0, s, list, from_seeds, nhe, t->n_vertices,
+                         t->twin, t->origin, he, vtx, c->stage, c->stage_cap, c->arena, c->arena_cap, ps,
+                         c->deferred, c->cnt);
+    else
+      hipLaunchKernelGGL(k_general<false>, dim3(gg), dim3(64), 0, s, list, from_seeds, nhe, t->n_vertices,
+                         t->twin, t->origin, he, vtx, c->stage, c->stage_cap, c->arena, c->arena_cap, ps,
+                         c->deferred, c->cnt);
+  }
+  {
+    Prof p(c, s, KR_SCAN);
+    const int64_t ntiles = (T + kTile - 1) / kTile + 1;
+    hipLaunchKernelGGL(k_scan_polys, dim3(ntiles), dim3(256), 0, s, ps, poly_off(c), vert_off(c),
+                       c->status + c->n_status / 2, out->offsets, out->counts, out->cap_polys, out->cap_verts,
+                       c->cnt);
+  }
+  {
+    Prof p(c, s, KR_EMIT);
+    hipLaunchKernelGGL(k_emit, dim3(grid_for(T, 256, 1 << 16)), dim3(256), 0, s, ps, poly_off(c), vert_off(c),
+                       c->stage, c->arena, out->offsets, out->verts, out->start, out->cap_polys, out->cap_verts,
+                       c->cnt);
+  }
+  return launched();
+}
+
+}  // namespace
+
+extern "C" {
+
+int polylla_ctx_create(polylla_ctx** out, int device) {
+  if (!out) return POLYLLA_EINVAL;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return POLYLLA_EINVAL;
+  if (hipSetDevice(device) != hipSuccess) return POLYLLA_EHIP;
+  polylla_ctx* c = new polylla_ctx();
+  c->device = device;
+  if (dalloc(&c->cnt, 1)) {
+    delete c;
+    return POLYLLA_ENOMEM;
+  }
+  if (hipMemset(c->cnt, 0, sizeof(Counters)) != hipSuccess) {
+    dfree(&c->cnt);
+    delete c;
+    return POLYLLA_EHIP;
+  }
+  *out = c;
+  return POLYLLA_OK;
+}
+
+void polylla_ctx_destroy(polylla_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  free_scratch(c);
+  dfree(&c->cnt);
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  delete c;
+}
+
+int polylla_reserve(polylla_ctx* c, int64_t n_halfedges, int64_t n_vertices) {
+  if (!c || n_halfedges < 0 || n_vertices < 0) return POLYLLA_EINVAL;
+  return ensure(c, n_halfedges / 3, n_vertices);
+}
+
+int polylla_label(polylla_ctx* c, const polylla_tri* t, polylla_labels* l, hipStream_t s) {
+  if (!c || !l) return POLYLLA_EINVAL;
+  int rc = check_tri(t);
+  if (rc) return rc;
+  const int64_t T = t->n_halfedges / 3;
+  if (T > 0 && (!l->he || !l->tri)) return POLYLLA_EINVAL;
+  if ((rc = ensure(c, T, t->n_vertices))) return rc;
+  if (hipSetDevice(c->device) != hipSuccess) return POLYLLA_EHIP;
+  reset(c, s, nullptr);
+  return run_label(c, t, l->he, l->tri, l->vtx, s);
+}
+
+int polylla_build(polylla_ctx* c, const polylla_tri* t, polylla_labels* l, polylla_polys* out, hipStream_t s) {
+  if (!c || !l) return POLYLLA_EINVAL;
+  int rc = check_tri(t);
+  if (rc) return rc;
+  if ((rc = check_polys(out, true))) return rc;
+  const int64_t T = t->n_halfedges / 3;
+  if (T > 0 && (!l->he || !l->tri || !l->vtx)) return POLYLLA_EINVAL;
+  if ((rc = ensure(c, T, t->n_vertices))) return rc;
+  if (hipSetDevice(c->device) != hipSuccess) return POLYLLA_EHIP;
+  reset(c, s, nullptr);
+  if (T > 0) {
+    Prof p(c, s, KR_COMPACT);
+    hipLaunchKernelGGL(k_label<false>, dim3((T + kTile - 1) / kTile), dim3(256), 0, s, T, t->twin, c->lg, l->he,
+                       l->tri, c->seeds, c->status, c->cnt, false);
+  }
+  return run_build(c, t, c->seeds, true, false, l->he, l->vtx, out, s);
+}
+
+int polylla_repair(polylla_ctx* c, const polylla_tri* t, polylla_labels* l, const polylla_polys* in,
+                   polylla_polys* out, hipStream_t s) {
+  if (!c || !l) return POLYLLA_EINVAL;
+  int rc = check_tri(t);
+  if (rc) return rc;
+  if ((rc = check_polys(in, true)) || (rc = check_polys(out, false))) return rc;
+  const int64_t T = t->n_halfedges / 3;
+  if (T > 0 && (!l->he || !l->vtx)) return POLYLLA_EINVAL;
+  if ((rc = ensure(c, T, t->n_vertices))) return rc;
+  if (hipSetDevice(c->device) != hipSuccess) return POLYLLA_EHIP;
+  reset(c, s, in->counts);
+  return run_build(c, t, in->start, false, true, l->he, l->vtx, out, s);
+}
+
+int polylla_mesh(polylla_ctx* c, const polylla_tri* t, polylla_labels* l, polylla_polys* out, hipStream_t s) {
+  if (!c) return POLYLLA_EINVAL;
+  int rc = check_tri(t);
+  if (rc) return rc;
+  if ((rc = check_polys(out, false))) return rc;
+  const int64_t T = t->n_halfedges / 3;
+  if ((rc = ensure(c, T, t->n_vertices))) return rc;
+  if (hipSetDevice(c->device) != hipSuccess) return POLYLLA_EHIP;
+  uint8_t* he = (l && l->he) ? l->he : c->he_s;
+  uint8_t* tri = (l && l->tri) ? l->tri : c->tri_s;
+  uint8_t* vtx = (l && l->vtx) ? l->vtx : c->vtx_s;
+  reset(c, s, nullptr);
+  if ((rc = run_label(c, t, he, tri, vtx, s))) return rc;
+  return run_build(c, t, c->seeds, true, true, he, vtx, out, s);
+}
+
+int polylla_validate(polylla_ctx* c, const polylla_tri* t, hipStream_t s) {
+  if (!c) return POLYLLA_EINVAL;
+  int rc = check_tri(t);
+  if (rc) return rc;
+  if (t->n_halfedges > 0 && !t->next) return POLYLLA_EINVAL;
+  if (hipSetDevice(c->device) != hipSuccess) return POLYLLA_EHIP;
+  hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, c->cnt, (uint64_t*)nullptr, (int64_t)0,
+                     (const int64_t*)nullptr);
+  Prof pv(c, s, KR_VALIDATE);
+  hipLaunchKernelGGL(k_validate, dim3(grid_for(t->n_halfedges, 256, 1 << 16)), dim3(256), 0, s, t->n_halfedges,
+                     t->n_vertices, t->twin, t->next, t->origin, c->cnt);
+  if ((rc = launched())) return rc;
+  return polylla_status(c, s);
+}
+
+int polylla_status(polylla_ctx* c, hipStream_t s) {
+  if (!c) return POLYLLA_EINVAL;
+  if (hipSetDevice(c->device) != hipSuccess) return POLYLLA_EHIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return POLYLLA_EHIP;
+  Counters h;
+  if (hipMemcpy(&h, c->cnt, sizeof(Counters), hipMemcpyDeviceToHost) != hipSuccess) return POLYLLA_EHIP;
+  c->last = h;
+  if (h.error) {
+    int32_t zero = 0;
+    if (hipMemcpy(&c->cnt->error, &zero, sizeof(zero), hipMemcpyHostToDevice) != hipSuccess) return POLYLLA_EHIP;
+  }
+  return h.error;
+}
+
+int polylla_stats(polylla_ctx* c, int64_t* out, int n) {
+  if (!c || !out || n < 0) return POLYLLA_EINVAL;
+  const int64_t v[4] = {c->last.n_seeds, c->last.n_deferred, c->last.n_tips, c->last.n_splits};
+  int k = std::min(n, 4);
+  for (int i = 0; i < k; ++i) out[i] = v[i];
+  return k;
+}
+
+int polylla_profile(polylla_ctx* c, int enable) {
+  if (!c) return POLYLLA_EINVAL;
+  if (hipSetDevice(c->device) != hipSuccess) return POLYLLA_EHIP;
+  if (enable) {
+    (void)hipDeviceSynchronize();
+    while (c->ev_pool.size() < 2 * kMaxProfiled) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return POLYLLA_EHIP;
+      c->ev_pool.push_back(e);
+    }
+    c->recs.clear();
+  }
+  c->prof = enable != 0;
+  return POLYLLA_OK;
+}
+
+int polylla_profile_read(polylla_ctx* c, char* names, double* ms, int64_t* launches, int n) {
+  if (!c || n < 0 || (n > 0 && (!names || !ms || !launches))) return POLYLLA_EINVAL;
+  if (hipSetDevice(c->device) != hipSuccess) return POLYLLA_EHIP;
+  if (hipDeviceSynchronize() != hipSuccess) return POLYLLA_EHIP;
+  double sum[KR_N] = {0};
+  int64_t cnt[KR_N] = {0};
+  for (const auto& r : c->recs) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) return POLYLLA_EHIP;
+    sum[r.kernel] += t;
+    cnt[r.kernel] += 1;
+  }
+  int w = 0;
+  for (int k = 0; k < KR_N && w < n; ++k) {
+    if (!cnt[k]) continue;
+    strncpy(names + 32 * w, kKernelNames[k], 31);
+    names[32 * w + 31] = 0;
+    ms[w] = sum[k];
+    launches[w] = cnt[k];
+    ++w;
+  }
+  return w;
+}
+
+const char* polylla_strerror(int code) {
+  switch (code) {
+    case POLYLLA_OK: return "ok";
+    case POLYLLA_EINVAL: return "invalid argument";
+    case POLYLLA_ELAYOUT: return "half-edge layout: n_halfedges % 3 != 0 or next not grouped";
+    case POLYLLA_ETOPO: return "invalid topology: index out of range or twin inconsistent";
+    case POLYLLA_ECAPACITY: return "output capacity too small";
+    case POLYLLA_ENOMEM: return "device scratch allocation failed";
+    case POLYLLA_EHIP: return "HIP runtime error";
+    case POLYLLA_EDEGEN: return "walk bound exceeded (not a valid triangulation)";
+    case POLYLLA_EINTERNAL: return "internal error: device scan did not complete";
+    default: return "unknown error";
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,55 @@
+// Internal definitions shared by the HIP kernels and the host side of
+// libpolylla (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/polylla.h"
+
+#pragma clang fp contract(off)
+
+namespace polylla {
+
+constexpr uint8_t kLongest = POLYLLA_LONGEST;
+constexpr uint8_t kFrontier = POLYLLA_FRONTIER;
+constexpr uint8_t kTerminal = POLYLLA_TERMINAL;
+constexpr uint8_t kBorder = POLYLLA_BORDER;
+constexpr uint8_t kBarrier = POLYLLA_BARRIER;
+constexpr uint8_t kRepaired = POLYLLA_REPAIRED;
+constexpr uint8_t kSeed = POLYLLA_SEED;
+constexpr uint8_t kTip = POLYLLA_TIP;
+
+// Device-side counters and error word, one block per context (zeroed by the
+// first kernel of every call).
+struct Counters {
+  int32_t error;          // first error code (0 = none)
+  uint32_t tile_ticket[4];  // dynamic tile ids of the look-back scans
+  uint32_t n_seeds;       // R
+  uint32_t n_deferred;    // polygons handled by the general path
+  uint32_t n_tips;
+  uint32_t n_splits;
+  uint32_t stage_top;     // bump allocator of the staging buffer (ints)
+  uint32_t arena_top;     // bump allocator of the general-path arena (ints)
+  uint32_t pad[5];
+};
+
+// Per-polygon results of the walk / general path, in seed order.
+struct PolyState {
+  int32_t* pstart;   // canonical start half-edge (single-piece polygons)
+  int32_t* plen;     // total output vertices of the polygon (all pieces)
+  int32_t* ppieces;  // number of output polygons
+  int32_t* prec;     // arena offset of piece records, -1 for one piece
+  int32_t* pstage;   // staging offset of the vertex data
+};
+
+__device__ __forceinline__ int32_t he_next(int32_t h) {
+  int32_t r = h % 3;
+  return r == 2 ? h - 2 : h + 1;
+}
+
+__device__ __forceinline__ void set_error(Counters* c, int32_t code) {
+  atomicCAS(&c->error, 0, code);
+}
+
+}  // namespace polylla

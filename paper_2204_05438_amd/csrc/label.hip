@@ -1,0 +1,224 @@
+// Label phase (Algorithm 2 of the paper: LabelMax, LabelSeed, LabelFrontier)
+// as two gfx950 kernels, plus seed compaction.
+//
+// k_longest : one thread per triangle. Gathers the three vertices, compares the
+//             squared edge lengths in binary64 (each product and sum rounded,
+//             no fused multiply-add) and writes the local index of the longest
+//             edge (the paper's Max array) as one byte per triangle.
+// k_label   : one tile of 1024 triangles per block, four consecutive triangles
+//             per thread so that twin, Max and the label bytes move as 16-byte
+//             and 4-byte vectors. Writes the half-edge labels and the SEED flag
+//             and appends the seed triangles, in increasing index, to a list
+//             placed by a single-pass decoupled look-back scan.
+#include "common.h"
+#include "scan.h"
+
+namespace polylla {
+
+__device__ __forceinline__ double sq_length(double2 a, double2 b) {
+  double dx = __dsub_rn(b.x, a.x);
+  double dy = __dsub_rn(b.y, a.y);
+  return __dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy));
+}
+
+// Edge key used to order equal lengths: the smaller half-edge of the edge.
+__device__ __forceinline__ int32_t edge_key(const int32_t* __restrict__ twin, int32_t h, int32_t nhe,
+                                            Counters* cnt) {
+  int32_t tw = twin[h];
+  if (tw < -1 || tw >= nhe) {
+    set_error(cnt, POLYLLA_ETOPO);
+    return h;
+  }
+  return (tw < 0 || h < tw) ? h : tw;
+}
+
+__global__ void k_reset(Counters* cnt, uint64_t* status, int64_t n_status, const int64_t* n_from) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t k = i; k < n_status; k += stride) status[k] = 0;
+  if (i == 0) {
+    int32_t* w = reinterpret_cast<int32_t*>(cnt);
+    for (size_t k = 0; k < sizeof(Counters) / 4; ++k) w[k] = 0;
+    if (n_from) cnt->n_seeds = (uint32_t)(*n_from);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_longest(int64_t nt, int64_t nv, const double* __restrict__ xy,
+                                                 const int32_t* __restrict__ origin,
+                                                 const int32_t* __restrict__ twin, uint8_t* __restrict__ lg,
+                                                 uint8_t* __restrict__ vtx, Counters* cnt) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  if (vtx)
+    for (int64_t v = gid; v < nv; v += stride) vtx[v] = 0;
+  const int32_t nhe = (int32_t)(3 * nt);
+  const double2* __restrict__ p = reinterpret_cast<const double2*>(xy);
+  for (int64_t t = gid; t < nt; t += stride) {
+    const int32_t h0 = (int32_t)(3 * t);
+    int32_t a = origin[h0], b = origin[h0 + 1], c = origin[h0 + 2];
+    if ((uint64_t)(uint32_t)a >= (uint64_t)nv || (uint64_t)(uint32_t)b >= (uint64_t)nv ||
+        (uint64_t)(uint32_t)c >= (uint64_t)nv) {
+      set_error(cnt, POLYLLA_ETOPO);
+      lg[t] = 0;
+      continue;
+    }
+    double2 pa = p[a], pb = p[b], pc = p[c];
+    double l0 = sq_length(pa, pb), l1 = sq_length(pb, pc), l2 = sq_length(pc, pa);
+    int best = 0;
+    double lb = l0;
+    if (l1 > lb) {
+      best = 1;
+      lb = l1;
+    } else if (l1 == lb && edge_key(twin, h0 + 1, nhe, cnt) < edge_key(twin, h0, nhe, cnt)) {
+      best = 1;
+    }
+    if (l2 > lb) {
+      best = 2;
+    } else if (l2 == lb && edge_key(twin, h0 + 2, nhe, cnt) < edge_key(twin, h0 + best, nhe, cnt)) {
+      best = 2;
+    }
+    lg[t] = (uint8_t)best;
+  }
+}
+
+// Labels of the three half-edges of triangle t and whether t is a seed.
+__device__ __forceinline__ uint32_t label_triangle(int64_t t, int m, const int32_t tw[3],
+                                                   const uint8_t* __restrict__ lg, int32_t nhe,
+                                                   Counters* cnt, bool* seed) {
+  uint32_t packed = 0;
+  bool s = false;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const bool mine = (m == i);
+    uint32_t lab = mine ? kLongest : 0u;
+    int32_t u = tw[i];
+    if (u < 0) {
+      lab |= kFrontier | kBorder;
+      if (mine) {
+        lab |= kTerminal;
+        s = true;
+      }
+      if (u != -1) set_error(cnt, POLYLLA_ETOPO);
+    } else {
+      if (u >= nhe) {
+        set_error(cnt, POLYLLA_ETOPO);
+        u = 0;
+      }
+      const int64_t tu = u / 3;
+      const bool theirs = lg[tu] == (uint8_t)(u - 3 * tu);
+      if (mine && theirs) {
+        lab |= kTerminal;
+        if (t < tu) s = true;
+      }
+      if (!mine && !theirs) lab |= kFrontier;
+    }
+    packed |= lab << (8 * i);
+  }
+  *seed = s;
+  return packed;
+}
+
+// COMPUTE = true : labels from twin + Max, then seed compaction.
+// COMPUTE = false: seed compaction only, from existing triangle labels.
+template <bool COMPUTE>
+__global__ __launch_bounds__(256) void k_label(int64_t nt, const int32_t* __restrict__ twin,
+                                               const uint8_t* __restrict__ lg, uint8_t* __restrict__ he,
+                                               uint8_t* __restrict__ tri, int32_t* __restrict__ seeds,
+                                               uint64_t* status, Counters* cnt, bool vec) {
+  constexpr int ITEMS = 4;
+  const uint32_t tile = take_tile(&cnt->tile_ticket[0]);
+  const int64_t t0 = ((int64_t)tile * 256 + threadIdx.x) * ITEMS;
+  const int32_t nhe = (int32_t)(3 * nt);
+  bool sd[ITEMS];
+  if (COMPUTE) {
+    if (vec && t0 + ITEMS <= nt) {
+      int32_t tw[3 * ITEMS];
+      const int4* tw4 = reinterpret_cast<const int4*>(twin + 3 * t0);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        int4 q = tw4[k];
+        tw[4 * k] = q.x;
+        tw[4 * k + 1] = q.y;
+        tw[4 * k + 2] = q.z;
+        tw[4 * k + 3] = q.w;
+      }
+      uint32_t mm = *reinterpret_cast<const uint32_t*>(lg + t0);
+      uint32_t lab[ITEMS];
+#pragma unroll
+      for (int j = 0; j < ITEMS; ++j)
+        lab[j] = label_triangle(t0 + j, (mm >> (8 * j)) & 0xFF, tw + 3 * j, lg, nhe, cnt, &sd[j]);
+      // 12 label bytes of 4 triangles -> three 32-bit words
+      uint32_t w0 = lab[0] | (lab[1] << 24);
+      uint32_t w1 = (lab[1] >> 8) | (lab[2] << 16);
+      uint32_t w2 = (lab[2] >> 16) | (lab[3] << 8);
+      uint32_t* he4 = reinterpret_cast<uint32_t*>(he + 3 * t0);
+      he4[0] = w0;
+      he4[1] = w1;
+      he4[2] = w2;
+      uint32_t sw = (sd[0] ? kSeed : 0u) | ((sd[1] ? kSeed : 0u) << 8) | ((sd[2] ? kSeed : 0u) << 16) |
+                    ((sd[3] ? kSeed : 0u) << 24);
+      *reinterpret_cast<uint32_t*>(tri + t0) = sw;
+    } else {
+#pragma unroll
+      for (int j = 0; j < ITEMS; ++j) {
+        sd[j] = false;
+        const int64_t t = t0 + j;
+        if (t >= nt) continue;
+        int32_t tw[3] = {twin[3 * t], twin[3 * t + 1], twin[3 * t + 2]};
+        uint32_t lab = label_triangle(t, lg[t], tw, lg, nhe, cnt, &sd[j]);
+        he[3 * t] = (uint8_t)lab;
+        he[3 * t + 1] = (uint8_t)(lab >> 8);
+        he[3 * t + 2] = (uint8_t)(lab >> 16);
+        tri[t] = sd[j] ? kSeed : 0;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      const int64_t t = t0 + j;
+      sd[j] = t < nt && (tri[t] & kSeed);
+    }
+  }
+  uint32_t mine = 0;
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) mine += sd[j] ? 1u : 0u;
+  uint2 total;
+  uint2 pre = block_exclusive_scan<256>(mine, 0u, &total);
+  uint2 ex = tile_lookback(status, tile, total, cnt);
+  uint32_t pos = ex.x + pre.x;
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j)
+    if (sd[j]) seeds[pos++] = (int32_t)(t0 + j);
+  const int64_t ntiles = (nt + 256 * ITEMS - 1) / (256 * ITEMS);
+  if (tile == ntiles - 1 && threadIdx.x == 0) cnt->n_seeds = ex.x + total.x;
+}
+
+// Full check of the input layout: grouped next, index ranges, twin involution
+// and matching endpoints.
+__global__ __launch_bounds__(256) void k_validate(int64_t nhe, int64_t nv, const int32_t* __restrict__ twin,
+                                                  const int32_t* __restrict__ next,
+                                                  const int32_t* __restrict__ origin, Counters* cnt) {
+  for (int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; h < nhe; h += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t hh = (int32_t)h;
+    if (next[h] != he_next(hh)) {
+      set_error(cnt, POLYLLA_ELAYOUT);
+      continue;
+    }
+    const int32_t o = origin[h], tw = twin[h];
+    if ((uint64_t)(uint32_t)o >= (uint64_t)nv || tw < -1 || tw >= nhe || tw == hh) {
+      set_error(cnt, POLYLLA_ETOPO);
+      continue;
+    }
+    if (tw >= 0) {
+      const int32_t on = origin[he_next(hh)];
+      if (twin[tw] != hh || origin[tw] != on) set_error(cnt, POLYLLA_ETOPO);
+    }
+  }
+}
+
+template __global__ void k_label<true>(int64_t, const int32_t*, const uint8_t*, uint8_t*, uint8_t*, int32_t*,
+                                       uint64_t*, Counters*, bool);
+template __global__ void k_label<false>(int64_t, const int32_t*, const uint8_t*, uint8_t*, uint8_t*, int32_t*,
+                                        uint64_t*, Counters*, bool);
+
+}  // namespace polylla

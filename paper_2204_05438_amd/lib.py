@@ -1,0 +1,270 @@
+"""Python binding of libpolylla (ctypes). Argument marshalling only: every step
+of the mesher runs in the HIP kernels of the shared library. PyTorch provides
+device memory and the current HIP stream.
+
+There is no CPU fallback: loading fails loudly when the library is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpolylla.so")
+
+OK, EINVAL, ELAYOUT, ETOPO, ECAPACITY, ENOMEM, EHIP, EDEGEN, EINTERNAL = 0, -1, -2, -3, -4, -5, -6, -7, -8
+LONGEST, FRONTIER, TERMINAL, BORDER, BARRIER, REPAIRED = 1, 2, 4, 8, 16, 32
+SEED, TIP = 1, 1
+
+
+class PolyllaError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what}: {strerror(code)} ({code})")
+        self.code = code
+
+
+class _Tri(ctypes.Structure):
+    _fields_ = [("n_vertices", ctypes.c_int64), ("n_halfedges", ctypes.c_int64),
+                ("xy", ctypes.c_void_p), ("twin", ctypes.c_void_p),
+                ("next", ctypes.c_void_p), ("origin", ctypes.c_void_p)]
+
+
+class _Labels(ctypes.Structure):
+    _fields_ = [("he", ctypes.c_void_p), ("tri", ctypes.c_void_p), ("vtx", ctypes.c_void_p)]
+
+
+class _Polys(ctypes.Structure):
+    _fields_ = [("offsets", ctypes.c_void_p), ("verts", ctypes.c_void_p), ("start", ctypes.c_void_p),
+                ("counts", ctypes.c_void_p), ("cap_polys", ctypes.c_int64), ("cap_verts", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libpolylla.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2204_05438_amd.build` (there is no fallback)")
+        lib = ctypes.CDLL(LIB_PATH)
+        P = ctypes.c_void_p
+        lib.polylla_ctx_create.argtypes = [ctypes.POINTER(P), ctypes.c_int]
+        lib.polylla_ctx_destroy.argtypes = [P]
+        lib.polylla_ctx_destroy.restype = None
+        lib.polylla_reserve.argtypes = [P, ctypes.c_int64, ctypes.c_int64]
+        lib.polylla_label.argtypes = [P, ctypes.POINTER(_Tri), ctypes.POINTER(_Labels), P]
+        lib.polylla_build.argtypes = [P, ctypes.POINTER(_Tri), ctypes.POINTER(_Labels), ctypes.POINTER(_Polys), P]
+        lib.polylla_repair.argtypes = [P, ctypes.POINTER(_Tri), ctypes.POINTER(_Labels), ctypes.POINTER(_Polys),
+                                       ctypes.POINTER(_Polys), P]
+        lib.polylla_mesh.argtypes = [P, ctypes.POINTER(_Tri), ctypes.POINTER(_Labels), ctypes.POINTER(_Polys), P]
+        lib.polylla_validate.argtypes = [P, ctypes.POINTER(_Tri), P]
+        lib.polylla_status.argtypes = [P, P]
+        lib.polylla_stats.argtypes = [P, ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
+        lib.polylla_profile.argtypes = [P, ctypes.c_int]
+        lib.polylla_profile_read.argtypes = [P, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
+                                             ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
+        lib.polylla_strerror.argtypes = [ctypes.c_int]
+        lib.polylla_strerror.restype = ctypes.c_char_p
+        for f in ("polylla_ctx_create", "polylla_reserve", "polylla_label", "polylla_build", "polylla_repair",
+                  "polylla_mesh", "polylla_validate", "polylla_status", "polylla_stats", "polylla_profile",
+                  "polylla_profile_read"):
+            getattr(lib, f).restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def strerror(code: int) -> str:
+    return load().polylla_strerror(int(code)).decode()
+
+
+def _check(code: int, what: str):
+    if code != OK:
+        raise PolyllaError(code, what)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+@dataclass
+class Tri:
+    """A triangulation resident on the device (see polylla.h for the layout)."""
+    xy: torch.Tensor       # float64 [V, 2]
+    twin: torch.Tensor     # int32 [H]
+    next: torch.Tensor     # int32 [H]
+    origin: torch.Tensor   # int32 [H]
+
+    @property
+    def n_vertices(self):
+        return int(self.xy.shape[0])
+
+    @property
+    def n_halfedges(self):
+        return int(self.origin.shape[0])
+
+    @property
+    def n_tri(self):
+        return self.n_halfedges // 3
+
+    def c(self) -> _Tri:
+        for name in ("xy", "twin", "next", "origin"):
+            t = getattr(self, name)
+            if not t.is_contiguous():
+                raise ValueError(f"{name} must be contiguous")
+        if self.xy.dtype != torch.float64 or any(
+                getattr(self, n).dtype != torch.int32 for n in ("twin", "next", "origin")):
+            raise TypeError("xy must be float64 and twin/next/origin int32")
+        return _Tri(self.n_vertices, self.n_halfedges, self.xy.data_ptr(), self.twin.data_ptr(),
+                    self.next.data_ptr(), self.origin.data_ptr())
+
+    @staticmethod
+    def from_mesh(mesh, device="cuda") -> "Tri":
+        """Copy a meshgen.Mesh (numpy arrays) to the device."""
+        return Tri(xy=torch.from_numpy(mesh.xy).to(device).contiguous(),
+                   twin=torch.from_numpy(mesh.twin).to(device),
+                   next=torch.from_numpy(mesh.next).to(device),
+                   origin=torch.from_numpy(mesh.origin).to(device))
+
+
+@dataclass
+class Labels:
+    he: torch.Tensor    # uint8 [H]
+    tri: torch.Tensor   # uint8 [T]
+    vtx: torch.Tensor   # uint8 [V]
+
+    @staticmethod
+    def empty(tri: Tri) -> "Labels":
+        dev = tri.origin.device
+        return Labels(he=torch.empty(tri.n_halfedges, dtype=torch.uint8, device=dev),
+                      tri=torch.empty(tri.n_tri, dtype=torch.uint8, device=dev),
+                      vtx=torch.empty(tri.n_vertices, dtype=torch.uint8, device=dev))
+
+    def c(self) -> _Labels:
+        return _Labels(self.he.data_ptr(), self.tri.data_ptr(), self.vtx.data_ptr())
+
+
+@dataclass
+class Polys:
+    offsets: torch.Tensor   # int32 [cap_polys + 1]
+    verts: torch.Tensor     # int32 [cap_verts]
+    start: torch.Tensor | None
+    counts: torch.Tensor    # int64 [2]
+
+    @staticmethod
+    def empty(tri: Tri, cap_polys: int | None = None, cap_verts: int | None = None, with_start=True) -> "Polys":
+        dev = tri.origin.device
+        T = tri.n_tri
+        cp = T if cap_polys is None else cap_polys
+        cv = 3 * T if cap_verts is None else cap_verts
+        return Polys(offsets=torch.empty(cp + 1, dtype=torch.int32, device=dev),
+                     verts=torch.empty(max(cv, 1), dtype=torch.int32, device=dev),
+                     start=torch.empty(max(cp, 1), dtype=torch.int32, device=dev) if with_start else None,
+                     counts=torch.zeros(2, dtype=torch.int64, device=dev))
+
+    def c(self) -> _Polys:
+        return _Polys(self.offsets.data_ptr(), self.verts.data_ptr(),
+                      None if self.start is None else self.start.data_ptr(),
+                      self.counts.data_ptr(), self.offsets.shape[0] - 1, self.verts.shape[0])
+
+    def trimmed(self):
+        """(offsets, verts, start) cut to the produced sizes (synchronises)."""
+        F, S = (int(x) for x in self.counts.tolist())
+        return (self.offsets[:F + 1], self.verts[:S],
+                None if self.start is None else self.start[:F])
+
+
+class Context:
+    """A libpolylla context on one device; calls run on torch's current stream."""
+
+    def __init__(self, device: int = 0):
+        lib = load()
+        h = ctypes.c_void_p()
+        _check(lib.polylla_ctx_create(ctypes.byref(h), int(device)), "polylla_ctx_create")
+        self._h = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().polylla_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _stream():
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    def reserve(self, n_halfedges: int, n_vertices: int):
+        _check(load().polylla_reserve(self._h, int(n_halfedges), int(n_vertices)), "polylla_reserve")
+
+    def label(self, tri: Tri, labels: Labels | None = None) -> Labels:
+        labels = labels or Labels.empty(tri)
+        t, l = tri.c(), labels.c()
+        _check(load().polylla_label(self._h, ctypes.byref(t), ctypes.byref(l), self._stream()), "polylla_label")
+        return labels
+
+    def build(self, tri: Tri, labels: Labels, out: Polys | None = None) -> Polys:
+        out = out or Polys.empty(tri)
+        t, l, o = tri.c(), labels.c(), out.c()
+        _check(load().polylla_build(self._h, ctypes.byref(t), ctypes.byref(l), ctypes.byref(o), self._stream()),
+               "polylla_build")
+        return out
+
+    def repair(self, tri: Tri, labels: Labels, polys_in: Polys, out: Polys | None = None) -> Polys:
+        out = out or Polys.empty(tri)
+        t, l, i, o = tri.c(), labels.c(), polys_in.c(), out.c()
+        _check(load().polylla_repair(self._h, ctypes.byref(t), ctypes.byref(l), ctypes.byref(i),
+                                     ctypes.byref(o), self._stream()), "polylla_repair")
+        return out
+
+    def mesh(self, tri: Tri, labels: Labels | None = None, out: Polys | None = None) -> Polys:
+        out = out or Polys.empty(tri)
+        t, o = tri.c(), out.c()
+        lp = ctypes.byref(labels.c()) if labels is not None else None
+        _check(load().polylla_mesh(self._h, ctypes.byref(t), lp, ctypes.byref(o), self._stream()), "polylla_mesh")
+        return out
+
+    def validate(self, tri: Tri) -> int:
+        t = tri.c()
+        return load().polylla_validate(self._h, ctypes.byref(t), self._stream())
+
+    def status(self, raise_on_error: bool = True) -> int:
+        code = load().polylla_status(self._h, self._stream())
+        if raise_on_error:
+            _check(code, "device")
+        return code
+
+    def stats(self) -> dict:
+        buf = (ctypes.c_int64 * 4)()
+        n = load().polylla_stats(self._h, buf, 4)
+        keys = ["seeds", "general_path", "tips", "splits"]
+        return {k: int(buf[i]) for i, k in enumerate(keys[:n])}
+
+    def profile(self, enable: bool):
+        """Start (clearing earlier records) or stop per-kernel event timing."""
+        _check(load().polylla_profile(self._h, 1 if enable else 0), "polylla_profile")
+
+    def profile_read(self) -> dict:
+        """{kernel name: (summed ms, launches)} of the recorded launches."""
+        n = 16
+        names = ctypes.create_string_buffer(32 * n)
+        ms = (ctypes.c_double * n)()
+        cnt = (ctypes.c_int64 * n)()
+        w = load().polylla_profile_read(self._h, names, ms, cnt, n)
+        if w < 0:
+            _check(w, "polylla_profile_read")
+        raw = names.raw
+        out = {}
+        for i in range(w):
+            nm = raw[32 * i:32 * i + 32].split(b"\0", 1)[0].decode()
+            out[nm] = (float(ms[i]), int(cnt[i]))
+        return out

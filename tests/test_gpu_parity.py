@@ -1,0 +1,163 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle,
+element by element, on hand fixtures, seeded tiny meshes and the workloads."""
+import numpy as np
+import pytest
+
+import oracle
+from bruteforce import csr_cycles
+from fixtures import empty_mesh, golden, golden_names, random_mesh
+from meshgen.gen import config_mesh
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2204_05438_amd import lib
+    c = lib.Context(0)
+    yield c
+    c.close()
+
+
+def gpu_mesh(ctx, mesh):
+    from paper_2204_05438_amd import lib
+    tri = lib.Tri.from_mesh(mesh)
+    labels = lib.Labels.empty(tri)
+    out = ctx.mesh(tri, labels)
+    ctx.status()
+    off, verts, start = out.trimmed()
+    return {"he": labels.he.cpu().numpy(), "tri": labels.tri.cpu().numpy(), "vtx": labels.vtx.cpu().numpy(),
+            "offsets": off.cpu().numpy(), "verts": verts.cpu().numpy(), "start": start.cpu().numpy(),
+            "stats": ctx.stats()}
+
+
+def gpu_three_calls(ctx, mesh):
+    from paper_2204_05438_amd import lib
+    tri = lib.Tri.from_mesh(mesh)
+    labels = ctx.label(tri)
+    pre = ctx.build(tri, labels)
+    out = ctx.repair(tri, labels, pre)
+    ctx.status()
+    po, pv, ps = pre.trimmed()
+    fo, fv, fs = out.trimmed()
+    return {"he": labels.he.cpu().numpy(), "tri": labels.tri.cpu().numpy(), "vtx": labels.vtx.cpu().numpy(),
+            "pre_offsets": po.cpu().numpy(), "pre_verts": pv.cpu().numpy(), "pre_start": ps.cpu().numpy(),
+            "offsets": fo.cpu().numpy(), "verts": fv.cpu().numpy(), "start": fs.cpu().numpy()}
+
+
+def assert_same(g, o, keys):
+    for k in keys:
+        a, b = np.asarray(g[k]), np.asarray(o[k])
+        assert a.shape == b.shape, (k, a.shape, b.shape)
+        if not np.array_equal(a, b):
+            bad = np.nonzero(a != b)[0]
+            raise AssertionError(f"{k}: {bad.size} mismatches, first at {bad[:5]}: gpu {a[bad[:5]]} oracle {b[bad[:5]]}")
+
+
+FULL = ["he", "tri", "vtx", "offsets", "verts", "start"]
+
+
+@pytest.mark.parametrize("name", golden_names())
+def test_golden(ctx, name):
+    _say(f"golden {name}")
+    mesh, g = golden(name)
+    r = gpu_mesh(ctx, mesh)
+    assert r["he"].tolist() == g["he"]
+    assert r["tri"].tolist() == g["tri"]
+    assert r["vtx"].tolist() == g["vtx"]
+    assert csr_cycles(r["offsets"], r["verts"]) == [tuple(c) for c in g["final"]]
+    assert_same(r, oracle.oracle_on(mesh), FULL)
+
+
+@pytest.mark.parametrize("kind", ["uniform", "cluster", "grid", "lattice"])
+@pytest.mark.parametrize("seed", range(10))
+def test_random_small(ctx, kind, seed):
+    n = [5, 10, 30, 60, 100, 200, 300, 500, 800, 1500][seed]
+    _say(f"random {kind} seed {seed} n {n}")
+    mesh = random_mesh(7000 + 13 * seed, n, kind)
+    assert_same(gpu_mesh(ctx, mesh), oracle.oracle_on(mesh), FULL)
+
+
+@pytest.mark.parametrize("kind", ["uniform", "cluster", "lattice"])
+def test_three_calls_match_oracle(ctx, kind):
+    _say(f"label/build/repair {kind}")
+    mesh = random_mesh(4242, 3000, kind)
+    o = oracle.oracle_on(mesh)
+    r = gpu_three_calls(ctx, mesh)
+    assert_same(r, o, FULL + ["pre_offsets", "pre_verts", "pre_start"])
+
+
+def test_empty(ctx):
+    _say("empty mesh")
+    r = gpu_mesh(ctx, empty_mesh())
+    assert r["offsets"].tolist() == [0] and r["verts"].size == 0
+
+
+@pytest.mark.parametrize("name", ["uniform10k", "mixed200k", "grid300x"])
+def test_workloads_small(ctx, name):
+    _say(f"workload {name}")
+    mesh = config_mesh(name)
+    o = oracle.oracle_on(mesh)
+    r = gpu_mesh(ctx, mesh)
+    assert_same(r, o, FULL)
+    assert r["stats"]["seeds"] == o["stats"]["seeds"]
+    assert r["stats"]["splits"] == o["stats"]["splits"]
+
+
+def test_workload_mixed1m(ctx):
+    _say("workload mixed1m")
+    mesh = config_mesh("mixed1m")
+    o = oracle.oracle_on(mesh)
+    r = gpu_mesh(ctx, mesh)
+    assert_same(r, o, FULL)
+
+
+def test_deterministic(ctx):
+    _say("determinism mixed200k x3")
+    mesh = config_mesh("mixed200k")
+    runs = [gpu_mesh(ctx, mesh) for _ in range(3)]
+    for r in runs[1:]:
+        assert_same(r, runs[0], FULL)
+
+
+def test_capacity_error(ctx):
+    _say("capacity error")
+    from paper_2204_05438_amd import lib
+    mesh = random_mesh(5, 400, "uniform")
+    tri = lib.Tri.from_mesh(mesh)
+    out = lib.Polys.empty(tri, cap_polys=10, cap_verts=40)
+    ctx.mesh(tri, None, out)
+    assert ctx.status(raise_on_error=False) == lib.ECAPACITY
+    # the context is usable afterwards
+    r = gpu_mesh(ctx, mesh)
+    assert_same(r, oracle.oracle_on(mesh), FULL)
+
+
+def test_layout_errors(ctx):
+    _say("layout errors")
+    from paper_2204_05438_amd import lib
+    mesh, _ = golden("square")
+    tri = lib.Tri.from_mesh(mesh)
+    assert ctx.validate(tri) == lib.OK
+    bad = lib.Tri(tri.xy, tri.twin.clone(), tri.next, tri.origin)
+    bad.twin[2] = 4
+    assert ctx.validate(bad) == lib.ETOPO
+    badn = lib.Tri(tri.xy, tri.twin, tri.next.clone(), tri.origin)
+    badn.next[0] = 2
+    assert ctx.validate(badn) == lib.ELAYOUT
+    short = lib.Tri(tri.xy, tri.twin[:5], tri.next[:5], tri.origin[:5])
+    with pytest.raises(lib.PolyllaError):
+        ctx.mesh(short)
+    # out-of-range twin inside the hot path: reported, no fault
+    badr = lib.Tri(tri.xy, tri.twin.clone(), tri.next, tri.origin)
+    badr.twin[2] = 1000
+    ctx.mesh(badr)
+    assert ctx.status(raise_on_error=False) == lib.ETOPO

@@ -151,7 +151,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: jittered 3163x3163 grid in [0,1]^2 (seed 3), Delaunay, "
                                f"{mesh.n_vertices} vertices, {T} triangles, one mesh per step",
-                   "polygons": F, "seeds": stats["seeds"], "general_path": stats["general_path"],
+                   "polygons": F, "seeds": stats["seeds"], "general_small": stats["general_small"],
+                   "general_big": stats["general_big"],
                    "tips": stats["tips"], "splits": stats["splits"]},
         "roofline": roofline,
         "kernels": per_kernel,

@@ -158,9 +158,19 @@ int polylla_validate(polylla_ctx *ctx, const polylla_tri *tri, hipStream_t strea
 int polylla_status(polylla_ctx *ctx, hipStream_t stream);
 
 /* Diagnostics of the last build / repair / mesh call, after polylla_status:
- * out[0] seeds, out[1] polygons routed to the general path, out[2] tips,
- * out[3] opened edges. Returns the number of values written (<= n). */
+ * out[0] seeds, out[1] short polygons with a tip or a repeated vertex (one
+ * lane each), out[2] tips, out[3] opened edges, out[4] long polygons (one
+ * workgroup each), out[5] long polygons beyond the workgroup's LDS capacity
+ * (one lane each). Returns the number of values written (<= n). */
 int polylla_stats(polylla_ctx *ctx, int64_t *out, int n);
+
+/* Tuning parameters of a context (defaults are the tuned values).
+ * POLYLLA_PARAM_WALK_CAP (1..24, default 24): the longest cycle one lane walks
+ * and stages by itself; longer polygons are built by a whole workgroup. Small
+ * values route more polygons through the cooperative kernel (used by tests).
+ * Returns POLYLLA_EINVAL for an unknown parameter or a value out of range. */
+#define POLYLLA_PARAM_WALK_CAP 1
+int polylla_set_param(polylla_ctx *ctx, int param, int64_t value);
 
 /* Per-kernel GPU timing with HIP events, for benchmarks (off by default).
  * polylla_profile(ctx, 1) clears earlier records and records an event pair on

@@ -18,10 +18,15 @@ __global__ void k_label(int64_t, const int32_t*, const uint8_t*, uint8_t*, uint8
                         Counters*, bool);
 template <bool FROM_SEEDS>
 __global__ void k_walk(const int32_t*, int32_t, const int32_t*, const int32_t*, const uint8_t*, int32_t*, int64_t,
-                       PolyState, int32_t*, Counters*);
+                       PolyState, int32_t*, int64_t, int, Counters*);
 template <bool REPAIR>
-__global__ void k_general(const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*, uint8_t*,
-                          uint8_t*, int32_t*, int64_t, int32_t*, int64_t, PolyState, const int32_t*, Counters*);
+__global__ void k_general_small(const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*, uint8_t*,
+                                uint8_t*, int32_t*, int64_t, int32_t*, int64_t, PolyState, const int32_t*,
+                                Counters*);
+template <bool REPAIR>
+__global__ void k_general_big(const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*, uint8_t*,
+                              uint8_t*, int32_t*, int64_t, int32_t*, int64_t, PolyState, const int32_t*, int64_t,
+                              Counters*);
 __global__ void k_scan_polys(PolyState, int32_t*, int32_t*, uint64_t*, int32_t*, int64_t*, int64_t, int64_t,
                              Counters*);
 __global__ void k_emit(PolyState, const int32_t*, const int32_t*, const int32_t*, const int32_t*, int32_t*,
@@ -51,6 +56,7 @@ struct polylla_ctx {
   uint8_t* tri_s = nullptr;
   uint8_t* vtx_s = nullptr;
   Counters last{};
+  int walk_cap = 24;  // vertices a lane walks before handing a polygon to a workgroup
   // event profiling
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;
@@ -66,9 +72,12 @@ namespace {
 constexpr int64_t kTile = 1024;
 constexpr size_t kMaxProfiled = 8192;
 
-enum KernelId { KR_RESET, KR_LONGEST, KR_LABEL, KR_COMPACT, KR_WALK, KR_GENERAL, KR_SCAN, KR_EMIT, KR_VALIDATE, KR_N };
-const char* kKernelNames[KR_N] = {"k_reset", "k_longest", "k_label", "k_compact_seeds", "k_walk",
-                                  "k_general", "k_scan_polys", "k_emit", "k_validate"};
+enum KernelId {
+  KR_RESET, KR_LONGEST, KR_LABEL, KR_COMPACT, KR_WALK, KR_GENERAL, KR_BIG, KR_SCAN, KR_EMIT, KR_VALIDATE, KR_N
+};
+const char* kKernelNames[KR_N] = {"k_reset",        "k_longest",     "k_label", "k_compact_seeds",
+                                  "k_walk",         "k_general_small", "k_general_big", "k_scan_polys",
+                                  "k_emit",         "k_validate"};
 
 // Event pair around one kernel launch when profiling is on.
 struct Prof {
@@ -217,22 +226,34 @@ int run_build(polylla_ctx* c, const polylla_tri* t, const int32_t* list, bool fr
     const int gw = grid_for(T, 1024, 1 << 16);
     if (from_seeds)
       hipLaunchKernelGGL(k_walk<true>, dim3(gw), dim3(256), 0, s, list, nhe, t->twin, t->origin, he, c->stage,
-                         c->stage_cap, ps, c->deferred, c->cnt);
+                         c->stage_cap, ps, c->deferred, c->cap_t, c->walk_cap, c->cnt);
     else
       hipLaunchKernelGGL(k_walk<false>, dim3(gw), dim3(256), 0, s, list, nhe, t->twin, t->origin, he, c->stage,
-                         c->stage_cap, ps, c->deferred, c->cnt);
+                         c->stage_cap, ps, c->deferred, c->cap_t, c->walk_cap, c->cnt);
   }
   {
     Prof p(c, s, KR_GENERAL);
     const int gg = 2048;
     if (repair)
-      hipLaunchKernelGGL(k_general<true>, dim3(gg), dim3(64), 0, s, list, from_seeds, nhe, t->n_vertices,
+      hipLaunchKernelGGL(k_general_small<true>, dim3(gg), dim3(64), 0, s, list, from_seeds, nhe, t->n_vertices,
                          t->twin, t->origin, he, vtx, c->stage, c->stage_cap, c->arena, c->arena_cap, ps,
                          c->deferred, c->cnt);
     else
-      hipLaunchKernelGGL(k_general<false>, dim3(gg), dim3(64), 0, s, list, from_seeds, nhe, t->n_vertices,
+      hipLaunchKernelGGL(k_general_small<false>, dim3(gg), dim3(64), 0, s, list, from_seeds, nhe, t->n_vertices,
                          t->twin, t->origin, he, vtx, c->stage, c->stage_cap, c->arena, c->arena_cap, ps,
                          c->deferred, c->cnt);
+  }
+  {
+    Prof p(c, s, KR_BIG);
+    const int gb = 256;
+    if (repair)
+      hipLaunchKernelGGL(k_general_big<true>, dim3(gb), dim3(256), 0, s, list, from_seeds, nhe, t->n_vertices,
+                         t->twin, t->origin, he, vtx, c->stage, c->stage_cap, c->arena, c->arena_cap, ps,
+                         c->deferred, c->cap_t, c->cnt);
+    else
+      hipLaunchKernelGGL(k_general_big<false>, dim3(gb), dim3(256), 0, s, list, from_seeds, nhe, t->n_vertices,
+                         t->twin, t->origin, he, vtx, c->stage, c->stage_cap, c->arena, c->arena_cap, ps,
+                         c->deferred, c->cap_t, c->cnt);
   }
   {
     Prof p(c, s, KR_SCAN);
@@ -381,10 +402,23 @@ int polylla_status(polylla_ctx* c, hipStream_t s) {
 
 int polylla_stats(polylla_ctx* c, int64_t* out, int n) {
   if (!c || !out || n < 0) return POLYLLA_EINVAL;
-  const int64_t v[4] = {c->last.n_seeds, c->last.n_deferred, c->last.n_tips, c->last.n_splits};
-  int k = std::min(n, 4);
+  const int64_t v[6] = {c->last.n_seeds, c->last.n_deferred, c->last.n_tips,
+                        c->last.n_splits, c->last.n_big,      c->last.n_fallback};
+  int k = std::min(n, 6);
   for (int i = 0; i < k; ++i) out[i] = v[i];
   return k;
+}
+
+int polylla_set_param(polylla_ctx* c, int param, int64_t value) {
+  if (!c) return POLYLLA_EINVAL;
+  switch (param) {
+    case POLYLLA_PARAM_WALK_CAP:
+      if (value < 1 || value > 24) return POLYLLA_EINVAL;
+      c->walk_cap = (int)value;
+      return POLYLLA_OK;
+    default:
+      return POLYLLA_EINVAL;
+  }
 }
 
 int polylla_profile(polylla_ctx* c, int enable) {

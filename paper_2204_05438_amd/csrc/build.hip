@@ -26,7 +26,7 @@
 
 namespace polylla {
 
-constexpr int kWalkCap = 32;
+constexpr int kWalkCap = 24;
 
 // Start half-edge of the region of seed triangle t: its first frontier
 // half-edge in local order, else the first frontier half-edge met turning
@@ -70,95 +70,168 @@ __device__ __forceinline__ int32_t walk_next(int32_t h, int32_t nhe, const int32
   return -1;
 }
 
+// Three values of a triangle selected by a local index without indexing a
+// register array (which would go to scratch memory).
+__device__ __forceinline__ int32_t sel3(int32_t a, int32_t b, int32_t c, int i) {
+  return i == 0 ? a : (i == 1 ? b : c);
+}
+
+// Twin triple, origin triple and label bytes of one triangle: nine
+// independent loads issued together, so a walk pays one memory round trip per
+// triangle it enters.
+struct TriRec {
+  int32_t tw0, tw1, tw2;
+  int32_t or0, or1, or2;
+  uint32_t lb0, lb1, lb2;
+  __device__ __forceinline__ int32_t tw(int i) const { return sel3(tw0, tw1, tw2, i); }
+  __device__ __forceinline__ int32_t org(int i) const { return sel3(or0, or1, or2, i); }
+  __device__ __forceinline__ uint32_t lab(int i) const { return (uint32_t)sel3(lb0, lb1, lb2, i); }
+  __device__ __forceinline__ void load(int32_t t, const int32_t* __restrict__ twin,
+                                       const int32_t* __restrict__ origin, const uint8_t* __restrict__ he) {
+    const int32_t h = 3 * t;
+    tw0 = twin[h];
+    tw1 = twin[h + 1];
+    tw2 = twin[h + 2];
+    or0 = origin[h];
+    or1 = origin[h + 1];
+    or2 = origin[h + 2];
+    lb0 = he[h];
+    lb1 = he[h + 1];
+    lb2 = he[h + 2];
+  }
+};
+
+__device__ __forceinline__ int next_local(int i) { return i == 2 ? 0 : i + 1; }
+
+// Walk states
+constexpr int kSimple = 0;    // complete here
+constexpr int kSmall = 1;     // short, with a tip or a repeated vertex
+constexpr int kInvalid = 2;   // input error (reported)
+constexpr int kLarge = 3;     // longer than kWalkCap
+
 template <bool FROM_SEEDS>
 __global__ __launch_bounds__(256) void k_walk(const int32_t* __restrict__ list, int32_t nhe,
                                               const int32_t* __restrict__ twin,
                                               const int32_t* __restrict__ origin,
                                               const uint8_t* __restrict__ he, int32_t* __restrict__ stage,
                                               int64_t stage_cap, PolyState ps, int32_t* __restrict__ deferred,
-                                              Counters* cnt) {
+                                              int64_t deferred_cap, int walk_cap, Counters* cnt) {
   __shared__ int32_t buf[kWalkCap][256];
+  walk_cap = walk_cap < 1 ? 1 : (walk_cap > kWalkCap ? kWalkCap : walk_cap);
   const int lane = threadIdx.x & 63;
   const uint32_t R = cnt->n_seeds;
+  const int32_t nt = nhe / 3;
   for (int64_t base = (int64_t)blockIdx.x * 256; base < (int64_t)R; base += (int64_t)gridDim.x * 256) {
     const int64_t i = base + threadIdx.x;
-    // 0 = complete here, 1 = queued for the general path, 2 = invalid input
-    int state = 1;
+    int state = kInvalid;
     int32_t L = 0, minpos = 0, minhe = -1;
     if (i < (int64_t)R) {
-      int32_t s = FROM_SEEDS ? seed_start(list[i], nhe, twin, he, cnt) : list[i];
-      if ((uint32_t)s >= (uint32_t)nhe) {
-        if (!FROM_SEEDS) set_error(cnt, POLYLLA_ETOPO);
-        state = 2;
-      } else {
-        state = 0;
-        int32_t minv = 0x7FFFFFFF;
-        int32_t h = s;
+      const int32_t item = list[i];
+      int32_t t = FROM_SEEDS ? item : item / 3;
+      if ((uint32_t)t < (uint32_t)nt && (FROM_SEEDS || item >= 0)) {
+        TriRec r;
+        r.load(t, twin, origin, he);
+        int cl = -1;
         int32_t steps = 0;
-        do {
-          const int32_t v = origin[h];
-          if (L == kWalkCap) {
-            state = 1;
-            break;
+        bool ok = true;
+        if (FROM_SEEDS) {
+          // first frontier half-edge of the seed triangle, else turn about its vertex 0
+          if (r.lb0 & kFrontier) cl = 0;
+          else if (r.lb1 & kFrontier) cl = 1;
+          else if (r.lb2 & kFrontier) cl = 2;
+          else {
+            int ci = 0;
+            while (ok && !(r.lab(ci) & kFrontier)) {
+              const int32_t tw = r.tw(ci);
+              if ((uint32_t)tw >= (uint32_t)nhe || ++steps > nhe) {
+                ok = false;
+                break;
+              }
+              t = tw / 3;
+              ci = next_local(tw - 3 * t);
+              r.load(t, twin, origin, he);
+            }
+            cl = ci;
           }
-          bool rep = false;
-          for (int j = 0; j < L; ++j) rep |= (buf[j][threadIdx.x] == v);
-          if (rep) {
-            state = 1;
-            break;
-          }
-          buf[L][threadIdx.x] = v;
-          if (v < minv) {
-            minv = v;
-            minhe = h;
-            minpos = L;
-          }
-          ++L;
-          const int32_t twh = twin[h];
-          int32_t c = he_next(h);
-          while (!(he[c] & kFrontier)) {
-            int32_t tw = twin[c];
-            if ((uint32_t)tw >= (uint32_t)nhe || ++steps > nhe) {
-              set_error(cnt, (uint32_t)tw >= (uint32_t)nhe ? POLYLLA_ETOPO : POLYLLA_EDEGEN);
-              state = 2;
+        } else {
+          cl = item - 3 * t;
+        }
+        if (ok) {
+          const int32_t s = 3 * t + cl;
+          state = kSimple;
+          bool complex = false;
+          int32_t minv = 0x7FFFFFFF;
+          int32_t h = s;
+          do {
+            if (L == walk_cap) {
+              state = kLarge;
               break;
             }
-            c = he_next(tw);
-          }
-          if (state == 2) break;
-          if (c == twh) {  // barrier-edge tip at the end of h
-            state = 1;
-            break;
-          }
-          h = c;
-        } while (h != s);
+            const int32_t v = r.org(cl);
+            if (!complex) {
+              bool rep = false;
+              for (int j = 0; j < L; ++j) rep |= (buf[j][threadIdx.x] == v);
+              if (rep) {
+                complex = true;
+              } else {
+                buf[L][threadIdx.x] = v;
+                if (v < minv) {
+                  minv = v;
+                  minhe = h;
+                  minpos = L;
+                }
+              }
+            }
+            ++L;
+            const int32_t twh = r.tw(cl);
+            // turn about the end vertex of h through internal edges
+            int ci = next_local(cl);
+            while (!(r.lab(ci) & kFrontier)) {
+              const int32_t tw = r.tw(ci);
+              if ((uint32_t)tw >= (uint32_t)nhe || ++steps > nhe) {
+                ok = false;
+                break;
+              }
+              t = tw / 3;
+              ci = next_local(tw - 3 * t);
+              r.load(t, twin, origin, he);
+            }
+            if (!ok) break;
+            const int32_t c = 3 * t + ci;
+            if (c == twh) complex = true;  // barrier-edge tip at the end of h
+            h = c;
+            cl = ci;
+          } while (h != s);
+          if (!ok) state = kInvalid;
+          else if (state == kSimple && complex) state = kSmall;
+        }
+        if (!ok) set_error(cnt, steps > nhe ? POLYLLA_EDEGEN : POLYLLA_ETOPO);
+      } else {
+        set_error(cnt, POLYLLA_ETOPO);
       }
     }
     // staging slots for complete polygons, one atomic per wave
-    uint32_t need = (i < (int64_t)R && state == 0) ? (uint32_t)L : 0u;
+    uint32_t need = (i < (int64_t)R && state == kSimple) ? (uint32_t)L : 0u;
     uint32_t incl = need;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
-      uint32_t t = __shfl_up(incl, o, 64);
-      if (lane >= o) incl += t;
+      uint32_t tt = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += tt;
     }
     uint32_t wbase = 0;
     if (lane == 63 && incl) wbase = atomicAdd(&cnt->stage_top, incl);
     wbase = __shfl(wbase, 63, 64);
     if (i < (int64_t)R) {
-      if (state == 0) {
+      if (state == kSimple) {
         const int64_t off = (int64_t)wbase + incl - need;
         if (off + L > stage_cap) {
           set_error(cnt, POLYLLA_ENOMEM);
-          ps.plen[i] = 0;
-          ps.ppieces[i] = 0;
-          ps.prec[i] = -1;
-          ps.pstage[i] = 0;
+          state = kInvalid;
         } else {
-          int p = minpos;
+          int pp = minpos;
           for (int k = 0; k < L; ++k) {
-            stage[off + k] = buf[p][threadIdx.x];
-            p = (p + 1 == L) ? 0 : p + 1;
+            stage[off + k] = buf[pp][threadIdx.x];
+            pp = (pp + 1 == L) ? 0 : pp + 1;
           }
           ps.plen[i] = L;
           ps.ppieces[i] = 1;
@@ -166,10 +239,14 @@ __global__ __launch_bounds__(256) void k_walk(const int32_t* __restrict__ list, 
           ps.prec[i] = -1;
           ps.pstage[i] = (int32_t)off;
         }
-      } else if (state == 1) {
+      } else if (state == kSmall) {
         uint32_t q = atomicAdd(&cnt->n_deferred, 1u);
         deferred[q] = (int32_t)i;
-      } else {
+      } else if (state == kLarge) {
+        uint32_t q = atomicAdd(&cnt->n_big, 1u);
+        deferred[deferred_cap - 1 - q] = (int32_t)i;
+      }
+      if (state == kInvalid) {
         ps.plen[i] = 0;
         ps.ppieces[i] = 0;
         ps.prec[i] = -1;
@@ -231,268 +308,776 @@ __device__ int compare_rotations(int32_t p, int32_t q, int32_t len, int32_t nhe,
   return 0;
 }
 
+// The whole general path for one polygon (index i in seed order, start
+// half-edge s), by one thread with its data in the global arena. Used for
+// short polygons with a tip or a repeated vertex, and for polygons too large
+// for the cooperative kernel.
 template <bool REPAIR>
-__global__ __launch_bounds__(64) void k_general(const int32_t* __restrict__ list, bool from_seeds, int32_t nhe,
-                                                int64_t nv, const int32_t* __restrict__ twin,
-                                                const int32_t* __restrict__ origin, uint8_t* __restrict__ he,
-                                                uint8_t* __restrict__ vtx, int32_t* __restrict__ stage,
-                                                int64_t stage_cap, int32_t* __restrict__ arena, int64_t arena_cap,
-                                                PolyState ps, const int32_t* __restrict__ deferred,
-                                                Counters* cnt) {
+__device__ void general_one(int32_t i, int32_t s, int32_t nhe, int64_t nv, const int32_t* __restrict__ twin,
+                            const int32_t* __restrict__ origin, uint8_t* __restrict__ he, uint8_t* __restrict__ vtx,
+                            int32_t* __restrict__ stage, int64_t stage_cap, int32_t* __restrict__ arena,
+                            int64_t arena_cap, PolyState ps, Counters* cnt) {
+  ps.plen[i] = 0;
+  ps.ppieces[i] = 0;
+  ps.prec[i] = -1;
+  ps.pstage[i] = 0;
+  if ((uint32_t)s >= (uint32_t)nhe) return;
+  // cycle length
+  int32_t L = 0;
+  {
+    int32_t h = s;
+    do {
+      ++L;
+      h = walk_next(h, nhe, twin, he, cnt);
+    } while (h >= 0 && h != s && L <= nhe);
+    if (h != s) {
+      set_error(cnt, POLYLLA_EDEGEN);
+      return;
+    }
+  }
+  const uint32_t need = 2u * (uint32_t)L;
+  const uint32_t a0 = atomicAdd(&cnt->arena_top, need);
+  if ((int64_t)a0 + need > arena_cap) {
+    set_error(cnt, POLYLLA_ENOMEM);
+    return;
+  }
+  int32_t* cyc = arena + a0;
+  int32_t* aux = cyc + L;
+  {
+    int32_t h = s;
+    for (int32_t k = 0; k < L; ++k) {
+      cyc[k] = h;
+      h = walk_next(h, nhe, twin, he, cnt);
+    }
+  }
+  // barrier edges: edge keys that occur twice on the cycle
+  for (int32_t k = 0; k < L; ++k) {
+    int32_t h = cyc[k], tw = twin[h];
+    aux[k] = (uint32_t)tw >= (uint32_t)nhe ? -1 : (h < tw ? h : tw);
+  }
+  heap_sort(aux, L);
+  for (int32_t k = 1; k < L; ++k) {
+    int32_t e = aux[k];
+    if (e >= 0 && e == aux[k - 1]) {
+      const int32_t te = twin[e];
+      he[e] |= kBarrier;
+      if ((uint32_t)te < (uint32_t)nhe) he[te] |= kBarrier;
+    }
+  }
+  // tips: the next frontier half-edge is the twin of the current one
+  int32_t ntip = 0;
+  for (int32_t k = 0; k < L; ++k) {
+    int32_t h = cyc[k], hn = cyc[k + 1 == L ? 0 : k + 1];
+    if (twin[h] == hn) {
+      int32_t v = origin[hn];
+      if ((uint64_t)(uint32_t)v < (uint64_t)nv) vtx[v] |= kTip;
+      aux[2 * ntip] = v;
+      aux[2 * ntip + 1] = hn;
+      ++ntip;
+    }
+  }
+  if (ntip) atomicAdd(&cnt->n_tips, (uint32_t)ntip);
+  int32_t nsplit = 0;
+  if (REPAIR && ntip) {
+    // middle internal edge at every tip: c_{floor(d/2)} clockwise from c0
+    for (int32_t q = 0; q < ntip; ++q) {
+      const int32_t c0 = aux[2 * q + 1];
+      int32_t d = 0, c = c0;
+      do {
+        const int32_t tw = twin[c];
+        if ((uint32_t)tw >= (uint32_t)nhe) {
+          d = -1;
+          break;
+        }
+        c = he_next(tw);
+        ++d;
+      } while (c != c0 && d <= nhe);
+      if (d < 0 || c != c0) {
+        set_error(cnt, POLYLLA_ETOPO);
+        d = 0;
+      }
+      int32_t e = c0;
+      for (int32_t k = 0; k < d / 2; ++k) e = he_next(twin[e]);
+      aux[2 * q + 1] = e;
+    }
+    // tips in increasing vertex id (insertion sort of pairs)
+    for (int32_t q = 1; q < ntip; ++q) {
+      int32_t v = aux[2 * q], e = aux[2 * q + 1], p = q;
+      while (p > 0 && aux[2 * (p - 1)] > v) {
+        aux[2 * p] = aux[2 * (p - 1)];
+        aux[2 * p + 1] = aux[2 * (p - 1) + 1];
+        --p;
+      }
+      aux[2 * p] = v;
+      aux[2 * p + 1] = e;
+    }
+    // a tip on an edge opened for a smaller live tip is no longer a tip
+    for (int32_t q = 0; q < ntip; ++q) {
+      const int32_t v = aux[2 * q];
+      bool dead = false;
+      for (int32_t p = 0; p < q && !dead; ++p) {
+        if (aux[2 * p] < 0) continue;  // dead tips are stored as -1 - v
+        dead = origin[he_next(aux[2 * p + 1])] == v;
+      }
+      if (dead) aux[2 * q] = -1 - v;
+    }
+    for (int32_t q = 0; q < ntip; ++q) {
+      if (aux[2 * q] < 0) continue;
+      int32_t e = aux[2 * q + 1];
+      const int32_t te = twin[e];
+      if ((uint32_t)te >= (uint32_t)nhe) {  // only reachable on an invalid mesh
+        set_error(cnt, POLYLLA_ETOPO);
+        aux[2 * q] = -1 - aux[2 * q];
+        continue;
+      }
+      he[e] |= kFrontier | kRepaired;
+      he[te] |= kFrontier | kRepaired;
+      ++nsplit;
+    }
+    if (nsplit) atomicAdd(&cnt->n_splits, (uint32_t)nsplit);
+  }
+  if (nsplit == 0) {
+    // one piece: the cycle itself, rotated to its smallest vertex sequence
+    int32_t best = 0, minv = origin[cyc[0]];
+    for (int32_t k = 1; k < L; ++k) {
+      int32_t v = origin[cyc[k]];
+      if (v < minv) {
+        minv = v;
+        best = k;
+      }
+    }
+    for (int32_t k = best + 1; k < L; ++k) {
+      if (origin[cyc[k]] != minv) continue;
+      for (int32_t m = 1; m < L; ++m) {
+        int32_t a = origin[cyc[(k + m) % L]], b = origin[cyc[(best + m) % L]];
+        if (a != b) {
+          if (a < b) best = k;
+          break;
+        }
+      }
+    }
+    const uint32_t off = atomicAdd(&cnt->stage_top, (uint32_t)L);
+    if ((int64_t)off + L > stage_cap) {
+      set_error(cnt, POLYLLA_ENOMEM);
+      return;
+    }
+    for (int32_t k = 0; k < L; ++k) stage[off + k] = origin[cyc[(best + k) % L]];
+    ps.plen[i] = L;
+    ps.ppieces[i] = 1;
+    ps.pstart[i] = cyc[best];
+    ps.pstage[i] = (int32_t)off;
+    return;
+  }
+  // pieces: walk from the opened half-edges, each piece once
+  const int32_t nc = 2 * nsplit;
+  int32_t* cand = cyc;  // the recorded cycle is no longer needed
+  {
+    int32_t w = 0;
+    for (int32_t q = 0; q < ntip; ++q) {
+      if (aux[2 * q] < 0) continue;
+      int32_t e = aux[2 * q + 1];
+      cand[w++] = e;
+      cand[w++] = twin[e];
+    }
+    heap_sort(cand, nc);
+  }
+  const int32_t npieces = nsplit + 1;
+  const uint32_t rneed = (uint32_t)(4 * npieces + nc);
+  const uint32_t r0 = atomicAdd(&cnt->arena_top, rneed);
+  if ((int64_t)r0 + rneed > arena_cap) {
+    set_error(cnt, POLYLLA_ENOMEM);
+    return;
+  }
+  int32_t* rec = arena + r0;
+  int32_t* seen = rec + 4 * npieces;
+  for (int32_t k = 0; k < nc; ++k) seen[k] = 0;
+  int32_t np = 0, total = 0;
+  bool bad = false;
+  for (int32_t k = 0; k < nc && !bad; ++k) {
+    if (seen[k]) continue;
+    const int32_t x = cand[k];
+    int32_t h = x, len = 0, minv = 0x7FFFFFFF, minh = -1, mincount = 0;
+    do {
+      int32_t v = origin[h];
+      if (v < minv) {
+        minv = v;
+        minh = h;
+        mincount = 1;
+      } else if (v == minv) {
+        ++mincount;
+      }
+      if (he[h] & kRepaired) {
+        int32_t idx = bsearch_idx(cand, nc, h);
+        if (idx >= 0) seen[idx] = 1;
+      }
+      ++len;
+      h = walk_next(h, nhe, twin, he, cnt);
+    } while (h >= 0 && h != x && len <= nhe);
+    if (h != x || np >= npieces) {
+      set_error(cnt, POLYLLA_EDEGEN);
+      bad = true;
+      break;
+    }
+    if (mincount > 1) {
+      // pinched piece: lexicographically smallest rotation among the
+      // occurrences of its smallest vertex
+      int32_t best = minh, q = walk_next(minh, nhe, twin, he, cnt);
+      for (int32_t m = 1; m < len && q >= 0; ++m) {
+        if (origin[q] == minv && compare_rotations(q, best, len, nhe, twin, origin, he, cnt) < 0) best = q;
+        q = walk_next(q, nhe, twin, he, cnt);
+      }
+      minh = best;
+    }
+    int32_t nxt = walk_next(minh, nhe, twin, he, cnt);
+    rec[4 * np] = minv;
+    rec[4 * np + 1] = nxt >= 0 ? origin[nxt] : 0;
+    rec[4 * np + 2] = minh;
+    rec[4 * np + 3] = len;
+    ++np;
+    total += len;
+  }
+  if (bad || np != npieces) {
+    if (!bad) set_error(cnt, POLYLLA_EDEGEN);
+    return;
+  }
+  // pieces by (first, second) vertex
+  for (int32_t q = 1; q < np; ++q) {
+    int32_t r[4] = {rec[4 * q], rec[4 * q + 1], rec[4 * q + 2], rec[4 * q + 3]};
+    int32_t p = q;
+    while (p > 0 && (rec[4 * (p - 1)] > r[0] || (rec[4 * (p - 1)] == r[0] && rec[4 * (p - 1) + 1] > r[1]))) {
+      for (int m = 0; m < 4; ++m) rec[4 * p + m] = rec[4 * (p - 1) + m];
+      --p;
+    }
+    for (int m = 0; m < 4; ++m) rec[4 * p + m] = r[m];
+  }
+  const uint32_t off = atomicAdd(&cnt->stage_top, (uint32_t)total);
+  if ((int64_t)off + total > stage_cap) {
+    set_error(cnt, POLYLLA_ENOMEM);
+    return;
+  }
+  int32_t w = (int32_t)off;
+  for (int32_t q = 0; q < np; ++q) {
+    int32_t h = rec[4 * q + 2];
+    for (int32_t k = 0; k < rec[4 * q + 3] && h >= 0; ++k) {
+      stage[w++] = origin[h];
+      h = walk_next(h, nhe, twin, he, cnt);
+    }
+  }
+  ps.plen[i] = total;
+  ps.ppieces[i] = np;
+  ps.prec[i] = (int32_t)r0;
+  ps.pstage[i] = (int32_t)off;
+
+}
+
+// Short polygons with a tip or a repeated vertex: one lane each.
+template <bool REPAIR>
+__global__ __launch_bounds__(64) void k_general_small(const int32_t* __restrict__ list, bool from_seeds,
+                                                      int32_t nhe, int64_t nv, const int32_t* __restrict__ twin,
+                                                      const int32_t* __restrict__ origin, uint8_t* __restrict__ he,
+                                                      uint8_t* __restrict__ vtx, int32_t* __restrict__ stage,
+                                                      int64_t stage_cap, int32_t* __restrict__ arena,
+                                                      int64_t arena_cap, PolyState ps,
+                                                      const int32_t* __restrict__ deferred, Counters* cnt) {
   const uint32_t nd = cnt->n_deferred;
   for (uint32_t j = blockIdx.x * 64 + threadIdx.x; j < nd; j += gridDim.x * 64) {
     const int32_t i = deferred[j];
-    ps.plen[i] = 0;
-    ps.ppieces[i] = 0;
-    ps.prec[i] = -1;
-    ps.pstage[i] = 0;
     const int32_t s = from_seeds ? seed_start(list[i], nhe, twin, he, cnt) : list[i];
-    if ((uint32_t)s >= (uint32_t)nhe) continue;
-    // cycle length
-    int32_t L = 0;
-    {
-      int32_t h = s;
-      do {
-        ++L;
-        h = walk_next(h, nhe, twin, he, cnt);
-      } while (h >= 0 && h != s && L <= nhe);
-      if (h != s) {
-        set_error(cnt, POLYLLA_EDEGEN);
-        continue;
-      }
+    general_one<REPAIR>(i, s, nhe, nv, twin, origin, he, vtx, stage, stage_cap, arena, arena_cap, ps, cnt);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Cooperative path: one workgroup per long polygon, the region in LDS.
+//
+// 1. Breadth-first search of the region's dual tree from its seed triangle
+//    through internal edges (depth = longest edge propagation path, short),
+//    collecting the frontier half-edges and a hash map half-edge -> slot.
+// 2. Successor of every frontier half-edge (turning about its end vertex),
+//    in parallel; tips (successor == twin) and barrier edges (twin also in the
+//    region) fall out of the same pass.
+// 3. Repair: middle edge of every tip in parallel, tips ranked by vertex id,
+//    the "a smaller live tip opened an edge at me" rule resolved in that
+//    order, opened edges added to the frontier set, successors recomputed.
+// 4. Pieces are the cycles of the successor map: piece id = smallest slot on
+//    the cycle and ranks from the canonical start, both by pointer jumping;
+//    pieces ordered by their first two vertices; vertices written to staging.
+// Regions beyond the LDS capacity go to general_one on one thread.
+
+constexpr int kBigThreads = 256;
+constexpr int kKCap = 4096;  // triangles of one region
+constexpr int kLCap = 4096;  // frontier half-edges, opened ones included
+constexpr int kHCap = 8192;  // hash slots (power of two)
+constexpr int kPer = kLCap / kBigThreads;
+
+struct BigLds {
+  int32_t q[kKCap];      // BFS queue; then tips (vertex, half-edge); then distances
+  int32_t fh[kLCap];     // frontier half-edges of the region
+  int32_t hkey[kHCap];   // hash keys; then per-piece smallest vertex / second vertex
+  int32_t hval[kLCap];   // hash values (int16 per hash slot); then per-piece start slot
+  int16_t nx[kLCap];     // successor slot; then sorted piece order
+  int16_t jp[kLCap];     // jump pointers; dead flags; piece list
+  int32_t a[kLCap];      // piece id (smallest slot on the cycle); tip order
+  int32_t b[kLCap];      // vertex id of each slot
+  int32_t sc[16];
+};
+
+enum { SC_QLEN, SC_LO, SC_HI, SC_NFH, SC_NTIP, SC_OVER, SC_BAD, SC_NSPLIT, SC_NP, SC_ITEM, SC_SBASE, SC_RBASE };
+
+__device__ __forceinline__ int hash_slot(int32_t key) {
+  return (int)(((uint32_t)key * 2654435761u) >> (32 - 13));
+}
+
+// Open-addressing hash (linear probing) from half-edge id to slot; keys in
+// hkey, values as int16 per hash slot in the hval area.
+__device__ __forceinline__ void hash_insert(BigLds& S, int16_t* hv, int32_t key, int32_t val) {
+  int s = hash_slot(key);
+  for (int k = 0; k < kHCap; ++k) {
+    int32_t old = atomicCAS(&S.hkey[s], -1, key);
+    if (old == -1 || old == key) {
+      hv[s] = (int16_t)val;
+      return;
     }
-    const uint32_t need = 2u * (uint32_t)L;
-    const uint32_t a0 = atomicAdd(&cnt->arena_top, need);
-    if ((int64_t)a0 + need > arena_cap) {
-      set_error(cnt, POLYLLA_ENOMEM);
+    s = (s + 1) & (kHCap - 1);
+  }
+}
+
+__device__ __forceinline__ int32_t hash_find(const BigLds& S, const int16_t* hv, int32_t key) {
+  int s = hash_slot(key);
+  for (int k = 0; k < kHCap; ++k) {
+    int32_t kk = S.hkey[s];
+    if (kk == key) return hv[s];
+    if (kk == -1) return -1;
+    s = (s + 1) & (kHCap - 1);
+  }
+  return -1;
+}
+
+// Successor of frontier half-edge h (global labels), or -1 on invalid input.
+__device__ __forceinline__ int32_t next_frontier(int32_t h, int32_t nhe, const int32_t* __restrict__ twin,
+                                                 const uint8_t* __restrict__ he) {
+  int32_t c = he_next(h);
+  for (int32_t steps = 0; steps <= nhe; ++steps) {
+    if (he[c] & kFrontier) return c;
+    const int32_t tw = twin[c];
+    if ((uint32_t)tw >= (uint32_t)nhe) return -1;
+    c = he_next(tw);
+  }
+  return -1;
+}
+
+template <bool REPAIR>
+__global__ __launch_bounds__(kBigThreads) void k_general_big(
+    const int32_t* __restrict__ list, bool from_seeds, int32_t nhe, int64_t nv, const int32_t* __restrict__ twin,
+    const int32_t* __restrict__ origin, uint8_t* __restrict__ he, uint8_t* __restrict__ vtx,
+    int32_t* __restrict__ stage, int64_t stage_cap, int32_t* __restrict__ arena, int64_t arena_cap, PolyState ps,
+    const int32_t* __restrict__ deferred, int64_t deferred_cap, Counters* cnt) {
+  __shared__ BigLds S;
+  int16_t* hv = reinterpret_cast<int16_t*>(S.hval);  // hash values: int16 per hash slot (kHCap of them)
+  const int tid = threadIdx.x;
+  const uint32_t nbig = cnt->n_big;
+  const int32_t nt = nhe / 3;
+  for (;;) {
+    if (tid == 0) S.sc[SC_ITEM] = (int32_t)atomicAdd(&cnt->big_ticket, 1u);
+    __syncthreads();
+    const uint32_t item = (uint32_t)S.sc[SC_ITEM];
+    if (item >= nbig) break;
+    const int32_t i = deferred[deferred_cap - 1 - item];
+    const int32_t li = list[i];
+    const int32_t t0 = from_seeds ? li : li / 3;
+    // ---- 1. breadth-first search of the region
+    for (int k = tid; k < kHCap; k += kBigThreads) S.hkey[k] = -1;
+    if (tid == 0) {
+      S.q[0] = -1 - 3 * t0;
+      S.sc[SC_QLEN] = 1;
+      S.sc[SC_LO] = 0;
+      S.sc[SC_HI] = 1;
+      S.sc[SC_NFH] = 0;
+      S.sc[SC_NTIP] = 0;
+      S.sc[SC_OVER] = ((uint32_t)t0 >= (uint32_t)nt) ? 1 : 0;
+      S.sc[SC_BAD] = 0;
+      S.sc[SC_NSPLIT] = 0;
+      S.sc[SC_NP] = 0;
+    }
+    __syncthreads();
+    for (;;) {
+      const int lo = S.sc[SC_LO], hi = S.sc[SC_HI];
+      if (lo >= hi || S.sc[SC_OVER]) break;
+      for (int j = lo + tid; j < hi; j += kBigThreads) {
+        const int32_t code = S.q[j];
+        const int32_t t = code < 0 ? (-1 - code) / 3 : code / 3;
+        const int32_t entry = code < 0 ? -1 : code;
+        for (int e = 0; e < 3; ++e) {
+          const int32_t h = 3 * t + e;
+          if (h == entry) continue;
+          if (he[h] & kFrontier) {
+            const int idx = atomicAdd(&S.sc[SC_NFH], 1);
+            if (idx < kLCap) {
+              S.fh[idx] = h;
+              hash_insert(S, hv, h, idx);
+            } else {
+              S.sc[SC_OVER] = 1;
+            }
+          } else {
+            const int32_t tw = twin[h];
+            if ((uint32_t)tw >= (uint32_t)nhe) {
+              S.sc[SC_BAD] = 1;
+              continue;
+            }
+            const int pos = atomicAdd(&S.sc[SC_QLEN], 1);
+            if (pos < kKCap) S.q[pos] = tw;
+            else S.sc[SC_OVER] = 1;
+          }
+        }
+      }
+      __syncthreads();
+      if (tid == 0) {
+        S.sc[SC_LO] = hi;
+        S.sc[SC_HI] = min(S.sc[SC_QLEN], kKCap);
+      }
+      __syncthreads();
+    }
+    if (S.sc[SC_BAD]) {
+      if (tid == 0) {
+        set_error(cnt, POLYLLA_ETOPO);
+        ps.plen[i] = 0;
+        ps.ppieces[i] = 0;
+        ps.prec[i] = -1;
+        ps.pstage[i] = 0;
+      }
+      __syncthreads();
       continue;
     }
-    int32_t* cyc = arena + a0;
-    int32_t* aux = cyc + L;
-    {
-      int32_t h = s;
-      for (int32_t k = 0; k < L; ++k) {
-        cyc[k] = h;
-        h = walk_next(h, nhe, twin, he, cnt);
+    if (S.sc[SC_OVER]) {
+      if (tid == 0) {
+        atomicAdd(&cnt->n_fallback, 1u);
+        const int32_t s = from_seeds ? seed_start(li, nhe, twin, he, cnt) : li;
+        general_one<REPAIR>(i, s, nhe, nv, twin, origin, he, vtx, stage, stage_cap, arena, arena_cap, ps, cnt);
       }
+      __syncthreads();
+      continue;
     }
-    // barrier edges: edge keys that occur twice on the cycle
-    for (int32_t k = 0; k < L; ++k) {
-      int32_t h = cyc[k], tw = twin[h];
-      aux[k] = (uint32_t)tw >= (uint32_t)nhe ? -1 : (h < tw ? h : tw);
-    }
-    heap_sort(aux, L);
-    for (int32_t k = 1; k < L; ++k) {
-      int32_t e = aux[k];
-      if (e >= 0 && e == aux[k - 1]) {
-        const int32_t te = twin[e];
-        he[e] |= kBarrier;
-        if ((uint32_t)te < (uint32_t)nhe) he[te] |= kBarrier;
+    int L = S.sc[SC_NFH];
+    // ---- 2. successors, tips, barrier edges, vertex ids
+    for (int k = tid; k < L; k += kBigThreads) {
+      const int32_t h = S.fh[k];
+      const int32_t c = next_frontier(h, nhe, twin, he);
+      const int32_t j = c < 0 ? -1 : hash_find(S, hv, c);
+      if (j < 0) {
+        S.sc[SC_BAD] = 1;
+        S.nx[k] = (int16_t)k;
+      } else {
+        S.nx[k] = (int16_t)j;
       }
-    }
-    // tips: the next frontier half-edge is the twin of the current one
-    int32_t ntip = 0;
-    for (int32_t k = 0; k < L; ++k) {
-      int32_t h = cyc[k], hn = cyc[k + 1 == L ? 0 : k + 1];
-      if (twin[h] == hn) {
-        int32_t v = origin[hn];
-        if ((uint64_t)(uint32_t)v < (uint64_t)nv) vtx[v] |= kTip;
-        aux[2 * ntip] = v;
-        aux[2 * ntip + 1] = hn;
-        ++ntip;
+      const int32_t tw = twin[h];
+      if (c >= 0 && c == tw) {
+        const int p = atomicAdd(&S.sc[SC_NTIP], 1);
+        S.q[2 * p] = origin[c];
+        S.q[2 * p + 1] = c;
       }
+      if ((uint32_t)tw < (uint32_t)nhe && hash_find(S, hv, tw) >= 0) he[h] |= kBarrier;
+      S.b[k] = origin[h];
     }
-    if (ntip) atomicAdd(&cnt->n_tips, (uint32_t)ntip);
-    int32_t nsplit = 0;
-    if (REPAIR && ntip) {
-      // middle internal edge at every tip: c_{floor(d/2)} clockwise from c0
-      for (int32_t q = 0; q < ntip; ++q) {
-        const int32_t c0 = aux[2 * q + 1];
+    __syncthreads();
+    if (S.sc[SC_BAD]) {
+      if (tid == 0) {
+        set_error(cnt, POLYLLA_EDEGEN);
+        ps.plen[i] = 0;
+        ps.ppieces[i] = 0;
+        ps.prec[i] = -1;
+        ps.pstage[i] = 0;
+      }
+      __syncthreads();
+      continue;
+    }
+    const int ntip = S.sc[SC_NTIP];
+    for (int p = tid; p < ntip; p += kBigThreads) {
+      const int32_t v = S.q[2 * p];
+      if ((uint64_t)(uint32_t)v < (uint64_t)nv) vtx[v] |= kTip;
+    }
+    if (tid == 0 && ntip) atomicAdd(&cnt->n_tips, (uint32_t)ntip);
+    // ---- 3. repair
+    if (REPAIR && ntip > 0) {
+      // middle internal edge at every tip; its far vertex goes to a[2048 + p]
+      for (int p = tid; p < ntip; p += kBigThreads) {
+        const int32_t c0 = S.q[2 * p + 1];
         int32_t d = 0, c = c0;
+        bool okr = true;
         do {
           const int32_t tw = twin[c];
           if ((uint32_t)tw >= (uint32_t)nhe) {
-            d = -1;
+            okr = false;
             break;
           }
           c = he_next(tw);
           ++d;
         } while (c != c0 && d <= nhe);
-        if (d < 0 || c != c0) {
-          set_error(cnt, POLYLLA_ETOPO);
+        if (!okr || c != c0) {
+          S.sc[SC_BAD] = 1;
           d = 0;
         }
         int32_t e = c0;
         for (int32_t k = 0; k < d / 2; ++k) e = he_next(twin[e]);
-        aux[2 * q + 1] = e;
+        S.q[2 * p + 1] = e;
+        S.a[kLCap / 2 + p] = origin[he_next(e)];
       }
-      // tips in increasing vertex id (insertion sort of pairs)
-      for (int32_t q = 1; q < ntip; ++q) {
-        int32_t v = aux[2 * q], e = aux[2 * q + 1], p = q;
-        while (p > 0 && aux[2 * (p - 1)] > v) {
-          aux[2 * p] = aux[2 * (p - 1)];
-          aux[2 * p + 1] = aux[2 * (p - 1) + 1];
-          --p;
+      __syncthreads();
+      // tips ranked by vertex id (ids are distinct): a[rank] = tip
+      for (int p = tid; p < ntip; p += kBigThreads) {
+        const int32_t v = S.q[2 * p];
+        int r = 0;
+        for (int p2 = 0; p2 < ntip; ++p2) r += S.q[2 * p2] < v;
+        S.a[r] = p;
+      }
+      __syncthreads();
+      if (tid == 0) {
+        // live tips in increasing vertex order; a live tip whose opened edge
+        // ends at a larger tip vertex removes that tip
+        for (int r = 0; r < ntip; ++r) S.jp[r] = 0;
+        int ns = 0;
+        for (int r = 0; r < ntip; ++r) {
+          if (S.jp[r]) continue;
+          ++ns;
+          const int32_t x = S.a[kLCap / 2 + S.a[r]];
+          int lo = r + 1, hi = ntip;
+          while (lo < hi) {
+            int mid = (lo + hi) >> 1;
+            if (S.q[2 * S.a[mid]] < x) lo = mid + 1;
+            else hi = mid;
+          }
+          if (lo < ntip && S.q[2 * S.a[lo]] == x) S.jp[lo] = 1;
         }
-        aux[2 * p] = v;
-        aux[2 * p + 1] = e;
+        S.sc[SC_NSPLIT] = ns;
+        if (L + 2 * ns > kLCap) S.sc[SC_OVER] = 1;
       }
-      // a tip on an edge opened for a smaller live tip is no longer a tip
-      for (int32_t q = 0; q < ntip; ++q) {
-        const int32_t v = aux[2 * q];
-        bool dead = false;
-        for (int32_t p = 0; p < q && !dead; ++p) {
-          if (aux[2 * p] < 0) continue;  // dead tips are stored as -1 - v
-          dead = origin[he_next(aux[2 * p + 1])] == v;
-        }
-        if (dead) aux[2 * q] = -1 - v;
-      }
-      for (int32_t q = 0; q < ntip; ++q) {
-        if (aux[2 * q] < 0) continue;
-        int32_t e = aux[2 * q + 1];
-        const int32_t te = twin[e];
-        if ((uint32_t)te >= (uint32_t)nhe) {  // only reachable on an invalid mesh
+      __syncthreads();
+      if (S.sc[SC_BAD]) {
+        if (tid == 0) {
           set_error(cnt, POLYLLA_ETOPO);
-          aux[2 * q] = -1 - aux[2 * q];
-          continue;
+          ps.plen[i] = 0;
+          ps.ppieces[i] = 0;
+          ps.prec[i] = -1;
+          ps.pstage[i] = 0;
         }
+        __syncthreads();
+        continue;
+      }
+      if (S.sc[SC_OVER]) {
+        if (tid == 0) {
+          atomicAdd(&cnt->n_fallback, 1u);
+          const int32_t s = from_seeds ? seed_start(li, nhe, twin, he, cnt) : li;
+          general_one<REPAIR>(i, s, nhe, nv, twin, origin, he, vtx, stage, stage_cap, arena, arena_cap, ps, cnt);
+        }
+        __syncthreads();
+        continue;
+      }
+      // open the edges of the live tips and add both half-edges
+      for (int r = tid; r < ntip; r += kBigThreads) {
+        if (S.jp[r]) continue;
+        const int32_t e = S.q[2 * S.a[r] + 1];
+        const int32_t te = twin[e];
         he[e] |= kFrontier | kRepaired;
         he[te] |= kFrontier | kRepaired;
-        ++nsplit;
+        const int idx = atomicAdd(&S.sc[SC_NFH], 2);
+        S.fh[idx] = e;
+        S.fh[idx + 1] = te;
+        S.b[idx] = origin[e];
+        S.b[idx + 1] = origin[te];
+        hash_insert(S, hv, e, idx);
+        hash_insert(S, hv, te, idx + 1);
       }
-      if (nsplit) atomicAdd(&cnt->n_splits, (uint32_t)nsplit);
+      __syncthreads();
+      if (tid == 0 && S.sc[SC_NSPLIT]) atomicAdd(&cnt->n_splits, (uint32_t)S.sc[SC_NSPLIT]);
+      L = S.sc[SC_NFH];
+      if (S.sc[SC_NSPLIT]) {
+        for (int k = tid; k < L; k += kBigThreads) {
+          const int32_t c = next_frontier(S.fh[k], nhe, twin, he);
+          const int32_t j = c < 0 ? -1 : hash_find(S, hv, c);
+          S.nx[k] = (int16_t)(j < 0 ? k : j);
+          if (j < 0) S.sc[SC_BAD] = 1;
+        }
+        __syncthreads();
+      }
     }
-    if (nsplit == 0) {
-      // one piece: the cycle itself, rotated to its smallest vertex sequence
-      int32_t best = 0, minv = origin[cyc[0]];
-      for (int32_t k = 1; k < L; ++k) {
-        int32_t v = origin[cyc[k]];
-        if (v < minv) {
-          minv = v;
-          best = k;
+    // ---- 4. pieces = cycles of nx. piece id: smallest slot on the cycle
+    for (int k = tid; k < L; k += kBigThreads) {
+      S.a[k] = k;
+      S.jp[k] = S.nx[k];
+    }
+    __syncthreads();
+    for (int span = 1; span < L; span <<= 1) {
+      int32_t na[kPer];
+      int16_t nj[kPer];
+#pragma unroll
+      for (int u = 0; u < kPer; ++u) {
+        const int k = tid + u * kBigThreads;
+        if (k < L) {
+          const int j = S.jp[k];
+          na[u] = min(S.a[k], S.a[j]);
+          nj[u] = S.jp[j];
         }
       }
-      for (int32_t k = best + 1; k < L; ++k) {
-        if (origin[cyc[k]] != minv) continue;
-        for (int32_t m = 1; m < L; ++m) {
-          int32_t a = origin[cyc[(k + m) % L]], b = origin[cyc[(best + m) % L]];
-          if (a != b) {
-            if (a < b) best = k;
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < kPer; ++u) {
+        const int k = tid + u * kBigThreads;
+        if (k < L) {
+          S.a[k] = na[u];
+          S.jp[k] = nj[u];
+        }
+      }
+      __syncthreads();
+    }
+    // per-piece smallest vertex (hkey[p]), its multiplicity (hkey[kLCap + p])
+    // and first slot holding it (hval[p] as int32)
+    int32_t* pmin = S.hkey;
+    int32_t* pcnt = S.hkey + kLCap;
+    int32_t* pstart = S.hval;
+    for (int k = tid; k < L; k += kBigThreads) {
+      pmin[k] = 0x7FFFFFFF;
+      pcnt[k] = 0;
+      pstart[k] = 0x7FFFFFFF;
+    }
+    __syncthreads();
+    for (int k = tid; k < L; k += kBigThreads) atomicMin(&pmin[S.a[k]], S.b[k]);
+    __syncthreads();
+    for (int k = tid; k < L; k += kBigThreads) {
+      const int p = S.a[k];
+      if (S.b[k] == pmin[p]) {
+        atomicAdd(&pcnt[p], 1);
+        atomicMin(&pstart[p], k);
+      }
+    }
+    __syncthreads();
+    // a piece visiting its smallest vertex twice starts at the occurrence
+    // with the lexicographically smallest continuation
+    for (int p = tid; p < L; p += kBigThreads) {
+      if (S.a[p] != p || pcnt[p] < 2) continue;
+      int best = pstart[p];
+      int len = 1;
+      for (int k = S.nx[best]; k != best && len <= L; k = S.nx[k]) ++len;
+      for (int k = S.nx[best], m = 1; m < len; k = S.nx[k], ++m) {
+        if (S.b[k] != pmin[p]) continue;
+        int x = k, y = best;
+        for (int z = 0; z < len; ++z) {
+          if (S.b[x] != S.b[y]) {
+            if (S.b[x] < S.b[y]) best = k;
             break;
+          }
+          x = S.nx[x];
+          y = S.nx[y];
+        }
+      }
+      pstart[p] = best;
+    }
+    __syncthreads();
+    // distance of every slot to the slot before its piece's start
+    for (int k = tid; k < L; k += kBigThreads) {
+      const int n = S.nx[k];
+      const bool last = (n == pstart[S.a[k]]);
+      S.jp[k] = last ? (int16_t)-1 : (int16_t)n;
+      S.q[k] = last ? 0 : 1;
+    }
+    __syncthreads();
+    for (int span = 1; span < L; span <<= 1) {
+      int32_t nd[kPer];
+      int16_t nj[kPer];
+#pragma unroll
+      for (int u = 0; u < kPer; ++u) {
+        const int k = tid + u * kBigThreads;
+        if (k < L) {
+          const int j = S.jp[k];
+          if (j >= 0) {
+            nd[u] = S.q[k] + S.q[j];
+            nj[u] = S.jp[j];
+          } else {
+            nd[u] = S.q[k];
+            nj[u] = -1;
           }
         }
       }
-      const uint32_t off = atomicAdd(&cnt->stage_top, (uint32_t)L);
-      if ((int64_t)off + L > stage_cap) {
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < kPer; ++u) {
+        const int k = tid + u * kBigThreads;
+        if (k < L) {
+          S.q[k] = nd[u];
+          S.jp[k] = nj[u];
+        }
+      }
+      __syncthreads();
+    }
+    // pieces: list (jp), second vertex (pcnt reused)
+    for (int k = tid; k < L; k += kBigThreads) {
+      if (S.a[k] != k) continue;
+      const int idx = atomicAdd(&S.sc[SC_NP], 1);
+      S.jp[idx] = (int16_t)k;
+      pcnt[k] = S.b[S.nx[pstart[k]]];
+    }
+    __syncthreads();
+    const int np = S.sc[SC_NP];
+    // order pieces by (first, second) vertex: nx[rank] = piece
+    for (int u = tid; u < np; u += kBigThreads) {
+      const int p = S.jp[u];
+      const int32_t k0 = pmin[p], k1 = pcnt[p];
+      int r = 0;
+      for (int w = 0; w < np; ++w) {
+        const int p2 = S.jp[w];
+        r += (pmin[p2] < k0) || (pmin[p2] == k0 && pcnt[p2] < k1);
+      }
+      S.nx[r] = (int16_t)p;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int32_t total = 0;
+      for (int r = 0; r < np; ++r) total += S.q[pstart[S.nx[r]]] + 1;
+      const uint32_t sb = atomicAdd(&cnt->stage_top, (uint32_t)total);
+      int32_t rb = -1;
+      bool ok = (int64_t)sb + total <= stage_cap;
+      if (ok && np > 1) {
+        rb = (int32_t)atomicAdd(&cnt->arena_top, (uint32_t)(4 * np));
+        ok = (int64_t)rb + 4 * np <= arena_cap;
+      }
+      if (!ok) {
         set_error(cnt, POLYLLA_ENOMEM);
-        continue;
-      }
-      for (int32_t k = 0; k < L; ++k) stage[off + k] = origin[cyc[(best + k) % L]];
-      ps.plen[i] = L;
-      ps.ppieces[i] = 1;
-      ps.pstart[i] = cyc[best];
-      ps.pstage[i] = (int32_t)off;
-      continue;
-    }
-    // pieces: walk from the opened half-edges, each piece once
-    const int32_t nc = 2 * nsplit;
-    int32_t* cand = cyc;  // the recorded cycle is no longer needed
-    {
-      int32_t w = 0;
-      for (int32_t q = 0; q < ntip; ++q) {
-        if (aux[2 * q] < 0) continue;
-        int32_t e = aux[2 * q + 1];
-        cand[w++] = e;
-        cand[w++] = twin[e];
-      }
-      heap_sort(cand, nc);
-    }
-    const int32_t npieces = nsplit + 1;
-    const uint32_t rneed = (uint32_t)(4 * npieces + nc);
-    const uint32_t r0 = atomicAdd(&cnt->arena_top, rneed);
-    if ((int64_t)r0 + rneed > arena_cap) {
-      set_error(cnt, POLYLLA_ENOMEM);
-      continue;
-    }
-    int32_t* rec = arena + r0;
-    int32_t* seen = rec + 4 * npieces;
-    for (int32_t k = 0; k < nc; ++k) seen[k] = 0;
-    int32_t np = 0, total = 0;
-    bool bad = false;
-    for (int32_t k = 0; k < nc && !bad; ++k) {
-      if (seen[k]) continue;
-      const int32_t x = cand[k];
-      int32_t h = x, len = 0, minv = 0x7FFFFFFF, minh = -1, mincount = 0;
-      do {
-        int32_t v = origin[h];
-        if (v < minv) {
-          minv = v;
-          minh = h;
-          mincount = 1;
-        } else if (v == minv) {
-          ++mincount;
+        S.sc[SC_OVER] = 1;
+      } else {
+        int32_t run = 0;
+        for (int r = 0; r < np; ++r) {
+          const int p = S.nx[r];
+          const int32_t len = S.q[pstart[p]] + 1;
+          if (np > 1) {
+            arena[rb + 4 * r] = pmin[p];
+            arena[rb + 4 * r + 1] = pcnt[p];
+            arena[rb + 4 * r + 2] = S.fh[pstart[p]];
+            arena[rb + 4 * r + 3] = len;
+          }
+          pcnt[p] = run;  // output offset of the piece
+          run += len;
         }
-        if (he[h] & kRepaired) {
-          int32_t idx = bsearch_idx(cand, nc, h);
-          if (idx >= 0) seen[idx] = 1;
-        }
-        ++len;
-        h = walk_next(h, nhe, twin, he, cnt);
-      } while (h >= 0 && h != x && len <= nhe);
-      if (h != x || np >= npieces) {
-        set_error(cnt, POLYLLA_EDEGEN);
-        bad = true;
-        break;
+        ps.plen[i] = total;
+        ps.ppieces[i] = np;
+        ps.pstage[i] = (int32_t)sb;
+        ps.prec[i] = np > 1 ? rb : -1;
+        ps.pstart[i] = np == 1 ? S.fh[pstart[S.nx[0]]] : -1;
       }
-      if (mincount > 1) {
-        // pinched piece: lexicographically smallest rotation among the
-        // occurrences of its smallest vertex
-        int32_t best = minh, q = walk_next(minh, nhe, twin, he, cnt);
-        for (int32_t m = 1; m < len && q >= 0; ++m) {
-          if (origin[q] == minv && compare_rotations(q, best, len, nhe, twin, origin, he, cnt) < 0) best = q;
-          q = walk_next(q, nhe, twin, he, cnt);
-        }
-        minh = best;
+      S.sc[SC_SBASE] = (int32_t)sb;
+    }
+    __syncthreads();
+    if (!S.sc[SC_OVER]) {
+      const int32_t sb = S.sc[SC_SBASE];
+      for (int k = tid; k < L; k += kBigThreads) {
+        const int p = S.a[k];
+        const int32_t len = S.q[pstart[p]] + 1;
+        stage[sb + pcnt[p] + (len - 1 - S.q[k])] = S.b[k];
       }
-      int32_t nxt = walk_next(minh, nhe, twin, he, cnt);
-      rec[4 * np] = minv;
-      rec[4 * np + 1] = nxt >= 0 ? origin[nxt] : 0;
-      rec[4 * np + 2] = minh;
-      rec[4 * np + 3] = len;
-      ++np;
-      total += len;
+    } else if (tid == 0) {
+      ps.plen[i] = 0;
+      ps.ppieces[i] = 0;
+      ps.prec[i] = -1;
+      ps.pstage[i] = 0;
     }
-    if (bad || np != npieces) {
-      if (!bad) set_error(cnt, POLYLLA_EDEGEN);
-      continue;
-    }
-    // pieces by (first, second) vertex
-    for (int32_t q = 1; q < np; ++q) {
-      int32_t r[4] = {rec[4 * q], rec[4 * q + 1], rec[4 * q + 2], rec[4 * q + 3]};
-      int32_t p = q;
-      while (p > 0 && (rec[4 * (p - 1)] > r[0] || (rec[4 * (p - 1)] == r[0] && rec[4 * (p - 1) + 1] > r[1]))) {
-        for (int m = 0; m < 4; ++m) rec[4 * p + m] = rec[4 * (p - 1) + m];
-        --p;
-      }
-      for (int m = 0; m < 4; ++m) rec[4 * p + m] = r[m];
-    }
-    const uint32_t off = atomicAdd(&cnt->stage_top, (uint32_t)total);
-    if ((int64_t)off + total > stage_cap) {
-      set_error(cnt, POLYLLA_ENOMEM);
-      continue;
-    }
-    int32_t w = (int32_t)off;
-    for (int32_t q = 0; q < np; ++q) {
-      int32_t h = rec[4 * q + 2];
-      for (int32_t k = 0; k < rec[4 * q + 3] && h >= 0; ++k) {
-        stage[w++] = origin[h];
-        h = walk_next(h, nhe, twin, he, cnt);
-      }
-    }
-    ps.plen[i] = total;
-    ps.ppieces[i] = np;
-    ps.prec[i] = (int32_t)r0;
-    ps.pstage[i] = (int32_t)off;
+    __syncthreads();
   }
 }
 
@@ -583,14 +1168,20 @@ __global__ __launch_bounds__(256) void k_emit(PolyState ps, const int32_t* __res
 }
 
 template __global__ void k_walk<true>(const int32_t*, int32_t, const int32_t*, const int32_t*, const uint8_t*,
-                                      int32_t*, int64_t, PolyState, int32_t*, Counters*);
+                                      int32_t*, int64_t, PolyState, int32_t*, int64_t, int, Counters*);
 template __global__ void k_walk<false>(const int32_t*, int32_t, const int32_t*, const int32_t*, const uint8_t*,
-                                       int32_t*, int64_t, PolyState, int32_t*, Counters*);
-template __global__ void k_general<true>(const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*,
-                                         uint8_t*, uint8_t*, int32_t*, int64_t, int32_t*, int64_t, PolyState,
-                                         const int32_t*, Counters*);
-template __global__ void k_general<false>(const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*,
-                                          uint8_t*, uint8_t*, int32_t*, int64_t, int32_t*, int64_t, PolyState,
-                                          const int32_t*, Counters*);
+                                       int32_t*, int64_t, PolyState, int32_t*, int64_t, int, Counters*);
+template __global__ void k_general_small<true>(const int32_t*, bool, int32_t, int64_t, const int32_t*,
+                                               const int32_t*, uint8_t*, uint8_t*, int32_t*, int64_t, int32_t*,
+                                               int64_t, PolyState, const int32_t*, Counters*);
+template __global__ void k_general_small<false>(const int32_t*, bool, int32_t, int64_t, const int32_t*,
+                                                const int32_t*, uint8_t*, uint8_t*, int32_t*, int64_t, int32_t*,
+                                                int64_t, PolyState, const int32_t*, Counters*);
+template __global__ void k_general_big<true>(const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*,
+                                             uint8_t*, uint8_t*, int32_t*, int64_t, int32_t*, int64_t, PolyState,
+                                             const int32_t*, int64_t, Counters*);
+template __global__ void k_general_big<false>(const int32_t*, bool, int32_t, int64_t, const int32_t*,
+                                              const int32_t*, uint8_t*, uint8_t*, int32_t*, int64_t, int32_t*,
+                                              int64_t, PolyState, const int32_t*, int64_t, Counters*);
 
 }  // namespace polylla

@@ -31,7 +31,10 @@ struct Counters {
   uint32_t n_splits;
   uint32_t stage_top;     // bump allocator of the staging buffer (ints)
   uint32_t arena_top;     // bump allocator of the general-path arena (ints)
-  uint32_t pad[5];
+  uint32_t n_big;         // polygons handled by the cooperative path
+  uint32_t big_ticket;    // work counter of the cooperative path
+  uint32_t n_fallback;    // cooperative polygons too large for LDS
+  uint32_t pad[2];
 };
 
 // Per-polygon results of the walk / general path, in seed order.

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libpolylla.so")
 OK, EINVAL, ELAYOUT, ETOPO, ECAPACITY, ENOMEM, EHIP, EDEGEN, EINTERNAL = 0, -1, -2, -3, -4, -5, -6, -7, -8
 LONGEST, FRONTIER, TERMINAL, BORDER, BARRIER, REPAIRED = 1, 2, 4, 8, 16, 32
 SEED, TIP = 1, 1
+PARAM_WALK_CAP = 1
 
 
 class PolyllaError(RuntimeError):
@@ -65,13 +66,14 @@ def load() -> ctypes.CDLL:
         lib.polylla_validate.argtypes = [P, ctypes.POINTER(_Tri), P]
         lib.polylla_status.argtypes = [P, P]
         lib.polylla_stats.argtypes = [P, ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
+        lib.polylla_set_param.argtypes = [P, ctypes.c_int, ctypes.c_int64]
         lib.polylla_profile.argtypes = [P, ctypes.c_int]
         lib.polylla_profile_read.argtypes = [P, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
                                              ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
         lib.polylla_strerror.argtypes = [ctypes.c_int]
         lib.polylla_strerror.restype = ctypes.c_char_p
         for f in ("polylla_ctx_create", "polylla_reserve", "polylla_label", "polylla_build", "polylla_repair",
-                  "polylla_mesh", "polylla_validate", "polylla_status", "polylla_stats", "polylla_profile",
+                  "polylla_mesh", "polylla_validate", "polylla_status", "polylla_stats", "polylla_set_param", "polylla_profile",
                   "polylla_profile_read"):
             getattr(lib, f).restype = ctypes.c_int
         _lib = lib
@@ -244,10 +246,13 @@ class Context:
         return code
 
     def stats(self) -> dict:
-        buf = (ctypes.c_int64 * 4)()
-        n = load().polylla_stats(self._h, buf, 4)
-        keys = ["seeds", "general_path", "tips", "splits"]
+        buf = (ctypes.c_int64 * 6)()
+        n = load().polylla_stats(self._h, buf, 6)
+        keys = ["seeds", "general_small", "tips", "splits", "general_big", "fallback"]
         return {k: int(buf[i]) for i, k in enumerate(keys[:n])}
+
+    def set_param(self, param: int, value: int):
+        _check(load().polylla_set_param(self._h, int(param), int(value)), "polylla_set_param")
 
     def profile(self, enable: bool):
         """Start (clearing earlier records) or stop per-kernel event timing."""

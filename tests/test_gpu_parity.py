@@ -27,25 +27,29 @@ def ctx():
     c.close()
 
 
-def gpu_mesh(ctx, mesh):
+def gpu_mesh(ctx, mesh, walk_cap=24):
     from paper_2204_05438_amd import lib
+    ctx.set_param(lib.PARAM_WALK_CAP, walk_cap)
     tri = lib.Tri.from_mesh(mesh)
     labels = lib.Labels.empty(tri)
     out = ctx.mesh(tri, labels)
     ctx.status()
+    ctx.set_param(lib.PARAM_WALK_CAP, 24)
     off, verts, start = out.trimmed()
     return {"he": labels.he.cpu().numpy(), "tri": labels.tri.cpu().numpy(), "vtx": labels.vtx.cpu().numpy(),
             "offsets": off.cpu().numpy(), "verts": verts.cpu().numpy(), "start": start.cpu().numpy(),
             "stats": ctx.stats()}
 
 
-def gpu_three_calls(ctx, mesh):
+def gpu_three_calls(ctx, mesh, walk_cap=24):
     from paper_2204_05438_amd import lib
+    ctx.set_param(lib.PARAM_WALK_CAP, walk_cap)
     tri = lib.Tri.from_mesh(mesh)
     labels = ctx.label(tri)
     pre = ctx.build(tri, labels)
     out = ctx.repair(tri, labels, pre)
     ctx.status()
+    ctx.set_param(lib.PARAM_WALK_CAP, 24)
     po, pv, ps = pre.trimmed()
     fo, fv, fs = out.trimmed()
     return {"he": labels.he.cpu().numpy(), "tri": labels.tri.cpu().numpy(), "vtx": labels.vtx.cpu().numpy(),
@@ -86,13 +90,27 @@ def test_random_small(ctx, kind, seed):
     assert_same(gpu_mesh(ctx, mesh), oracle.oracle_on(mesh), FULL)
 
 
+@pytest.mark.parametrize("walk_cap", [3, 10, 24])
 @pytest.mark.parametrize("kind", ["uniform", "cluster", "lattice"])
-def test_three_calls_match_oracle(ctx, kind):
-    _say(f"label/build/repair {kind}")
+def test_three_calls_match_oracle(ctx, kind, walk_cap):
+    _say(f"label/build/repair {kind} walk_cap {walk_cap}")
     mesh = random_mesh(4242, 3000, kind)
     o = oracle.oracle_on(mesh)
-    r = gpu_three_calls(ctx, mesh)
+    r = gpu_three_calls(ctx, mesh, walk_cap)
     assert_same(r, o, FULL + ["pre_offsets", "pre_verts", "pre_start"])
+
+
+@pytest.mark.parametrize("walk_cap", [1, 3, 6, 12])
+@pytest.mark.parametrize("kind", ["uniform", "cluster", "grid", "lattice"])
+def test_cooperative_path(ctx, kind, walk_cap):
+    """Small walk caps send most polygons through the workgroup kernel."""
+    _say(f"cooperative {kind} walk_cap {walk_cap}")
+    for seed in range(3):
+        mesh = random_mesh(900 + seed, 2000, kind)
+        r = gpu_mesh(ctx, mesh, walk_cap)
+        assert_same(r, oracle.oracle_on(mesh), FULL)
+        if walk_cap <= 3:
+            assert r["stats"]["general_big"] > 0
 
 
 def test_empty(ctx):
@@ -118,6 +136,20 @@ def test_workload_mixed1m(ctx):
     o = oracle.oracle_on(mesh)
     r = gpu_mesh(ctx, mesh)
     assert_same(r, o, FULL)
+    _say("workload mixed1m, walk cap 4")
+    r = gpu_mesh(ctx, mesh, 4)
+    assert_same(r, o, FULL)
+
+
+def test_workload_grid10m(ctx):
+    """The benchmark workload at full size, in the benchmark's configuration."""
+    _say("workload grid10m")
+    mesh = config_mesh("grid10m")
+    r = gpu_mesh(ctx, mesh)
+    _say("grid10m: oracle")
+    o = oracle.oracle_on(mesh)
+    assert_same(r, o, FULL)
+    assert r["stats"]["general_big"] > 0
 
 
 def test_deterministic(ctx):

@@ -14,11 +14,12 @@ __global__ void k_reset(Counters*, uint64_t*, int64_t, const int64_t*);
 __global__ void k_longest(int64_t, int64_t, const double*, const int32_t*, const int32_t*, uint8_t*, uint8_t*,
                           Counters*);
 template <bool COMPUTE>
-__global__ void k_label(int64_t, const int32_t*, const uint8_t*, uint8_t*, uint8_t*, int32_t*, uint64_t*,
-                        Counters*, bool);
+__global__ void k_label(int64_t, const int32_t*, const uint8_t*, uint8_t*, uint8_t*, int32_t*, uint32_t*,
+                        uint64_t*, Counters*, bool);
+__global__ void k_pack_labels(int64_t, const uint8_t*, uint32_t*);
 template <bool FROM_SEEDS>
-__global__ void k_walk(const int32_t*, int32_t, const int32_t*, const int32_t*, const uint8_t*, int32_t*, int64_t,
-                       PolyState, int32_t*, int64_t, int, Counters*);
+__global__ void k_walk(const int32_t*, int32_t, const int32_t*, const int32_t*, const uint32_t*, int32_t*,
+                       int64_t, PolyState, int32_t*, int64_t, int, Counters*);
 template <bool REPAIR>
 __global__ void k_general_small(const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*, uint8_t*,
                                 uint8_t*, int32_t*, int64_t, int32_t*, int64_t, PolyState, const int32_t*,
@@ -26,11 +27,13 @@ __global__ void k_general_small(const int32_t*, bool, int32_t, int64_t, const in
 template <bool REPAIR>
 __global__ void k_general_big(const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*, uint8_t*,
                               uint8_t*, int32_t*, int64_t, int32_t*, int64_t, PolyState, const int32_t*, int64_t,
-                              Counters*);
-__global__ void k_scan_polys(PolyState, int32_t*, int32_t*, uint64_t*, int32_t*, int64_t*, int64_t, int64_t,
-                             Counters*);
-__global__ void k_emit(PolyState, const int32_t*, const int32_t*, const int32_t*, const int32_t*, int32_t*,
-                       int32_t*, int32_t*, int64_t, int64_t, Counters*);
+                              int32_t*, Counters*);
+template <bool REPAIR>
+__global__ void k_general_huge(const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*, uint8_t*,
+                               uint8_t*, int32_t*, int64_t, int32_t*, int64_t, PolyState, const int32_t*,
+                               Counters*);
+__global__ void k_scan_emit(PolyState, uint64_t*, const int32_t*, const int32_t*, int32_t*, int32_t*, int32_t*,
+                            int64_t*, int64_t, int64_t, Counters*);
 __global__ void k_validate(int64_t, int64_t, const int32_t*, const int32_t*, const int32_t*, Counters*);
 
 }  // namespace polylla
@@ -43,9 +46,11 @@ struct polylla_ctx {
   int64_t cap_t = 0;  // triangles
   int64_t cap_v = 0;  // vertices
   uint8_t* lg = nullptr;
+  uint32_t* lab4 = nullptr;  // packed label word per triangle (walk)
   int32_t* seeds = nullptr;
   int32_t* deferred = nullptr;
-  int32_t* poly_arrays = nullptr;  // 7 arrays of cap_t ints
+  int32_t* huge = nullptr;  // long regions beyond the workgroup's LDS
+  int32_t* poly_arrays = nullptr;  // 5 arrays of cap_t ints (PolyState)
   int32_t* stage = nullptr;
   int64_t stage_cap = 0;
   int32_t* arena = nullptr;
@@ -69,15 +74,20 @@ struct polylla_ctx {
 
 namespace {
 
-constexpr int64_t kTile = 1024;
+constexpr int64_t kTile = 2048;  // triangles per tile of k_label
 constexpr size_t kMaxProfiled = 8192;
+constexpr int64_t kScanTileHost = 2048;   // polygons per tile of k_scan_emit
+constexpr int64_t kWalkBlocks = 2048;     // persistent grid of k_walk
+constexpr int64_t kWalkWaves = kWalkBlocks * 4;
+constexpr int64_t kStageChunkHost = 4096; // staging ints a walk wave reserves at a time
 
 enum KernelId {
-  KR_RESET, KR_LONGEST, KR_LABEL, KR_COMPACT, KR_WALK, KR_GENERAL, KR_BIG, KR_SCAN, KR_EMIT, KR_VALIDATE, KR_N
+  KR_RESET, KR_LONGEST, KR_LABEL, KR_COMPACT, KR_PACK, KR_WALK, KR_GENERAL, KR_BIG, KR_HUGE, KR_SCAN, KR_VALIDATE,
+  KR_N
 };
-const char* kKernelNames[KR_N] = {"k_reset",        "k_longest",     "k_label", "k_compact_seeds",
-                                  "k_walk",         "k_general_small", "k_general_big", "k_scan_polys",
-                                  "k_emit",         "k_validate"};
+const char* kKernelNames[KR_N] = {"k_reset",     "k_longest",       "k_label",       "k_compact_seeds",
+                                  "k_pack_labels", "k_walk",     "k_general_small", "k_general_big",
+                                  "k_general_huge", "k_scan_emit", "k_validate"};
 
 // Event pair around one kernel launch when profiling is on.
 struct Prof {
@@ -117,8 +127,10 @@ void dfree(T** p) {
 
 void free_scratch(polylla_ctx* c) {
   dfree(&c->lg);
+  dfree(&c->lab4);
   dfree(&c->seeds);
   dfree(&c->deferred);
+  dfree(&c->huge);
   dfree(&c->poly_arrays);
   dfree(&c->stage);
   dfree(&c->arena);
@@ -139,11 +151,16 @@ int ensure(polylla_ctx* c, int64_t nt, int64_t nv) {
   V = std::max<int64_t>(V, 1024);
   int rc = POLYLLA_OK;
   const int64_t ntiles = (T + kTile - 1) / kTile + 1;
-  c->stage_cap = 3 * T + 64;
+  // polygon vertices (<= 3T), plus what the walk's per-wave staging chunks can
+  // leave unused: a chunk is abandoned only when the next group of cycles
+  // (< 64 * 24 ints) does not fit, so at most 3/5 of each chunk, plus the
+  // last chunk of every wave. Offsets stay int32.
+  c->stage_cap = std::min<int64_t>(5 * T + kWalkWaves * kStageChunkHost + ((int64_t)1 << 20),
+                                   ((int64_t)1 << 31) - 1);
   c->arena_cap = 6 * T + 4096;
   c->n_status = 2 * ntiles;
-  if ((rc = dalloc(&c->lg, T)) || (rc = dalloc(&c->seeds, T)) || (rc = dalloc(&c->deferred, T)) ||
-      (rc = dalloc(&c->poly_arrays, 7 * T)) || (rc = dalloc(&c->stage, c->stage_cap)) ||
+  if ((rc = dalloc(&c->lg, T)) || (rc = dalloc(&c->lab4, T)) || (rc = dalloc(&c->seeds, T)) || (rc = dalloc(&c->deferred, T)) || (rc = dalloc(&c->huge, T / 1024 + 64)) ||
+      (rc = dalloc(&c->poly_arrays, 5 * T)) || (rc = dalloc(&c->stage, c->stage_cap)) ||
       (rc = dalloc(&c->arena, c->arena_cap)) || (rc = dalloc(&c->status, c->n_status)) ||
       (rc = dalloc(&c->he_s, 3 * T)) || (rc = dalloc(&c->tri_s, T)) || (rc = dalloc(&c->vtx_s, V))) {
     free_scratch(c);
@@ -164,8 +181,6 @@ PolyState poly_state(polylla_ctx* c) {
   ps.pstage = b + 4 * c->cap_t;
   return ps;
 }
-int32_t* poly_off(polylla_ctx* c) { return c->poly_arrays + 5 * c->cap_t; }
-int32_t* vert_off(polylla_ctx* c) { return c->poly_arrays + 6 * c->cap_t; }
 
 int check_tri(const polylla_tri* t) {
   if (!t) return POLYLLA_EINVAL;
@@ -209,7 +224,7 @@ int run_label(polylla_ctx* c, const polylla_tri* t, uint8_t* he, uint8_t* tri, u
     // 16-byte loads of twin and 4-byte label stores need aligned arrays
     const bool vec = ((uintptr_t)t->twin % 16 == 0) && ((uintptr_t)he % 4 == 0) && ((uintptr_t)tri % 4 == 0);
     hipLaunchKernelGGL(k_label<true>, dim3((T + kTile - 1) / kTile), dim3(256), 0, s, T, t->twin, c->lg, he, tri,
-                       c->seeds, c->status, c->cnt, vec);
+                       c->seeds, c->lab4, c->status, c->cnt, vec);
   }
   return launched();
 }
@@ -223,12 +238,12 @@ int run_build(polylla_ctx* c, const polylla_tri* t, const int32_t* list, bool fr
   PolyState ps = poly_state(c);
   {
     Prof p(c, s, KR_WALK);
-    const int gw = grid_for(T, 1024, 1 << 16);
+    const int gw = (int)kWalkBlocks;  // persistent: waves take seeds from per-XCD queues
     if (from_seeds)
-      hipLaunchKernelGGL(k_walk<true>, dim3(gw), dim3(256), 0, s, list, nhe, t->twin, t->origin, he, c->stage,
+      hipLaunchKernelGGL(k_walk<true>, dim3(gw), dim3(256), 0, s, list, nhe, t->twin, t->origin, c->lab4, c->stage,
                          c->stage_cap, ps, c->deferred, c->cap_t, c->walk_cap, c->cnt);
     else
-      hipLaunchKernelGGL(k_walk<false>, dim3(gw), dim3(256), 0, s, list, nhe, t->twin, t->origin, he, c->stage,
+      hipLaunchKernelGGL(k_walk<false>, dim3(gw), dim3(256), 0, s, list, nhe, t->twin, t->origin, c->lab4, c->stage,
                          c->stage_cap, ps, c->deferred, c->cap_t, c->walk_cap, c->cnt);
   }
   {
@@ -247,26 +262,31 @@ int run_build(polylla_ctx* c, const polylla_tri* t, const int32_t* list, bool fr
     Prof p(c, s, KR_BIG);
     const int gb = 256;
     if (repair)
-      hipLaunchKernelGGL(k_general_big<true>, dim3(gb), dim3(256), 0, s, list, from_seeds, nhe, t->n_vertices,
+      hipLaunchKernelGGL(k_general_big<true>, dim3(gb), dim3(1024), 0, s, list, from_seeds, nhe, t->n_vertices,
                          t->twin, t->origin, he, vtx, c->stage, c->stage_cap, c->arena, c->arena_cap, ps,
-                         c->deferred, c->cap_t, c->cnt);
+                         c->deferred, c->cap_t, c->huge, c->cnt);
     else
-      hipLaunchKernelGGL(k_general_big<false>, dim3(gb), dim3(256), 0, s, list, from_seeds, nhe, t->n_vertices,
+      hipLaunchKernelGGL(k_general_big<false>, dim3(gb), dim3(1024), 0, s, list, from_seeds, nhe, t->n_vertices,
                          t->twin, t->origin, he, vtx, c->stage, c->stage_cap, c->arena, c->arena_cap, ps,
-                         c->deferred, c->cap_t, c->cnt);
+                         c->deferred, c->cap_t, c->huge, c->cnt);
+  }
+  {
+    Prof p(c, s, KR_HUGE);
+    if (repair)
+      hipLaunchKernelGGL(k_general_huge<true>, dim3(4), dim3(64), 0, s, list, from_seeds, nhe, t->n_vertices,
+                         t->twin, t->origin, he, vtx, c->stage, c->stage_cap, c->arena, c->arena_cap, ps, c->huge,
+                         c->cnt);
+    else
+      hipLaunchKernelGGL(k_general_huge<false>, dim3(4), dim3(64), 0, s, list, from_seeds, nhe, t->n_vertices,
+                         t->twin, t->origin, he, vtx, c->stage, c->stage_cap, c->arena, c->arena_cap, ps, c->huge,
+                         c->cnt);
   }
   {
     Prof p(c, s, KR_SCAN);
-    const int64_t ntiles = (T + kTile - 1) / kTile + 1;
-    hipLaunchKernelGGL(k_scan_polys, dim3(ntiles), dim3(256), 0, s, ps, poly_off(c), vert_off(c),
-                       c->status + c->n_status / 2, out->offsets, out->counts, out->cap_polys, out->cap_verts,
-                       c->cnt);
-  }
-  {
-    Prof p(c, s, KR_EMIT);
-    hipLaunchKernelGGL(k_emit, dim3(grid_for(T, 256, 1 << 16)), dim3(256), 0, s, ps, poly_off(c), vert_off(c),
-                       c->stage, c->arena, out->offsets, out->verts, out->start, out->cap_polys, out->cap_verts,
-                       c->cnt);
+    const int64_t ntiles = (T + kScanTileHost - 1) / kScanTileHost + 1;
+    hipLaunchKernelGGL(k_scan_emit, dim3(ntiles), dim3(256), 0, s, ps, c->status + c->n_status / 2, c->stage,
+                       c->arena, out->offsets, out->verts, out->start, out->counts, out->cap_polys,
+                       out->cap_verts, c->cnt);
   }
   return launched();
 }
@@ -336,7 +356,11 @@ int polylla_build(polylla_ctx* c, const polylla_tri* t, polylla_labels* l, polyl
   if (T > 0) {
     Prof p(c, s, KR_COMPACT);
     hipLaunchKernelGGL(k_label<false>, dim3((T + kTile - 1) / kTile), dim3(256), 0, s, T, t->twin, c->lg, l->he,
-                       l->tri, c->seeds, c->status, c->cnt, false);
+                       l->tri, c->seeds, c->lab4, c->status, c->cnt, false);
+  }
+  if (T > 0) {
+    Prof p(c, s, KR_PACK);
+    hipLaunchKernelGGL(k_pack_labels, dim3(grid_for(T, 256, 1 << 16)), dim3(256), 0, s, T, l->he, c->lab4);
   }
   return run_build(c, t, c->seeds, true, false, l->he, l->vtx, out, s);
 }
@@ -352,6 +376,10 @@ int polylla_repair(polylla_ctx* c, const polylla_tri* t, polylla_labels* l, cons
   if ((rc = ensure(c, T, t->n_vertices))) return rc;
   if (hipSetDevice(c->device) != hipSuccess) return POLYLLA_EHIP;
   reset(c, s, in->counts);
+  if (T > 0) {
+    Prof p(c, s, KR_PACK);
+    hipLaunchKernelGGL(k_pack_labels, dim3(grid_for(T, 256, 1 << 16)), dim3(256), 0, s, T, l->he, c->lab4);
+  }
   return run_build(c, t, in->start, false, true, l->he, l->vtx, out, s);
 }
 

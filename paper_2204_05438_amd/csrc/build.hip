@@ -58,8 +58,10 @@ __device__ __forceinline__ int32_t walk_next(int32_t h, int32_t nhe, const int32
                                              const uint8_t* __restrict__ he, Counters* cnt) {
   int32_t c = he_next(h);
   for (int32_t steps = 0; steps <= nhe; ++steps) {
-    if (he[c] & kFrontier) return c;
-    int32_t tw = twin[c];
+    // label and twin are loaded together: one memory round trip per step
+    const uint8_t lab = he[c];
+    const int32_t tw = twin[c];
+    if (lab & kFrontier) return c;
     if ((uint32_t)tw >= (uint32_t)nhe) {
       set_error(cnt, POLYLLA_ETOPO);
       return -1;
@@ -79,25 +81,29 @@ __device__ __forceinline__ int32_t sel3(int32_t a, int32_t b, int32_t c, int i) 
 // Twin triple, origin triple and label bytes of one triangle: nine
 // independent loads issued together, so a walk pays one memory round trip per
 // triangle it enters.
+struct alignas(4) Int3 {
+  int32_t x, y, z;
+};
+
 struct TriRec {
   int32_t tw0, tw1, tw2;
   int32_t or0, or1, or2;
-  uint32_t lb0, lb1, lb2;
+  uint32_t lab3;  // three label bytes
   __device__ __forceinline__ int32_t tw(int i) const { return sel3(tw0, tw1, tw2, i); }
   __device__ __forceinline__ int32_t org(int i) const { return sel3(or0, or1, or2, i); }
-  __device__ __forceinline__ uint32_t lab(int i) const { return (uint32_t)sel3(lb0, lb1, lb2, i); }
+  __device__ __forceinline__ uint32_t lab(int i) const { return (lab3 >> (8 * i)) & 0xFFu; }
+  // three loads: twin triple, origin triple (12 bytes each) and the label word
   __device__ __forceinline__ void load(int32_t t, const int32_t* __restrict__ twin,
-                                       const int32_t* __restrict__ origin, const uint8_t* __restrict__ he) {
-    const int32_t h = 3 * t;
-    tw0 = twin[h];
-    tw1 = twin[h + 1];
-    tw2 = twin[h + 2];
-    or0 = origin[h];
-    or1 = origin[h + 1];
-    or2 = origin[h + 2];
-    lb0 = he[h];
-    lb1 = he[h + 1];
-    lb2 = he[h + 2];
+                                       const int32_t* __restrict__ origin, const uint32_t* __restrict__ lab4) {
+    const Int3 a = *reinterpret_cast<const Int3*>(twin + 3 * t);
+    const Int3 b = *reinterpret_cast<const Int3*>(origin + 3 * t);
+    lab3 = lab4[t];
+    tw0 = a.x;
+    tw1 = a.y;
+    tw2 = a.z;
+    or0 = b.x;
+    or1 = b.y;
+    or2 = b.z;
   }
 };
 
@@ -109,157 +115,275 @@ constexpr int kSmall = 1;     // short, with a tip or a repeated vertex
 constexpr int kInvalid = 2;   // input error (reported)
 constexpr int kLarge = 3;     // longer than kWalkCap
 
+// Walk kernel as a persistent state machine: every lane walks one polygon at
+// a time and takes the next one as soon as it finishes. The seed range is cut
+// into one contiguous part per XCD (workgroups are dispatched to the 8 XCDs
+// round-robin), each consumed in chunks of 64 seeds through its own counter,
+// so the polygons in flight on an XCD are spatial neighbours that share
+// cache lines in that XCD's L2. Each loop iteration advances every busy lane
+// until it needs the record of the next triangle and issues that load into a
+// second record buffer, so no instruction waits on a load in flight and a
+// wave pays one memory round trip per iteration.
+constexpr int kXcds = 8;
+constexpr int32_t kStageChunk = 4096;  // staging ints a wave reserves at a time
+
 template <bool FROM_SEEDS>
 __global__ __launch_bounds__(256) void k_walk(const int32_t* __restrict__ list, int32_t nhe,
                                               const int32_t* __restrict__ twin,
                                               const int32_t* __restrict__ origin,
-                                              const uint8_t* __restrict__ he, int32_t* __restrict__ stage,
+                                              const uint32_t* __restrict__ lab4, int32_t* __restrict__ stage,
                                               int64_t stage_cap, PolyState ps, int32_t* __restrict__ deferred,
                                               int64_t deferred_cap, int walk_cap, Counters* cnt) {
   __shared__ int32_t buf[kWalkCap][256];
   walk_cap = walk_cap < 1 ? 1 : (walk_cap > kWalkCap ? kWalkCap : walk_cap);
   const int lane = threadIdx.x & 63;
-  const uint32_t R = cnt->n_seeds;
+  const int32_t R = (int32_t)cnt->n_seeds;
   const int32_t nt = nhe / 3;
-  for (int64_t base = (int64_t)blockIdx.x * 256; base < (int64_t)R; base += (int64_t)gridDim.x * 256) {
-    const int64_t i = base + threadIdx.x;
-    int state = kInvalid;
-    int32_t L = 0, minpos = 0, minhe = -1;
-    if (i < (int64_t)R) {
-      const int32_t item = list[i];
-      int32_t t = FROM_SEEDS ? item : item / 3;
-      if ((uint32_t)t < (uint32_t)nt && (FROM_SEEDS || item >= 0)) {
-        TriRec r;
-        r.load(t, twin, origin, he);
-        int cl = -1;
-        int32_t steps = 0;
-        bool ok = true;
-        if (FROM_SEEDS) {
-          // first frontier half-edge of the seed triangle, else turn about its vertex 0
-          if (r.lb0 & kFrontier) cl = 0;
-          else if (r.lb1 & kFrontier) cl = 1;
-          else if (r.lb2 & kFrontier) cl = 2;
-          else {
-            int ci = 0;
-            while (ok && !(r.lab(ci) & kFrontier)) {
-              const int32_t tw = r.tw(ci);
-              if ((uint32_t)tw >= (uint32_t)nhe || ++steps > nhe) {
-                ok = false;
-                break;
-              }
-              t = tw / 3;
-              ci = next_local(tw - 3 * t);
-              r.load(t, twin, origin, he);
-            }
-            cl = ci;
+  const int xcd = blockIdx.x % kXcds;
+  const int32_t part_lo = (int32_t)((int64_t)R * xcd / kXcds);
+  const int32_t part_hi = (int32_t)((int64_t)R * (xcd + 1) / kXcds);
+  uint32_t* ticket = &cnt->xcd_ticket[xcd];
+  // wave-uniform: current chunk [cbase, cbase + clen), next unused slot cpos;
+  // chunk_item: list entry of slot `lane` of the chunk
+  int32_t cbase = 0, clen = 0, cpos = 0, chunk_item = 0;
+  bool more = true;
+  int64_t sbase = 0;
+  int32_t sleft = 0;
+  // lane state
+  int32_t idx = -1;
+  int32_t s = -1, t = 0, ci = 0, twh = -1, L = 0, minv = 0, minpos = 0, minhe = -1, steps = 0;
+  uint64_t sig = 0;  // bit (v & 63) of every staged vertex: repeat pre-filter
+  bool complex = false, pending = false, fresh = false, done = false;
+  int result = kSimple;
+  TriRec r, rn;
+  r.tw0 = r.tw1 = r.tw2 = r.or0 = r.or1 = r.or2 = 0;
+  r.lab3 = 0;
+  rn = r;
+  for (;;) {
+    if (pending) {
+      r = rn;
+      pending = false;
+    }
+    // ---- idle lanes take the next polygons of the chunk (refilled in 64s)
+    const bool want = idx < 0;
+    const uint64_t wmask = __ballot(want);
+    bool got = false;  // this lane took a polygon in this iteration
+    if (wmask && more) {
+      const int nwant = __popcll(wmask);
+      const int rank = __popcll(wmask & ((1ull << lane) - 1ull));
+      int32_t take_old = min(clen - cpos, nwant);
+      // slots of the current chunk
+      const int32_t src_old = cpos + rank;
+      const int32_t item_old = __shfl(chunk_item, src_old & 63, 64);
+      if (want && rank < take_old) {
+        idx = cbase + src_old;
+        got = true;
+        t = item_old;
+      }
+      cpos += take_old;
+      if (take_old < nwant) {
+        int32_t base = 0;
+        if (lane == 0) base = part_lo + 64 * (int32_t)atomicAdd(ticket, 1u);
+        base = __shfl(base, 0, 64);
+        if (base < part_hi) {
+          cbase = base;
+          clen = min(64, part_hi - base);
+          chunk_item = lane < clen ? list[base + lane] : 0;
+          const int32_t src_new = rank - take_old;
+          const int32_t item_new = __shfl(chunk_item, src_new & 63, 64);
+          if (want && rank >= take_old && src_new < clen) {
+            idx = cbase + src_new;
+            got = true;
+            t = item_new;
           }
+          cpos = min(nwant - take_old, clen);
         } else {
-          cl = item - 3 * t;
+          more = false;
+          clen = cpos = 0;
         }
-        if (ok) {
-          const int32_t s = 3 * t + cl;
-          state = kSimple;
-          bool complex = false;
-          int32_t minv = 0x7FFFFFFF;
-          int32_t h = s;
-          do {
-            if (L == walk_cap) {
-              state = kLarge;
-              break;
-            }
-            const int32_t v = r.org(cl);
-            if (!complex) {
-              bool rep = false;
-              for (int j = 0; j < L; ++j) rep |= (buf[j][threadIdx.x] == v);
-              if (rep) {
-                complex = true;
-              } else {
-                buf[L][threadIdx.x] = v;
-                if (v < minv) {
-                  minv = v;
-                  minhe = h;
-                  minpos = L;
-                }
-              }
-            }
-            ++L;
-            const int32_t twh = r.tw(cl);
-            // turn about the end vertex of h through internal edges
-            int ci = next_local(cl);
-            while (!(r.lab(ci) & kFrontier)) {
-              const int32_t tw = r.tw(ci);
-              if ((uint32_t)tw >= (uint32_t)nhe || ++steps > nhe) {
-                ok = false;
-                break;
-              }
-              t = tw / 3;
-              ci = next_local(tw - 3 * t);
-              r.load(t, twin, origin, he);
-            }
-            if (!ok) break;
-            const int32_t c = 3 * t + ci;
-            if (c == twh) complex = true;  // barrier-edge tip at the end of h
-            h = c;
-            cl = ci;
-          } while (h != s);
-          if (!ok) state = kInvalid;
-          else if (state == kSimple && complex) state = kSmall;
+      }
+      if (got) {
+        // new polygon: t holds the list entry (seed triangle or start half-edge)
+        fresh = true;
+        const int32_t item = t;
+        t = FROM_SEEDS ? item : item / 3;
+        L = 0;
+        steps = 0;
+        complex = false;
+        done = false;
+        sig = 0;
+        minv = 0x7FFFFFFF;
+        minpos = 0;
+        minhe = -1;
+        result = kSimple;
+        twh = -1;
+        if ((uint32_t)t < (uint32_t)nt && (FROM_SEEDS || item >= 0)) {
+          rn.load(t, twin, origin, lab4);
+          pending = true;
+          s = FROM_SEEDS ? -1 : item;  // -1: start not found yet
+          ci = FROM_SEEDS ? 0 : item - 3 * t;
+        } else {
+          result = kInvalid;
+          done = true;
         }
-        if (!ok) set_error(cnt, steps > nhe ? POLYLLA_EDEGEN : POLYLLA_ETOPO);
-      } else {
-        set_error(cnt, POLYLLA_ETOPO);
       }
     }
-    // staging slots for complete polygons, one atomic per wave
-    uint32_t need = (i < (int64_t)R && state == kSimple) ? (uint32_t)L : 0u;
-    uint32_t incl = need;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      uint32_t tt = __shfl_up(incl, o, 64);
-      if (lane >= o) incl += tt;
+    // ---- advance every busy lane up to its next load
+    if (idx >= 0 && !pending && !done) {
+      if (fresh && FROM_SEEDS) {
+        // seed triangle: its first frontier half-edge, else turn about vertex 0
+        fresh = false;
+        if (r.lab(0) & kFrontier) ci = 0;
+        else if (r.lab(1) & kFrontier) ci = 1;
+        else if (r.lab(2) & kFrontier) ci = 2;
+        else ci = -1;
+        if (ci < 0) {
+          const int32_t tw = r.tw0;
+          if ((uint32_t)tw >= (uint32_t)nhe) {
+            result = kInvalid;
+            done = true;
+          } else {
+            t = tw / 3;
+            ci = next_local(tw - 3 * t);
+            rn.load(t, twin, origin, lab4);
+            pending = true;
+          }
+        } else {
+          s = 3 * t + ci;
+        }
+      }
+      fresh = false;
+      while (!pending && !done) {
+        if (r.lab(ci) & kFrontier) {
+          const int32_t c = 3 * t + ci;
+          if (s < 0) s = c;  // start found by turning about the seed's vertex 0
+          else if (L > 0) {
+            if (c == twh) complex = true;  // barrier-edge tip
+            if (c == s) {
+              done = true;
+              break;
+            }
+          }
+          if (L == walk_cap) {
+            result = kLarge;
+            done = true;
+            break;
+          }
+          const int32_t v = r.org(ci);
+          if (!complex) {
+            const uint64_t bit = 1ull << (v & 63);
+            bool rep = false;
+            if (sig & bit)
+              for (int j = 0; j < L; ++j) rep |= (buf[j][threadIdx.x] == v);
+            if (rep) {
+              complex = true;
+            } else {
+              sig |= bit;
+              buf[L][threadIdx.x] = v;
+              if (v < minv) {
+                minv = v;
+                minhe = c;
+                minpos = L;
+              }
+            }
+          }
+          ++L;
+          twh = r.tw(ci);
+          ci = next_local(ci);
+        } else {
+          // internal edge: cross it, turning about the current vertex
+          const int32_t tw = r.tw(ci);
+          if ((uint32_t)tw >= (uint32_t)nhe || ++steps > nhe) {
+            result = kInvalid;
+            done = true;
+            break;
+          }
+          t = tw / 3;
+          ci = next_local(tw - 3 * t);
+          rn.load(t, twin, origin, lab4);
+          pending = true;
+        }
+      }
     }
-    uint32_t wbase = 0;
-    if (lane == 63 && incl) wbase = atomicAdd(&cnt->stage_top, incl);
-    wbase = __shfl(wbase, 63, 64);
-    if (i < (int64_t)R) {
-      if (state == kSimple) {
-        const int64_t off = (int64_t)wbase + incl - need;
+    // ---- finished lanes: stage complete polygons, queue the others
+    const bool fin = idx >= 0 && done;
+    if (fin && result == kSimple && complex) result = kSmall;
+    const bool fin_simple = fin && result == kSimple;
+    if (__ballot(fin_simple)) {
+      const uint32_t need = fin_simple ? (uint32_t)L : 0u;
+      uint32_t incl = need;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        uint32_t tt = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += tt;
+      }
+      const int32_t tot = (int32_t)__shfl(incl, 63, 64);
+      if (tot > sleft) {  // new staging chunk for this wave
+        const int32_t want_ints = max(tot, kStageChunk);
+        int64_t nb = 0;
+        if (lane == 0) nb = (int64_t)atomicAdd(&cnt->stage_top, (uint32_t)want_ints);
+        sbase = __shfl(nb, 0, 64);
+        sleft = want_ints;
+      }
+      if (fin_simple) {
+        const int64_t off = sbase + incl - need;
         if (off + L > stage_cap) {
           set_error(cnt, POLYLLA_ENOMEM);
-          state = kInvalid;
+          result = kInvalid;
         } else {
           int pp = minpos;
           for (int k = 0; k < L; ++k) {
             stage[off + k] = buf[pp][threadIdx.x];
             pp = (pp + 1 == L) ? 0 : pp + 1;
           }
-          ps.plen[i] = L;
-          ps.ppieces[i] = 1;
-          ps.pstart[i] = minhe;
-          ps.prec[i] = -1;
-          ps.pstage[i] = (int32_t)off;
+          ps.plen[idx] = L;
+          ps.ppieces[idx] = 1;
+          ps.pstart[idx] = minhe;
+          ps.prec[idx] = -1;
+          ps.pstage[idx] = (int32_t)off;
         }
-      } else if (state == kSmall) {
-        uint32_t q = atomicAdd(&cnt->n_deferred, 1u);
-        deferred[q] = (int32_t)i;
-      } else if (state == kLarge) {
-        uint32_t q = atomicAdd(&cnt->n_big, 1u);
-        deferred[deferred_cap - 1 - q] = (int32_t)i;
       }
-      if (state == kInvalid) {
-        ps.plen[i] = 0;
-        ps.ppieces[i] = 0;
-        ps.prec[i] = -1;
-        ps.pstage[i] = 0;
-      }
+      sbase += tot;
+      sleft -= tot;
     }
+    if (fin) {
+      if (result == kSmall) {
+        const uint32_t q = atomicAdd(&cnt->n_deferred, 1u);
+        deferred[q] = idx;
+        ps.plen[idx] = L;  // cycle length for the per-lane general path
+      } else if (result == kLarge) {
+        const uint32_t q = atomicAdd(&cnt->n_big, 1u);
+        deferred[deferred_cap - 1 - q] = idx;
+      } else if (result == kInvalid) {
+        set_error(cnt, steps > nhe ? POLYLLA_EDEGEN : POLYLLA_ETOPO);
+        ps.plen[idx] = 0;
+        ps.ppieces[idx] = 0;
+        ps.prec[idx] = -1;
+        ps.pstage[idx] = 0;
+      }
+      idx = -1;
+      done = false;
+    }
+    if (!more && __ballot(idx >= 0) == 0ull) break;
   }
 }
 
 // ---------------------------------------------------------------------------
 // general path
 
-__device__ void heap_sort(int32_t* a, int32_t n) {
+// Arrays of the per-lane general path: a plain pointer (global arena) or a
+// column of an LDS array interleaved over the 64 lanes of a block.
+struct GPtr {
+  int32_t* p;
+  __device__ __forceinline__ int32_t& operator[](int32_t k) const { return p[k]; }
+};
+struct LdsCol {
+  int32_t* p;
+  __device__ __forceinline__ int32_t& operator[](int32_t k) const { return p[k * 64]; }
+};
+
+template <typename A>
+__device__ void heap_sort(A a, int32_t n) {
   auto sift = [&](int32_t root, int32_t end) {
     while (2 * root + 1 < end) {
       int32_t child = 2 * root + 1;
@@ -284,7 +408,8 @@ __device__ void heap_sort(int32_t* a, int32_t n) {
 }
 
 // index of x in sorted a[0..n), or -1
-__device__ __forceinline__ int32_t bsearch_idx(const int32_t* a, int32_t n, int32_t x) {
+template <typename A>
+__device__ __forceinline__ int32_t bsearch_idx(A a, int32_t n, int32_t x) {
   int32_t lo = 0, hi = n;
   while (lo < hi) {
     int32_t mid = (lo + hi) >> 1;
@@ -312,37 +437,12 @@ __device__ int compare_rotations(int32_t p, int32_t q, int32_t len, int32_t nhe,
 // half-edge s), by one thread with its data in the global arena. Used for
 // short polygons with a tip or a repeated vertex, and for polygons too large
 // for the cooperative kernel.
-template <bool REPAIR>
-__device__ void general_one(int32_t i, int32_t s, int32_t nhe, int64_t nv, const int32_t* __restrict__ twin,
-                            const int32_t* __restrict__ origin, uint8_t* __restrict__ he, uint8_t* __restrict__ vtx,
-                            int32_t* __restrict__ stage, int64_t stage_cap, int32_t* __restrict__ arena,
-                            int64_t arena_cap, PolyState ps, Counters* cnt) {
-  ps.plen[i] = 0;
-  ps.ppieces[i] = 0;
-  ps.prec[i] = -1;
-  ps.pstage[i] = 0;
-  if ((uint32_t)s >= (uint32_t)nhe) return;
-  // cycle length
-  int32_t L = 0;
-  {
-    int32_t h = s;
-    do {
-      ++L;
-      h = walk_next(h, nhe, twin, he, cnt);
-    } while (h >= 0 && h != s && L <= nhe);
-    if (h != s) {
-      set_error(cnt, POLYLLA_EDEGEN);
-      return;
-    }
-  }
-  const uint32_t need = 2u * (uint32_t)L;
-  const uint32_t a0 = atomicAdd(&cnt->arena_top, need);
-  if ((int64_t)a0 + need > arena_cap) {
-    set_error(cnt, POLYLLA_ENOMEM);
-    return;
-  }
-  int32_t* cyc = arena + a0;
-  int32_t* aux = cyc + L;
+template <bool REPAIR, typename A>
+__device__ void general_core(int32_t i, int32_t s, int32_t L, A cyc, A aux, int32_t nhe, int64_t nv,
+                             const int32_t* __restrict__ twin, const int32_t* __restrict__ origin,
+                             uint8_t* __restrict__ he, uint8_t* __restrict__ vtx, int32_t* __restrict__ stage,
+                             int64_t stage_cap, int32_t* __restrict__ arena, int64_t arena_cap, PolyState ps,
+                             Counters* cnt) {
   {
     int32_t h = s;
     for (int32_t k = 0; k < L; ++k) {
@@ -470,7 +570,7 @@ __device__ void general_one(int32_t i, int32_t s, int32_t nhe, int64_t nv, const
   }
   // pieces: walk from the opened half-edges, each piece once
   const int32_t nc = 2 * nsplit;
-  int32_t* cand = cyc;  // the recorded cycle is no longer needed
+  A cand = cyc;  // the recorded cycle is no longer needed
   {
     int32_t w = 0;
     for (int32_t q = 0; q < ntip; ++q) {
@@ -570,7 +670,43 @@ __device__ void general_one(int32_t i, int32_t s, int32_t nhe, int64_t nv, const
 
 }
 
-// Short polygons with a tip or a repeated vertex: one lane each.
+template <bool REPAIR>
+__device__ void general_one(int32_t i, int32_t s, int32_t nhe, int64_t nv, const int32_t* __restrict__ twin,
+                            const int32_t* __restrict__ origin, uint8_t* __restrict__ he, uint8_t* __restrict__ vtx,
+                            int32_t* __restrict__ stage, int64_t stage_cap, int32_t* __restrict__ arena,
+                            int64_t arena_cap, PolyState ps, Counters* cnt) {
+  ps.plen[i] = 0;
+  ps.ppieces[i] = 0;
+  ps.prec[i] = -1;
+  ps.pstage[i] = 0;
+  if ((uint32_t)s >= (uint32_t)nhe) return;
+  // cycle length
+  int32_t L = 0;
+  {
+    int32_t h = s;
+    do {
+      ++L;
+      h = walk_next(h, nhe, twin, he, cnt);
+    } while (h >= 0 && h != s && L <= nhe);
+    if (h != s) {
+      set_error(cnt, POLYLLA_EDEGEN);
+      return;
+    }
+  }
+  const uint32_t need = 2u * (uint32_t)L;
+  const uint32_t a0 = atomicAdd(&cnt->arena_top, need);
+  if ((int64_t)a0 + need > arena_cap) {
+    set_error(cnt, POLYLLA_ENOMEM);
+    return;
+  }
+  int32_t* cyc = arena + a0;
+  int32_t* aux = cyc + L;
+  general_core<REPAIR>(i, s, L, GPtr{cyc}, GPtr{aux}, nhe, nv, twin, origin, he, vtx, stage, stage_cap, arena,
+                       arena_cap, ps, cnt);
+}
+
+// Short polygons with a tip or a repeated vertex: one lane each, the cycle
+// and its scratch in LDS columns. The walk left the cycle length in plen.
 template <bool REPAIR>
 __global__ __launch_bounds__(64) void k_general_small(const int32_t* __restrict__ list, bool from_seeds,
                                                       int32_t nhe, int64_t nv, const int32_t* __restrict__ twin,
@@ -579,11 +715,23 @@ __global__ __launch_bounds__(64) void k_general_small(const int32_t* __restrict_
                                                       int64_t stage_cap, int32_t* __restrict__ arena,
                                                       int64_t arena_cap, PolyState ps,
                                                       const int32_t* __restrict__ deferred, Counters* cnt) {
+  __shared__ int32_t cyc_s[kWalkCap * 64];
+  __shared__ int32_t aux_s[kWalkCap * 64];
   const uint32_t nd = cnt->n_deferred;
   for (uint32_t j = blockIdx.x * 64 + threadIdx.x; j < nd; j += gridDim.x * 64) {
     const int32_t i = deferred[j];
     const int32_t s = from_seeds ? seed_start(list[i], nhe, twin, he, cnt) : list[i];
-    general_one<REPAIR>(i, s, nhe, nv, twin, origin, he, vtx, stage, stage_cap, arena, arena_cap, ps, cnt);
+    const int32_t L = ps.plen[i];
+    if ((uint32_t)s >= (uint32_t)nhe || L < 1 || L > kWalkCap) {
+      general_one<REPAIR>(i, s, nhe, nv, twin, origin, he, vtx, stage, stage_cap, arena, arena_cap, ps, cnt);
+      continue;
+    }
+    ps.plen[i] = 0;
+    ps.ppieces[i] = 0;
+    ps.prec[i] = -1;
+    ps.pstage[i] = 0;
+    general_core<REPAIR>(i, s, L, LdsCol{cyc_s + threadIdx.x}, LdsCol{aux_s + threadIdx.x}, nhe, nv, twin,
+                         origin, he, vtx, stage, stage_cap, arena, arena_cap, ps, cnt);
   }
 }
 
@@ -602,9 +750,9 @@ __global__ __launch_bounds__(64) void k_general_small(const int32_t* __restrict_
 // 4. Pieces are the cycles of the successor map: piece id = smallest slot on
 //    the cycle and ranks from the canonical start, both by pointer jumping;
 //    pieces ordered by their first two vertices; vertices written to staging.
-// Regions beyond the LDS capacity go to general_one on one thread.
+// Regions beyond the LDS capacity are queued for general_one on one lane.
 
-constexpr int kBigThreads = 256;
+constexpr int kBigThreads = 1024;
 constexpr int kKCap = 4096;  // triangles of one region
 constexpr int kLCap = 4096;  // frontier half-edges, opened ones included
 constexpr int kHCap = 8192;  // hash slots (power of two)
@@ -622,7 +770,7 @@ struct BigLds {
   int32_t sc[16];
 };
 
-enum { SC_QLEN, SC_LO, SC_HI, SC_NFH, SC_NTIP, SC_OVER, SC_BAD, SC_NSPLIT, SC_NP, SC_ITEM, SC_SBASE, SC_RBASE };
+enum { SC_QLEN, SC_LO, SC_HI, SC_NFH, SC_NTIP, SC_OVER, SC_BAD, SC_NSPLIT, SC_NP, SC_ITEM, SC_SBASE, SC_NEND };
 
 __device__ __forceinline__ int hash_slot(int32_t key) {
   return (int)(((uint32_t)key * 2654435761u) >> (32 - 13));
@@ -666,12 +814,66 @@ __device__ __forceinline__ int32_t next_frontier(int32_t h, int32_t nhe, const i
   return -1;
 }
 
+constexpr int32_t kNoChange = -2;
+
+// Successor (next frontier half-edge) of this thread's slots k = tid + u *
+// kBigThreads < L, the chains of all its slots advanced together so that their
+// loads overlap. With `ends` given, a slot below `first_new` is only
+// recomputed when the end vertex of its half-edge is in ends[0..ne); other
+// slots get kNoChange. -1 marks an invalid mesh.
+__device__ __forceinline__ void successors(const BigLds& S, int L, int first_new, const int32_t* ends, int ne,
+                                           int32_t (&succ)[kPer], int32_t nhe, const int32_t* __restrict__ twin,
+                                           const uint8_t* __restrict__ he) {
+  const int tid = threadIdx.x;
+  bool act[kPer];
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int k = tid + u * kBigThreads;
+    act[u] = k < L;
+    if (act[u] && ends && k < first_new) {
+      const int32_t head = S.b[S.nx[k]];
+      bool hit = false;
+      for (int e = 0; e < ne; ++e) hit |= ends[e] == head;
+      act[u] = hit;
+    }
+    succ[u] = act[u] ? he_next(S.fh[k]) : kNoChange;
+  }
+  for (int32_t it = 0; it <= nhe; ++it) {
+    uint8_t lab[kPer];
+    int32_t tw[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int32_t c = act[u] ? succ[u] : 0;
+      lab[u] = he[c];
+      tw[u] = twin[c];
+    }
+    bool any = false;
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      if (!act[u]) continue;
+      if (lab[u] & kFrontier) {
+        act[u] = false;
+      } else if ((uint32_t)tw[u] >= (uint32_t)nhe) {
+        act[u] = false;
+        succ[u] = -1;
+      } else {
+        succ[u] = he_next(tw[u]);
+        any = true;
+      }
+    }
+    if (!any) break;
+  }
+#pragma unroll
+  for (int u = 0; u < kPer; ++u)
+    if (act[u]) succ[u] = -1;  // walk bound exceeded
+}
+
 template <bool REPAIR>
 __global__ __launch_bounds__(kBigThreads) void k_general_big(
     const int32_t* __restrict__ list, bool from_seeds, int32_t nhe, int64_t nv, const int32_t* __restrict__ twin,
     const int32_t* __restrict__ origin, uint8_t* __restrict__ he, uint8_t* __restrict__ vtx,
     int32_t* __restrict__ stage, int64_t stage_cap, int32_t* __restrict__ arena, int64_t arena_cap, PolyState ps,
-    const int32_t* __restrict__ deferred, int64_t deferred_cap, Counters* cnt) {
+    const int32_t* __restrict__ deferred, int64_t deferred_cap, int32_t* __restrict__ huge, Counters* cnt) {
   __shared__ BigLds S;
   int16_t* hv = reinterpret_cast<int16_t*>(S.hval);  // hash values: int16 per hash slot (kHCap of them)
   const int tid = threadIdx.x;
@@ -749,19 +951,20 @@ __global__ __launch_bounds__(kBigThreads) void k_general_big(
       continue;
     }
     if (S.sc[SC_OVER]) {
-      if (tid == 0) {
-        atomicAdd(&cnt->n_fallback, 1u);
-        const int32_t s = from_seeds ? seed_start(li, nhe, twin, he, cnt) : li;
-        general_one<REPAIR>(i, s, nhe, nv, twin, origin, he, vtx, stage, stage_cap, arena, arena_cap, ps, cnt);
-      }
+      if (tid == 0) huge[atomicAdd(&cnt->n_fallback, 1u)] = i;
       __syncthreads();
       continue;
     }
     int L = S.sc[SC_NFH];
     // ---- 2. successors, tips, barrier edges, vertex ids
-    for (int k = tid; k < L; k += kBigThreads) {
+    int32_t succ[kPer];
+    successors(S, L, 0, nullptr, 0, succ, nhe, twin, he);
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int k = tid + u * kBigThreads;
+      if (k >= L) continue;
       const int32_t h = S.fh[k];
-      const int32_t c = next_frontier(h, nhe, twin, he);
+      const int32_t c = succ[u];
       const int32_t j = c < 0 ? -1 : hash_find(S, hv, c);
       if (j < 0) {
         S.sc[SC_BAD] = 1;
@@ -863,11 +1066,7 @@ __global__ __launch_bounds__(kBigThreads) void k_general_big(
         continue;
       }
       if (S.sc[SC_OVER]) {
-        if (tid == 0) {
-          atomicAdd(&cnt->n_fallback, 1u);
-          const int32_t s = from_seeds ? seed_start(li, nhe, twin, he, cnt) : li;
-          general_one<REPAIR>(i, s, nhe, nv, twin, origin, he, vtx, stage, stage_cap, arena, arena_cap, ps, cnt);
-        }
+        if (tid == 0) huge[atomicAdd(&cnt->n_fallback, 1u)] = i;
         __syncthreads();
         continue;
       }
@@ -886,12 +1085,34 @@ __global__ __launch_bounds__(kBigThreads) void k_general_big(
         hash_insert(S, hv, e, idx);
         hash_insert(S, hv, te, idx + 1);
       }
+      // end points of the opened edges (q[2048..] while it has room)
+      if (tid == 0) {
+        int ne = 0;
+        if (2 * ntip + 2 * S.sc[SC_NSPLIT] <= kKCap) {
+          for (int r = 0; r < ntip; ++r) {
+            if (S.jp[r]) continue;
+            const int p = S.a[r];
+            S.q[2 * ntip + ne++] = S.q[2 * p];
+            S.q[2 * ntip + ne++] = S.a[kLCap / 2 + p];
+          }
+        } else {
+          ne = -1;  // too many: recompute every successor
+        }
+        S.sc[SC_NEND] = ne;
+      }
       __syncthreads();
       if (tid == 0 && S.sc[SC_NSPLIT]) atomicAdd(&cnt->n_splits, (uint32_t)S.sc[SC_NSPLIT]);
+      const int L0 = L;
       L = S.sc[SC_NFH];
       if (S.sc[SC_NSPLIT]) {
-        for (int k = tid; k < L; k += kBigThreads) {
-          const int32_t c = next_frontier(S.fh[k], nhe, twin, he);
+        const int ne = S.sc[SC_NEND];
+        successors(S, L, L0, ne >= 0 ? S.q + 2 * ntip : nullptr, ne, succ, nhe, twin, he);
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+          const int k = tid + u * kBigThreads;
+          if (k >= L || succ[u] == kNoChange) continue;
+          const int32_t c = succ[u];
           const int32_t j = c < 0 ? -1 : hash_find(S, hv, c);
           S.nx[k] = (int16_t)(j < 0 ? k : j);
           if (j < 0) S.sc[SC_BAD] = 1;
@@ -1083,28 +1304,58 @@ __global__ __launch_bounds__(kBigThreads) void k_general_big(
 
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void k_scan_polys(PolyState ps, int32_t* __restrict__ poly_off,
-                                                    int32_t* __restrict__ vert_off, uint64_t* status,
-                                                    int32_t* __restrict__ offsets, int64_t* __restrict__ counts,
-                                                    int64_t cap_polys, int64_t cap_verts, Counters* cnt) {
-  constexpr int ITEMS = 4;
+// Long regions beyond the workgroup's LDS capacity: one lane each, global arena.
+template <bool REPAIR>
+__global__ __launch_bounds__(64) void k_general_huge(const int32_t* __restrict__ list, bool from_seeds,
+                                                     int32_t nhe, int64_t nv, const int32_t* __restrict__ twin,
+                                                     const int32_t* __restrict__ origin, uint8_t* __restrict__ he,
+                                                     uint8_t* __restrict__ vtx, int32_t* __restrict__ stage,
+                                                     int64_t stage_cap, int32_t* __restrict__ arena,
+                                                     int64_t arena_cap, PolyState ps, const int32_t* __restrict__ huge,
+                                                     Counters* cnt) {
+  const uint32_t n = cnt->n_fallback;
+  for (uint32_t j = blockIdx.x * 64 + threadIdx.x; j < n; j += gridDim.x * 64) {
+    const int32_t i = huge[j];
+    const int32_t s = from_seeds ? seed_start(list[i], nhe, twin, he, cnt) : list[i];
+    general_one<REPAIR>(i, s, nhe, nv, twin, origin, he, vtx, stage, stage_cap, arena, arena_cap, ps, cnt);
+  }
+}
+
+// Scan and emission in one pass. A tile of kScanTile polygons (in seed order)
+// sums its (pieces, vertices), gets its exclusive prefix by decoupled
+// look-back and writes its part of the CSR output: offsets and start
+// half-edges per polygon, then the vertex range of the whole tile with all
+// threads, each output slot finding its polygon by binary search in LDS so
+// that the stores are coalesced. Blocks beyond the tile count exit before
+// taking a ticket.
+constexpr int kScanItems = 8;
+constexpr int kScanTile = 256 * kScanItems;
+
+__global__ __launch_bounds__(256) void k_scan_emit(PolyState ps, uint64_t* status, const int32_t* __restrict__ stage,
+                                                   const int32_t* __restrict__ arena, int32_t* __restrict__ offsets,
+                                                   int32_t* __restrict__ verts, int32_t* __restrict__ start,
+                                                   int64_t* __restrict__ counts, int64_t cap_polys,
+                                                   int64_t cap_verts, Counters* cnt) {
+  __shared__ int32_t s_voff[kScanTile + 1];
+  __shared__ int32_t s_src[kScanTile];
+  __shared__ int32_t s_ok;
   const uint32_t R = cnt->n_seeds;
-  const uint32_t ntiles = (R + 256 * ITEMS - 1) / (256 * ITEMS);
-  const uint32_t tile = take_tile(&cnt->tile_ticket[1]);
+  const uint32_t ntiles = (R + kScanTile - 1) / kScanTile;
   if (ntiles == 0) {
-    if (tile == 0 && threadIdx.x == 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
       counts[0] = 0;
       counts[1] = 0;
-      if (cap_polys >= 0) offsets[0] = 0;
+      offsets[0] = 0;
     }
     return;
   }
-  if (tile >= ntiles) return;
-  const int64_t i0 = ((int64_t)tile * 256 + threadIdx.x) * ITEMS;
+  if (blockIdx.x >= ntiles) return;
+  const uint32_t tile = take_tile(&cnt->tile_ticket[1]);
+  const int64_t i0 = (int64_t)tile * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  int32_t np[kScanItems], nl[kScanItems];
   uint32_t a = 0, b = 0;
-  int32_t np[ITEMS], nl[ITEMS];
 #pragma unroll
-  for (int j = 0; j < ITEMS; ++j) {
+  for (int j = 0; j < kScanItems; ++j) {
     const int64_t i = i0 + j;
     np[j] = i < R ? ps.ppieces[i] : 0;
     nl[j] = i < R ? ps.plen[i] : 0;
@@ -1112,64 +1363,65 @@ __global__ __launch_bounds__(256) void k_scan_polys(PolyState ps, int32_t* __res
     b += (uint32_t)nl[j];
   }
   uint2 total;
-  uint2 pre = block_exclusive_scan<256>(a, b, &total);
-  uint2 ex = tile_lookback(status, tile, total, cnt);
-  uint32_t ra = ex.x + pre.x, rb = ex.y + pre.y;
+  const uint2 pre = block_exclusive_scan<256>(a, b, &total);
+  const uint2 ex = tile_lookback(status, tile, total, cnt);
+  const int64_t tile_v0 = ex.y, tile_v1 = (int64_t)ex.y + total.y;
+  const int64_t tile_p1 = (int64_t)ex.x + total.x;
+  if (threadIdx.x == 0) s_ok = (tile_p1 <= cap_polys && tile_v1 <= cap_verts) ? 1 : 0;
+  if (tile == ntiles - 1 && threadIdx.x == 0) {
+    counts[0] = tile_p1;
+    counts[1] = tile_v1;
+    if (tile_p1 <= cap_polys) offsets[tile_p1] = (int32_t)tile_v1;
+  }
+  __syncthreads();
+  const bool ok = s_ok != 0;
+  if (!ok && threadIdx.x == 0) set_error(cnt, POLYLLA_ECAPACITY);
+  // per-polygon offsets and start half-edges; tile-local vertex offsets in LDS
+  uint32_t ra = ex.x + pre.x, rb = pre.y;
 #pragma unroll
-  for (int j = 0; j < ITEMS; ++j) {
+  for (int j = 0; j < kScanItems; ++j) {
     const int64_t i = i0 + j;
-    if (i < R) {
-      poly_off[i] = (int32_t)ra;
-      vert_off[i] = (int32_t)rb;
+    const int k = threadIdx.x * kScanItems + j;
+    s_voff[k] = (int32_t)rb;
+    s_src[k] = (i < R && nl[j] > 0) ? ps.pstage[i] : 0;
+    if (ok && i < R && np[j] > 0) {
+      const int32_t r = ps.prec[i];
+      const int32_t vg = (int32_t)(tile_v0 + rb);
+      if (r < 0) {
+        offsets[ra] = vg;
+        if (start) start[ra] = ps.pstart[i];
+      } else {
+        const int32_t* rec = arena + r;
+        int32_t acc = 0;
+        for (int32_t q = 0; q < np[j]; ++q) {
+          offsets[ra + q] = vg + acc;
+          if (start) start[ra + q] = rec[4 * q + 2];
+          acc += rec[4 * q + 3];
+        }
+      }
     }
     ra += (uint32_t)np[j];
     rb += (uint32_t)nl[j];
   }
-  if (tile == ntiles - 1 && threadIdx.x == 0) {
-    const int64_t F = (int64_t)ex.x + total.x, S = (int64_t)ex.y + total.y;
-    counts[0] = F;
-    counts[1] = S;
-    if (F <= cap_polys) offsets[F] = (int32_t)S;
-    if (F > cap_polys || S > cap_verts) set_error(cnt, POLYLLA_ECAPACITY);
+  if (threadIdx.x == 255) s_voff[kScanTile] = (int32_t)rb;
+  __syncthreads();
+  if (!ok) return;
+  // the tile's vertex range, coalesced
+  const int32_t nv_tile = (int32_t)total.y;
+  for (int32_t k = threadIdx.x; k < nv_tile; k += 256) {
+    int lo = 0, hi = kScanTile;  // last polygon with s_voff <= k
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (s_voff[mid] <= k) lo = mid;
+      else hi = mid;
+    }
+    verts[tile_v0 + k] = stage[s_src[lo] + (k - s_voff[lo])];
   }
 }
 
-__global__ __launch_bounds__(256) void k_emit(PolyState ps, const int32_t* __restrict__ poly_off,
-                                              const int32_t* __restrict__ vert_off,
-                                              const int32_t* __restrict__ stage, const int32_t* __restrict__ arena,
-                                              int32_t* __restrict__ offsets, int32_t* __restrict__ verts,
-                                              int32_t* __restrict__ start, int64_t cap_polys, int64_t cap_verts,
-                                              Counters* cnt) {
-  const uint32_t R = cnt->n_seeds;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (int64_t)R;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t p0 = poly_off[i], v0 = vert_off[i], np = ps.ppieces[i], len = ps.plen[i];
-    if (np == 0) continue;
-    if ((int64_t)p0 + np > cap_polys || (int64_t)v0 + len > cap_verts) {
-      set_error(cnt, POLYLLA_ECAPACITY);
-      continue;
-    }
-    const int32_t* src = stage + ps.pstage[i];
-    for (int32_t k = 0; k < len; ++k) verts[v0 + k] = src[k];
-    const int32_t r = ps.prec[i];
-    if (r < 0) {
-      offsets[p0] = v0;
-      if (start) start[p0] = ps.pstart[i];
-    } else {
-      const int32_t* rec = arena + r;
-      int32_t acc = 0;
-      for (int32_t q = 0; q < np; ++q) {
-        offsets[p0 + q] = v0 + acc;
-        if (start) start[p0 + q] = rec[4 * q + 2];
-        acc += rec[4 * q + 3];
-      }
-    }
-  }
-}
-
-template __global__ void k_walk<true>(const int32_t*, int32_t, const int32_t*, const int32_t*, const uint8_t*,
+template __global__ void k_walk<true>(const int32_t*, int32_t, const int32_t*, const int32_t*, const uint32_t*,
                                       int32_t*, int64_t, PolyState, int32_t*, int64_t, int, Counters*);
-template __global__ void k_walk<false>(const int32_t*, int32_t, const int32_t*, const int32_t*, const uint8_t*,
+template __global__ void k_walk<false>(const int32_t*, int32_t, const int32_t*, const int32_t*, const uint32_t*,
                                        int32_t*, int64_t, PolyState, int32_t*, int64_t, int, Counters*);
 template __global__ void k_general_small<true>(const int32_t*, bool, int32_t, int64_t, const int32_t*,
                                                const int32_t*, uint8_t*, uint8_t*, int32_t*, int64_t, int32_t*,
@@ -1179,9 +1431,15 @@ template __global__ void k_general_small<false>(const int32_t*, bool, int32_t, i
                                                 int64_t, PolyState, const int32_t*, Counters*);
 template __global__ void k_general_big<true>(const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*,
                                              uint8_t*, uint8_t*, int32_t*, int64_t, int32_t*, int64_t, PolyState,
-                                             const int32_t*, int64_t, Counters*);
+                                             const int32_t*, int64_t, int32_t*, Counters*);
 template __global__ void k_general_big<false>(const int32_t*, bool, int32_t, int64_t, const int32_t*,
                                               const int32_t*, uint8_t*, uint8_t*, int32_t*, int64_t, int32_t*,
-                                              int64_t, PolyState, const int32_t*, int64_t, Counters*);
+                                              int64_t, PolyState, const int32_t*, int64_t, int32_t*, Counters*);
+template __global__ void k_general_huge<true>(const int32_t*, bool, int32_t, int64_t, const int32_t*,
+                                              const int32_t*, uint8_t*, uint8_t*, int32_t*, int64_t, int32_t*,
+                                              int64_t, PolyState, const int32_t*, Counters*);
+template __global__ void k_general_huge<false>(const int32_t*, bool, int32_t, int64_t, const int32_t*,
+                                               const int32_t*, uint8_t*, uint8_t*, int32_t*, int64_t, int32_t*,
+                                               int64_t, PolyState, const int32_t*, Counters*);
 
 }  // namespace polylla

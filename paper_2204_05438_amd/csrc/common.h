@@ -34,7 +34,9 @@ struct Counters {
   uint32_t n_big;         // polygons handled by the cooperative path
   uint32_t big_ticket;    // work counter of the cooperative path
   uint32_t n_fallback;    // cooperative polygons too large for LDS
-  uint32_t pad[2];
+  uint32_t walk_ticket;   // (unused slot)
+  uint32_t pad[1];
+  uint32_t xcd_ticket[8]; // walk work queues, one per XCD
 };
 
 // Per-polygon results of the walk / general path, in seed order.

@@ -118,46 +118,55 @@ __device__ __forceinline__ uint32_t label_triangle(int64_t t, int m, const int32
   return packed;
 }
 
+constexpr int kLabelItems = 8;  // triangles per thread of k_label (multiple of 4)
+
 // COMPUTE = true : labels from twin + Max, then seed compaction.
 // COMPUTE = false: seed compaction only, from existing triangle labels.
 template <bool COMPUTE>
 __global__ __launch_bounds__(256) void k_label(int64_t nt, const int32_t* __restrict__ twin,
                                                const uint8_t* __restrict__ lg, uint8_t* __restrict__ he,
                                                uint8_t* __restrict__ tri, int32_t* __restrict__ seeds,
-                                               uint64_t* status, Counters* cnt, bool vec) {
-  constexpr int ITEMS = 4;
+                                               uint32_t* __restrict__ lab4, uint64_t* status, Counters* cnt,
+                                               bool vec) {
+  constexpr int ITEMS = kLabelItems;
   const uint32_t tile = take_tile(&cnt->tile_ticket[0]);
   const int64_t t0 = ((int64_t)tile * 256 + threadIdx.x) * ITEMS;
   const int32_t nhe = (int32_t)(3 * nt);
   bool sd[ITEMS];
   if (COMPUTE) {
     if (vec && t0 + ITEMS <= nt) {
+      // ITEMS triangles: 3*ITEMS twins as int4, ITEMS Max bytes and labels as words
       int32_t tw[3 * ITEMS];
       const int4* tw4 = reinterpret_cast<const int4*>(twin + 3 * t0);
 #pragma unroll
-      for (int k = 0; k < 3; ++k) {
+      for (int k = 0; k < 3 * ITEMS / 4; ++k) {
         int4 q = tw4[k];
         tw[4 * k] = q.x;
         tw[4 * k + 1] = q.y;
         tw[4 * k + 2] = q.z;
         tw[4 * k + 3] = q.w;
       }
-      uint32_t mm = *reinterpret_cast<const uint32_t*>(lg + t0);
-      uint32_t lab[ITEMS];
+      uint32_t mm[ITEMS / 4];
 #pragma unroll
-      for (int j = 0; j < ITEMS; ++j)
-        lab[j] = label_triangle(t0 + j, (mm >> (8 * j)) & 0xFF, tw + 3 * j, lg, nhe, cnt, &sd[j]);
-      // 12 label bytes of 4 triangles -> three 32-bit words
-      uint32_t w0 = lab[0] | (lab[1] << 24);
-      uint32_t w1 = (lab[1] >> 8) | (lab[2] << 16);
-      uint32_t w2 = (lab[2] >> 16) | (lab[3] << 8);
+      for (int k = 0; k < ITEMS / 4; ++k) mm[k] = reinterpret_cast<const uint32_t*>(lg + t0)[k];
       uint32_t* he4 = reinterpret_cast<uint32_t*>(he + 3 * t0);
-      he4[0] = w0;
-      he4[1] = w1;
-      he4[2] = w2;
-      uint32_t sw = (sd[0] ? kSeed : 0u) | ((sd[1] ? kSeed : 0u) << 8) | ((sd[2] ? kSeed : 0u) << 16) |
-                    ((sd[3] ? kSeed : 0u) << 24);
-      *reinterpret_cast<uint32_t*>(tri + t0) = sw;
+      uint32_t* tr4 = reinterpret_cast<uint32_t*>(tri + t0);
+#pragma unroll
+      for (int g = 0; g < ITEMS / 4; ++g) {
+        uint32_t lab[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          lab[j] = label_triangle(t0 + 4 * g + j, (mm[g] >> (8 * j)) & 0xFF, tw + 3 * (4 * g + j), lg, nhe, cnt,
+                                  &sd[4 * g + j]);
+        // packed label word per triangle for the walk (aligned 16-byte store)
+        reinterpret_cast<uint4*>(lab4 + t0)[g] = make_uint4(lab[0], lab[1], lab[2], lab[3]);
+        // 12 label bytes of 4 triangles -> three 32-bit words
+        he4[3 * g] = lab[0] | (lab[1] << 24);
+        he4[3 * g + 1] = (lab[1] >> 8) | (lab[2] << 16);
+        he4[3 * g + 2] = (lab[2] >> 16) | (lab[3] << 8);
+        tr4[g] = (sd[4 * g] ? kSeed : 0u) | ((sd[4 * g + 1] ? kSeed : 0u) << 8) |
+                 ((sd[4 * g + 2] ? kSeed : 0u) << 16) | ((sd[4 * g + 3] ? kSeed : 0u) << 24);
+      }
     } else {
 #pragma unroll
       for (int j = 0; j < ITEMS; ++j) {
@@ -166,6 +175,7 @@ __global__ __launch_bounds__(256) void k_label(int64_t nt, const int32_t* __rest
         if (t >= nt) continue;
         int32_t tw[3] = {twin[3 * t], twin[3 * t + 1], twin[3 * t + 2]};
         uint32_t lab = label_triangle(t, lg[t], tw, lg, nhe, cnt, &sd[j]);
+        lab4[t] = lab;
         he[3 * t] = (uint8_t)lab;
         he[3 * t + 1] = (uint8_t)(lab >> 8);
         he[3 * t + 2] = (uint8_t)(lab >> 16);
@@ -189,7 +199,7 @@ __global__ __launch_bounds__(256) void k_label(int64_t nt, const int32_t* __rest
 #pragma unroll
   for (int j = 0; j < ITEMS; ++j)
     if (sd[j]) seeds[pos++] = (int32_t)(t0 + j);
-  const int64_t ntiles = (nt + 256 * ITEMS - 1) / (256 * ITEMS);
+  const int64_t ntiles = (nt + 256 * ITEMS - 1) / (256 * ITEMS);  // tiles of this launch
   if (tile == ntiles - 1 && threadIdx.x == 0) cnt->n_seeds = ex.x + total.x;
 }
 
@@ -217,8 +227,16 @@ __global__ __launch_bounds__(256) void k_validate(int64_t nhe, int64_t nv, const
 }
 
 template __global__ void k_label<true>(int64_t, const int32_t*, const uint8_t*, uint8_t*, uint8_t*, int32_t*,
-                                       uint64_t*, Counters*, bool);
+                                       uint32_t*, uint64_t*, Counters*, bool);
 template __global__ void k_label<false>(int64_t, const int32_t*, const uint8_t*, uint8_t*, uint8_t*, int32_t*,
-                                        uint64_t*, Counters*, bool);
+                                        uint32_t*, uint64_t*, Counters*, bool);
+
+// Packed label word per triangle (three label bytes) from the half-edge
+// labels, for calls that start from existing labels.
+__global__ __launch_bounds__(256) void k_pack_labels(int64_t nt, const uint8_t* __restrict__ he,
+                                                     uint32_t* __restrict__ lab4) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nt; t += (int64_t)gridDim.x * blockDim.x)
+    lab4[t] = (uint32_t)he[3 * t] | ((uint32_t)he[3 * t + 1] << 8) | ((uint32_t)he[3 * t + 2] << 16);
+}
 
 }  // namespace polylla

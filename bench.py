@@ -53,6 +53,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="grid10m")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--param", action="append", default=[],
+                    help="context parameter NAME=VALUE (walk_cap, walk_blocks)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -76,6 +78,9 @@ def main():
     labels = lib.Labels.empty(tri)
     out = lib.Polys.empty(tri, with_start=True)
     ctx.reserve(tri.n_halfedges, tri.n_vertices)
+    for kv in args.param:
+        name, val = kv.split("=")
+        ctx.set_param({"walk_cap": lib.PARAM_WALK_CAP, "walk_blocks": lib.PARAM_WALK_BLOCKS}[name], int(val))
     torch.cuda.synchronize()
     log("inputs resident on the device")
 

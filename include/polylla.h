@@ -149,6 +149,19 @@ int polylla_repair(polylla_ctx *ctx, const polylla_tri *tri, polylla_labels *lab
 int polylla_mesh(polylla_ctx *ctx, const polylla_tri *tri, polylla_labels *labels,
                  polylla_polys *out, hipStream_t stream);
 
+/* Many triangulations in one call (packed CSR of meshes). The meshes are
+ * stored one after another in the arrays of `tri`, with GLOBAL indices: mesh m
+ * owns vertices [vtx_off[m], vtx_off[m+1]) and half-edges [he_off[m],
+ * he_off[m+1]) (multiples of 3, increasing), and its twin and origin entries
+ * point into its own ranges, so no edge joins two meshes. Since terminal-edge
+ * regions never cross a mesh boundary, the whole batch runs as one launch
+ * sequence over the union. Output polygons carry global vertex ids, meshes in
+ * order; poly_off (device int64 [n_meshes + 1]) receives the first polygon of
+ * every mesh and F at the end. vtx_off is a device int64 [n_meshes + 1] array.
+ * Same results as n_meshes calls of polylla_mesh (up to the index offsets). */
+int polylla_mesh_batched(polylla_ctx *ctx, const polylla_tri *tri, int64_t n_meshes, const int64_t *vtx_off,
+                         polylla_labels *labels, polylla_polys *out, int64_t *poly_off, hipStream_t stream);
+
 /* Full input check on the device (layout of next, index ranges, twin
  * involution and endpoints). Waits for the stream; returns the first error. */
 int polylla_validate(polylla_ctx *ctx, const polylla_tri *tri, hipStream_t stream);
@@ -170,6 +183,10 @@ int polylla_stats(polylla_ctx *ctx, int64_t *out, int n);
  * values route more polygons through the cooperative kernel (used by tests).
  * Returns POLYLLA_EINVAL for an unknown parameter or a value out of range. */
 #define POLYLLA_PARAM_WALK_CAP 1
+/* POLYLLA_PARAM_WALK_BLOCKS (8..2048, multiple of 8): workgroups of 256
+ * threads of the walk kernel; fewer keep the polygons in flight within each
+ * XCD's L2, more hide more latency. */
+#define POLYLLA_PARAM_WALK_BLOCKS 2
 int polylla_set_param(polylla_ctx *ctx, int param, int64_t value);
 
 /* Per-kernel GPU timing with HIP events, for benchmarks (off by default).

@@ -9,6 +9,7 @@ from .gen import (  # noqa: F401
     build_native,
     mesh_from_points,
     mesh_from_triangles,
+    pack_meshes,
     config_points,
     config_mesh,
     batch_sizes,

@@ -262,6 +262,31 @@ def request_points(n: int, kind: str, seed: int) -> np.ndarray:
     return _clusters(rng, n, 4, 0.05)
 
 
+def pack_meshes(meshes):
+    """Concatenate meshes into one packed CSR of meshes with global indices:
+    returns (mesh, vtx_off, he_off) where mesh m owns vertices
+    vtx_off[m]:vtx_off[m+1] and half-edges he_off[m]:he_off[m+1]."""
+    V = np.array([m.n_vertices for m in meshes], dtype=np.int64)
+    H = np.array([m.n_halfedges for m in meshes], dtype=np.int64)
+    vtx_off = np.zeros(len(meshes) + 1, np.int64)
+    he_off = np.zeros(len(meshes) + 1, np.int64)
+    np.cumsum(V, out=vtx_off[1:])
+    np.cumsum(H, out=he_off[1:])
+    if he_off[-1] >= 2 ** 31 or vtx_off[-1] >= 2 ** 31:
+        raise ValueError("packed batch exceeds 2^31 half-edges or vertices")
+    xy = np.empty((int(vtx_off[-1]), 2), np.float64)
+    origin = np.empty(int(he_off[-1]), np.int32)
+    twin = np.empty(int(he_off[-1]), np.int32)
+    for k, m in enumerate(meshes):
+        a, b = int(he_off[k]), int(he_off[k + 1])
+        xy[vtx_off[k]:vtx_off[k + 1]] = m.xy
+        origin[a:b] = m.origin + np.int32(vtx_off[k])
+        twin[a:b] = np.where(m.twin >= 0, m.twin + np.int32(a), -1)
+    packed = Mesh(xy=xy, origin=origin, twin=twin, next=_grouped_next(int(he_off[-1])), lattice=None,
+                  meta={"n_meshes": len(meshes)})
+    return packed, vtx_off, he_off
+
+
 # --------------------------------------------------------------------------
 # Validation of the half-edge layout
 # --------------------------------------------------------------------------

@@ -35,6 +35,8 @@ __global__ void k_general_huge(const int32_t*, bool, int32_t, int64_t, const int
 __global__ void k_scan_emit(PolyState, uint64_t*, const int32_t*, const int32_t*, int32_t*, int32_t*, int32_t*,
                             int64_t*, int64_t, int64_t, Counters*);
 __global__ void k_validate(int64_t, int64_t, const int32_t*, const int32_t*, const int32_t*, Counters*);
+__global__ void k_batch_offsets(int64_t, const int64_t*, const int32_t*, const int32_t*, const int64_t*, int64_t,
+                                int64_t, int64_t*);
 
 }  // namespace polylla
 
@@ -50,7 +52,7 @@ struct polylla_ctx {
   int32_t* seeds = nullptr;
   int32_t* deferred = nullptr;
   int32_t* huge = nullptr;  // long regions beyond the workgroup's LDS
-  int32_t* poly_arrays = nullptr;  // 5 arrays of cap_t ints (PolyState)
+  int32_t* poly_arrays = nullptr;  // per-polygon records: 4 ints + 1 int per polygon (PolyState)
   int32_t* stage = nullptr;
   int64_t stage_cap = 0;
   int32_t* arena = nullptr;
@@ -62,6 +64,7 @@ struct polylla_ctx {
   uint8_t* vtx_s = nullptr;
   Counters last{};
   int walk_cap = 24;  // vertices a lane walks before handing a polygon to a workgroup
+  int walk_blocks = 512;  // persistent grid of the walk kernel (swept: 256..2048, 512 best at 10M)
   // event profiling
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;
@@ -83,11 +86,11 @@ constexpr int64_t kStageChunkHost = 4096; // staging ints a walk wave reserves a
 
 enum KernelId {
   KR_RESET, KR_LONGEST, KR_LABEL, KR_COMPACT, KR_PACK, KR_WALK, KR_GENERAL, KR_BIG, KR_HUGE, KR_SCAN, KR_VALIDATE,
-  KR_N
+  KR_BATCH, KR_N
 };
 const char* kKernelNames[KR_N] = {"k_reset",     "k_longest",       "k_label",       "k_compact_seeds",
                                   "k_pack_labels", "k_walk",     "k_general_small", "k_general_big",
-                                  "k_general_huge", "k_scan_emit", "k_validate"};
+                                  "k_general_huge", "k_scan_emit", "k_validate",     "k_batch_offsets"};
 
 // Event pair around one kernel launch when profiling is on.
 struct Prof {
@@ -151,10 +154,8 @@ int ensure(polylla_ctx* c, int64_t nt, int64_t nv) {
   V = std::max<int64_t>(V, 1024);
   int rc = POLYLLA_OK;
   const int64_t ntiles = (T + kTile - 1) / kTile + 1;
-  // polygon vertices (<= 3T), plus what the walk's per-wave staging chunks can
-  // leave unused: a chunk is abandoned only when the next group of cycles
-  // (< 64 * 24 ints) does not fit, so at most 3/5 of each chunk, plus the
-  // last chunk of every wave. Offsets stay int32.
+  // polygon vertices (<= 3T) and the general paths' staging, plus the unused
+  // tail of the last staging chunk of every walk wave. Offsets stay int32.
   c->stage_cap = std::min<int64_t>(5 * T + kWalkWaves * kStageChunkHost + ((int64_t)1 << 20),
                                    ((int64_t)1 << 31) - 1);
   c->arena_cap = 6 * T + 4096;
@@ -173,12 +174,8 @@ int ensure(polylla_ctx* c, int64_t nt, int64_t nv) {
 
 PolyState poly_state(polylla_ctx* c) {
   PolyState ps;
-  int32_t* b = c->poly_arrays;
-  ps.pstart = b;
-  ps.plen = b + c->cap_t;
-  ps.ppieces = b + 2 * c->cap_t;
-  ps.prec = b + 3 * c->cap_t;
-  ps.pstage = b + 4 * c->cap_t;
+  ps.rec = reinterpret_cast<int4*>(c->poly_arrays);
+  ps.prec = c->poly_arrays + 4 * c->cap_t;
   return ps;
 }
 
@@ -238,7 +235,7 @@ int run_build(polylla_ctx* c, const polylla_tri* t, const int32_t* list, bool fr
   PolyState ps = poly_state(c);
   {
     Prof p(c, s, KR_WALK);
-    const int gw = (int)kWalkBlocks;  // persistent: waves take seeds from per-XCD queues
+    const int gw = c->walk_blocks;  // persistent: waves take seeds from per-XCD queues
     if (from_seeds)
       hipLaunchKernelGGL(k_walk<true>, dim3(gw), dim3(256), 0, s, list, nhe, t->twin, t->origin, c->lab4, c->stage,
                          c->stage_cap, ps, c->deferred, c->cap_t, c->walk_cap, c->cnt);
@@ -399,6 +396,19 @@ int polylla_mesh(polylla_ctx* c, const polylla_tri* t, polylla_labels* l, polyll
   return run_build(c, t, c->seeds, true, true, he, vtx, out, s);
 }
 
+int polylla_mesh_batched(polylla_ctx* c, const polylla_tri* t, int64_t n_meshes, const int64_t* vtx_off,
+                         polylla_labels* l, polylla_polys* out, int64_t* poly_off, hipStream_t s) {
+  if (!c || n_meshes < 0 || (n_meshes > 0 && (!vtx_off || !poly_off))) return POLYLLA_EINVAL;
+  int rc = polylla_mesh(c, t, l, out, s);
+  if (rc) return rc;
+  if (n_meshes >= 0 && poly_off) {
+    Prof p(c, s, KR_BATCH);
+    hipLaunchKernelGGL(k_batch_offsets, dim3(grid_for(n_meshes + 1, 256, 4096)), dim3(256), 0, s, n_meshes,
+                       vtx_off, out->offsets, out->verts, out->counts, out->cap_polys, out->cap_verts, poly_off);
+  }
+  return launched();
+}
+
 int polylla_validate(polylla_ctx* c, const polylla_tri* t, hipStream_t s) {
   if (!c) return POLYLLA_EINVAL;
   int rc = check_tri(t);
@@ -443,6 +453,10 @@ int polylla_set_param(polylla_ctx* c, int param, int64_t value) {
     case POLYLLA_PARAM_WALK_CAP:
       if (value < 1 || value > 24) return POLYLLA_EINVAL;
       c->walk_cap = (int)value;
+      return POLYLLA_OK;
+    case POLYLLA_PARAM_WALK_BLOCKS:
+      if (value < 8 || value > kWalkBlocks || value % 8) return POLYLLA_EINVAL;
+      c->walk_blocks = (int)value;
       return POLYLLA_OK;
     default:
       return POLYLLA_EINVAL;

@@ -126,6 +126,7 @@ constexpr int kLarge = 3;     // longer than kWalkCap
 // wave pays one memory round trip per iteration.
 constexpr int kXcds = 8;
 constexpr int32_t kStageChunk = 4096;  // staging ints a wave reserves at a time
+constexpr int kRefill = 8;             // idle lanes of a wave before it hands out polygons
 
 template <bool FROM_SEEDS>
 __global__ __launch_bounds__(256) void k_walk(const int32_t* __restrict__ list, int32_t nhe,
@@ -147,12 +148,12 @@ __global__ __launch_bounds__(256) void k_walk(const int32_t* __restrict__ list, 
   // chunk_item: list entry of slot `lane` of the chunk
   int32_t cbase = 0, clen = 0, cpos = 0, chunk_item = 0;
   bool more = true;
-  int64_t sbase = 0;
+  int64_t sbase = 0;  // wave-uniform: free part of the wave's staging chunk
   int32_t sleft = 0;
-  // lane state
+  // lane state; the cycle's vertices are kept in LDS column buf[.][threadIdx.x]
   int32_t idx = -1;
   int32_t s = -1, t = 0, ci = 0, twh = -1, L = 0, minv = 0, minpos = 0, minhe = -1, steps = 0;
-  uint64_t sig = 0;  // bit (v & 63) of every staged vertex: repeat pre-filter
+  uint64_t sig = 0;  // bit (v & 63) of every vertex so far: repeat pre-filter
   bool complex = false, pending = false, fresh = false, done = false;
   int result = kSimple;
   TriRec r, rn;
@@ -164,15 +165,14 @@ __global__ __launch_bounds__(256) void k_walk(const int32_t* __restrict__ list, 
       r = rn;
       pending = false;
     }
-    // ---- idle lanes take the next polygons of the chunk (refilled in 64s)
+    // ---- idle lanes take the next polygons, in batches of kRefill lanes
     const bool want = idx < 0;
     const uint64_t wmask = __ballot(want);
-    bool got = false;  // this lane took a polygon in this iteration
-    if (wmask && more) {
-      const int nwant = __popcll(wmask);
+    const int nwant = __popcll(wmask);
+    bool got = false;
+    if (more && (nwant >= kRefill || nwant == 64)) {
       const int rank = __popcll(wmask & ((1ull << lane) - 1ull));
-      int32_t take_old = min(clen - cpos, nwant);
-      // slots of the current chunk
+      const int32_t take_old = min(clen - cpos, nwant);
       const int32_t src_old = cpos + rank;
       const int32_t item_old = __shfl(chunk_item, src_old & 63, 64);
       if (want && rank < take_old) {
@@ -232,7 +232,6 @@ __global__ __launch_bounds__(256) void k_walk(const int32_t* __restrict__ list, 
     if (idx >= 0 && !pending && !done) {
       if (fresh && FROM_SEEDS) {
         // seed triangle: its first frontier half-edge, else turn about vertex 0
-        fresh = false;
         if (r.lab(0) & kFrontier) ci = 0;
         else if (r.lab(1) & kFrontier) ci = 1;
         else if (r.lab(2) & kFrontier) ci = 2;
@@ -275,16 +274,13 @@ __global__ __launch_bounds__(256) void k_walk(const int32_t* __restrict__ list, 
             bool rep = false;
             if (sig & bit)
               for (int j = 0; j < L; ++j) rep |= (buf[j][threadIdx.x] == v);
-            if (rep) {
-              complex = true;
-            } else {
-              sig |= bit;
-              buf[L][threadIdx.x] = v;
-              if (v < minv) {
-                minv = v;
-                minhe = c;
-                minpos = L;
-              }
+            complex = rep;
+            sig |= bit;
+            buf[L][threadIdx.x] = v;
+            if (v < minv) {
+              minv = v;
+              minhe = c;
+              minpos = L;
             }
           }
           ++L;
@@ -305,7 +301,8 @@ __global__ __launch_bounds__(256) void k_walk(const int32_t* __restrict__ list, 
         }
       }
     }
-    // ---- finished lanes: stage complete polygons, queue the others
+    // ---- finished lanes: stage complete cycles (packed per wave, unrotated:
+    // the emitter starts each at slot minpos, its smallest vertex), queue the others
     const bool fin = idx >= 0 && done;
     if (fin && result == kSimple && complex) result = kSmall;
     const bool fin_simple = fin && result == kSimple;
@@ -314,7 +311,7 @@ __global__ __launch_bounds__(256) void k_walk(const int32_t* __restrict__ list, 
       uint32_t incl = need;
 #pragma unroll
       for (int o = 1; o < 64; o <<= 1) {
-        uint32_t tt = __shfl_up(incl, o, 64);
+        const uint32_t tt = __shfl_up(incl, o, 64);
         if (lane >= o) incl += tt;
       }
       const int32_t tot = (int32_t)__shfl(incl, 63, 64);
@@ -329,18 +326,10 @@ __global__ __launch_bounds__(256) void k_walk(const int32_t* __restrict__ list, 
         const int64_t off = sbase + incl - need;
         if (off + L > stage_cap) {
           set_error(cnt, POLYLLA_ENOMEM);
-          result = kInvalid;
+          ps.clear(idx);
         } else {
-          int pp = minpos;
-          for (int k = 0; k < L; ++k) {
-            stage[off + k] = buf[pp][threadIdx.x];
-            pp = (pp + 1 == L) ? 0 : pp + 1;
-          }
-          ps.plen[idx] = L;
-          ps.ppieces[idx] = 1;
-          ps.pstart[idx] = minhe;
-          ps.prec[idx] = -1;
-          ps.pstage[idx] = (int32_t)off;
+          for (int k = 0; k < L; ++k) stage[off + k] = buf[k][threadIdx.x];
+          ps.set(idx, L, 1 | (minpos << kRotShift), minhe, (int32_t)off);
         }
       }
       sbase += tot;
@@ -350,16 +339,13 @@ __global__ __launch_bounds__(256) void k_walk(const int32_t* __restrict__ list, 
       if (result == kSmall) {
         const uint32_t q = atomicAdd(&cnt->n_deferred, 1u);
         deferred[q] = idx;
-        ps.plen[idx] = L;  // cycle length for the per-lane general path
+        ps.set_len(idx, L);  // cycle length for the per-lane general path
       } else if (result == kLarge) {
         const uint32_t q = atomicAdd(&cnt->n_big, 1u);
         deferred[deferred_cap - 1 - q] = idx;
       } else if (result == kInvalid) {
         set_error(cnt, steps > nhe ? POLYLLA_EDEGEN : POLYLLA_ETOPO);
-        ps.plen[idx] = 0;
-        ps.ppieces[idx] = 0;
-        ps.prec[idx] = -1;
-        ps.pstage[idx] = 0;
+        ps.clear(idx);
       }
       idx = -1;
       done = false;
@@ -562,10 +548,7 @@ __device__ void general_core(int32_t i, int32_t s, int32_t L, A cyc, A aux, int3
       return;
     }
     for (int32_t k = 0; k < L; ++k) stage[off + k] = origin[cyc[(best + k) % L]];
-    ps.plen[i] = L;
-    ps.ppieces[i] = 1;
-    ps.pstart[i] = cyc[best];
-    ps.pstage[i] = (int32_t)off;
+    ps.set(i, L, 1, cyc[best], (int32_t)off);
     return;
   }
   // pieces: walk from the opened half-edges, each piece once
@@ -663,10 +646,8 @@ __device__ void general_core(int32_t i, int32_t s, int32_t L, A cyc, A aux, int3
       h = walk_next(h, nhe, twin, he, cnt);
     }
   }
-  ps.plen[i] = total;
-  ps.ppieces[i] = np;
+  ps.set(i, total, np, -1, (int32_t)off);
   ps.prec[i] = (int32_t)r0;
-  ps.pstage[i] = (int32_t)off;
 
 }
 
@@ -675,10 +656,7 @@ __device__ void general_one(int32_t i, int32_t s, int32_t nhe, int64_t nv, const
                             const int32_t* __restrict__ origin, uint8_t* __restrict__ he, uint8_t* __restrict__ vtx,
                             int32_t* __restrict__ stage, int64_t stage_cap, int32_t* __restrict__ arena,
                             int64_t arena_cap, PolyState ps, Counters* cnt) {
-  ps.plen[i] = 0;
-  ps.ppieces[i] = 0;
-  ps.prec[i] = -1;
-  ps.pstage[i] = 0;
+  ps.clear(i);
   if ((uint32_t)s >= (uint32_t)nhe) return;
   // cycle length
   int32_t L = 0;
@@ -721,15 +699,12 @@ __global__ __launch_bounds__(64) void k_general_small(const int32_t* __restrict_
   for (uint32_t j = blockIdx.x * 64 + threadIdx.x; j < nd; j += gridDim.x * 64) {
     const int32_t i = deferred[j];
     const int32_t s = from_seeds ? seed_start(list[i], nhe, twin, he, cnt) : list[i];
-    const int32_t L = ps.plen[i];
+    const int32_t L = ps.len(i);
     if ((uint32_t)s >= (uint32_t)nhe || L < 1 || L > kWalkCap) {
       general_one<REPAIR>(i, s, nhe, nv, twin, origin, he, vtx, stage, stage_cap, arena, arena_cap, ps, cnt);
       continue;
     }
-    ps.plen[i] = 0;
-    ps.ppieces[i] = 0;
-    ps.prec[i] = -1;
-    ps.pstage[i] = 0;
+    ps.clear(i);
     general_core<REPAIR>(i, s, L, LdsCol{cyc_s + threadIdx.x}, LdsCol{aux_s + threadIdx.x}, nhe, nv, twin,
                          origin, he, vtx, stage, stage_cap, arena, arena_cap, ps, cnt);
   }
@@ -942,10 +917,7 @@ __global__ __launch_bounds__(kBigThreads) void k_general_big(
     if (S.sc[SC_BAD]) {
       if (tid == 0) {
         set_error(cnt, POLYLLA_ETOPO);
-        ps.plen[i] = 0;
-        ps.ppieces[i] = 0;
-        ps.prec[i] = -1;
-        ps.pstage[i] = 0;
+        ps.clear(i);
       }
       __syncthreads();
       continue;
@@ -985,10 +957,7 @@ __global__ __launch_bounds__(kBigThreads) void k_general_big(
     if (S.sc[SC_BAD]) {
       if (tid == 0) {
         set_error(cnt, POLYLLA_EDEGEN);
-        ps.plen[i] = 0;
-        ps.ppieces[i] = 0;
-        ps.prec[i] = -1;
-        ps.pstage[i] = 0;
+        ps.clear(i);
       }
       __syncthreads();
       continue;
@@ -1057,10 +1026,7 @@ __global__ __launch_bounds__(kBigThreads) void k_general_big(
       if (S.sc[SC_BAD]) {
         if (tid == 0) {
           set_error(cnt, POLYLLA_ETOPO);
-          ps.plen[i] = 0;
-          ps.ppieces[i] = 0;
-          ps.prec[i] = -1;
-          ps.pstage[i] = 0;
+          ps.clear(i);
         }
         __syncthreads();
         continue;
@@ -1276,11 +1242,8 @@ __global__ __launch_bounds__(kBigThreads) void k_general_big(
           pcnt[p] = run;  // output offset of the piece
           run += len;
         }
-        ps.plen[i] = total;
-        ps.ppieces[i] = np;
-        ps.pstage[i] = (int32_t)sb;
+        ps.set(i, total, np, np == 1 ? S.fh[pstart[S.nx[0]]] : -1, (int32_t)sb);
         ps.prec[i] = np > 1 ? rb : -1;
-        ps.pstart[i] = np == 1 ? S.fh[pstart[S.nx[0]]] : -1;
       }
       S.sc[SC_SBASE] = (int32_t)sb;
     }
@@ -1293,10 +1256,7 @@ __global__ __launch_bounds__(kBigThreads) void k_general_big(
         stage[sb + pcnt[p] + (len - 1 - S.q[k])] = S.b[k];
       }
     } else if (tid == 0) {
-      ps.plen[i] = 0;
-      ps.ppieces[i] = 0;
-      ps.prec[i] = -1;
-      ps.pstage[i] = 0;
+      ps.clear(i);
     }
     __syncthreads();
   }
@@ -1338,6 +1298,7 @@ __global__ __launch_bounds__(256) void k_scan_emit(PolyState ps, uint64_t* statu
                                                    int64_t cap_verts, Counters* cnt) {
   __shared__ int32_t s_voff[kScanTile + 1];
   __shared__ int32_t s_src[kScanTile];
+  __shared__ uint8_t s_rot[kScanTile];
   __shared__ int32_t s_ok;
   const uint32_t R = cnt->n_seeds;
   const uint32_t ntiles = (R + kScanTile - 1) / kScanTile;
@@ -1352,15 +1313,14 @@ __global__ __launch_bounds__(256) void k_scan_emit(PolyState ps, uint64_t* statu
   if (blockIdx.x >= ntiles) return;
   const uint32_t tile = take_tile(&cnt->tile_ticket[1]);
   const int64_t i0 = (int64_t)tile * kScanTile + (int64_t)threadIdx.x * kScanItems;
-  int32_t np[kScanItems], nl[kScanItems];
+  int4 rc[kScanItems];
   uint32_t a = 0, b = 0;
 #pragma unroll
   for (int j = 0; j < kScanItems; ++j) {
     const int64_t i = i0 + j;
-    np[j] = i < R ? ps.ppieces[i] : 0;
-    nl[j] = i < R ? ps.plen[i] : 0;
-    a += (uint32_t)np[j];
-    b += (uint32_t)nl[j];
+    rc[j] = i < R ? ps.rec[i] : make_int4(0, 0, -1, 0);
+    a += (uint32_t)(rc[j].y & kPiecesMask);
+    b += (uint32_t)rc[j].x;
   }
   uint2 total;
   const uint2 pre = block_exclusive_scan<256>(a, b, &total);
@@ -1382,26 +1342,27 @@ __global__ __launch_bounds__(256) void k_scan_emit(PolyState ps, uint64_t* statu
   for (int j = 0; j < kScanItems; ++j) {
     const int64_t i = i0 + j;
     const int k = threadIdx.x * kScanItems + j;
+    const int32_t nl = rc[j].x, np = rc[j].y & kPiecesMask, rot = (int32_t)((uint32_t)rc[j].y >> kRotShift);
     s_voff[k] = (int32_t)rb;
-    s_src[k] = (i < R && nl[j] > 0) ? ps.pstage[i] : 0;
-    if (ok && i < R && np[j] > 0) {
-      const int32_t r = ps.prec[i];
+    s_src[k] = nl > 0 ? rc[j].w : 0;
+    s_rot[k] = rot;
+    if (ok && i < R && np > 0) {
       const int32_t vg = (int32_t)(tile_v0 + rb);
-      if (r < 0) {
+      if (np == 1) {
         offsets[ra] = vg;
-        if (start) start[ra] = ps.pstart[i];
+        if (start) start[ra] = rc[j].z;
       } else {
-        const int32_t* rec = arena + r;
+        const int32_t* rec = arena + ps.prec[i];
         int32_t acc = 0;
-        for (int32_t q = 0; q < np[j]; ++q) {
+        for (int32_t q = 0; q < np; ++q) {
           offsets[ra + q] = vg + acc;
           if (start) start[ra + q] = rec[4 * q + 2];
           acc += rec[4 * q + 3];
         }
       }
     }
-    ra += (uint32_t)np[j];
-    rb += (uint32_t)nl[j];
+    ra += (uint32_t)np;
+    rb += (uint32_t)nl;
   }
   if (threadIdx.x == 255) s_voff[kScanTile] = (int32_t)rb;
   __syncthreads();
@@ -1415,7 +1376,45 @@ __global__ __launch_bounds__(256) void k_scan_emit(PolyState ps, uint64_t* statu
       if (s_voff[mid] <= k) lo = mid;
       else hi = mid;
     }
-    verts[tile_v0 + k] = stage[s_src[lo] + (k - s_voff[lo])];
+    const int32_t len = s_voff[lo + 1] - s_voff[lo];
+    int32_t off = k - s_voff[lo] + s_rot[lo];
+    off = off >= len ? off - len : off;
+    verts[tile_v0 + k] = stage[s_src[lo] + off];
+  }
+}
+
+// First output polygon of every mesh of a batch: polygons come in mesh order
+// and each starts at its smallest vertex, which lies in its mesh's vertex
+// range, so the first polygon of mesh m is the first polygon whose first
+// vertex is at least vtx_off[m] (binary search).
+__global__ __launch_bounds__(256) void k_batch_offsets(int64_t n_meshes, const int64_t* __restrict__ vtx_off,
+                                                       const int32_t* __restrict__ offsets,
+                                                       const int32_t* __restrict__ verts,
+                                                       const int64_t* __restrict__ counts, int64_t cap_polys,
+                                                       int64_t cap_verts, int64_t* __restrict__ poly_off) {
+  const int64_t F = counts[0];
+  // after a capacity error the CSR arrays are not filled: report -1
+  const bool ok = F <= cap_polys && counts[1] <= cap_verts;
+  for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m <= n_meshes;
+       m += (int64_t)gridDim.x * blockDim.x) {
+    if (!ok) {
+      poly_off[m] = -1;
+      continue;
+    }
+    if (m == n_meshes) {
+      poly_off[m] = F;
+      continue;
+    }
+    const int64_t v0 = vtx_off[m];
+    int64_t lo = 0, hi = F;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      const int32_t o = offsets[mid];
+      const int64_t first = (o >= 0 && o < cap_verts) ? (int64_t)verts[o] : v0;
+      if (first < v0) lo = mid + 1;
+      else hi = mid;
+    }
+    poly_off[m] = lo;
   }
 }
 

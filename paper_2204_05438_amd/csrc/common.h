@@ -39,13 +39,24 @@ struct Counters {
   uint32_t xcd_ticket[8]; // walk work queues, one per XCD
 };
 
-// Per-polygon results of the walk / general path, in seed order.
+// Per-polygon results of the walk / general path, in seed order: one 16-byte
+// record {vertices of all pieces, pieces | rotation << 24, canonical start
+// half-edge (one piece), staging offset} written with a single store, plus the
+// arena offset of the piece records, read only for polygons of more than one
+// piece. The rotation is the slot of the staged cycle that the output starts
+// at (the walk stages cycles unrotated; the general paths stage them rotated).
+constexpr int kRotShift = 24;
+constexpr int32_t kPiecesMask = (1 << kRotShift) - 1;
+
 struct PolyState {
-  int32_t* pstart;   // canonical start half-edge (single-piece polygons)
-  int32_t* plen;     // total output vertices of the polygon (all pieces)
-  int32_t* ppieces;  // number of output polygons
-  int32_t* prec;     // arena offset of piece records, -1 for one piece
-  int32_t* pstage;   // staging offset of the vertex data
+  int4* rec;
+  int32_t* prec;
+  __device__ __forceinline__ void set(int64_t i, int32_t len, int32_t pieces, int32_t start, int32_t stage) const {
+    rec[i] = make_int4(len, pieces, start, stage);
+  }
+  __device__ __forceinline__ void clear(int64_t i) const { rec[i] = make_int4(0, 0, -1, 0); }
+  __device__ __forceinline__ void set_len(int64_t i, int32_t len) const { reinterpret_cast<int32_t*>(rec + i)[0] = len; }
+  __device__ __forceinline__ int32_t len(int64_t i) const { return reinterpret_cast<const int32_t*>(rec + i)[0]; }
 };
 
 __device__ __forceinline__ int32_t he_next(int32_t h) {

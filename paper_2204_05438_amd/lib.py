@@ -19,6 +19,7 @@ OK, EINVAL, ELAYOUT, ETOPO, ECAPACITY, ENOMEM, EHIP, EDEGEN, EINTERNAL = 0, -1, 
 LONGEST, FRONTIER, TERMINAL, BORDER, BARRIER, REPAIRED = 1, 2, 4, 8, 16, 32
 SEED, TIP = 1, 1
 PARAM_WALK_CAP = 1
+PARAM_WALK_BLOCKS = 2
 
 
 class PolyllaError(RuntimeError):
@@ -64,6 +65,8 @@ def load() -> ctypes.CDLL:
                                        ctypes.POINTER(_Polys), P]
         lib.polylla_mesh.argtypes = [P, ctypes.POINTER(_Tri), ctypes.POINTER(_Labels), ctypes.POINTER(_Polys), P]
         lib.polylla_validate.argtypes = [P, ctypes.POINTER(_Tri), P]
+        lib.polylla_mesh_batched.argtypes = [P, ctypes.POINTER(_Tri), ctypes.c_int64, P, ctypes.POINTER(_Labels),
+                                             ctypes.POINTER(_Polys), P, P]
         lib.polylla_status.argtypes = [P, P]
         lib.polylla_stats.argtypes = [P, ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
         lib.polylla_set_param.argtypes = [P, ctypes.c_int, ctypes.c_int64]
@@ -73,7 +76,7 @@ def load() -> ctypes.CDLL:
         lib.polylla_strerror.argtypes = [ctypes.c_int]
         lib.polylla_strerror.restype = ctypes.c_char_p
         for f in ("polylla_ctx_create", "polylla_reserve", "polylla_label", "polylla_build", "polylla_repair",
-                  "polylla_mesh", "polylla_validate", "polylla_status", "polylla_stats", "polylla_set_param", "polylla_profile",
+                  "polylla_mesh", "polylla_mesh_batched", "polylla_validate", "polylla_status", "polylla_stats", "polylla_set_param", "polylla_profile",
                   "polylla_profile_read"):
             getattr(lib, f).restype = ctypes.c_int
         _lib = lib
@@ -234,6 +237,22 @@ class Context:
         lp = ctypes.byref(labels.c()) if labels is not None else None
         _check(load().polylla_mesh(self._h, ctypes.byref(t), lp, ctypes.byref(o), self._stream()), "polylla_mesh")
         return out
+
+    def mesh_batched(self, tri: Tri, vtx_off: torch.Tensor, labels: Labels | None = None,
+                     out: Polys | None = None, poly_off: torch.Tensor | None = None):
+        """Packed batch of meshes (global indices, see polylla_mesh_batched);
+        returns (polys, poly_off) with poly_off int64 [n_meshes + 1] on the device."""
+        n = int(vtx_off.shape[0]) - 1
+        out = out or Polys.empty(tri)
+        if poly_off is None:
+            poly_off = torch.empty(n + 1, dtype=torch.int64, device=tri.origin.device)
+        if vtx_off.dtype != torch.int64 or not vtx_off.is_cuda:
+            raise TypeError("vtx_off must be an int64 device tensor")
+        t, o = tri.c(), out.c()
+        lp = ctypes.byref(labels.c()) if labels is not None else None
+        _check(load().polylla_mesh_batched(self._h, ctypes.byref(t), n, _ptr(vtx_off), lp, ctypes.byref(o),
+                                           _ptr(poly_off), self._stream()), "polylla_mesh_batched")
+        return out, poly_off
 
     def validate(self, tri: Tri) -> int:
         t = tri.c()

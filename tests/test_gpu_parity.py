@@ -193,3 +193,34 @@ def test_layout_errors(ctx):
     badr.twin[2] = 1000
     ctx.mesh(badr)
     assert ctx.status(raise_on_error=False) == lib.ETOPO
+
+
+@pytest.mark.parametrize("walk_cap", [4, 24])
+def test_batched_equals_per_mesh(ctx, walk_cap):
+    """A packed batch of uneven meshes gives each mesh's own polygons."""
+    _say(f"batched 40 meshes walk_cap {walk_cap}")
+    from meshgen.gen import pack_meshes
+    from paper_2204_05438_amd import lib
+    rng = np.random.default_rng(11)
+    meshes = [random_mesh(300 + k, int(n), ["uniform", "cluster", "grid", "lattice"][k % 4])
+              for k, n in enumerate(np.rint(10 ** rng.uniform(0.8, 3.6, 40)))]
+    packed, vtx_off, he_off = pack_meshes(meshes)
+    ctx.set_param(lib.PARAM_WALK_CAP, walk_cap)
+    tri = lib.Tri.from_mesh(packed)
+    labels = lib.Labels.empty(tri)
+    out, poly_off = ctx.mesh_batched(tri, torch.from_numpy(vtx_off).cuda(), labels)
+    ctx.status()
+    ctx.set_param(lib.PARAM_WALK_CAP, 24)
+    off, verts, start = (x.cpu().numpy() for x in out.trimmed())
+    po = poly_off.cpu().numpy()
+    he = labels.he.cpu().numpy()
+    assert po[0] == 0 and po[-1] == off.size - 1
+    for k, m in enumerate(meshes):
+        o = oracle.oracle_on(m)
+        a, b = int(po[k]), int(po[k + 1])
+        got_off = off[a:b + 1] - off[a]
+        got_verts = verts[off[a]:off[b]] - vtx_off[k]
+        assert np.array_equal(got_off, o["offsets"]), k
+        assert np.array_equal(got_verts, o["verts"]), k
+        assert np.array_equal(start[a:b] - he_off[k], o["start"]), k
+        assert np.array_equal(he[he_off[k]:he_off[k + 1]], o["he"]), k

@@ -683,30 +683,434 @@ __device__ void general_one(int32_t i, int32_t s, int32_t nhe, int64_t nv, const
                        arena_cap, ps, cnt);
 }
 
-// Short polygons with a tip or a repeated vertex: one lane each, the cycle
-// and its scratch in LDS columns. The walk left the cycle length in plen.
+// ---------------------------------------------------------------------------
+// Per-lane region path for short polygons with a tip or a repeated vertex.
+//
+// Every step of the general path stays inside the polygon's region: turning
+// about a vertex from one frontier half-edge to the next crosses internal
+// edges only, and the whole fan of a barrier-edge tip lies in the region. So
+// the lane first gathers the region's triangles (breadth-first over internal
+// edges, all triangles of a level loaded together), keeping per triangle its
+// id, its three vertex ids and one link per local edge:
+//   internal edge : code of the twin in the region (slot * 4 + local index)
+//   frontier edge : -2 - twin half-edge id, or -1 on the hull
+// and then runs the cycle, barrier, tip, repair and piece steps on these LDS
+// arrays. A region of a cycle with at most kWalkCap frontier half-edges has at
+// most kWalkCap - 2 triangles (3k half-edges = L frontier + 2(k - 1) internal).
+
+constexpr int kSmallK = kWalkCap - 2;
+constexpr int32_t kUnset = INT32_MIN;
+constexpr int kGather = 4;  // triangle records a lane loads per round
+
+template <typename A>
+struct Region {
+  A tri, lnk, org;
+  __device__ __forceinline__ int32_t gid(int c) const { return 3 * tri[c >> 2] + (c & 3); }
+  __device__ __forceinline__ int32_t link(int c) const { return lnk[(c >> 2) * 3 + (c & 3)]; }
+  __device__ __forceinline__ void set_link(int c, int32_t v) const { lnk[(c >> 2) * 3 + (c & 3)] = v; }
+  __device__ __forceinline__ int32_t vert(int c) const { return org[(c >> 2) * 3 + (c & 3)]; }
+  __device__ __forceinline__ int32_t twin_gid(int c) const {
+    const int32_t l = link(c);
+    return l >= 0 ? gid(l) : (l == -1 ? -1 : -2 - l);
+  }
+  // code of the edge after crossing internal code c: next local edge of its twin
+  __device__ __forceinline__ int turn(int c) const {
+    const int32_t l = link(c);
+    return (l & ~3) | next_local(l & 3);
+  }
+  // next frontier code after frontier code c, turning about its end vertex; -1 if none within limit
+  __device__ __forceinline__ int next_frontier(int c, int limit) const {
+    int x = (c & ~3) | next_local(c & 3);
+    for (int n = 0; n < limit; ++n) {
+      if (link(x) < 0) return x;
+      x = turn(x);
+    }
+    return -1;
+  }
+};
+
+// Gather the region of triangle t0 into R. Returns its triangle count, or
+// -1 if it has more than kcap triangles, -2 on an invalid mesh.
+template <typename A>
+__device__ int gather_region(const Region<A>& R, int32_t t0, int kcap, int32_t nhe, const int32_t* __restrict__ twin,
+                             const int32_t* __restrict__ origin, const uint32_t* __restrict__ lab4) {
+  R.tri[0] = t0;
+  R.lnk[0] = R.lnk[1] = R.lnk[2] = kUnset;
+  int head = 0, tail = 1, status = 0;
+  while (head < tail && status == 0) {
+    const int n = min(tail - head, kGather);
+    TriRec rr[kGather];
+#pragma unroll
+    for (int u = 0; u < kGather; ++u)
+      if (u < n) rr[u].load(R.tri[head + u], twin, origin, lab4);
+#pragma unroll
+    for (int u = 0; u < kGather; ++u) {
+      if (u >= n) continue;
+      const int s = head + u;
+#pragma unroll
+      for (int e = 0; e < 3; ++e) {
+        R.org[3 * s + e] = rr[u].org(e);
+        if (R.lnk[3 * s + e] != kUnset) continue;  // the edge it was entered through
+        const int32_t tw = rr[u].tw(e);
+        if (rr[u].lab(e) & kFrontier) {
+          R.lnk[3 * s + e] = tw < 0 ? -1 : -2 - tw;
+        } else if ((uint32_t)tw >= (uint32_t)nhe) {
+          R.lnk[3 * s + e] = -1;
+          status = -2;
+        } else if (tail >= kcap) {
+          R.lnk[3 * s + e] = -1;
+          status = status ? status : -1;
+        } else {
+          const int ns = tail++;
+          const int32_t t2 = tw / 3, e2 = tw - 3 * t2;
+          R.tri[ns] = t2;
+          R.lnk[3 * ns] = R.lnk[3 * ns + 1] = R.lnk[3 * ns + 2] = kUnset;
+          R.lnk[3 * ns + e2] = 4 * s + e;
+          R.lnk[3 * s + e] = 4 * ns + e2;
+        }
+      }
+    }
+    head += n;
+  }
+  return status ? status : tail;
+}
+
+// Lexicographic comparison of the vertex sequences of length len from
+// frontier codes p and q of the same piece: -1, 0 or 1.
+template <typename A>
+__device__ int compare_rotations_lds(const Region<A>& R, int p, int q, int32_t len, int limit) {
+  for (int32_t k = 0; k < len; ++k) {
+    const int32_t a = R.vert(p), b = R.vert(q);
+    if (a != b) return a < b ? -1 : 1;
+    p = R.next_frontier(p, limit);
+    q = R.next_frontier(q, limit);
+    if (p < 0 || q < 0) return 0;
+  }
+  return 0;
+}
+
+// The general path for one polygon on its gathered region (k triangles);
+// same steps and tie rules as general_core. cyc and aux hold kWalkCap ints.
+template <bool REPAIR, typename A>
+__device__ void region_core(int32_t i, const Region<A>& R, int k, int start, A cyc, A aux, int64_t nv,
+                            uint8_t* __restrict__ he, uint8_t* __restrict__ vtx, int32_t* __restrict__ stage,
+                            int64_t stage_cap, int32_t* __restrict__ arena, int64_t arena_cap, PolyState ps,
+                            Counters* cnt) {
+  const int limit = 3 * k + 3;
+  // the cycle
+  int32_t L = 0;
+  {
+    int c = start;
+    do {
+      if (L == kWalkCap) {
+        set_error(cnt, POLYLLA_EINTERNAL);  // k <= kWalkCap - 2 bounds the cycle
+        return;
+      }
+      cyc[L++] = c;
+      c = R.next_frontier(c, limit);
+    } while (c >= 0 && c != start);
+    if (c != start) {
+      set_error(cnt, POLYLLA_EDEGEN);
+      return;
+    }
+  }
+  // barrier edges: edge keys that occur twice on the cycle
+  for (int32_t m = 0; m < L; ++m) {
+    const int32_t h = R.gid(cyc[m]), tw = R.twin_gid(cyc[m]);
+    aux[m] = tw < 0 ? -1 : (h < tw ? h : tw);
+  }
+  heap_sort(aux, L);
+  for (int32_t m = 0; m < L; ++m) {
+    const int32_t h = R.gid(cyc[m]), tw = R.twin_gid(cyc[m]);
+    if (tw < 0) continue;
+    const int32_t key = h < tw ? h : tw;
+    const int32_t at = bsearch_idx(aux, L, key);
+    if (at >= 0 && at + 1 < L && aux[at + 1] == key) he[h] |= kBarrier;
+  }
+  // tips: the next frontier half-edge is the twin of the current one; the
+  // pair keeps the tip vertex and the cycle position of that next half-edge
+  int32_t ntip = 0;
+  for (int32_t m = 0; m < L; ++m) {
+    const int mn = m + 1 == L ? 0 : m + 1;
+    if (R.twin_gid(cyc[m]) == R.gid(cyc[mn])) {
+      const int32_t v = R.vert(cyc[mn]);
+      if ((uint64_t)(uint32_t)v < (uint64_t)nv) vtx[v] |= kTip;
+      aux[2 * ntip] = v;
+      aux[2 * ntip + 1] = mn;
+      ++ntip;
+    }
+  }
+  if (ntip) atomicAdd(&cnt->n_tips, (uint32_t)ntip);
+  int32_t nsplit = 0;
+  uint64_t opened[2] = {0ull, 0ull};  // codes of opened half-edges (code < 128)
+  if (REPAIR && ntip) {
+    // middle internal edge at every tip: c_{floor(d/2)} turning about the tip
+    // vertex from its barrier half-edge c0 (whose twin is the previous cycle edge)
+    for (int32_t q = 0; q < ntip; ++q) {
+      const int32_t mn = aux[2 * q + 1];
+      const int c0 = cyc[mn], tw0 = cyc[mn == 0 ? L - 1 : mn - 1];
+      int32_t d = 0;
+      int c = c0;
+      do {
+        const int tc = c == c0 ? tw0 : R.link(c);
+        if (tc < 0) {
+          d = -1;
+          break;
+        }
+        c = (tc & ~3) | next_local(tc & 3);
+        ++d;
+      } while (c != c0 && d <= limit);
+      if (d < 0 || c != c0) {
+        set_error(cnt, POLYLLA_ETOPO);
+        d = 0;
+      }
+      int e = c0;
+      for (int32_t m = 0; m < d / 2; ++m) {
+        const int tc = e == c0 ? tw0 : R.link(e);
+        e = (tc & ~3) | next_local(tc & 3);
+      }
+      aux[2 * q + 1] = e;
+    }
+    // tips in increasing vertex id (insertion sort of pairs)
+    for (int32_t q = 1; q < ntip; ++q) {
+      int32_t v = aux[2 * q], e = aux[2 * q + 1], p = q;
+      while (p > 0 && aux[2 * (p - 1)] > v) {
+        aux[2 * p] = aux[2 * (p - 1)];
+        aux[2 * p + 1] = aux[2 * (p - 1) + 1];
+        --p;
+      }
+      aux[2 * p] = v;
+      aux[2 * p + 1] = e;
+    }
+    // a tip on an edge opened for a smaller live tip is no longer a tip
+    for (int32_t q = 0; q < ntip; ++q) {
+      const int32_t v = aux[2 * q];
+      bool dead = false;
+      for (int32_t p = 0; p < q && !dead; ++p) {
+        if (aux[2 * p] < 0) continue;  // dead tips are stored as -1 - v
+        const int e = aux[2 * p + 1];
+        dead = R.vert((e & ~3) | next_local(e & 3)) == v;
+      }
+      if (dead) aux[2 * q] = -1 - v;
+    }
+    // open the edges of the live tips; both half-edge codes go to cyc, which
+    // is not needed any more once an edge is opened
+    for (int32_t q = 0; q < ntip; ++q) {
+      if (aux[2 * q] < 0) continue;
+      const int e = aux[2 * q + 1];
+      const int32_t te = R.link(e);
+      if (te < 0) {  // only reachable on an invalid mesh
+        set_error(cnt, POLYLLA_ETOPO);
+        aux[2 * q] = -1 - aux[2 * q];
+        continue;
+      }
+      const int32_t ge = R.gid(e), gt = R.gid(te);
+      he[ge] |= kFrontier | kRepaired;
+      he[gt] |= kFrontier | kRepaired;
+      R.set_link(e, -2 - gt);
+      R.set_link(te, -2 - ge);
+      opened[e >> 6] |= 1ull << (e & 63);
+      opened[te >> 6] |= 1ull << (te & 63);
+      cyc[2 * nsplit] = e;
+      cyc[2 * nsplit + 1] = te;
+      ++nsplit;
+    }
+    if (nsplit) atomicAdd(&cnt->n_splits, (uint32_t)nsplit);
+  }
+  if (nsplit == 0) {
+    // one piece: the cycle itself, rotated to its smallest vertex sequence
+    int32_t best = 0, minv = R.vert(cyc[0]);
+    for (int32_t m = 1; m < L; ++m) {
+      const int32_t v = R.vert(cyc[m]);
+      if (v < minv) {
+        minv = v;
+        best = m;
+      }
+    }
+    for (int32_t m = best + 1; m < L; ++m) {
+      if (R.vert(cyc[m]) != minv) continue;
+      for (int32_t z = 1; z < L; ++z) {
+        const int32_t a = R.vert(cyc[(m + z) % L]), b = R.vert(cyc[(best + z) % L]);
+        if (a != b) {
+          if (a < b) best = m;
+          break;
+        }
+      }
+    }
+    const uint32_t off = atomicAdd(&cnt->stage_top, (uint32_t)L);
+    if ((int64_t)off + L > stage_cap) {
+      set_error(cnt, POLYLLA_ENOMEM);
+      return;
+    }
+    for (int32_t m = 0; m < L; ++m) stage[off + m] = R.vert(cyc[(best + m) % L]);
+    ps.set(i, L, 1, R.gid(cyc[best]), (int32_t)off);
+    return;
+  }
+  // pieces: walk from the opened half-edges in increasing half-edge id, each
+  // piece once
+  const int32_t nc = 2 * nsplit;
+  A cand = cyc;
+  for (int32_t q = 1; q < nc; ++q) {
+    const int32_t x = cand[q], gx = R.gid(x);
+    int32_t p = q;
+    while (p > 0 && R.gid(cand[p - 1]) > gx) {
+      cand[p] = cand[p - 1];
+      --p;
+    }
+    cand[p] = x;
+  }
+  const int32_t npieces = nsplit + 1;
+  const uint32_t rneed = (uint32_t)(4 * npieces);
+  const uint32_t r0 = atomicAdd(&cnt->arena_top, rneed);
+  if ((int64_t)r0 + rneed > arena_cap) {
+    set_error(cnt, POLYLLA_ENOMEM);
+    return;
+  }
+  int32_t* rec = arena + r0;
+  uint32_t seen = 0;
+  int32_t np = 0, total = 0;
+  bool bad = false;
+  for (int32_t m = 0; m < nc && !bad; ++m) {
+    if ((seen >> m) & 1u) continue;
+    const int x = cand[m];
+    int h = x;
+    int32_t len = 0, minv = 0x7FFFFFFF, mincount = 0;
+    int minh = -1;
+    do {
+      const int32_t v = R.vert(h);
+      if (v < minv) {
+        minv = v;
+        minh = h;
+        mincount = 1;
+      } else if (v == minv) {
+        ++mincount;
+      }
+      if ((opened[h >> 6] >> (h & 63)) & 1ull)
+        for (int32_t z = 0; z < nc; ++z)
+          if (cand[z] == h) seen |= 1u << z;
+      ++len;
+      h = R.next_frontier(h, limit);
+    } while (h >= 0 && h != x && len <= limit);
+    if (h != x || np >= npieces) {
+      set_error(cnt, POLYLLA_EDEGEN);
+      bad = true;
+      break;
+    }
+    if (mincount > 1) {
+      // pinched piece: lexicographically smallest rotation among the
+      // occurrences of its smallest vertex
+      int best = minh, q = R.next_frontier(minh, limit);
+      for (int32_t z = 1; z < len && q >= 0; ++z) {
+        if (R.vert(q) == minv && compare_rotations_lds(R, q, best, len, limit) < 0) best = q;
+        q = R.next_frontier(q, limit);
+      }
+      minh = best;
+    }
+    const int nxt = R.next_frontier(minh, limit);
+    rec[4 * np] = minv;
+    rec[4 * np + 1] = nxt >= 0 ? R.vert(nxt) : 0;
+    rec[4 * np + 2] = R.gid(minh);
+    rec[4 * np + 3] = len;
+    aux[np] = minh;  // start code of the piece, for staging its vertices
+    ++np;
+    total += len;
+  }
+  if (bad || np != npieces) {
+    if (!bad) set_error(cnt, POLYLLA_EDEGEN);
+    return;
+  }
+  // pieces by (first, second) vertex
+  for (int32_t q = 1; q < np; ++q) {
+    int32_t r[4] = {rec[4 * q], rec[4 * q + 1], rec[4 * q + 2], rec[4 * q + 3]};
+    const int32_t sc = aux[q];
+    int32_t p = q;
+    while (p > 0 && (rec[4 * (p - 1)] > r[0] || (rec[4 * (p - 1)] == r[0] && rec[4 * (p - 1) + 1] > r[1]))) {
+      for (int z = 0; z < 4; ++z) rec[4 * p + z] = rec[4 * (p - 1) + z];
+      aux[p] = aux[p - 1];
+      --p;
+    }
+    for (int z = 0; z < 4; ++z) rec[4 * p + z] = r[z];
+    aux[p] = sc;
+  }
+  const uint32_t off = atomicAdd(&cnt->stage_top, (uint32_t)total);
+  if ((int64_t)off + total > stage_cap) {
+    set_error(cnt, POLYLLA_ENOMEM);
+    return;
+  }
+  int32_t w = (int32_t)off;
+  for (int32_t q = 0; q < np; ++q) {
+    int h = aux[q];
+    const int32_t len = rec[4 * q + 3];
+    for (int32_t z = 0; z < len && h >= 0; ++z) {
+      stage[w++] = R.vert(h);
+      h = R.next_frontier(h, limit);
+    }
+  }
+  ps.set(i, total, np, -1, (int32_t)off);
+  ps.prec[i] = (int32_t)r0;
+}
+
+// Short polygons with a tip or a repeated vertex: one lane each, the region
+// in LDS columns interleaved over the 64 lanes of the block. Regions larger
+// than kSmallK triangles (only on invalid input: the walk queues cycles of at
+// most kWalkCap half-edges here) take general_one.
 template <bool REPAIR>
 __global__ __launch_bounds__(64) void k_general_small(const int32_t* __restrict__ list, bool from_seeds,
                                                       int32_t nhe, int64_t nv, const int32_t* __restrict__ twin,
-                                                      const int32_t* __restrict__ origin, uint8_t* __restrict__ he,
+                                                      const int32_t* __restrict__ origin,
+                                                      const uint32_t* __restrict__ lab4, uint8_t* __restrict__ he,
                                                       uint8_t* __restrict__ vtx, int32_t* __restrict__ stage,
                                                       int64_t stage_cap, int32_t* __restrict__ arena,
                                                       int64_t arena_cap, PolyState ps,
                                                       const int32_t* __restrict__ deferred, Counters* cnt) {
-  __shared__ int32_t cyc_s[kWalkCap * 64];
-  __shared__ int32_t aux_s[kWalkCap * 64];
+  __shared__ int32_t s_tri[kSmallK * 64];
+  __shared__ int32_t s_lnk[3 * kSmallK * 64];
+  __shared__ int32_t s_org[3 * kSmallK * 64];
+  __shared__ int32_t s_cyc[kWalkCap * 64];
+  __shared__ int32_t s_aux[kWalkCap * 64];
+  const int lane = threadIdx.x;
+  const Region<LdsCol> R{LdsCol{s_tri + lane}, LdsCol{s_lnk + lane}, LdsCol{s_org + lane}};
+  const int32_t nt = nhe / 3;
   const uint32_t nd = cnt->n_deferred;
   for (uint32_t j = blockIdx.x * 64 + threadIdx.x; j < nd; j += gridDim.x * 64) {
     const int32_t i = deferred[j];
-    const int32_t s = from_seeds ? seed_start(list[i], nhe, twin, he, cnt) : list[i];
-    const int32_t L = ps.len(i);
-    if ((uint32_t)s >= (uint32_t)nhe || L < 1 || L > kWalkCap) {
+    const int32_t item = list[i];
+    ps.clear(i);
+    const int32_t t0 = from_seeds ? item : (item >= 0 ? item / 3 : -1);
+    if ((uint32_t)t0 >= (uint32_t)nt) {
+      set_error(cnt, POLYLLA_ETOPO);
+      continue;
+    }
+    const int k = gather_region(R, t0, kSmallK, nhe, twin, origin, lab4);
+    if (k == -2) {
+      set_error(cnt, POLYLLA_ETOPO);
+      continue;
+    }
+    if (k < 0) {
+      const int32_t s = from_seeds ? seed_start(item, nhe, twin, he, cnt) : item;
       general_one<REPAIR>(i, s, nhe, nv, twin, origin, he, vtx, stage, stage_cap, arena, arena_cap, ps, cnt);
       continue;
     }
-    ps.clear(i);
-    general_core<REPAIR>(i, s, L, LdsCol{cyc_s + threadIdx.x}, LdsCol{aux_s + threadIdx.x}, nhe, nv, twin,
-                         origin, he, vtx, stage, stage_cap, arena, arena_cap, ps, cnt);
+    // start: the seed's first frontier half-edge in local order, else the
+    // first met turning about its vertex 0; or the given start half-edge
+    int start;
+    if (from_seeds) {
+      start = R.link(0) < 0 ? 0 : (R.link(1) < 0 ? 1 : (R.link(2) < 0 ? 2 : -1));
+      if (start < 0) {
+        int c = 0;
+        for (int n = 0; n <= 3 * k && R.link(c) >= 0; ++n) c = R.turn(c);
+        start = R.link(c) < 0 ? c : -1;
+      }
+    } else {
+      start = item - 3 * t0;
+      if (R.link(start) >= 0) start = -1;
+    }
+    if (start < 0) {
+      set_error(cnt, POLYLLA_EDEGEN);
+      continue;
+    }
+    region_core<REPAIR>(i, R, k, start, LdsCol{s_cyc + lane}, LdsCol{s_aux + lane}, nv, he, vtx, stage, stage_cap,
+                        arena, arena_cap, ps, cnt);
   }
 }
 
@@ -1423,11 +1827,11 @@ template __global__ void k_walk<true>(const int32_t*, int32_t, const int32_t*, c
 template __global__ void k_walk<false>(const int32_t*, int32_t, const int32_t*, const int32_t*, const uint32_t*,
                                        int32_t*, int64_t, PolyState, int32_t*, int64_t, int, Counters*);
 template __global__ void k_general_small<true>(const int32_t*, bool, int32_t, int64_t, const int32_t*,
-                                               const int32_t*, uint8_t*, uint8_t*, int32_t*, int64_t, int32_t*,
-                                               int64_t, PolyState, const int32_t*, Counters*);
+                                               const int32_t*, const uint32_t*, uint8_t*, uint8_t*, int32_t*,
+                                               int64_t, int32_t*, int64_t, PolyState, const int32_t*, Counters*);
 template __global__ void k_general_small<false>(const int32_t*, bool, int32_t, int64_t, const int32_t*,
-                                                const int32_t*, uint8_t*, uint8_t*, int32_t*, int64_t, int32_t*,
-                                                int64_t, PolyState, const int32_t*, Counters*);
+                                                const int32_t*, const uint32_t*, uint8_t*, uint8_t*, int32_t*,
+                                                int64_t, int32_t*, int64_t, PolyState, const int32_t*, Counters*);
 template __global__ void k_general_big<true>(const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*,
                                              uint8_t*, uint8_t*, int32_t*, int64_t, int32_t*, int64_t, PolyState,
                                              const int32_t*, int64_t, int32_t*, Counters*);

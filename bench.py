@@ -46,6 +46,36 @@ def algorithmic_bytes(kernel: str, n: dict) -> int:
     return table.get(kernel, 0)
 
 
+def kernel_sources_digest() -> str:
+    """sha256 over the HIP sources of the library (file names and contents)."""
+    import hashlib
+    d = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2204_05438_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h")):
+            d.update(name.encode())
+            with open(os.path.join(csrc, name), "rb") as f:
+                d.update(f.read())
+    return d.hexdigest()
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    or None when it is missing or was taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic.{workload}.md")
+    try:
+        lines = open(path).read().splitlines()
+    except OSError:
+        return None
+    if f"sources sha256: {kernel_sources_digest()}" not in lines:
+        return None
+    for ln in lines:
+        cells = [c.strip() for c in ln.strip("|").split("|")]
+        if len(cells) == 6 and cells[0].split("<")[0] == kernel:
+            return int(float(cells[5]) * 1e6)
+    return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -127,7 +157,8 @@ def main():
     dom_bytes = algorithmic_bytes(dominant, counts)
     achieved = dom_bytes / (dom_ms / 1e3) / 1e9 if dom_bytes else 0.0
     roofline = {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic(dominant, args.workload),
                 "avg_launch_us": round(dom_ms * 1e3, 1), "algorithmic_bytes": dom_bytes}
     per_kernel = {k: {"us_per_launch": round(ms / n * 1e3, 1),
                       "algorithmic_GBps": round(algorithmic_bytes(k, counts) / (ms / n / 1e3) / 1e9, 1)}

@@ -25,9 +25,9 @@ __global__ void k_general_small(const int32_t*, bool, int32_t, int64_t, const in
                                 const uint32_t*, uint8_t*, uint8_t*, int32_t*, int64_t, int32_t*, int64_t, PolyState,
                                 const int32_t*, Counters*);
 template <bool REPAIR>
-__global__ void k_general_big(const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*, uint8_t*,
-                              uint8_t*, int32_t*, int64_t, int32_t*, int64_t, PolyState, const int32_t*, int64_t,
-                              int32_t*, Counters*);
+__global__ void k_general_big(const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*, const uint32_t*,
+                              uint8_t*, uint8_t*, int32_t*, int64_t, int32_t*, int64_t, PolyState, const int32_t*,
+                              int64_t, int32_t*, Counters*);
 template <bool REPAIR>
 __global__ void k_general_huge(const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*, uint8_t*,
                                uint8_t*, int32_t*, int64_t, int32_t*, int64_t, PolyState, const int32_t*,
@@ -260,11 +260,11 @@ int run_build(polylla_ctx* c, const polylla_tri* t, const int32_t* list, bool fr
     const int gb = 256;
     if (repair)
       hipLaunchKernelGGL(k_general_big<true>, dim3(gb), dim3(1024), 0, s, list, from_seeds, nhe, t->n_vertices,
-                         t->twin, t->origin, he, vtx, c->stage, c->stage_cap, c->arena, c->arena_cap, ps,
+                         t->twin, t->origin, c->lab4, he, vtx, c->stage, c->stage_cap, c->arena, c->arena_cap, ps,
                          c->deferred, c->cap_t, c->huge, c->cnt);
     else
       hipLaunchKernelGGL(k_general_big<false>, dim3(gb), dim3(1024), 0, s, list, from_seeds, nhe, t->n_vertices,
-                         t->twin, t->origin, he, vtx, c->stage, c->stage_cap, c->arena, c->arena_cap, ps,
+                         t->twin, t->origin, c->lab4, he, vtx, c->stage, c->stage_cap, c->arena, c->arena_cap, ps,
                          c->deferred, c->cap_t, c->huge, c->cnt);
   }
   {

@@ -1144,12 +1144,18 @@ struct BigLds {
   int32_t hval[kLCap];   // hash values (int16 per hash slot); then per-piece start slot
   int16_t nx[kLCap];     // successor slot; then sorted piece order
   int16_t jp[kLCap];     // jump pointers; dead flags; piece list
-  int32_t a[kLCap];      // piece id (smallest slot on the cycle); tip order
+  int32_t a[kLCap];      // twin of each slot; then tip order; then piece id (smallest slot on the cycle)
   int32_t b[kLCap];      // vertex id of each slot
+  int32_t kc[kLCap / 2]; // repair: undecided smaller tips whose opened edge ends at this tip
+  int16_t kf[kLCap / 2]; // repair: rank of the tip at the far end of this tip's opened edge, or -1
+  uint32_t emask[128];   // repair: end vertices of opened edges, hashed to 4096 bits
   int32_t sc[16];
 };
 
-enum { SC_QLEN, SC_LO, SC_HI, SC_NFH, SC_NTIP, SC_OVER, SC_BAD, SC_NSPLIT, SC_NP, SC_ITEM, SC_SBASE, SC_NEND };
+enum {
+  SC_QLEN, SC_LO, SC_HI, SC_NFH, SC_NTIP, SC_OVER, SC_BAD, SC_NSPLIT, SC_NP, SC_ITEM, SC_SBASE, SC_NEND, SC_RB,
+  SC_PEND  // two slots, used alternately
+};
 
 __device__ __forceinline__ int hash_slot(int32_t key) {
   return (int)(((uint32_t)key * 2654435761u) >> (32 - 13));
@@ -1203,6 +1209,7 @@ constexpr int32_t kNoChange = -2;
 __device__ __forceinline__ void successors(const BigLds& S, int L, int first_new, const int32_t* ends, int ne,
                                            int32_t (&succ)[kPer], int32_t nhe, const int32_t* __restrict__ twin,
                                            const uint8_t* __restrict__ he) {
+  // ends are also hashed into S.emask (vertex & 4095): most slots are decided by one bit
   const int tid = threadIdx.x;
   bool act[kPer];
 #pragma unroll
@@ -1211,8 +1218,11 @@ __device__ __forceinline__ void successors(const BigLds& S, int L, int first_new
     act[u] = k < L;
     if (act[u] && ends && k < first_new) {
       const int32_t head = S.b[S.nx[k]];
-      bool hit = false;
-      for (int e = 0; e < ne; ++e) hit |= ends[e] == head;
+      bool hit = (S.emask[(head & 4095) >> 5] >> (head & 31)) & 1u;
+      if (hit) {
+        hit = false;
+        for (int e = 0; e < ne; ++e) hit |= ends[e] == head;
+      }
       act[u] = hit;
     }
     succ[u] = act[u] ? he_next(S.fh[k]) : kNoChange;
@@ -1250,9 +1260,10 @@ __device__ __forceinline__ void successors(const BigLds& S, int L, int first_new
 template <bool REPAIR>
 __global__ __launch_bounds__(kBigThreads) void k_general_big(
     const int32_t* __restrict__ list, bool from_seeds, int32_t nhe, int64_t nv, const int32_t* __restrict__ twin,
-    const int32_t* __restrict__ origin, uint8_t* __restrict__ he, uint8_t* __restrict__ vtx,
-    int32_t* __restrict__ stage, int64_t stage_cap, int32_t* __restrict__ arena, int64_t arena_cap, PolyState ps,
-    const int32_t* __restrict__ deferred, int64_t deferred_cap, int32_t* __restrict__ huge, Counters* cnt) {
+    const int32_t* __restrict__ origin, const uint32_t* __restrict__ lab4, uint8_t* __restrict__ he,
+    uint8_t* __restrict__ vtx, int32_t* __restrict__ stage, int64_t stage_cap, int32_t* __restrict__ arena,
+    int64_t arena_cap, PolyState ps, const int32_t* __restrict__ deferred, int64_t deferred_cap,
+    int32_t* __restrict__ huge, Counters* cnt) {
   __shared__ BigLds S;
   int16_t* hv = reinterpret_cast<int16_t*>(S.hval);  // hash values: int16 per hash slot (kHCap of them)
   const int tid = threadIdx.x;
@@ -1288,19 +1299,26 @@ __global__ __launch_bounds__(kBigThreads) void k_general_big(
         const int32_t code = S.q[j];
         const int32_t t = code < 0 ? (-1 - code) / 3 : code / 3;
         const int32_t entry = code < 0 ? -1 : code;
+        // label word, twin and origin triples of the triangle: one round trip
+        const Int3 tw3 = *reinterpret_cast<const Int3*>(twin + 3 * t);
+        const Int3 or3 = *reinterpret_cast<const Int3*>(origin + 3 * t);
+        const uint32_t lw = lab4[t];
+#pragma unroll
         for (int e = 0; e < 3; ++e) {
           const int32_t h = 3 * t + e;
           if (h == entry) continue;
-          if (he[h] & kFrontier) {
+          const int32_t tw = sel3(tw3.x, tw3.y, tw3.z, e);
+          if ((lw >> (8 * e)) & kFrontier) {
             const int idx = atomicAdd(&S.sc[SC_NFH], 1);
             if (idx < kLCap) {
               S.fh[idx] = h;
+              S.b[idx] = sel3(or3.x, or3.y, or3.z, e);
+              S.a[idx] = tw;
               hash_insert(S, hv, h, idx);
             } else {
               S.sc[SC_OVER] = 1;
             }
           } else {
-            const int32_t tw = twin[h];
             if ((uint32_t)tw >= (uint32_t)nhe) {
               S.sc[SC_BAD] = 1;
               continue;
@@ -1348,14 +1366,13 @@ __global__ __launch_bounds__(kBigThreads) void k_general_big(
       } else {
         S.nx[k] = (int16_t)j;
       }
-      const int32_t tw = twin[h];
-      if (c >= 0 && c == tw) {
+      const int32_t tw = S.a[k];
+      if (c >= 0 && c == tw && j >= 0) {
         const int p = atomicAdd(&S.sc[SC_NTIP], 1);
-        S.q[2 * p] = origin[c];
+        S.q[2 * p] = S.b[j];
         S.q[2 * p + 1] = c;
       }
       if ((uint32_t)tw < (uint32_t)nhe && hash_find(S, hv, tw) >= 0) he[h] |= kBarrier;
-      S.b[k] = origin[h];
     }
     __syncthreads();
     if (S.sc[SC_BAD]) {
@@ -1406,25 +1423,82 @@ __global__ __launch_bounds__(kBigThreads) void k_general_big(
         S.a[r] = p;
       }
       __syncthreads();
+      // Live tips in increasing vertex order; a live tip whose opened edge
+      // ends at a larger tip's vertex removes that tip. kf[r] is that larger
+      // tip's rank; the ranks form a forest with edges to larger ranks, decided
+      // in rounds: a tip none of whose undecided smaller tips point at it is
+      // live, and the tip it points at is dead.
+      for (int r = tid; r < ntip; r += kBigThreads) {
+        S.kc[r] = 0;
+        S.jp[r] = 0;
+      }
+      for (int w = tid; w < 128; w += kBigThreads) S.emask[w] = 0;
       if (tid == 0) {
-        // live tips in increasing vertex order; a live tip whose opened edge
-        // ends at a larger tip vertex removes that tip
-        for (int r = 0; r < ntip; ++r) S.jp[r] = 0;
-        int ns = 0;
-        for (int r = 0; r < ntip; ++r) {
-          if (S.jp[r]) continue;
-          ++ns;
-          const int32_t x = S.a[kLCap / 2 + S.a[r]];
-          int lo = r + 1, hi = ntip;
-          while (lo < hi) {
-            int mid = (lo + hi) >> 1;
-            if (S.q[2 * S.a[mid]] < x) lo = mid + 1;
-            else hi = mid;
-          }
-          if (lo < ntip && S.q[2 * S.a[lo]] == x) S.jp[lo] = 1;
+        S.sc[SC_PEND] = 0;
+        S.sc[SC_PEND + 1] = 0;
+        S.sc[SC_NSPLIT] = 0;
+        S.sc[SC_NEND] = 0;
+      }
+      __syncthreads();
+      for (int r = tid; r < ntip; r += kBigThreads) {
+        const int32_t x = S.a[kLCap / 2 + S.a[r]];
+        int lo = r + 1, hi = ntip;
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (S.q[2 * S.a[mid]] < x) lo = mid + 1;
+          else hi = mid;
         }
-        S.sc[SC_NSPLIT] = ns;
-        if (L + 2 * ns > kLCap) S.sc[SC_OVER] = 1;
+        const int f = (lo < ntip && S.q[2 * S.a[lo]] == x) ? lo : -1;
+        S.kf[r] = (int16_t)f;
+        if (f >= 0) atomicAdd(&S.kc[f], 1);
+      }
+      __syncthreads();
+      // jp: 0 undecided, 1 newly live, 2 live, 3 newly dead, 4 dead
+      for (int round = 0;; ++round) {
+        const int par = SC_PEND + (round & 1);
+        for (int r = tid; r < ntip; r += kBigThreads) {
+          if (S.jp[r] != 0) continue;
+          if (S.kc[r] == 0) S.jp[r] = 1;
+          else S.sc[par] = 1;
+        }
+        __syncthreads();
+        if (tid == 0) S.sc[SC_PEND + ((round + 1) & 1)] = 0;
+        for (int r = tid; r < ntip; r += kBigThreads) {
+          if (S.jp[r] != 1) continue;
+          S.jp[r] = 2;
+          if (S.kf[r] >= 0) S.jp[S.kf[r]] = 3;
+        }
+        __syncthreads();
+        for (int r = tid; r < ntip; r += kBigThreads) {
+          if (S.jp[r] != 3) continue;
+          S.jp[r] = 4;
+          if (S.kf[r] >= 0) atomicSub(&S.kc[S.kf[r]], 1);
+        }
+        __syncthreads();
+        if (!S.sc[par]) break;
+      }
+      // jp[r] = 1 marks a dead tip from here on; live tips count the splits
+      // and list the end vertices of their opened edges (q[2 * ntip ...])
+      const bool ends_fit = 4 * ntip <= kKCap;
+      for (int r = tid; r < ntip; r += kBigThreads) {
+        const bool dead = S.jp[r] == 4;
+        S.jp[r] = dead ? 1 : 0;
+        if (dead) continue;
+        atomicAdd(&S.sc[SC_NSPLIT], 1);
+        if (ends_fit) {
+          const int p = S.a[r];
+          const int32_t v0 = S.q[2 * p], v1 = S.a[kLCap / 2 + p];
+          const int pos = atomicAdd(&S.sc[SC_NEND], 2);
+          S.q[2 * ntip + pos] = v0;
+          S.q[2 * ntip + pos + 1] = v1;
+          atomicOr(&S.emask[(v0 & 4095) >> 5], 1u << (v0 & 31));
+          atomicOr(&S.emask[(v1 & 4095) >> 5], 1u << (v1 & 31));
+        }
+      }
+      __syncthreads();
+      if (tid == 0) {
+        if (!ends_fit) S.sc[SC_NEND] = -1;  // too many: recompute every successor
+        if (L + 2 * S.sc[SC_NSPLIT] > kLCap) S.sc[SC_OVER] = 1;
       }
       __syncthreads();
       if (S.sc[SC_BAD]) {
@@ -1454,21 +1528,6 @@ __global__ __launch_bounds__(kBigThreads) void k_general_big(
         S.b[idx + 1] = origin[te];
         hash_insert(S, hv, e, idx);
         hash_insert(S, hv, te, idx + 1);
-      }
-      // end points of the opened edges (q[2048..] while it has room)
-      if (tid == 0) {
-        int ne = 0;
-        if (2 * ntip + 2 * S.sc[SC_NSPLIT] <= kKCap) {
-          for (int r = 0; r < ntip; ++r) {
-            if (S.jp[r]) continue;
-            const int p = S.a[r];
-            S.q[2 * ntip + ne++] = S.q[2 * p];
-            S.q[2 * ntip + ne++] = S.a[kLCap / 2 + p];
-          }
-        } else {
-          ne = -1;  // too many: recompute every successor
-        }
-        S.sc[SC_NEND] = ne;
       }
       __syncthreads();
       if (tid == 0 && S.sc[SC_NSPLIT]) atomicAdd(&cnt->n_splits, (uint32_t)S.sc[SC_NSPLIT]);
@@ -1619,9 +1678,19 @@ __global__ __launch_bounds__(kBigThreads) void k_general_big(
       S.nx[r] = (int16_t)p;
     }
     __syncthreads();
+    // piece lengths in output order and their offsets (block scan; np <= kLCap = 4 * kBigThreads)
+    int32_t lens[4];
+    uint32_t mine = 0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int r = 4 * tid + u;
+      lens[u] = r < np ? S.q[pstart[S.nx[r]]] + 1 : 0;
+      mine += (uint32_t)lens[u];
+    }
+    uint2 tot;
+    const uint2 pre = block_exclusive_scan<kBigThreads>(mine, 0u, &tot);
     if (tid == 0) {
-      int32_t total = 0;
-      for (int r = 0; r < np; ++r) total += S.q[pstart[S.nx[r]]] + 1;
+      const int32_t total = (int32_t)tot.x;
       const uint32_t sb = atomicAdd(&cnt->stage_top, (uint32_t)total);
       int32_t rb = -1;
       bool ok = (int64_t)sb + total <= stage_cap;
@@ -1633,23 +1702,31 @@ __global__ __launch_bounds__(kBigThreads) void k_general_big(
         set_error(cnt, POLYLLA_ENOMEM);
         S.sc[SC_OVER] = 1;
       } else {
-        int32_t run = 0;
-        for (int r = 0; r < np; ++r) {
-          const int p = S.nx[r];
-          const int32_t len = S.q[pstart[p]] + 1;
-          if (np > 1) {
-            arena[rb + 4 * r] = pmin[p];
-            arena[rb + 4 * r + 1] = pcnt[p];
-            arena[rb + 4 * r + 2] = S.fh[pstart[p]];
-            arena[rb + 4 * r + 3] = len;
-          }
-          pcnt[p] = run;  // output offset of the piece
-          run += len;
-        }
         ps.set(i, total, np, np == 1 ? S.fh[pstart[S.nx[0]]] : -1, (int32_t)sb);
         ps.prec[i] = np > 1 ? rb : -1;
       }
       S.sc[SC_SBASE] = (int32_t)sb;
+      S.sc[SC_RB] = rb;
+    }
+    __syncthreads();
+    if (!S.sc[SC_OVER]) {
+      // piece records for the emitter; pcnt[p] becomes the piece's output offset
+      const int32_t rb = S.sc[SC_RB];
+      int32_t run = (int32_t)pre.x;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int r = 4 * tid + u;
+        if (r >= np) continue;
+        const int p = S.nx[r];
+        if (np > 1) {
+          arena[rb + 4 * r] = pmin[p];
+          arena[rb + 4 * r + 1] = pcnt[p];
+          arena[rb + 4 * r + 2] = S.fh[pstart[p]];
+          arena[rb + 4 * r + 3] = lens[u];
+        }
+        pcnt[p] = run;
+        run += lens[u];
+      }
     }
     __syncthreads();
     if (!S.sc[SC_OVER]) {
@@ -1833,11 +1910,11 @@ template __global__ void k_general_small<false>(const int32_t*, bool, int32_t, i
                                                 const int32_t*, const uint32_t*, uint8_t*, uint8_t*, int32_t*,
                                                 int64_t, int32_t*, int64_t, PolyState, const int32_t*, Counters*);
 template __global__ void k_general_big<true>(const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*,
-                                             uint8_t*, uint8_t*, int32_t*, int64_t, int32_t*, int64_t, PolyState,
-                                             const int32_t*, int64_t, int32_t*, Counters*);
-template __global__ void k_general_big<false>(const int32_t*, bool, int32_t, int64_t, const int32_t*,
-                                              const int32_t*, uint8_t*, uint8_t*, int32_t*, int64_t, int32_t*,
-                                              int64_t, PolyState, const int32_t*, int64_t, int32_t*, Counters*);
+                                             const uint32_t*, uint8_t*, uint8_t*, int32_t*, int64_t, int32_t*, int64_t,
+                                             PolyState, const int32_t*, int64_t, int32_t*, Counters*);
+template __global__ void k_general_big<false>(const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*,
+                                              const uint32_t*, uint8_t*, uint8_t*, int32_t*, int64_t, int32_t*, int64_t,
+                                              PolyState, const int32_t*, int64_t, int32_t*, Counters*);
 template __global__ void k_general_huge<true>(const int32_t*, bool, int32_t, int64_t, const int32_t*,
                                               const int32_t*, uint8_t*, uint8_t*, int32_t*, int64_t, int32_t*,
                                               int64_t, PolyState, const int32_t*, Counters*);

@@ -65,6 +65,10 @@ struct polylla_ctx {
   Counters last{};
   int walk_cap = 24;  // vertices a lane walks before handing a polygon to a workgroup
   int walk_blocks = 512;  // persistent grid of the walk kernel (swept: 256..2048, 512 best at 10M)
+  // second stream: the workgroup region kernel runs beside the per-lane one
+  // (they touch disjoint regions); fork and join through events
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
   // event profiling
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;
@@ -243,6 +247,23 @@ int run_build(polylla_ctx* c, const polylla_tri* t, const int32_t* list, bool fr
       hipLaunchKernelGGL(k_walk<false>, dim3(gw), dim3(256), 0, s, list, nhe, t->twin, t->origin, c->lab4, c->stage,
                          c->stage_cap, ps, c->deferred, c->cap_t, c->walk_cap, c->cnt);
   }
+  // the long regions (workgroup kernel, side stream) and the short ones
+  // (per-lane kernel, caller's stream) in parallel
+  if (hipEventRecord(c->fork, s) != hipSuccess || hipStreamWaitEvent(c->side, c->fork, 0) != hipSuccess)
+    return POLYLLA_EHIP;
+  {
+    Prof p(c, c->side, KR_BIG);
+    const int gb = 128;  // persistent: blocks take long regions by ticket
+    if (repair)
+      hipLaunchKernelGGL(k_general_big<true>, dim3(gb), dim3(1024), 0, c->side, list, from_seeds, nhe, t->n_vertices,
+                         t->twin, t->origin, c->lab4, he, vtx, c->stage, c->stage_cap, c->arena, c->arena_cap, ps,
+                         c->deferred, c->cap_t, c->huge, c->cnt);
+    else
+      hipLaunchKernelGGL(k_general_big<false>, dim3(gb), dim3(1024), 0, c->side, list, from_seeds, nhe, t->n_vertices,
+                         t->twin, t->origin, c->lab4, he, vtx, c->stage, c->stage_cap, c->arena, c->arena_cap, ps,
+                         c->deferred, c->cap_t, c->huge, c->cnt);
+  }
+  if (hipEventRecord(c->join, c->side) != hipSuccess) return POLYLLA_EHIP;
   {
     Prof p(c, s, KR_GENERAL);
     const int gg = 2048;
@@ -255,18 +276,7 @@ int run_build(polylla_ctx* c, const polylla_tri* t, const int32_t* list, bool fr
                          t->twin, t->origin, c->lab4, he, vtx, c->stage, c->stage_cap, c->arena, c->arena_cap, ps,
                          c->deferred, c->cnt);
   }
-  {
-    Prof p(c, s, KR_BIG);
-    const int gb = 256;
-    if (repair)
-      hipLaunchKernelGGL(k_general_big<true>, dim3(gb), dim3(1024), 0, s, list, from_seeds, nhe, t->n_vertices,
-                         t->twin, t->origin, c->lab4, he, vtx, c->stage, c->stage_cap, c->arena, c->arena_cap, ps,
-                         c->deferred, c->cap_t, c->huge, c->cnt);
-    else
-      hipLaunchKernelGGL(k_general_big<false>, dim3(gb), dim3(1024), 0, s, list, from_seeds, nhe, t->n_vertices,
-                         t->twin, t->origin, c->lab4, he, vtx, c->stage, c->stage_cap, c->arena, c->arena_cap, ps,
-                         c->deferred, c->cap_t, c->huge, c->cnt);
-  }
+  if (hipStreamWaitEvent(s, c->join, 0) != hipSuccess) return POLYLLA_EHIP;
   {
     Prof p(c, s, KR_HUGE);
     if (repair)
@@ -304,7 +314,13 @@ int polylla_ctx_create(polylla_ctx** out, int device) {
     delete c;
     return POLYLLA_ENOMEM;
   }
-  if (hipMemset(c->cnt, 0, sizeof(Counters)) != hipSuccess) {
+  if (hipMemset(c->cnt, 0, sizeof(Counters)) != hipSuccess ||
+      hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->join, hipEventDisableTiming) != hipSuccess) {
+    if (c->join) (void)hipEventDestroy(c->join);
+    if (c->fork) (void)hipEventDestroy(c->fork);
+    if (c->side) (void)hipStreamDestroy(c->side);
     dfree(&c->cnt);
     delete c;
     return POLYLLA_EHIP;
@@ -320,6 +336,9 @@ void polylla_ctx_destroy(polylla_ctx* c) {
   free_scratch(c);
   dfree(&c->cnt);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  (void)hipEventDestroy(c->join);
+  (void)hipEventDestroy(c->fork);
+  (void)hipStreamDestroy(c->side);
   delete c;
 }
 

@@ -133,7 +133,54 @@ __global__ __launch_bounds__(256) void k_label(int64_t nt, const int32_t* __rest
   const int64_t t0 = ((int64_t)tile * 256 + threadIdx.x) * ITEMS;
   const int32_t nhe = (int32_t)(3 * nt);
   bool sd[ITEMS];
-  if (COMPUTE) {
+  // Whole tiles stage their labels in LDS and write them with coalesced
+  // 16-byte stores (the per-thread layout would write every line in pieces).
+  __shared__ uint4 s_w4[256 * ITEMS / 2];  // label words, then he words, then tri words of the tile
+  const int64_t tile_t0 = (int64_t)tile * 256 * ITEMS;
+  const bool full = COMPUTE && vec && tile_t0 + 256 * ITEMS <= nt &&
+                    ((reinterpret_cast<uintptr_t>(he) | reinterpret_cast<uintptr_t>(tri) |
+                      reinterpret_cast<uintptr_t>(lab4)) & 15) == 0;
+  if (full) {
+    uint32_t* s_w = reinterpret_cast<uint32_t*>(s_w4);
+    uint32_t* s_lab = s_w;
+    uint32_t* s_he = s_w + 256 * ITEMS;
+    uint32_t* s_tri = s_w + 256 * ITEMS + 256 * ITEMS * 3 / 4;
+    int32_t tw[3 * ITEMS];
+    const int4* tw4 = reinterpret_cast<const int4*>(twin + 3 * t0);
+#pragma unroll
+    for (int k = 0; k < 3 * ITEMS / 4; ++k) {
+      int4 q = tw4[k];
+      tw[4 * k] = q.x;
+      tw[4 * k + 1] = q.y;
+      tw[4 * k + 2] = q.z;
+      tw[4 * k + 3] = q.w;
+    }
+    uint32_t mm[ITEMS / 4];
+#pragma unroll
+    for (int k = 0; k < ITEMS / 4; ++k) mm[k] = reinterpret_cast<const uint32_t*>(lg + t0)[k];
+    const int lt = threadIdx.x * ITEMS;  // first triangle of this thread within the tile
+#pragma unroll
+    for (int g = 0; g < ITEMS / 4; ++g) {
+      uint32_t lab[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        lab[j] = label_triangle(t0 + 4 * g + j, (mm[g] >> (8 * j)) & 0xFF, tw + 3 * (4 * g + j), lg, nhe, cnt,
+                                &sd[4 * g + j]);
+      reinterpret_cast<uint4*>(s_lab + lt)[g] = make_uint4(lab[0], lab[1], lab[2], lab[3]);
+      s_he[3 * (lt / 4 + g)] = lab[0] | (lab[1] << 24);
+      s_he[3 * (lt / 4 + g) + 1] = (lab[1] >> 8) | (lab[2] << 16);
+      s_he[3 * (lt / 4 + g) + 2] = (lab[2] >> 16) | (lab[3] << 8);
+      s_tri[lt / 4 + g] = (sd[4 * g] ? kSeed : 0u) | ((sd[4 * g + 1] ? kSeed : 0u) << 8) |
+                          ((sd[4 * g + 2] ? kSeed : 0u) << 16) | ((sd[4 * g + 3] ? kSeed : 0u) << 24);
+    }
+    __syncthreads();
+    uint4* glab = reinterpret_cast<uint4*>(lab4 + tile_t0);
+    uint4* ghe = reinterpret_cast<uint4*>(he + 3 * tile_t0);
+    uint4* gtri = reinterpret_cast<uint4*>(tri + tile_t0);
+    for (int k = threadIdx.x; k < 256 * ITEMS / 4; k += 256) glab[k] = s_w4[k];
+    for (int k = threadIdx.x; k < 256 * ITEMS * 3 / 16; k += 256) ghe[k] = s_w4[256 * ITEMS / 4 + k];
+    for (int k = threadIdx.x; k < 256 * ITEMS / 16; k += 256) gtri[k] = s_w4[256 * ITEMS / 4 + 256 * ITEMS * 3 / 16 + k];
+  } else if (COMPUTE) {
     if (vec && t0 + ITEMS <= nt) {
       // ITEMS triangles: 3*ITEMS twins as int4, ITEMS Max bytes and labels as words
       int32_t tw[3 * ITEMS];

@@ -1,26 +1,25 @@
 // Traversal phase (Algorithm 3, PolyConstruction) and Reparation phase
 // (Algorithm 4) as gfx950 kernels.
 //
-// k_walk    : one lane per polygon. Walks the frontier half-edges of the
-//             region from its start half-edge with the region on the left
-//             (turning about each vertex through internal edges), staging the
-//             vertex ids in LDS (interleaved [slot][lane], conflict free). A
-//             cycle with no repeated vertex and at most kWalkCap vertices is
-//             complete: it is rotated to start at its smallest vertex and
-//             copied to a staging buffer at a wave-allocated slot. Every other
-//             cycle (a barrier-edge tip, another repeated vertex, or a long
-//             cycle) is queued for k_general.
-// k_general : one lane per queued polygon, data in a global arena. Records
-//             the whole cycle, marks barrier edges (frontier edges met twice),
-//             finds the tips (next frontier half-edge == twin), and, when
-//             repairing, opens the middle internal edge at every tip that is
-//             still a tip once the smaller tips are handled; then walks the
-//             pieces, each once, and sorts them by their canonical first two
-//             vertices.
-// k_scan_polys : single-pass decoupled look-back scan of (pieces, vertices)
-//             per polygon in seed order; writes counts and the final offset.
-// k_emit    : copies every polygon from staging to its place in the CSR output
-//             and writes its offsets and start half-edges.
+// k_walk          : persistent lanes, one polygon each at a time. Walks the
+//                   frontier half-edges of the region from its start
+//                   half-edge with the region on the left (turning about each
+//                   vertex through internal edges), keeping the vertex ids in
+//                   LDS (interleaved [slot][lane]). A cycle with no repeated
+//                   vertex and at most kWalkCap vertices is complete and is
+//                   staged unrotated with the slot of its smallest vertex;
+//                   cycles with a tip or another repeated vertex are queued
+//                   for k_general_small, longer ones for k_general_big.
+// k_general_small : one lane per queued short polygon; gathers the region
+//                   into LDS and runs barrier marking, tip detection, the
+//                   repair and the piece walk there.
+// k_general_big   : one 1024-thread workgroup per long polygon; the same
+//                   steps with the region's frontier in LDS, in parallel.
+// k_general_huge  : one lane per region beyond the workgroup's LDS, global
+//                   arena (none in the benchmark workloads).
+// k_scan_emit     : single-pass decoupled look-back scan of (pieces,
+//                   vertices) per polygon in seed order fused with the CSR
+//                   write.
 #include "common.h"
 #include "scan.h"
 
@@ -1765,12 +1764,15 @@ __global__ __launch_bounds__(64) void k_general_huge(const int32_t* __restrict__
 // Scan and emission in one pass. A tile of kScanTile polygons (in seed order)
 // sums its (pieces, vertices), gets its exclusive prefix by decoupled
 // look-back and writes its part of the CSR output: offsets and start
-// half-edges per polygon, then the vertex range of the whole tile with all
-// threads, each output slot finding its polygon by binary search in LDS so
-// that the stores are coalesced. Blocks beyond the tile count exit before
-// taking a ticket.
+// half-edges per output polygon (staged in LDS, stored coalesced), then the
+// vertex range of the whole tile with all threads, each output slot finding
+// its polygon by binary search in LDS so that the stores are coalesced.
+// Blocks beyond the tile count exit before taking a ticket.
 constexpr int kScanItems = 8;
 constexpr int kScanTile = 256 * kScanItems;
+constexpr int kScanLog = 11;            // log2(kScanTile)
+constexpr int kScanOut = 2 * kScanTile;  // output polygons of a tile staged in LDS
+static_assert((1 << kScanLog) == kScanTile, "binary search depth");
 
 __global__ __launch_bounds__(256) void k_scan_emit(PolyState ps, uint64_t* status, const int32_t* __restrict__ stage,
                                                    const int32_t* __restrict__ arena, int32_t* __restrict__ offsets,
@@ -1780,6 +1782,8 @@ __global__ __launch_bounds__(256) void k_scan_emit(PolyState ps, uint64_t* statu
   __shared__ int32_t s_voff[kScanTile + 1];
   __shared__ int32_t s_src[kScanTile];
   __shared__ uint8_t s_rot[kScanTile];
+  __shared__ int32_t s_po[kScanOut];  // offsets of the tile's output polygons
+  __shared__ int32_t s_ps[kScanOut];  // their start half-edges
   __shared__ int32_t s_ok;
   const uint32_t R = cnt->n_seeds;
   const uint32_t ntiles = (R + kScanTile - 1) / kScanTile;
@@ -1817,7 +1821,9 @@ __global__ __launch_bounds__(256) void k_scan_emit(PolyState ps, uint64_t* statu
   __syncthreads();
   const bool ok = s_ok != 0;
   if (!ok && threadIdx.x == 0) set_error(cnt, POLYLLA_ECAPACITY);
-  // per-polygon offsets and start half-edges; tile-local vertex offsets in LDS
+  // per-polygon offsets and start half-edges (staged in LDS when the tile's
+  // output polygons fit, then stored coalesced); tile-local vertex offsets
+  const bool fit = total.x <= (uint32_t)kScanOut;
   uint32_t ra = ex.x + pre.x, rb = pre.y;
 #pragma unroll
   for (int j = 0; j < kScanItems; ++j) {
@@ -1829,15 +1835,26 @@ __global__ __launch_bounds__(256) void k_scan_emit(PolyState ps, uint64_t* statu
     s_rot[k] = rot;
     if (ok && i < R && np > 0) {
       const int32_t vg = (int32_t)(tile_v0 + rb);
+      const uint32_t lp = ra - ex.x;  // tile-local output polygon
       if (np == 1) {
-        offsets[ra] = vg;
-        if (start) start[ra] = rc[j].z;
+        if (fit) {
+          s_po[lp] = vg;
+          s_ps[lp] = rc[j].z;
+        } else {
+          offsets[ra] = vg;
+          if (start) start[ra] = rc[j].z;
+        }
       } else {
         const int32_t* rec = arena + ps.prec[i];
         int32_t acc = 0;
         for (int32_t q = 0; q < np; ++q) {
-          offsets[ra + q] = vg + acc;
-          if (start) start[ra + q] = rec[4 * q + 2];
+          if (fit) {
+            s_po[lp + q] = vg + acc;
+            s_ps[lp + q] = rec[4 * q + 2];
+          } else {
+            offsets[ra + q] = vg + acc;
+            if (start) start[ra + q] = rec[4 * q + 2];
+          }
           acc += rec[4 * q + 3];
         }
       }
@@ -1848,19 +1865,45 @@ __global__ __launch_bounds__(256) void k_scan_emit(PolyState ps, uint64_t* statu
   if (threadIdx.x == 255) s_voff[kScanTile] = (int32_t)rb;
   __syncthreads();
   if (!ok) return;
-  // the tile's vertex range, coalesced
-  const int32_t nv_tile = (int32_t)total.y;
-  for (int32_t k = threadIdx.x; k < nv_tile; k += 256) {
-    int lo = 0, hi = kScanTile;  // last polygon with s_voff <= k
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (s_voff[mid] <= k) lo = mid;
-      else hi = mid;
+  if (fit) {
+    for (uint32_t k = threadIdx.x; k < total.x; k += 256) {
+      offsets[ex.x + k] = s_po[k];
+      if (start) start[ex.x + k] = s_ps[k];
     }
-    const int32_t len = s_voff[lo + 1] - s_voff[lo];
-    int32_t off = k - s_voff[lo] + s_rot[lo];
-    off = off >= len ? off - len : off;
-    verts[tile_v0 + k] = stage[s_src[lo] + off];
+  }
+  // the tile's vertex range, coalesced: every slot finds its polygon by
+  // binary search in LDS, four independent searches in lockstep per thread
+  const int32_t nv_tile = (int32_t)total.y;
+  for (int32_t k0 = threadIdx.x; k0 < nv_tile; k0 += 4 * 256) {
+    int lo[4], hi[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      lo[u] = 0;
+      hi[u] = kScanTile;
+    }
+#pragma unroll
+    for (int step = 0; step < kScanLog; ++step) {  // last polygon with s_voff <= k
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int mid = (lo[u] + hi[u]) >> 1;
+        if (s_voff[mid] <= k0 + 256 * u) lo[u] = mid;
+        else hi[u] = mid;
+      }
+    }
+    int32_t v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int32_t k = k0 + 256 * u;
+      if (k < nv_tile) {
+        const int32_t len = s_voff[lo[u] + 1] - s_voff[lo[u]];
+        int32_t off = k - s_voff[lo[u]] + s_rot[lo[u]];
+        off = off >= len ? off - len : off;
+        v[u] = stage[s_src[lo[u]] + off];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (k0 + 256 * u < nv_tile) verts[tile_v0 + k0 + 256 * u] = v[u];
   }
 }
 

@@ -251,21 +251,28 @@ __global__ __launch_bounds__(256) void k_walk(const int32_t* __restrict__ list, 
         }
       }
       fresh = false;
-      while (!pending && !done) {
+      // At most three frontier half-edges of one triangle follow each other
+      // (a triangle with three is its own region and closes at the fourth
+      // check), so four unrolled steps take every lane to its next crossing
+      // (a load) or to the end of its cycle; no divergent loop.
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (pending || done) continue;
         if (r.lab(ci) & kFrontier) {
           const int32_t c = 3 * t + ci;
-          if (s < 0) s = c;  // start found by turning about the seed's vertex 0
-          else if (L > 0) {
+          if (s < 0) {
+            s = c;  // start found by turning about the seed's vertex 0
+          } else if (L > 0) {
             if (c == twh) complex = true;  // barrier-edge tip
             if (c == s) {
               done = true;
-              break;
+              continue;
             }
           }
           if (L == walk_cap) {
             result = kLarge;
             done = true;
-            break;
+            continue;
           }
           const int32_t v = r.org(ci);
           if (!complex) {
@@ -291,7 +298,7 @@ __global__ __launch_bounds__(256) void k_walk(const int32_t* __restrict__ list, 
           if ((uint32_t)tw >= (uint32_t)nhe || ++steps > nhe) {
             result = kInvalid;
             done = true;
-            break;
+            continue;
           }
           t = tw / 3;
           ci = next_local(tw - 3 * t);

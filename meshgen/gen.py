@@ -262,10 +262,11 @@ def request_points(n: int, kind: str, seed: int) -> np.ndarray:
     return _clusters(rng, n, 4, 0.05)
 
 
-def pack_meshes(meshes):
+def pack_meshes(meshes, with_next: bool = True):
     """Concatenate meshes into one packed CSR of meshes with global indices:
     returns (mesh, vtx_off, he_off) where mesh m owns vertices
-    vtx_off[m]:vtx_off[m+1] and half-edges he_off[m]:he_off[m+1]."""
+    vtx_off[m]:vtx_off[m+1] and half-edges he_off[m]:he_off[m+1]. Without
+    `with_next` the implied grouped next array is left out (None)."""
     V = np.array([m.n_vertices for m in meshes], dtype=np.int64)
     H = np.array([m.n_halfedges for m in meshes], dtype=np.int64)
     vtx_off = np.zeros(len(meshes) + 1, np.int64)
@@ -282,8 +283,8 @@ def pack_meshes(meshes):
         xy[vtx_off[k]:vtx_off[k + 1]] = m.xy
         origin[a:b] = m.origin + np.int32(vtx_off[k])
         twin[a:b] = np.where(m.twin >= 0, m.twin + np.int32(a), -1)
-    packed = Mesh(xy=xy, origin=origin, twin=twin, next=_grouped_next(int(he_off[-1])), lattice=None,
-                  meta={"n_meshes": len(meshes)})
+    nxt = _grouped_next(int(he_off[-1])) if with_next else None
+    packed = Mesh(xy=xy, origin=origin, twin=twin, next=nxt, lattice=None, meta={"n_meshes": len(meshes)})
     return packed, vtx_off, he_off
 
 

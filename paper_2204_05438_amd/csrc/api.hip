@@ -24,10 +24,10 @@ template <bool REPAIR>
 __global__ void k_general_small(const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*,
                                 const uint32_t*, uint8_t*, uint8_t*, int32_t*, int64_t, int32_t*, int64_t, PolyState,
                                 const int32_t*, Counters*);
-template <bool REPAIR>
+template <bool REPAIR, int NT, int KC, int LC, int HB>
 __global__ void k_general_big(const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*, const uint32_t*,
                               uint8_t*, uint8_t*, int32_t*, int64_t, int32_t*, int64_t, PolyState, const int32_t*,
-                              int64_t, int32_t*, Counters*);
+                              bool, int64_t, const uint32_t*, uint32_t*, int32_t*, int64_t, uint32_t*, Counters*);
 template <bool REPAIR>
 __global__ void k_general_huge(const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*, uint8_t*,
                                uint8_t*, int32_t*, int64_t, int32_t*, int64_t, PolyState, const int32_t*,
@@ -51,7 +51,9 @@ struct polylla_ctx {
   uint32_t* lab4 = nullptr;  // packed label word per triangle (walk)
   int32_t* seeds = nullptr;
   int32_t* deferred = nullptr;
-  int32_t* huge = nullptr;  // long regions beyond the workgroup's LDS
+  int32_t* over = nullptr;  // regions beyond the one-wave workgroup's LDS
+  int32_t* huge = nullptr;  // regions beyond the 1024-thread workgroup's LDS
+  int64_t over_cap = 0, huge_cap = 0;
   int32_t* poly_arrays = nullptr;  // per-polygon records: 4 ints + 1 int per polygon (PolyState)
   int32_t* stage = nullptr;
   int64_t stage_cap = 0;
@@ -90,11 +92,12 @@ constexpr int64_t kStageChunkHost = 4096; // staging ints a walk wave reserves a
 
 enum KernelId {
   KR_RESET, KR_LONGEST, KR_LABEL, KR_COMPACT, KR_PACK, KR_WALK, KR_GENERAL, KR_BIG, KR_HUGE, KR_SCAN, KR_VALIDATE,
-  KR_BATCH, KR_N
+  KR_BATCH, KR_BIGW, KR_N
 };
-const char* kKernelNames[KR_N] = {"k_reset",     "k_longest",       "k_label",       "k_compact_seeds",
-                                  "k_pack_labels", "k_walk",     "k_general_small", "k_general_big",
-                                  "k_general_huge", "k_scan_emit", "k_validate",     "k_batch_offsets"};
+const char* kKernelNames[KR_N] = {"k_reset",         "k_longest",       "k_label",          "k_compact_seeds",
+                                  "k_pack_labels",   "k_walk",          "k_general_small",  "k_general_big",
+                                  "k_general_huge",  "k_scan_emit",     "k_validate",       "k_batch_offsets",
+                                  "k_general_big_wg"};
 
 // Event pair around one kernel launch when profiling is on.
 struct Prof {
@@ -138,6 +141,7 @@ void free_scratch(polylla_ctx* c) {
   dfree(&c->seeds);
   dfree(&c->deferred);
   dfree(&c->huge);
+  dfree(&c->over);
   dfree(&c->poly_arrays);
   dfree(&c->stage);
   dfree(&c->arena);
@@ -164,7 +168,8 @@ int ensure(polylla_ctx* c, int64_t nt, int64_t nv) {
                                    ((int64_t)1 << 31) - 1);
   c->arena_cap = 6 * T + 4096;
   c->n_status = 2 * ntiles;
-  if ((rc = dalloc(&c->lg, T)) || (rc = dalloc(&c->lab4, T)) || (rc = dalloc(&c->seeds, T)) || (rc = dalloc(&c->deferred, T)) || (rc = dalloc(&c->huge, T / 1024 + 64)) ||
+  if ((rc = dalloc(&c->lg, T)) || (rc = dalloc(&c->lab4, T)) || (rc = dalloc(&c->seeds, T)) || (rc = dalloc(&c->deferred, T)) || (rc = dalloc(&c->huge, c->huge_cap = T / 1024 + 64)) ||
+      (rc = dalloc(&c->over, c->over_cap = T / 32 + 64)) ||
       (rc = dalloc(&c->poly_arrays, 5 * T)) || (rc = dalloc(&c->stage, c->stage_cap)) ||
       (rc = dalloc(&c->arena, c->arena_cap)) || (rc = dalloc(&c->status, c->n_status)) ||
       (rc = dalloc(&c->he_s, 3 * T)) || (rc = dalloc(&c->tri_s, T)) || (rc = dalloc(&c->vtx_s, V))) {
@@ -251,17 +256,37 @@ int run_build(polylla_ctx* c, const polylla_tri* t, const int32_t* list, bool fr
   // (per-lane kernel, caller's stream) in parallel
   if (hipEventRecord(c->fork, s) != hipSuccess || hipStreamWaitEvent(c->side, c->fork, 0) != hipSuccess)
     return POLYLLA_EHIP;
+  // long regions: one wave per region first (regions of up to 128 triangles
+  // and frontier half-edges), then 1024 threads per region for the rest
   {
     Prof p(c, c->side, KR_BIG);
-    const int gb = 128;  // persistent: blocks take long regions by ticket
+    Counters* k = c->cnt;
+    const int gm = 4096;  // persistent: one-wave blocks take regions by ticket
     if (repair)
-      hipLaunchKernelGGL(k_general_big<true>, dim3(gb), dim3(1024), 0, c->side, list, from_seeds, nhe, t->n_vertices,
-                         t->twin, t->origin, c->lab4, he, vtx, c->stage, c->stage_cap, c->arena, c->arena_cap, ps,
-                         c->deferred, c->cap_t, c->huge, c->cnt);
+      hipLaunchKernelGGL((k_general_big<true, 64, 128, 128, 8>), dim3(gm), dim3(64), 0, c->side, list, from_seeds, nhe,
+                         t->n_vertices, t->twin, t->origin, c->lab4, he, vtx, c->stage, c->stage_cap, c->arena,
+                         c->arena_cap, ps, c->deferred, true, c->cap_t, &k->n_big, &k->big_ticket, c->over,
+                         c->over_cap, &k->n_over, k);
     else
-      hipLaunchKernelGGL(k_general_big<false>, dim3(gb), dim3(1024), 0, c->side, list, from_seeds, nhe, t->n_vertices,
-                         t->twin, t->origin, c->lab4, he, vtx, c->stage, c->stage_cap, c->arena, c->arena_cap, ps,
-                         c->deferred, c->cap_t, c->huge, c->cnt);
+      hipLaunchKernelGGL((k_general_big<false, 64, 128, 128, 8>), dim3(gm), dim3(64), 0, c->side, list, from_seeds,
+                         nhe, t->n_vertices, t->twin, t->origin, c->lab4, he, vtx, c->stage, c->stage_cap, c->arena,
+                         c->arena_cap, ps, c->deferred, true, c->cap_t, &k->n_big, &k->big_ticket, c->over,
+                         c->over_cap, &k->n_over, k);
+  }
+  {
+    Prof p(c, c->side, KR_BIGW);
+    Counters* k = c->cnt;
+    const int gb = 128;  // persistent: blocks take the remaining long regions by ticket
+    if (repair)
+      hipLaunchKernelGGL((k_general_big<true, 1024, 4096, 4096, 13>), dim3(gb), dim3(1024), 0, c->side, list,
+                         from_seeds, nhe, t->n_vertices, t->twin, t->origin, c->lab4, he, vtx, c->stage, c->stage_cap,
+                         c->arena, c->arena_cap, ps, c->over, false, (int64_t)0, &k->n_over, &k->over_ticket, c->huge,
+                         c->huge_cap, &k->n_fallback, k);
+    else
+      hipLaunchKernelGGL((k_general_big<false, 1024, 4096, 4096, 13>), dim3(gb), dim3(1024), 0, c->side, list,
+                         from_seeds, nhe, t->n_vertices, t->twin, t->origin, c->lab4, he, vtx, c->stage, c->stage_cap,
+                         c->arena, c->arena_cap, ps, c->over, false, (int64_t)0, &k->n_over, &k->over_ticket, c->huge,
+                         c->huge_cap, &k->n_fallback, k);
   }
   if (hipEventRecord(c->join, c->side) != hipSuccess) return POLYLLA_EHIP;
   {

@@ -1137,23 +1137,22 @@ __global__ __launch_bounds__(64) void k_general_small(const int32_t* __restrict_
 //    pieces ordered by their first two vertices; vertices written to staging.
 // Regions beyond the LDS capacity are queued for general_one on one lane.
 
-constexpr int kBigThreads = 1024;
-constexpr int kKCap = 4096;  // triangles of one region
-constexpr int kLCap = 4096;  // frontier half-edges, opened ones included
-constexpr int kHCap = 8192;  // hash slots (power of two)
-constexpr int kPer = kLCap / kBigThreads;
-
+// Capacities of one instance: KC triangles, LC frontier half-edges (opened
+// ones included), HB hash bits (2^HB = 2 LC hash slots).
+template <int KC, int LC, int HB>
 struct BigLds {
-  int32_t q[kKCap];      // BFS queue; then tips (vertex, half-edge); then distances
-  int32_t fh[kLCap];     // frontier half-edges of the region
+  static constexpr int kKCap = KC, kLCap = LC, kHBits = HB, kHCap = 1 << HB;
+  static_assert(kHCap == 2 * LC, "the hash area is reused for two per-piece arrays");
+  int32_t q[KC];         // BFS queue; then tips (vertex, half-edge); then distances
+  int32_t fh[LC];        // frontier half-edges of the region
   int32_t hkey[kHCap];   // hash keys; then per-piece smallest vertex / second vertex
-  int32_t hval[kLCap];   // hash values (int16 per hash slot); then per-piece start slot
-  int16_t nx[kLCap];     // successor slot; then sorted piece order
-  int16_t jp[kLCap];     // jump pointers; dead flags; piece list
-  int32_t a[kLCap];      // twin of each slot; then tip order; then piece id (smallest slot on the cycle)
-  int32_t b[kLCap];      // vertex id of each slot
-  int32_t kc[kLCap / 2]; // repair: undecided smaller tips whose opened edge ends at this tip
-  int16_t kf[kLCap / 2]; // repair: rank of the tip at the far end of this tip's opened edge, or -1
+  int32_t hval[LC];      // hash values (int16 per hash slot); then per-piece start slot
+  int16_t nx[LC];        // successor slot; then sorted piece order
+  int16_t jp[LC];        // jump pointers; dead flags; piece list
+  int32_t a[LC];         // twin of each slot; then tip order; then piece id (smallest slot on the cycle)
+  int32_t b[LC];         // vertex id of each slot
+  int32_t kc[LC / 2];    // repair: undecided smaller tips whose opened edge ends at this tip
+  int16_t kf[LC / 2];    // repair: rank of the tip at the far end of this tip's opened edge, or -1
   uint32_t emask[128];   // repair: end vertices of opened edges, hashed to 4096 bits
   int32_t sc[16];
 };
@@ -1163,14 +1162,17 @@ enum {
   SC_PEND  // two slots, used alternately
 };
 
+template <int HB>
 __device__ __forceinline__ int hash_slot(int32_t key) {
-  return (int)(((uint32_t)key * 2654435761u) >> (32 - 13));
+  return (int)(((uint32_t)key * 2654435761u) >> (32 - HB));
 }
 
 // Open-addressing hash (linear probing) from half-edge id to slot; keys in
 // hkey, values as int16 per hash slot in the hval area.
-__device__ __forceinline__ void hash_insert(BigLds& S, int16_t* hv, int32_t key, int32_t val) {
-  int s = hash_slot(key);
+template <class LDS>
+__device__ __forceinline__ void hash_insert(LDS& S, int16_t* hv, int32_t key, int32_t val) {
+  constexpr int kHCap = LDS::kHCap;
+  int s = hash_slot<LDS::kHBits>(key);
   for (int k = 0; k < kHCap; ++k) {
     int32_t old = atomicCAS(&S.hkey[s], -1, key);
     if (old == -1 || old == key) {
@@ -1181,8 +1183,10 @@ __device__ __forceinline__ void hash_insert(BigLds& S, int16_t* hv, int32_t key,
   }
 }
 
-__device__ __forceinline__ int32_t hash_find(const BigLds& S, const int16_t* hv, int32_t key) {
-  int s = hash_slot(key);
+template <class LDS>
+__device__ __forceinline__ int32_t hash_find(const LDS& S, const int16_t* hv, int32_t key) {
+  constexpr int kHCap = LDS::kHCap;
+  int s = hash_slot<LDS::kHBits>(key);
   for (int k = 0; k < kHCap; ++k) {
     int32_t kk = S.hkey[s];
     if (kk == key) return hv[s];
@@ -1212,9 +1216,11 @@ constexpr int32_t kNoChange = -2;
 // loads overlap. With `ends` given, a slot below `first_new` is only
 // recomputed when the end vertex of its half-edge is in ends[0..ne); other
 // slots get kNoChange. -1 marks an invalid mesh.
-__device__ __forceinline__ void successors(const BigLds& S, int L, int first_new, const int32_t* ends, int ne,
+template <int NT, class LDS, int kPer = LDS::kLCap / NT>
+__device__ __forceinline__ void successors(const LDS& S, int L, int first_new, const int32_t* ends, int ne,
                                            int32_t (&succ)[kPer], int32_t nhe, const int32_t* __restrict__ twin,
                                            const uint8_t* __restrict__ he) {
+  constexpr int kBigThreads = NT;
   // ends are also hashed into S.emask (vertex & 4095): most slots are decided by one bit
   const int tid = threadIdx.x;
   bool act[kPer];
@@ -1263,24 +1269,40 @@ __device__ __forceinline__ void successors(const BigLds& S, int L, int first_new
     if (act[u]) succ[u] = -1;  // walk bound exceeded
 }
 
-template <bool REPAIR>
-__global__ __launch_bounds__(kBigThreads) void k_general_big(
+// Queue a polygon for the next, larger instance (bounded: the queues are sized
+// from the smallest region that can exceed an instance's capacities).
+__device__ __forceinline__ void push_over(int32_t* over, int64_t over_cap, uint32_t* over_count, int32_t i,
+                                          Counters* cnt) {
+  const uint32_t q = atomicAdd(over_count, 1u);
+  if ((int64_t)q < over_cap) over[q] = i;
+  else set_error(cnt, POLYLLA_EINTERNAL);
+}
+
+// One instance of the workgroup region path: NT threads per region, LDS
+// capacities KC/LC/HB. Polygons come from `in` (in_rev: counted from the back
+// of the array, in_cap its length), `in_count` of them, taken by `in_ticket`;
+// regions beyond the capacities go to `over` (count `over_count`).
+template <bool REPAIR, int NT, int KC, int LC, int HB>
+__global__ __launch_bounds__(NT) void k_general_big(
     const int32_t* __restrict__ list, bool from_seeds, int32_t nhe, int64_t nv, const int32_t* __restrict__ twin,
     const int32_t* __restrict__ origin, const uint32_t* __restrict__ lab4, uint8_t* __restrict__ he,
     uint8_t* __restrict__ vtx, int32_t* __restrict__ stage, int64_t stage_cap, int32_t* __restrict__ arena,
-    int64_t arena_cap, PolyState ps, const int32_t* __restrict__ deferred, int64_t deferred_cap,
-    int32_t* __restrict__ huge, Counters* cnt) {
-  __shared__ BigLds S;
+    int64_t arena_cap, PolyState ps, const int32_t* __restrict__ in, bool in_rev, int64_t in_cap,
+    const uint32_t* in_count, uint32_t* in_ticket, int32_t* __restrict__ over, int64_t over_cap,
+    uint32_t* over_count, Counters* cnt) {
+  constexpr int kBigThreads = NT, kKCap = KC, kLCap = LC, kHCap = 1 << HB, kPer = LC / NT;
+  static_assert(LC % NT == 0 && kPer >= 1, "slots per thread");
+  __shared__ BigLds<KC, LC, HB> S;
   int16_t* hv = reinterpret_cast<int16_t*>(S.hval);  // hash values: int16 per hash slot (kHCap of them)
   const int tid = threadIdx.x;
-  const uint32_t nbig = cnt->n_big;
+  const uint32_t nbig = *in_count;
   const int32_t nt = nhe / 3;
   for (;;) {
-    if (tid == 0) S.sc[SC_ITEM] = (int32_t)atomicAdd(&cnt->big_ticket, 1u);
+    if (tid == 0) S.sc[SC_ITEM] = (int32_t)atomicAdd(in_ticket, 1u);
     __syncthreads();
     const uint32_t item = (uint32_t)S.sc[SC_ITEM];
     if (item >= nbig) break;
-    const int32_t i = deferred[deferred_cap - 1 - item];
+    const int32_t i = in_rev ? in[in_cap - 1 - item] : in[item];
     const int32_t li = list[i];
     const int32_t t0 = from_seeds ? li : li / 3;
     // ---- 1. breadth-first search of the region
@@ -1351,14 +1373,14 @@ __global__ __launch_bounds__(kBigThreads) void k_general_big(
       continue;
     }
     if (S.sc[SC_OVER]) {
-      if (tid == 0) huge[atomicAdd(&cnt->n_fallback, 1u)] = i;
+      if (tid == 0) push_over(over, over_cap, over_count, i, cnt);
       __syncthreads();
       continue;
     }
     int L = S.sc[SC_NFH];
     // ---- 2. successors, tips, barrier edges, vertex ids
     int32_t succ[kPer];
-    successors(S, L, 0, nullptr, 0, succ, nhe, twin, he);
+    successors<NT>(S, L, 0, nullptr, 0, succ, nhe, twin, he);
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
       const int k = tid + u * kBigThreads;
@@ -1516,7 +1538,7 @@ __global__ __launch_bounds__(kBigThreads) void k_general_big(
         continue;
       }
       if (S.sc[SC_OVER]) {
-        if (tid == 0) huge[atomicAdd(&cnt->n_fallback, 1u)] = i;
+        if (tid == 0) push_over(over, over_cap, over_count, i, cnt);
         __syncthreads();
         continue;
       }
@@ -1541,7 +1563,7 @@ __global__ __launch_bounds__(kBigThreads) void k_general_big(
       L = S.sc[SC_NFH];
       if (S.sc[SC_NSPLIT]) {
         const int ne = S.sc[SC_NEND];
-        successors(S, L, L0, ne >= 0 ? S.q + 2 * ntip : nullptr, ne, succ, nhe, twin, he);
+        successors<NT>(S, L, L0, ne >= 0 ? S.q + 2 * ntip : nullptr, ne, succ, nhe, twin, he);
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < kPer; ++u) {
@@ -1684,17 +1706,17 @@ __global__ __launch_bounds__(kBigThreads) void k_general_big(
       S.nx[r] = (int16_t)p;
     }
     __syncthreads();
-    // piece lengths in output order and their offsets (block scan; np <= kLCap = 4 * kBigThreads)
-    int32_t lens[4];
+    // piece lengths in output order and their offsets (block scan; np <= kLCap = kPer * kBigThreads)
+    int32_t lens[kPer];
     uint32_t mine = 0;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int r = 4 * tid + u;
+    for (int u = 0; u < kPer; ++u) {
+      const int r = kPer * tid + u;
       lens[u] = r < np ? S.q[pstart[S.nx[r]]] + 1 : 0;
       mine += (uint32_t)lens[u];
     }
     uint2 tot;
-    const uint2 pre = block_exclusive_scan<kBigThreads>(mine, 0u, &tot);
+    const uint2 pre = block_exclusive_scan<NT>(mine, 0u, &tot);
     if (tid == 0) {
       const int32_t total = (int32_t)tot.x;
       const uint32_t sb = atomicAdd(&cnt->stage_top, (uint32_t)total);
@@ -1720,8 +1742,8 @@ __global__ __launch_bounds__(kBigThreads) void k_general_big(
       const int32_t rb = S.sc[SC_RB];
       int32_t run = (int32_t)pre.x;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int r = 4 * tid + u;
+      for (int u = 0; u < kPer; ++u) {
+        const int r = kPer * tid + u;
         if (r >= np) continue;
         const int p = S.nx[r];
         if (np > 1) {
@@ -1959,12 +1981,22 @@ template __global__ void k_general_small<true>(const int32_t*, bool, int32_t, in
 template __global__ void k_general_small<false>(const int32_t*, bool, int32_t, int64_t, const int32_t*,
                                                 const int32_t*, const uint32_t*, uint8_t*, uint8_t*, int32_t*,
                                                 int64_t, int32_t*, int64_t, PolyState, const int32_t*, Counters*);
-template __global__ void k_general_big<true>(const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*,
-                                             const uint32_t*, uint8_t*, uint8_t*, int32_t*, int64_t, int32_t*, int64_t,
-                                             PolyState, const int32_t*, int64_t, int32_t*, Counters*);
-template __global__ void k_general_big<false>(const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*,
-                                              const uint32_t*, uint8_t*, uint8_t*, int32_t*, int64_t, int32_t*, int64_t,
-                                              PolyState, const int32_t*, int64_t, int32_t*, Counters*);
+template __global__ void k_general_big<true, 64, 128, 128, 8>(
+    const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*, const uint32_t*, uint8_t*, uint8_t*,
+    int32_t*, int64_t, int32_t*, int64_t, PolyState, const int32_t*, bool, int64_t, const uint32_t*, uint32_t*,
+    int32_t*, int64_t, uint32_t*, Counters*);
+template __global__ void k_general_big<true, 1024, 4096, 4096, 13>(
+    const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*, const uint32_t*, uint8_t*, uint8_t*,
+    int32_t*, int64_t, int32_t*, int64_t, PolyState, const int32_t*, bool, int64_t, const uint32_t*, uint32_t*,
+    int32_t*, int64_t, uint32_t*, Counters*);
+template __global__ void k_general_big<false, 64, 128, 128, 8>(
+    const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*, const uint32_t*, uint8_t*, uint8_t*,
+    int32_t*, int64_t, int32_t*, int64_t, PolyState, const int32_t*, bool, int64_t, const uint32_t*, uint32_t*,
+    int32_t*, int64_t, uint32_t*, Counters*);
+template __global__ void k_general_big<false, 1024, 4096, 4096, 13>(
+    const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*, const uint32_t*, uint8_t*, uint8_t*,
+    int32_t*, int64_t, int32_t*, int64_t, PolyState, const int32_t*, bool, int64_t, const uint32_t*, uint32_t*,
+    int32_t*, int64_t, uint32_t*, Counters*);
 template __global__ void k_general_huge<true>(const int32_t*, bool, int32_t, int64_t, const int32_t*,
                                               const int32_t*, uint8_t*, uint8_t*, int32_t*, int64_t, int32_t*,
                                               int64_t, PolyState, const int32_t*, Counters*);

@@ -31,11 +31,11 @@ struct Counters {
   uint32_t n_splits;
   uint32_t stage_top;     // bump allocator of the staging buffer (ints)
   uint32_t arena_top;     // bump allocator of the general-path arena (ints)
-  uint32_t n_big;         // polygons handled by the cooperative path
-  uint32_t big_ticket;    // work counter of the cooperative path
-  uint32_t n_fallback;    // cooperative polygons too large for LDS
-  uint32_t walk_ticket;   // (unused slot)
-  uint32_t pad[1];
+  uint32_t n_big;         // polygons longer than the walk cap (one-wave workgroup path)
+  uint32_t big_ticket;    // work counter of the one-wave workgroup path
+  uint32_t n_fallback;    // polygons too large for the 1024-thread workgroup's LDS
+  uint32_t over_ticket;   // work counter of the 1024-thread workgroup path
+  uint32_t n_over;        // polygons too large for the one-wave workgroup's LDS
   uint32_t xcd_ticket[8]; // walk work queues, one per XCD
 };
 

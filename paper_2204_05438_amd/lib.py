@@ -101,7 +101,7 @@ class Tri:
     """A triangulation resident on the device (see polylla.h for the layout)."""
     xy: torch.Tensor       # float64 [V, 2]
     twin: torch.Tensor     # int32 [H]
-    next: torch.Tensor     # int32 [H]
+    next: torch.Tensor | None  # int32 [H]; only polylla_validate reads it
     origin: torch.Tensor   # int32 [H]
 
     @property
@@ -117,22 +117,21 @@ class Tri:
         return self.n_halfedges // 3
 
     def c(self) -> _Tri:
-        for name in ("xy", "twin", "next", "origin"):
-            t = getattr(self, name)
-            if not t.is_contiguous():
+        names = ("xy", "twin", "origin") + (("next",) if self.next is not None else ())
+        for name in names:
+            if not getattr(self, name).is_contiguous():
                 raise ValueError(f"{name} must be contiguous")
-        if self.xy.dtype != torch.float64 or any(
-                getattr(self, n).dtype != torch.int32 for n in ("twin", "next", "origin")):
+        if self.xy.dtype != torch.float64 or any(getattr(self, n).dtype != torch.int32 for n in names[1:]):
             raise TypeError("xy must be float64 and twin/next/origin int32")
         return _Tri(self.n_vertices, self.n_halfedges, self.xy.data_ptr(), self.twin.data_ptr(),
-                    self.next.data_ptr(), self.origin.data_ptr())
+                    None if self.next is None else self.next.data_ptr(), self.origin.data_ptr())
 
     @staticmethod
-    def from_mesh(mesh, device="cuda") -> "Tri":
+    def from_mesh(mesh, device="cuda", with_next: bool = True) -> "Tri":
         """Copy a meshgen.Mesh (numpy arrays) to the device."""
         return Tri(xy=torch.from_numpy(mesh.xy).to(device).contiguous(),
                    twin=torch.from_numpy(mesh.twin).to(device),
-                   next=torch.from_numpy(mesh.next).to(device),
+                   next=torch.from_numpy(mesh.next).to(device) if with_next else None,
                    origin=torch.from_numpy(mesh.origin).to(device))
 
 

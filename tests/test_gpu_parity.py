@@ -224,3 +224,52 @@ def test_batched_equals_per_mesh(ctx, walk_cap):
         assert np.array_equal(got_verts, o["verts"]), k
         assert np.array_equal(start[a:b] - he_off[k], o["start"]), k
         assert np.array_equal(he[he_off[k]:he_off[k + 1]], o["he"]), k
+
+
+def test_batched_graph_replay(ctx):
+    """polylla_mesh_batched captured in a HIP graph: every replay, with eager
+    work and synchronisation between replays, equals the eager call."""
+    _say("batched graph replay, 24 meshes")
+    from meshgen.gen import pack_meshes
+    from paper_2204_05438_amd import lib
+    rng = np.random.default_rng(21)
+    kinds = ["uniform", "cluster", "grid", "lattice"]
+    meshes = [random_mesh(600 + k, int(n), kinds[k % 4])
+              for k, n in enumerate(np.rint(10 ** rng.uniform(1.0, 3.7, 24)))]
+    packed, vtx_off, _ = pack_meshes(meshes)
+    tri = lib.Tri.from_mesh(packed, with_next=False)
+    voff = torch.from_numpy(vtx_off).cuda()
+    ctx.reserve(tri.n_halfedges, tri.n_vertices)
+    labels = lib.Labels.empty(tri)
+    out = lib.Polys.empty(tri)
+    poly_off = torch.empty(len(meshes) + 1, dtype=torch.int64, device="cuda")
+
+    def snapshot():
+        off, verts, start = (x.cpu().numpy().copy() for x in out.trimmed())
+        return off, verts, start, poly_off.cpu().numpy().copy(), labels.he.cpu().numpy().copy()
+
+    ctx.mesh_batched(tri, voff, labels, out, poly_off)
+    ctx.status()
+    ref = snapshot()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        ctx.mesh_batched(tri, voff, labels, out, poly_off)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        ctx.mesh_batched(tri, voff, labels, out, poly_off)
+    for rep in range(3):
+        out.verts.fill_(-1)
+        out.offsets.fill_(-1)
+        poly_off.fill_(-7)
+        labels.he.zero_()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert ctx.status(raise_on_error=False) == lib.OK, rep
+        got = snapshot()
+        for a, b, name in zip(got, ref, ["offsets", "verts", "start", "poly_off", "he"]):
+            assert np.array_equal(a, b), (rep, name)
+    del graph

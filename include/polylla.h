@@ -162,6 +162,17 @@ int polylla_mesh(polylla_ctx *ctx, const polylla_tri *tri, polylla_labels *label
 int polylla_mesh_batched(polylla_ctx *ctx, const polylla_tri *tri, int64_t n_meshes, const int64_t *vtx_off,
                          polylla_labels *labels, polylla_polys *out, int64_t *poly_off, hipStream_t stream);
 
+/* Packing helper for polylla_mesh_batched (not a step of the method): turns
+ * meshes copied one after another with LOCAL indices into the global
+ * indexing of a packed batch, in place on `stream`. For every half-edge h of
+ * mesh m (he_off[m] <= h < he_off[m+1]): origin[h] += vtx_off[m], and
+ * twin[h] += he_off[m] unless it is -1. he_off and vtx_off are device int64
+ * arrays of n_meshes + 1 increasing entries (he_off[n_meshes] = half-edges in
+ * total, each mesh a multiple of 3). Returns EINVAL on null or negative
+ * arguments; the offsets themselves are trusted. */
+int polylla_rebase(int32_t *twin, int32_t *origin, int64_t n_meshes, const int64_t *he_off,
+                   const int64_t *vtx_off, hipStream_t stream);
+
 /* Full input check on the device (layout of next, index ranges, twin
  * involution and endpoints). Waits for the stream; returns the first error. */
 int polylla_validate(polylla_ctx *ctx, const polylla_tri *tri, hipStream_t stream);

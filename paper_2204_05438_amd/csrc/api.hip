@@ -35,6 +35,7 @@ __global__ void k_general_huge(const int32_t*, bool, int32_t, int64_t, const int
 __global__ void k_scan_emit(PolyState, uint64_t*, const int32_t*, const int32_t*, int32_t*, int32_t*, int32_t*,
                             int64_t*, int64_t, int64_t, Counters*);
 __global__ void k_validate(int64_t, int64_t, const int32_t*, const int32_t*, const int32_t*, Counters*);
+__global__ void k_rebase(int32_t*, int32_t*, int64_t, const int64_t*, const int64_t*);
 __global__ void k_batch_offsets(int64_t, const int64_t*, const int32_t*, const int32_t*, const int64_t*, int64_t,
                                 int64_t, int64_t*);
 
@@ -450,6 +451,14 @@ int polylla_mesh_batched(polylla_ctx* c, const polylla_tri* t, int64_t n_meshes,
     hipLaunchKernelGGL(k_batch_offsets, dim3(grid_for(n_meshes + 1, 256, 4096)), dim3(256), 0, s, n_meshes,
                        vtx_off, out->offsets, out->verts, out->counts, out->cap_polys, out->cap_verts, poly_off);
   }
+  return launched();
+}
+
+int polylla_rebase(int32_t* twin, int32_t* origin, int64_t n_meshes, const int64_t* he_off, const int64_t* vtx_off,
+                   hipStream_t s) {
+  if (n_meshes < 0 || (n_meshes > 0 && (!twin || !origin || !he_off || !vtx_off))) return POLYLLA_EINVAL;
+  if (n_meshes == 0) return POLYLLA_OK;
+  hipLaunchKernelGGL(k_rebase, dim3(4096), dim3(256), 0, s, twin, origin, n_meshes, he_off, vtx_off);
   return launched();
 }
 

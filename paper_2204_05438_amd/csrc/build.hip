@@ -1936,6 +1936,26 @@ __global__ __launch_bounds__(256) void k_scan_emit(PolyState ps, uint64_t* statu
   }
 }
 
+// Packing helper: local indices of meshes copied one after another become
+// the global indices of the packed batch (mesh of a half-edge by binary
+// search over he_off).
+__global__ __launch_bounds__(256) void k_rebase(int32_t* __restrict__ twin, int32_t* __restrict__ origin,
+                                                int64_t n_meshes, const int64_t* __restrict__ he_off,
+                                                const int64_t* __restrict__ vtx_off) {
+  const int64_t H = he_off[n_meshes];
+  for (int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; h < H; h += (int64_t)gridDim.x * blockDim.x) {
+    int64_t lo = 0, hi = n_meshes;  // last mesh with he_off <= h
+    while (hi - lo > 1) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (he_off[mid] <= h) lo = mid;
+      else hi = mid;
+    }
+    origin[h] += (int32_t)vtx_off[lo];
+    const int32_t tw = twin[h];
+    if (tw != -1) twin[h] = tw + (int32_t)he_off[lo];
+  }
+}
+
 // First output polygon of every mesh of a batch: polygons come in mesh order
 // and each starts at its smallest vertex, which lies in its mesh's vertex
 // range, so the first polygon of mesh m is the first polygon whose first

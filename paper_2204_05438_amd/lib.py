@@ -67,6 +67,7 @@ def load() -> ctypes.CDLL:
         lib.polylla_validate.argtypes = [P, ctypes.POINTER(_Tri), P]
         lib.polylla_mesh_batched.argtypes = [P, ctypes.POINTER(_Tri), ctypes.c_int64, P, ctypes.POINTER(_Labels),
                                              ctypes.POINTER(_Polys), P, P]
+        lib.polylla_rebase.argtypes = [P, P, ctypes.c_int64, P, P, P]
         lib.polylla_status.argtypes = [P, P]
         lib.polylla_stats.argtypes = [P, ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
         lib.polylla_set_param.argtypes = [P, ctypes.c_int, ctypes.c_int64]
@@ -76,8 +77,8 @@ def load() -> ctypes.CDLL:
         lib.polylla_strerror.argtypes = [ctypes.c_int]
         lib.polylla_strerror.restype = ctypes.c_char_p
         for f in ("polylla_ctx_create", "polylla_reserve", "polylla_label", "polylla_build", "polylla_repair",
-                  "polylla_mesh", "polylla_mesh_batched", "polylla_validate", "polylla_status", "polylla_stats", "polylla_set_param", "polylla_profile",
-                  "polylla_profile_read"):
+                  "polylla_mesh", "polylla_mesh_batched", "polylla_rebase", "polylla_validate", "polylla_status",
+                  "polylla_stats", "polylla_set_param", "polylla_profile", "polylla_profile_read"):
             getattr(lib, f).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -180,6 +181,19 @@ class Polys:
         F, S = (int(x) for x in self.counts.tolist())
         return (self.offsets[:F + 1], self.verts[:S],
                 None if self.start is None else self.start[:F])
+
+
+def rebase(twin: torch.Tensor, origin: torch.Tensor, he_off: torch.Tensor, vtx_off: torch.Tensor):
+    """polylla_rebase on torch's current stream: meshes copied one after
+    another with local indices get the global indices of the packed batch."""
+    for t in (he_off, vtx_off):
+        if t.dtype != torch.int64 or not t.is_cuda:
+            raise TypeError("he_off and vtx_off must be int64 device tensors")
+    for t in (twin, origin):
+        if t.dtype != torch.int32 or not t.is_cuda or not t.is_contiguous():
+            raise TypeError("twin and origin must be contiguous int32 device tensors")
+    _check(load().polylla_rebase(_ptr(twin), _ptr(origin), int(he_off.shape[0]) - 1, _ptr(he_off), _ptr(vtx_off),
+                                 ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)), "polylla_rebase")
 
 
 class Context:

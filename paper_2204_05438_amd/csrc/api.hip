@@ -23,7 +23,10 @@ __global__ void k_walk(const int32_t*, int32_t, const int32_t*, const int32_t*, 
 template <bool REPAIR>
 __global__ void k_general_small(const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*,
                                 const uint32_t*, uint8_t*, uint8_t*, int32_t*, int64_t, int32_t*, int64_t, PolyState,
-                                const int32_t*, Counters*);
+                                const int32_t*, const uint32_t*, Counters*);
+template <bool REPAIR>
+__global__ void k_tip(int32_t, int64_t, const int32_t*, const int32_t*, uint8_t*, uint8_t*, int32_t*, int64_t,
+                      int32_t*, int64_t, PolyState, const int32_t*, int32_t*, int64_t, Counters*);
 template <bool REPAIR, int NT, int KC, int LC, int HB>
 __global__ void k_general_big(const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*, const uint32_t*,
                               uint8_t*, uint8_t*, int32_t*, int64_t, int32_t*, int64_t, PolyState, const int32_t*,
@@ -55,6 +58,8 @@ struct polylla_ctx {
   int32_t* over = nullptr;  // regions beyond the one-wave workgroup's LDS
   int32_t* huge = nullptr;  // regions beyond the 1024-thread workgroup's LDS
   int64_t over_cap = 0, huge_cap = 0;
+  int32_t* rest = nullptr;  // short polygons the tip path leaves to the region path
+  int64_t rest_cap = 0;
   int32_t* poly_arrays = nullptr;  // per-polygon records: 4 ints + 1 int per polygon (PolyState)
   int32_t* stage = nullptr;
   int64_t stage_cap = 0;
@@ -93,12 +98,12 @@ constexpr int64_t kStageChunkHost = 4096; // staging ints a walk wave reserves a
 
 enum KernelId {
   KR_RESET, KR_LONGEST, KR_LABEL, KR_COMPACT, KR_PACK, KR_WALK, KR_GENERAL, KR_BIG, KR_HUGE, KR_SCAN, KR_VALIDATE,
-  KR_BATCH, KR_BIGW, KR_N
+  KR_BATCH, KR_BIGW, KR_TIP, KR_N
 };
 const char* kKernelNames[KR_N] = {"k_reset",         "k_longest",       "k_label",          "k_compact_seeds",
                                   "k_pack_labels",   "k_walk",          "k_general_small",  "k_general_big",
                                   "k_general_huge",  "k_scan_emit",     "k_validate",       "k_batch_offsets",
-                                  "k_general_big_wg"};
+                                  "k_general_big_wg", "k_tip"};
 
 // Event pair around one kernel launch when profiling is on.
 struct Prof {
@@ -143,6 +148,7 @@ void free_scratch(polylla_ctx* c) {
   dfree(&c->deferred);
   dfree(&c->huge);
   dfree(&c->over);
+  dfree(&c->rest);
   dfree(&c->poly_arrays);
   dfree(&c->stage);
   dfree(&c->arena);
@@ -171,6 +177,7 @@ int ensure(polylla_ctx* c, int64_t nt, int64_t nv) {
   c->n_status = 2 * ntiles;
   if ((rc = dalloc(&c->lg, T)) || (rc = dalloc(&c->lab4, T)) || (rc = dalloc(&c->seeds, T)) || (rc = dalloc(&c->deferred, T)) || (rc = dalloc(&c->huge, c->huge_cap = T / 1024 + 64)) ||
       (rc = dalloc(&c->over, c->over_cap = T / 32 + 64)) ||
+      (rc = dalloc(&c->rest, c->rest_cap = T / 3 + 64)) ||
       (rc = dalloc(&c->poly_arrays, 5 * T)) || (rc = dalloc(&c->stage, c->stage_cap)) ||
       (rc = dalloc(&c->arena, c->arena_cap)) || (rc = dalloc(&c->status, c->n_status)) ||
       (rc = dalloc(&c->he_s, 3 * T)) || (rc = dalloc(&c->tri_s, T)) || (rc = dalloc(&c->vtx_s, V))) {
@@ -291,16 +298,28 @@ int run_build(polylla_ctx* c, const polylla_tri* t, const int32_t* list, bool fr
   }
   if (hipEventRecord(c->join, c->side) != hipSuccess) return POLYLLA_EHIP;
   {
+    Prof p(c, s, KR_TIP);
+    const int gt = 2048;  // one lane per short polygon with a repeat, grid-stride
+    if (repair)
+      hipLaunchKernelGGL(k_tip<true>, dim3(gt), dim3(64), 0, s, nhe, t->n_vertices, t->twin, t->origin, he, vtx,
+                         c->stage, c->stage_cap, c->arena, c->arena_cap, ps, c->deferred, c->rest, c->rest_cap,
+                         c->cnt);
+    else
+      hipLaunchKernelGGL(k_tip<false>, dim3(gt), dim3(64), 0, s, nhe, t->n_vertices, t->twin, t->origin, he, vtx,
+                         c->stage, c->stage_cap, c->arena, c->arena_cap, ps, c->deferred, c->rest, c->rest_cap,
+                         c->cnt);
+  }
+  {
     Prof p(c, s, KR_GENERAL);
     const int gg = 2048;
     if (repair)
       hipLaunchKernelGGL(k_general_small<true>, dim3(gg), dim3(64), 0, s, list, from_seeds, nhe, t->n_vertices,
                          t->twin, t->origin, c->lab4, he, vtx, c->stage, c->stage_cap, c->arena, c->arena_cap, ps,
-                         c->deferred, c->cnt);
+                         c->rest, &c->cnt->n_gen, c->cnt);
     else
       hipLaunchKernelGGL(k_general_small<false>, dim3(gg), dim3(64), 0, s, list, from_seeds, nhe, t->n_vertices,
                          t->twin, t->origin, c->lab4, he, vtx, c->stage, c->stage_cap, c->arena, c->arena_cap, ps,
-                         c->deferred, c->cnt);
+                         c->rest, &c->cnt->n_gen, c->cnt);
   }
   if (hipStreamWaitEvent(s, c->join, 0) != hipSuccess) return POLYLLA_EHIP;
   {

@@ -134,7 +134,8 @@ __global__ __launch_bounds__(256) void k_walk(const int32_t* __restrict__ list, 
                                               const uint32_t* __restrict__ lab4, int32_t* __restrict__ stage,
                                               int64_t stage_cap, PolyState ps, int32_t* __restrict__ deferred,
                                               int64_t deferred_cap, int walk_cap, Counters* cnt) {
-  __shared__ int32_t buf[kWalkCap][256];
+  __shared__ int32_t buf[kWalkCap][256];   // vertex ids of the cycle, per lane
+  __shared__ int32_t hbuf[kWalkCap][256];  // its half-edges (staged for polygons with a repeat)
   walk_cap = walk_cap < 1 ? 1 : (walk_cap > kWalkCap ? kWalkCap : walk_cap);
   const int lane = threadIdx.x & 63;
   const int32_t R = (int32_t)cnt->n_seeds;
@@ -275,6 +276,8 @@ __global__ __launch_bounds__(256) void k_walk(const int32_t* __restrict__ list, 
             continue;
           }
           const int32_t v = r.org(ci);
+          buf[L][threadIdx.x] = v;
+          hbuf[L][threadIdx.x] = c;
           if (!complex) {
             const uint64_t bit = 1ull << (v & 63);
             bool rep = false;
@@ -282,7 +285,6 @@ __global__ __launch_bounds__(256) void k_walk(const int32_t* __restrict__ list, 
               for (int j = 0; j < L; ++j) rep |= (buf[j][threadIdx.x] == v);
             complex = rep;
             sig |= bit;
-            buf[L][threadIdx.x] = v;
             if (v < minv) {
               minv = v;
               minhe = c;
@@ -312,8 +314,9 @@ __global__ __launch_bounds__(256) void k_walk(const int32_t* __restrict__ list, 
     const bool fin = idx >= 0 && done;
     if (fin && result == kSimple && complex) result = kSmall;
     const bool fin_simple = fin && result == kSimple;
-    if (__ballot(fin_simple)) {
-      const uint32_t need = fin_simple ? (uint32_t)L : 0u;
+    const bool fin_small = fin && result == kSmall;  // its vertices and half-edges are staged for the tip path
+    if (__ballot(fin_simple || fin_small)) {
+      const uint32_t need = fin_simple ? (uint32_t)L : (fin_small ? 2u * (uint32_t)L : 0u);
       uint32_t incl = need;
 #pragma unroll
       for (int o = 1; o < 64; o <<= 1) {
@@ -328,14 +331,19 @@ __global__ __launch_bounds__(256) void k_walk(const int32_t* __restrict__ list, 
         sbase = __shfl(nb, 0, 64);
         sleft = want_ints;
       }
-      if (fin_simple) {
+      if (fin_simple || fin_small) {
         const int64_t off = sbase + incl - need;
-        if (off + L > stage_cap) {
+        if (off + need > stage_cap) {
           set_error(cnt, POLYLLA_ENOMEM);
           ps.clear(idx);
-        } else {
+        } else if (fin_simple) {
           for (int k = 0; k < L; ++k) stage[off + k] = buf[k][threadIdx.x];
           ps.set(idx, L, 1 | (minpos << kRotShift), minhe, (int32_t)off);
+        } else {
+          // no output yet (pieces 0): cycle vertices, then its half-edges
+          for (int k = 0; k < L; ++k) stage[off + k] = buf[k][threadIdx.x];
+          for (int k = 0; k < L; ++k) stage[off + L + k] = hbuf[k][threadIdx.x];
+          ps.set(idx, L, 0, -1, (int32_t)off);
         }
       }
       sbase += tot;
@@ -345,7 +353,6 @@ __global__ __launch_bounds__(256) void k_walk(const int32_t* __restrict__ list, 
       if (result == kSmall) {
         const uint32_t q = atomicAdd(&cnt->n_deferred, 1u);
         deferred[q] = idx;
-        ps.set_len(idx, L);  // cycle length for the per-lane general path
       } else if (result == kLarge) {
         const uint32_t q = atomicAdd(&cnt->n_big, 1u);
         deferred[deferred_cap - 1 - q] = idx;
@@ -1056,6 +1063,174 @@ __device__ void region_core(int32_t i, const Region<A>& R, int k, int start, A c
   ps.prec[i] = (int32_t)r0;
 }
 
+// ---------------------------------------------------------------------------
+// Tip path: the common case of a short polygon with a repeated vertex, one
+// barrier-edge tip, repaired from its cycle alone.
+//
+// The walk staged the cycle (vertices v and half-edges h, v[k] = origin of
+// h[k]). A tip is a position m with v[m-1] = v[m+1] (the next frontier
+// half-edge is the twin: the only edge joining two vertices). With exactly one
+// tip, Algorithm 4 opens the middle internal edge e of its fan (found by
+// turning about v[m] through the mesh, a few dependent loads), from v[m] to
+// x. If x occurs once on the cycle, at q, the two pieces are the cycle from m
+// to q closed by twin(e) and the cycle from q to m closed by e: their
+// vertices are contiguous stretches of the staged cycle. Barrier edges are
+// the pairs (a, b), (b, a) of consecutive vertices both on the cycle. Every
+// other polygon (several tips, x repeated, a cycle not staged) is queued for
+// the region path.
+// vertex k of a piece: the stretch of `len` cycle positions from `a`
+__device__ __forceinline__ int32_t piece_vertex(const LdsCol& v, int L, int a, int k) {
+  const int p = a + k;
+  return v[p >= L ? p - L : p];
+}
+
+// start (0..len-1) of the lexicographically smallest rotation of a piece
+__device__ int piece_rotation(const LdsCol& v, int L, int a, int len) {
+  int best = 0;
+  int32_t mv = piece_vertex(v, L, a, 0);
+  for (int k = 1; k < len; ++k) {
+    const int32_t x = piece_vertex(v, L, a, k);
+    if (x < mv) {
+      mv = x;
+      best = k;
+    }
+  }
+  for (int k = best + 1; k < len; ++k) {
+    if (piece_vertex(v, L, a, k) != mv) continue;
+    for (int z = 1; z < len; ++z) {
+      const int32_t p = piece_vertex(v, L, a, (k + z) % len), q = piece_vertex(v, L, a, (best + z) % len);
+      if (p != q) {
+        if (p < q) best = k;
+        break;
+      }
+    }
+  }
+  return best;
+}
+
+template <bool REPAIR>
+__global__ __launch_bounds__(64) void k_tip(int32_t nhe, int64_t nv, const int32_t* __restrict__ twin,
+                                            const int32_t* __restrict__ origin, uint8_t* __restrict__ he,
+                                            uint8_t* __restrict__ vtx, int32_t* __restrict__ stage,
+                                            int64_t stage_cap, int32_t* __restrict__ arena, int64_t arena_cap,
+                                            PolyState ps, const int32_t* __restrict__ deferred,
+                                            int32_t* __restrict__ rest, int64_t rest_cap, Counters* cnt) {
+  __shared__ int32_t s_v[kWalkCap * 64];
+  __shared__ int32_t s_h[kWalkCap * 64];
+  const LdsCol v{s_v + threadIdx.x}, h{s_h + threadIdx.x};
+  const uint32_t nd = cnt->n_deferred;
+  for (uint32_t j = blockIdx.x * 64 + threadIdx.x; j < nd; j += gridDim.x * 64) {
+    const int32_t i = deferred[j];
+    const int4 rc = ps.rec[i];
+    const int L = rc.x;
+    bool fast = REPAIR && rc.y == 0 && L >= 4 && L <= kWalkCap;
+    int m = -1;
+    if (fast) {
+      // every load of the staged cycle issued before the first LDS store
+      int32_t rv[kWalkCap], rh[kWalkCap];
+#pragma unroll
+      for (int k = 0; k < kWalkCap; ++k) {
+        rv[k] = k < L ? stage[rc.w + k] : 0;
+        rh[k] = k < L ? stage[rc.w + L + k] : 0;
+      }
+#pragma unroll
+      for (int k = 0; k < kWalkCap; ++k) {
+        v[k] = rv[k];
+        h[k] = rh[k];
+      }
+      int ntip = 0;
+      for (int k = 0; k < L; ++k) {
+        const int32_t vp = v[k == 0 ? L - 1 : k - 1], vn = v[k + 1 == L ? 0 : k + 1];
+        if (vp == vn) {
+          ++ntip;
+          m = k;
+        }
+      }
+      fast = ntip == 1;
+    }
+    int32_t e = -1, te = -1, x = -1;
+    int q = -1;
+    if (fast) {
+      // middle internal edge c_{floor(d/2)} turning clockwise about v[m] from c0 = h[m]
+      const int32_t c0 = h[m];
+      int32_t d = 0, c = c0;
+      do {
+        const int32_t tw = twin[c];
+        if ((uint32_t)tw >= (uint32_t)nhe) {
+          d = -1;
+          break;
+        }
+        c = he_next(tw);
+        ++d;
+      } while (c != c0 && d <= nhe);
+      fast = d >= 2 && c == c0;
+      if (fast) {
+        e = c0;
+        for (int32_t k = 0; k < d / 2; ++k) e = he_next(twin[e]);
+        te = twin[e];
+        x = origin[he_next(e)];
+        int occ = 0;
+        for (int k = 0; k < L; ++k)
+          if (v[k] == x) {
+            ++occ;
+            q = k;
+          }
+        fast = occ == 1 && q != m && (uint32_t)te < (uint32_t)nhe;
+      }
+    }
+    if (!fast) {
+      const uint32_t r = atomicAdd(&cnt->n_gen, 1u);
+      if ((int64_t)r < rest_cap) rest[r] = i;
+      else set_error(cnt, POLYLLA_EINTERNAL);
+      continue;
+    }
+    // labels: barrier edges, the tip, the opened edge. The barrier edges of a
+    // region form a forest inside it whose leaves are tips, so with one tip
+    // they are the path v[m-k-1] = v[m+k+1] read outwards from the tip.
+    for (int k = 0; 2 * k + 2 < L; ++k) {
+      const int lo = (m - k - 1 + L) % L, hi = (m + k + 1) % L;
+      if (v[lo] != v[hi]) break;
+      he[h[lo]] |= kBarrier;             // v[lo] -> v[lo + 1]
+      he[h[(m + k) % L]] |= kBarrier;    // v[m + k] -> v[hi]
+    }
+    const int32_t vt = v[m];
+    if ((uint64_t)(uint32_t)vt < (uint64_t)nv) vtx[vt] |= kTip;
+    he[e] |= kFrontier | kRepaired;
+    he[te] |= kFrontier | kRepaired;
+    atomicAdd(&cnt->n_tips, 1u);
+    atomicAdd(&cnt->n_splits, 1u);
+    // pieces: A = positions m..q (x last, leaving by te), B = q..m (v[m] last, leaving by e)
+    const int lenA = (q - m + L) % L + 1, lenB = (m - q + L) % L + 1;
+    const int ra = piece_rotation(v, L, m, lenA), rb = piece_rotation(v, L, q, lenB);
+    const int32_t a0 = piece_vertex(v, L, m, ra), a1 = piece_vertex(v, L, m, (ra + 1) % lenA);
+    const int32_t b0 = piece_vertex(v, L, q, rb), b1 = piece_vertex(v, L, q, (rb + 1) % lenB);
+    const int32_t sa = ra == lenA - 1 ? te : h[(m + ra) % L];
+    const int32_t sb = rb == lenB - 1 ? e : h[(q + rb) % L];
+    const bool a_first = a0 < b0 || (a0 == b0 && a1 < b1);
+    const uint32_t off = atomicAdd(&cnt->stage_top, (uint32_t)(L + 2));
+    const uint32_t r0 = atomicAdd(&cnt->arena_top, 8u);
+    if ((int64_t)off + L + 2 > stage_cap || (int64_t)r0 + 8 > arena_cap) {
+      set_error(cnt, POLYLLA_ENOMEM);
+      ps.clear(i);
+      continue;
+    }
+    const int oa = a_first ? 0 : lenB, ob = a_first ? lenA : 0;
+    for (int k = 0; k < lenA; ++k) stage[off + oa + k] = piece_vertex(v, L, m, (ra + k) % lenA);
+    for (int k = 0; k < lenB; ++k) stage[off + ob + k] = piece_vertex(v, L, q, (rb + k) % lenB);
+    const int pa = a_first ? 0 : 1, pb = 1 - pa;
+    arena[r0 + 4 * pa] = a0;
+    arena[r0 + 4 * pa + 1] = a1;
+    arena[r0 + 4 * pa + 2] = sa;
+    arena[r0 + 4 * pa + 3] = lenA;
+    arena[r0 + 4 * pb] = b0;
+    arena[r0 + 4 * pb + 1] = b1;
+    arena[r0 + 4 * pb + 2] = sb;
+    arena[r0 + 4 * pb + 3] = lenB;
+    ps.set(i, L + 2, 2, -1, (int32_t)off);
+    ps.prec[i] = (int32_t)r0;
+  }
+}
+
 // Short polygons with a tip or a repeated vertex: one lane each, the region
 // in LDS columns interleaved over the 64 lanes of the block. Regions larger
 // than kSmallK triangles (only on invalid input: the walk queues cycles of at
@@ -1068,7 +1243,8 @@ __global__ __launch_bounds__(64) void k_general_small(const int32_t* __restrict_
                                                       uint8_t* __restrict__ vtx, int32_t* __restrict__ stage,
                                                       int64_t stage_cap, int32_t* __restrict__ arena,
                                                       int64_t arena_cap, PolyState ps,
-                                                      const int32_t* __restrict__ deferred, Counters* cnt) {
+                                                      const int32_t* __restrict__ deferred,
+                                                      const uint32_t* n_in, Counters* cnt) {
   __shared__ int32_t s_tri[kSmallK * 64];
   __shared__ int32_t s_lnk[3 * kSmallK * 64];
   __shared__ int32_t s_org[3 * kSmallK * 64];
@@ -1077,7 +1253,7 @@ __global__ __launch_bounds__(64) void k_general_small(const int32_t* __restrict_
   const int lane = threadIdx.x;
   const Region<LdsCol> R{LdsCol{s_tri + lane}, LdsCol{s_lnk + lane}, LdsCol{s_org + lane}};
   const int32_t nt = nhe / 3;
-  const uint32_t nd = cnt->n_deferred;
+  const uint32_t nd = *n_in;
   for (uint32_t j = blockIdx.x * 64 + threadIdx.x; j < nd; j += gridDim.x * 64) {
     const int32_t i = deferred[j];
     const int32_t item = list[i];
@@ -1997,10 +2173,18 @@ template __global__ void k_walk<false>(const int32_t*, int32_t, const int32_t*, 
                                        int32_t*, int64_t, PolyState, int32_t*, int64_t, int, Counters*);
 template __global__ void k_general_small<true>(const int32_t*, bool, int32_t, int64_t, const int32_t*,
                                                const int32_t*, const uint32_t*, uint8_t*, uint8_t*, int32_t*,
-                                               int64_t, int32_t*, int64_t, PolyState, const int32_t*, Counters*);
+                                               int64_t, int32_t*, int64_t, PolyState, const int32_t*,
+                                               const uint32_t*, Counters*);
 template __global__ void k_general_small<false>(const int32_t*, bool, int32_t, int64_t, const int32_t*,
                                                 const int32_t*, const uint32_t*, uint8_t*, uint8_t*, int32_t*,
-                                                int64_t, int32_t*, int64_t, PolyState, const int32_t*, Counters*);
+                                                int64_t, int32_t*, int64_t, PolyState, const int32_t*,
+                                                const uint32_t*, Counters*);
+template __global__ void k_tip<true>(int32_t, int64_t, const int32_t*, const int32_t*, uint8_t*, uint8_t*, int32_t*,
+                                     int64_t, int32_t*, int64_t, PolyState, const int32_t*, int32_t*, int64_t,
+                                     Counters*);
+template __global__ void k_tip<false>(int32_t, int64_t, const int32_t*, const int32_t*, uint8_t*, uint8_t*, int32_t*,
+                                      int64_t, int32_t*, int64_t, PolyState, const int32_t*, int32_t*, int64_t,
+                                      Counters*);
 template __global__ void k_general_big<true, 64, 128, 128, 8>(
     const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*, const uint32_t*, uint8_t*, uint8_t*,
     int32_t*, int64_t, int32_t*, int64_t, PolyState, const int32_t*, bool, int64_t, const uint32_t*, uint32_t*,

@@ -36,6 +36,7 @@ struct Counters {
   uint32_t n_fallback;    // polygons too large for the 1024-thread workgroup's LDS
   uint32_t over_ticket;   // work counter of the 1024-thread workgroup path
   uint32_t n_over;        // polygons too large for the one-wave workgroup's LDS
+  uint32_t n_gen;         // short polygons the tip path leaves to the region path
   uint32_t xcd_ticket[8]; // walk work queues, one per XCD
 };
 

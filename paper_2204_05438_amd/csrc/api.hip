@@ -14,8 +14,9 @@ __global__ void k_reset(Counters*, uint64_t*, int64_t, const int64_t*);
 __global__ void k_longest(int64_t, int64_t, const double*, const int32_t*, const int32_t*, uint8_t*, uint8_t*,
                           Counters*);
 template <bool COMPUTE>
-__global__ void k_label(int64_t, const int32_t*, const uint8_t*, uint8_t*, uint8_t*, int32_t*, uint32_t*,
-                        uint64_t*, Counters*, bool);
+__global__ void k_label(int64_t, const int32_t*, const uint8_t*, uint8_t*, uint8_t*, uint32_t*, uint32_t*, uint32_t*,
+                        Counters*, bool);
+__global__ void k_seeds(int64_t, const uint8_t*, const uint32_t*, const uint32_t*, int32_t*, Counters*);
 __global__ void k_pack_labels(int64_t, const uint8_t*, uint32_t*);
 template <bool FROM_SEEDS>
 __global__ void k_walk(const int32_t*, int32_t, const int32_t*, const int32_t*, const uint32_t*, int32_t*,
@@ -98,12 +99,12 @@ constexpr int64_t kStageChunkHost = 4096; // staging ints a walk wave reserves a
 
 enum KernelId {
   KR_RESET, KR_LONGEST, KR_LABEL, KR_COMPACT, KR_PACK, KR_WALK, KR_GENERAL, KR_BIG, KR_HUGE, KR_SCAN, KR_VALIDATE,
-  KR_BATCH, KR_BIGW, KR_TIP, KR_N
+  KR_BATCH, KR_BIGW, KR_TIP, KR_SEEDS, KR_N
 };
 const char* kKernelNames[KR_N] = {"k_reset",         "k_longest",       "k_label",          "k_compact_seeds",
                                   "k_pack_labels",   "k_walk",          "k_general_small",  "k_general_big",
                                   "k_general_huge",  "k_scan_emit",     "k_validate",       "k_batch_offsets",
-                                  "k_general_big_wg", "k_tip"};
+                                  "k_general_big_wg", "k_tip",           "k_seeds"};
 
 // Event pair around one kernel launch when profiling is on.
 struct Prof {
@@ -226,6 +227,18 @@ void reset(polylla_ctx* c, hipStream_t s, const int64_t* n_from) {
                      c->n_status, n_from);
 }
 
+// Seed counts per label tile (first ntiles words of the status array) and
+// their sums per group of 64 tiles (the next ntiles / 64 + 1 words, zeroed by
+// k_reset).
+uint32_t* tile_counts(polylla_ctx* c) { return reinterpret_cast<uint32_t*>(c->status); }
+uint32_t* tile_groups(polylla_ctx* c, int64_t T) { return tile_counts(c) + (T + kTile - 1) / kTile; }
+
+void launch_seeds(polylla_ctx* c, int64_t T, const uint8_t* tri, hipStream_t s) {
+  Prof p(c, s, KR_SEEDS);
+  hipLaunchKernelGGL(k_seeds, dim3((T + kTile - 1) / kTile), dim3(256), 0, s, T, tri, tile_counts(c),
+                     tile_groups(c, T), c->seeds, c->cnt);
+}
+
 int run_label(polylla_ctx* c, const polylla_tri* t, uint8_t* he, uint8_t* tri, uint8_t* vtx, hipStream_t s) {
   const int64_t T = t->n_halfedges / 3;
   {
@@ -238,8 +251,9 @@ int run_label(polylla_ctx* c, const polylla_tri* t, uint8_t* he, uint8_t* tri, u
     // 16-byte loads of twin and 4-byte label stores need aligned arrays
     const bool vec = ((uintptr_t)t->twin % 16 == 0) && ((uintptr_t)he % 4 == 0) && ((uintptr_t)tri % 4 == 0);
     hipLaunchKernelGGL(k_label<true>, dim3((T + kTile - 1) / kTile), dim3(256), 0, s, T, t->twin, c->lg, he, tri,
-                       c->seeds, c->lab4, c->status, c->cnt, vec);
+                       c->lab4, tile_counts(c), tile_groups(c, T), c->cnt, vec);
   }
+  if (T > 0) launch_seeds(c, T, tri, s);
   return launched();
 }
 
@@ -417,8 +431,9 @@ int polylla_build(polylla_ctx* c, const polylla_tri* t, polylla_labels* l, polyl
   if (T > 0) {
     Prof p(c, s, KR_COMPACT);
     hipLaunchKernelGGL(k_label<false>, dim3((T + kTile - 1) / kTile), dim3(256), 0, s, T, t->twin, c->lg, l->he,
-                       l->tri, c->seeds, c->lab4, c->status, c->cnt, false);
+                       l->tri, c->lab4, tile_counts(c), tile_groups(c, T), c->cnt, false);
   }
+  if (T > 0) launch_seeds(c, T, l->tri, s);
   if (T > 0) {
     Prof p(c, s, KR_PACK);
     hipLaunchKernelGGL(k_pack_labels, dim3(grid_for(T, 256, 1 << 16)), dim3(256), 0, s, T, l->he, c->lab4);

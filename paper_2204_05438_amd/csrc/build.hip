@@ -1976,7 +1976,7 @@ __global__ __launch_bounds__(64) void k_general_huge(const int32_t* __restrict__
 constexpr int kScanItems = 8;
 constexpr int kScanTile = 256 * kScanItems;
 constexpr int kScanLog = 11;            // log2(kScanTile)
-constexpr int kScanOut = 2 * kScanTile;  // output polygons of a tile staged in LDS
+constexpr int kScanOut = kScanTile + 512;  // output polygons of a tile staged in LDS (else direct stores)
 static_assert((1 << kScanLog) == kScanTile, "binary search depth");
 
 __global__ __launch_bounds__(256) void k_scan_emit(PolyState ps, uint64_t* status, const int32_t* __restrict__ stage,
@@ -2077,27 +2077,27 @@ __global__ __launch_bounds__(256) void k_scan_emit(PolyState ps, uint64_t* statu
     }
   }
   // the tile's vertex range, coalesced: every slot finds its polygon by
-  // binary search in LDS, four independent searches in lockstep per thread
+  // binary search in LDS, eight independent searches in lockstep per thread
   const int32_t nv_tile = (int32_t)total.y;
-  for (int32_t k0 = threadIdx.x; k0 < nv_tile; k0 += 4 * 256) {
-    int lo[4], hi[4];
+  for (int32_t k0 = threadIdx.x; k0 < nv_tile; k0 += 8 * 256) {
+    int lo[8], hi[8];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < 8; ++u) {
       lo[u] = 0;
       hi[u] = kScanTile;
     }
 #pragma unroll
     for (int step = 0; step < kScanLog; ++step) {  // last polygon with s_voff <= k
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < 8; ++u) {
         const int mid = (lo[u] + hi[u]) >> 1;
         if (s_voff[mid] <= k0 + 256 * u) lo[u] = mid;
         else hi[u] = mid;
       }
     }
-    int32_t v[4];
+    int32_t v[8];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < 8; ++u) {
       const int32_t k = k0 + 256 * u;
       if (k < nv_tile) {
         const int32_t len = s_voff[lo[u] + 1] - s_voff[lo[u]];
@@ -2107,7 +2107,7 @@ __global__ __launch_bounds__(256) void k_scan_emit(PolyState ps, uint64_t* statu
       }
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < 8; ++u)
       if (k0 + 256 * u < nv_tile) verts[tile_v0 + k0 + 256 * u] = v[u];
   }
 }

@@ -5,11 +5,15 @@
 //             squared edge lengths in binary64 (each product and sum rounded,
 //             no fused multiply-add) and writes the local index of the longest
 //             edge (the paper's Max array) as one byte per triangle.
-// k_label   : one tile of 1024 triangles per block, four consecutive triangles
-//             per thread so that twin, Max and the label bytes move as 16-byte
-//             and 4-byte vectors. Writes the half-edge labels and the SEED flag
-//             and appends the seed triangles, in increasing index, to a list
-//             placed by a single-pass decoupled look-back scan.
+// k_label   : one tile of 2048 triangles per block, eight consecutive
+//             triangles per thread so that twin, Max and the label bytes move
+//             as 16-byte and 4-byte vectors. Writes the half-edge labels and
+//             the SEED flag, and the tile's seed count (also added to the sum
+//             of its group of 64 tiles).
+// k_seeds   : the seed triangles in increasing index: each tile finds the
+//             seeds before it from the group sums and the counts of its own
+//             group, then places its seeds after them (no tile waits for
+//             another).
 #include "common.h"
 #include "scan.h"
 
@@ -125,11 +129,11 @@ constexpr int kLabelItems = 8;  // triangles per thread of k_label (multiple of 
 template <bool COMPUTE>
 __global__ __launch_bounds__(256) void k_label(int64_t nt, const int32_t* __restrict__ twin,
                                                const uint8_t* __restrict__ lg, uint8_t* __restrict__ he,
-                                               uint8_t* __restrict__ tri, int32_t* __restrict__ seeds,
-                                               uint32_t* __restrict__ lab4, uint64_t* status, Counters* cnt,
-                                               bool vec) {
+                                               uint8_t* __restrict__ tri, uint32_t* __restrict__ lab4,
+                                               uint32_t* __restrict__ tcount, uint32_t* __restrict__ tsuper,
+                                               Counters* cnt, bool vec) {
   constexpr int ITEMS = kLabelItems;
-  const uint32_t tile = take_tile(&cnt->tile_ticket[0]);
+  const uint32_t tile = blockIdx.x;
   const int64_t t0 = ((int64_t)tile * 256 + threadIdx.x) * ITEMS;
   const int32_t nhe = (int32_t)(3 * nt);
   bool sd[ITEMS];
@@ -240,14 +244,55 @@ __global__ __launch_bounds__(256) void k_label(int64_t nt, const int32_t* __rest
 #pragma unroll
   for (int j = 0; j < ITEMS; ++j) mine += sd[j] ? 1u : 0u;
   uint2 total;
-  uint2 pre = block_exclusive_scan<256>(mine, 0u, &total);
-  uint2 ex = tile_lookback(status, tile, total, cnt);
-  uint32_t pos = ex.x + pre.x;
+  (void)block_exclusive_scan<256>(mine, 0u, &total);
+  if (threadIdx.x == 0) {
+    tcount[tile] = total.x;
+    if (total.x) atomicAdd(&tsuper[tile >> 6], total.x);
+  }
+}
+
+// Seed list of the tiles of k_label (tsuper zeroed before k_label ran).
+__global__ __launch_bounds__(256) void k_seeds(int64_t nt, const uint8_t* __restrict__ tri,
+                                               const uint32_t* __restrict__ tcount,
+                                               const uint32_t* __restrict__ tsuper, int32_t* __restrict__ seeds,
+                                               Counters* cnt) {
+  constexpr int ITEMS = kLabelItems;
+  static_assert(ITEMS == 8, "flags are read as two words");
+  __shared__ uint32_t s_base;
+  const uint32_t tile = blockIdx.x;
+  if (threadIdx.x < 64) {
+    const uint32_t lane = threadIdx.x;
+    uint32_t acc = 0;
+    for (uint32_t k = lane; k < (tile >> 6); k += 64) acc += tsuper[k];
+    const uint32_t c = (tile & ~63u) + lane;
+    if (c < tile) acc += tcount[c];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (lane == 0) s_base = acc;
+  }
+  __syncthreads();
+  const uint32_t base = s_base;
+  const int64_t t0 = ((int64_t)tile * 256 + threadIdx.x) * ITEMS;
+  uint32_t bits = 0;  // bit j: triangle t0 + j is a seed
+  if (t0 + ITEMS <= nt && (reinterpret_cast<uintptr_t>(tri) & 7) == 0) {
+    const uint2 f = *reinterpret_cast<const uint2*>(tri + t0);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      bits |= ((f.x >> (8 * j)) & kSeed) ? (1u << j) : 0u;
+      bits |= ((f.y >> (8 * j)) & kSeed) ? (1u << (4 + j)) : 0u;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j)
+      if (t0 + j < nt && (tri[t0 + j] & kSeed)) bits |= 1u << j;
+  }
+  uint2 total;
+  const uint2 pre = block_exclusive_scan<256>((uint32_t)__popc(bits), 0u, &total);
+  uint32_t pos = base + pre.x;
 #pragma unroll
   for (int j = 0; j < ITEMS; ++j)
-    if (sd[j]) seeds[pos++] = (int32_t)(t0 + j);
-  const int64_t ntiles = (nt + 256 * ITEMS - 1) / (256 * ITEMS);  // tiles of this launch
-  if (tile == ntiles - 1 && threadIdx.x == 0) cnt->n_seeds = ex.x + total.x;
+    if ((bits >> j) & 1u) seeds[pos++] = (int32_t)(t0 + j);
+  if (tile == gridDim.x - 1 && threadIdx.x == 0) cnt->n_seeds = base + total.x;
 }
 
 // Full check of the input layout: grouped next, index ranges, twin involution
@@ -273,10 +318,10 @@ __global__ __launch_bounds__(256) void k_validate(int64_t nhe, int64_t nv, const
   }
 }
 
-template __global__ void k_label<true>(int64_t, const int32_t*, const uint8_t*, uint8_t*, uint8_t*, int32_t*,
-                                       uint32_t*, uint64_t*, Counters*, bool);
-template __global__ void k_label<false>(int64_t, const int32_t*, const uint8_t*, uint8_t*, uint8_t*, int32_t*,
-                                        uint32_t*, uint64_t*, Counters*, bool);
+template __global__ void k_label<true>(int64_t, const int32_t*, const uint8_t*, uint8_t*, uint8_t*, uint32_t*,
+                                       uint32_t*, uint32_t*, Counters*, bool);
+template __global__ void k_label<false>(int64_t, const int32_t*, const uint8_t*, uint8_t*, uint8_t*, uint32_t*,
+                                        uint32_t*, uint32_t*, Counters*, bool);
 
 // Packed label word per triangle (three label bytes) from the half-edge
 // labels, for calls that start from existing labels.

@@ -459,8 +459,8 @@ __device__ void general_core(int32_t i, int32_t s, int32_t L, A cyc, A aux, int3
     int32_t e = aux[k];
     if (e >= 0 && e == aux[k - 1]) {
       const int32_t te = twin[e];
-      he[e] |= kBarrier;
-      if ((uint32_t)te < (uint32_t)nhe) he[te] |= kBarrier;
+      or_bits(he, e, kBarrier);
+      if ((uint32_t)te < (uint32_t)nhe) or_bits(he, te, kBarrier);
     }
   }
   // tips: the next frontier half-edge is the twin of the current one
@@ -469,7 +469,7 @@ __device__ void general_core(int32_t i, int32_t s, int32_t L, A cyc, A aux, int3
     int32_t h = cyc[k], hn = cyc[k + 1 == L ? 0 : k + 1];
     if (twin[h] == hn) {
       int32_t v = origin[hn];
-      if ((uint64_t)(uint32_t)v < (uint64_t)nv) vtx[v] |= kTip;
+      if ((uint64_t)(uint32_t)v < (uint64_t)nv) or_bits(vtx, v, kTip);
       aux[2 * ntip] = v;
       aux[2 * ntip + 1] = hn;
       ++ntip;
@@ -529,7 +529,7 @@ __device__ void general_core(int32_t i, int32_t s, int32_t L, A cyc, A aux, int3
         aux[2 * q] = -1 - aux[2 * q];
         continue;
       }
-      he[e] |= kFrontier | kRepaired;
+      he[e] |= kFrontier | kRepaired;  // read back by the piece walk below
       he[te] |= kFrontier | kRepaired;
       ++nsplit;
     }
@@ -838,7 +838,7 @@ __device__ void region_core(int32_t i, const Region<A>& R, int k, int start, A c
     if (tw < 0) continue;
     const int32_t key = h < tw ? h : tw;
     const int32_t at = bsearch_idx(aux, L, key);
-    if (at >= 0 && at + 1 < L && aux[at + 1] == key) he[h] |= kBarrier;
+    if (at >= 0 && at + 1 < L && aux[at + 1] == key) or_bits(he, h, kBarrier);
   }
   // tips: the next frontier half-edge is the twin of the current one; the
   // pair keeps the tip vertex and the cycle position of that next half-edge
@@ -847,7 +847,7 @@ __device__ void region_core(int32_t i, const Region<A>& R, int k, int start, A c
     const int mn = m + 1 == L ? 0 : m + 1;
     if (R.twin_gid(cyc[m]) == R.gid(cyc[mn])) {
       const int32_t v = R.vert(cyc[mn]);
-      if ((uint64_t)(uint32_t)v < (uint64_t)nv) vtx[v] |= kTip;
+      if ((uint64_t)(uint32_t)v < (uint64_t)nv) or_bits(vtx, v, kTip);
       aux[2 * ntip] = v;
       aux[2 * ntip + 1] = mn;
       ++ntip;
@@ -918,8 +918,8 @@ __device__ void region_core(int32_t i, const Region<A>& R, int k, int start, A c
         continue;
       }
       const int32_t ge = R.gid(e), gt = R.gid(te);
-      he[ge] |= kFrontier | kRepaired;
-      he[gt] |= kFrontier | kRepaired;
+      or_bits(he, ge, kFrontier | kRepaired);
+      or_bits(he, gt, kFrontier | kRepaired);
       R.set_link(e, -2 - gt);
       R.set_link(te, -2 - ge);
       opened[e >> 6] |= 1ull << (e & 63);
@@ -1117,7 +1117,8 @@ __global__ __launch_bounds__(64) void k_tip(int32_t nhe, int64_t nv, const int32
                                             int32_t* __restrict__ rest, int64_t rest_cap, Counters* cnt) {
   __shared__ int32_t s_v[kWalkCap * 64];
   __shared__ int32_t s_h[kWalkCap * 64];
-  const LdsCol v{s_v + threadIdx.x}, h{s_h + threadIdx.x};
+  __shared__ int32_t s_f[kWalkCap * 64];
+  const LdsCol v{s_v + threadIdx.x}, h{s_h + threadIdx.x}, f{s_f + threadIdx.x};
   const uint32_t nd = cnt->n_deferred;
   for (uint32_t j = blockIdx.x * 64 + threadIdx.x; j < nd; j += gridDim.x * 64) {
     const int32_t i = deferred[j];
@@ -1152,9 +1153,11 @@ __global__ __launch_bounds__(64) void k_tip(int32_t nhe, int64_t nv, const int32
     int q = -1;
     if (fast) {
       // middle internal edge c_{floor(d/2)} turning clockwise about v[m] from c0 = h[m]
+      // (the fan's half-edges are kept, so the middle one needs no second walk)
       const int32_t c0 = h[m];
       int32_t d = 0, c = c0;
       do {
+        if (d < kWalkCap) f[d] = c;
         const int32_t tw = twin[c];
         if ((uint32_t)tw >= (uint32_t)nhe) {
           d = -1;
@@ -1165,8 +1168,12 @@ __global__ __launch_bounds__(64) void k_tip(int32_t nhe, int64_t nv, const int32
       } while (c != c0 && d <= nhe);
       fast = d >= 2 && c == c0;
       if (fast) {
-        e = c0;
-        for (int32_t k = 0; k < d / 2; ++k) e = he_next(twin[e]);
+        if (d / 2 < kWalkCap) {
+          e = f[d / 2];
+        } else {
+          e = c0;
+          for (int32_t k = 0; k < d / 2; ++k) e = he_next(twin[e]);
+        }
         te = twin[e];
         x = origin[he_next(e)];
         int occ = 0;
@@ -1190,13 +1197,13 @@ __global__ __launch_bounds__(64) void k_tip(int32_t nhe, int64_t nv, const int32
     for (int k = 0; 2 * k + 2 < L; ++k) {
       const int lo = (m - k - 1 + L) % L, hi = (m + k + 1) % L;
       if (v[lo] != v[hi]) break;
-      he[h[lo]] |= kBarrier;             // v[lo] -> v[lo + 1]
-      he[h[(m + k) % L]] |= kBarrier;    // v[m + k] -> v[hi]
+      or_bits(he, h[lo], kBarrier);             // v[lo] -> v[lo + 1]
+      or_bits(he, h[(m + k) % L], kBarrier);    // v[m + k] -> v[hi]
     }
     const int32_t vt = v[m];
-    if ((uint64_t)(uint32_t)vt < (uint64_t)nv) vtx[vt] |= kTip;
-    he[e] |= kFrontier | kRepaired;
-    he[te] |= kFrontier | kRepaired;
+    if ((uint64_t)(uint32_t)vt < (uint64_t)nv) or_bits(vtx, vt, kTip);
+    or_bits(he, e, kFrontier | kRepaired);
+    or_bits(he, te, kFrontier | kRepaired);
     atomicAdd(&cnt->n_tips, 1u);
     atomicAdd(&cnt->n_splits, 1u);
     // pieces: A = positions m..q (x last, leaving by te), B = q..m (v[m] last, leaving by e)
@@ -1576,7 +1583,7 @@ __global__ __launch_bounds__(NT) void k_general_big(
         S.q[2 * p] = S.b[j];
         S.q[2 * p + 1] = c;
       }
-      if ((uint32_t)tw < (uint32_t)nhe && hash_find(S, hv, tw) >= 0) he[h] |= kBarrier;
+      if ((uint32_t)tw < (uint32_t)nhe && hash_find(S, hv, tw) >= 0) or_bits(he, h, kBarrier);
     }
     __syncthreads();
     if (S.sc[SC_BAD]) {
@@ -1590,7 +1597,7 @@ __global__ __launch_bounds__(NT) void k_general_big(
     const int ntip = S.sc[SC_NTIP];
     for (int p = tid; p < ntip; p += kBigThreads) {
       const int32_t v = S.q[2 * p];
-      if ((uint64_t)(uint32_t)v < (uint64_t)nv) vtx[v] |= kTip;
+      if ((uint64_t)(uint32_t)v < (uint64_t)nv) or_bits(vtx, v, kTip);
     }
     if (tid == 0 && ntip) atomicAdd(&cnt->n_tips, (uint32_t)ntip);
     // ---- 3. repair
@@ -1723,7 +1730,7 @@ __global__ __launch_bounds__(NT) void k_general_big(
         if (S.jp[r]) continue;
         const int32_t e = S.q[2 * S.a[r] + 1];
         const int32_t te = twin[e];
-        he[e] |= kFrontier | kRepaired;
+        he[e] |= kFrontier | kRepaired;  // read back by the successor pass
         he[te] |= kFrontier | kRepaired;
         const int idx = atomicAdd(&S.sc[SC_NFH], 2);
         S.fh[idx] = e;

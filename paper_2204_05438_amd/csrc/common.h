@@ -65,6 +65,15 @@ __device__ __forceinline__ int32_t he_next(int32_t h) {
   return r == 2 ? h - 2 : h + 1;
 }
 
+// Sets label bits in byte i of a byte array with an atomic OR on the aligned
+// 32-bit word that holds it, whose result is not needed, so the thread does
+// not wait for it. The word stays in the page of the byte and its other
+// bytes are ORed with zero.
+__device__ __forceinline__ void or_bits(uint8_t* a, int64_t i, uint32_t bits) {
+  const uintptr_t p = reinterpret_cast<uintptr_t>(a + i);
+  atomicOr(reinterpret_cast<uint32_t*>(p & ~(uintptr_t)3), bits << (8 * (uint32_t)(p & 3)));
+}
+
 __device__ __forceinline__ void set_error(Counters* c, int32_t code) {
   atomicCAS(&c->error, 0, code);
 }

@@ -31,7 +31,8 @@ __global__ void k_tip(int32_t, int64_t, const int32_t*, const int32_t*, uint8_t*
 template <bool REPAIR, int NT, int KC, int LC, int HB>
 __global__ void k_general_big(const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*, const uint32_t*,
                               uint8_t*, uint8_t*, int32_t*, int64_t, int32_t*, int64_t, PolyState, const int32_t*,
-                              bool, int64_t, const uint32_t*, uint32_t*, int32_t*, int64_t, uint32_t*, Counters*);
+                              bool, int64_t, const uint32_t*, uint32_t*, int32_t*, int64_t, uint32_t*,
+                              const int32_t*, int64_t, const uint32_t*, uint32_t, Counters*);
 template <bool REPAIR>
 __global__ void k_general_huge(const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*, uint8_t*,
                                uint8_t*, int32_t*, int64_t, int32_t*, int64_t, PolyState, const int32_t*,
@@ -279,7 +280,9 @@ int run_build(polylla_ctx* c, const polylla_tri* t, const int32_t* list, bool fr
   if (hipEventRecord(c->fork, s) != hipSuccess || hipStreamWaitEvent(c->side, c->fork, 0) != hipSuccess)
     return POLYLLA_EHIP;
   // long regions: one wave per region first (regions of up to 128 triangles
-  // and frontier half-edges), then 1024 threads per region for the rest
+  // and frontier half-edges), then 1024 threads per region for the rest; when
+  // there are at most `few` of them, all go to the 1024-thread instance
+  const uint32_t few = 128;
   {
     Prof p(c, c->side, KR_BIG);
     Counters* k = c->cnt;
@@ -288,12 +291,12 @@ int run_build(polylla_ctx* c, const polylla_tri* t, const int32_t* list, bool fr
       hipLaunchKernelGGL((k_general_big<true, 64, 128, 128, 8>), dim3(gm), dim3(64), 0, c->side, list, from_seeds, nhe,
                          t->n_vertices, t->twin, t->origin, c->lab4, he, vtx, c->stage, c->stage_cap, c->arena,
                          c->arena_cap, ps, c->deferred, true, c->cap_t, &k->n_big, &k->big_ticket, c->over,
-                         c->over_cap, &k->n_over, k);
+                         c->over_cap, &k->n_over, nullptr, (int64_t)0, &k->n_big, few, k);
     else
       hipLaunchKernelGGL((k_general_big<false, 64, 128, 128, 8>), dim3(gm), dim3(64), 0, c->side, list, from_seeds,
                          nhe, t->n_vertices, t->twin, t->origin, c->lab4, he, vtx, c->stage, c->stage_cap, c->arena,
                          c->arena_cap, ps, c->deferred, true, c->cap_t, &k->n_big, &k->big_ticket, c->over,
-                         c->over_cap, &k->n_over, k);
+                         c->over_cap, &k->n_over, nullptr, (int64_t)0, &k->n_big, few, k);
   }
   {
     Prof p(c, c->side, KR_BIGW);
@@ -303,12 +306,12 @@ int run_build(polylla_ctx* c, const polylla_tri* t, const int32_t* list, bool fr
       hipLaunchKernelGGL((k_general_big<true, 1024, 4096, 4096, 13>), dim3(gb), dim3(1024), 0, c->side, list,
                          from_seeds, nhe, t->n_vertices, t->twin, t->origin, c->lab4, he, vtx, c->stage, c->stage_cap,
                          c->arena, c->arena_cap, ps, c->over, false, (int64_t)0, &k->n_over, &k->over_ticket, c->huge,
-                         c->huge_cap, &k->n_fallback, k);
+                         c->huge_cap, &k->n_fallback, c->deferred, c->cap_t, &k->n_big, few, k);
     else
       hipLaunchKernelGGL((k_general_big<false, 1024, 4096, 4096, 13>), dim3(gb), dim3(1024), 0, c->side, list,
                          from_seeds, nhe, t->n_vertices, t->twin, t->origin, c->lab4, he, vtx, c->stage, c->stage_cap,
                          c->arena, c->arena_cap, ps, c->over, false, (int64_t)0, &k->n_over, &k->over_ticket, c->huge,
-                         c->huge_cap, &k->n_fallback, k);
+                         c->huge_cap, &k->n_fallback, c->deferred, c->cap_t, &k->n_big, few, k);
   }
   if (hipEventRecord(c->join, c->side) != hipSuccess) return POLYLLA_EHIP;
   {

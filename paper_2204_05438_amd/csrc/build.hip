@@ -1465,6 +1465,10 @@ __device__ __forceinline__ void push_over(int32_t* over, int64_t over_cap, uint3
 // capacities KC/LC/HB. Polygons come from `in` (in_rev: counted from the back
 // of the array, in_cap its length), `in_count` of them, taken by `in_ticket`;
 // regions beyond the capacities go to `over` (count `over_count`).
+// With `few_count` given and at most `few_max` long polygons in all, the first
+// instance (few_in null) leaves them all to the second, which then takes them
+// from few_in (from the back, few_cap long) instead of `in`: a few long
+// regions are then not gathered twice.
 template <bool REPAIR, int NT, int KC, int LC, int HB>
 __global__ __launch_bounds__(NT) void k_general_big(
     const int32_t* __restrict__ list, bool from_seeds, int32_t nhe, int64_t nv, const int32_t* __restrict__ twin,
@@ -1472,12 +1476,20 @@ __global__ __launch_bounds__(NT) void k_general_big(
     uint8_t* __restrict__ vtx, int32_t* __restrict__ stage, int64_t stage_cap, int32_t* __restrict__ arena,
     int64_t arena_cap, PolyState ps, const int32_t* __restrict__ in, bool in_rev, int64_t in_cap,
     const uint32_t* in_count, uint32_t* in_ticket, int32_t* __restrict__ over, int64_t over_cap,
-    uint32_t* over_count, Counters* cnt) {
+    uint32_t* over_count, const int32_t* __restrict__ few_in, int64_t few_cap, const uint32_t* few_count,
+    uint32_t few_max, Counters* cnt) {
   constexpr int kBigThreads = NT, kKCap = KC, kLCap = LC, kHCap = 1 << HB, kPer = LC / NT;
   static_assert(LC % NT == 0 && kPer >= 1, "slots per thread");
   __shared__ BigLds<KC, LC, HB> S;
   int16_t* hv = reinterpret_cast<int16_t*>(S.hval);  // hash values: int16 per hash slot (kHCap of them)
   const int tid = threadIdx.x;
+  if (few_count && *few_count <= few_max) {
+    if (!few_in) return;
+    in = few_in;
+    in_rev = true;
+    in_cap = few_cap;
+    in_count = few_count;
+  }
   const uint32_t nbig = *in_count;
   const int32_t nt = nhe / 3;
   for (;;) {
@@ -2195,19 +2207,19 @@ template __global__ void k_tip<false>(int32_t, int64_t, const int32_t*, const in
 template __global__ void k_general_big<true, 64, 128, 128, 8>(
     const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*, const uint32_t*, uint8_t*, uint8_t*,
     int32_t*, int64_t, int32_t*, int64_t, PolyState, const int32_t*, bool, int64_t, const uint32_t*, uint32_t*,
-    int32_t*, int64_t, uint32_t*, Counters*);
+    int32_t*, int64_t, uint32_t*, const int32_t*, int64_t, const uint32_t*, uint32_t, Counters*);
 template __global__ void k_general_big<true, 1024, 4096, 4096, 13>(
     const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*, const uint32_t*, uint8_t*, uint8_t*,
     int32_t*, int64_t, int32_t*, int64_t, PolyState, const int32_t*, bool, int64_t, const uint32_t*, uint32_t*,
-    int32_t*, int64_t, uint32_t*, Counters*);
+    int32_t*, int64_t, uint32_t*, const int32_t*, int64_t, const uint32_t*, uint32_t, Counters*);
 template __global__ void k_general_big<false, 64, 128, 128, 8>(
     const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*, const uint32_t*, uint8_t*, uint8_t*,
     int32_t*, int64_t, int32_t*, int64_t, PolyState, const int32_t*, bool, int64_t, const uint32_t*, uint32_t*,
-    int32_t*, int64_t, uint32_t*, Counters*);
+    int32_t*, int64_t, uint32_t*, const int32_t*, int64_t, const uint32_t*, uint32_t, Counters*);
 template __global__ void k_general_big<false, 1024, 4096, 4096, 13>(
     const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*, const uint32_t*, uint8_t*, uint8_t*,
     int32_t*, int64_t, int32_t*, int64_t, PolyState, const int32_t*, bool, int64_t, const uint32_t*, uint32_t*,
-    int32_t*, int64_t, uint32_t*, Counters*);
+    int32_t*, int64_t, uint32_t*, const int32_t*, int64_t, const uint32_t*, uint32_t, Counters*);
 template __global__ void k_general_huge<true>(const int32_t*, bool, int32_t, int64_t, const int32_t*,
                                               const int32_t*, uint8_t*, uint8_t*, int32_t*, int64_t, int32_t*,
                                               int64_t, PolyState, const int32_t*, Counters*);

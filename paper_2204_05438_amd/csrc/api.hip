@@ -97,6 +97,10 @@ constexpr int64_t kScanTileHost = 2048;   // polygons per tile of k_scan_emit
 constexpr int64_t kWalkBlocks = 2048;     // persistent grid of k_walk
 constexpr int64_t kWalkWaves = kWalkBlocks * 4;
 constexpr int64_t kStageChunkHost = 4096; // staging ints a walk wave reserves at a time
+// unused tails of the staging and arena chunks of the region workgroups (two
+// launches of the one-wave instance, one of the 1024-thread instance)
+constexpr int64_t kBigStageTails = 2 * (int64_t)kBigGrid64 * kBigStageChunk64 + (int64_t)kBigGrid1024 * kBigStageChunk1024;
+constexpr int64_t kBigArenaTails = 2 * (int64_t)kBigGrid64 * kBigArenaChunk64 + (int64_t)kBigGrid1024 * kBigArenaChunk1024;
 
 enum KernelId {
   KR_RESET, KR_LONGEST, KR_LABEL, KR_COMPACT, KR_PACK, KR_WALK, KR_GENERAL, KR_BIG, KR_HUGE, KR_SCAN, KR_VALIDATE,
@@ -173,9 +177,9 @@ int ensure(polylla_ctx* c, int64_t nt, int64_t nv) {
   const int64_t ntiles = (T + kTile - 1) / kTile + 1;
   // polygon vertices (<= 3T) and the general paths' staging, plus the unused
   // tail of the last staging chunk of every walk wave. Offsets stay int32.
-  c->stage_cap = std::min<int64_t>(5 * T + kWalkWaves * kStageChunkHost + ((int64_t)1 << 20),
+  c->stage_cap = std::min<int64_t>(5 * T + kWalkWaves * kStageChunkHost + kBigStageTails + ((int64_t)1 << 20),
                                    ((int64_t)1 << 31) - 1);
-  c->arena_cap = 6 * T + 4096;
+  c->arena_cap = 6 * T + kBigArenaTails + 4096;
   c->n_status = 2 * ntiles;
   if ((rc = dalloc(&c->lg, T)) || (rc = dalloc(&c->lab4, T)) || (rc = dalloc(&c->seeds, T)) || (rc = dalloc(&c->deferred, T)) || (rc = dalloc(&c->huge, c->huge_cap = T / 1024 + 64)) ||
       (rc = dalloc(&c->over, c->over_cap = T / 32 + 64)) ||
@@ -286,7 +290,7 @@ int run_build(polylla_ctx* c, const polylla_tri* t, const int32_t* list, bool fr
   {
     Prof p(c, c->side, KR_BIG);
     Counters* k = c->cnt;
-    const int gm = 4096;  // persistent: one-wave blocks take regions by ticket
+    const int gm = kBigGrid64;  // persistent: one-wave blocks take regions round-robin
     if (repair)
       hipLaunchKernelGGL((k_general_big<true, 64, 128, 128, 8>), dim3(gm), dim3(64), 0, c->side, list, from_seeds, nhe,
                          t->n_vertices, t->twin, t->origin, c->lab4, he, vtx, c->stage, c->stage_cap, c->arena,
@@ -301,7 +305,7 @@ int run_build(polylla_ctx* c, const polylla_tri* t, const int32_t* list, bool fr
   {
     Prof p(c, c->side, KR_BIGW);
     Counters* k = c->cnt;
-    const int gb = 128;  // persistent: blocks take the remaining long regions by ticket
+    const int gb = kBigGrid1024;  // persistent: blocks take the remaining long regions by ticket
     if (repair)
       hipLaunchKernelGGL((k_general_big<true, 1024, 4096, 4096, 13>), dim3(gb), dim3(1024), 0, c->side, list,
                          from_seeds, nhe, t->n_vertices, t->twin, t->origin, c->lab4, he, vtx, c->stage, c->stage_cap,

@@ -143,7 +143,7 @@ __global__ __launch_bounds__(256) void k_walk(const int32_t* __restrict__ list, 
   const int xcd = blockIdx.x % kXcds;
   const int32_t part_lo = (int32_t)((int64_t)R * xcd / kXcds);
   const int32_t part_hi = (int32_t)((int64_t)R * (xcd + 1) / kXcds);
-  uint32_t* ticket = &cnt->xcd_ticket[xcd];
+  uint32_t* ticket = &cnt->xcd_ticket[64 * xcd];
   // wave-uniform: current chunk [cbase, cbase + clen), next unused slot cpos;
   // chunk_item: list entry of slot `lane` of the chunk
   int32_t cbase = 0, clen = 0, cpos = 0, chunk_item = 0;
@@ -1337,12 +1337,22 @@ struct BigLds {
   int32_t kc[LC / 2];    // repair: undecided smaller tips whose opened edge ends at this tip
   int16_t kf[LC / 2];    // repair: rank of the tip at the far end of this tip's opened edge, or -1
   uint32_t emask[128];   // repair: end vertices of opened edges, hashed to 4096 bits
-  int32_t sc[16];
+  int32_t sc[20];
+  // Small instances keep the region's links, so that successors and the
+  // repair never go back to global memory: code = 4 slot + local edge.
+  static constexpr bool kLinks = KC <= 256;
+  static constexpr int kLK = kLinks ? KC : 1, kLL = kLinks ? LC : 1;
+  int32_t tri[kLK];      // triangle of each region slot
+  int32_t org[3 * kLK];  // origin of each local edge
+  int16_t lnk[3 * kLK];  // internal edge: code of its twin; frontier edge: -1 - its frontier slot
+  int16_t fcode[kLL];    // code of each frontier slot
+  int16_t tslot[kLL];    // frontier slot of the twin (barrier edges), else -1
 };
 
 enum {
   SC_QLEN, SC_LO, SC_HI, SC_NFH, SC_NTIP, SC_OVER, SC_BAD, SC_NSPLIT, SC_NP, SC_ITEM, SC_SBASE, SC_NEND, SC_RB,
-  SC_PEND  // two slots, used alternately
+  SC_PEND,  // two slots, used alternately
+  SC_SNEXT = SC_PEND + 2, SC_SLEFT, SC_ANEXT, SC_ALEFT  // the workgroup's staging and arena chunks
 };
 
 template <int HB>
@@ -1452,6 +1462,45 @@ __device__ __forceinline__ void successors(const LDS& S, int L, int first_new, c
     if (act[u]) succ[u] = -1;  // walk bound exceeded
 }
 
+// Successor slot of every frontier slot from the region links (LDS only);
+// flags an invalid region.
+template <int NT, class LDS>
+__device__ __forceinline__ void successors_links(LDS& S, int L) {
+  constexpr int kBound = 3 * LDS::kKCap + 3;
+  for (int k = threadIdx.x; k < L; k += NT) {
+    int x = S.fcode[k];
+    x = (x & ~3) | next_local(x & 3);
+    int r = -1;
+    for (int n = 0; n < kBound; ++n) {
+      const int l = S.lnk[3 * (x >> 2) + (x & 3)];
+      if (l < 0) {
+        r = -1 - l;
+        break;
+      }
+      x = (l & ~3) | next_local(l & 3);
+    }
+    if (r < 0) {
+      S.sc[SC_BAD] = 1;
+      r = k;
+    }
+    S.nx[k] = (int16_t)r;
+  }
+}
+
+// One step of a turn about a vertex inside the region: cross the edge of code
+// x to its twin and take the twin's next local edge; -1 if the twin is not in
+// the region.
+template <class LDS>
+__device__ __forceinline__ int turn_links(const LDS& S, int x) {
+  int y = S.lnk[3 * (x >> 2) + (x & 3)];
+  if (y < 0) {
+    const int f2 = S.tslot[-1 - y];
+    if (f2 < 0) return -1;
+    y = S.fcode[f2];
+  }
+  return (y & ~3) | next_local(y & 3);
+}
+
 // Queue a polygon for the next, larger instance (bounded: the queues are sized
 // from the smallest region that can exceed an instance's capacities).
 __device__ __forceinline__ void push_over(int32_t* over, int64_t over_cap, uint32_t* over_count, int32_t i,
@@ -1481,8 +1530,18 @@ __global__ __launch_bounds__(NT) void k_general_big(
   constexpr int kBigThreads = NT, kKCap = KC, kLCap = LC, kHCap = 1 << HB, kPer = LC / NT;
   static_assert(LC % NT == 0 && kPer >= 1, "slots per thread");
   __shared__ BigLds<KC, LC, HB> S;
+  constexpr bool LINKS = BigLds<KC, LC, HB>::kLinks;
   int16_t* hv = reinterpret_cast<int16_t*>(S.hval);  // hash values: int16 per hash slot (kHCap of them)
   const int tid = threadIdx.x;
+  // one-wave instances take polygons round-robin (no shared work counter);
+  // staging and arena space is reserved in chunks per workgroup
+  constexpr bool kStaticItems = NT == 64;
+  constexpr int32_t kStageChunkWg = NT == 64 ? kBigStageChunk64 : kBigStageChunk1024;
+  constexpr int32_t kArenaChunkWg = NT == 64 ? kBigArenaChunk64 : kBigArenaChunk1024;
+  if (tid == 0) {
+    S.sc[SC_SLEFT] = 0;
+    S.sc[SC_ALEFT] = 0;
+  }
   if (few_count && *few_count <= few_max) {
     if (!few_in) return;
     in = few_in;
@@ -1492,10 +1551,18 @@ __global__ __launch_bounds__(NT) void k_general_big(
   }
   const uint32_t nbig = *in_count;
   const int32_t nt = nhe / 3;
+  uint32_t next_item = blockIdx.x;
   for (;;) {
-    if (tid == 0) S.sc[SC_ITEM] = (int32_t)atomicAdd(in_ticket, 1u);
-    __syncthreads();
-    const uint32_t item = (uint32_t)S.sc[SC_ITEM];
+    uint32_t item;
+    if constexpr (kStaticItems) {
+      item = next_item;
+      next_item += gridDim.x;
+      __syncthreads();
+    } else {
+      if (tid == 0) S.sc[SC_ITEM] = (int32_t)atomicAdd(in_ticket, 1u);
+      __syncthreads();
+      item = (uint32_t)S.sc[SC_ITEM];
+    }
     if (item >= nbig) break;
     const int32_t i = in_rev ? in[in_cap - 1 - item] : in[item];
     const int32_t li = list[i];
@@ -1526,10 +1593,12 @@ __global__ __launch_bounds__(NT) void k_general_big(
         const Int3 tw3 = *reinterpret_cast<const Int3*>(twin + 3 * t);
         const Int3 or3 = *reinterpret_cast<const Int3*>(origin + 3 * t);
         const uint32_t lw = lab4[t];
+        if constexpr (LINKS) S.tri[j] = t;
 #pragma unroll
         for (int e = 0; e < 3; ++e) {
           const int32_t h = 3 * t + e;
-          if (h == entry) continue;
+          if constexpr (LINKS) S.org[3 * j + e] = sel3(or3.x, or3.y, or3.z, e);
+          if (h == entry) continue;  // (its link was set by the parent)
           const int32_t tw = sel3(tw3.x, tw3.y, tw3.z, e);
           if ((lw >> (8 * e)) & kFrontier) {
             const int idx = atomicAdd(&S.sc[SC_NFH], 1);
@@ -1538,6 +1607,10 @@ __global__ __launch_bounds__(NT) void k_general_big(
               S.b[idx] = sel3(or3.x, or3.y, or3.z, e);
               S.a[idx] = tw;
               hash_insert(S, hv, h, idx);
+              if constexpr (LINKS) {
+                S.fcode[idx] = (int16_t)(4 * j + e);
+                S.lnk[3 * j + e] = (int16_t)(-1 - idx);
+              }
             } else {
               S.sc[SC_OVER] = 1;
             }
@@ -1547,8 +1620,16 @@ __global__ __launch_bounds__(NT) void k_general_big(
               continue;
             }
             const int pos = atomicAdd(&S.sc[SC_QLEN], 1);
-            if (pos < kKCap) S.q[pos] = tw;
-            else S.sc[SC_OVER] = 1;
+            if (pos < kKCap) {
+              S.q[pos] = tw;
+              if constexpr (LINKS) {
+                const int e2 = tw - 3 * (tw / 3);
+                S.lnk[3 * j + e] = (int16_t)(4 * pos + e2);
+                S.lnk[3 * pos + e2] = (int16_t)(4 * j + e);
+              }
+            } else {
+              S.sc[SC_OVER] = 1;
+            }
           }
         }
       }
@@ -1575,27 +1656,45 @@ __global__ __launch_bounds__(NT) void k_general_big(
     int L = S.sc[SC_NFH];
     // ---- 2. successors, tips, barrier edges, vertex ids
     int32_t succ[kPer];
-    successors<NT>(S, L, 0, nullptr, 0, succ, nhe, twin, he);
+    if constexpr (LINKS) {
+      // tips keep the frontier slot of their barrier half-edge
+      successors_links<NT>(S, L);
+      __syncthreads();
+      for (int k = tid; k < L; k += kBigThreads) {
+        const int j = S.nx[k];
+        const int32_t tw = S.a[k];
+        const int32_t ts = (uint32_t)tw < (uint32_t)nhe ? hash_find(S, hv, tw) : -1;
+        S.tslot[k] = (int16_t)ts;
+        if (S.fh[j] == tw && j != k) {
+          const int p = atomicAdd(&S.sc[SC_NTIP], 1);
+          S.q[2 * p] = S.b[j];
+          S.q[2 * p + 1] = j;
+        }
+        if (ts >= 0) or_bits(he, S.fh[k], kBarrier);
+      }
+    } else {
+      successors<NT>(S, L, 0, nullptr, 0, succ, nhe, twin, he);
 #pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-      const int k = tid + u * kBigThreads;
-      if (k >= L) continue;
-      const int32_t h = S.fh[k];
-      const int32_t c = succ[u];
-      const int32_t j = c < 0 ? -1 : hash_find(S, hv, c);
-      if (j < 0) {
-        S.sc[SC_BAD] = 1;
-        S.nx[k] = (int16_t)k;
-      } else {
-        S.nx[k] = (int16_t)j;
+      for (int u = 0; u < kPer; ++u) {
+        const int k = tid + u * kBigThreads;
+        if (k >= L) continue;
+        const int32_t h = S.fh[k];
+        const int32_t c = succ[u];
+        const int32_t j = c < 0 ? -1 : hash_find(S, hv, c);
+        if (j < 0) {
+          S.sc[SC_BAD] = 1;
+          S.nx[k] = (int16_t)k;
+        } else {
+          S.nx[k] = (int16_t)j;
+        }
+        const int32_t tw = S.a[k];
+        if (c >= 0 && c == tw && j >= 0) {
+          const int p = atomicAdd(&S.sc[SC_NTIP], 1);
+          S.q[2 * p] = S.b[j];
+          S.q[2 * p + 1] = c;
+        }
+        if ((uint32_t)tw < (uint32_t)nhe && hash_find(S, hv, tw) >= 0) or_bits(he, h, kBarrier);
       }
-      const int32_t tw = S.a[k];
-      if (c >= 0 && c == tw && j >= 0) {
-        const int p = atomicAdd(&S.sc[SC_NTIP], 1);
-        S.q[2 * p] = S.b[j];
-        S.q[2 * p + 1] = c;
-      }
-      if ((uint32_t)tw < (uint32_t)nhe && hash_find(S, hv, tw) >= 0) or_bits(he, h, kBarrier);
     }
     __syncthreads();
     if (S.sc[SC_BAD]) {
@@ -1616,26 +1715,44 @@ __global__ __launch_bounds__(NT) void k_general_big(
     if (REPAIR && ntip > 0) {
       // middle internal edge at every tip; its far vertex goes to a[2048 + p]
       for (int p = tid; p < ntip; p += kBigThreads) {
-        const int32_t c0 = S.q[2 * p + 1];
-        int32_t d = 0, c = c0;
-        bool okr = true;
-        do {
-          const int32_t tw = twin[c];
-          if ((uint32_t)tw >= (uint32_t)nhe) {
-            okr = false;
-            break;
+        if constexpr (LINKS) {
+          // the fan of the tip lies in the region: turn about it in LDS
+          const int x0 = S.fcode[S.q[2 * p + 1]];
+          int d = 0, x = x0;
+          do {
+            x = turn_links(S, x);
+            ++d;
+          } while (x >= 0 && x != x0 && d <= 3 * kKCap);
+          if (x != x0) {
+            S.sc[SC_BAD] = 1;
+            d = 0;
           }
-          c = he_next(tw);
-          ++d;
-        } while (c != c0 && d <= nhe);
-        if (!okr || c != c0) {
-          S.sc[SC_BAD] = 1;
-          d = 0;
+          int ec = x0;
+          for (int k = 0; k < d / 2; ++k) ec = turn_links(S, ec);
+          S.q[2 * p + 1] = ec;  // a code from here on
+          S.a[kLCap / 2 + p] = S.org[3 * (ec >> 2) + next_local(ec & 3)];
+        } else {
+          const int32_t c0 = S.q[2 * p + 1];
+          int32_t d = 0, c = c0;
+          bool okr = true;
+          do {
+            const int32_t tw = twin[c];
+            if ((uint32_t)tw >= (uint32_t)nhe) {
+              okr = false;
+              break;
+            }
+            c = he_next(tw);
+            ++d;
+          } while (c != c0 && d <= nhe);
+          if (!okr || c != c0) {
+            S.sc[SC_BAD] = 1;
+            d = 0;
+          }
+          int32_t e = c0;
+          for (int32_t k = 0; k < d / 2; ++k) e = he_next(twin[e]);
+          S.q[2 * p + 1] = e;
+          S.a[kLCap / 2 + p] = origin[he_next(e)];
         }
-        int32_t e = c0;
-        for (int32_t k = 0; k < d / 2; ++k) e = he_next(twin[e]);
-        S.q[2 * p + 1] = e;
-        S.a[kLCap / 2 + p] = origin[he_next(e)];
       }
       __syncthreads();
       // tips ranked by vertex id (ids are distinct): a[rank] = tip
@@ -1740,36 +1857,69 @@ __global__ __launch_bounds__(NT) void k_general_big(
       // open the edges of the live tips and add both half-edges
       for (int r = tid; r < ntip; r += kBigThreads) {
         if (S.jp[r]) continue;
-        const int32_t e = S.q[2 * S.a[r] + 1];
-        const int32_t te = twin[e];
-        he[e] |= kFrontier | kRepaired;  // read back by the successor pass
-        he[te] |= kFrontier | kRepaired;
-        const int idx = atomicAdd(&S.sc[SC_NFH], 2);
-        S.fh[idx] = e;
-        S.fh[idx + 1] = te;
-        S.b[idx] = origin[e];
-        S.b[idx + 1] = origin[te];
-        hash_insert(S, hv, e, idx);
-        hash_insert(S, hv, te, idx + 1);
+        if constexpr (LINKS) {
+          const int ec = S.q[2 * S.a[r] + 1];
+          const int tc = S.lnk[3 * (ec >> 2) + (ec & 3)];
+          if (tc < 0) {  // the middle edge must be internal
+            S.sc[SC_BAD] = 1;
+            continue;
+          }
+          const int32_t ge = 3 * S.tri[ec >> 2] + (ec & 3), gt = 3 * S.tri[tc >> 2] + (tc & 3);
+          or_bits(he, ge, kFrontier | kRepaired);
+          or_bits(he, gt, kFrontier | kRepaired);
+          const int idx = atomicAdd(&S.sc[SC_NFH], 2);
+          S.fh[idx] = ge;
+          S.fh[idx + 1] = gt;
+          S.b[idx] = S.org[3 * (ec >> 2) + (ec & 3)];
+          S.b[idx + 1] = S.org[3 * (tc >> 2) + (tc & 3)];
+          S.fcode[idx] = (int16_t)ec;
+          S.fcode[idx + 1] = (int16_t)tc;
+          S.lnk[3 * (ec >> 2) + (ec & 3)] = (int16_t)(-1 - idx);
+          S.lnk[3 * (tc >> 2) + (tc & 3)] = (int16_t)(-2 - idx);
+        } else {
+          const int32_t e = S.q[2 * S.a[r] + 1];
+          const int32_t te = twin[e];
+          he[e] |= kFrontier | kRepaired;  // read back by the successor pass
+          he[te] |= kFrontier | kRepaired;
+          const int idx = atomicAdd(&S.sc[SC_NFH], 2);
+          S.fh[idx] = e;
+          S.fh[idx + 1] = te;
+          S.b[idx] = origin[e];
+          S.b[idx + 1] = origin[te];
+          hash_insert(S, hv, e, idx);
+          hash_insert(S, hv, te, idx + 1);
+        }
       }
       __syncthreads();
       if (tid == 0 && S.sc[SC_NSPLIT]) atomicAdd(&cnt->n_splits, (uint32_t)S.sc[SC_NSPLIT]);
       const int L0 = L;
       L = S.sc[SC_NFH];
       if (S.sc[SC_NSPLIT]) {
-        const int ne = S.sc[SC_NEND];
-        successors<NT>(S, L, L0, ne >= 0 ? S.q + 2 * ntip : nullptr, ne, succ, nhe, twin, he);
-        __syncthreads();
+        if constexpr (LINKS) {
+          successors_links<NT>(S, L);
+        } else {
+          const int ne = S.sc[SC_NEND];
+          successors<NT>(S, L, L0, ne >= 0 ? S.q + 2 * ntip : nullptr, ne, succ, nhe, twin, he);
+          __syncthreads();
 #pragma unroll
-        for (int u = 0; u < kPer; ++u) {
-          const int k = tid + u * kBigThreads;
-          if (k >= L || succ[u] == kNoChange) continue;
-          const int32_t c = succ[u];
-          const int32_t j = c < 0 ? -1 : hash_find(S, hv, c);
-          S.nx[k] = (int16_t)(j < 0 ? k : j);
-          if (j < 0) S.sc[SC_BAD] = 1;
+          for (int u = 0; u < kPer; ++u) {
+            const int k = tid + u * kBigThreads;
+            if (k >= L || succ[u] == kNoChange) continue;
+            const int32_t c = succ[u];
+            const int32_t j = c < 0 ? -1 : hash_find(S, hv, c);
+            S.nx[k] = (int16_t)(j < 0 ? k : j);
+            if (j < 0) S.sc[SC_BAD] = 1;
+          }
         }
         __syncthreads();
+      }
+      if (S.sc[SC_BAD]) {
+        if (tid == 0) {
+          set_error(cnt, POLYLLA_EDEGEN);
+          ps.clear(i);
+        }
+        __syncthreads();
+        continue;
       }
     }
     // ---- 4. pieces = cycles of nx. piece id: smallest slot on the cycle
@@ -1914,12 +2064,34 @@ __global__ __launch_bounds__(NT) void k_general_big(
     const uint2 pre = block_exclusive_scan<NT>(mine, 0u, &tot);
     if (tid == 0) {
       const int32_t total = (int32_t)tot.x;
-      const uint32_t sb = atomicAdd(&cnt->stage_top, (uint32_t)total);
+      bool ok = true;
+      if (total > S.sc[SC_SLEFT]) {  // a new staging chunk for this workgroup
+        const int32_t want = max(total, kStageChunkWg);
+        const uint32_t nb = atomicAdd(&cnt->stage_top, (uint32_t)want);
+        ok = (int64_t)nb + want <= stage_cap;
+        S.sc[SC_SNEXT] = (int32_t)nb;
+        S.sc[SC_SLEFT] = ok ? want : 0;
+      }
+      const int32_t sb = S.sc[SC_SNEXT];
+      if (ok) {
+        S.sc[SC_SNEXT] += total;
+        S.sc[SC_SLEFT] -= total;
+      }
       int32_t rb = -1;
-      bool ok = (int64_t)sb + total <= stage_cap;
       if (ok && np > 1) {
-        rb = (int32_t)atomicAdd(&cnt->arena_top, (uint32_t)(4 * np));
-        ok = (int64_t)rb + 4 * np <= arena_cap;
+        const int32_t need = 4 * np;
+        if (need > S.sc[SC_ALEFT]) {
+          const int32_t want = max(need, kArenaChunkWg);
+          const uint32_t nb = atomicAdd(&cnt->arena_top, (uint32_t)want);
+          ok = (int64_t)nb + want <= arena_cap;
+          S.sc[SC_ANEXT] = (int32_t)nb;
+          S.sc[SC_ALEFT] = ok ? want : 0;
+        }
+        rb = S.sc[SC_ANEXT];
+        if (ok) {
+          S.sc[SC_ANEXT] += need;
+          S.sc[SC_ALEFT] -= need;
+        }
       }
       if (!ok) {
         set_error(cnt, POLYLLA_ENOMEM);

@@ -21,23 +21,24 @@ constexpr uint8_t kSeed = POLYLLA_SEED;
 constexpr uint8_t kTip = POLYLLA_TIP;
 
 // Device-side counters and error word, one block per context (zeroed by the
-// first kernel of every call).
+// first kernel of every call). Counters that many workgroups update during a
+// kernel sit 256 bytes apart, so that their atomics do not queue on one line.
 struct Counters {
   int32_t error;          // first error code (0 = none)
   uint32_t tile_ticket[4];  // dynamic tile ids of the look-back scans
   uint32_t n_seeds;       // R
-  uint32_t n_deferred;    // polygons handled by the general path
   uint32_t n_tips;
   uint32_t n_splits;
-  uint32_t stage_top;     // bump allocator of the staging buffer (ints)
-  uint32_t arena_top;     // bump allocator of the general-path arena (ints)
-  uint32_t n_big;         // polygons longer than the walk cap (one-wave workgroup path)
-  uint32_t big_ticket;    // work counter of the one-wave workgroup path
   uint32_t n_fallback;    // polygons too large for the 1024-thread workgroup's LDS
-  uint32_t over_ticket;   // work counter of the 1024-thread workgroup path
   uint32_t n_over;        // polygons too large for the one-wave workgroup's LDS
   uint32_t n_gen;         // short polygons the tip path leaves to the region path
-  uint32_t xcd_ticket[8]; // walk work queues, one per XCD
+  alignas(256) uint32_t n_deferred;  // polygons handled by the general path
+  alignas(256) uint32_t n_big;       // polygons longer than the walk cap (one-wave workgroup path)
+  alignas(256) uint32_t stage_top;   // bump allocator of the staging buffer (ints)
+  alignas(256) uint32_t arena_top;   // bump allocator of the general-path arena (ints)
+  alignas(256) uint32_t big_ticket;  // work counter of the one-wave workgroup path
+  alignas(256) uint32_t over_ticket; // work counter of the 1024-thread workgroup path
+  alignas(256) uint32_t xcd_ticket[8 * 64];  // walk work queues, one per XCD (xcd_ticket[64 x])
 };
 
 // Per-polygon results of the walk / general path, in seed order: one 16-byte
@@ -59,6 +60,12 @@ struct PolyState {
   __device__ __forceinline__ void set_len(int64_t i, int32_t len) const { reinterpret_cast<int32_t*>(rec + i)[0] = len; }
   __device__ __forceinline__ int32_t len(int64_t i) const { return reinterpret_cast<const int32_t*>(rec + i)[0]; }
 };
+
+// Staging and arena chunks that one workgroup of the region kernels reserves
+// at a time (the host adds the unused tails to the capacities).
+constexpr int32_t kBigStageChunk64 = 1024, kBigArenaChunk64 = 256;
+constexpr int32_t kBigStageChunk1024 = 8192, kBigArenaChunk1024 = 2048;
+constexpr int kBigGrid64 = 4096, kBigGrid1024 = 128;
 
 __device__ __forceinline__ int32_t he_next(int32_t h) {
   int32_t r = h % 3;

@@ -40,10 +40,11 @@ __global__ void k_reset(Counters* cnt, uint64_t* status, int64_t n_status, const
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t k = i; k < n_status; k += stride) status[k] = 0;
-  if (i == 0) {
+  if (blockIdx.x == 0) {
     int32_t* w = reinterpret_cast<int32_t*>(cnt);
-    for (size_t k = 0; k < sizeof(Counters) / 4; ++k) w[k] = 0;
-    if (n_from) cnt->n_seeds = (uint32_t)(*n_from);
+    for (size_t k = threadIdx.x; k < sizeof(Counters) / 4; k += blockDim.x) w[k] = 0;
+    __syncthreads();
+    if (threadIdx.x == 0 && n_from) cnt->n_seeds = (uint32_t)(*n_from);
   }
 }
 

@@ -201,12 +201,18 @@ int polylla_stats(polylla_ctx *ctx, int64_t *out, int n);
 int polylla_set_param(polylla_ctx *ctx, int param, int64_t value);
 
 /* Per-kernel GPU timing with HIP events, for benchmarks (off by default).
- * polylla_profile(ctx, 1) clears earlier records and records an event pair on
- * the call's stream around every kernel launched by later calls (up to 8192
- * launches); polylla_profile(ctx, 0) stops recording. polylla_profile_read
- * waits for the device and fills, for up to n kernels, the kernel name
- * (NUL-terminated, 32 bytes per entry in `names`), the summed milliseconds and
- * the number of launches; it returns the number of kernels written. */
+ * polylla_profile(ctx, POLYLLA_PROFILE_ALL) clears earlier records and records
+ * an event pair on the launching stream around every kernel launched by later
+ * calls (up to 8192 launches); POLYLLA_PROFILE_WALK does the same for the walk
+ * kernel only (two events per call, so that timing a whole call is barely
+ * disturbed); POLYLLA_PROFILE_OFF stops recording. Other values:
+ * POLYLLA_EINVAL. polylla_profile_read waits for the device and fills, for up
+ * to n kernels, the kernel name (NUL-terminated, 32 bytes per entry in
+ * `names`), the summed milliseconds and the number of launches; it returns the
+ * number of kernels written. */
+#define POLYLLA_PROFILE_OFF 0
+#define POLYLLA_PROFILE_ALL 1
+#define POLYLLA_PROFILE_WALK 2
 int polylla_profile(polylla_ctx *ctx, int enable);
 int polylla_profile_read(polylla_ctx *ctx, char *names, double *ms, int64_t *launches, int n);
 

@@ -80,7 +80,7 @@ struct polylla_ctx {
   hipStream_t side = nullptr;
   hipEvent_t fork = nullptr, join = nullptr;
   // event profiling
-  bool prof = false;
+  int prof = 0;  // POLYLLA_PROFILE_* mode
   std::vector<hipEvent_t> ev_pool;
   struct Rec {
     int kernel;
@@ -118,7 +118,9 @@ struct Prof {
   int id;
   hipEvent_t b = nullptr;
   Prof(polylla_ctx* c_, hipStream_t s_, int id_) : c(c_), s(s_), id(id_) {
-    if (!c->prof || c->recs.size() >= kMaxProfiled || c->ev_pool.size() < 2 * (c->recs.size() + 1)) return;
+    if (!c->prof || (c->prof == POLYLLA_PROFILE_WALK && id != KR_WALK) || c->recs.size() >= kMaxProfiled ||
+        c->ev_pool.size() < 2 * (c->recs.size() + 1))
+      return;
     hipEvent_t a = c->ev_pool[2 * c->recs.size()];
     b = c->ev_pool[2 * c->recs.size() + 1];
     (void)hipEventRecord(a, s);
@@ -558,7 +560,7 @@ int polylla_set_param(polylla_ctx* c, int param, int64_t value) {
 }
 
 int polylla_profile(polylla_ctx* c, int enable) {
-  if (!c) return POLYLLA_EINVAL;
+  if (!c || enable < 0 || enable > POLYLLA_PROFILE_WALK) return POLYLLA_EINVAL;
   if (hipSetDevice(c->device) != hipSuccess) return POLYLLA_EHIP;
   if (enable) {
     (void)hipDeviceSynchronize();
@@ -569,7 +571,7 @@ int polylla_profile(polylla_ctx* c, int enable) {
     }
     c->recs.clear();
   }
-  c->prof = enable != 0;
+  c->prof = enable;
   return POLYLLA_OK;
 }
 

@@ -20,6 +20,7 @@ LONGEST, FRONTIER, TERMINAL, BORDER, BARRIER, REPAIRED = 1, 2, 4, 8, 16, 32
 SEED, TIP = 1, 1
 PARAM_WALK_CAP = 1
 PARAM_WALK_BLOCKS = 2
+PROFILE_OFF, PROFILE_ALL, PROFILE_WALK = 0, 1, 2
 
 
 class PolyllaError(RuntimeError):
@@ -286,9 +287,11 @@ class Context:
     def set_param(self, param: int, value: int):
         _check(load().polylla_set_param(self._h, int(param), int(value)), "polylla_set_param")
 
-    def profile(self, enable: bool):
-        """Start (clearing earlier records) or stop per-kernel event timing."""
-        _check(load().polylla_profile(self._h, 1 if enable else 0), "polylla_profile")
+    def profile(self, enable, walk_only: bool = False):
+        """Start (clearing earlier records) or stop per-kernel event timing;
+        walk_only times the walk kernel alone."""
+        mode = (PROFILE_WALK if walk_only else PROFILE_ALL) if enable else PROFILE_OFF
+        _check(load().polylla_profile(self._h, mode), "polylla_profile")
 
     def profile_read(self) -> dict:
         """{kernel name: (summed ms, launches)} of the recorded launches."""

@@ -74,7 +74,7 @@ struct polylla_ctx {
   uint8_t* vtx_s = nullptr;
   Counters last{};
   int walk_cap = 24;  // vertices a lane walks before handing a polygon to a workgroup
-  int walk_blocks = 640;  // persistent grid of the walk kernel (swept: 256..2048, 640 best at 10M)
+  int walk_blocks = 768;  // persistent grid of the walk kernel: three 49 KB workgroups per CU (swept at 10M)
   // second stream: the workgroup region kernel runs beside the per-lane one
   // (they touch disjoint regions); fork and join through events
   hipStream_t side = nullptr;

@@ -1321,39 +1321,39 @@ __global__ __launch_bounds__(64) void k_general_small(const int32_t* __restrict_
 // Regions beyond the LDS capacity are queued for general_one on one lane.
 
 // Capacities of one instance: KC triangles, LC frontier half-edges (opened
-// ones included), HB hash bits (2^HB = 2 LC hash slots).
+// ones included), HB hash bits (2^HB = 2 LC hash slots). The region is kept
+// as links between local edges (code = 4 slot + local edge), so successors
+// and the repair never go back to global memory. Several arrays change role
+// between phases to fit the 1024-thread instance in 160 KB.
 template <int KC, int LC, int HB>
 struct BigLds {
   static constexpr int kKCap = KC, kLCap = LC, kHBits = HB, kHCap = 1 << HB;
+  static constexpr bool kOrg = KC <= 256;  // small instances keep every local edge's origin
   static_assert(kHCap == 2 * LC, "the hash area is reused for two per-piece arrays");
-  int32_t q[KC];         // BFS queue; then tips (vertex, half-edge); then distances
-  int32_t fh[LC];        // frontier half-edges of the region
-  int32_t hkey[kHCap];   // hash keys; then per-piece smallest vertex / second vertex
-  int32_t hval[LC];      // hash values (int16 per hash slot); then per-piece start slot
-  int16_t nx[LC];        // successor slot; then sorted piece order
-  int16_t jp[LC];        // jump pointers; dead flags; piece list
-  int32_t a[LC];         // twin of each slot; then tip order; then piece id (smallest slot on the cycle)
-  int32_t b[LC];         // vertex id of each slot
-  int32_t kc[LC / 2];    // repair: undecided smaller tips whose opened edge ends at this tip
-  int16_t kf[LC / 2];    // repair: rank of the tip at the far end of this tip's opened edge, or -1
-  uint32_t emask[128];   // repair: end vertices of opened edges, hashed to 4096 bits
+  static_assert(3 * KC >= 2 * LC, "the link area holds the vertex ids of the frontier slots");
+  int32_t q[KC];        // triangle of each region slot | (entry edge + 1) << 30; then distances
+  int32_t fh[LC];       // frontier half-edges of the region
+  int32_t hkey[kHCap];  // hash keys; then tips (vertex, frontier slot / middle edge code); then per-piece arrays
+  int32_t hval[LC];     // hash values (int16 per hash slot); then per-piece start slot
+  int16_t nx[LC];       // successor slot; then sorted piece order
+  int16_t jp[LC];       // jump pointers; dead flags; piece list
+  int32_t a[LC];        // twin of each frontier slot; then (int16) its frontier slot, far vertex of
+                        // each tip's middle edge (upper half); tip order; piece id
+  int32_t kc[LC / 2];   // repair: undecided smaller tips whose opened edge ends at this tip
+  int16_t kf[LC / 2];   // repair: rank of the tip at the far end of this tip's opened edge, or -1
   int32_t sc[20];
-  // Small instances keep the region's links, so that successors and the
-  // repair never go back to global memory: code = 4 slot + local edge.
-  static constexpr bool kLinks = KC <= 256;
-  static constexpr int kLK = kLinks ? KC : 1, kLL = kLinks ? LC : 1;
-  int32_t tri[kLK];      // triangle of each region slot
-  int32_t org[3 * kLK];  // origin of each local edge
-  int16_t lnk[3 * kLK];  // internal edge: code of its twin; frontier edge: -1 - its frontier slot
-  int16_t fcode[kLL];    // code of each frontier slot
-  int16_t tslot[kLL];    // frontier slot of the twin (barrier edges), else -1
+  int16_t lnk[3 * KC];  // internal edge: code of its twin; frontier edge: -1 - its frontier slot;
+                        // after the repair: vertex id of each frontier slot (int32)
+  int16_t fcode[LC];    // code of each frontier slot
+  int32_t org[kOrg ? 3 * KC : 1];  // origin of each local edge (small instances)
 };
 
 enum {
-  SC_QLEN, SC_LO, SC_HI, SC_NFH, SC_NTIP, SC_OVER, SC_BAD, SC_NSPLIT, SC_NP, SC_ITEM, SC_SBASE, SC_NEND, SC_RB,
+  SC_QLEN, SC_LO, SC_HI, SC_NFH, SC_NTIP, SC_OVER, SC_BAD, SC_NSPLIT, SC_NP, SC_ITEM, SC_SBASE, SC_RB,
   SC_PEND,  // two slots, used alternately
   SC_SNEXT = SC_PEND + 2, SC_SLEFT, SC_ANEXT, SC_ALEFT  // the workgroup's staging and arena chunks
 };
+constexpr uint32_t kSlotTri = 0x3FFFFFFFu;  // triangle bits of q[slot]
 
 template <int HB>
 __device__ __forceinline__ int hash_slot(int32_t key) {
@@ -1381,85 +1381,12 @@ __device__ __forceinline__ int32_t hash_find(const LDS& S, const int16_t* hv, in
   constexpr int kHCap = LDS::kHCap;
   int s = hash_slot<LDS::kHBits>(key);
   for (int k = 0; k < kHCap; ++k) {
-    int32_t kk = S.hkey[s];
+    const int32_t kk = S.hkey[s];
     if (kk == key) return hv[s];
     if (kk == -1) return -1;
     s = (s + 1) & (kHCap - 1);
   }
   return -1;
-}
-
-// Successor of frontier half-edge h (global labels), or -1 on invalid input.
-__device__ __forceinline__ int32_t next_frontier(int32_t h, int32_t nhe, const int32_t* __restrict__ twin,
-                                                 const uint8_t* __restrict__ he) {
-  int32_t c = he_next(h);
-  for (int32_t steps = 0; steps <= nhe; ++steps) {
-    if (he[c] & kFrontier) return c;
-    const int32_t tw = twin[c];
-    if ((uint32_t)tw >= (uint32_t)nhe) return -1;
-    c = he_next(tw);
-  }
-  return -1;
-}
-
-constexpr int32_t kNoChange = -2;
-
-// Successor (next frontier half-edge) of this thread's slots k = tid + u *
-// kBigThreads < L, the chains of all its slots advanced together so that their
-// loads overlap. With `ends` given, a slot below `first_new` is only
-// recomputed when the end vertex of its half-edge is in ends[0..ne); other
-// slots get kNoChange. -1 marks an invalid mesh.
-template <int NT, class LDS, int kPer = LDS::kLCap / NT>
-__device__ __forceinline__ void successors(const LDS& S, int L, int first_new, const int32_t* ends, int ne,
-                                           int32_t (&succ)[kPer], int32_t nhe, const int32_t* __restrict__ twin,
-                                           const uint8_t* __restrict__ he) {
-  constexpr int kBigThreads = NT;
-  // ends are also hashed into S.emask (vertex & 4095): most slots are decided by one bit
-  const int tid = threadIdx.x;
-  bool act[kPer];
-#pragma unroll
-  for (int u = 0; u < kPer; ++u) {
-    const int k = tid + u * kBigThreads;
-    act[u] = k < L;
-    if (act[u] && ends && k < first_new) {
-      const int32_t head = S.b[S.nx[k]];
-      bool hit = (S.emask[(head & 4095) >> 5] >> (head & 31)) & 1u;
-      if (hit) {
-        hit = false;
-        for (int e = 0; e < ne; ++e) hit |= ends[e] == head;
-      }
-      act[u] = hit;
-    }
-    succ[u] = act[u] ? he_next(S.fh[k]) : kNoChange;
-  }
-  for (int32_t it = 0; it <= nhe; ++it) {
-    uint8_t lab[kPer];
-    int32_t tw[kPer];
-#pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-      const int32_t c = act[u] ? succ[u] : 0;
-      lab[u] = he[c];
-      tw[u] = twin[c];
-    }
-    bool any = false;
-#pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-      if (!act[u]) continue;
-      if (lab[u] & kFrontier) {
-        act[u] = false;
-      } else if ((uint32_t)tw[u] >= (uint32_t)nhe) {
-        act[u] = false;
-        succ[u] = -1;
-      } else {
-        succ[u] = he_next(tw[u]);
-        any = true;
-      }
-    }
-    if (!any) break;
-  }
-#pragma unroll
-  for (int u = 0; u < kPer; ++u)
-    if (act[u]) succ[u] = -1;  // walk bound exceeded
 }
 
 // Successor slot of every frontier slot from the region links (LDS only);
@@ -1489,16 +1416,29 @@ __device__ __forceinline__ void successors_links(LDS& S, int L) {
 
 // One step of a turn about a vertex inside the region: cross the edge of code
 // x to its twin and take the twin's next local edge; -1 if the twin is not in
-// the region.
+// the region. ts: frontier slot of the twin of each frontier slot, or -1.
 template <class LDS>
-__device__ __forceinline__ int turn_links(const LDS& S, int x) {
+__device__ __forceinline__ int turn_links(const LDS& S, const int16_t* ts, int x) {
   int y = S.lnk[3 * (x >> 2) + (x & 3)];
   if (y < 0) {
-    const int f2 = S.tslot[-1 - y];
+    const int f2 = ts[-1 - y];
     if (f2 < 0) return -1;
     y = S.fcode[f2];
   }
   return (y & ~3) | next_local(y & 3);
+}
+
+// Global half-edge of a local edge code.
+template <class LDS>
+__device__ __forceinline__ int32_t code_gid(const LDS& S, int c) {
+  return 3 * (int32_t)((uint32_t)S.q[c >> 2] & kSlotTri) + (c & 3);
+}
+
+// Origin of a local edge code: from LDS in small instances, else one load.
+template <class LDS>
+__device__ __forceinline__ int32_t code_origin(const LDS& S, const int32_t* __restrict__ origin, int c) {
+  if constexpr (LDS::kOrg) return S.org[3 * (c >> 2) + (c & 3)];
+  else return origin[code_gid(S, c)];
 }
 
 // Queue a polygon for the next, larger instance (bounded: the queues are sized
@@ -1529,9 +1469,11 @@ __global__ __launch_bounds__(NT) void k_general_big(
     uint32_t few_max, Counters* cnt) {
   constexpr int kBigThreads = NT, kKCap = KC, kLCap = LC, kHCap = 1 << HB, kPer = LC / NT;
   static_assert(LC % NT == 0 && kPer >= 1, "slots per thread");
+  static_assert(KC < (1 << 13) && LC < (1 << 14), "codes and slots are int16");
   __shared__ BigLds<KC, LC, HB> S;
-  constexpr bool LINKS = BigLds<KC, LC, HB>::kLinks;
   int16_t* hv = reinterpret_cast<int16_t*>(S.hval);  // hash values: int16 per hash slot (kHCap of them)
+  int16_t* tslot = reinterpret_cast<int16_t*>(S.a);  // (after the successor pass)
+  int32_t* bv = reinterpret_cast<int32_t*>(S.lnk);   // (after the repair)
   const int tid = threadIdx.x;
   // one-wave instances take polygons round-robin (no shared work counter);
   // staging and arena space is reserved in chunks per workgroup
@@ -1567,10 +1509,11 @@ __global__ __launch_bounds__(NT) void k_general_big(
     const int32_t i = in_rev ? in[in_cap - 1 - item] : in[item];
     const int32_t li = list[i];
     const int32_t t0 = from_seeds ? li : li / 3;
-    // ---- 1. breadth-first search of the region
+    // ---- 1. breadth-first search of the region's dual tree: slots, links,
+    // frontier slots (half-edge, twin, code) and the hash half-edge -> slot
     for (int k = tid; k < kHCap; k += kBigThreads) S.hkey[k] = -1;
     if (tid == 0) {
-      S.q[0] = -1 - 3 * t0;
+      S.q[0] = t0;  // entry edge: none
       S.sc[SC_QLEN] = 1;
       S.sc[SC_LO] = 0;
       S.sc[SC_HI] = 1;
@@ -1586,31 +1529,27 @@ __global__ __launch_bounds__(NT) void k_general_big(
       const int lo = S.sc[SC_LO], hi = S.sc[SC_HI];
       if (lo >= hi || S.sc[SC_OVER]) break;
       for (int j = lo + tid; j < hi; j += kBigThreads) {
-        const int32_t code = S.q[j];
-        const int32_t t = code < 0 ? (-1 - code) / 3 : code / 3;
-        const int32_t entry = code < 0 ? -1 : code;
+        const uint32_t qj = (uint32_t)S.q[j];
+        const int32_t t = (int32_t)(qj & kSlotTri);
+        const int entry = (int)(qj >> 30) - 1;
         // label word, twin and origin triples of the triangle: one round trip
         const Int3 tw3 = *reinterpret_cast<const Int3*>(twin + 3 * t);
         const Int3 or3 = *reinterpret_cast<const Int3*>(origin + 3 * t);
         const uint32_t lw = lab4[t];
-        if constexpr (LINKS) S.tri[j] = t;
 #pragma unroll
         for (int e = 0; e < 3; ++e) {
           const int32_t h = 3 * t + e;
-          if constexpr (LINKS) S.org[3 * j + e] = sel3(or3.x, or3.y, or3.z, e);
-          if (h == entry) continue;  // (its link was set by the parent)
+          if constexpr (BigLds<KC, LC, HB>::kOrg) S.org[3 * j + e] = sel3(or3.x, or3.y, or3.z, e);
+          if (e == entry) continue;  // (its link was set by the parent)
           const int32_t tw = sel3(tw3.x, tw3.y, tw3.z, e);
           if ((lw >> (8 * e)) & kFrontier) {
             const int idx = atomicAdd(&S.sc[SC_NFH], 1);
             if (idx < kLCap) {
               S.fh[idx] = h;
-              S.b[idx] = sel3(or3.x, or3.y, or3.z, e);
               S.a[idx] = tw;
+              S.fcode[idx] = (int16_t)(4 * j + e);
+              S.lnk[3 * j + e] = (int16_t)(-1 - idx);
               hash_insert(S, hv, h, idx);
-              if constexpr (LINKS) {
-                S.fcode[idx] = (int16_t)(4 * j + e);
-                S.lnk[3 * j + e] = (int16_t)(-1 - idx);
-              }
             } else {
               S.sc[SC_OVER] = 1;
             }
@@ -1621,12 +1560,11 @@ __global__ __launch_bounds__(NT) void k_general_big(
             }
             const int pos = atomicAdd(&S.sc[SC_QLEN], 1);
             if (pos < kKCap) {
-              S.q[pos] = tw;
-              if constexpr (LINKS) {
-                const int e2 = tw - 3 * (tw / 3);
-                S.lnk[3 * j + e] = (int16_t)(4 * pos + e2);
-                S.lnk[3 * pos + e2] = (int16_t)(4 * j + e);
-              }
+              const int32_t t2 = tw / 3;
+              const int e2 = tw - 3 * t2;
+              S.q[pos] = (int32_t)((uint32_t)t2 | ((uint32_t)(e2 + 1) << 30));
+              S.lnk[3 * j + e] = (int16_t)(4 * pos + e2);
+              S.lnk[3 * pos + e2] = (int16_t)(4 * j + e);
             } else {
               S.sc[SC_OVER] = 1;
             }
@@ -1654,46 +1592,36 @@ __global__ __launch_bounds__(NT) void k_general_big(
       continue;
     }
     int L = S.sc[SC_NFH];
-    // ---- 2. successors, tips, barrier edges, vertex ids
-    int32_t succ[kPer];
-    if constexpr (LINKS) {
-      // tips keep the frontier slot of their barrier half-edge
-      successors_links<NT>(S, L);
-      __syncthreads();
-      for (int k = tid; k < L; k += kBigThreads) {
-        const int j = S.nx[k];
-        const int32_t tw = S.a[k];
-        const int32_t ts = (uint32_t)tw < (uint32_t)nhe ? hash_find(S, hv, tw) : -1;
-        S.tslot[k] = (int16_t)ts;
-        if (S.fh[j] == tw && j != k) {
-          const int p = atomicAdd(&S.sc[SC_NTIP], 1);
-          S.q[2 * p] = S.b[j];
-          S.q[2 * p + 1] = j;
-        }
-        if (ts >= 0) or_bits(he, S.fh[k], kBarrier);
-      }
-    } else {
-      successors<NT>(S, L, 0, nullptr, 0, succ, nhe, twin, he);
+    // ---- 2. successors, barrier edges (twin also a frontier slot), tips
+    // (successor = twin)
+    successors_links<NT>(S, L);
+    __syncthreads();
+    int16_t tsr[kPer];
+    bool tip[kPer];
 #pragma unroll
-      for (int u = 0; u < kPer; ++u) {
-        const int k = tid + u * kBigThreads;
-        if (k >= L) continue;
-        const int32_t h = S.fh[k];
-        const int32_t c = succ[u];
-        const int32_t j = c < 0 ? -1 : hash_find(S, hv, c);
-        if (j < 0) {
-          S.sc[SC_BAD] = 1;
-          S.nx[k] = (int16_t)k;
-        } else {
-          S.nx[k] = (int16_t)j;
-        }
-        const int32_t tw = S.a[k];
-        if (c >= 0 && c == tw && j >= 0) {
-          const int p = atomicAdd(&S.sc[SC_NTIP], 1);
-          S.q[2 * p] = S.b[j];
-          S.q[2 * p + 1] = c;
-        }
-        if ((uint32_t)tw < (uint32_t)nhe && hash_find(S, hv, tw) >= 0) or_bits(he, h, kBarrier);
+    for (int u = 0; u < kPer; ++u) {
+      const int k = tid + u * kBigThreads;
+      tsr[u] = -1;
+      tip[u] = false;
+      if (k >= L) continue;
+      const int j = S.nx[k];
+      const int32_t tw = S.a[k];
+      const int32_t ts = (uint32_t)tw < (uint32_t)nhe ? hash_find(S, hv, tw) : -1;
+      tsr[u] = (int16_t)ts;
+      tip[u] = S.fh[j] == tw && j != k;
+      if (ts >= 0) or_bits(he, S.fh[k], kBarrier);
+    }
+    __syncthreads();  // the hash and the twins are done with
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int k = tid + u * kBigThreads;
+      if (k >= L) continue;
+      tslot[k] = tsr[u];
+      if (tip[u]) {  // tip list (vertex, frontier slot of the barrier half-edge leaving it)
+        const int j = S.nx[k];
+        const int p = atomicAdd(&S.sc[SC_NTIP], 1);
+        S.hkey[2 * p] = code_origin(S, origin, S.fcode[j]);
+        S.hkey[2 * p + 1] = j;
       }
     }
     __syncthreads();
@@ -1707,59 +1635,37 @@ __global__ __launch_bounds__(NT) void k_general_big(
     }
     const int ntip = S.sc[SC_NTIP];
     for (int p = tid; p < ntip; p += kBigThreads) {
-      const int32_t v = S.q[2 * p];
+      const int32_t v = S.hkey[2 * p];
       if ((uint64_t)(uint32_t)v < (uint64_t)nv) or_bits(vtx, v, kTip);
     }
     if (tid == 0 && ntip) atomicAdd(&cnt->n_tips, (uint32_t)ntip);
     // ---- 3. repair
     if (REPAIR && ntip > 0) {
-      // middle internal edge at every tip; its far vertex goes to a[2048 + p]
+      // middle internal edge c_{floor(d/2)} of every tip's fan (which lies in
+      // the region), turning from the barrier half-edge; its far vertex goes
+      // to a[LC/2 + p]
       for (int p = tid; p < ntip; p += kBigThreads) {
-        if constexpr (LINKS) {
-          // the fan of the tip lies in the region: turn about it in LDS
-          const int x0 = S.fcode[S.q[2 * p + 1]];
-          int d = 0, x = x0;
-          do {
-            x = turn_links(S, x);
-            ++d;
-          } while (x >= 0 && x != x0 && d <= 3 * kKCap);
-          if (x != x0) {
-            S.sc[SC_BAD] = 1;
-            d = 0;
-          }
-          int ec = x0;
-          for (int k = 0; k < d / 2; ++k) ec = turn_links(S, ec);
-          S.q[2 * p + 1] = ec;  // a code from here on
-          S.a[kLCap / 2 + p] = S.org[3 * (ec >> 2) + next_local(ec & 3)];
-        } else {
-          const int32_t c0 = S.q[2 * p + 1];
-          int32_t d = 0, c = c0;
-          bool okr = true;
-          do {
-            const int32_t tw = twin[c];
-            if ((uint32_t)tw >= (uint32_t)nhe) {
-              okr = false;
-              break;
-            }
-            c = he_next(tw);
-            ++d;
-          } while (c != c0 && d <= nhe);
-          if (!okr || c != c0) {
-            S.sc[SC_BAD] = 1;
-            d = 0;
-          }
-          int32_t e = c0;
-          for (int32_t k = 0; k < d / 2; ++k) e = he_next(twin[e]);
-          S.q[2 * p + 1] = e;
-          S.a[kLCap / 2 + p] = origin[he_next(e)];
+        const int x0 = S.fcode[S.hkey[2 * p + 1]];
+        int d = 0, x = x0;
+        do {
+          x = turn_links(S, tslot, x);
+          ++d;
+        } while (x >= 0 && x != x0 && d <= 3 * kKCap);
+        if (x != x0) {
+          S.sc[SC_BAD] = 1;
+          d = 0;
         }
+        int ec = x0;
+        for (int k = 0; k < d / 2; ++k) ec = turn_links(S, tslot, ec);
+        S.hkey[2 * p + 1] = ec;  // a code from here on
+        S.a[kLCap / 2 + p] = code_origin(S, origin, (ec & ~3) | next_local(ec & 3));
       }
       __syncthreads();
       // tips ranked by vertex id (ids are distinct): a[rank] = tip
       for (int p = tid; p < ntip; p += kBigThreads) {
-        const int32_t v = S.q[2 * p];
+        const int32_t v = S.hkey[2 * p];
         int r = 0;
-        for (int p2 = 0; p2 < ntip; ++p2) r += S.q[2 * p2] < v;
+        for (int p2 = 0; p2 < ntip; ++p2) r += S.hkey[2 * p2] < v;
         S.a[r] = p;
       }
       __syncthreads();
@@ -1772,12 +1678,10 @@ __global__ __launch_bounds__(NT) void k_general_big(
         S.kc[r] = 0;
         S.jp[r] = 0;
       }
-      for (int w = tid; w < 128; w += kBigThreads) S.emask[w] = 0;
       if (tid == 0) {
         S.sc[SC_PEND] = 0;
         S.sc[SC_PEND + 1] = 0;
         S.sc[SC_NSPLIT] = 0;
-        S.sc[SC_NEND] = 0;
       }
       __syncthreads();
       for (int r = tid; r < ntip; r += kBigThreads) {
@@ -1785,10 +1689,10 @@ __global__ __launch_bounds__(NT) void k_general_big(
         int lo = r + 1, hi = ntip;
         while (lo < hi) {
           const int mid = (lo + hi) >> 1;
-          if (S.q[2 * S.a[mid]] < x) lo = mid + 1;
+          if (S.hkey[2 * S.a[mid]] < x) lo = mid + 1;
           else hi = mid;
         }
-        const int f = (lo < ntip && S.q[2 * S.a[lo]] == x) ? lo : -1;
+        const int f = (lo < ntip && S.hkey[2 * S.a[lo]] == x) ? lo : -1;
         S.kf[r] = (int16_t)f;
         if (f >= 0) atomicAdd(&S.kc[f], 1);
       }
@@ -1818,28 +1722,13 @@ __global__ __launch_bounds__(NT) void k_general_big(
         if (!S.sc[par]) break;
       }
       // jp[r] = 1 marks a dead tip from here on; live tips count the splits
-      // and list the end vertices of their opened edges (q[2 * ntip ...])
-      const bool ends_fit = 4 * ntip <= kKCap;
       for (int r = tid; r < ntip; r += kBigThreads) {
         const bool dead = S.jp[r] == 4;
         S.jp[r] = dead ? 1 : 0;
-        if (dead) continue;
-        atomicAdd(&S.sc[SC_NSPLIT], 1);
-        if (ends_fit) {
-          const int p = S.a[r];
-          const int32_t v0 = S.q[2 * p], v1 = S.a[kLCap / 2 + p];
-          const int pos = atomicAdd(&S.sc[SC_NEND], 2);
-          S.q[2 * ntip + pos] = v0;
-          S.q[2 * ntip + pos + 1] = v1;
-          atomicOr(&S.emask[(v0 & 4095) >> 5], 1u << (v0 & 31));
-          atomicOr(&S.emask[(v1 & 4095) >> 5], 1u << (v1 & 31));
-        }
+        if (!dead) atomicAdd(&S.sc[SC_NSPLIT], 1);
       }
       __syncthreads();
-      if (tid == 0) {
-        if (!ends_fit) S.sc[SC_NEND] = -1;  // too many: recompute every successor
-        if (L + 2 * S.sc[SC_NSPLIT] > kLCap) S.sc[SC_OVER] = 1;
-      }
+      if (tid == 0 && L + 2 * S.sc[SC_NSPLIT] > kLCap) S.sc[SC_OVER] = 1;
       __syncthreads();
       if (S.sc[SC_BAD]) {
         if (tid == 0) {
@@ -1854,63 +1743,32 @@ __global__ __launch_bounds__(NT) void k_general_big(
         __syncthreads();
         continue;
       }
-      // open the edges of the live tips and add both half-edges
+      // open the middle edges of the live tips: both half-edges become
+      // frontier slots
       for (int r = tid; r < ntip; r += kBigThreads) {
         if (S.jp[r]) continue;
-        if constexpr (LINKS) {
-          const int ec = S.q[2 * S.a[r] + 1];
-          const int tc = S.lnk[3 * (ec >> 2) + (ec & 3)];
-          if (tc < 0) {  // the middle edge must be internal
-            S.sc[SC_BAD] = 1;
-            continue;
-          }
-          const int32_t ge = 3 * S.tri[ec >> 2] + (ec & 3), gt = 3 * S.tri[tc >> 2] + (tc & 3);
-          or_bits(he, ge, kFrontier | kRepaired);
-          or_bits(he, gt, kFrontier | kRepaired);
-          const int idx = atomicAdd(&S.sc[SC_NFH], 2);
-          S.fh[idx] = ge;
-          S.fh[idx + 1] = gt;
-          S.b[idx] = S.org[3 * (ec >> 2) + (ec & 3)];
-          S.b[idx + 1] = S.org[3 * (tc >> 2) + (tc & 3)];
-          S.fcode[idx] = (int16_t)ec;
-          S.fcode[idx + 1] = (int16_t)tc;
-          S.lnk[3 * (ec >> 2) + (ec & 3)] = (int16_t)(-1 - idx);
-          S.lnk[3 * (tc >> 2) + (tc & 3)] = (int16_t)(-2 - idx);
-        } else {
-          const int32_t e = S.q[2 * S.a[r] + 1];
-          const int32_t te = twin[e];
-          he[e] |= kFrontier | kRepaired;  // read back by the successor pass
-          he[te] |= kFrontier | kRepaired;
-          const int idx = atomicAdd(&S.sc[SC_NFH], 2);
-          S.fh[idx] = e;
-          S.fh[idx + 1] = te;
-          S.b[idx] = origin[e];
-          S.b[idx + 1] = origin[te];
-          hash_insert(S, hv, e, idx);
-          hash_insert(S, hv, te, idx + 1);
+        const int ec = S.hkey[2 * S.a[r] + 1];
+        const int tc = S.lnk[3 * (ec >> 2) + (ec & 3)];
+        if (tc < 0) {  // the middle edge must be internal
+          S.sc[SC_BAD] = 1;
+          continue;
         }
+        const int32_t ge = code_gid(S, ec), gt = code_gid(S, tc);
+        or_bits(he, ge, kFrontier | kRepaired);
+        or_bits(he, gt, kFrontier | kRepaired);
+        const int idx = atomicAdd(&S.sc[SC_NFH], 2);
+        S.fh[idx] = ge;
+        S.fh[idx + 1] = gt;
+        S.fcode[idx] = (int16_t)ec;
+        S.fcode[idx + 1] = (int16_t)tc;
+        S.lnk[3 * (ec >> 2) + (ec & 3)] = (int16_t)(-1 - idx);
+        S.lnk[3 * (tc >> 2) + (tc & 3)] = (int16_t)(-2 - idx);
       }
       __syncthreads();
       if (tid == 0 && S.sc[SC_NSPLIT]) atomicAdd(&cnt->n_splits, (uint32_t)S.sc[SC_NSPLIT]);
-      const int L0 = L;
       L = S.sc[SC_NFH];
       if (S.sc[SC_NSPLIT]) {
-        if constexpr (LINKS) {
-          successors_links<NT>(S, L);
-        } else {
-          const int ne = S.sc[SC_NEND];
-          successors<NT>(S, L, L0, ne >= 0 ? S.q + 2 * ntip : nullptr, ne, succ, nhe, twin, he);
-          __syncthreads();
-#pragma unroll
-          for (int u = 0; u < kPer; ++u) {
-            const int k = tid + u * kBigThreads;
-            if (k >= L || succ[u] == kNoChange) continue;
-            const int32_t c = succ[u];
-            const int32_t j = c < 0 ? -1 : hash_find(S, hv, c);
-            S.nx[k] = (int16_t)(j < 0 ? k : j);
-            if (j < 0) S.sc[SC_BAD] = 1;
-          }
-        }
+        successors_links<NT>(S, L);
         __syncthreads();
       }
       if (S.sc[SC_BAD]) {
@@ -1922,6 +1780,21 @@ __global__ __launch_bounds__(NT) void k_general_big(
         continue;
       }
     }
+    // vertex id of every frontier slot, into the link area (the links are
+    // done with)
+    int32_t vreg[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int k = tid + u * kBigThreads;
+      vreg[u] = k < L ? code_origin(S, origin, S.fcode[k]) : 0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int k = tid + u * kBigThreads;
+      if (k < L) bv[k] = vreg[u];
+    }
+    __syncthreads();
     // ---- 4. pieces = cycles of nx. piece id: smallest slot on the cycle
     for (int k = tid; k < L; k += kBigThreads) {
       S.a[k] = k;
@@ -1962,11 +1835,11 @@ __global__ __launch_bounds__(NT) void k_general_big(
       pstart[k] = 0x7FFFFFFF;
     }
     __syncthreads();
-    for (int k = tid; k < L; k += kBigThreads) atomicMin(&pmin[S.a[k]], S.b[k]);
+    for (int k = tid; k < L; k += kBigThreads) atomicMin(&pmin[S.a[k]], bv[k]);
     __syncthreads();
     for (int k = tid; k < L; k += kBigThreads) {
       const int p = S.a[k];
-      if (S.b[k] == pmin[p]) {
+      if (bv[k] == pmin[p]) {
         atomicAdd(&pcnt[p], 1);
         atomicMin(&pstart[p], k);
       }
@@ -1980,11 +1853,11 @@ __global__ __launch_bounds__(NT) void k_general_big(
       int len = 1;
       for (int k = S.nx[best]; k != best && len <= L; k = S.nx[k]) ++len;
       for (int k = S.nx[best], m = 1; m < len; k = S.nx[k], ++m) {
-        if (S.b[k] != pmin[p]) continue;
+        if (bv[k] != pmin[p]) continue;
         int x = k, y = best;
         for (int z = 0; z < len; ++z) {
-          if (S.b[x] != S.b[y]) {
-            if (S.b[x] < S.b[y]) best = k;
+          if (bv[x] != bv[y]) {
+            if (bv[x] < bv[y]) best = k;
             break;
           }
           x = S.nx[x];
@@ -2035,7 +1908,7 @@ __global__ __launch_bounds__(NT) void k_general_big(
       if (S.a[k] != k) continue;
       const int idx = atomicAdd(&S.sc[SC_NP], 1);
       S.jp[idx] = (int16_t)k;
-      pcnt[k] = S.b[S.nx[pstart[k]]];
+      pcnt[k] = bv[S.nx[pstart[k]]];
     }
     __syncthreads();
     const int np = S.sc[SC_NP];
@@ -2129,7 +2002,7 @@ __global__ __launch_bounds__(NT) void k_general_big(
       for (int k = tid; k < L; k += kBigThreads) {
         const int p = S.a[k];
         const int32_t len = S.q[pstart[p]] + 1;
-        stage[sb + pcnt[p] + (len - 1 - S.q[k])] = S.b[k];
+        stage[sb + pcnt[p] + (len - 1 - S.q[k])] = bv[k];
       }
     } else if (tid == 0) {
       ps.clear(i);

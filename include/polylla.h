@@ -199,6 +199,11 @@ int polylla_stats(polylla_ctx *ctx, int64_t *out, int n);
  * XCD's L2, more hide more latency. Default 768 (three per compute unit, all
  * resident at once: a larger grid only adds workgroups that find no work). */
 #define POLYLLA_PARAM_WALK_BLOCKS 2
+/* POLYLLA_PARAM_GEN_WAVE_MAX (0..2^32-2, default 8192): the short polygons
+ * with a repeated vertex that the single-tip path declines are repaired one
+ * wave per polygon when there are at most this many (lowest latency), else
+ * one lane per polygon (highest throughput). */
+#define POLYLLA_PARAM_GEN_WAVE_MAX 3
 int polylla_set_param(polylla_ctx *ctx, int param, int64_t value);
 
 /* Per-kernel GPU timing with HIP events, for benchmarks (off by default).

@@ -24,7 +24,7 @@ __global__ void k_walk(const int32_t*, int32_t, const int32_t*, const int32_t*, 
 template <bool REPAIR>
 __global__ void k_general_small(const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*,
                                 const uint32_t*, uint8_t*, uint8_t*, int32_t*, int64_t, int32_t*, int64_t, PolyState,
-                                const int32_t*, const uint32_t*, Counters*);
+                                const int32_t*, const uint32_t*, uint32_t, Counters*);
 template <bool REPAIR>
 __global__ void k_tip(int32_t, int64_t, const int32_t*, const int32_t*, uint8_t*, uint8_t*, int32_t*, int64_t,
                       int32_t*, int64_t, PolyState, const int32_t*, int32_t*, int64_t, Counters*);
@@ -32,7 +32,7 @@ template <bool REPAIR, int NT, int KC, int LC, int HB>
 __global__ void k_general_big(const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*, const uint32_t*,
                               uint8_t*, uint8_t*, int32_t*, int64_t, int32_t*, int64_t, PolyState, const int32_t*,
                               bool, int64_t, const uint32_t*, uint32_t*, int32_t*, int64_t, uint32_t*,
-                              const int32_t*, int64_t, const uint32_t*, uint32_t, Counters*);
+                              const int32_t*, int64_t, const uint32_t*, uint32_t, uint32_t, Counters*);
 template <bool REPAIR>
 __global__ void k_general_huge(const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*, uint8_t*,
                                uint8_t*, int32_t*, int64_t, int32_t*, int64_t, PolyState, const int32_t*,
@@ -47,6 +47,9 @@ __global__ void k_batch_offsets(int64_t, const int64_t*, const int32_t*, const i
 }  // namespace polylla
 
 using namespace polylla;
+
+// default number of declined short polygons up to which each gets a wave
+constexpr uint32_t kGenWaveMax = 2 * polylla::kBigGrid64;
 
 struct polylla_ctx {
   int device = 0;
@@ -74,6 +77,7 @@ struct polylla_ctx {
   uint8_t* vtx_s = nullptr;
   Counters last{};
   int walk_cap = 24;  // vertices a lane walks before handing a polygon to a workgroup
+  uint32_t gen_wave_max = kGenWaveMax;  // declined short polygons up to which each gets a wave
   int walk_blocks = 768;  // persistent grid of the walk kernel: three 49 KB workgroups per CU (swept at 10M)
   // second stream: the workgroup region kernel runs beside the per-lane one
   // (they touch disjoint regions); fork and join through events
@@ -104,12 +108,12 @@ constexpr int64_t kBigArenaTails = 2 * (int64_t)kBigGrid64 * kBigArenaChunk64 + 
 
 enum KernelId {
   KR_RESET, KR_LONGEST, KR_LABEL, KR_COMPACT, KR_PACK, KR_WALK, KR_GENERAL, KR_BIG, KR_HUGE, KR_SCAN, KR_VALIDATE,
-  KR_BATCH, KR_BIGW, KR_TIP, KR_SEEDS, KR_N
+  KR_BATCH, KR_BIGW, KR_TIP, KR_SEEDS, KR_GENW, KR_N
 };
 const char* kKernelNames[KR_N] = {"k_reset",         "k_longest",       "k_label",          "k_compact_seeds",
                                   "k_pack_labels",   "k_walk",          "k_general_small",  "k_general_big",
                                   "k_general_huge",  "k_scan_emit",     "k_validate",       "k_batch_offsets",
-                                  "k_general_big_wg", "k_tip",           "k_seeds"};
+                                  "k_general_big_wg", "k_tip",           "k_seeds",          "k_general_wave"};
 
 // Event pair around one kernel launch when profiling is on.
 struct Prof {
@@ -297,12 +301,12 @@ int run_build(polylla_ctx* c, const polylla_tri* t, const int32_t* list, bool fr
       hipLaunchKernelGGL((k_general_big<true, 64, 128, 128, 8>), dim3(gm), dim3(64), 0, c->side, list, from_seeds, nhe,
                          t->n_vertices, t->twin, t->origin, c->lab4, he, vtx, c->stage, c->stage_cap, c->arena,
                          c->arena_cap, ps, c->deferred, true, c->cap_t, &k->n_big, &k->big_ticket, c->over,
-                         c->over_cap, &k->n_over, nullptr, (int64_t)0, &k->n_big, few, k);
+                         c->over_cap, &k->n_over, nullptr, (int64_t)0, &k->n_big, few, UINT32_MAX, k);
     else
       hipLaunchKernelGGL((k_general_big<false, 64, 128, 128, 8>), dim3(gm), dim3(64), 0, c->side, list, from_seeds,
                          nhe, t->n_vertices, t->twin, t->origin, c->lab4, he, vtx, c->stage, c->stage_cap, c->arena,
                          c->arena_cap, ps, c->deferred, true, c->cap_t, &k->n_big, &k->big_ticket, c->over,
-                         c->over_cap, &k->n_over, nullptr, (int64_t)0, &k->n_big, few, k);
+                         c->over_cap, &k->n_over, nullptr, (int64_t)0, &k->n_big, few, UINT32_MAX, k);
   }
   {
     Prof p(c, c->side, KR_BIGW);
@@ -312,12 +316,12 @@ int run_build(polylla_ctx* c, const polylla_tri* t, const int32_t* list, bool fr
       hipLaunchKernelGGL((k_general_big<true, 1024, 4096, 4096, 13>), dim3(gb), dim3(1024), 0, c->side, list,
                          from_seeds, nhe, t->n_vertices, t->twin, t->origin, c->lab4, he, vtx, c->stage, c->stage_cap,
                          c->arena, c->arena_cap, ps, c->over, false, (int64_t)0, &k->n_over, &k->over_ticket, c->huge,
-                         c->huge_cap, &k->n_fallback, c->deferred, c->cap_t, &k->n_big, few, k);
+                         c->huge_cap, &k->n_fallback, c->deferred, c->cap_t, &k->n_big, few, UINT32_MAX, k);
     else
       hipLaunchKernelGGL((k_general_big<false, 1024, 4096, 4096, 13>), dim3(gb), dim3(1024), 0, c->side, list,
                          from_seeds, nhe, t->n_vertices, t->twin, t->origin, c->lab4, he, vtx, c->stage, c->stage_cap,
                          c->arena, c->arena_cap, ps, c->over, false, (int64_t)0, &k->n_over, &k->over_ticket, c->huge,
-                         c->huge_cap, &k->n_fallback, c->deferred, c->cap_t, &k->n_big, few, k);
+                         c->huge_cap, &k->n_fallback, c->deferred, c->cap_t, &k->n_big, few, UINT32_MAX, k);
   }
   if (hipEventRecord(c->join, c->side) != hipSuccess) return POLYLLA_EHIP;
   {
@@ -332,17 +336,34 @@ int run_build(polylla_ctx* c, const polylla_tri* t, const int32_t* list, bool fr
                          c->stage, c->stage_cap, c->arena, c->arena_cap, ps, c->deferred, c->rest, c->rest_cap,
                          c->cnt);
   }
+  // short polygons the tip path declines: up to gen_wave_max of them one wave
+  // each (latency), more one lane each (throughput); each kernel reads the
+  // count and the one not meant for it returns at once
+  {
+    Prof p(c, s, KR_GENW);
+    Counters* k = c->cnt;
+    if (repair)
+      hipLaunchKernelGGL((k_general_big<true, 64, 128, 128, 8>), dim3(kBigGrid64), dim3(64), 0, s, list, from_seeds,
+                         nhe, t->n_vertices, t->twin, t->origin, c->lab4, he, vtx, c->stage, c->stage_cap, c->arena,
+                         c->arena_cap, ps, c->rest, false, (int64_t)0, &k->n_gen, nullptr, c->huge, c->huge_cap,
+                         &k->n_fallback, nullptr, (int64_t)0, nullptr, 0u, c->gen_wave_max, k);
+    else
+      hipLaunchKernelGGL((k_general_big<false, 64, 128, 128, 8>), dim3(kBigGrid64), dim3(64), 0, s, list, from_seeds,
+                         nhe, t->n_vertices, t->twin, t->origin, c->lab4, he, vtx, c->stage, c->stage_cap, c->arena,
+                         c->arena_cap, ps, c->rest, false, (int64_t)0, &k->n_gen, nullptr, c->huge, c->huge_cap,
+                         &k->n_fallback, nullptr, (int64_t)0, nullptr, 0u, c->gen_wave_max, k);
+  }
   {
     Prof p(c, s, KR_GENERAL);
     const int gg = 2048;
     if (repair)
       hipLaunchKernelGGL(k_general_small<true>, dim3(gg), dim3(64), 0, s, list, from_seeds, nhe, t->n_vertices,
                          t->twin, t->origin, c->lab4, he, vtx, c->stage, c->stage_cap, c->arena, c->arena_cap, ps,
-                         c->rest, &c->cnt->n_gen, c->cnt);
+                         c->rest, &c->cnt->n_gen, c->gen_wave_max, c->cnt);
     else
       hipLaunchKernelGGL(k_general_small<false>, dim3(gg), dim3(64), 0, s, list, from_seeds, nhe, t->n_vertices,
                          t->twin, t->origin, c->lab4, he, vtx, c->stage, c->stage_cap, c->arena, c->arena_cap, ps,
-                         c->rest, &c->cnt->n_gen, c->cnt);
+                         c->rest, &c->cnt->n_gen, c->gen_wave_max, c->cnt);
   }
   if (hipStreamWaitEvent(s, c->join, 0) != hipSuccess) return POLYLLA_EHIP;
   {
@@ -553,6 +574,10 @@ int polylla_set_param(polylla_ctx* c, int param, int64_t value) {
     case POLYLLA_PARAM_WALK_BLOCKS:
       if (value < 8 || value > kWalkBlocks || value % 8) return POLYLLA_EINVAL;
       c->walk_blocks = (int)value;
+      return POLYLLA_OK;
+    case POLYLLA_PARAM_GEN_WAVE_MAX:
+      if (value < 0 || value > UINT32_MAX - 1) return POLYLLA_EINVAL;
+      c->gen_wave_max = (uint32_t)value;
       return POLYLLA_OK;
     default:
       return POLYLLA_EINVAL;

@@ -1251,7 +1251,7 @@ __global__ __launch_bounds__(64) void k_general_small(const int32_t* __restrict_
                                                       int64_t stage_cap, int32_t* __restrict__ arena,
                                                       int64_t arena_cap, PolyState ps,
                                                       const int32_t* __restrict__ deferred,
-                                                      const uint32_t* n_in, Counters* cnt) {
+                                                      const uint32_t* n_in, uint32_t run_min, Counters* cnt) {
   __shared__ int32_t s_tri[kSmallK * 64];
   __shared__ int32_t s_lnk[3 * kSmallK * 64];
   __shared__ int32_t s_org[3 * kSmallK * 64];
@@ -1261,6 +1261,7 @@ __global__ __launch_bounds__(64) void k_general_small(const int32_t* __restrict_
   const Region<LdsCol> R{LdsCol{s_tri + lane}, LdsCol{s_lnk + lane}, LdsCol{s_org + lane}};
   const int32_t nt = nhe / 3;
   const uint32_t nd = *n_in;
+  if (nd <= run_min) return;  // few of them: the one-wave region kernel takes them
   for (uint32_t j = blockIdx.x * 64 + threadIdx.x; j < nd; j += gridDim.x * 64) {
     const int32_t i = deferred[j];
     const int32_t item = list[i];
@@ -1457,7 +1458,8 @@ __device__ __forceinline__ void push_over(int32_t* over, int64_t over_cap, uint3
 // With `few_count` given and at most `few_max` long polygons in all, the first
 // instance (few_in null) leaves them all to the second, which then takes them
 // from few_in (from the back, few_cap long) instead of `in`: a few long
-// regions are then not gathered twice.
+// regions are then not gathered twice. An instance with more than `run_max`
+// polygons to take does nothing (another kernel takes them).
 template <bool REPAIR, int NT, int KC, int LC, int HB>
 __global__ __launch_bounds__(NT) void k_general_big(
     const int32_t* __restrict__ list, bool from_seeds, int32_t nhe, int64_t nv, const int32_t* __restrict__ twin,
@@ -1466,7 +1468,7 @@ __global__ __launch_bounds__(NT) void k_general_big(
     int64_t arena_cap, PolyState ps, const int32_t* __restrict__ in, bool in_rev, int64_t in_cap,
     const uint32_t* in_count, uint32_t* in_ticket, int32_t* __restrict__ over, int64_t over_cap,
     uint32_t* over_count, const int32_t* __restrict__ few_in, int64_t few_cap, const uint32_t* few_count,
-    uint32_t few_max, Counters* cnt) {
+    uint32_t few_max, uint32_t run_max, Counters* cnt) {
   constexpr int kBigThreads = NT, kKCap = KC, kLCap = LC, kHCap = 1 << HB, kPer = LC / NT;
   static_assert(LC % NT == 0 && kPer >= 1, "slots per thread");
   static_assert(KC < (1 << 13) && LC < (1 << 14), "codes and slots are int16");
@@ -1492,6 +1494,7 @@ __global__ __launch_bounds__(NT) void k_general_big(
     in_count = few_count;
   }
   const uint32_t nbig = *in_count;
+  if (nbig > run_max) return;
   const int32_t nt = nhe / 3;
   uint32_t next_item = blockIdx.x;
   for (;;) {
@@ -2238,11 +2241,11 @@ template __global__ void k_walk<false>(const int32_t*, int32_t, const int32_t*, 
 template __global__ void k_general_small<true>(const int32_t*, bool, int32_t, int64_t, const int32_t*,
                                                const int32_t*, const uint32_t*, uint8_t*, uint8_t*, int32_t*,
                                                int64_t, int32_t*, int64_t, PolyState, const int32_t*,
-                                               const uint32_t*, Counters*);
+                                               const uint32_t*, uint32_t, Counters*);
 template __global__ void k_general_small<false>(const int32_t*, bool, int32_t, int64_t, const int32_t*,
                                                 const int32_t*, const uint32_t*, uint8_t*, uint8_t*, int32_t*,
                                                 int64_t, int32_t*, int64_t, PolyState, const int32_t*,
-                                                const uint32_t*, Counters*);
+                                                const uint32_t*, uint32_t, Counters*);
 template __global__ void k_tip<true>(int32_t, int64_t, const int32_t*, const int32_t*, uint8_t*, uint8_t*, int32_t*,
                                      int64_t, int32_t*, int64_t, PolyState, const int32_t*, int32_t*, int64_t,
                                      Counters*);
@@ -2252,19 +2255,19 @@ template __global__ void k_tip<false>(int32_t, int64_t, const int32_t*, const in
 template __global__ void k_general_big<true, 64, 128, 128, 8>(
     const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*, const uint32_t*, uint8_t*, uint8_t*,
     int32_t*, int64_t, int32_t*, int64_t, PolyState, const int32_t*, bool, int64_t, const uint32_t*, uint32_t*,
-    int32_t*, int64_t, uint32_t*, const int32_t*, int64_t, const uint32_t*, uint32_t, Counters*);
+    int32_t*, int64_t, uint32_t*, const int32_t*, int64_t, const uint32_t*, uint32_t, uint32_t, Counters*);
 template __global__ void k_general_big<true, 1024, 4096, 4096, 13>(
     const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*, const uint32_t*, uint8_t*, uint8_t*,
     int32_t*, int64_t, int32_t*, int64_t, PolyState, const int32_t*, bool, int64_t, const uint32_t*, uint32_t*,
-    int32_t*, int64_t, uint32_t*, const int32_t*, int64_t, const uint32_t*, uint32_t, Counters*);
+    int32_t*, int64_t, uint32_t*, const int32_t*, int64_t, const uint32_t*, uint32_t, uint32_t, Counters*);
 template __global__ void k_general_big<false, 64, 128, 128, 8>(
     const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*, const uint32_t*, uint8_t*, uint8_t*,
     int32_t*, int64_t, int32_t*, int64_t, PolyState, const int32_t*, bool, int64_t, const uint32_t*, uint32_t*,
-    int32_t*, int64_t, uint32_t*, const int32_t*, int64_t, const uint32_t*, uint32_t, Counters*);
+    int32_t*, int64_t, uint32_t*, const int32_t*, int64_t, const uint32_t*, uint32_t, uint32_t, Counters*);
 template __global__ void k_general_big<false, 1024, 4096, 4096, 13>(
     const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*, const uint32_t*, uint8_t*, uint8_t*,
     int32_t*, int64_t, int32_t*, int64_t, PolyState, const int32_t*, bool, int64_t, const uint32_t*, uint32_t*,
-    int32_t*, int64_t, uint32_t*, const int32_t*, int64_t, const uint32_t*, uint32_t, Counters*);
+    int32_t*, int64_t, uint32_t*, const int32_t*, int64_t, const uint32_t*, uint32_t, uint32_t, Counters*);
 template __global__ void k_general_huge<true>(const int32_t*, bool, int32_t, int64_t, const int32_t*,
                                               const int32_t*, uint8_t*, uint8_t*, int32_t*, int64_t, int32_t*,
                                               int64_t, PolyState, const int32_t*, Counters*);

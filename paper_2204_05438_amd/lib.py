@@ -20,6 +20,7 @@ LONGEST, FRONTIER, TERMINAL, BORDER, BARRIER, REPAIRED = 1, 2, 4, 8, 16, 32
 SEED, TIP = 1, 1
 PARAM_WALK_CAP = 1
 PARAM_WALK_BLOCKS = 2
+PARAM_GEN_WAVE_MAX = 3
 PROFILE_OFF, PROFILE_ALL, PROFILE_WALK = 0, 1, 2
 
 

@@ -113,6 +113,23 @@ def test_cooperative_path(ctx, kind, walk_cap):
             assert r["stats"]["general_big"] > 0
 
 
+@pytest.mark.parametrize("wave_max", [0, 1 << 20])
+@pytest.mark.parametrize("kind", ["uniform", "cluster"])
+def test_declined_short_polygon_paths(ctx, kind, wave_max):
+    """The short polygons the single-tip path declines go one lane each (count
+    above the threshold) or one wave each (count at most the threshold)."""
+    from paper_2204_05438_amd import lib
+    _say(f"declined short polygons {kind} wave_max {wave_max}")
+    ctx.set_param(lib.PARAM_GEN_WAVE_MAX, wave_max)
+    try:
+        for seed in range(3):
+            mesh = random_mesh(1300 + seed, 20000, kind)
+            for walk_cap in (24, 12):
+                assert_same(gpu_mesh(ctx, mesh, walk_cap), oracle.oracle_on(mesh), FULL)
+    finally:
+        ctx.set_param(lib.PARAM_GEN_WAVE_MAX, 8192)
+
+
 def test_empty(ctx):
     _say("empty mesh")
     r = gpu_mesh(ctx, empty_mesh())

@@ -86,9 +86,23 @@ __global__ __launch_bounds__(256) void k_longest(int64_t nt, int64_t nv, const d
   }
 }
 
+// Max of triangle u: from the block's LDS window of Max bytes when u falls in
+// it (most neighbours do: triangles are numbered along a space-filling order),
+// else from global memory.
+struct LgView {
+  const uint8_t* __restrict__ lg;
+  const uint8_t* win;  // LDS copy of lg[lo, lo + n), or null
+  int64_t lo;
+  int n;
+  __device__ __forceinline__ uint8_t operator[](int64_t u) const {
+    const int64_t r = u - lo;
+    return (win && (uint64_t)r < (uint64_t)n) ? win[r] : lg[u];
+  }
+};
+
 // Labels of the three half-edges of triangle t and whether t is a seed.
-__device__ __forceinline__ uint32_t label_triangle(int64_t t, int m, const int32_t tw[3],
-                                                   const uint8_t* __restrict__ lg, int32_t nhe,
+template <class LG>
+__device__ __forceinline__ uint32_t label_triangle(int64_t t, int m, const int32_t tw[3], const LG& lg, int32_t nhe,
                                                    Counters* cnt, bool* seed) {
   uint32_t packed = 0;
   bool s = false;
@@ -124,6 +138,8 @@ __device__ __forceinline__ uint32_t label_triangle(int64_t t, int m, const int32
 }
 
 constexpr int kLabelItems = 8;  // triangles per thread of k_label (multiple of 4)
+constexpr int kLgMargin = 2048;  // Max bytes before and after a tile kept in LDS
+constexpr int kLgWin = 256 * kLabelItems + 2 * kLgMargin;
 
 // COMPUTE = true : labels from twin + Max, then seed compaction.
 // COMPUTE = false: seed compaction only, from existing triangle labels.
@@ -145,7 +161,25 @@ __global__ __launch_bounds__(256) void k_label(int64_t nt, const int32_t* __rest
   const bool full = COMPUTE && vec && tile_t0 + 256 * ITEMS <= nt &&
                     ((reinterpret_cast<uintptr_t>(he) | reinterpret_cast<uintptr_t>(tri) |
                       reinterpret_cast<uintptr_t>(lab4)) & 15) == 0;
+  __shared__ uint4 s_lg4[kLgWin / 16];
   if (full) {
+    // Max bytes of the tile and its margins (16-byte aligned: tiles and
+    // margins are multiples of 16 triangles)
+    const int64_t wlo = tile_t0 - kLgMargin;
+    for (int k = threadIdx.x; k < kLgWin / 16; k += 256) {
+      const int64_t g = wlo + 16 * (int64_t)k;
+      uint4 w = make_uint4(0u, 0u, 0u, 0u);
+      if (g >= 0 && g + 16 <= nt) {
+        w = *reinterpret_cast<const uint4*>(lg + g);
+      } else {
+        uint8_t* wb = reinterpret_cast<uint8_t*>(&w);
+        for (int b = 0; b < 16; ++b)
+          if (g + b >= 0 && g + b < nt) wb[b] = lg[g + b];
+      }
+      s_lg4[k] = w;
+    }
+    __syncthreads();
+    const LgView lgv{lg, reinterpret_cast<const uint8_t*>(s_lg4), wlo, kLgWin};
     uint32_t* s_w = reinterpret_cast<uint32_t*>(s_w4);
     uint32_t* s_lab = s_w;
     uint32_t* s_he = s_w + 256 * ITEMS;
@@ -162,14 +196,15 @@ __global__ __launch_bounds__(256) void k_label(int64_t nt, const int32_t* __rest
     }
     uint32_t mm[ITEMS / 4];
 #pragma unroll
-    for (int k = 0; k < ITEMS / 4; ++k) mm[k] = reinterpret_cast<const uint32_t*>(lg + t0)[k];
+    for (int k = 0; k < ITEMS / 4; ++k)
+      mm[k] = reinterpret_cast<const uint32_t*>(s_lg4)[(kLgMargin + threadIdx.x * ITEMS) / 4 + k];
     const int lt = threadIdx.x * ITEMS;  // first triangle of this thread within the tile
 #pragma unroll
     for (int g = 0; g < ITEMS / 4; ++g) {
       uint32_t lab[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j)
-        lab[j] = label_triangle(t0 + 4 * g + j, (mm[g] >> (8 * j)) & 0xFF, tw + 3 * (4 * g + j), lg, nhe, cnt,
+        lab[j] = label_triangle(t0 + 4 * g + j, (mm[g] >> (8 * j)) & 0xFF, tw + 3 * (4 * g + j), lgv, nhe, cnt,
                                 &sd[4 * g + j]);
       reinterpret_cast<uint4*>(s_lab + lt)[g] = make_uint4(lab[0], lab[1], lab[2], lab[3]);
       s_he[3 * (lt / 4 + g)] = lab[0] | (lab[1] << 24);
@@ -208,7 +243,7 @@ __global__ __launch_bounds__(256) void k_label(int64_t nt, const int32_t* __rest
         uint32_t lab[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-          lab[j] = label_triangle(t0 + 4 * g + j, (mm[g] >> (8 * j)) & 0xFF, tw + 3 * (4 * g + j), lg, nhe, cnt,
+          lab[j] = label_triangle(t0 + 4 * g + j, (mm[g] >> (8 * j)) & 0xFF, tw + 3 * (4 * g + j), LgView{lg, nullptr, 0, 0}, nhe, cnt,
                                   &sd[4 * g + j]);
         // packed label word per triangle for the walk (aligned 16-byte store)
         reinterpret_cast<uint4*>(lab4 + t0)[g] = make_uint4(lab[0], lab[1], lab[2], lab[3]);
@@ -226,7 +261,7 @@ __global__ __launch_bounds__(256) void k_label(int64_t nt, const int32_t* __rest
         const int64_t t = t0 + j;
         if (t >= nt) continue;
         int32_t tw[3] = {twin[3 * t], twin[3 * t + 1], twin[3 * t + 2]};
-        uint32_t lab = label_triangle(t, lg[t], tw, lg, nhe, cnt, &sd[j]);
+        uint32_t lab = label_triangle(t, lg[t], tw, LgView{lg, nullptr, 0, 0}, nhe, cnt, &sd[j]);
         lab4[t] = lab;
         he[3 * t] = (uint8_t)lab;
         he[3 * t + 1] = (uint8_t)(lab >> 8);

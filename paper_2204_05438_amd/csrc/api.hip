@@ -14,22 +14,22 @@ __global__ void k_reset(Counters*, uint64_t*, int64_t, const int64_t*);
 __global__ void k_longest(int64_t, int64_t, const double*, const int32_t*, const int32_t*, uint8_t*, uint8_t*,
                           Counters*);
 template <bool COMPUTE>
-__global__ void k_label(int64_t, const int32_t*, const uint8_t*, uint8_t*, uint8_t*, uint32_t*, uint32_t*, uint32_t*,
-                        Counters*, bool);
+__global__ void k_label(int64_t, const int32_t*, const uint8_t*, uint8_t*, uint8_t*, const int32_t*, int32_t*,
+                        uint32_t*, uint32_t*, Counters*, bool);
 __global__ void k_seeds(int64_t, const uint8_t*, const uint32_t*, const uint32_t*, int32_t*, Counters*);
-__global__ void k_pack_labels(int64_t, const uint8_t*, uint32_t*);
+__global__ void k_pack_walk(int64_t, const uint8_t*, const int32_t*, const int32_t*, int32_t*);
 template <bool FROM_SEEDS>
-__global__ void k_walk(const int32_t*, int32_t, const int32_t*, const int32_t*, const uint32_t*, int32_t*,
-                       int64_t, PolyState, int32_t*, int64_t, int, Counters*);
+__global__ void k_walk(const int32_t*, int32_t, const int32_t*, int32_t*, int64_t, PolyState, int32_t*, int64_t, int,
+                       Counters*);
 template <bool REPAIR>
 __global__ void k_general_small(const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*,
-                                const uint32_t*, uint8_t*, uint8_t*, int32_t*, int64_t, int32_t*, int64_t, PolyState,
+                                const int32_t*, uint8_t*, uint8_t*, int32_t*, int64_t, int32_t*, int64_t, PolyState,
                                 const int32_t*, const uint32_t*, uint32_t, Counters*);
 template <bool REPAIR>
 __global__ void k_tip(int32_t, int64_t, const int32_t*, const int32_t*, uint8_t*, uint8_t*, int32_t*, int64_t,
                       int32_t*, int64_t, PolyState, const int32_t*, int32_t*, int64_t, Counters*);
 template <bool REPAIR, int NT, int KC, int LC, int HB>
-__global__ void k_general_big(const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*, const uint32_t*,
+__global__ void k_general_big(const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*, const int32_t*,
                               uint8_t*, uint8_t*, int32_t*, int64_t, int32_t*, int64_t, PolyState, const int32_t*,
                               bool, int64_t, const uint32_t*, uint32_t*, int32_t*, int64_t, uint32_t*,
                               const int32_t*, int64_t, const uint32_t*, uint32_t, uint32_t, Counters*);
@@ -57,7 +57,7 @@ struct polylla_ctx {
   int64_t cap_t = 0;  // triangles
   int64_t cap_v = 0;  // vertices
   uint8_t* lg = nullptr;
-  uint32_t* lab4 = nullptr;  // packed label word per triangle (walk)
+  int32_t* wk = nullptr;  // walk word per half-edge: twin (internal) or -1 - origin (frontier)
   int32_t* seeds = nullptr;
   int32_t* deferred = nullptr;
   int32_t* over = nullptr;  // regions beyond the one-wave workgroup's LDS
@@ -111,7 +111,7 @@ enum KernelId {
   KR_BATCH, KR_BIGW, KR_TIP, KR_SEEDS, KR_GENW, KR_N
 };
 const char* kKernelNames[KR_N] = {"k_reset",         "k_longest",       "k_label",          "k_compact_seeds",
-                                  "k_pack_labels",   "k_walk",          "k_general_small",  "k_general_big",
+                                  "k_pack_walk",     "k_walk",          "k_general_small",  "k_general_big",
                                   "k_general_huge",  "k_scan_emit",     "k_validate",       "k_batch_offsets",
                                   "k_general_big_wg", "k_tip",           "k_seeds",          "k_general_wave"};
 
@@ -155,7 +155,7 @@ void dfree(T** p) {
 
 void free_scratch(polylla_ctx* c) {
   dfree(&c->lg);
-  dfree(&c->lab4);
+  dfree(&c->wk);
   dfree(&c->seeds);
   dfree(&c->deferred);
   dfree(&c->huge);
@@ -187,7 +187,7 @@ int ensure(polylla_ctx* c, int64_t nt, int64_t nv) {
                                    ((int64_t)1 << 31) - 1);
   c->arena_cap = 6 * T + kBigArenaTails + 4096;
   c->n_status = 2 * ntiles;
-  if ((rc = dalloc(&c->lg, T)) || (rc = dalloc(&c->lab4, T)) || (rc = dalloc(&c->seeds, T)) || (rc = dalloc(&c->deferred, T)) || (rc = dalloc(&c->huge, c->huge_cap = T / 1024 + 64)) ||
+  if ((rc = dalloc(&c->lg, T)) || (rc = dalloc(&c->wk, 3 * T)) || (rc = dalloc(&c->seeds, T)) || (rc = dalloc(&c->deferred, T)) || (rc = dalloc(&c->huge, c->huge_cap = T / 1024 + 64)) ||
       (rc = dalloc(&c->over, c->over_cap = T / 32 + 64)) ||
       (rc = dalloc(&c->rest, c->rest_cap = T / 3 + 64)) ||
       (rc = dalloc(&c->poly_arrays, 5 * T)) || (rc = dalloc(&c->stage, c->stage_cap)) ||
@@ -260,9 +260,10 @@ int run_label(polylla_ctx* c, const polylla_tri* t, uint8_t* he, uint8_t* tri, u
   if (T > 0) {
     Prof p(c, s, KR_LABEL);
     // 16-byte loads of twin and 4-byte label stores need aligned arrays
-    const bool vec = ((uintptr_t)t->twin % 16 == 0) && ((uintptr_t)he % 4 == 0) && ((uintptr_t)tri % 4 == 0);
+    const bool vec = ((uintptr_t)t->twin % 16 == 0) && ((uintptr_t)t->origin % 16 == 0) && ((uintptr_t)he % 4 == 0) &&
+                     ((uintptr_t)tri % 4 == 0);
     hipLaunchKernelGGL(k_label<true>, dim3((T + kTile - 1) / kTile), dim3(256), 0, s, T, t->twin, c->lg, he, tri,
-                       c->lab4, tile_counts(c), tile_groups(c, T), c->cnt, vec);
+                       t->origin, c->wk, tile_counts(c), tile_groups(c, T), c->cnt, vec);
   }
   if (T > 0) launch_seeds(c, T, tri, s);
   return launched();
@@ -279,10 +280,10 @@ int run_build(polylla_ctx* c, const polylla_tri* t, const int32_t* list, bool fr
     Prof p(c, s, KR_WALK);
     const int gw = c->walk_blocks;  // persistent: waves take seeds from per-XCD queues
     if (from_seeds)
-      hipLaunchKernelGGL(k_walk<true>, dim3(gw), dim3(256), 0, s, list, nhe, t->twin, t->origin, c->lab4, c->stage,
+      hipLaunchKernelGGL(k_walk<true>, dim3(gw), dim3(256), 0, s, list, nhe, c->wk, c->stage,
                          c->stage_cap, ps, c->deferred, c->cap_t, c->walk_cap, c->cnt);
     else
-      hipLaunchKernelGGL(k_walk<false>, dim3(gw), dim3(256), 0, s, list, nhe, t->twin, t->origin, c->lab4, c->stage,
+      hipLaunchKernelGGL(k_walk<false>, dim3(gw), dim3(256), 0, s, list, nhe, c->wk, c->stage,
                          c->stage_cap, ps, c->deferred, c->cap_t, c->walk_cap, c->cnt);
   }
   // the long regions (workgroup kernel, side stream) and the short ones
@@ -299,12 +300,12 @@ int run_build(polylla_ctx* c, const polylla_tri* t, const int32_t* list, bool fr
     const int gm = kBigGrid64;  // persistent: one-wave blocks take regions round-robin
     if (repair)
       hipLaunchKernelGGL((k_general_big<true, 64, 128, 128, 8>), dim3(gm), dim3(64), 0, c->side, list, from_seeds, nhe,
-                         t->n_vertices, t->twin, t->origin, c->lab4, he, vtx, c->stage, c->stage_cap, c->arena,
+                         t->n_vertices, t->twin, t->origin, c->wk, he, vtx, c->stage, c->stage_cap, c->arena,
                          c->arena_cap, ps, c->deferred, true, c->cap_t, &k->n_big, &k->big_ticket, c->over,
                          c->over_cap, &k->n_over, nullptr, (int64_t)0, &k->n_big, few, UINT32_MAX, k);
     else
       hipLaunchKernelGGL((k_general_big<false, 64, 128, 128, 8>), dim3(gm), dim3(64), 0, c->side, list, from_seeds,
-                         nhe, t->n_vertices, t->twin, t->origin, c->lab4, he, vtx, c->stage, c->stage_cap, c->arena,
+                         nhe, t->n_vertices, t->twin, t->origin, c->wk, he, vtx, c->stage, c->stage_cap, c->arena,
                          c->arena_cap, ps, c->deferred, true, c->cap_t, &k->n_big, &k->big_ticket, c->over,
                          c->over_cap, &k->n_over, nullptr, (int64_t)0, &k->n_big, few, UINT32_MAX, k);
   }
@@ -314,12 +315,12 @@ int run_build(polylla_ctx* c, const polylla_tri* t, const int32_t* list, bool fr
     const int gb = kBigGrid1024;  // persistent: blocks take the remaining long regions by ticket
     if (repair)
       hipLaunchKernelGGL((k_general_big<true, 1024, 4096, 4096, 13>), dim3(gb), dim3(1024), 0, c->side, list,
-                         from_seeds, nhe, t->n_vertices, t->twin, t->origin, c->lab4, he, vtx, c->stage, c->stage_cap,
+                         from_seeds, nhe, t->n_vertices, t->twin, t->origin, c->wk, he, vtx, c->stage, c->stage_cap,
                          c->arena, c->arena_cap, ps, c->over, false, (int64_t)0, &k->n_over, &k->over_ticket, c->huge,
                          c->huge_cap, &k->n_fallback, c->deferred, c->cap_t, &k->n_big, few, UINT32_MAX, k);
     else
       hipLaunchKernelGGL((k_general_big<false, 1024, 4096, 4096, 13>), dim3(gb), dim3(1024), 0, c->side, list,
-                         from_seeds, nhe, t->n_vertices, t->twin, t->origin, c->lab4, he, vtx, c->stage, c->stage_cap,
+                         from_seeds, nhe, t->n_vertices, t->twin, t->origin, c->wk, he, vtx, c->stage, c->stage_cap,
                          c->arena, c->arena_cap, ps, c->over, false, (int64_t)0, &k->n_over, &k->over_ticket, c->huge,
                          c->huge_cap, &k->n_fallback, c->deferred, c->cap_t, &k->n_big, few, UINT32_MAX, k);
   }
@@ -344,12 +345,12 @@ int run_build(polylla_ctx* c, const polylla_tri* t, const int32_t* list, bool fr
     Counters* k = c->cnt;
     if (repair)
       hipLaunchKernelGGL((k_general_big<true, 64, 128, 128, 8>), dim3(kBigGrid64), dim3(64), 0, s, list, from_seeds,
-                         nhe, t->n_vertices, t->twin, t->origin, c->lab4, he, vtx, c->stage, c->stage_cap, c->arena,
+                         nhe, t->n_vertices, t->twin, t->origin, c->wk, he, vtx, c->stage, c->stage_cap, c->arena,
                          c->arena_cap, ps, c->rest, false, (int64_t)0, &k->n_gen, nullptr, c->huge, c->huge_cap,
                          &k->n_fallback, nullptr, (int64_t)0, nullptr, 0u, c->gen_wave_max, k);
     else
       hipLaunchKernelGGL((k_general_big<false, 64, 128, 128, 8>), dim3(kBigGrid64), dim3(64), 0, s, list, from_seeds,
-                         nhe, t->n_vertices, t->twin, t->origin, c->lab4, he, vtx, c->stage, c->stage_cap, c->arena,
+                         nhe, t->n_vertices, t->twin, t->origin, c->wk, he, vtx, c->stage, c->stage_cap, c->arena,
                          c->arena_cap, ps, c->rest, false, (int64_t)0, &k->n_gen, nullptr, c->huge, c->huge_cap,
                          &k->n_fallback, nullptr, (int64_t)0, nullptr, 0u, c->gen_wave_max, k);
   }
@@ -358,11 +359,11 @@ int run_build(polylla_ctx* c, const polylla_tri* t, const int32_t* list, bool fr
     const int gg = 2048;
     if (repair)
       hipLaunchKernelGGL(k_general_small<true>, dim3(gg), dim3(64), 0, s, list, from_seeds, nhe, t->n_vertices,
-                         t->twin, t->origin, c->lab4, he, vtx, c->stage, c->stage_cap, c->arena, c->arena_cap, ps,
+                         t->twin, t->origin, c->wk, he, vtx, c->stage, c->stage_cap, c->arena, c->arena_cap, ps,
                          c->rest, &c->cnt->n_gen, c->gen_wave_max, c->cnt);
     else
       hipLaunchKernelGGL(k_general_small<false>, dim3(gg), dim3(64), 0, s, list, from_seeds, nhe, t->n_vertices,
-                         t->twin, t->origin, c->lab4, he, vtx, c->stage, c->stage_cap, c->arena, c->arena_cap, ps,
+                         t->twin, t->origin, c->wk, he, vtx, c->stage, c->stage_cap, c->arena, c->arena_cap, ps,
                          c->rest, &c->cnt->n_gen, c->gen_wave_max, c->cnt);
   }
   if (hipStreamWaitEvent(s, c->join, 0) != hipSuccess) return POLYLLA_EHIP;
@@ -461,12 +462,13 @@ int polylla_build(polylla_ctx* c, const polylla_tri* t, polylla_labels* l, polyl
   if (T > 0) {
     Prof p(c, s, KR_COMPACT);
     hipLaunchKernelGGL(k_label<false>, dim3((T + kTile - 1) / kTile), dim3(256), 0, s, T, t->twin, c->lg, l->he,
-                       l->tri, c->lab4, tile_counts(c), tile_groups(c, T), c->cnt, false);
+                       l->tri, t->origin, c->wk, tile_counts(c), tile_groups(c, T), c->cnt, false);
   }
   if (T > 0) launch_seeds(c, T, l->tri, s);
   if (T > 0) {
     Prof p(c, s, KR_PACK);
-    hipLaunchKernelGGL(k_pack_labels, dim3(grid_for(T, 256, 1 << 16)), dim3(256), 0, s, T, l->he, c->lab4);
+    hipLaunchKernelGGL(k_pack_walk, dim3(grid_for(3 * T, 256, 1 << 16)), dim3(256), 0, s, 3 * T, l->he, t->twin,
+                       t->origin, c->wk);
   }
   return run_build(c, t, c->seeds, true, false, l->he, l->vtx, out, s);
 }
@@ -484,7 +486,8 @@ int polylla_repair(polylla_ctx* c, const polylla_tri* t, polylla_labels* l, cons
   reset(c, s, in->counts);
   if (T > 0) {
     Prof p(c, s, KR_PACK);
-    hipLaunchKernelGGL(k_pack_labels, dim3(grid_for(T, 256, 1 << 16)), dim3(256), 0, s, T, l->he, c->lab4);
+    hipLaunchKernelGGL(k_pack_walk, dim3(grid_for(3 * T, 256, 1 << 16)), dim3(256), 0, s, 3 * T, l->he, t->twin,
+                       t->origin, c->wk);
   }
   return run_build(c, t, in->start, false, true, l->he, l->vtx, out, s);
 }

@@ -77,26 +77,39 @@ __device__ __forceinline__ int32_t sel3(int32_t a, int32_t b, int32_t c, int i) 
   return i == 0 ? a : (i == 1 ? b : c);
 }
 
-// Twin triple, origin triple and label bytes of one triangle: nine
-// independent loads issued together, so a walk pays one memory round trip per
-// triangle it enters.
 struct alignas(4) Int3 {
   int32_t x, y, z;
 };
 
+// The walk array holds one word per half-edge: the twin of an internal
+// half-edge, -1 - origin of a frontier one. A walk reads one 12-byte triple
+// per triangle it enters: its next step (crossing) or its next vertex.
+struct WalkRec {
+  int32_t w0, w1, w2;
+  __device__ __forceinline__ int32_t w(int i) const { return sel3(w0, w1, w2, i); }
+  __device__ __forceinline__ void load(int32_t t, const int32_t* __restrict__ wk) {
+    const Int3 a = *reinterpret_cast<const Int3*>(wk + 3 * t);
+    w0 = a.x;
+    w1 = a.y;
+    w2 = a.z;
+  }
+};
+
+// Twin triple, origin triple and frontier flags (from the walk array) of one
+// triangle: three independent loads issued together.
 struct TriRec {
   int32_t tw0, tw1, tw2;
   int32_t or0, or1, or2;
-  uint32_t lab3;  // three label bytes
+  uint32_t fm;  // bit i: half-edge i is a frontier edge
   __device__ __forceinline__ int32_t tw(int i) const { return sel3(tw0, tw1, tw2, i); }
   __device__ __forceinline__ int32_t org(int i) const { return sel3(or0, or1, or2, i); }
-  __device__ __forceinline__ uint32_t lab(int i) const { return (lab3 >> (8 * i)) & 0xFFu; }
-  // three loads: twin triple, origin triple (12 bytes each) and the label word
+  __device__ __forceinline__ bool frontier(int i) const { return (fm >> i) & 1u; }
   __device__ __forceinline__ void load(int32_t t, const int32_t* __restrict__ twin,
-                                       const int32_t* __restrict__ origin, const uint32_t* __restrict__ lab4) {
+                                       const int32_t* __restrict__ origin, const int32_t* __restrict__ wk) {
     const Int3 a = *reinterpret_cast<const Int3*>(twin + 3 * t);
     const Int3 b = *reinterpret_cast<const Int3*>(origin + 3 * t);
-    lab3 = lab4[t];
+    const Int3 c = *reinterpret_cast<const Int3*>(wk + 3 * t);
+    fm = (c.x < 0 ? 1u : 0u) | (c.y < 0 ? 2u : 0u) | (c.z < 0 ? 4u : 0u);
     tw0 = a.x;
     tw1 = a.y;
     tw2 = a.z;
@@ -129,9 +142,7 @@ constexpr int kRefill = 8;             // idle lanes of a wave before it hands o
 
 template <bool FROM_SEEDS>
 __global__ __launch_bounds__(256) void k_walk(const int32_t* __restrict__ list, int32_t nhe,
-                                              const int32_t* __restrict__ twin,
-                                              const int32_t* __restrict__ origin,
-                                              const uint32_t* __restrict__ lab4, int32_t* __restrict__ stage,
+                                              const int32_t* __restrict__ wk, int32_t* __restrict__ stage,
                                               int64_t stage_cap, PolyState ps, int32_t* __restrict__ deferred,
                                               int64_t deferred_cap, int walk_cap, Counters* cnt) {
   __shared__ int32_t buf[kWalkCap][256];   // vertex ids of the cycle, per lane
@@ -152,13 +163,12 @@ __global__ __launch_bounds__(256) void k_walk(const int32_t* __restrict__ list, 
   int32_t sleft = 0;
   // lane state; the cycle's vertices are kept in LDS column buf[.][threadIdx.x]
   int32_t idx = -1;
-  int32_t s = -1, t = 0, ci = 0, twh = -1, L = 0, minv = 0, minpos = 0, minhe = -1, steps = 0;
+  int32_t s = -1, t = 0, ci = 0, L = 0, minv = 0, minpos = 0, minhe = -1, steps = 0;
   uint64_t sig = 0;  // bit (v & 63) of every vertex so far: repeat pre-filter
   bool complex = false, pending = false, fresh = false, done = false;
   int result = kSimple;
-  TriRec r, rn;
-  r.tw0 = r.tw1 = r.tw2 = r.or0 = r.or1 = r.or2 = 0;
-  r.lab3 = 0;
+  WalkRec r, rn;
+  r.w0 = r.w1 = r.w2 = 0;
   rn = r;
   for (;;) {
     if (pending) {
@@ -216,9 +226,8 @@ __global__ __launch_bounds__(256) void k_walk(const int32_t* __restrict__ list, 
         minpos = 0;
         minhe = -1;
         result = kSimple;
-        twh = -1;
         if ((uint32_t)t < (uint32_t)nt && (FROM_SEEDS || item >= 0)) {
-          rn.load(t, twin, origin, lab4);
+          rn.load(t, wk);
           pending = true;
           s = FROM_SEEDS ? -1 : item;  // -1: start not found yet
           ci = FROM_SEEDS ? 0 : item - 3 * t;
@@ -232,19 +241,19 @@ __global__ __launch_bounds__(256) void k_walk(const int32_t* __restrict__ list, 
     if (idx >= 0 && !pending && !done) {
       if (fresh && FROM_SEEDS) {
         // seed triangle: its first frontier half-edge, else turn about vertex 0
-        if (r.lab(0) & kFrontier) ci = 0;
-        else if (r.lab(1) & kFrontier) ci = 1;
-        else if (r.lab(2) & kFrontier) ci = 2;
+        if (r.w0 < 0) ci = 0;
+        else if (r.w1 < 0) ci = 1;
+        else if (r.w2 < 0) ci = 2;
         else ci = -1;
         if (ci < 0) {
-          const int32_t tw = r.tw0;
+          const int32_t tw = r.w0;
           if ((uint32_t)tw >= (uint32_t)nhe) {
             result = kInvalid;
             done = true;
           } else {
             t = tw / 3;
             ci = next_local(tw - 3 * t);
-            rn.load(t, twin, origin, lab4);
+            rn.load(t, wk);
             pending = true;
           }
         } else {
@@ -259,23 +268,22 @@ __global__ __launch_bounds__(256) void k_walk(const int32_t* __restrict__ list, 
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         if (pending || done) continue;
-        if (r.lab(ci) & kFrontier) {
+        const int32_t wv = r.w(ci);
+        if (wv < 0) {
+          // frontier half-edge (a barrier-edge tip shows as a repeated vertex)
           const int32_t c = 3 * t + ci;
           if (s < 0) {
             s = c;  // start found by turning about the seed's vertex 0
-          } else if (L > 0) {
-            if (c == twh) complex = true;  // barrier-edge tip
-            if (c == s) {
-              done = true;
-              continue;
-            }
+          } else if (L > 0 && c == s) {
+            done = true;
+            continue;
           }
           if (L == walk_cap) {
             result = kLarge;
             done = true;
             continue;
           }
-          const int32_t v = r.org(ci);
+          const int32_t v = -1 - wv;
           buf[L][threadIdx.x] = v;
           hbuf[L][threadIdx.x] = c;
           if (!complex) {
@@ -292,11 +300,10 @@ __global__ __launch_bounds__(256) void k_walk(const int32_t* __restrict__ list, 
             }
           }
           ++L;
-          twh = r.tw(ci);
           ci = next_local(ci);
         } else {
           // internal edge: cross it, turning about the current vertex
-          const int32_t tw = r.tw(ci);
+          const int32_t tw = wv;
           if ((uint32_t)tw >= (uint32_t)nhe || ++steps > nhe) {
             result = kInvalid;
             done = true;
@@ -304,7 +311,7 @@ __global__ __launch_bounds__(256) void k_walk(const int32_t* __restrict__ list, 
           }
           t = tw / 3;
           ci = next_local(tw - 3 * t);
-          rn.load(t, twin, origin, lab4);
+          rn.load(t, wk);
           pending = true;
         }
       }
@@ -746,7 +753,7 @@ struct Region {
 // -1 if it has more than kcap triangles, -2 on an invalid mesh.
 template <typename A>
 __device__ int gather_region(const Region<A>& R, int32_t t0, int kcap, int32_t nhe, const int32_t* __restrict__ twin,
-                             const int32_t* __restrict__ origin, const uint32_t* __restrict__ lab4) {
+                             const int32_t* __restrict__ origin, const int32_t* __restrict__ wk) {
   R.tri[0] = t0;
   R.lnk[0] = R.lnk[1] = R.lnk[2] = kUnset;
   int head = 0, tail = 1, status = 0;
@@ -755,7 +762,7 @@ __device__ int gather_region(const Region<A>& R, int32_t t0, int kcap, int32_t n
     TriRec rr[kGather];
 #pragma unroll
     for (int u = 0; u < kGather; ++u)
-      if (u < n) rr[u].load(R.tri[head + u], twin, origin, lab4);
+      if (u < n) rr[u].load(R.tri[head + u], twin, origin, wk);
 #pragma unroll
     for (int u = 0; u < kGather; ++u) {
       if (u >= n) continue;
@@ -765,7 +772,7 @@ __device__ int gather_region(const Region<A>& R, int32_t t0, int kcap, int32_t n
         R.org[3 * s + e] = rr[u].org(e);
         if (R.lnk[3 * s + e] != kUnset) continue;  // the edge it was entered through
         const int32_t tw = rr[u].tw(e);
-        if (rr[u].lab(e) & kFrontier) {
+        if (rr[u].frontier(e)) {
           R.lnk[3 * s + e] = tw < 0 ? -1 : -2 - tw;
         } else if ((uint32_t)tw >= (uint32_t)nhe) {
           R.lnk[3 * s + e] = -1;
@@ -1246,7 +1253,7 @@ template <bool REPAIR>
 __global__ __launch_bounds__(64) void k_general_small(const int32_t* __restrict__ list, bool from_seeds,
                                                       int32_t nhe, int64_t nv, const int32_t* __restrict__ twin,
                                                       const int32_t* __restrict__ origin,
-                                                      const uint32_t* __restrict__ lab4, uint8_t* __restrict__ he,
+                                                      const int32_t* __restrict__ wk, uint8_t* __restrict__ he,
                                                       uint8_t* __restrict__ vtx, int32_t* __restrict__ stage,
                                                       int64_t stage_cap, int32_t* __restrict__ arena,
                                                       int64_t arena_cap, PolyState ps,
@@ -1271,7 +1278,7 @@ __global__ __launch_bounds__(64) void k_general_small(const int32_t* __restrict_
       set_error(cnt, POLYLLA_ETOPO);
       continue;
     }
-    const int k = gather_region(R, t0, kSmallK, nhe, twin, origin, lab4);
+    const int k = gather_region(R, t0, kSmallK, nhe, twin, origin, wk);
     if (k == -2) {
       set_error(cnt, POLYLLA_ETOPO);
       continue;
@@ -1463,7 +1470,7 @@ __device__ __forceinline__ void push_over(int32_t* over, int64_t over_cap, uint3
 template <bool REPAIR, int NT, int KC, int LC, int HB>
 __global__ __launch_bounds__(NT) void k_general_big(
     const int32_t* __restrict__ list, bool from_seeds, int32_t nhe, int64_t nv, const int32_t* __restrict__ twin,
-    const int32_t* __restrict__ origin, const uint32_t* __restrict__ lab4, uint8_t* __restrict__ he,
+    const int32_t* __restrict__ origin, const int32_t* __restrict__ wk, uint8_t* __restrict__ he,
     uint8_t* __restrict__ vtx, int32_t* __restrict__ stage, int64_t stage_cap, int32_t* __restrict__ arena,
     int64_t arena_cap, PolyState ps, const int32_t* __restrict__ in, bool in_rev, int64_t in_cap,
     const uint32_t* in_count, uint32_t* in_ticket, int32_t* __restrict__ over, int64_t over_cap,
@@ -1535,17 +1542,17 @@ __global__ __launch_bounds__(NT) void k_general_big(
         const uint32_t qj = (uint32_t)S.q[j];
         const int32_t t = (int32_t)(qj & kSlotTri);
         const int entry = (int)(qj >> 30) - 1;
-        // label word, twin and origin triples of the triangle: one round trip
+        // walk, twin and origin triples of the triangle: one round trip
         const Int3 tw3 = *reinterpret_cast<const Int3*>(twin + 3 * t);
         const Int3 or3 = *reinterpret_cast<const Int3*>(origin + 3 * t);
-        const uint32_t lw = lab4[t];
+        const Int3 wk3 = *reinterpret_cast<const Int3*>(wk + 3 * t);
 #pragma unroll
         for (int e = 0; e < 3; ++e) {
           const int32_t h = 3 * t + e;
           if constexpr (BigLds<KC, LC, HB>::kOrg) S.org[3 * j + e] = sel3(or3.x, or3.y, or3.z, e);
           if (e == entry) continue;  // (its link was set by the parent)
           const int32_t tw = sel3(tw3.x, tw3.y, tw3.z, e);
-          if ((lw >> (8 * e)) & kFrontier) {
+          if (sel3(wk3.x, wk3.y, wk3.z, e) < 0) {  // frontier
             const int idx = atomicAdd(&S.sc[SC_NFH], 1);
             if (idx < kLCap) {
               S.fh[idx] = h;
@@ -2234,16 +2241,16 @@ __global__ __launch_bounds__(256) void k_batch_offsets(int64_t n_meshes, const i
   }
 }
 
-template __global__ void k_walk<true>(const int32_t*, int32_t, const int32_t*, const int32_t*, const uint32_t*,
+template __global__ void k_walk<true>(const int32_t*, int32_t, const int32_t*,
                                       int32_t*, int64_t, PolyState, int32_t*, int64_t, int, Counters*);
-template __global__ void k_walk<false>(const int32_t*, int32_t, const int32_t*, const int32_t*, const uint32_t*,
+template __global__ void k_walk<false>(const int32_t*, int32_t, const int32_t*,
                                        int32_t*, int64_t, PolyState, int32_t*, int64_t, int, Counters*);
 template __global__ void k_general_small<true>(const int32_t*, bool, int32_t, int64_t, const int32_t*,
-                                               const int32_t*, const uint32_t*, uint8_t*, uint8_t*, int32_t*,
+                                               const int32_t*, const int32_t*, uint8_t*, uint8_t*, int32_t*,
                                                int64_t, int32_t*, int64_t, PolyState, const int32_t*,
                                                const uint32_t*, uint32_t, Counters*);
 template __global__ void k_general_small<false>(const int32_t*, bool, int32_t, int64_t, const int32_t*,
-                                                const int32_t*, const uint32_t*, uint8_t*, uint8_t*, int32_t*,
+                                                const int32_t*, const int32_t*, uint8_t*, uint8_t*, int32_t*,
                                                 int64_t, int32_t*, int64_t, PolyState, const int32_t*,
                                                 const uint32_t*, uint32_t, Counters*);
 template __global__ void k_tip<true>(int32_t, int64_t, const int32_t*, const int32_t*, uint8_t*, uint8_t*, int32_t*,
@@ -2253,19 +2260,19 @@ template __global__ void k_tip<false>(int32_t, int64_t, const int32_t*, const in
                                       int64_t, int32_t*, int64_t, PolyState, const int32_t*, int32_t*, int64_t,
                                       Counters*);
 template __global__ void k_general_big<true, 64, 128, 128, 8>(
-    const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*, const uint32_t*, uint8_t*, uint8_t*,
+    const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*, const int32_t*, uint8_t*, uint8_t*,
     int32_t*, int64_t, int32_t*, int64_t, PolyState, const int32_t*, bool, int64_t, const uint32_t*, uint32_t*,
     int32_t*, int64_t, uint32_t*, const int32_t*, int64_t, const uint32_t*, uint32_t, uint32_t, Counters*);
 template __global__ void k_general_big<true, 1024, 4096, 4096, 13>(
-    const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*, const uint32_t*, uint8_t*, uint8_t*,
+    const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*, const int32_t*, uint8_t*, uint8_t*,
     int32_t*, int64_t, int32_t*, int64_t, PolyState, const int32_t*, bool, int64_t, const uint32_t*, uint32_t*,
     int32_t*, int64_t, uint32_t*, const int32_t*, int64_t, const uint32_t*, uint32_t, uint32_t, Counters*);
 template __global__ void k_general_big<false, 64, 128, 128, 8>(
-    const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*, const uint32_t*, uint8_t*, uint8_t*,
+    const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*, const int32_t*, uint8_t*, uint8_t*,
     int32_t*, int64_t, int32_t*, int64_t, PolyState, const int32_t*, bool, int64_t, const uint32_t*, uint32_t*,
     int32_t*, int64_t, uint32_t*, const int32_t*, int64_t, const uint32_t*, uint32_t, uint32_t, Counters*);
 template __global__ void k_general_big<false, 1024, 4096, 4096, 13>(
-    const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*, const uint32_t*, uint8_t*, uint8_t*,
+    const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*, const int32_t*, uint8_t*, uint8_t*,
     int32_t*, int64_t, int32_t*, int64_t, PolyState, const int32_t*, bool, int64_t, const uint32_t*, uint32_t*,
     int32_t*, int64_t, uint32_t*, const int32_t*, int64_t, const uint32_t*, uint32_t, uint32_t, Counters*);
 template __global__ void k_general_huge<true>(const int32_t*, bool, int32_t, int64_t, const int32_t*,

@@ -8,8 +8,10 @@
 // k_label   : one tile of 2048 triangles per block, eight consecutive
 //             triangles per thread so that twin, Max and the label bytes move
 //             as 16-byte and 4-byte vectors. Writes the half-edge labels and
-//             the SEED flag, and the tile's seed count (also added to the sum
-//             of its group of 64 tiles).
+//             the SEED flag, the walk word of every half-edge (the twin of
+//             an internal one, -1 - origin of a frontier one: all a polygon
+//             walk reads) and the tile's seed count (also added to the sum of
+//             its group of 64 tiles).
 // k_seeds   : the seed triangles in increasing index: each tile finds the
 //             seeds before it from the group sums and the counts of its own
 //             group, then places its seeds after them (no tile waits for
@@ -138,6 +140,34 @@ __device__ __forceinline__ uint32_t label_triangle(int64_t t, int m, const int32
 }
 
 constexpr int kLabelItems = 8;  // triangles per thread of k_label (multiple of 4)
+
+// 3 ITEMS consecutive words as 16-byte loads / stores (16-byte aligned).
+template <int ITEMS>
+__device__ __forceinline__ void load_words(const int32_t* __restrict__ src, int32_t (&w)[3 * ITEMS]) {
+  const int4* s4 = reinterpret_cast<const int4*>(src);
+#pragma unroll
+  for (int k = 0; k < 3 * ITEMS / 4; ++k) {
+    const int4 q = s4[k];
+    w[4 * k] = q.x;
+    w[4 * k + 1] = q.y;
+    w[4 * k + 2] = q.z;
+    w[4 * k + 3] = q.w;
+  }
+}
+template <int ITEMS>
+__device__ __forceinline__ void store_words(int32_t* __restrict__ dst, const int32_t (&w)[3 * ITEMS]) {
+  int4* d4 = reinterpret_cast<int4*>(dst);
+#pragma unroll
+  for (int k = 0; k < 3 * ITEMS / 4; ++k) d4[k] = make_int4(w[4 * k], w[4 * k + 1], w[4 * k + 2], w[4 * k + 3]);
+}
+
+// Walk words of one triangle, in place of its twins: the twin of an internal
+// half-edge, -1 - origin of a frontier one.
+__device__ __forceinline__ void walk_words(uint32_t lab, int32_t* tw, const int32_t* og) {
+#pragma unroll
+  for (int e = 0; e < 3; ++e)
+    if ((lab >> (8 * e)) & kFrontier) tw[e] = -1 - og[e];
+}
 constexpr int kLgMargin = 2048;  // Max bytes before and after a tile kept in LDS
 constexpr int kLgWin = 256 * kLabelItems + 2 * kLgMargin;
 
@@ -146,9 +176,9 @@ constexpr int kLgWin = 256 * kLabelItems + 2 * kLgMargin;
 template <bool COMPUTE>
 __global__ __launch_bounds__(256) void k_label(int64_t nt, const int32_t* __restrict__ twin,
                                                const uint8_t* __restrict__ lg, uint8_t* __restrict__ he,
-                                               uint8_t* __restrict__ tri, uint32_t* __restrict__ lab4,
-                                               uint32_t* __restrict__ tcount, uint32_t* __restrict__ tsuper,
-                                               Counters* cnt, bool vec) {
+                                               uint8_t* __restrict__ tri, const int32_t* __restrict__ origin,
+                                               int32_t* __restrict__ wk, uint32_t* __restrict__ tcount,
+                                               uint32_t* __restrict__ tsuper, Counters* cnt, bool vec) {
   constexpr int ITEMS = kLabelItems;
   const uint32_t tile = blockIdx.x;
   const int64_t t0 = ((int64_t)tile * 256 + threadIdx.x) * ITEMS;
@@ -156,11 +186,11 @@ __global__ __launch_bounds__(256) void k_label(int64_t nt, const int32_t* __rest
   bool sd[ITEMS];
   // Whole tiles stage their labels in LDS and write them with coalesced
   // 16-byte stores (the per-thread layout would write every line in pieces).
-  __shared__ uint4 s_w4[256 * ITEMS / 2];  // label words, then he words, then tri words of the tile
+  __shared__ uint4 s_w4[256 * ITEMS / 4];  // he words, then tri words of the tile
   const int64_t tile_t0 = (int64_t)tile * 256 * ITEMS;
   const bool full = COMPUTE && vec && tile_t0 + 256 * ITEMS <= nt &&
                     ((reinterpret_cast<uintptr_t>(he) | reinterpret_cast<uintptr_t>(tri) |
-                      reinterpret_cast<uintptr_t>(lab4)) & 15) == 0;
+                      reinterpret_cast<uintptr_t>(wk)) & 15) == 0;
   __shared__ uint4 s_lg4[kLgWin / 16];
   if (full) {
     // Max bytes of the tile and its margins (16-byte aligned: tiles and
@@ -181,19 +211,11 @@ __global__ __launch_bounds__(256) void k_label(int64_t nt, const int32_t* __rest
     __syncthreads();
     const LgView lgv{lg, reinterpret_cast<const uint8_t*>(s_lg4), wlo, kLgWin};
     uint32_t* s_w = reinterpret_cast<uint32_t*>(s_w4);
-    uint32_t* s_lab = s_w;
-    uint32_t* s_he = s_w + 256 * ITEMS;
-    uint32_t* s_tri = s_w + 256 * ITEMS + 256 * ITEMS * 3 / 4;
-    int32_t tw[3 * ITEMS];
-    const int4* tw4 = reinterpret_cast<const int4*>(twin + 3 * t0);
-#pragma unroll
-    for (int k = 0; k < 3 * ITEMS / 4; ++k) {
-      int4 q = tw4[k];
-      tw[4 * k] = q.x;
-      tw[4 * k + 1] = q.y;
-      tw[4 * k + 2] = q.z;
-      tw[4 * k + 3] = q.w;
-    }
+    uint32_t* s_he = s_w;
+    uint32_t* s_tri = s_w + 256 * ITEMS * 3 / 4;
+    int32_t tw[3 * ITEMS], og[3 * ITEMS];
+    load_words<ITEMS>(twin + 3 * t0, tw);
+    load_words<ITEMS>(origin + 3 * t0, og);
     uint32_t mm[ITEMS / 4];
 #pragma unroll
     for (int k = 0; k < ITEMS / 4; ++k)
@@ -203,36 +225,29 @@ __global__ __launch_bounds__(256) void k_label(int64_t nt, const int32_t* __rest
     for (int g = 0; g < ITEMS / 4; ++g) {
       uint32_t lab[4];
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
+      for (int j = 0; j < 4; ++j) {
         lab[j] = label_triangle(t0 + 4 * g + j, (mm[g] >> (8 * j)) & 0xFF, tw + 3 * (4 * g + j), lgv, nhe, cnt,
                                 &sd[4 * g + j]);
-      reinterpret_cast<uint4*>(s_lab + lt)[g] = make_uint4(lab[0], lab[1], lab[2], lab[3]);
+        walk_words(lab[j], tw + 3 * (4 * g + j), og + 3 * (4 * g + j));
+      }
       s_he[3 * (lt / 4 + g)] = lab[0] | (lab[1] << 24);
       s_he[3 * (lt / 4 + g) + 1] = (lab[1] >> 8) | (lab[2] << 16);
       s_he[3 * (lt / 4 + g) + 2] = (lab[2] >> 16) | (lab[3] << 8);
       s_tri[lt / 4 + g] = (sd[4 * g] ? kSeed : 0u) | ((sd[4 * g + 1] ? kSeed : 0u) << 8) |
                           ((sd[4 * g + 2] ? kSeed : 0u) << 16) | ((sd[4 * g + 3] ? kSeed : 0u) << 24);
     }
+    store_words<ITEMS>(wk + 3 * t0, tw);
     __syncthreads();
-    uint4* glab = reinterpret_cast<uint4*>(lab4 + tile_t0);
     uint4* ghe = reinterpret_cast<uint4*>(he + 3 * tile_t0);
     uint4* gtri = reinterpret_cast<uint4*>(tri + tile_t0);
-    for (int k = threadIdx.x; k < 256 * ITEMS / 4; k += 256) glab[k] = s_w4[k];
-    for (int k = threadIdx.x; k < 256 * ITEMS * 3 / 16; k += 256) ghe[k] = s_w4[256 * ITEMS / 4 + k];
-    for (int k = threadIdx.x; k < 256 * ITEMS / 16; k += 256) gtri[k] = s_w4[256 * ITEMS / 4 + 256 * ITEMS * 3 / 16 + k];
+    for (int k = threadIdx.x; k < 256 * ITEMS * 3 / 16; k += 256) ghe[k] = s_w4[k];
+    for (int k = threadIdx.x; k < 256 * ITEMS / 16; k += 256) gtri[k] = s_w4[256 * ITEMS * 3 / 16 + k];
   } else if (COMPUTE) {
     if (vec && t0 + ITEMS <= nt) {
-      // ITEMS triangles: 3*ITEMS twins as int4, ITEMS Max bytes and labels as words
-      int32_t tw[3 * ITEMS];
-      const int4* tw4 = reinterpret_cast<const int4*>(twin + 3 * t0);
-#pragma unroll
-      for (int k = 0; k < 3 * ITEMS / 4; ++k) {
-        int4 q = tw4[k];
-        tw[4 * k] = q.x;
-        tw[4 * k + 1] = q.y;
-        tw[4 * k + 2] = q.z;
-        tw[4 * k + 3] = q.w;
-      }
+      // ITEMS triangles: twins and origins as int4, ITEMS Max bytes and labels as words
+      int32_t tw[3 * ITEMS], og[3 * ITEMS];
+      load_words<ITEMS>(twin + 3 * t0, tw);
+      load_words<ITEMS>(origin + 3 * t0, og);
       uint32_t mm[ITEMS / 4];
 #pragma unroll
       for (int k = 0; k < ITEMS / 4; ++k) mm[k] = reinterpret_cast<const uint32_t*>(lg + t0)[k];
@@ -242,11 +257,11 @@ __global__ __launch_bounds__(256) void k_label(int64_t nt, const int32_t* __rest
       for (int g = 0; g < ITEMS / 4; ++g) {
         uint32_t lab[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-          lab[j] = label_triangle(t0 + 4 * g + j, (mm[g] >> (8 * j)) & 0xFF, tw + 3 * (4 * g + j), LgView{lg, nullptr, 0, 0}, nhe, cnt,
-                                  &sd[4 * g + j]);
-        // packed label word per triangle for the walk (aligned 16-byte store)
-        reinterpret_cast<uint4*>(lab4 + t0)[g] = make_uint4(lab[0], lab[1], lab[2], lab[3]);
+        for (int j = 0; j < 4; ++j) {
+          lab[j] = label_triangle(t0 + 4 * g + j, (mm[g] >> (8 * j)) & 0xFF, tw + 3 * (4 * g + j),
+                                  LgView{lg, nullptr, 0, 0}, nhe, cnt, &sd[4 * g + j]);
+          walk_words(lab[j], tw + 3 * (4 * g + j), og + 3 * (4 * g + j));
+        }
         // 12 label bytes of 4 triangles -> three 32-bit words
         he4[3 * g] = lab[0] | (lab[1] << 24);
         he4[3 * g + 1] = (lab[1] >> 8) | (lab[2] << 16);
@@ -254,6 +269,7 @@ __global__ __launch_bounds__(256) void k_label(int64_t nt, const int32_t* __rest
         tr4[g] = (sd[4 * g] ? kSeed : 0u) | ((sd[4 * g + 1] ? kSeed : 0u) << 8) |
                  ((sd[4 * g + 2] ? kSeed : 0u) << 16) | ((sd[4 * g + 3] ? kSeed : 0u) << 24);
       }
+      store_words<ITEMS>(wk + 3 * t0, tw);
     } else {
 #pragma unroll
       for (int j = 0; j < ITEMS; ++j) {
@@ -261,8 +277,12 @@ __global__ __launch_bounds__(256) void k_label(int64_t nt, const int32_t* __rest
         const int64_t t = t0 + j;
         if (t >= nt) continue;
         int32_t tw[3] = {twin[3 * t], twin[3 * t + 1], twin[3 * t + 2]};
+        const int32_t og[3] = {origin[3 * t], origin[3 * t + 1], origin[3 * t + 2]};
         uint32_t lab = label_triangle(t, lg[t], tw, LgView{lg, nullptr, 0, 0}, nhe, cnt, &sd[j]);
-        lab4[t] = lab;
+        walk_words(lab, tw, og);
+        wk[3 * t] = tw[0];
+        wk[3 * t + 1] = tw[1];
+        wk[3 * t + 2] = tw[2];
         he[3 * t] = (uint8_t)lab;
         he[3 * t + 1] = (uint8_t)(lab >> 8);
         he[3 * t + 2] = (uint8_t)(lab >> 16);
@@ -354,17 +374,17 @@ __global__ __launch_bounds__(256) void k_validate(int64_t nhe, int64_t nv, const
   }
 }
 
-template __global__ void k_label<true>(int64_t, const int32_t*, const uint8_t*, uint8_t*, uint8_t*, uint32_t*,
-                                       uint32_t*, uint32_t*, Counters*, bool);
-template __global__ void k_label<false>(int64_t, const int32_t*, const uint8_t*, uint8_t*, uint8_t*, uint32_t*,
-                                        uint32_t*, uint32_t*, Counters*, bool);
+template __global__ void k_label<true>(int64_t, const int32_t*, const uint8_t*, uint8_t*, uint8_t*, const int32_t*,
+                                       int32_t*, uint32_t*, uint32_t*, Counters*, bool);
+template __global__ void k_label<false>(int64_t, const int32_t*, const uint8_t*, uint8_t*, uint8_t*, const int32_t*,
+                                        int32_t*, uint32_t*, uint32_t*, Counters*, bool);
 
-// Packed label word per triangle (three label bytes) from the half-edge
-// labels, for calls that start from existing labels.
-__global__ __launch_bounds__(256) void k_pack_labels(int64_t nt, const uint8_t* __restrict__ he,
-                                                     uint32_t* __restrict__ lab4) {
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nt; t += (int64_t)gridDim.x * blockDim.x)
-    lab4[t] = (uint32_t)he[3 * t] | ((uint32_t)he[3 * t + 1] << 8) | ((uint32_t)he[3 * t + 2] << 16);
+// Walk words from existing half-edge labels, for calls that start from them.
+__global__ __launch_bounds__(256) void k_pack_walk(int64_t nhe, const uint8_t* __restrict__ he,
+                                                   const int32_t* __restrict__ twin,
+                                                   const int32_t* __restrict__ origin, int32_t* __restrict__ wk) {
+  for (int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; h < nhe; h += (int64_t)gridDim.x * blockDim.x)
+    wk[h] = (he[h] & kFrontier) ? -1 - origin[h] : twin[h];
 }
 
 }  // namespace polylla

@@ -78,7 +78,7 @@ struct polylla_ctx {
   Counters last{};
   int walk_cap = 24;  // vertices a lane walks before handing a polygon to a workgroup
   uint32_t gen_wave_max = kGenWaveMax;  // declined short polygons up to which each gets a wave
-  int walk_blocks = 768;  // persistent grid of the walk kernel: three 49 KB workgroups per CU (swept at 10M)
+  int walk_blocks = 640;  // persistent grid of the walk kernel (swept at 10M: 512 851, 640 782, 768 791 us)
   // second stream: the workgroup region kernel runs beside the per-lane one
   // (they touch disjoint regions); fork and join through events
   hipStream_t side = nullptr;

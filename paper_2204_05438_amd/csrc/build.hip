@@ -227,8 +227,7 @@ __global__ __launch_bounds__(256) void k_walk(const int32_t* __restrict__ list, 
         minhe = -1;
         result = kSimple;
         if ((uint32_t)t < (uint32_t)nt && (FROM_SEEDS || item >= 0)) {
-          rn.load(t, wk);
-          pending = true;
+          pending = true;  // (loaded below)
           s = FROM_SEEDS ? -1 : item;  // -1: start not found yet
           ci = FROM_SEEDS ? 0 : item - 3 * t;
         } else {
@@ -253,7 +252,6 @@ __global__ __launch_bounds__(256) void k_walk(const int32_t* __restrict__ list, 
           } else {
             t = tw / 3;
             ci = next_local(tw - 3 * t);
-            rn.load(t, wk);
             pending = true;
           }
         } else {
@@ -311,11 +309,13 @@ __global__ __launch_bounds__(256) void k_walk(const int32_t* __restrict__ list, 
           }
           t = tw / 3;
           ci = next_local(tw - 3 * t);
-          rn.load(t, wk);
           pending = true;
         }
       }
     }
+    // one load site: the record of the triangle every lane that crossed an
+    // edge (or took a new polygon) enters next, consumed next iteration
+    if (pending) rn.load(t, wk);
     // ---- finished lanes: stage complete cycles (packed per wave, unrotated:
     // the emitter starts each at slot minpos, its smallest vertex), queue the others
     const bool fin = idx >= 0 && done;
@@ -338,19 +338,38 @@ __global__ __launch_bounds__(256) void k_walk(const int32_t* __restrict__ list, 
         sbase = __shfl(nb, 0, 64);
         sleft = want_ints;
       }
+      const bool fits = sbase + tot <= stage_cap;
       if (fin_simple || fin_small) {
         const int64_t off = sbase + incl - need;
-        if (off + need > stage_cap) {
+        if (!fits) {
           set_error(cnt, POLYLLA_ENOMEM);
           ps.clear(idx);
         } else if (fin_simple) {
-          for (int k = 0; k < L; ++k) stage[off + k] = buf[k][threadIdx.x];
           ps.set(idx, L, 1 | (minpos << kRotShift), minhe, (int32_t)off);
         } else {
           // no output yet (pieces 0): cycle vertices, then its half-edges
-          for (int k = 0; k < L; ++k) stage[off + k] = buf[k][threadIdx.x];
-          for (int k = 0; k < L; ++k) stage[off + L + k] = hbuf[k][threadIdx.x];
           ps.set(idx, L, 0, -1, (int32_t)off);
+        }
+      }
+      // the staged words of all finished lanes, copied by the whole wave with
+      // coalesced stores: word k belongs to the first lane whose inclusive
+      // offset exceeds k (binary search over the 64 offsets by lane shuffles)
+      if (fits) {
+        const int col0 = threadIdx.x & ~63;
+        for (int32_t k0 = 0; k0 < tot; k0 += 64) {
+          const int32_t k = k0 + lane;
+          int f = 0;
+#pragma unroll
+          for (int step = 32; step > 0; step >>= 1) {
+            const uint32_t v = __shfl(incl, f + step - 1, 64);
+            if (v <= (uint32_t)k) f += step;
+          }
+          const int32_t start = (int32_t)__shfl(incl - need, f, 64);
+          const int32_t lf = __shfl(L, f, 64);
+          if (k < tot) {
+            const int32_t loc = k - start;
+            stage[sbase + k] = loc < lf ? buf[loc][col0 + f] : hbuf[loc - lf][col0 + f];
+          }
         }
       }
       sbase += tot;

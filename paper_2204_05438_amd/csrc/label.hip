@@ -5,9 +5,10 @@
 //             squared edge lengths in binary64 (each product and sum rounded,
 //             no fused multiply-add) and writes the local index of the longest
 //             edge (the paper's Max array) as one byte per triangle.
-// k_label   : one tile of 2048 triangles per block, eight consecutive
-//             triangles per thread so that twin, Max and the label bytes move
-//             as 16-byte and 4-byte vectors. Writes the half-edge labels and
+// k_label   : one tile of 2048 triangles per block, eight per thread; in
+//             whole tiles lane l of a wave takes every 64th triangle from l,
+//             so twin, origin and walk-word accesses of a wave are contiguous
+//             12-byte triples. Writes the half-edge labels and
 //             the SEED flag, the walk word of every half-edge (the twin of
 //             an internal one, -1 - origin of a frontier one: all a polygon
 //             walk reads) and the tile's seed count (also added to the sum of
@@ -20,6 +21,10 @@
 #include "scan.h"
 
 namespace polylla {
+
+struct alignas(4) Int3 {
+  int32_t x, y, z;
+};
 
 __device__ __forceinline__ double sq_length(double2 a, double2 b) {
   double dx = __dsub_rn(b.x, a.x);
@@ -62,7 +67,8 @@ __global__ __launch_bounds__(256) void k_longest(int64_t nt, int64_t nv, const d
   const double2* __restrict__ p = reinterpret_cast<const double2*>(xy);
   for (int64_t t = gid; t < nt; t += stride) {
     const int32_t h0 = (int32_t)(3 * t);
-    int32_t a = origin[h0], b = origin[h0 + 1], c = origin[h0 + 2];
+    const Int3 o3 = *reinterpret_cast<const Int3*>(origin + h0);  // one 12-byte load
+    const int32_t a = o3.x, b = o3.y, c = o3.z;
     if ((uint64_t)(uint32_t)a >= (uint64_t)nv || (uint64_t)(uint32_t)b >= (uint64_t)nv ||
         (uint64_t)(uint32_t)c >= (uint64_t)nv) {
       set_error(cnt, POLYLLA_ETOPO);
@@ -184,8 +190,8 @@ __global__ __launch_bounds__(256) void k_label(int64_t nt, const int32_t* __rest
   const int64_t t0 = ((int64_t)tile * 256 + threadIdx.x) * ITEMS;
   const int32_t nhe = (int32_t)(3 * nt);
   bool sd[ITEMS];
-  // Whole tiles stage their labels in LDS and write them with coalesced
-  // 16-byte stores (the per-thread layout would write every line in pieces).
+  // Whole tiles stage their label bytes in LDS and write them with coalesced
+  // 16-byte stores.
   __shared__ uint4 s_w4[256 * ITEMS / 4];  // he words, then tri words of the tile
   const int64_t tile_t0 = (int64_t)tile * 256 * ITEMS;
   const bool full = COMPUTE && vec && tile_t0 + 256 * ITEMS <= nt &&
@@ -210,33 +216,39 @@ __global__ __launch_bounds__(256) void k_label(int64_t nt, const int32_t* __rest
     }
     __syncthreads();
     const LgView lgv{lg, reinterpret_cast<const uint8_t*>(s_lg4), wlo, kLgWin};
-    uint32_t* s_w = reinterpret_cast<uint32_t*>(s_w4);
-    uint32_t* s_he = s_w;
-    uint32_t* s_tri = s_w + 256 * ITEMS * 3 / 4;
-    int32_t tw[3 * ITEMS], og[3 * ITEMS];
-    load_words<ITEMS>(twin + 3 * t0, tw);
-    load_words<ITEMS>(origin + 3 * t0, og);
-    uint32_t mm[ITEMS / 4];
+    // interleaved: lane l of wave w takes triangles tile_t0 + 512 w + l + 64 k,
+    // so every twin / origin / walk-word access of a wave covers 768
+    // contiguous bytes
+    uint8_t* s_heb = reinterpret_cast<uint8_t*>(s_w4);
+    uint8_t* s_trib = s_heb + 256 * ITEMS * 3;
+    const int lane = threadIdx.x & 63;
+    const int wbase = (threadIdx.x >> 6) * 64 * ITEMS;  // tile-local first triangle of the wave
+    Int3 tw3[ITEMS], og3[ITEMS];
 #pragma unroll
-    for (int k = 0; k < ITEMS / 4; ++k)
-      mm[k] = reinterpret_cast<const uint32_t*>(s_lg4)[(kLgMargin + threadIdx.x * ITEMS) / 4 + k];
-    const int lt = threadIdx.x * ITEMS;  // first triangle of this thread within the tile
-#pragma unroll
-    for (int g = 0; g < ITEMS / 4; ++g) {
-      uint32_t lab[4];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        lab[j] = label_triangle(t0 + 4 * g + j, (mm[g] >> (8 * j)) & 0xFF, tw + 3 * (4 * g + j), lgv, nhe, cnt,
-                                &sd[4 * g + j]);
-        walk_words(lab[j], tw + 3 * (4 * g + j), og + 3 * (4 * g + j));
-      }
-      s_he[3 * (lt / 4 + g)] = lab[0] | (lab[1] << 24);
-      s_he[3 * (lt / 4 + g) + 1] = (lab[1] >> 8) | (lab[2] << 16);
-      s_he[3 * (lt / 4 + g) + 2] = (lab[2] >> 16) | (lab[3] << 8);
-      s_tri[lt / 4 + g] = (sd[4 * g] ? kSeed : 0u) | ((sd[4 * g + 1] ? kSeed : 0u) << 8) |
-                          ((sd[4 * g + 2] ? kSeed : 0u) << 16) | ((sd[4 * g + 3] ? kSeed : 0u) << 24);
+    for (int k = 0; k < ITEMS; ++k) {
+      const int64_t t = tile_t0 + wbase + lane + 64 * k;
+      tw3[k] = *reinterpret_cast<const Int3*>(twin + 3 * t);
+      og3[k] = *reinterpret_cast<const Int3*>(origin + 3 * t);
     }
-    store_words<ITEMS>(wk + 3 * t0, tw);
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+      const int lt = wbase + lane + 64 * k;
+      const int64_t t = tile_t0 + lt;
+      int32_t tw[3] = {tw3[k].x, tw3[k].y, tw3[k].z};
+      const int32_t og[3] = {og3[k].x, og3[k].y, og3[k].z};
+      const uint32_t lab = label_triangle(t, reinterpret_cast<const uint8_t*>(s_lg4)[kLgMargin + lt], tw, lgv, nhe,
+                                          cnt, &sd[k]);
+      walk_words(lab, tw, og);
+      Int3 w3;
+      w3.x = tw[0];
+      w3.y = tw[1];
+      w3.z = tw[2];
+      *reinterpret_cast<Int3*>(wk + 3 * t) = w3;
+      s_heb[3 * lt] = (uint8_t)lab;
+      s_heb[3 * lt + 1] = (uint8_t)(lab >> 8);
+      s_heb[3 * lt + 2] = (uint8_t)(lab >> 16);
+      s_trib[lt] = sd[k] ? kSeed : 0;
+    }
     __syncthreads();
     uint4* ghe = reinterpret_cast<uint4*>(he + 3 * tile_t0);
     uint4* gtri = reinterpret_cast<uint4*>(tri + tile_t0);

@@ -130,6 +130,17 @@ def test_declined_short_polygon_paths(ctx, kind, wave_max):
         ctx.set_param(lib.PARAM_GEN_WAVE_MAX, 8192)
 
 
+@pytest.mark.parametrize("walk_cap,many", [(24, False), (4, True)])
+def test_long_region_routes(ctx, walk_cap, many):
+    """At most 128 long polygons go straight to the 1024-thread region kernel;
+    more go through the one-wave kernel first (its overflow to the former)."""
+    _say(f"long-region route walk_cap {walk_cap}")
+    mesh = random_mesh(1400, 20000, "uniform")
+    r = gpu_mesh(ctx, mesh, walk_cap)
+    assert (r["stats"]["general_big"] > 128) == many, r["stats"]
+    assert_same(r, oracle.oracle_on(mesh), FULL)
+
+
 def test_empty(ctx):
     _say("empty mesh")
     r = gpu_mesh(ctx, empty_mesh())

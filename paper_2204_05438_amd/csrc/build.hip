@@ -2107,7 +2107,42 @@ __global__ __launch_bounds__(256) void k_scan_emit(PolyState ps, uint64_t* statu
   }
   uint2 total;
   const uint2 pre = block_exclusive_scan<256>(a, b, &total);
-  const uint2 ex = tile_lookback(status, tile, total, cnt);
+  tile_publish(status, tile, total);
+  // Tile-local staging before the look-back (so that it overlaps the wait
+  // for earlier tiles): per input polygon its first vertex slot, staging
+  // offset and rotation; per output polygon its tile-local vertex offset and
+  // start half-edge.
+  const bool fit = total.x <= (uint32_t)kScanOut;
+  {
+    uint32_t ra = pre.x, rb = pre.y;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+      const int64_t i = i0 + j;
+      const int k = threadIdx.x * kScanItems + j;
+      const int32_t nl = rc[j].x, np = rc[j].y & kPiecesMask, rot = (int32_t)((uint32_t)rc[j].y >> kRotShift);
+      s_voff[k] = (int32_t)rb;
+      s_src[k] = nl > 0 ? rc[j].w : 0;
+      s_rot[k] = rot;
+      if (fit && i < R && np > 0) {
+        if (np == 1) {
+          s_po[ra] = (int32_t)rb;
+          s_ps[ra] = rc[j].z;
+        } else {
+          const int32_t* rec = arena + ps.prec[i];
+          int32_t acc = 0;
+          for (int32_t q = 0; q < np; ++q) {
+            s_po[ra + q] = (int32_t)rb + acc;
+            s_ps[ra + q] = rec[4 * q + 2];
+            acc += rec[4 * q + 3];
+          }
+        }
+      }
+      ra += (uint32_t)np;
+      rb += (uint32_t)nl;
+    }
+    if (threadIdx.x == 255) s_voff[kScanTile] = (int32_t)rb;
+  }
+  const uint2 ex = tile_lookback(status, tile, total, cnt, true);  // (its barriers publish the staging)
   const int64_t tile_v0 = ex.y, tile_v1 = (int64_t)ex.y + total.y;
   const int64_t tile_p1 = (int64_t)ex.x + total.x;
   if (threadIdx.x == 0) s_ok = (tile_p1 <= cap_polys && tile_v1 <= cap_verts) ? 1 : 0;
@@ -2119,54 +2154,36 @@ __global__ __launch_bounds__(256) void k_scan_emit(PolyState ps, uint64_t* statu
   __syncthreads();
   const bool ok = s_ok != 0;
   if (!ok && threadIdx.x == 0) set_error(cnt, POLYLLA_ECAPACITY);
-  // per-polygon offsets and start half-edges (staged in LDS when the tile's
-  // output polygons fit, then stored coalesced); tile-local vertex offsets
-  const bool fit = total.x <= (uint32_t)kScanOut;
-  uint32_t ra = ex.x + pre.x, rb = pre.y;
-#pragma unroll
-  for (int j = 0; j < kScanItems; ++j) {
-    const int64_t i = i0 + j;
-    const int k = threadIdx.x * kScanItems + j;
-    const int32_t nl = rc[j].x, np = rc[j].y & kPiecesMask, rot = (int32_t)((uint32_t)rc[j].y >> kRotShift);
-    s_voff[k] = (int32_t)rb;
-    s_src[k] = nl > 0 ? rc[j].w : 0;
-    s_rot[k] = rot;
-    if (ok && i < R && np > 0) {
-      const int32_t vg = (int32_t)(tile_v0 + rb);
-      const uint32_t lp = ra - ex.x;  // tile-local output polygon
-      if (np == 1) {
-        if (fit) {
-          s_po[lp] = vg;
-          s_ps[lp] = rc[j].z;
-        } else {
-          offsets[ra] = vg;
-          if (start) start[ra] = rc[j].z;
-        }
-      } else {
-        const int32_t* rec = arena + ps.prec[i];
-        int32_t acc = 0;
-        for (int32_t q = 0; q < np; ++q) {
-          if (fit) {
-            s_po[lp + q] = vg + acc;
-            s_ps[lp + q] = rec[4 * q + 2];
-          } else {
-            offsets[ra + q] = vg + acc;
-            if (start) start[ra + q] = rec[4 * q + 2];
-          }
-          acc += rec[4 * q + 3];
-        }
-      }
-    }
-    ra += (uint32_t)np;
-    rb += (uint32_t)nl;
-  }
-  if (threadIdx.x == 255) s_voff[kScanTile] = (int32_t)rb;
-  __syncthreads();
   if (!ok) return;
   if (fit) {
     for (uint32_t k = threadIdx.x; k < total.x; k += 256) {
-      offsets[ex.x + k] = s_po[k];
+      offsets[ex.x + k] = (int32_t)(tile_v0 + s_po[k]);
       if (start) start[ex.x + k] = s_ps[k];
+    }
+  } else {
+    // more output polygons than the LDS staging holds: direct stores
+    uint32_t ra = ex.x + pre.x, rb = pre.y;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+      const int64_t i = i0 + j;
+      const int32_t nl = rc[j].x, np = rc[j].y & kPiecesMask;
+      if (i < R && np > 0) {
+        const int32_t vg = (int32_t)(tile_v0 + rb);
+        if (np == 1) {
+          offsets[ra] = vg;
+          if (start) start[ra] = rc[j].z;
+        } else {
+          const int32_t* rec = arena + ps.prec[i];
+          int32_t acc = 0;
+          for (int32_t q = 0; q < np; ++q) {
+            offsets[ra + q] = vg + acc;
+            if (start) start[ra + q] = rec[4 * q + 2];
+            acc += rec[4 * q + 3];
+          }
+        }
+      }
+      ra += (uint32_t)np;
+      rb += (uint32_t)nl;
     }
   }
   // the tile's vertex range, coalesced: every slot finds its polygon by

@@ -61,17 +61,27 @@ __device__ __forceinline__ uint2 block_exclusive_scan(uint32_t a, uint32_t b, ui
   return make_uint2(oa + ia - a, ob + ib - b);
 }
 
+// Publishes this tile's sums for later tiles (its prefix if it is tile 0).
+// Call once per tile, as early as the sums are known; tile_lookback then
+// gives the exclusive prefix.
+__device__ __forceinline__ void tile_publish(uint64_t* status, uint32_t tile, uint2 agg) {
+  if (threadIdx.x == 0)
+    status_store(&status[tile], (tile == 0 ? kStatPrefix : kStatAggregate) | pack_pair(agg.x, agg.y));
+}
+
 // Exclusive prefix of tile `tile` across the grid, given this tile's sums.
-// Called by every thread of the block; all get the same result.
-__device__ __forceinline__ uint2 tile_lookback(uint64_t* status, uint32_t tile, uint2 agg, Counters* cnt) {
+// Called by every thread of the block; all get the same result. With
+// `published`, tile_publish has already been called for this tile.
+__device__ __forceinline__ uint2 tile_lookback(uint64_t* status, uint32_t tile, uint2 agg, Counters* cnt,
+                                               bool published = false) {
   __shared__ uint2 s_ex;
   if (threadIdx.x < 64) {
     const int lane = threadIdx.x;
     uint32_t ea = 0, eb = 0;
     if (tile == 0) {
-      if (lane == 0) status_store(&status[0], kStatPrefix | pack_pair(agg.x, agg.y));
+      if (lane == 0 && !published) status_store(&status[0], kStatPrefix | pack_pair(agg.x, agg.y));
     } else {
-      if (lane == 0) status_store(&status[tile], kStatAggregate | pack_pair(agg.x, agg.y));
+      if (lane == 0 && !published) status_store(&status[tile], kStatAggregate | pack_pair(agg.x, agg.y));
       int64_t base = (int64_t)tile - 1;
       uint32_t spins = 0;
       for (;;) {

@@ -2187,9 +2187,11 @@ __global__ __launch_bounds__(256) void k_scan_emit(PolyState ps, uint64_t* statu
     }
   }
   // the tile's vertex range, coalesced: every slot finds its polygon by
-  // binary search in LDS, eight independent searches in lockstep per thread
+  // binary search in LDS, eight independent searches in lockstep per thread;
+  // the searches of the next eight slots run while the staging words of the
+  // current ones are being loaded
   const int32_t nv_tile = (int32_t)total.y;
-  for (int32_t k0 = threadIdx.x; k0 < nv_tile; k0 += 8 * 256) {
+  auto locate = [&](int32_t k0, int32_t (&src)[8]) {
     int lo[8], hi[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
@@ -2205,20 +2207,27 @@ __global__ __launch_bounds__(256) void k_scan_emit(PolyState ps, uint64_t* statu
         else hi[u] = mid;
       }
     }
-    int32_t v[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int32_t k = k0 + 256 * u;
-      if (k < nv_tile) {
-        const int32_t len = s_voff[lo[u] + 1] - s_voff[lo[u]];
-        int32_t off = k - s_voff[lo[u]] + s_rot[lo[u]];
-        off = off >= len ? off - len : off;
-        v[u] = stage[s_src[lo[u]] + off];
-      }
+      const int32_t len = s_voff[lo[u] + 1] - s_voff[lo[u]];
+      int32_t off = k - s_voff[lo[u]] + s_rot[lo[u]];
+      off = off >= len ? off - len : off;
+      src[u] = k < nv_tile ? s_src[lo[u]] + off : -1;
     }
+  };
+  int32_t src[8], v[8];
+  int32_t k0 = threadIdx.x;
+  if (k0 < nv_tile) locate(k0, src);
+  while (k0 < nv_tile) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = src[u] >= 0 ? stage[src[u]] : 0;
+    const int32_t k1 = k0 + 8 * 256;
+    if (k1 < nv_tile) locate(k1, src);
 #pragma unroll
     for (int u = 0; u < 8; ++u)
       if (k0 + 256 * u < nv_tile) verts[tile_v0 + k0 + 256 * u] = v[u];
+    k0 = k1;
   }
 }
 

@@ -61,6 +61,15 @@ struct PolyState {
   __device__ __forceinline__ int32_t len(int64_t i) const { return reinterpret_cast<const int32_t*>(rec + i)[0]; }
 };
 
+// Workgroups are dispatched to the 8 XCDs round-robin (workgroup b to XCD
+// b % 8). Streaming kernels renumber them so that each XCD takes one
+// contiguous eighth of the work in order, and neighbouring data (vertices of
+// neighbouring triangles, Max bytes of neighbouring tiles) stays in one L2.
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb) {
+  const uint32_t q = nb / 8, r = nb % 8, x = b % 8, i = b / 8;
+  return x * q + min(x, r) + i;
+}
+
 // Staging and arena chunks that one workgroup of the region kernels reserves
 // at a time (the host adds the unused tails to the capacities).
 constexpr int32_t kBigStageChunk64 = 1024, kBigArenaChunk64 = 256;

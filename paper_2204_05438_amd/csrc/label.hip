@@ -59,7 +59,7 @@ __global__ __launch_bounds__(256) void k_longest(int64_t nt, int64_t nv, const d
                                                  const int32_t* __restrict__ origin,
                                                  const int32_t* __restrict__ twin, uint8_t* __restrict__ lg,
                                                  uint8_t* __restrict__ vtx, Counters* cnt) {
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t gid = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   if (vtx)
     for (int64_t v = gid; v < nv; v += stride) vtx[v] = 0;
@@ -186,7 +186,7 @@ __global__ __launch_bounds__(256) void k_label(int64_t nt, const int32_t* __rest
                                                int32_t* __restrict__ wk, uint32_t* __restrict__ tcount,
                                                uint32_t* __restrict__ tsuper, Counters* cnt, bool vec) {
   constexpr int ITEMS = kLabelItems;
-  const uint32_t tile = blockIdx.x;
+  const uint32_t tile = xcd_block(blockIdx.x, gridDim.x);
   const int64_t t0 = ((int64_t)tile * 256 + threadIdx.x) * ITEMS;
   const int32_t nhe = (int32_t)(3 * nt);
   bool sd[ITEMS];

@@ -184,8 +184,10 @@ int polylla_status(polylla_ctx *ctx, hipStream_t stream);
 /* Diagnostics of the last build / repair / mesh call, after polylla_status:
  * out[0] seeds, out[1] short polygons with a tip or a repeated vertex (one
  * lane each), out[2] tips, out[3] opened edges, out[4] long polygons (one
- * workgroup each), out[5] long polygons beyond the workgroup's LDS capacity
- * (one lane each). Returns the number of values written (<= n). */
+ * workgroup each), out[5] regions beyond the LDS of the 1024-thread
+ * workgroup (one workgroup each, region kept in global memory), out[6]
+ * regions beyond that path's store as well (one lane each). Returns the
+ * number of values written (<= n). */
 int polylla_stats(polylla_ctx *ctx, int64_t *out, int n);
 
 /* Tuning parameters of a context (defaults are the tuned values).
@@ -205,6 +207,17 @@ int polylla_stats(polylla_ctx *ctx, int64_t *out, int n);
  * wave per polygon when there are at most this many (lowest latency), else
  * one lane per polygon (highest throughput). */
 #define POLYLLA_PARAM_GEN_WAVE_MAX 3
+/* POLYLLA_PARAM_REGION_LDS_MAX (32..4096, default 4096): regions with more
+ * triangles or frontier half-edges than this are not built by the 1024-thread
+ * workgroup out of LDS but by the global-memory workgroup path. Lower values
+ * exercise that path (used by tests). */
+#define POLYLLA_PARAM_REGION_LDS_MAX 4
+/* POLYLLA_PARAM_REGION_MEM_MAX (32..65536, default 65536): regions with more
+ * triangles than this, or more than twice as many frontier half-edges, are
+ * not built by the global-memory workgroup path but one lane each. Its store
+ * holds min(triangles of the mesh, 65536) triangles per workgroup (8
+ * workgroups, about 260 bytes per triangle of capacity). */
+#define POLYLLA_PARAM_REGION_MEM_MAX 5
 int polylla_set_param(polylla_ctx *ctx, int param, int64_t value);
 
 /* Per-kernel GPU timing with HIP events, for benchmarks (off by default).

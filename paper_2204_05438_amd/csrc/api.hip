@@ -32,10 +32,11 @@ template <bool REPAIR, int NT, int KC, int LC, int HB>
 __global__ void k_general_big(const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*, const int32_t*,
                               uint8_t*, uint8_t*, int32_t*, int64_t, int32_t*, int64_t, PolyState, const int32_t*,
                               bool, int64_t, const uint32_t*, uint32_t*, int32_t*, int64_t, uint32_t*,
-                              const int32_t*, int64_t, const uint32_t*, uint32_t, uint32_t, Counters*);
+                              const int32_t*, int64_t, const uint32_t*, uint32_t, uint32_t, int32_t, Counters*);
 template <bool REPAIR>
-__global__ void k_general_huge(const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*, uint8_t*,
-                               uint8_t*, int32_t*, int64_t, int32_t*, int64_t, PolyState, const int32_t*,
+__global__ void k_general_huge(const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*,
+                               const int32_t*, uint8_t*, uint8_t*, int32_t*, int64_t, int32_t*, int64_t, PolyState,
+                               const int32_t*, int64_t, int32_t*, int64_t, int32_t*, int64_t, int32_t, int32_t,
                                Counters*);
 __global__ void k_scan_emit(PolyState, uint64_t*, const int32_t*, const int32_t*, int32_t*, int32_t*, int32_t*,
                             int64_t*, int64_t, int64_t, Counters*);
@@ -62,7 +63,10 @@ struct polylla_ctx {
   int32_t* deferred = nullptr;
   int32_t* over = nullptr;  // regions beyond the one-wave workgroup's LDS
   int32_t* huge = nullptr;  // regions beyond the 1024-thread workgroup's LDS
-  int64_t over_cap = 0, huge_cap = 0;
+  int32_t* lane = nullptr;  // regions beyond the global-memory workgroup path
+  int64_t over_cap = 0, huge_cap = 0, lane_cap = 0;
+  int32_t* mem_store = nullptr;  // region stores of the global-memory workgroup path
+  int64_t mem_km = 0;            // triangles of capacity of one store
   int32_t* rest = nullptr;  // short polygons the tip path leaves to the region path
   int64_t rest_cap = 0;
   int32_t* poly_arrays = nullptr;  // per-polygon records: 4 ints + 1 int per polygon (PolyState)
@@ -78,6 +82,8 @@ struct polylla_ctx {
   Counters last{};
   int walk_cap = 24;  // vertices a lane walks before handing a polygon to a workgroup
   uint32_t gen_wave_max = kGenWaveMax;  // declined short polygons up to which each gets a wave
+  int32_t lds_max = 4096;               // region size limit of the 1024-thread LDS workgroup
+  int32_t mem_max = (int32_t)kMemRegionMax;  // region size limit of the global-memory workgroup
   int walk_blocks = 640;  // persistent grid of the walk kernel (swept at 10M: 512 851, 640 782, 768 791 us)
   // second stream: the workgroup region kernel runs beside the per-lane one
   // (they touch disjoint regions); fork and join through events
@@ -159,6 +165,8 @@ void free_scratch(polylla_ctx* c) {
   dfree(&c->seeds);
   dfree(&c->deferred);
   dfree(&c->huge);
+  dfree(&c->lane);
+  dfree(&c->mem_store);
   dfree(&c->over);
   dfree(&c->rest);
   dfree(&c->poly_arrays);
@@ -187,7 +195,9 @@ int ensure(polylla_ctx* c, int64_t nt, int64_t nv) {
                                    ((int64_t)1 << 31) - 1);
   c->arena_cap = 6 * T + kBigArenaTails + 4096;
   c->n_status = 2 * ntiles;
-  if ((rc = dalloc(&c->lg, T)) || (rc = dalloc(&c->wk, 3 * T)) || (rc = dalloc(&c->seeds, T)) || (rc = dalloc(&c->deferred, T)) || (rc = dalloc(&c->huge, c->huge_cap = T / 1024 + 64)) ||
+  if ((rc = dalloc(&c->lg, T)) || (rc = dalloc(&c->wk, 3 * T)) || (rc = dalloc(&c->seeds, T)) || (rc = dalloc(&c->deferred, T)) || (rc = dalloc(&c->huge, c->huge_cap = 3 * T / 32 + 64)) ||
+      (rc = dalloc(&c->lane, c->lane_cap = 3 * T / 32 + 64)) ||
+      (rc = dalloc(&c->mem_store, kMemGrid * mem_words(c->mem_km = std::min<int64_t>(T, kMemRegionMax)))) ||
       (rc = dalloc(&c->over, c->over_cap = T / 32 + 64)) ||
       (rc = dalloc(&c->rest, c->rest_cap = T / 3 + 64)) ||
       (rc = dalloc(&c->poly_arrays, 5 * T)) || (rc = dalloc(&c->stage, c->stage_cap)) ||
@@ -302,12 +312,12 @@ int run_build(polylla_ctx* c, const polylla_tri* t, const int32_t* list, bool fr
       hipLaunchKernelGGL((k_general_big<true, 64, 128, 128, 8>), dim3(gm), dim3(64), 0, c->side, list, from_seeds, nhe,
                          t->n_vertices, t->twin, t->origin, c->wk, he, vtx, c->stage, c->stage_cap, c->arena,
                          c->arena_cap, ps, c->deferred, true, c->cap_t, &k->n_big, &k->big_ticket, c->over,
-                         c->over_cap, &k->n_over, nullptr, (int64_t)0, &k->n_big, few, UINT32_MAX, k);
+                         c->over_cap, &k->n_over, nullptr, (int64_t)0, &k->n_big, few, UINT32_MAX, 128, k);
     else
       hipLaunchKernelGGL((k_general_big<false, 64, 128, 128, 8>), dim3(gm), dim3(64), 0, c->side, list, from_seeds,
                          nhe, t->n_vertices, t->twin, t->origin, c->wk, he, vtx, c->stage, c->stage_cap, c->arena,
                          c->arena_cap, ps, c->deferred, true, c->cap_t, &k->n_big, &k->big_ticket, c->over,
-                         c->over_cap, &k->n_over, nullptr, (int64_t)0, &k->n_big, few, UINT32_MAX, k);
+                         c->over_cap, &k->n_over, nullptr, (int64_t)0, &k->n_big, few, UINT32_MAX, 128, k);
   }
   {
     Prof p(c, c->side, KR_BIGW);
@@ -317,12 +327,14 @@ int run_build(polylla_ctx* c, const polylla_tri* t, const int32_t* list, bool fr
       hipLaunchKernelGGL((k_general_big<true, 1024, 4096, 4096, 13>), dim3(gb), dim3(1024), 0, c->side, list,
                          from_seeds, nhe, t->n_vertices, t->twin, t->origin, c->wk, he, vtx, c->stage, c->stage_cap,
                          c->arena, c->arena_cap, ps, c->over, false, (int64_t)0, &k->n_over, &k->over_ticket, c->huge,
-                         c->huge_cap, &k->n_fallback, c->deferred, c->cap_t, &k->n_big, few, UINT32_MAX, k);
+                         c->huge_cap, &k->n_fallback, c->deferred, c->cap_t, &k->n_big, few, UINT32_MAX,
+                         c->lds_max, k);
     else
       hipLaunchKernelGGL((k_general_big<false, 1024, 4096, 4096, 13>), dim3(gb), dim3(1024), 0, c->side, list,
                          from_seeds, nhe, t->n_vertices, t->twin, t->origin, c->wk, he, vtx, c->stage, c->stage_cap,
                          c->arena, c->arena_cap, ps, c->over, false, (int64_t)0, &k->n_over, &k->over_ticket, c->huge,
-                         c->huge_cap, &k->n_fallback, c->deferred, c->cap_t, &k->n_big, few, UINT32_MAX, k);
+                         c->huge_cap, &k->n_fallback, c->deferred, c->cap_t, &k->n_big, few, UINT32_MAX,
+                         c->lds_max, k);
   }
   if (hipEventRecord(c->join, c->side) != hipSuccess) return POLYLLA_EHIP;
   {
@@ -347,12 +359,12 @@ int run_build(polylla_ctx* c, const polylla_tri* t, const int32_t* list, bool fr
       hipLaunchKernelGGL((k_general_big<true, 64, 128, 128, 8>), dim3(kBigGrid64), dim3(64), 0, s, list, from_seeds,
                          nhe, t->n_vertices, t->twin, t->origin, c->wk, he, vtx, c->stage, c->stage_cap, c->arena,
                          c->arena_cap, ps, c->rest, false, (int64_t)0, &k->n_gen, nullptr, c->huge, c->huge_cap,
-                         &k->n_fallback, nullptr, (int64_t)0, nullptr, 0u, c->gen_wave_max, k);
+                         &k->n_fallback, nullptr, (int64_t)0, nullptr, 0u, c->gen_wave_max, 128, k);
     else
       hipLaunchKernelGGL((k_general_big<false, 64, 128, 128, 8>), dim3(kBigGrid64), dim3(64), 0, s, list, from_seeds,
                          nhe, t->n_vertices, t->twin, t->origin, c->wk, he, vtx, c->stage, c->stage_cap, c->arena,
                          c->arena_cap, ps, c->rest, false, (int64_t)0, &k->n_gen, nullptr, c->huge, c->huge_cap,
-                         &k->n_fallback, nullptr, (int64_t)0, nullptr, 0u, c->gen_wave_max, k);
+                         &k->n_fallback, nullptr, (int64_t)0, nullptr, 0u, c->gen_wave_max, 128, k);
   }
   {
     Prof p(c, s, KR_GENERAL);
@@ -369,14 +381,20 @@ int run_build(polylla_ctx* c, const polylla_tri* t, const int32_t* list, bool fr
   if (hipStreamWaitEvent(s, c->join, 0) != hipSuccess) return POLYLLA_EHIP;
   {
     Prof p(c, s, KR_HUGE);
+    // regions beyond the LDS instance: a workgroup each with the region in
+    // global memory; beyond that, one lane each
+    const int32_t kcap = (int32_t)std::min<int64_t>(c->mem_km, c->mem_max);
+    const int32_t lcap = 2 * kcap;
     if (repair)
-      hipLaunchKernelGGL(k_general_huge<true>, dim3(4), dim3(64), 0, s, list, from_seeds, nhe, t->n_vertices,
-                         t->twin, t->origin, he, vtx, c->stage, c->stage_cap, c->arena, c->arena_cap, ps, c->huge,
-                         c->cnt);
+      hipLaunchKernelGGL(k_general_huge<true>, dim3(kMemGrid), dim3(1024), 0, s, list, from_seeds, nhe,
+                         t->n_vertices, t->twin, t->origin, c->wk, he, vtx, c->stage, c->stage_cap, c->arena,
+                         c->arena_cap, ps, c->huge, c->huge_cap, c->lane, c->lane_cap, c->mem_store, c->mem_km,
+                         kcap, lcap, c->cnt);
     else
-      hipLaunchKernelGGL(k_general_huge<false>, dim3(4), dim3(64), 0, s, list, from_seeds, nhe, t->n_vertices,
-                         t->twin, t->origin, he, vtx, c->stage, c->stage_cap, c->arena, c->arena_cap, ps, c->huge,
-                         c->cnt);
+      hipLaunchKernelGGL(k_general_huge<false>, dim3(kMemGrid), dim3(1024), 0, s, list, from_seeds, nhe,
+                         t->n_vertices, t->twin, t->origin, c->wk, he, vtx, c->stage, c->stage_cap, c->arena,
+                         c->arena_cap, ps, c->huge, c->huge_cap, c->lane, c->lane_cap, c->mem_store, c->mem_km,
+                         kcap, lcap, c->cnt);
   }
   {
     Prof p(c, s, KR_SCAN);
@@ -560,9 +578,9 @@ int polylla_status(polylla_ctx* c, hipStream_t s) {
 
 int polylla_stats(polylla_ctx* c, int64_t* out, int n) {
   if (!c || !out || n < 0) return POLYLLA_EINVAL;
-  const int64_t v[6] = {c->last.n_seeds, c->last.n_deferred, c->last.n_tips,
-                        c->last.n_splits, c->last.n_big,      c->last.n_fallback};
-  int k = std::min(n, 6);
+  const int64_t v[7] = {c->last.n_seeds,  c->last.n_deferred, c->last.n_tips, c->last.n_splits,
+                        c->last.n_big,    c->last.n_fallback, c->last.n_lane};
+  int k = std::min(n, 7);
   for (int i = 0; i < k; ++i) out[i] = v[i];
   return k;
 }
@@ -581,6 +599,14 @@ int polylla_set_param(polylla_ctx* c, int param, int64_t value) {
     case POLYLLA_PARAM_GEN_WAVE_MAX:
       if (value < 0 || value > UINT32_MAX - 1) return POLYLLA_EINVAL;
       c->gen_wave_max = (uint32_t)value;
+      return POLYLLA_OK;
+    case POLYLLA_PARAM_REGION_LDS_MAX:
+      if (value < 32 || value > 4096) return POLYLLA_EINVAL;
+      c->lds_max = (int32_t)value;
+      return POLYLLA_OK;
+    case POLYLLA_PARAM_REGION_MEM_MAX:
+      if (value < 32 || value > kMemRegionMax) return POLYLLA_EINVAL;
+      c->mem_max = (int32_t)value;
       return POLYLLA_OK;
     default:
       return POLYLLA_EINVAL;

@@ -1494,8 +1494,9 @@ __global__ __launch_bounds__(NT) void k_general_big(
     int64_t arena_cap, PolyState ps, const int32_t* __restrict__ in, bool in_rev, int64_t in_cap,
     const uint32_t* in_count, uint32_t* in_ticket, int32_t* __restrict__ over, int64_t over_cap,
     uint32_t* over_count, const int32_t* __restrict__ few_in, int64_t few_cap, const uint32_t* few_count,
-    uint32_t few_max, uint32_t run_max, Counters* cnt) {
+    uint32_t few_max, uint32_t run_max, int32_t cap_lim, Counters* cnt) {
   constexpr int kBigThreads = NT, kKCap = KC, kLCap = LC, kHCap = 1 << HB, kPer = LC / NT;
+  const int kcap = min(kKCap, cap_lim), lcap = min(kLCap, cap_lim);  // limits in use
   static_assert(LC % NT == 0 && kPer >= 1, "slots per thread");
   static_assert(KC < (1 << 13) && LC < (1 << 14), "codes and slots are int16");
   __shared__ BigLds<KC, LC, HB> S;
@@ -1573,7 +1574,7 @@ __global__ __launch_bounds__(NT) void k_general_big(
           const int32_t tw = sel3(tw3.x, tw3.y, tw3.z, e);
           if (sel3(wk3.x, wk3.y, wk3.z, e) < 0) {  // frontier
             const int idx = atomicAdd(&S.sc[SC_NFH], 1);
-            if (idx < kLCap) {
+            if (idx < lcap) {
               S.fh[idx] = h;
               S.a[idx] = tw;
               S.fcode[idx] = (int16_t)(4 * j + e);
@@ -1588,7 +1589,7 @@ __global__ __launch_bounds__(NT) void k_general_big(
               continue;
             }
             const int pos = atomicAdd(&S.sc[SC_QLEN], 1);
-            if (pos < kKCap) {
+            if (pos < kcap) {
               const int32_t t2 = tw / 3;
               const int e2 = tw - 3 * t2;
               S.q[pos] = (int32_t)((uint32_t)t2 | ((uint32_t)(e2 + 1) << 30));
@@ -1603,7 +1604,7 @@ __global__ __launch_bounds__(NT) void k_general_big(
       __syncthreads();
       if (tid == 0) {
         S.sc[SC_LO] = hi;
-        S.sc[SC_HI] = min(S.sc[SC_QLEN], kKCap);
+        S.sc[SC_HI] = min(S.sc[SC_QLEN], kcap);
       }
       __syncthreads();
     }
@@ -1663,11 +1664,6 @@ __global__ __launch_bounds__(NT) void k_general_big(
       continue;
     }
     const int ntip = S.sc[SC_NTIP];
-    for (int p = tid; p < ntip; p += kBigThreads) {
-      const int32_t v = S.hkey[2 * p];
-      if ((uint64_t)(uint32_t)v < (uint64_t)nv) or_bits(vtx, v, kTip);
-    }
-    if (tid == 0 && ntip) atomicAdd(&cnt->n_tips, (uint32_t)ntip);
     // ---- 3. repair
     if (REPAIR && ntip > 0) {
       // middle internal edge c_{floor(d/2)} of every tip's fan (which lies in
@@ -1757,7 +1753,7 @@ __global__ __launch_bounds__(NT) void k_general_big(
         if (!dead) atomicAdd(&S.sc[SC_NSPLIT], 1);
       }
       __syncthreads();
-      if (tid == 0 && L + 2 * S.sc[SC_NSPLIT] > kLCap) S.sc[SC_OVER] = 1;
+      if (tid == 0 && L + 2 * S.sc[SC_NSPLIT] > lcap) S.sc[SC_OVER] = 1;
       __syncthreads();
       if (S.sc[SC_BAD]) {
         if (tid == 0) {
@@ -1809,6 +1805,12 @@ __global__ __launch_bounds__(NT) void k_general_big(
         continue;
       }
     }
+    // tips (counted once the region stays in this instance)
+    for (int p = tid; p < ntip; p += kBigThreads) {
+      const int32_t v = S.hkey[2 * p];
+      if ((uint64_t)(uint32_t)v < (uint64_t)nv) or_bits(vtx, v, kTip);
+    }
+    if (tid == 0 && ntip) atomicAdd(&cnt->n_tips, (uint32_t)ntip);
     // vertex id of every frontier slot, into the link area (the links are
     // done with)
     int32_t vreg[kPer];
@@ -2042,18 +2044,593 @@ __global__ __launch_bounds__(NT) void k_general_big(
 
 // ---------------------------------------------------------------------------
 
-// Long regions beyond the workgroup's LDS capacity: one lane each, global arena.
+// Views of one workgroup's part of the global-memory region store (the same
+// four steps as the LDS kernel, one array per role instead of shared areas,
+// and ping-pong arrays instead of registers for the pointer jumping).
+struct MemRegion {
+  int32_t *q, *lnk;                                      // slots: km, links: 3 km
+  int32_t *hkey, *hval;                                  // hash: mem_hcap(km) each
+  int32_t *fh, *tw, *fcode, *nx, *ts, *bv;               // frontier slots: 2 km each
+  int32_t *pid[2], *jp[2], *dd[2];                       // pointer jumping: 2 km each
+  int32_t *pmin, *pcnt, *pstart, *psec, *poff, *plist, *porder;  // pieces: 2 km each
+  int32_t *tipv, *tipc, *tipfar, *torder, *kc, *kf, *tst;        // tips: km each
+};
+
+__device__ __forceinline__ MemRegion mem_region(int32_t* base, int64_t km) {
+  MemRegion r;
+  int32_t* p = base;
+  auto take = [&](int64_t n) {
+    int32_t* q = p;
+    p += n;
+    return q;
+  };
+  const int64_t lm = 2 * km, hc = mem_hcap(km);
+  r.q = take(km);
+  r.lnk = take(3 * km);
+  r.hkey = take(hc);
+  r.hval = take(hc);
+  r.fh = take(lm);
+  r.tw = take(lm);
+  r.fcode = take(lm);
+  r.nx = take(lm);
+  r.ts = take(lm);
+  r.bv = take(lm);
+  for (int k = 0; k < 2; ++k) {
+    r.pid[k] = take(lm);
+    r.jp[k] = take(lm);
+    r.dd[k] = take(lm);
+  }
+  r.pmin = take(lm);
+  r.pcnt = take(lm);
+  r.pstart = take(lm);
+  r.psec = take(lm);
+  r.poff = take(lm);
+  r.plist = take(lm);
+  r.porder = take(lm);
+  r.tipv = take(km);
+  r.tipc = take(km);
+  r.tipfar = take(km);
+  r.torder = take(km);
+  r.kc = take(km);
+  r.kf = take(km);
+  r.tst = take(km);
+  return r;
+}
+
+__device__ __forceinline__ int32_t mem_code_gid(const MemRegion& R, int c) {
+  return 3 * (int32_t)((uint32_t)R.q[c >> 2] & kSlotTri) + (c & 3);
+}
+
+__device__ __forceinline__ int mem_turn(const MemRegion& R, int x) {
+  int y = R.lnk[3 * (x >> 2) + (x & 3)];
+  if (y < 0) {
+    const int f2 = R.ts[-1 - y];
+    if (f2 < 0) return -1;
+    y = R.fcode[f2];
+  }
+  return (y & ~3) | next_local(y & 3);
+}
+
+template <int NT>
+__device__ __forceinline__ void mem_successors(const MemRegion& R, int L, int kcap, int32_t* sc) {
+  const int bound = 3 * kcap + 3;
+  for (int k = threadIdx.x; k < L; k += NT) {
+    int x = R.fcode[k];
+    x = (x & ~3) | next_local(x & 3);
+    int r = -1;
+    for (int n = 0; n < bound; ++n) {
+      const int l = R.lnk[3 * (x >> 2) + (x & 3)];
+      if (l < 0) {
+        r = -1 - l;
+        break;
+      }
+      x = (l & ~3) | next_local(l & 3);
+    }
+    if (r < 0) {
+      sc[SC_BAD] = 1;
+      r = k;
+    }
+    R.nx[k] = r;
+  }
+}
+
+// Rank of key[p] among key[0..n) (keys distinct) for every p < n, into
+// out[rank] = p; the keys are read back a workgroup-sized tile at a time
+// through LDS. Two keys compare lexicographically when key2 is given.
+template <int NT>
+__device__ __forceinline__ void mem_rank(const int32_t* key, const int32_t* key2, const int32_t* ids, int n,
+                                         int32_t* out, int32_t* s_k1, int32_t* s_k2) {
+  const int tid = threadIdx.x;
+  for (int pb = 0; pb < n; pb += NT) {
+    const int u = pb + tid;
+    const int p = u < n ? (ids ? ids[u] : u) : 0;
+    const int32_t v1 = u < n ? key[p] : 0, v2 = (u < n && key2) ? key2[p] : 0;
+    int r = 0;
+    for (int tb = 0; tb < n; tb += NT) {
+      __syncthreads();
+      if (tb + tid < n) {
+        const int q = ids ? ids[tb + tid] : tb + tid;
+        s_k1[tid] = key[q];
+        s_k2[tid] = key2 ? key2[q] : 0;
+      }
+      __syncthreads();
+      const int m = min(NT, n - tb);
+      for (int w = 0; w < m; ++w) r += (s_k1[w] < v1) || (s_k1[w] == v1 && s_k2[w] < v2);
+    }
+    if (u < n) out[r] = p;
+  }
+  __syncthreads();
+}
+
+// One region by one workgroup with its arrays in global memory (capacities
+// kcap triangles, lcap frontier slots); beyond them it goes to the lane list.
+template <bool REPAIR, int NT>
+__device__ void region_mem(const MemRegion& R, int32_t i, int32_t t0, int32_t nhe, int64_t nv,
+                           const int32_t* __restrict__ twin, const int32_t* __restrict__ origin,
+                           const int32_t* __restrict__ wk, uint8_t* __restrict__ he, uint8_t* __restrict__ vtx,
+                           int32_t* __restrict__ stage, int64_t stage_cap, int32_t* __restrict__ arena,
+                           int64_t arena_cap, PolyState ps, int32_t* lane, int64_t lane_cap, int kcap, int lcap,
+                           int32_t* sc, int32_t* s_k1, int32_t* s_k2, Counters* cnt) {
+  const int tid = threadIdx.x;
+  const int32_t nt = nhe / 3;
+  // ---- 1. breadth-first search of the region's dual tree
+  if (tid == 0) {
+    R.q[0] = t0;
+    sc[SC_QLEN] = 1;
+    sc[SC_LO] = 0;
+    sc[SC_HI] = 1;
+    sc[SC_NFH] = 0;
+    sc[SC_NTIP] = 0;
+    sc[SC_OVER] = ((uint32_t)t0 >= (uint32_t)nt) ? 1 : 0;
+    sc[SC_BAD] = 0;
+    sc[SC_NSPLIT] = 0;
+    sc[SC_NP] = 0;
+  }
+  __syncthreads();
+  for (;;) {
+    const int lo = sc[SC_LO], hi = sc[SC_HI];
+    if (lo >= hi || sc[SC_OVER]) break;
+    for (int j = lo + tid; j < hi; j += NT) {
+      const uint32_t qj = (uint32_t)R.q[j];
+      const int32_t t = (int32_t)(qj & kSlotTri);
+      const int entry = (int)(qj >> 30) - 1;
+      const Int3 tw3 = *reinterpret_cast<const Int3*>(twin + 3 * t);
+      const Int3 wk3 = *reinterpret_cast<const Int3*>(wk + 3 * t);
+#pragma unroll
+      for (int e = 0; e < 3; ++e) {
+        if (e == entry) continue;
+        const int32_t h = 3 * t + e;
+        const int32_t tw = sel3(tw3.x, tw3.y, tw3.z, e);
+        if (sel3(wk3.x, wk3.y, wk3.z, e) < 0) {  // frontier
+          const int idx = atomicAdd(&sc[SC_NFH], 1);
+          if (idx < lcap) {
+            R.fh[idx] = h;
+            R.tw[idx] = tw;
+            R.fcode[idx] = 4 * j + e;
+            R.lnk[3 * j + e] = -1 - idx;
+          } else {
+            sc[SC_OVER] = 1;
+          }
+        } else {
+          if ((uint32_t)tw >= (uint32_t)nhe) {
+            sc[SC_BAD] = 1;
+            continue;
+          }
+          const int pos = atomicAdd(&sc[SC_QLEN], 1);
+          if (pos < kcap) {
+            const int32_t t2 = tw / 3;
+            const int e2 = tw - 3 * t2;
+            R.q[pos] = (int32_t)((uint32_t)t2 | ((uint32_t)(e2 + 1) << 30));
+            R.lnk[3 * j + e] = 4 * pos + e2;
+            R.lnk[3 * pos + e2] = 4 * j + e;
+          } else {
+            sc[SC_OVER] = 1;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    if (tid == 0) {
+      sc[SC_LO] = hi;
+      sc[SC_HI] = min(sc[SC_QLEN], kcap);
+    }
+    __syncthreads();
+  }
+  if (sc[SC_BAD]) {
+    if (tid == 0) {
+      set_error(cnt, POLYLLA_ETOPO);
+      ps.clear(i);
+    }
+    return;
+  }
+  if (sc[SC_OVER]) {
+    if (tid == 0) push_over(lane, lane_cap, &cnt->n_lane, i, cnt);
+    return;
+  }
+  int L = sc[SC_NFH];
+  // hash of the frontier half-edges (open addressing, 2 L <= capacity)
+  int hb = 6;
+  while ((1 << hb) < 2 * L) ++hb;
+  const int hcap = 1 << hb;
+  for (int k = tid; k < hcap; k += NT) R.hkey[k] = -1;
+  __syncthreads();
+  for (int k = tid; k < L; k += NT) {
+    const int32_t key = R.fh[k];
+    int s = (int)(((uint32_t)key * 2654435761u) >> (32 - hb));
+    for (int n = 0; n < hcap; ++n) {
+      const int32_t old = atomicCAS(&R.hkey[s], -1, key);
+      if (old == -1 || old == key) {
+        R.hval[s] = k;
+        break;
+      }
+      s = (s + 1) & (hcap - 1);
+    }
+  }
+  __syncthreads();
+  // ---- 2. successors, barrier edges, tips
+  mem_successors<NT>(R, L, kcap, sc);
+  __syncthreads();
+  const int tipcap = lcap / 2;
+  for (int k = tid; k < L; k += NT) {
+    const int j = R.nx[k];
+    const int32_t tw = R.tw[k];
+    int32_t f = -1;
+    if ((uint32_t)tw < (uint32_t)nhe) {
+      int s = (int)(((uint32_t)tw * 2654435761u) >> (32 - hb));
+      for (int n = 0; n < hcap; ++n) {
+        const int32_t kk = R.hkey[s];
+        if (kk == tw) {
+          f = R.hval[s];
+          break;
+        }
+        if (kk == -1) break;
+        s = (s + 1) & (hcap - 1);
+      }
+    }
+    R.ts[k] = f;
+    if (f >= 0) or_bits(he, R.fh[k], kBarrier);
+    if (R.fh[j] == tw && j != k) {  // tip (vertex, frontier slot of the barrier half-edge leaving it)
+      const int p = atomicAdd(&sc[SC_NTIP], 1);
+      if (p < tipcap) {
+        R.tipv[p] = origin[mem_code_gid(R, R.fcode[j])];
+        R.tipc[p] = j;
+      } else {
+        sc[SC_OVER] = 1;
+      }
+    }
+  }
+  __syncthreads();
+  if (sc[SC_BAD]) {
+    if (tid == 0) {
+      set_error(cnt, POLYLLA_EDEGEN);
+      ps.clear(i);
+    }
+    return;
+  }
+  if (sc[SC_OVER]) {
+    if (tid == 0) push_over(lane, lane_cap, &cnt->n_lane, i, cnt);
+    return;
+  }
+  const int ntip = sc[SC_NTIP];
+  // ---- 3. repair
+  if (REPAIR && ntip > 0) {
+    // middle internal edge of every tip's fan, turning from the barrier
+    // half-edge, and the far vertex of that edge
+    for (int p = tid; p < ntip; p += NT) {
+      const int x0 = R.fcode[R.tipc[p]];
+      int d = 0, x = x0;
+      do {
+        x = mem_turn(R, x);
+        ++d;
+      } while (x >= 0 && x != x0 && d <= 3 * kcap);
+      if (x != x0) {
+        sc[SC_BAD] = 1;
+        d = 0;
+      }
+      int ec = x0;
+      for (int k = 0; k < d / 2; ++k) ec = mem_turn(R, ec);
+      R.tipc[p] = ec;
+      R.tipfar[p] = origin[mem_code_gid(R, (ec & ~3) | next_local(ec & 3))];
+    }
+    __syncthreads();
+    // tips in increasing vertex order: torder[rank] = tip
+    mem_rank<NT>(R.tipv, nullptr, nullptr, ntip, R.torder, s_k1, s_k2);
+    // the rule of the LDS kernel: the live tips, in vertex order, remove the
+    // larger tips at the far ends of their opened edges; decided in rounds
+    // over the forest of ranks (tst: 0 undecided, 1 newly live, 2 live,
+    // 3 newly dead, 4 dead)
+    for (int r = tid; r < ntip; r += NT) {
+      R.kc[r] = 0;
+      R.tst[r] = 0;
+    }
+    if (tid == 0) {
+      sc[SC_PEND] = 0;
+      sc[SC_PEND + 1] = 0;
+      sc[SC_NSPLIT] = 0;
+    }
+    __syncthreads();
+    for (int r = tid; r < ntip; r += NT) {
+      const int32_t x = R.tipfar[R.torder[r]];
+      int lo = r + 1, hi = ntip;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (R.tipv[R.torder[mid]] < x) lo = mid + 1;
+        else hi = mid;
+      }
+      const int f = (lo < ntip && R.tipv[R.torder[lo]] == x) ? lo : -1;
+      R.kf[r] = f;
+      if (f >= 0) atomicAdd(&R.kc[f], 1);
+    }
+    __syncthreads();
+    for (int round = 0;; ++round) {
+      const int par = SC_PEND + (round & 1);
+      for (int r = tid; r < ntip; r += NT) {
+        if (R.tst[r] != 0) continue;
+        if (R.kc[r] == 0) R.tst[r] = 1;
+        else sc[par] = 1;
+      }
+      __syncthreads();
+      if (tid == 0) sc[SC_PEND + ((round + 1) & 1)] = 0;
+      for (int r = tid; r < ntip; r += NT) {
+        if (R.tst[r] != 1) continue;
+        R.tst[r] = 2;
+        if (R.kf[r] >= 0) R.tst[R.kf[r]] = 3;
+      }
+      __syncthreads();
+      for (int r = tid; r < ntip; r += NT) {
+        if (R.tst[r] != 3) continue;
+        R.tst[r] = 4;
+        if (R.kf[r] >= 0) atomicSub(&R.kc[R.kf[r]], 1);
+      }
+      __syncthreads();
+      if (!sc[par]) break;
+    }
+    // tst = 1 marks a dead tip from here on; live tips count the splits
+    for (int r = tid; r < ntip; r += NT) {
+      const bool dead = R.tst[r] == 4;
+      R.tst[r] = dead ? 1 : 0;
+      if (!dead) atomicAdd(&sc[SC_NSPLIT], 1);
+    }
+    __syncthreads();
+    if (tid == 0 && L + 2 * sc[SC_NSPLIT] > lcap) sc[SC_OVER] = 1;
+    __syncthreads();
+    if (sc[SC_BAD]) {
+      if (tid == 0) {
+        set_error(cnt, POLYLLA_ETOPO);
+        ps.clear(i);
+      }
+      return;
+    }
+    if (sc[SC_OVER]) {
+      if (tid == 0) push_over(lane, lane_cap, &cnt->n_lane, i, cnt);
+      return;
+    }
+    // open the middle edges of the live tips
+    for (int r = tid; r < ntip; r += NT) {
+      if (R.tst[r]) continue;
+      const int ec = R.tipc[R.torder[r]];
+      const int tc = R.lnk[3 * (ec >> 2) + (ec & 3)];
+      if (tc < 0) {
+        sc[SC_BAD] = 1;
+        continue;
+      }
+      const int32_t ge = mem_code_gid(R, ec), gt = mem_code_gid(R, tc);
+      or_bits(he, ge, kFrontier | kRepaired);
+      or_bits(he, gt, kFrontier | kRepaired);
+      const int idx = atomicAdd(&sc[SC_NFH], 2);
+      R.fh[idx] = ge;
+      R.fh[idx + 1] = gt;
+      R.fcode[idx] = ec;
+      R.fcode[idx + 1] = tc;
+      R.lnk[3 * (ec >> 2) + (ec & 3)] = -1 - idx;
+      R.lnk[3 * (tc >> 2) + (tc & 3)] = -2 - idx;
+    }
+    __syncthreads();
+    if (tid == 0 && sc[SC_NSPLIT]) atomicAdd(&cnt->n_splits, (uint32_t)sc[SC_NSPLIT]);
+    L = sc[SC_NFH];
+    if (sc[SC_NSPLIT]) {
+      mem_successors<NT>(R, L, kcap, sc);
+      __syncthreads();
+    }
+    if (sc[SC_BAD]) {
+      if (tid == 0) {
+        set_error(cnt, POLYLLA_EDEGEN);
+        ps.clear(i);
+      }
+      return;
+    }
+  }
+  for (int p = tid; p < ntip; p += NT) {
+    const int32_t v = R.tipv[p];
+    if ((uint64_t)(uint32_t)v < (uint64_t)nv) or_bits(vtx, v, kTip);
+  }
+  if (tid == 0 && ntip) atomicAdd(&cnt->n_tips, (uint32_t)ntip);
+  // ---- 4. pieces = cycles of nx; piece id: smallest slot on the cycle
+  for (int k = tid; k < L; k += NT) {
+    R.bv[k] = origin[mem_code_gid(R, R.fcode[k])];
+    R.pid[0][k] = k;
+    R.jp[0][k] = R.nx[k];
+  }
+  __syncthreads();
+  int c = 0;
+  for (int span = 1; span < L; span <<= 1) {
+    for (int k = tid; k < L; k += NT) {
+      const int j = R.jp[c][k];
+      R.pid[c ^ 1][k] = min(R.pid[c][k], R.pid[c][j]);
+      R.jp[c ^ 1][k] = R.jp[c][j];
+    }
+    __syncthreads();
+    c ^= 1;
+  }
+  const int32_t* pid = R.pid[c];
+  // per-piece smallest vertex, its multiplicity and first slot holding it
+  for (int k = tid; k < L; k += NT) {
+    R.pmin[k] = 0x7FFFFFFF;
+    R.pcnt[k] = 0;
+    R.pstart[k] = 0x7FFFFFFF;
+  }
+  __syncthreads();
+  for (int k = tid; k < L; k += NT) atomicMin(&R.pmin[pid[k]], R.bv[k]);
+  __syncthreads();
+  for (int k = tid; k < L; k += NT) {
+    const int p = pid[k];
+    if (R.bv[k] == R.pmin[p]) {
+      atomicAdd(&R.pcnt[p], 1);
+      atomicMin(&R.pstart[p], k);
+    }
+  }
+  __syncthreads();
+  // a piece visiting its smallest vertex twice starts at the occurrence with
+  // the lexicographically smallest continuation
+  for (int p = tid; p < L; p += NT) {
+    if (pid[p] != p || R.pcnt[p] < 2) continue;
+    int best = R.pstart[p];
+    int len = 1;
+    for (int k = R.nx[best]; k != best && len <= L; k = R.nx[k]) ++len;
+    for (int k = R.nx[best], m = 1; m < len; k = R.nx[k], ++m) {
+      if (R.bv[k] != R.pmin[p]) continue;
+      int x = k, y = best;
+      for (int z = 0; z < len; ++z) {
+        if (R.bv[x] != R.bv[y]) {
+          if (R.bv[x] < R.bv[y]) best = k;
+          break;
+        }
+        x = R.nx[x];
+        y = R.nx[y];
+      }
+    }
+    R.pstart[p] = best;
+  }
+  __syncthreads();
+  // distance of every slot to the slot before its piece's start
+  for (int k = tid; k < L; k += NT) {
+    const int n = R.nx[k];
+    const bool last = (n == R.pstart[pid[k]]);
+    R.jp[0][k] = last ? -1 : n;
+    R.dd[0][k] = last ? 0 : 1;
+  }
+  __syncthreads();
+  int e = 0;
+  for (int span = 1; span < L; span <<= 1) {
+    for (int k = tid; k < L; k += NT) {
+      const int j = R.jp[e][k];
+      if (j >= 0) {
+        R.dd[e ^ 1][k] = R.dd[e][k] + R.dd[e][j];
+        R.jp[e ^ 1][k] = R.jp[e][j];
+      } else {
+        R.dd[e ^ 1][k] = R.dd[e][k];
+        R.jp[e ^ 1][k] = -1;
+      }
+    }
+    __syncthreads();
+    e ^= 1;
+  }
+  const int32_t* dist = R.dd[e];
+  // pieces: list and second vertex
+  for (int k = tid; k < L; k += NT) {
+    if (pid[k] != k) continue;
+    const int idx = atomicAdd(&sc[SC_NP], 1);
+    R.plist[idx] = k;
+    R.psec[k] = R.bv[R.nx[R.pstart[k]]];
+  }
+  __syncthreads();
+  const int np = sc[SC_NP];
+  // order pieces by (first, second) vertex: porder[rank] = piece
+  mem_rank<NT>(R.pmin, R.psec, R.plist, np, R.porder, s_k1, s_k2);
+  // output offset of every piece within the polygon
+  uint32_t run = 0;
+  for (int base = 0; base < np; base += NT) {
+    const int r = base + tid;
+    const uint32_t len = r < np ? (uint32_t)R.dd[e][R.pstart[R.porder[r]]] + 1u : 0u;
+    uint2 tot;
+    const uint2 pre = block_exclusive_scan<NT>(len, 0u, &tot);
+    if (r < np) R.poff[R.porder[r]] = (int32_t)(run + pre.x);
+    run += tot.x;
+  }
+  if (tid == 0) {
+    const int32_t total = (int32_t)run;
+    const uint32_t sb = atomicAdd(&cnt->stage_top, (uint32_t)total);
+    bool ok = (int64_t)sb + total <= stage_cap;
+    int32_t rb = -1;
+    if (ok && np > 1) {
+      const uint32_t ab = atomicAdd(&cnt->arena_top, (uint32_t)(4 * np));
+      ok = (int64_t)ab + 4 * np <= arena_cap;
+      rb = (int32_t)ab;
+    }
+    if (!ok) {
+      set_error(cnt, POLYLLA_ENOMEM);
+      sc[SC_OVER] = 1;
+      ps.clear(i);
+    } else {
+      ps.set(i, total, np, np == 1 ? R.fh[R.pstart[R.porder[0]]] : -1, (int32_t)sb);
+      ps.prec[i] = np > 1 ? rb : -1;
+    }
+    sc[SC_SBASE] = (int32_t)sb;
+    sc[SC_RB] = rb;
+  }
+  __syncthreads();
+  if (sc[SC_OVER]) return;
+  const int32_t sb = sc[SC_SBASE], rb = sc[SC_RB];
+  if (np > 1) {
+    for (int r = tid; r < np; r += NT) {
+      const int p = R.porder[r];
+      arena[rb + 4 * r] = R.pmin[p];
+      arena[rb + 4 * r + 1] = R.psec[p];
+      arena[rb + 4 * r + 2] = R.fh[R.pstart[p]];
+      arena[rb + 4 * r + 3] = dist[R.pstart[p]] + 1;
+    }
+  }
+  for (int k = tid; k < L; k += NT) {
+    const int p = pid[k];
+    const int32_t len = dist[R.pstart[p]] + 1;
+    stage[sb + R.poff[p] + (len - 1 - dist[k])] = R.bv[k];
+  }
+}
+
+// Regions beyond the LDS of the 1024-thread workgroup (listed in `in`,
+// cnt->n_fallback of them, in_cap at most): one workgroup each, taken by ticket, with the
+// region in the workgroup's part of `store` (km triangles of capacity; kcap,
+// lcap the limits in use). Regions beyond those go to `lane`; the last
+// workgroup to finish then builds them one lane each.
 template <bool REPAIR>
-__global__ __launch_bounds__(64) void k_general_huge(const int32_t* __restrict__ list, bool from_seeds,
-                                                     int32_t nhe, int64_t nv, const int32_t* __restrict__ twin,
-                                                     const int32_t* __restrict__ origin, uint8_t* __restrict__ he,
-                                                     uint8_t* __restrict__ vtx, int32_t* __restrict__ stage,
-                                                     int64_t stage_cap, int32_t* __restrict__ arena,
-                                                     int64_t arena_cap, PolyState ps, const int32_t* __restrict__ huge,
-                                                     Counters* cnt) {
-  const uint32_t n = cnt->n_fallback;
-  for (uint32_t j = blockIdx.x * 64 + threadIdx.x; j < n; j += gridDim.x * 64) {
-    const int32_t i = huge[j];
+__global__ __launch_bounds__(1024) void k_general_huge(
+    const int32_t* __restrict__ list, bool from_seeds, int32_t nhe, int64_t nv, const int32_t* __restrict__ twin,
+    const int32_t* __restrict__ origin, const int32_t* __restrict__ wk, uint8_t* __restrict__ he,
+    uint8_t* __restrict__ vtx, int32_t* __restrict__ stage, int64_t stage_cap, int32_t* __restrict__ arena,
+    int64_t arena_cap, PolyState ps, const int32_t* __restrict__ in, int64_t in_cap, int32_t* __restrict__ lane,
+    int64_t lane_cap, int32_t* __restrict__ store, int64_t km, int32_t kcap, int32_t lcap, Counters* cnt) {
+  constexpr int NT = 1024;
+  __shared__ int32_t sc[24];
+  __shared__ int32_t s_k1[NT], s_k2[NT];
+  __shared__ int32_t s_last;
+  const int tid = threadIdx.x;
+  const uint32_t nin = (uint32_t)min((int64_t)cnt->n_fallback, in_cap);
+  if (nin > 0) {
+    const MemRegion R = mem_region(store + (int64_t)blockIdx.x * mem_words(km), km);
+    for (;;) {
+      if (tid == 0) sc[SC_ITEM] = (int32_t)atomicAdd(&cnt->mem_ticket, 1u);
+      __syncthreads();
+      const uint32_t item = (uint32_t)sc[SC_ITEM];
+      if (item >= nin) break;
+      const int32_t i = in[item];
+      const int32_t li = list[i];
+      const int32_t t0 = from_seeds ? li : li / 3;
+      region_mem<REPAIR, NT>(R, i, t0, nhe, nv, twin, origin, wk, he, vtx, stage, stage_cap, arena, arena_cap, ps,
+                             lane, lane_cap, kcap, lcap, sc, s_k1, s_k2, cnt);
+      __syncthreads();
+    }
+  }
+  // the last workgroup to finish sees every region queued for one lane
+  if (tid == 0) {
+    __threadfence();
+    s_last = atomicAdd(&cnt->mem_done, 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  const uint32_t n = __hip_atomic_load(&cnt->n_lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (uint32_t j = tid; j < n && (int64_t)j < lane_cap; j += NT) {
+    const int32_t i = lane[j];
     const int32_t s = from_seeds ? seed_start(list[i], nhe, twin, he, cnt) : list[i];
     general_one<REPAIR>(i, s, nhe, nv, twin, origin, he, vtx, stage, stage_cap, arena, arena_cap, ps, cnt);
   }
@@ -2307,24 +2884,26 @@ template __global__ void k_tip<false>(int32_t, int64_t, const int32_t*, const in
 template __global__ void k_general_big<true, 64, 128, 128, 8>(
     const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*, const int32_t*, uint8_t*, uint8_t*,
     int32_t*, int64_t, int32_t*, int64_t, PolyState, const int32_t*, bool, int64_t, const uint32_t*, uint32_t*,
-    int32_t*, int64_t, uint32_t*, const int32_t*, int64_t, const uint32_t*, uint32_t, uint32_t, Counters*);
+    int32_t*, int64_t, uint32_t*, const int32_t*, int64_t, const uint32_t*, uint32_t, uint32_t, int32_t, Counters*);
 template __global__ void k_general_big<true, 1024, 4096, 4096, 13>(
     const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*, const int32_t*, uint8_t*, uint8_t*,
     int32_t*, int64_t, int32_t*, int64_t, PolyState, const int32_t*, bool, int64_t, const uint32_t*, uint32_t*,
-    int32_t*, int64_t, uint32_t*, const int32_t*, int64_t, const uint32_t*, uint32_t, uint32_t, Counters*);
+    int32_t*, int64_t, uint32_t*, const int32_t*, int64_t, const uint32_t*, uint32_t, uint32_t, int32_t, Counters*);
 template __global__ void k_general_big<false, 64, 128, 128, 8>(
     const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*, const int32_t*, uint8_t*, uint8_t*,
     int32_t*, int64_t, int32_t*, int64_t, PolyState, const int32_t*, bool, int64_t, const uint32_t*, uint32_t*,
-    int32_t*, int64_t, uint32_t*, const int32_t*, int64_t, const uint32_t*, uint32_t, uint32_t, Counters*);
+    int32_t*, int64_t, uint32_t*, const int32_t*, int64_t, const uint32_t*, uint32_t, uint32_t, int32_t, Counters*);
 template __global__ void k_general_big<false, 1024, 4096, 4096, 13>(
     const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*, const int32_t*, uint8_t*, uint8_t*,
     int32_t*, int64_t, int32_t*, int64_t, PolyState, const int32_t*, bool, int64_t, const uint32_t*, uint32_t*,
-    int32_t*, int64_t, uint32_t*, const int32_t*, int64_t, const uint32_t*, uint32_t, uint32_t, Counters*);
+    int32_t*, int64_t, uint32_t*, const int32_t*, int64_t, const uint32_t*, uint32_t, uint32_t, int32_t, Counters*);
 template __global__ void k_general_huge<true>(const int32_t*, bool, int32_t, int64_t, const int32_t*,
-                                              const int32_t*, uint8_t*, uint8_t*, int32_t*, int64_t, int32_t*,
-                                              int64_t, PolyState, const int32_t*, Counters*);
+                                              const int32_t*, const int32_t*, uint8_t*, uint8_t*, int32_t*, int64_t,
+                                              int32_t*, int64_t, PolyState, const int32_t*, int64_t, int32_t*,
+                                              int64_t, int32_t*, int64_t, int32_t, int32_t, Counters*);
 template __global__ void k_general_huge<false>(const int32_t*, bool, int32_t, int64_t, const int32_t*,
-                                               const int32_t*, uint8_t*, uint8_t*, int32_t*, int64_t, int32_t*,
-                                               int64_t, PolyState, const int32_t*, Counters*);
+                                               const int32_t*, const int32_t*, uint8_t*, uint8_t*, int32_t*, int64_t,
+                                               int32_t*, int64_t, PolyState, const int32_t*, int64_t, int32_t*,
+                                               int64_t, int32_t*, int64_t, int32_t, int32_t, Counters*);
 
 }  // namespace polylla

@@ -30,6 +30,9 @@ struct Counters {
   uint32_t n_tips;
   uint32_t n_splits;
   uint32_t n_fallback;    // polygons too large for the 1024-thread workgroup's LDS
+  uint32_t n_lane;        // polygons too large for the global-memory workgroup path (one lane each)
+  uint32_t mem_ticket;    // work counter of the global-memory workgroup path
+  uint32_t mem_done;      // workgroups of that path that have finished
   uint32_t n_over;        // polygons too large for the one-wave workgroup's LDS
   uint32_t n_gen;         // short polygons the tip path leaves to the region path
   alignas(256) uint32_t n_deferred;  // polygons handled by the general path
@@ -75,6 +78,21 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb) {
 constexpr int32_t kBigStageChunk64 = 1024, kBigArenaChunk64 = 256;
 constexpr int32_t kBigStageChunk1024 = 8192, kBigArenaChunk1024 = 2048;
 constexpr int kBigGrid64 = 4096, kBigGrid1024 = 128;
+
+// Global-memory workgroup path for regions beyond the LDS of the 1024-thread
+// workgroup: kMemGrid workgroups, each with a store for one region of up to
+// km triangles (km = min(triangles of the mesh, kMemRegionMax)) and 2 km
+// frontier half-edges. Int32 words of one workgroup's store: 4 km for the
+// triangle slots and their links, 2 hash areas of mem_hcap(km) words, 6 + 13
+// arrays of 2 km (frontier slots; pieces) and 7 arrays of km (tips).
+constexpr int kMemGrid = 8;
+constexpr int64_t kMemRegionMax = 1 << 16;
+__host__ __device__ inline int64_t mem_hcap(int64_t km) {
+  int64_t h = 64;
+  while (h < 4 * km) h <<= 1;
+  return h;
+}
+__host__ __device__ inline int64_t mem_words(int64_t km) { return 4 * km + 2 * mem_hcap(km) + 38 * km + 7 * km; }
 
 __device__ __forceinline__ int32_t he_next(int32_t h) {
   int32_t r = h % 3;

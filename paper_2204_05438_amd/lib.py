@@ -21,6 +21,8 @@ SEED, TIP = 1, 1
 PARAM_WALK_CAP = 1
 PARAM_WALK_BLOCKS = 2
 PARAM_GEN_WAVE_MAX = 3
+PARAM_REGION_LDS_MAX = 4
+PARAM_REGION_MEM_MAX = 5
 PROFILE_OFF, PROFILE_ALL, PROFILE_WALK = 0, 1, 2
 
 
@@ -280,9 +282,9 @@ class Context:
         return code
 
     def stats(self) -> dict:
-        buf = (ctypes.c_int64 * 6)()
-        n = load().polylla_stats(self._h, buf, 6)
-        keys = ["seeds", "general_small", "tips", "splits", "general_big", "fallback"]
+        buf = (ctypes.c_int64 * 7)()
+        n = load().polylla_stats(self._h, buf, 7)
+        keys = ["seeds", "general_small", "tips", "splits", "general_big", "fallback", "lane"]
         return {k: int(buf[i]) for i, k in enumerate(keys[:n])}
 
     def set_param(self, param: int, value: int):

@@ -141,6 +141,36 @@ def test_long_region_routes(ctx, walk_cap, many):
     assert_same(r, oracle.oracle_on(mesh), FULL)
 
 
+@pytest.mark.parametrize("lds_max,mem_max", [(32, 65536), (32, 32), (4096, 65536)])
+@pytest.mark.parametrize("kind", ["uniform", "cluster"])
+def test_region_memory_paths(ctx, kind, lds_max, mem_max):
+    """Regions beyond the LDS limit of the 1024-thread kernel are built by the
+    global-memory workgroup path, and beyond its own limit one lane each
+    (limits lowered so that many regions take each route). The uniform mesh
+    has at most 128 long polygons at walk cap 24 (all go to the 1024-thread
+    kernel) and long regions past the one-wave kernel at walk cap 4."""
+    from paper_2204_05438_amd import lib
+    _say(f"region memory paths {kind} lds_max {lds_max} mem_max {mem_max}")
+    ctx.set_param(lib.PARAM_REGION_LDS_MAX, lds_max)
+    ctx.set_param(lib.PARAM_REGION_MEM_MAX, mem_max)
+    try:
+        mesh = random_mesh(1500, 20000, kind)
+        o = oracle.oracle_on(mesh)
+        for walk_cap in (24, 4):
+            r = gpu_mesh(ctx, mesh, walk_cap)
+            st = r["stats"]
+            assert_same(r, o, FULL)
+            if kind == "uniform":
+                assert (st["fallback"] > 0) == (lds_max < 4096), st
+                assert (st["lane"] > 0) == (lds_max < 4096 and mem_max < 65536), st
+            assert st["splits"] == o["stats"]["splits"]
+        r3 = gpu_three_calls(ctx, mesh, 24)
+        assert_same(r3, o, FULL + ["pre_offsets", "pre_verts", "pre_start"])
+    finally:
+        ctx.set_param(lib.PARAM_REGION_LDS_MAX, 4096)
+        ctx.set_param(lib.PARAM_REGION_MEM_MAX, 65536)
+
+
 def test_empty(ctx):
     _say("empty mesh")
     r = gpu_mesh(ctx, empty_mesh())

@@ -9,14 +9,19 @@
 //                   vertex and at most kWalkCap vertices is complete and is
 //                   staged unrotated with the slot of its smallest vertex;
 //                   cycles with a tip or another repeated vertex are queued
-//                   for k_general_small, longer ones for k_general_big.
-// k_general_small : one lane per queued short polygon; gathers the region
-//                   into LDS and runs barrier marking, tip detection, the
-//                   repair and the piece walk there.
-// k_general_big   : one 1024-thread workgroup per long polygon; the same
-//                   steps with the region's frontier in LDS, in parallel.
-// k_general_huge  : one lane per region beyond the workgroup's LDS, global
-//                   arena (none in the benchmark workloads).
+//                   for the tip path, longer ones for the region path.
+// k_tip           : one lane per short polygon with a repeated vertex; a
+//                   single tip is repaired from the staged cycle, other
+//                   cases are left to the region path.
+// k_general_big   : the region path: a breadth-first search gathers the
+//                   region into LDS as links between local edges, then
+//                   barrier marking, tips, the repair and the pieces run
+//                   there in parallel. One wave per region (up to 128
+//                   triangles), then 1024 threads per region (up to 4096).
+// k_general_small : one lane per declined short polygon when there are many.
+// k_general_huge  : regions beyond 4096: the same steps by 1024 threads with
+//                   the region in global memory; beyond that store, one lane
+//                   per region.
 // k_scan_emit     : single-pass decoupled look-back scan of (pieces,
 //                   vertices) per polygon in seed order fused with the CSR
 //                   write.

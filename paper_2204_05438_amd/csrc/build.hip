@@ -132,6 +132,26 @@ constexpr int kSmall = 1;     // short, with a tip or a repeated vertex
 constexpr int kInvalid = 2;   // input error (reported)
 constexpr int kLarge = 3;     // longer than kWalkCap
 
+// Inclusive sum over the 64 lanes of a wave with DPP row shifts and row
+// broadcasts (no LDS round trip); every lane of the wave must be active.
+__device__ __forceinline__ uint32_t wave_incl_sum(uint32_t x) {
+  const int lane = threadIdx.x & 63, rl = lane & 15;
+  uint32_t t;
+  t = __builtin_amdgcn_update_dpp(0u, x, 0x111, 0xf, 0xf, false);  // row_shr:1
+  if (rl >= 1) x += t;
+  t = __builtin_amdgcn_update_dpp(0u, x, 0x112, 0xf, 0xf, false);  // row_shr:2
+  if (rl >= 2) x += t;
+  t = __builtin_amdgcn_update_dpp(0u, x, 0x114, 0xf, 0xf, false);  // row_shr:4
+  if (rl >= 4) x += t;
+  t = __builtin_amdgcn_update_dpp(0u, x, 0x118, 0xf, 0xf, false);  // row_shr:8
+  if (rl >= 8) x += t;
+  t = __builtin_amdgcn_update_dpp(0u, x, 0x142, 0xf, 0xf, false);  // row_bcast:15 (rows 1, 3)
+  if ((lane & 31) >= 16) x += t;
+  t = __builtin_amdgcn_update_dpp(0u, x, 0x143, 0xf, 0xf, false);  // row_bcast:31 (rows 2, 3)
+  if (lane >= 32) x += t;
+  return x;
+}
+
 // Walk kernel as a persistent state machine: every lane walks one polygon at
 // a time and takes the next one as soon as it finishes. The seed range is cut
 // into one contiguous part per XCD (workgroups are dispatched to the 8 XCDs
@@ -329,13 +349,8 @@ __global__ __launch_bounds__(256) void k_walk(const int32_t* __restrict__ list, 
     const bool fin_small = fin && result == kSmall;  // its vertices and half-edges are staged for the tip path
     if (__ballot(fin_simple || fin_small)) {
       const uint32_t need = fin_simple ? (uint32_t)L : (fin_small ? 2u * (uint32_t)L : 0u);
-      uint32_t incl = need;
-#pragma unroll
-      for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t tt = __shfl_up(incl, o, 64);
-        if (lane >= o) incl += tt;
-      }
-      const int32_t tot = (int32_t)__shfl(incl, 63, 64);
+      const uint32_t incl = wave_incl_sum(need);
+      const int32_t tot = __builtin_amdgcn_readlane((int32_t)incl, 63);
       if (tot > sleft) {  // new staging chunk for this wave
         const int32_t want_ints = max(tot, kStageChunk);
         int64_t nb = 0;
@@ -1831,21 +1846,29 @@ __global__ __launch_bounds__(NT) void k_general_big(
       if (k < L) bv[k] = vreg[u];
     }
     __syncthreads();
-    // ---- 4. pieces = cycles of nx. piece id: smallest slot on the cycle
+    // ---- 4. pieces = cycles of nx. One pointer-jumping pass gives every
+    // slot the smallest (vertex, slot) pair on its cycle and its distance to
+    // that slot, which starts the piece and names it: the window of slot k
+    // grows to [k, k + 2 span) from its own and the one of the slot span
+    // ahead; a = best vertex, q = best slot << 16 | distance (both < 2^13).
     for (int k = tid; k < L; k += kBigThreads) {
-      S.a[k] = k;
+      S.a[k] = bv[k];
+      S.q[k] = k << 16;
       S.jp[k] = S.nx[k];
     }
     __syncthreads();
     for (int span = 1; span < L; span <<= 1) {
-      int32_t na[kPer];
+      int32_t na[kPer], nq[kPer];
       int16_t nj[kPer];
 #pragma unroll
       for (int u = 0; u < kPer; ++u) {
         const int k = tid + u * kBigThreads;
         if (k < L) {
           const int j = S.jp[k];
-          na[u] = min(S.a[k], S.a[j]);
+          const int32_t va = S.a[k], vq = S.q[k], ja = S.a[j], jq = S.q[j] + span;
+          const bool take = ja < va || (ja == va && jq < vq);
+          na[u] = take ? ja : va;
+          nq[u] = take ? jq : vq;
           nj[u] = S.jp[j];
         }
       }
@@ -1855,40 +1878,46 @@ __global__ __launch_bounds__(NT) void k_general_big(
         const int k = tid + u * kBigThreads;
         if (k < L) {
           S.a[k] = na[u];
+          S.q[k] = nq[u];
           S.jp[k] = nj[u];
         }
       }
       __syncthreads();
     }
-    // per-piece smallest vertex (hkey[p]), its multiplicity (hkey[kLCap + p])
-    // and first slot holding it (hval[p] as int32)
+    // piece id (its start slot) into a, distance to the start into q; per
+    // piece: smallest vertex (hkey[p]), its multiplicity (hkey[kLCap + p]),
+    // start slot (hval[p] as int32), length (fcode[p])
     int32_t* pmin = S.hkey;
     int32_t* pcnt = S.hkey + kLCap;
     int32_t* pstart = S.hval;
+    int16_t* plen = S.fcode;
     for (int k = tid; k < L; k += kBigThreads) {
-      pmin[k] = 0x7FFFFFFF;
-      pcnt[k] = 0;
-      pstart[k] = 0x7FFFFFFF;
+      const int32_t v = S.q[k];
+      S.a[k] = v >> 16;
+      S.q[k] = v & 0xFFFF;
     }
     __syncthreads();
-    for (int k = tid; k < L; k += kBigThreads) atomicMin(&pmin[S.a[k]], bv[k]);
+    for (int k = tid; k < L; k += kBigThreads) {
+      if (S.a[k] != k) continue;
+      pmin[k] = bv[k];
+      pcnt[k] = 0;
+      pstart[k] = k;
+      plen[k] = (int16_t)(S.q[S.nx[k]] + 1);
+    }
     __syncthreads();
     for (int k = tid; k < L; k += kBigThreads) {
       const int p = S.a[k];
-      if (bv[k] == pmin[p]) {
-        atomicAdd(&pcnt[p], 1);
-        atomicMin(&pstart[p], k);
-      }
+      if (bv[k] == pmin[p]) atomicAdd(&pcnt[p], 1);
     }
     __syncthreads();
     // a piece visiting its smallest vertex twice starts at the occurrence
-    // with the lexicographically smallest continuation
+    // with the lexicographically smallest continuation; its distances are
+    // then taken again from that slot
     for (int p = tid; p < L; p += kBigThreads) {
       if (S.a[p] != p || pcnt[p] < 2) continue;
-      int best = pstart[p];
-      int len = 1;
-      for (int k = S.nx[best]; k != best && len <= L; k = S.nx[k]) ++len;
-      for (int k = S.nx[best], m = 1; m < len; k = S.nx[k], ++m) {
+      const int len = plen[p];
+      int best = p;
+      for (int k = S.nx[p], m = 1; m < len; k = S.nx[k], ++m) {
         if (bv[k] != pmin[p]) continue;
         int x = k, y = best;
         for (int z = 0; z < len; ++z) {
@@ -1900,45 +1929,12 @@ __global__ __launch_bounds__(NT) void k_general_big(
           y = S.nx[y];
         }
       }
-      pstart[p] = best;
+      if (best != p) {
+        for (int k = best, m = 0; m < len; k = S.nx[k], ++m) S.q[k] = m ? len - m : 0;
+        pstart[p] = best;
+      }
     }
     __syncthreads();
-    // distance of every slot to the slot before its piece's start
-    for (int k = tid; k < L; k += kBigThreads) {
-      const int n = S.nx[k];
-      const bool last = (n == pstart[S.a[k]]);
-      S.jp[k] = last ? (int16_t)-1 : (int16_t)n;
-      S.q[k] = last ? 0 : 1;
-    }
-    __syncthreads();
-    for (int span = 1; span < L; span <<= 1) {
-      int32_t nd[kPer];
-      int16_t nj[kPer];
-#pragma unroll
-      for (int u = 0; u < kPer; ++u) {
-        const int k = tid + u * kBigThreads;
-        if (k < L) {
-          const int j = S.jp[k];
-          if (j >= 0) {
-            nd[u] = S.q[k] + S.q[j];
-            nj[u] = S.jp[j];
-          } else {
-            nd[u] = S.q[k];
-            nj[u] = -1;
-          }
-        }
-      }
-      __syncthreads();
-#pragma unroll
-      for (int u = 0; u < kPer; ++u) {
-        const int k = tid + u * kBigThreads;
-        if (k < L) {
-          S.q[k] = nd[u];
-          S.jp[k] = nj[u];
-        }
-      }
-      __syncthreads();
-    }
     // pieces: list (jp), second vertex (pcnt reused)
     for (int k = tid; k < L; k += kBigThreads) {
       if (S.a[k] != k) continue;
@@ -1966,7 +1962,7 @@ __global__ __launch_bounds__(NT) void k_general_big(
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
       const int r = kPer * tid + u;
-      lens[u] = r < np ? S.q[pstart[S.nx[r]]] + 1 : 0;
+      lens[u] = r < np ? plen[S.nx[r]] : 0;
       mine += (uint32_t)lens[u];
     }
     uint2 tot;
@@ -2037,8 +2033,8 @@ __global__ __launch_bounds__(NT) void k_general_big(
       const int32_t sb = S.sc[SC_SBASE];
       for (int k = tid; k < L; k += kBigThreads) {
         const int p = S.a[k];
-        const int32_t len = S.q[pstart[p]] + 1;
-        stage[sb + pcnt[p] + (len - 1 - S.q[k])] = bv[k];
+        const int32_t d = S.q[k];
+        stage[sb + pcnt[p] + (d ? plen[p] - d : 0)] = bv[k];
       }
     } else if (tid == 0) {
       ps.clear(i);

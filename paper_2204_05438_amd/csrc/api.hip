@@ -264,8 +264,9 @@ int run_label(polylla_ctx* c, const polylla_tri* t, uint8_t* he, uint8_t* tri, u
   const int64_t T = t->n_halfedges / 3;
   {
     Prof p(c, s, KR_LONGEST);
-    hipLaunchKernelGGL(k_longest, dim3(grid_for(std::max(T, t->n_vertices), 256, 1 << 20)), dim3(256), 0, s, T,
-                       t->n_vertices, t->xy, t->origin, t->twin, c->lg, vtx, c->cnt);
+    // two triangles per thread (and one vertex to clear)
+    hipLaunchKernelGGL(k_longest, dim3(grid_for(std::max((T + 1) / 2, t->n_vertices), 256, 1 << 20)), dim3(256), 0,
+                       s, T, t->n_vertices, t->xy, t->origin, t->twin, c->lg, vtx, c->cnt);
   }
   if (T > 0) {
     Prof p(c, s, KR_LABEL);

@@ -199,6 +199,18 @@ def test_workload_mixed1m(ctx):
     assert_same(r, o, FULL)
 
 
+def test_uniform5m_large_regions(ctx):
+    """5M uniform points: two regions exceed the LDS of the 1024-thread
+    kernel at the default limits and are built by the global-memory path."""
+    _say("uniform5m (regions beyond the workgroup LDS)")
+    mesh = config_mesh("uniform5m")
+    o = oracle.oracle_on(mesh)
+    r = gpu_mesh(ctx, mesh)
+    assert r["stats"]["fallback"] >= 1 and r["stats"]["lane"] == 0, r["stats"]
+    assert_same(r, o, FULL)
+    assert r["stats"]["splits"] == o["stats"]["splits"]
+
+
 def test_workload_grid10m(ctx):
     """The benchmark workload at full size, in the benchmark's configuration."""
     _say("workload grid10m")

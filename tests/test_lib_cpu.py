@@ -43,3 +43,34 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(lib, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError, match="no fallback"):
         lib.load()
+
+
+def header_constants():
+    src = open(HEADER).read()
+    out = {}
+    for name, val in re.findall(r"#define POLYLLA_([A-Z0-9_]+)\s+\(?(-?\d+)u?\)?", src):
+        out[name] = int(val)
+    return out
+
+
+def test_binding_constants_match_header():
+    """Every constant the Python binding passes through the C ABI has the
+    value the header defines (error codes, label bits, parameters, profile
+    modes)."""
+    from paper_2204_05438_amd import lib
+    h = header_constants()
+    pairs = {
+        "OK": lib.OK, "EINVAL": lib.EINVAL, "ELAYOUT": lib.ELAYOUT, "ETOPO": lib.ETOPO,
+        "ECAPACITY": lib.ECAPACITY, "ENOMEM": lib.ENOMEM, "EHIP": lib.EHIP, "EDEGEN": lib.EDEGEN,
+        "EINTERNAL": lib.EINTERNAL,
+        "LONGEST": lib.LONGEST, "FRONTIER": lib.FRONTIER, "TERMINAL": lib.TERMINAL, "BORDER": lib.BORDER,
+        "BARRIER": lib.BARRIER, "REPAIRED": lib.REPAIRED, "SEED": lib.SEED, "TIP": lib.TIP,
+        "PARAM_WALK_CAP": lib.PARAM_WALK_CAP, "PARAM_WALK_BLOCKS": lib.PARAM_WALK_BLOCKS,
+        "PARAM_GEN_WAVE_MAX": lib.PARAM_GEN_WAVE_MAX, "PARAM_REGION_LDS_MAX": lib.PARAM_REGION_LDS_MAX,
+        "PARAM_REGION_MEM_MAX": lib.PARAM_REGION_MEM_MAX,
+        "PROFILE_OFF": lib.PROFILE_OFF, "PROFILE_ALL": lib.PROFILE_ALL, "PROFILE_WALK": lib.PROFILE_WALK,
+    }
+    for name, val in pairs.items():
+        assert h[name] == val, (name, h.get(name), val)
+    params = {k for k in h if k.startswith("PARAM_")}
+    assert params == {k for k in pairs if k.startswith("PARAM_")}, params

@@ -265,10 +265,13 @@ def test_layout_errors(ctx):
     assert ctx.status(raise_on_error=False) == lib.ETOPO
 
 
-@pytest.mark.parametrize("walk_cap", [4, 24])
-def test_batched_equals_per_mesh(ctx, walk_cap):
-    """A packed batch of uneven meshes gives each mesh's own polygons."""
-    _say(f"batched 40 meshes walk_cap {walk_cap}")
+@pytest.mark.parametrize("walk_cap,lds_max,mem_max", [(4, 4096, 65536), (24, 4096, 65536), (24, 32, 65536),
+                                                     (24, 32, 32), (4, 32, 32)])
+def test_batched_equals_per_mesh(ctx, walk_cap, lds_max, mem_max):
+    """A packed batch of uneven meshes gives each mesh's own polygons (also
+    with the region limits lowered, so that regions of the batch take the
+    global-memory and the one-lane paths)."""
+    _say(f"batched 40 meshes walk_cap {walk_cap} lds_max {lds_max} mem_max {mem_max}")
     from meshgen.gen import pack_meshes
     from paper_2204_05438_amd import lib
     rng = np.random.default_rng(11)
@@ -276,11 +279,18 @@ def test_batched_equals_per_mesh(ctx, walk_cap):
               for k, n in enumerate(np.rint(10 ** rng.uniform(0.8, 3.6, 40)))]
     packed, vtx_off, he_off = pack_meshes(meshes)
     ctx.set_param(lib.PARAM_WALK_CAP, walk_cap)
-    tri = lib.Tri.from_mesh(packed)
-    labels = lib.Labels.empty(tri)
-    out, poly_off = ctx.mesh_batched(tri, torch.from_numpy(vtx_off).cuda(), labels)
-    ctx.status()
-    ctx.set_param(lib.PARAM_WALK_CAP, 24)
+    ctx.set_param(lib.PARAM_REGION_LDS_MAX, lds_max)
+    ctx.set_param(lib.PARAM_REGION_MEM_MAX, mem_max)
+    try:
+        tri = lib.Tri.from_mesh(packed)
+        labels = lib.Labels.empty(tri)
+        out, poly_off = ctx.mesh_batched(tri, torch.from_numpy(vtx_off).cuda(), labels)
+        ctx.status()
+        _say(f"  stats {ctx.stats()}")
+    finally:
+        ctx.set_param(lib.PARAM_WALK_CAP, 24)
+        ctx.set_param(lib.PARAM_REGION_LDS_MAX, 4096)
+        ctx.set_param(lib.PARAM_REGION_MEM_MAX, 65536)
     off, verts, start = (x.cpu().numpy() for x in out.trimmed())
     po = poly_off.cpu().numpy()
     he = labels.he.cpu().numpy()

@@ -2052,7 +2052,7 @@ struct MemRegion {
   int32_t *q, *lnk;                                      // slots: km, links: 3 km
   int32_t *hkey, *hval;                                  // hash: mem_hcap(km) each
   int32_t *fh, *tw, *fcode, *nx, *ts, *bv;               // frontier slots: 2 km each
-  int32_t *pid[2], *jp[2], *dd[2];                       // pointer jumping: 2 km each
+  int32_t *pid[2], *jp[2], *dd[2], *ds[2];               // pointer jumping: 2 km each
   int32_t *pmin, *pcnt, *pstart, *psec, *poff, *plist, *porder;  // pieces: 2 km each
   int32_t *tipv, *tipc, *tipfar, *torder, *kc, *kf, *tst;        // tips: km each
 };
@@ -2080,6 +2080,7 @@ __device__ __forceinline__ MemRegion mem_region(int32_t* base, int64_t km) {
     r.pid[k] = take(lm);
     r.jp[k] = take(lm);
     r.dd[k] = take(lm);
+    r.ds[k] = take(lm);
   }
   r.pmin = take(lm);
   r.pcnt = take(lm);
@@ -2446,10 +2447,16 @@ __device__ void region_mem(const MemRegion& R, int32_t i, int32_t t0, int32_t nh
     if ((uint64_t)(uint32_t)v < (uint64_t)nv) or_bits(vtx, v, kTip);
   }
   if (tid == 0 && ntip) atomicAdd(&cnt->n_tips, (uint32_t)ntip);
-  // ---- 4. pieces = cycles of nx; piece id: smallest slot on the cycle
+  // ---- 4. pieces = cycles of nx: one pointer-jumping pass gives every slot
+  // the smallest (vertex, slot) pair on its cycle (the piece's start and
+  // name) and its distance to it (best vertex in pid, best slot in dd,
+  // distance in ds; ping-pong buffers)
   for (int k = tid; k < L; k += NT) {
-    R.bv[k] = origin[mem_code_gid(R, R.fcode[k])];
-    R.pid[0][k] = k;
+    const int32_t v = origin[mem_code_gid(R, R.fcode[k])];
+    R.bv[k] = v;
+    R.pid[0][k] = v;
+    R.dd[0][k] = k;
+    R.ds[0][k] = 0;
     R.jp[0][k] = R.nx[k];
   }
   __syncthreads();
@@ -2457,38 +2464,42 @@ __device__ void region_mem(const MemRegion& R, int32_t i, int32_t t0, int32_t nh
   for (int span = 1; span < L; span <<= 1) {
     for (int k = tid; k < L; k += NT) {
       const int j = R.jp[c][k];
-      R.pid[c ^ 1][k] = min(R.pid[c][k], R.pid[c][j]);
+      const int32_t va = R.pid[c][k], vs = R.dd[c][k], vd = R.ds[c][k];
+      const int32_t ja = R.pid[c][j], js = R.dd[c][j], jd = R.ds[c][j] + span;
+      const bool take = ja < va || (ja == va && (js < vs || (js == vs && jd < vd)));
+      R.pid[c ^ 1][k] = take ? ja : va;
+      R.dd[c ^ 1][k] = take ? js : vs;
+      R.ds[c ^ 1][k] = take ? jd : vd;
       R.jp[c ^ 1][k] = R.jp[c][j];
     }
     __syncthreads();
     c ^= 1;
   }
-  const int32_t* pid = R.pid[c];
-  // per-piece smallest vertex, its multiplicity and first slot holding it
+  const int32_t* pid = R.dd[c];  // piece id: its start slot
+  int32_t* dist = R.ds[c];       // distance to the piece's start
+  int32_t* plen = R.pid[c];      // (best vertices no longer needed) piece length, by piece id
+  // per piece: smallest vertex, its multiplicity, start slot, length
   for (int k = tid; k < L; k += NT) {
-    R.pmin[k] = 0x7FFFFFFF;
+    if (pid[k] != k) continue;
+    R.pmin[k] = R.bv[k];
     R.pcnt[k] = 0;
-    R.pstart[k] = 0x7FFFFFFF;
+    R.pstart[k] = k;
+    plen[k] = dist[R.nx[k]] + 1;
   }
-  __syncthreads();
-  for (int k = tid; k < L; k += NT) atomicMin(&R.pmin[pid[k]], R.bv[k]);
   __syncthreads();
   for (int k = tid; k < L; k += NT) {
     const int p = pid[k];
-    if (R.bv[k] == R.pmin[p]) {
-      atomicAdd(&R.pcnt[p], 1);
-      atomicMin(&R.pstart[p], k);
-    }
+    if (R.bv[k] == R.pmin[p]) atomicAdd(&R.pcnt[p], 1);
   }
   __syncthreads();
   // a piece visiting its smallest vertex twice starts at the occurrence with
-  // the lexicographically smallest continuation
+  // the lexicographically smallest continuation; its distances are then
+  // taken again from that slot
   for (int p = tid; p < L; p += NT) {
     if (pid[p] != p || R.pcnt[p] < 2) continue;
-    int best = R.pstart[p];
-    int len = 1;
-    for (int k = R.nx[best]; k != best && len <= L; k = R.nx[k]) ++len;
-    for (int k = R.nx[best], m = 1; m < len; k = R.nx[k], ++m) {
+    const int len = plen[p];
+    int best = p;
+    for (int k = R.nx[p], m = 1; m < len; k = R.nx[k], ++m) {
       if (R.bv[k] != R.pmin[p]) continue;
       int x = k, y = best;
       for (int z = 0; z < len; ++z) {
@@ -2500,33 +2511,12 @@ __device__ void region_mem(const MemRegion& R, int32_t i, int32_t t0, int32_t nh
         y = R.nx[y];
       }
     }
-    R.pstart[p] = best;
-  }
-  __syncthreads();
-  // distance of every slot to the slot before its piece's start
-  for (int k = tid; k < L; k += NT) {
-    const int n = R.nx[k];
-    const bool last = (n == R.pstart[pid[k]]);
-    R.jp[0][k] = last ? -1 : n;
-    R.dd[0][k] = last ? 0 : 1;
-  }
-  __syncthreads();
-  int e = 0;
-  for (int span = 1; span < L; span <<= 1) {
-    for (int k = tid; k < L; k += NT) {
-      const int j = R.jp[e][k];
-      if (j >= 0) {
-        R.dd[e ^ 1][k] = R.dd[e][k] + R.dd[e][j];
-        R.jp[e ^ 1][k] = R.jp[e][j];
-      } else {
-        R.dd[e ^ 1][k] = R.dd[e][k];
-        R.jp[e ^ 1][k] = -1;
-      }
+    if (best != p) {
+      for (int k = best, m = 0; m < len; k = R.nx[k], ++m) dist[k] = m ? len - m : 0;
+      R.pstart[p] = best;
     }
-    __syncthreads();
-    e ^= 1;
   }
-  const int32_t* dist = R.dd[e];
+  __syncthreads();
   // pieces: list and second vertex
   for (int k = tid; k < L; k += NT) {
     if (pid[k] != k) continue;
@@ -2542,7 +2532,7 @@ __device__ void region_mem(const MemRegion& R, int32_t i, int32_t t0, int32_t nh
   uint32_t run = 0;
   for (int base = 0; base < np; base += NT) {
     const int r = base + tid;
-    const uint32_t len = r < np ? (uint32_t)R.dd[e][R.pstart[R.porder[r]]] + 1u : 0u;
+    const uint32_t len = r < np ? (uint32_t)plen[R.porder[r]] : 0u;
     uint2 tot;
     const uint2 pre = block_exclusive_scan<NT>(len, 0u, &tot);
     if (r < np) R.poff[R.porder[r]] = (int32_t)(run + pre.x);
@@ -2578,13 +2568,13 @@ __device__ void region_mem(const MemRegion& R, int32_t i, int32_t t0, int32_t nh
       arena[rb + 4 * r] = R.pmin[p];
       arena[rb + 4 * r + 1] = R.psec[p];
       arena[rb + 4 * r + 2] = R.fh[R.pstart[p]];
-      arena[rb + 4 * r + 3] = dist[R.pstart[p]] + 1;
+      arena[rb + 4 * r + 3] = plen[p];
     }
   }
   for (int k = tid; k < L; k += NT) {
     const int p = pid[k];
-    const int32_t len = dist[R.pstart[p]] + 1;
-    stage[sb + R.poff[p] + (len - 1 - dist[k])] = R.bv[k];
+    const int32_t d = dist[k];
+    stage[sb + R.poff[p] + (d ? plen[p] - d : 0)] = R.bv[k];
   }
 }
 

@@ -83,7 +83,7 @@ constexpr int kBigGrid64 = 4096, kBigGrid1024 = 128;
 // workgroup: kMemGrid workgroups, each with a store for one region of up to
 // km triangles (km = min(triangles of the mesh, kMemRegionMax)) and 2 km
 // frontier half-edges. Int32 words of one workgroup's store: 4 km for the
-// triangle slots and their links, 2 hash areas of mem_hcap(km) words, 6 + 13
+// triangle slots and their links, 2 hash areas of mem_hcap(km) words, 6 + 15
 // arrays of 2 km (frontier slots; pieces) and 7 arrays of km (tips).
 constexpr int kMemGrid = 8;
 constexpr int64_t kMemRegionMax = 1 << 16;
@@ -92,7 +92,7 @@ __host__ __device__ inline int64_t mem_hcap(int64_t km) {
   while (h < 4 * km) h <<= 1;
   return h;
 }
-__host__ __device__ inline int64_t mem_words(int64_t km) { return 4 * km + 2 * mem_hcap(km) + 38 * km + 7 * km; }
+__host__ __device__ inline int64_t mem_words(int64_t km) { return 4 * km + 2 * mem_hcap(km) + 42 * km + 7 * km; }
 
 __device__ __forceinline__ int32_t he_next(int32_t h) {
   int32_t r = h % 3;

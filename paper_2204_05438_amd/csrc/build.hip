@@ -2596,7 +2596,8 @@ __global__ __launch_bounds__(1024) void k_general_huge(
   __shared__ int32_t s_last;
   const int tid = threadIdx.x;
   const uint32_t nin = (uint32_t)min((int64_t)cnt->n_fallback, in_cap);
-  if (nin > 0) {
+  if (nin == 0) return;  // (the one-lane list is filled only by this path)
+  {
     const MemRegion R = mem_region(store + (int64_t)blockIdx.x * mem_words(km), km);
     for (;;) {
       if (tid == 0) sc[SC_ITEM] = (int32_t)atomicAdd(&cnt->mem_ticket, 1u);

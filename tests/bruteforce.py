@@ -163,6 +163,20 @@ class Brute:
             return (t, i) in front
 
         comp, pre = self.faces(fr)
+        # barrier edges: both directions of one frontier edge on the same
+        # boundary cycle before the repair; tips: v_b with v_a == v_c there
+        barrier = np.zeros(3 * self.T, np.uint8)
+        tipv = set()
+        for _, c in pre:
+            L = len(c)
+            steps = {(c[k], c[(k + 1) % L]) for k in range(L)}
+            for k in range(L):
+                a, b = c[k], c[(k + 1) % L]
+                if (b, a) in steps:
+                    t, i = self.dedge[(a, b)]
+                    barrier[3 * t + i] = BARRIER
+                if L >= 3 and c[k] == c[(k + 2) % L]:
+                    tipv.add(c[(k + 1) % L])
         extra = set()  # undirected frontier edges added by the repair
 
         def fr2(t, i):
@@ -189,7 +203,7 @@ class Brute:
             if not changed:
                 break
         _, final = self.faces(fr2)
-        return {"longest": lg, "he": he, "seed": seed, "comp": comp,
+        return {"longest": lg, "he": he, "seed": seed, "comp": comp, "barrier": barrier, "tips": tipv,
                 "pre": [c for _, c in pre], "final": [c for _, c in final], "extra": extra}
 
 

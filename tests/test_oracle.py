@@ -66,6 +66,9 @@ def _compare_with_brute(mesh):
     rep = {frozenset((int(tri[h // 3][h % 3]), int(tri[h // 3][(h % 3 + 1) % 3])))
            for h in np.nonzero(o["he"] & REPAIRED)[0]}
     assert rep == b["extra"]
+    # barrier edges and barrier-edge tips of the polygons before repair
+    assert np.array_equal(o["he"] & BARRIER, b["barrier"])
+    assert set(np.nonzero(o["vtx"] & 1)[0].tolist()) == b["tips"]
     return o
 
 
@@ -74,6 +77,36 @@ def _compare_with_brute(mesh):
 def test_oracle_vs_bruteforce(kind, seed):
     n = [6, 12, 25, 40, 60, 90, 120, 160, 200, 250, 300, 20][seed]
     _compare_with_brute(random_mesh(1000 * seed + 7, n, kind))
+
+
+# Tiny meshes chosen (by their seeds) because they reach the rare corners of
+# the repair: a split at a smaller tip that removes a larger tip of the same
+# polygon (fewer splits than tips: Algorithm 4 repeated per Algorithm 1 finds
+# the second tip gone on the next pass), and a region that touches itself at a
+# vertex without a barrier edge (a pinched cycle, which the tip rule leaves as
+# it is). The brute force decides every expected value.
+KILLED_TIP_CASES = [("cluster", 30, 143), ("cluster", 30, 229), ("cluster", 30, 112),
+                    ("uniform", 30, 193), ("cluster", 30, 118)]
+PINCH_CASES = [("cluster", 30, 383), ("cluster", 60, 315), ("cluster", 100, 130)]
+
+
+@pytest.mark.parametrize("kind,n,seed", KILLED_TIP_CASES)
+def test_killed_tip_vs_bruteforce(kind, n, seed):
+    mesh = random_mesh(seed * 7919 + n, n, kind)
+    o = _compare_with_brute(mesh)
+    b = Brute(mesh).mesh_pipeline()
+    assert len(b["tips"]) > len(b["extra"]), "the case must remove a tip without a split"
+    assert o["stats"]["tips"] == len(b["tips"]) and o["stats"]["splits"] == len(b["extra"])
+
+
+@pytest.mark.parametrize("kind,n,seed", PINCH_CASES)
+def test_pinched_region_vs_bruteforce(kind, n, seed):
+    mesh = random_mesh(seed * 7919 + n, n, kind)
+    o = _compare_with_brute(mesh)
+    b = Brute(mesh).mesh_pipeline()
+    pinched = [c for c in b["final"] if len(set(c)) < len(c)]
+    assert pinched, "the case must keep a cycle with a repeated vertex"
+    assert o["stats"]["nonsimple_final"] == len(pinched)
 
 
 def test_bruteforce_sees_repairs():

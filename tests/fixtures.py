@@ -50,3 +50,36 @@ def random_mesh(seed: int, n: int, kind: str = "uniform"):
 
 def empty_mesh():
     return mesh_from_triangles(np.zeros((0, 2)), np.zeros((0, 3), dtype=np.int64))
+
+
+def permute_mesh(mesh, seed: int, block: int = 0, rotate: bool = True):
+    """The same triangulation with its triangles renumbered and each triangle's
+    half-edges rotated (a seeded relabelling, no geometry changes).
+
+    block = 0 shuffles triangles uniformly (no index locality left); block > 0
+    shuffles whole runs of `block` consecutive triangles, keeping locality
+    inside each run. Returns (mesh, tri_map, rot): old triangle t becomes
+    tri_map[t], and its half-edge 3t+i becomes 3*tri_map[t] + (i - rot[t]) % 3.
+    """
+    from meshgen.gen import Mesh
+    T = mesh.n_tri
+    rng = np.random.default_rng(seed)
+    if block > 0:
+        nb = (T + block - 1) // block
+        order = np.concatenate([np.arange(b * block, min(T, (b + 1) * block)) for b in rng.permutation(nb)])
+    else:
+        order = rng.permutation(T)
+    tri_map = np.empty(T, np.int64)
+    tri_map[order] = np.arange(T)
+    rot = rng.integers(0, 3, T) if rotate else np.zeros(T, np.int64)
+    h = np.arange(3 * T, dtype=np.int64)
+    t, i = np.divmod(h, 3)
+    he_map = 3 * tri_map[t] + (i - rot[t]) % 3
+    origin = np.empty(3 * T, np.int32)
+    origin[he_map] = mesh.origin
+    twin = np.full(3 * T, -1, np.int32)
+    inner = mesh.twin >= 0
+    twin[he_map[inner]] = he_map[mesh.twin[inner]]
+    nxt = (h - h % 3 + (h + 1) % 3).astype(np.int32)
+    out = Mesh(xy=mesh.xy, origin=origin, twin=twin, next=nxt, lattice=mesh.lattice, meta=dict(mesh.meta))
+    return out, tri_map, rot

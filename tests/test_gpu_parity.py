@@ -5,12 +5,22 @@ import pytest
 
 import oracle
 from bruteforce import csr_cycles
-from fixtures import empty_mesh, golden, golden_names, random_mesh
-from meshgen.gen import config_mesh
+from fixtures import empty_mesh, golden, golden_names, permute_mesh, random_mesh
+from meshgen.gen import config_mesh as _config_mesh
 
 pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
+
+
+_MESHES = {}
+
+
+def config_mesh(name):
+    """Workload meshes, generated once per test session."""
+    if name not in _MESHES:
+        _MESHES[name] = _config_mesh(name)
+    return _MESHES[name]
 
 
 def _say(msg):
@@ -197,6 +207,25 @@ def test_workload_mixed1m(ctx):
     _say("workload mixed1m, walk cap 4")
     r = gpu_mesh(ctx, mesh, 4)
     assert_same(r, o, FULL)
+
+
+@pytest.mark.parametrize("block", [0, 3000])
+def test_permuted_layout_mixed1m(ctx, block):
+    """The 1M-point mixed workload with its triangles renumbered (uniformly at
+    random, or as shuffled runs of 3000 triangles that straddle the label
+    kernel's tiles) and every triangle's half-edges rotated. Without the
+    space-filling order most neighbour lookups miss the label kernel's LDS
+    window and the walk's per-XCD seed ranges hold scattered triangles; the
+    output must still equal the oracle's on the same input, and its polygons
+    those of the unpermuted mesh."""
+    _say(f"permuted mixed1m block {block}")
+    mesh = config_mesh("mixed1m")
+    p, _, _ = permute_mesh(mesh, 17 + block, block=block)
+    r = gpu_mesh(ctx, p)
+    o = oracle.oracle_on(p)
+    assert_same(r, o, FULL)
+    base = oracle.oracle_on(mesh)
+    assert sorted(csr_cycles(r["offsets"], r["verts"])) == sorted(csr_cycles(base["offsets"], base["verts"]))
 
 
 def test_uniform5m_large_regions(ctx):

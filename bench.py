@@ -1,22 +1,35 @@
 """Throughput benchmark of the terminal-edge-region mesher on one MI355X.
 
-One step = label -> build -> repair (polylla_mesh) over the resident 10M-point
-jittered-grid Delaunay mesh (inputs in HBM before timing starts, outputs at
-worst-case capacity). Prints ONE JSON line on stdout; progress goes to stderr.
+The default run measures the three workloads of the metric and prints ONE
+JSON line on stdout (progress goes to stderr):
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload grid10m]
-                  [--no-cpu] [--calib-copy-mb M]
-  python bench.py --workload batched2000 [--steps K] [--retune]
-        (2,000 meshes in one packed launch, eager and graph-replayed, against
-         one launch per mesh; walk parameters from the autotuner)
-  python bench.py --workload serve2000 [--slots S]
-        (continuous-batching server: capacity, then 0.5x and 0.9x of it)
+  grid10m  (headline) one step = label -> build -> repair (polylla_mesh) over
+           the resident 10M-point jittered-grid Delaunay mesh: inputs in HBM
+           before timing starts, outputs at worst-case capacity; one event
+           pair per step (mean, median, p99), per-kernel table from separate
+           steps, HBM roofline of the dominant kernel and of the whole step;
+  batched2000  2,000 uniform meshes (points log-uniform in [1e3, 1e6]) in one
+           polylla_mesh_batched call, eager and replayed from a HIP graph,
+           against one polylla_mesh launch per mesh on the same GPU;
+  serve2000    continuous-batching server: capacity, then Poisson arrivals at
+           0.5x and 0.9x of it; meshes/s, triangles/s, p50/p99 latency.
+
+Every batched and served result is compared with the CPU oracle (digests of
+labels and polygons per mesh, the oracle run by a process pool over the host
+cores while the meshes are generated). cpu_baseline: the oracle on one core,
+median of 3 runs on a bounded sample of the grid workload, plus the pool
+throughput of the batched and served oracle runs.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload all|grid10m|batched2000|serve2000]
+                  [--no-cpu] [--calib-copy-mb M] [--retune]
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
@@ -25,35 +38,49 @@ sys.path.insert(0, ROOT)
 
 METRIC = "triangles/sec (label+build+repair) at 10M pts; batched vs per-mesh launch; p99"
 HBM_PEAK_GBS = 8000.0
+POOL_MAX = 16  # host processes (the GPU machine's CPU share)
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(kernel: str, n: dict) -> int:
-    """Compulsory bytes of one launch: every array element the kernel must
-    read or write, counted once."""
+# ---------------------------------------------------------------------------
+# byte models
+
+def paper_bytes(n: dict) -> dict:
+    """Compulsory HBM bytes of one step by the method's own data flow (each
+    array element read or written once): label 16N (xy) + 12T (origin) + 12T
+    (twin) + 1T (labels); build 4R (seed list) + 8T (twin of the internal
+    edges, crossed twice) + 1T (labels) + 4S' (origin of the cycle vertices)
+    + 4S (vertex ids written) + 4F (offsets), S' = T + 2R before the repair,
+    S = T + 2F after. Split by kernel of the path."""
     V, T, R, F, S, Sp = n["V"], n["T"], n["R"], n["F"], n["S"], n["Sp"]
-    table = {
-        # origin 12T + xy 16V read, Max 1T + vtx clear 1V written
-        "k_longest": 13 * T + 17 * V,
-        # twin 12T + origin 12T + Max 1T read; labels 3T + 1T and walk words 12T written
-        "k_label": 41 * T,
-        # seed flags 1T read, the seed list 4R written
+    return {
+        "k_longest": 16 * V + 12 * T,          # xy, origin (LabelMax)
+        "k_label": 12 * T + T,                 # twin, labels (LabelSeed, LabelFrontier)
+        "k_seeds": 4 * R,                      # seed list
+        "k_walk": 8 * T + T + 4 * Sp,          # twin crossings, labels, cycle origins
+        "k_scan_emit": 4 * S + 4 * F,          # CSR written
+        "step": 16 * V + 25 * T + 4 * R + 9 * T + 4 * Sp + 4 * S + 4 * F,
+    }
+
+
+def design_bytes(n: dict) -> dict:
+    """Bytes each kernel of this design moves by its own data layout (every
+    array element once, including its own intermediate arrays)."""
+    V, T, R, F, S, Sp = n["V"], n["T"], n["R"], n["F"], n["S"], n["Sp"]
+    return {
+        "k_longest": 13 * T + 17 * V,          # origin 12T + xy 16V read, Max 1T + vtx clear 1V written
+        "k_label": 41 * T,                     # twin 12T + origin 12T + Max 1T; labels 4T + walk words 12T
         "k_seeds": T + 4 * R,
-        # walk words 12T (one triple per triangle of every region) + seed list
-        # 4R read; staged cycles 4Sp and five per-polygon words 20R written
-        "k_walk": 12 * T + 24 * R + 4 * Sp,
-        # staged cycles 4S + per-polygon words 28R read; verts 4S + offsets 4F written
+        "k_walk": 12 * T + 24 * R + 4 * Sp,    # walk words, seeds; staged cycles + per-polygon records
         "k_scan_emit": 8 * S + 28 * R + 4 * F,
     }
-    return table.get(kernel, 0)
 
 
 def kernel_sources_digest() -> str:
     """sha256 over the HIP sources of the library (file names and contents)."""
-    import hashlib
     d = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2204_05438_amd", "csrc")
     for name in sorted(os.listdir(csrc)):
@@ -81,161 +108,301 @@ def measured_traffic(kernel: str, workload: str):
     return None
 
 
-def _gen_batch_mesh(job):
-    """Worker: triangulate mesh m of the batched workload (host only)."""
-    m, n = job
+def host_info() -> dict:
+    model = platform.processor() or ""
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return {"cpu_model": model, "nproc": os.cpu_count(), "cpus_available": avail}
+
+
+def percentile(xs, p):
+    import numpy as np
+    return float(np.percentile(np.asarray(xs, dtype=np.float64), p))
+
+
+# ---------------------------------------------------------------------------
+# host workers (forked before the first GPU call; they never touch the GPU)
+
+def digest(offsets, verts, he) -> str:
+    import numpy as np
+    d = hashlib.sha256()
+    for a, dt in ((offsets, np.int32), (verts, np.int32), (he, np.uint8)):
+        d.update(np.ascontiguousarray(a, dtype=dt).tobytes())
+    return d.hexdigest()
+
+
+def _oracle_digest(mesh, with_labels=True):
+    import numpy as np
+    import oracle
+    t0 = time.perf_counter()
+    o = oracle.oracle_on(mesh)
+    dt = time.perf_counter() - t0
+    he = o["he"] if with_labels else np.zeros(0, np.uint8)
+    return digest(o["offsets"], o["verts"], he), dt, int(o["offsets"].size - 1)
+
+
+def _job_batch_mesh(job):
+    """Triangulate mesh m of the batched workload and digest its oracle output."""
+    m, n, with_oracle = job
     from meshgen.gen import batch_points, mesh_from_points
     mesh = mesh_from_points(batch_points(m, n))
-    return m, mesh.xy, mesh.origin, mesh.twin
+    dg = _oracle_digest(mesh) if with_oracle else (None, 0.0, -1)
+    return m, mesh.xy, mesh.origin, mesh.twin, dg
 
 
-def batch_meshes(n_meshes: int):
-    """The batched workload's meshes, generated by a process pool (before any
-    GPU call, so the workers fork from a process without a GPU context)."""
-    from multiprocessing import get_context
-    from meshgen.gen import Mesh, batch_sizes
-    sizes = batch_sizes(n_meshes)
-    order = sorted(range(n_meshes), key=lambda m: -int(sizes[m]))  # largest first balances the pool
-    workers = max(1, min(16, os.cpu_count() or 1))
-    meshes = [None] * n_meshes
-    with get_context("fork").Pool(workers) as pool:
-        for m, xy, origin, twin in pool.imap_unordered(_gen_batch_mesh, [(m, int(sizes[m])) for m in order]):
-            meshes[m] = Mesh(xy=xy, origin=origin, twin=twin, next=None)
-    return meshes, workers
-
-
-def _gen_request(job):
-    """Worker: triangulate one request of the serving workload (host only)."""
-    j, n, kind, seed = job
+def _job_request(job):
+    """Triangulate one request of the serving workload and digest its oracle output."""
+    j, n, kind, seed, with_oracle = job
     from meshgen.gen import mesh_from_points, request_points
     mesh = mesh_from_points(request_points(n, kind, seed))
-    return j, mesh.xy, mesh.origin, mesh.twin
+    dg = _oracle_digest(mesh, with_labels=False) if with_oracle else (None, 0.0, -1)
+    return j, mesh.xy, mesh.origin, mesh.twin, dg
 
 
-def bench_serve(args, n_requests: int):
-    """Serving: capacity with every request at t = 0, then Poisson arrivals at
-    0.5x and 0.9x of that capacity; throughput and p50/p99 latency."""
+def _job_workload_oracle(name):
+    """The oracle on a whole single-mesh workload (identity check of the
+    timed GPU output)."""
+    from meshgen.gen import config_mesh
+    mesh = config_mesh(name)
+    return _oracle_digest(mesh)
+
+
+def generate(pool, fn, jobs, n):
+    """Run generation jobs largest first; returns meshes, digests, oracle seconds."""
+    from meshgen.gen import Mesh
+    meshes, digests, secs = [None] * n, [None] * n, 0.0
+    for k, xy, origin, twin, (dg, dt, _) in pool.imap_unordered(fn, jobs):
+        meshes[k] = Mesh(xy=xy, origin=origin, twin=twin, next=None)
+        digests[k] = dg
+        secs += dt
+    return meshes, digests, secs
+
+
+# ---------------------------------------------------------------------------
+# grid10m
+
+def bench_single(args, pool, workload: str):
     import numpy as np
-    from multiprocessing import get_context
-    from meshgen.gen import Mesh, serve_requests
-    t0 = time.time()
-    base = serve_requests(n_requests, rate=1.0)   # arrival times for rate 1/s; scaled below
-    workers = max(1, min(16, os.cpu_count() or 1))
-    order = sorted(range(n_requests), key=lambda j: -base[j][1])
-    meshes = [None] * n_requests
-    with get_context("fork").Pool(workers) as pool:
-        for j, xy, origin, twin in pool.imap_unordered(
-                _gen_request, [(j, base[j][1], base[j][2], base[j][3]) for j in order]):
-            meshes[j] = Mesh(xy=xy, origin=origin, twin=twin, next=None)
-    T_all = sum(m.n_tri for m in meshes)
-    log(f"generated {n_requests} requests ({T_all} triangles) with {workers} processes in {time.time() - t0:.1f}s")
     import torch
-    from paper_2204_05438_amd import serve
-    server = serve.Server(0, slots=args.slots, budget_bytes=64 << 30, max_batch_tri=1 << 24)
-    log(f"server: {args.slots} slots, 64 GB admission budget, batches of up to 2^24 triangles")
+    from meshgen.gen import config_mesh
+    from paper_2204_05438_amd import lib
 
-    pinned = [serve.Request.from_mesh(j, 0.0, meshes[j]) for j in range(n_requests)]  # pinned once
-    del meshes
-
-    def requests(scale):
-        return [serve.Request(j, base[j][0] * scale, p.xy, p.twin, p.origin) for j, p in enumerate(pinned)]
-
-    warm = server.run(requests(0.0)[: min(32, n_requests)])
-    cap = server.run(requests(0.0))
-    log(f"capacity (all at t=0): {cap['meshes_per_s']} meshes/s, {cap['triangles_per_s']:.4g} triangles/s")
-    runs = {"saturated": cap}
-    for f in (0.5, 0.9):
-        rate = f * cap["meshes_per_s"]
-        res = server.run(requests(1.0 / rate))
-        res["rate_meshes_per_s"] = round(rate, 2)
-        runs[f"{f}x"] = res
-        log(f"{f}x capacity ({rate:.1f}/s): p50 {res['latency_ms']['p50']} ms, p99 {res['latency_ms']['p99']} ms, "
-            f"{res['meshes_per_s']} meshes/s")
-    server.close()
-    del warm
-    line = {
-        "metric": "served meshes: triangles/sec and p50/p99 latency at 0.9x capacity",
-        "value": runs["0.9x"]["triangles_per_s"], "unit": "triangles/s", "n_gpus": 1,
-        "steps": n_requests, "warmup": 32, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64+i32", "data": "synthetic",
-        "config": {"workload": f"serve{n_requests}: Poisson arrivals (seed 5), points round(10^U(3, log10 2e6)), "
-                               f"uniform or 4-cluster (sigma 0.05) with probability 1/2, request j seeded 50000+j; "
-                               f"{T_all} triangles in total; 64 GB admission budget; {args.slots} slots",
-                   "requests": n_requests, "triangles": T_all},
-        "serving": runs,
-    }
-    print(json.dumps(line), flush=True)
-
-
-def bench_batched(args, n_meshes: int):
-    """One packed launch (eager and replayed from a captured HIP graph) against
-    one polylla_mesh launch per mesh, on the same GPU with the same outputs."""
-    import numpy as np
+    ident = None if args.no_cpu else pool.apply_async(_job_workload_oracle, (workload,))
     t0 = time.time()
-    meshes, workers = batch_meshes(n_meshes)
+    mesh = config_mesh(workload)
+    log(f"generated {workload}: {mesh.n_vertices} vertices, {mesh.n_tri} triangles in {time.time() - t0:.1f}s")
+    dev = torch.device("cuda:0")
+    ctx = lib.Context(0)
+    tri = lib.Tri.from_mesh(mesh, device=dev)
+    labels = lib.Labels.empty(tri)
+    out = lib.Polys.empty(tri, with_start=True)
+    ctx.reserve(tri.n_halfedges, tri.n_vertices)
+    for kv in args.param:
+        name, val = kv.split("=")
+        ctx.set_param({"walk_cap": lib.PARAM_WALK_CAP, "walk_blocks": lib.PARAM_WALK_BLOCKS}[name], int(val))
+    torch.cuda.synchronize()
+    log("inputs resident on the device")
+    if args.calib_copy_mb:
+        nb = args.calib_copy_mb << 20
+        src = torch.empty(nb // 4, dtype=torch.int32, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy of {args.calib_copy_mb} MiB done")
+    for _ in range(args.warmup):
+        ctx.mesh(tri, labels, out)
+    ctx.status()
+    stats = ctx.stats()
+    F, S = (int(x) for x in out.counts.tolist())
+    log(f"warmup done: {stats}, F={F}, S={S}")
+
+    # Timed steps, one event pair per step on the launching stream; the
+    # library records events around the walk kernel only (its live duration
+    # feeds the roofline; events around every kernel would add gaps).
+    stream = torch.cuda.current_stream()
+    ctx.profile(True, walk_only=True)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    for a, b in evs:
+        a.record(stream)
+        ctx.mesh(tri, labels, out)
+        b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ctx.status()
+    walk_live = ctx.profile_read()
+    ctx.profile(False)
+    step_ms = [a.elapsed_time(b) for a, b in evs]
+    ms_total = evs[0][0].elapsed_time(evs[-1][1])
+    ms_step = ms_total / args.steps
+    T = mesh.n_tri
+    value = T / (ms_step / 1e3)
+    log(f"{args.steps} steps: {ms_step:.3f} ms/step (median {percentile(step_ms, 50):.3f}, "
+        f"p99 {percentile(step_ms, 99):.3f}), {value:.4g} triangles/s")
+    ctx.profile(True)
+    for _ in range(min(args.steps, 5)):
+        ctx.mesh(tri, labels, out)
+    torch.cuda.synchronize()
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    ctx.status()
+    prof.update(walk_live)
+    for k, (ms, nlaunch) in sorted(prof.items(), key=lambda kv: -kv[1][0] / max(kv[1][1], 1)):
+        log(f"  {k:16s} {ms / max(nlaunch, 1) * 1e3:10.1f} us/launch  ({nlaunch} launches)")
+
+    n = {"V": mesh.n_vertices, "T": T, "R": stats["seeds"], "F": F, "S": S, "Sp": T + 2 * stats["seeds"]}
+    pb, db = paper_bytes(n), design_bytes(n)
+    us = {k: ms / max(nl, 1) * 1e3 for k, (ms, nl) in prof.items()}
+    dominant = max(us, key=us.get)
+    dom_us = us[dominant]
+    achieved = pb.get(dominant, 0) / (dom_us / 1e6) / 1e9
+    step_gbs = pb["step"] / (ms_step / 1e3) / 1e9
+    roofline = {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic(dominant, workload),
+                "avg_launch_us": round(dom_us, 1), "algorithmic_bytes": pb.get(dominant, 0),
+                "whole_step": {"algorithmic_bytes": pb["step"], "achieved": round(step_gbs, 1),
+                               "frac": round(step_gbs / HBM_PEAK_GBS, 4)},
+                "design_bytes": {"bytes": db.get(dominant, 0),
+                                 "achieved": round(db.get(dominant, 0) / (dom_us / 1e6) / 1e9, 1)}}
+    kernels = {k: {"us_per_launch": round(v, 1),
+                   "paper_GBps": round(pb.get(k, 0) / (v / 1e6) / 1e9, 1),
+                   "design_GBps": round(db.get(k, 0) / (v / 1e6) / 1e9, 1)} for k, v in us.items()}
+
+    cpu, identical = None, None
+    if not args.no_cpu:
+        import oracle
+        off, verts, _ = (x.cpu().numpy() for x in out.trimmed())
+        gpu_dg = digest(off, verts, labels.he.cpu().numpy())
+        # the CPU baseline: the oracle alone on one core, median of 3, on a
+        # bounded sample of the same recipe (a 1000 x 1000 jittered grid)
+        sample = config_mesh("grid1000x")
+        secs = []
+        for _ in range(3):
+            c0 = time.perf_counter()
+            oracle.oracle_on(sample)
+            secs.append(time.perf_counter() - c0)
+        med = sorted(secs)[1]
+        dg, full_s, _ = ident.get()
+        identical = dg == gpu_dg
+        cpu = {"value": round(sample.n_tri / med, 1), "unit": "triangles/s", "cores": 1, "kind": "oracle",
+               "sample": f"grid1000x ({sample.n_tri} triangles, the grid recipe at 1M points), label+build+repair, "
+                         f"median of 3 runs on one host core",
+               "seconds_runs": [round(x, 3) for x in secs],
+               "full_mesh": {"seconds": round(full_s, 2), "triangles_per_s": round(T / full_s, 1),
+                             "note": "one run on the whole grid10m mesh, in a pool process beside the GPU steps"},
+               **host_info()}
+        log(f"oracle: sample median {med:.2f}s ({cpu['value']:.4g} triangles/s); full mesh {full_s:.1f}s, "
+            f"GPU output identical: {identical}")
+    ctx.close()
+    del tri, labels, out
+    torch.cuda.empty_cache()
+    return {
+        "ms_per_step": round(ms_step, 4), "value": round(value, 1),
+        "steps_ms": {"mean": round(ms_step, 4), "median": round(percentile(step_ms, 50), 4),
+                     "p99": round(percentile(step_ms, 99), 4), "min": round(min(step_ms), 4),
+                     "wall_mean": round(wall / args.steps * 1e3, 4)},
+        "config": {"workload": f"{workload}: jittered 3163x3163 grid in [0,1]^2 (seed 3), Delaunay, "
+                               f"{mesh.n_vertices} vertices, {T} triangles, one mesh per step",
+                   "polygons": F, "seeds": stats["seeds"], "tips": stats["tips"], "splits": stats["splits"],
+                   "general_small": stats["general_small"], "general_big": stats["general_big"]},
+        "roofline": roofline, "kernels": kernels, "cpu_baseline": cpu, "oracle_identical": identical,
+    }
+
+
+# ---------------------------------------------------------------------------
+# batched
+
+def batch_digests(meshes, out, labels, he_off):
+    """Per mesh: digest of its labels and polygons in the oracle's form."""
+    import numpy as np
+    off, verts, _, po = (x.cpu().numpy() if x is not None else None for x in out.trimmed())
+    he = labels.he.cpu().numpy()
+    res = []
+    for k in range(len(meshes)):
+        a, b = int(po[k]), int(po[k + 1])
+        o = off[a:b + 1]
+        res.append(digest((o - o[0]).astype(np.int32), verts[o[0]:o[-1]], he[he_off[k]:he_off[k + 1]]))
+    return res
+
+
+def bench_batched(args, pool, n_meshes: int):
+    import numpy as np
+    from meshgen.gen import batch_sizes
+    t0 = time.time()
+    sizes = batch_sizes(n_meshes)
+    order = sorted(range(n_meshes), key=lambda m: -int(sizes[m]))
+    meshes, ref, oracle_s = generate(pool, _job_batch_mesh, [(m, int(sizes[m]), not args.no_cpu) for m in order],
+                                     n_meshes)
     T_all = sum(m.n_tri for m in meshes)
-    log(f"generated {n_meshes} meshes ({T_all} triangles) with {workers} processes in {time.time() - t0:.1f}s")
-    from meshgen.gen import pack_meshes
-    packed, vtx_off, he_off = pack_meshes(meshes, with_next=False)
+    log(f"batched: generated {n_meshes} meshes ({T_all} triangles) with {pool._processes} processes "
+        f"in {time.time() - t0:.1f}s (oracle {oracle_s:.1f} process-s)")
     import torch
     from paper_2204_05438_amd import autotune, lib
     dev = torch.device("cuda:0")
     ctx = lib.Context(0)
-    tri = lib.Tri.from_mesh(packed, device=dev, with_next=False)
-    del packed
-    labels = lib.Labels.empty(tri)
-    out = lib.Polys.empty(tri, with_start=True)
-    voff = torch.from_numpy(vtx_off).to(dev)
-    poly_off = torch.empty(n_meshes + 1, dtype=torch.int64, device=dev)
-    ctx.reserve(tri.n_halfedges, tri.n_vertices)
+    batch = lib.Batch.from_meshes(meshes, device=dev)
+    labels = lib.Labels.empty(batch)
+    out = lib.BatchOut.empty(batch, with_start=True)
+    ctx.reserve_batch(batch.n_halfedges, batch.n_vertices, n_meshes)
     tris = [lib.Tri.from_mesh(m, device=dev, with_next=False) for m in meshes]
     labs = [lib.Labels.empty(t) for t in tris]
     outs = [lib.Polys.empty(t, with_start=True) for t in tris]
+    ctx.reserve(max(t.n_halfedges for t in tris), max(t.n_vertices for t in tris))
     torch.cuda.synchronize()
-    log("inputs resident on the device (packed and per mesh)")
+    log("batched: inputs resident on the device (batch and per mesh)")
 
     def packed_call():
-        ctx.mesh_batched(tri, voff, labels, out, poly_off)
+        ctx.mesh_batched(batch, labels, out)
 
     def per_mesh_loop():
         for t_, l_, o_ in zip(tris, labs, outs):
             ctx.mesh(t_, l_, o_)
 
-    tuned = autotune.tune(ctx, packed_call, tri.n_halfedges, batched=True, reps=2,
+    tuned = autotune.tune(ctx, packed_call, batch.n_halfedges, batched=True, reps=2,
                           cache=args.tune_cache or autotune.DEFAULT_CACHE, force=args.retune)
-    log(f"tuned: walk_blocks {tuned['walk_blocks']}, walk_cap {tuned['walk_cap']} ({tuned['source']})")
+    log(f"batched: tuned {tuned}")
     stream = torch.cuda.current_stream()
 
     def timed(fn, reps):
         fn()
         ctx.status()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
+        ms = []
         torch.cuda.synchronize()
-        w0 = time.perf_counter()
-        e0.record(stream)
         for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
             fn()
-        e1.record(stream)
-        torch.cuda.synchronize()
-        wall = (time.perf_counter() - w0) / reps
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
         ctx.status()
-        return e0.elapsed_time(e1) / reps, wall * 1e3
+        return {"ms_mean": round(sum(ms) / len(ms), 3), "ms_median": round(percentile(ms, 50), 3),
+                "ms_p99": round(percentile(ms, 99), 3)}
 
-    loop_ms, loop_wall = timed(per_mesh_loop, args.steps)
-    log(f"one launch per mesh: {loop_ms:.2f} ms (wall {loop_wall:.2f} ms)")
-    eager_ms, eager_wall = timed(packed_call, args.steps)
-    log(f"packed, eager: {eager_ms:.2f} ms")
+    steps = max(2, args.batch_steps)
+    loop = timed(per_mesh_loop, steps)
+    log(f"batched: one launch per mesh {loop}")
+    eager = timed(packed_call, steps)
+    log(f"batched: one call, eager {eager}")
     ctx.profile(True)
     packed_call()
     ctx.status()
     prof = ctx.profile_read()
     ctx.profile(False)
     stats = ctx.stats()
-    log(f"packed: {stats}")
-    for k, (ms, nl) in sorted(prof.items(), key=lambda kv: -kv[1][0]):
-        log(f"  {k:16s} {ms / max(nl, 1) * 1e3:10.1f} us/launch")
-    # capture the packed call in a HIP graph and replay it
     side = torch.cuda.Stream()
     side.wait_stream(stream)
     with torch.cuda.stream(side):
@@ -246,48 +413,101 @@ def bench_batched(args, n_meshes: int):
     with torch.cuda.graph(graph):
         packed_call()
     torch.cuda.synchronize()
-    graph_ms, graph_wall = timed(graph.replay, args.steps)
-    log(f"packed, graph replay: {graph_ms:.2f} ms")
-    # the outputs agree mesh by mesh (sample, plus every polygon count)
-    po = poly_off.cpu().numpy()
-    counts = np.array([o.counts.cpu().numpy() for o in outs])
-    same = bool(np.array_equal(np.diff(po), counts[:, 0]))
-    off_all = out.offsets[:int(po[-1]) + 1].cpu().numpy()
-    rng = np.random.default_rng(0)
-    for m in sorted(set(rng.integers(0, n_meshes, 12).tolist()) | {int(np.argmax([x.n_tri for x in meshes]))}):
-        o_off, o_verts, _ = (x.cpu().numpy() for x in outs[m].trimmed())
-        a, b = int(po[m]), int(po[m + 1])
-        got_off = off_all[a:b + 1] - off_all[a]
-        got_verts = out.verts[int(off_all[a]):int(off_all[b])].cpu().numpy() - vtx_off[m]
-        same &= bool(np.array_equal(got_off, o_off) and np.array_equal(got_verts, o_verts))
-    log(f"packed output equals the per-mesh outputs: {same}")
-    value = T_all / (graph_ms / 1e3)
-    line = {
-        "metric": "triangles/sec (label+build+repair), batched meshes in one packed graph launch",
-        "value": round(value, 1), "unit": "triangles/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
-        "ms_per_step": round(graph_ms, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64+i32", "data": "synthetic",
-        "config": {"workload": f"batched{n_meshes}: {n_meshes} uniform meshes, points round(10^U(3,6)) (seed 4), "
-                               f"mesh m seeded 40000+m; {T_all} triangles, {int(vtx_off[-1])} vertices in total",
-                   "meshes": n_meshes, "triangles": T_all},
-        "batched": {
-            "one_launch_per_mesh": {"ms": round(loop_ms, 3), "wall_ms": round(loop_wall, 3),
-                                    "triangles_per_s": round(T_all / (loop_ms / 1e3), 1),
-                                    "meshes_per_s": round(n_meshes / (loop_ms / 1e3), 1)},
-            "packed_eager": {"ms": round(eager_ms, 3), "triangles_per_s": round(T_all / (eager_ms / 1e3), 1),
-                             "meshes_per_s": round(n_meshes / (eager_ms / 1e3), 1)},
-            "packed_graph": {"ms": round(graph_ms, 3), "triangles_per_s": round(value, 1),
-                             "meshes_per_s": round(n_meshes / (graph_ms / 1e3), 1)},
-            "speedup_vs_one_launch_per_mesh": round(loop_ms / graph_ms, 3),
-            "tuned": {k: tuned[k] for k in ("walk_blocks", "walk_cap", "source")},
-            "paths": stats,
-            "kernels_us": {k: round(ms / max(nl, 1) * 1e3, 1) for k, (ms, nl) in prof.items()},
-            "outputs_identical": same,
-        },
+    replay = timed(graph.replay, steps)
+    log(f"batched: graph replay {replay}")
+    # every mesh against the oracle, and the per-mesh launches against the batch
+    identical, per_mesh_same = None, None
+    got = batch_digests(meshes, out, labels, batch.he_off_host.numpy())
+    if not args.no_cpu:
+        identical = sum(1 for a, b in zip(got, ref) if a == b)
+    per = []
+    for t_, l_, o_ in zip(tris, labs, outs):
+        off, verts, _ = (x.cpu().numpy() for x in o_.trimmed())
+        per.append(digest(off, verts, l_.he.cpu().numpy()))
+    per_mesh_same = sum(1 for a, b in zip(got, per) if a == b)
+    log(f"batched: oracle-identical meshes {identical}/{n_meshes}, per-mesh launches identical {per_mesh_same}")
+    g_ms = replay["ms_mean"]
+    res = {
+        "workload": f"batched{n_meshes}: {n_meshes} uniform meshes, points round(10^U(3,6)) (seed 4), mesh m seeded "
+                    f"40000+m; {T_all} triangles, {batch.n_vertices} vertices, {batch.n_halfedges} half-edges",
+        "meshes": n_meshes, "triangles": T_all,
+        "one_launch_per_mesh": {**loop, "triangles_per_s": round(T_all / (loop["ms_mean"] / 1e3), 1),
+                                "meshes_per_s": round(n_meshes / (loop["ms_mean"] / 1e3), 1)},
+        "one_call_eager": {**eager, "triangles_per_s": round(T_all / (eager["ms_mean"] / 1e3), 1)},
+        "one_call_graph": {**replay, "triangles_per_s": round(T_all / (g_ms / 1e3), 1),
+                           "meshes_per_s": round(n_meshes / (g_ms / 1e3), 1)},
+        "speedup_vs_one_launch_per_mesh": round(loop["ms_mean"] / g_ms, 3),
+        "tuned": tuned, "paths": stats,
+        "kernels_us": {k: round(ms / max(nl, 1) * 1e3, 1) for k, (ms, nl) in prof.items()},
+        "oracle_identical_meshes": identical, "per_mesh_launch_identical_meshes": per_mesh_same,
     }
-    print(json.dumps(line), flush=True)
+    if not args.no_cpu and oracle_s > 0:
+        res["cpu_pool"] = {"value": round(T_all / (oracle_s / pool._processes), 1), "unit": "triangles/s",
+                           "cores": pool._processes, "kind": "oracle",
+                           "sample": f"every mesh of batched{n_meshes}, one oracle per mesh, "
+                                     f"{pool._processes} processes; value = triangles / (summed oracle seconds "
+                                     f"/ processes)", "oracle_process_seconds": round(oracle_s, 1)}
     del graph
     ctx.close()
+    del batch, labels, out, tris, labs, outs
+    torch.cuda.empty_cache()
+    return res
+
+
+# ---------------------------------------------------------------------------
+# serving
+
+def bench_serve(args, pool, n_requests: int):
+    import numpy as np
+    from meshgen.gen import serve_requests
+    t0 = time.time()
+    base = serve_requests(n_requests, rate=1.0)   # arrival times for rate 1/s; scaled below
+    order = sorted(range(n_requests), key=lambda j: -base[j][1])
+    meshes, ref, oracle_s = generate(
+        pool, _job_request, [(j, base[j][1], base[j][2], base[j][3], not args.no_cpu) for j in order], n_requests)
+    T_all = sum(m.n_tri for m in meshes)
+    log(f"serve: generated {n_requests} requests ({T_all} triangles) in {time.time() - t0:.1f}s "
+        f"(oracle {oracle_s:.1f} process-s)")
+    from paper_2204_05438_amd import serve
+    server = serve.Server(0, slots=args.slots, budget_bytes=64 << 30, max_batch_tri=1 << 24)
+    log(f"serve: {args.slots} slots, 64 GB admission budget, batches of up to 2^24 triangles")
+    pinned = [serve.Request.from_mesh(j, 0.0, meshes[j]) for j in range(n_requests)]
+    del meshes
+
+    def requests(scale):
+        return [serve.Request(j, base[j][0] * scale, p.xy, p.twin, p.origin) for j, p in enumerate(pinned)]
+
+    server.run(requests(0.0)[: min(32, n_requests)])  # warm-up
+    runs = {}
+    cap_reqs = requests(0.0)
+    runs["saturated"] = server.run(cap_reqs)
+    cap = runs["saturated"]["meshes_per_s"]
+    log(f"serve: capacity (all at t=0) {cap} meshes/s, {runs['saturated']['triangles_per_s']:.4g} triangles/s")
+    checked = None
+    if not args.no_cpu:
+        checked = 0
+        for r in cap_reqs:
+            if r.error == 0 and digest(r.offsets, r.verts, np.zeros(0, np.uint8)) == ref[r.rid]:
+                checked += 1
+    for f in (0.5, 0.9):
+        rate = f * cap
+        res = server.run(requests(1.0 / rate))
+        res["rate_meshes_per_s"] = round(rate, 2)
+        runs[f"{f}x"] = res
+        log(f"serve: {f}x capacity ({rate:.1f}/s): p50 {res['latency_ms']['p50']} ms, "
+            f"p99 {res['latency_ms']['p99']} ms, {res['meshes_per_s']} meshes/s")
+    server.close()
+    out = {"workload": f"serve{n_requests}: Poisson arrivals (seed 5), points round(10^U(3, log10 2e6)), uniform "
+                       f"or 4-cluster (sigma 0.05) with probability 1/2, request j seeded 50000+j; {T_all} "
+                       f"triangles; 64 GB admission budget; {args.slots} slots",
+           "requests": n_requests, "triangles": T_all, "runs": runs,
+           "oracle_identical_requests": checked}
+    if not args.no_cpu and oracle_s > 0:
+        out["cpu_pool"] = {"value": round(T_all / (oracle_s / pool._processes), 1), "unit": "triangles/s",
+                           "cores": pool._processes, "kind": "oracle",
+                           "sample": f"every request of serve{n_requests}, one oracle per request, "
+                                     f"{pool._processes} processes", "oracle_process_seconds": round(oracle_s, 1)}
+    return out
 
 
 def main():
@@ -295,8 +515,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="grid10m")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--workload", default="all", help="all | grid10m (or another single mesh) | batchedN | serveN")
+    ap.add_argument("--batched", type=int, default=2000, help="meshes of the batched workload (with --workload all)")
+    ap.add_argument("--serve", type=int, default=2000, help="requests of the serving workload (with --workload all)")
+    ap.add_argument("--batch-steps", type=int, default=3, help="timed repetitions of each batched variant")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle (baseline and identity checks)")
     ap.add_argument("--param", action="append", default=[],
                     help="context parameter NAME=VALUE (walk_cap, walk_blocks)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
@@ -310,128 +533,44 @@ def main():
               "batched and served meshes would shard across GPUs without communication", file=sys.stderr)
         sys.exit(2)
 
-    if args.workload.startswith("serve"):
-        bench_serve(args, int(args.workload[len("serve"):] or 2000))
-        return
-    if args.workload.startswith("batched"):
-        bench_batched(args, int(args.workload[len("batched"):] or 2000))
-        return
-
-    import numpy as np
-    import torch
-    from meshgen.gen import config_mesh
-    from paper_2204_05438_amd import lib
-
-    t0 = time.time()
-    mesh = config_mesh(args.workload)
-    log(f"generated {args.workload}: {mesh.n_vertices} vertices, {mesh.n_tri} triangles in {time.time() - t0:.1f}s")
-
-    dev = torch.device("cuda:0")
-    ctx = lib.Context(0)
-    tri = lib.Tri.from_mesh(mesh, device=dev)
-    labels = lib.Labels.empty(tri)
-    out = lib.Polys.empty(tri, with_start=True)
-    ctx.reserve(tri.n_halfedges, tri.n_vertices)
-    for kv in args.param:
-        name, val = kv.split("=")
-        ctx.set_param({"walk_cap": lib.PARAM_WALK_CAP, "walk_blocks": lib.PARAM_WALK_BLOCKS}[name], int(val))
-    torch.cuda.synchronize()
-    log("inputs resident on the device")
-
-    if args.calib_copy_mb:
-        nb = args.calib_copy_mb << 20
-        src = torch.empty(nb // 4, dtype=torch.int32, device=dev).fill_(1)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        log(f"calibration copy of {args.calib_copy_mb} MiB done")
-
-    for _ in range(args.warmup):
-        ctx.mesh(tri, labels, out)
-    ctx.status()
-    stats = ctx.stats()
-    F, S = (int(x) for x in out.counts.tolist())
-    log(f"warmup done: {stats}, F={F}, S={S}")
-
-    # Timed steps: the library records HIP events around the walk kernel only
-    # (the dominant kernel, whose live duration the roofline uses); events
-    # around every kernel would add their own gaps to the step.
-    stream = torch.cuda.current_stream()
-    ctx.profile(True, walk_only=True)
-    torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
-    for _ in range(args.steps):
-        ctx.mesh(tri, labels, out)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    ms_total = ev0.elapsed_time(ev1)
-    ctx.status()
-    walk_live = ctx.profile_read()
-    ctx.profile(False)
-    ms_step = ms_total / args.steps
-    T = mesh.n_tri
-    value = T / (ms_step / 1e3)
-    log(f"{args.steps} steps: {ms_step:.3f} ms/step, {value:.4g} triangles/s")
-    # per-kernel table from separate, untimed steps with events around every kernel
-    ctx.profile(True)
-    for _ in range(min(args.steps, 5)):
-        ctx.mesh(tri, labels, out)
-    torch.cuda.synchronize()
-    prof = ctx.profile_read()
-    ctx.profile(False)
-    ctx.status()
-    prof.update(walk_live)  # the walk as timed live in the timed steps
-    for k, (ms, nlaunch) in sorted(prof.items(), key=lambda kv: -kv[1][0] / max(kv[1][1], 1)):
-        log(f"  {k:14s} {ms / max(nlaunch, 1) * 1e3:10.1f} us/launch  ({nlaunch} launches)")
-
-    counts = {"V": mesh.n_vertices, "T": T, "R": stats["seeds"], "F": F, "S": S, "Sp": T + 2 * stats["seeds"]}
-    dominant = max(prof.items(), key=lambda kv: kv[1][0] / max(kv[1][1], 1))[0]
-    dom_ms = prof[dominant][0] / prof[dominant][1]
-    dom_bytes = algorithmic_bytes(dominant, counts)
-    achieved = dom_bytes / (dom_ms / 1e3) / 1e9 if dom_bytes else 0.0
-    roofline = {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(dominant, args.workload),
-                "avg_launch_us": round(dom_ms * 1e3, 1), "algorithmic_bytes": dom_bytes}
-    per_kernel = {k: {"us_per_launch": round(ms / n * 1e3, 1),
-                      "algorithmic_GBps": round(algorithmic_bytes(k, counts) / (ms / n / 1e3) / 1e9, 1)}
-                  for k, (ms, n) in prof.items()}
-
-    cpu = None
-    if not args.no_cpu:
-        import oracle
-        log("timing the CPU oracle on the same mesh (1 thread)")
-        c0 = time.perf_counter()
-        ref = oracle.oracle_on(mesh)
-        c1 = time.perf_counter()
-        cpu = {"value": round(T / (c1 - c0), 1), "unit": "triangles/s", "cores": 1, "kind": "oracle",
-               "sample": f"the full {args.workload} mesh ({T} triangles), one run, label+build+repair",
-               "seconds": round(c1 - c0, 2)}
-        # the timed GPU output is the oracle's output
-        off, verts, _ = (x.cpu().numpy() for x in out.trimmed())
-        cpu["gpu_output_identical"] = bool(np.array_equal(off, ref["offsets"]) and
-                                           np.array_equal(verts, ref["verts"]))
-        log(f"oracle: {c1 - c0:.1f}s, identical output: {cpu['gpu_output_identical']}")
-
-    line = {
-        "metric": METRIC, "value": round(value, 1), "unit": "triangles/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64+i32",
-        "data": "synthetic",
-        "config": {"workload": f"{args.workload}: jittered 3163x3163 grid in [0,1]^2 (seed 3), Delaunay, "
-                               f"{mesh.n_vertices} vertices, {T} triangles, one mesh per step",
-                   "polygons": F, "seeds": stats["seeds"], "general_small": stats["general_small"],
-                   "general_big": stats["general_big"],
-                   "tips": stats["tips"], "splits": stats["splits"]},
-        "roofline": roofline,
-        "kernels": per_kernel,
-        "cpu_baseline": cpu,
-    }
+    # the host pool is forked before anything touches the GPU
+    from multiprocessing import get_context
+    try:
+        ncpu = len(os.sched_getaffinity(0))
+    except AttributeError:
+        ncpu = os.cpu_count() or 1
+    pool = get_context("fork").Pool(max(1, min(POOL_MAX, ncpu)))
+    t_start = time.time()
+    wl = args.workload
+    line = {"metric": METRIC, "unit": "triangles/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64+i32",
+            "data": "synthetic"}
+    try:
+        if wl == "all" or not (wl.startswith("batched") or wl.startswith("serve")):
+            single = bench_single(args, pool, "grid10m" if wl == "all" else wl)
+            line.update(value=single["value"], ms_per_step=single["ms_per_step"], config=single["config"],
+                        steps_ms=single["steps_ms"], roofline=single["roofline"], kernels=single["kernels"],
+                        cpu_baseline=single["cpu_baseline"], oracle_identical=single["oracle_identical"])
+        if wl == "all" or wl.startswith("batched"):
+            nb = args.batched if wl == "all" else int(wl[len("batched"):] or 2000)
+            b = bench_batched(args, pool, nb)
+            line["batched"] = b
+            if wl != "all":
+                line.update(metric="triangles/sec (label+build+repair), batched meshes in one graph-replayed call",
+                            value=b["one_call_graph"]["triangles_per_s"], ms_per_step=b["one_call_graph"]["ms_mean"],
+                            config={"workload": b["workload"]}, steps=args.batch_steps, warmup=1)
+        if wl == "all" or wl.startswith("serve"):
+            ns = args.serve if wl == "all" else int(wl[len("serve"):] or 2000)
+            sv = bench_serve(args, pool, ns)
+            line["serving"] = sv
+            if wl != "all":
+                line.update(metric="served meshes: triangles/sec and p50/p99 latency at 0.9x capacity",
+                            value=sv["runs"]["0.9x"]["triangles_per_s"], ms_per_step=None,
+                            config={"workload": sv["workload"]}, steps=ns, warmup=32)
+    finally:
+        pool.terminate()
+    line["bench_wall_s"] = round(time.time() - t_start, 1)
     print(json.dumps(line), flush=True)
-    ctx.close()
 
 
 if __name__ == "__main__":

@@ -125,6 +125,10 @@ int polylla_ctx_create(polylla_ctx **out, int device);
 void polylla_ctx_destroy(polylla_ctx *ctx);
 /* Pre-allocate scratch for meshes up to n_halfedges / n_vertices (optional). */
 int polylla_reserve(polylla_ctx *ctx, int64_t n_halfedges, int64_t n_vertices);
+/* Pre-allocate scratch for batches (polylla_mesh_batched) of up to
+ * n_halfedges and n_vertices in total and n_meshes meshes (optional: a
+ * batched call grows the scratch to its own size). */
+int polylla_reserve_batch(polylla_ctx *ctx, int64_t n_halfedges, int64_t n_vertices, int64_t n_meshes);
 
 /* Label phase (Algorithm 2: LabelMax, LabelSeed, LabelFrontier): writes
  * LONGEST, FRONTIER, TERMINAL, BORDER for every half-edge, SEED for every
@@ -149,29 +153,60 @@ int polylla_repair(polylla_ctx *ctx, const polylla_tri *tri, polylla_labels *lab
 int polylla_mesh(polylla_ctx *ctx, const polylla_tri *tri, polylla_labels *labels,
                  polylla_polys *out, hipStream_t stream);
 
-/* Many triangulations in one call (packed CSR of meshes). The meshes are
- * stored one after another in the arrays of `tri`, with GLOBAL indices: mesh m
- * owns vertices [vtx_off[m], vtx_off[m+1]) and half-edges [he_off[m],
- * he_off[m+1]) (multiples of 3, increasing), and its twin and origin entries
- * point into its own ranges, so no edge joins two meshes. Since terminal-edge
- * regions never cross a mesh boundary, the whole batch runs as one launch
- * sequence over the union. Output polygons carry global vertex ids, meshes in
- * order; poly_off (device int64 [n_meshes + 1]) receives the first polygon of
- * every mesh and F at the end. vtx_off is a device int64 [n_meshes + 1] array.
- * Same results as n_meshes calls of polylla_mesh (up to the index offsets). */
-int polylla_mesh_batched(polylla_ctx *ctx, const polylla_tri *tri, int64_t n_meshes, const int64_t *vtx_off,
-                         polylla_labels *labels, polylla_polys *out, int64_t *poly_off, hipStream_t stream);
+/* A batch of independent triangulations stored one after another (CSR of
+ * meshes, each mesh in the layout of polylla_tri). Mesh m owns vertices
+ * [vtx_off[m], vtx_off[m+1]) of xy and half-edges [he_off[m], he_off[m+1])
+ * of twin and origin, and its twin and origin entries are LOCAL to the mesh:
+ * vertex ids count from the mesh's first vertex, half-edge ids (and twin)
+ * from its first half-edge. The offsets are int64, so a batch may hold more
+ * than 2^31 half-edges in total; each mesh holds fewer than 2^31 - 64
+ * half-edges (a multiple of 3) and fewer than 2^31 vertices. The offsets are
+ * given twice: on the device (read by the kernels) and on the host (the
+ * library splits the batch into launches from them, so a captured HIP graph
+ * replays the same launches); both copies must hold the same values. */
+typedef struct {
+  int64_t n_meshes;
+  const int64_t *vtx_off;       /* device [n_meshes + 1], vtx_off[0] == 0, non-decreasing */
+  const int64_t *he_off;        /* device [n_meshes + 1], he_off[0] == 0, non-decreasing, multiples of 3 */
+  const int64_t *vtx_off_host;  /* host copy of vtx_off */
+  const int64_t *he_off_host;   /* host copy of he_off */
+  const double *xy;             /* device [2 * vtx_off[n_meshes]] */
+  const int32_t *twin;          /* device [he_off[n_meshes]], local, -1 on the boundary */
+  const int32_t *origin;        /* device [he_off[n_meshes]], local */
+} polylla_batch;
 
-/* Packing helper for polylla_mesh_batched (not a step of the method): turns
- * meshes copied one after another with LOCAL indices into the global
- * indexing of a packed batch, in place on `stream`. For every half-edge h of
- * mesh m (he_off[m] <= h < he_off[m+1]): origin[h] += vtx_off[m], and
- * twin[h] += he_off[m] unless it is -1. he_off and vtx_off are device int64
- * arrays of n_meshes + 1 increasing entries (he_off[n_meshes] = half-edges in
- * total, each mesh a multiple of 3). Returns EINVAL on null or negative
- * arguments; the offsets themselves are trusted. */
-int polylla_rebase(int32_t *twin, int32_t *origin, int64_t n_meshes, const int64_t *he_off,
-                   const int64_t *vtx_off, hipStream_t stream);
+/* Polygons of a batch: one CSR over all meshes, meshes in order, each mesh's
+ * polygons as polylla_mesh gives them for that mesh alone. Offsets are int64;
+ * vertex ids (verts) and half-edge ids (start) are LOCAL to the polygon's
+ * mesh. poly_off[m] is the first polygon of mesh m and poly_off[n_meshes] = F
+ * (all -1 when the output capacity was too small). cap_polys >= total
+ * triangles and cap_verts >= 3 * total triangles are always enough. */
+typedef struct {
+  int64_t *offsets;   /* device [cap_polys + 1] */
+  int32_t *verts;     /* device [cap_verts] */
+  int32_t *start;     /* device [cap_polys], may be NULL */
+  int64_t *poly_off;  /* device [n_meshes + 1] */
+  int64_t *counts;    /* device [2]: F, sum of lengths */
+  int64_t cap_polys;
+  int64_t cap_verts;
+} polylla_batch_out;
+
+/* Algorithm 1 on every mesh of a batch in one call on one stream. Terminal-
+ * edge regions never cross a mesh boundary, so the library runs the label,
+ * traversal and repair kernels once over a group of consecutive meshes at a
+ * time (as many as keep its int32 scratch indices in range, by default up to
+ * 2^30 - 2^24 half-edges; POLYLLA_PARAM_BATCH_GROUP_HE lowers it): the
+ * group's twin and origin are first rewritten into scratch with indices over
+ * the group, and its polygons are written into `out` with the mesh-local ids
+ * restored. `labels` (NULL allowed) holds the label arrays of the whole
+ * batch (he [he_off[n]], tri [he_off[n] / 3], vtx [vtx_off[n]]). The same
+ * results as n_meshes calls of polylla_mesh, up to the offsets of the CSR.
+ * Scratch grows on the first call at a given size; a call of the same size
+ * can then be captured in a HIP graph. Host-side errors: EINVAL (null
+ * pointers, offsets not increasing, a mesh too large), ELAYOUT (a mesh's
+ * half-edges not a multiple of 3); device-side ones as for polylla_mesh. */
+int polylla_mesh_batched(polylla_ctx *ctx, const polylla_batch *batch, polylla_labels *labels,
+                         polylla_batch_out *out, hipStream_t stream);
 
 /* Full input check on the device (layout of next, index ranges, twin
  * involution and endpoints). Waits for the stream; returns the first error. */
@@ -218,6 +253,11 @@ int polylla_stats(polylla_ctx *ctx, int64_t *out, int n);
  * holds min(triangles of the mesh, 65536) triangles per workgroup (8
  * workgroups, about 260 bytes per triangle of capacity). */
 #define POLYLLA_PARAM_REGION_MEM_MAX 5
+/* POLYLLA_PARAM_BATCH_GROUP_HE (3..2^30 - 2^24, default 2^30 - 2^24): the
+ * most half-edges polylla_mesh_batched runs in one group of consecutive
+ * meshes (a larger mesh forms a group of its own). Lower values split a
+ * batch into more groups (used by tests). */
+#define POLYLLA_PARAM_BATCH_GROUP_HE 6
 int polylla_set_param(polylla_ctx *ctx, int param, int64_t value);
 
 /* Per-kernel GPU timing with HIP events, for benchmarks (off by default).

@@ -10,7 +10,8 @@
 
 namespace polylla {
 
-__global__ void k_reset(Counters*, uint64_t*, int64_t, const int64_t*);
+__global__ void k_reset(Counters*, uint64_t*, int64_t, const int64_t*, int);
+__global__ void k_accumulate(Counters*);
 __global__ void k_longest(int64_t, int64_t, const double*, const int32_t*, const int32_t*, uint8_t*, uint8_t*,
                           Counters*);
 template <bool COMPUTE>
@@ -41,9 +42,17 @@ __global__ void k_general_huge(const int32_t*, bool, int32_t, int64_t, const int
 __global__ void k_scan_emit(PolyState, uint64_t*, const int32_t*, const int32_t*, int32_t*, int32_t*, int32_t*,
                             int64_t*, int64_t, int64_t, Counters*);
 __global__ void k_validate(int64_t, int64_t, const int32_t*, const int32_t*, const int32_t*, Counters*);
-__global__ void k_rebase(int32_t*, int32_t*, int64_t, const int64_t*, const int64_t*);
 __global__ void k_batch_offsets(int64_t, const int64_t*, const int32_t*, const int32_t*, const int64_t*, int64_t,
                                 int64_t, int64_t*);
+__global__ void k_group_rebase(const int32_t*, const int32_t*, int32_t*, int32_t*, int64_t, const int64_t*,
+                               const int64_t*);
+__global__ void k_batch_begin(int64_t*);
+__global__ void k_group_finish(int64_t, const int64_t*, const int64_t*, const int32_t*, const int32_t*,
+                               const int32_t*, const int64_t*, const int64_t*, const int64_t*, int64_t*, int32_t*,
+                               int32_t*, int64_t*, int64_t, int64_t, int64_t, Counters*);
+__global__ void k_group_advance(const int64_t*, int64_t*, bool, int64_t, int64_t*, int64_t*, int64_t*, int64_t,
+                                int64_t, const Counters*);
+__global__ void k_batch_close(const int64_t*, int64_t, int64_t*);
 
 }  // namespace polylla
 
@@ -51,6 +60,9 @@ using namespace polylla;
 
 // default number of declined short polygons up to which each gets a wave
 constexpr uint32_t kGenWaveMax = 2 * polylla::kBigGrid64;
+// most half-edges of one group of a batched call: keeps every int32 offset of
+// the scratch arrays (arena 6T, staging 5T plus chunk tails) below 2^31
+constexpr int64_t kGroupHeMax = ((int64_t)1 << 30) - ((int64_t)1 << 24);
 
 struct polylla_ctx {
   int device = 0;
@@ -80,6 +92,20 @@ struct polylla_ctx {
   uint8_t* tri_s = nullptr;
   uint8_t* vtx_s = nullptr;
   Counters last{};
+  bool last_batched = false;  // polylla_stats reports the sums over the groups of the last batched call
+  // batched calls: a group's twin and origin with indices over the group, its
+  // polygons in int32 CSR, the first polygon of each of its meshes, running
+  // totals {polygons, vertices, capacity failure}
+  int32_t* g_twin = nullptr;
+  int32_t* g_origin = nullptr;
+  int32_t* g_off = nullptr;
+  int32_t* g_verts = nullptr;
+  int32_t* g_start = nullptr;
+  int64_t* g_counts = nullptr;
+  int64_t* g_poly = nullptr;
+  int64_t* g_base = nullptr;
+  int64_t g_cap_he = 0, g_cap_m = 0;
+  int64_t group_he = kGroupHeMax;
   int walk_cap = 24;  // vertices a lane walks before handing a polygon to a workgroup
   uint32_t gen_wave_max = kGenWaveMax;  // declined short polygons up to which each gets a wave
   int32_t lds_max = 4096;               // region size limit of the 1024-thread LDS workgroup
@@ -179,6 +205,38 @@ void free_scratch(polylla_ctx* c) {
   c->cap_t = c->cap_v = 0;
 }
 
+void free_group(polylla_ctx* c) {
+  dfree(&c->g_twin);
+  dfree(&c->g_origin);
+  dfree(&c->g_off);
+  dfree(&c->g_verts);
+  dfree(&c->g_start);
+  dfree(&c->g_counts);
+  dfree(&c->g_poly);
+  dfree(&c->g_base);
+  c->g_cap_he = c->g_cap_m = 0;
+}
+
+// Scratch of batched calls for groups of up to n_he half-edges and n_m meshes.
+int ensure_group(polylla_ctx* c, int64_t n_he, int64_t n_m) {
+  if (n_he <= c->g_cap_he && n_m <= c->g_cap_m && c->g_base) return POLYLLA_OK;
+  const int64_t H = std::max({n_he, c->g_cap_he, (int64_t)3072}), M = std::max({n_m, c->g_cap_m, (int64_t)64});
+  if (hipSetDevice(c->device) != hipSuccess) return POLYLLA_EHIP;
+  (void)hipDeviceSynchronize();
+  free_group(c);
+  const int64_t T = H / 3;
+  int rc = POLYLLA_OK;
+  if ((rc = dalloc(&c->g_twin, H)) || (rc = dalloc(&c->g_origin, H)) || (rc = dalloc(&c->g_off, T + 1)) ||
+      (rc = dalloc(&c->g_verts, 3 * T)) || (rc = dalloc(&c->g_start, T)) || (rc = dalloc(&c->g_counts, 2)) ||
+      (rc = dalloc(&c->g_poly, M + 1)) || (rc = dalloc(&c->g_base, 4))) {
+    free_group(c);
+    return rc;
+  }
+  c->g_cap_he = H;
+  c->g_cap_m = M;
+  return POLYLLA_OK;
+}
+
 int ensure(polylla_ctx* c, int64_t nt, int64_t nv) {
   if (nt <= c->cap_t && nv <= c->cap_v && c->lg) return POLYLLA_OK;
   int64_t T = std::max(nt, c->cap_t), V = std::max(nv, c->cap_v);
@@ -193,7 +251,7 @@ int ensure(polylla_ctx* c, int64_t nt, int64_t nv) {
   // tail of the last staging chunk of every walk wave. Offsets stay int32.
   c->stage_cap = std::min<int64_t>(5 * T + kWalkWaves * kStageChunkHost + kBigStageTails + ((int64_t)1 << 20),
                                    ((int64_t)1 << 31) - 1);
-  c->arena_cap = 6 * T + kBigArenaTails + 4096;
+  c->arena_cap = std::min<int64_t>(6 * T + kBigArenaTails + 4096, ((int64_t)1 << 31) - 1);  // offsets stay int32
   c->n_status = 2 * ntiles;
   if ((rc = dalloc(&c->lg, T)) || (rc = dalloc(&c->wk, 3 * T)) || (rc = dalloc(&c->seeds, T)) || (rc = dalloc(&c->deferred, T)) || (rc = dalloc(&c->huge, c->huge_cap = 3 * T / 32 + 64)) ||
       (rc = dalloc(&c->lane, c->lane_cap = 3 * T / 32 + 64)) ||
@@ -242,10 +300,10 @@ int grid_for(int64_t n, int64_t per_block, int64_t cap) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(g, cap));
 }
 
-void reset(polylla_ctx* c, hipStream_t s, const int64_t* n_from) {
+void reset(polylla_ctx* c, hipStream_t s, const int64_t* n_from, int keep = 0) {
   Prof p(c, s, KR_RESET);
   hipLaunchKernelGGL(k_reset, dim3(grid_for(c->n_status, 256, 4096)), dim3(256), 0, s, c->cnt, c->status,
-                     c->n_status, n_from);
+                     c->n_status, n_from, keep);
 }
 
 // Seed counts per label tile (first ntiles words of the status array) and
@@ -407,6 +465,19 @@ int run_build(polylla_ctx* c, const polylla_tri* t, const int32_t* list, bool fr
   return launched();
 }
 
+// Label, build and repair of one mesh (label arrays NULL: context scratch);
+// keep != 0 keeps the error word and batch sums of earlier groups.
+int mesh_run(polylla_ctx* c, const polylla_tri* t, uint8_t* he, uint8_t* tri, uint8_t* vtx, polylla_polys* out,
+             hipStream_t s, int keep) {
+  he = he ? he : c->he_s;
+  tri = tri ? tri : c->tri_s;
+  vtx = vtx ? vtx : c->vtx_s;
+  reset(c, s, nullptr, keep);
+  int rc = run_label(c, t, he, tri, vtx, s);
+  if (rc) return rc;
+  return run_build(c, t, c->seeds, true, true, he, vtx, out, s);
+}
+
 }  // namespace
 
 extern "C" {
@@ -443,6 +514,7 @@ void polylla_ctx_destroy(polylla_ctx* c) {
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
   free_scratch(c);
+  free_group(c);
   dfree(&c->cnt);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   (void)hipEventDestroy(c->join);
@@ -454,6 +526,16 @@ void polylla_ctx_destroy(polylla_ctx* c) {
 int polylla_reserve(polylla_ctx* c, int64_t n_halfedges, int64_t n_vertices) {
   if (!c || n_halfedges < 0 || n_vertices < 0) return POLYLLA_EINVAL;
   return ensure(c, n_halfedges / 3, n_vertices);
+}
+
+int polylla_reserve_batch(polylla_ctx* c, int64_t n_halfedges, int64_t n_vertices, int64_t n_meshes) {
+  if (!c || n_halfedges < 0 || n_vertices < 0 || n_meshes < 0) return POLYLLA_EINVAL;
+  // the largest group a batch of this size forms (unless one mesh alone is larger)
+  const int64_t H = std::min(n_halfedges, c->group_he);
+  const int64_t V = std::min<int64_t>(n_vertices, ((int64_t)1 << 31) - 1);
+  int rc = ensure(c, H / 3, V);
+  if (rc) return rc;
+  return ensure_group(c, H, std::max<int64_t>(n_meshes, 1));
 }
 
 int polylla_label(polylla_ctx* c, const polylla_tri* t, polylla_labels* l, hipStream_t s) {
@@ -519,32 +601,91 @@ int polylla_mesh(polylla_ctx* c, const polylla_tri* t, polylla_labels* l, polyll
   const int64_t T = t->n_halfedges / 3;
   if ((rc = ensure(c, T, t->n_vertices))) return rc;
   if (hipSetDevice(c->device) != hipSuccess) return POLYLLA_EHIP;
-  uint8_t* he = (l && l->he) ? l->he : c->he_s;
-  uint8_t* tri = (l && l->tri) ? l->tri : c->tri_s;
-  uint8_t* vtx = (l && l->vtx) ? l->vtx : c->vtx_s;
-  reset(c, s, nullptr);
-  if ((rc = run_label(c, t, he, tri, vtx, s))) return rc;
-  return run_build(c, t, c->seeds, true, true, he, vtx, out, s);
+  c->last_batched = false;
+  return mesh_run(c, t, l ? l->he : nullptr, l ? l->tri : nullptr, l ? l->vtx : nullptr, out, s, 0);
 }
 
-int polylla_mesh_batched(polylla_ctx* c, const polylla_tri* t, int64_t n_meshes, const int64_t* vtx_off,
-                         polylla_labels* l, polylla_polys* out, int64_t* poly_off, hipStream_t s) {
-  if (!c || n_meshes < 0 || (n_meshes > 0 && (!vtx_off || !poly_off))) return POLYLLA_EINVAL;
-  int rc = polylla_mesh(c, t, l, out, s);
-  if (rc) return rc;
-  if (n_meshes >= 0 && poly_off) {
-    Prof p(c, s, KR_BATCH);
-    hipLaunchKernelGGL(k_batch_offsets, dim3(grid_for(n_meshes + 1, 256, 4096)), dim3(256), 0, s, n_meshes,
-                       vtx_off, out->offsets, out->verts, out->counts, out->cap_polys, out->cap_verts, poly_off);
+int polylla_mesh_batched(polylla_ctx* c, const polylla_batch* b, polylla_labels* l, polylla_batch_out* out,
+                         hipStream_t s) {
+  if (!c || !b || !out || b->n_meshes < 0) return POLYLLA_EINVAL;
+  const int64_t n = b->n_meshes;
+  if (!b->vtx_off || !b->he_off || !b->vtx_off_host || !b->he_off_host || !out->offsets || !out->poly_off ||
+      !out->counts || out->cap_polys < 0 || out->cap_verts < 0 || (out->cap_verts > 0 && !out->verts))
+    return POLYLLA_EINVAL;
+  const int64_t* ho = b->he_off_host;
+  const int64_t* vo = b->vtx_off_host;
+  if (ho[0] != 0 || vo[0] != 0) return POLYLLA_EINVAL;
+  for (int64_t m = 0; m < n; ++m) {
+    const int64_t dh = ho[m + 1] - ho[m], dv = vo[m + 1] - vo[m];
+    if (dh < 0 || dv < 0) return POLYLLA_EINVAL;
+    if (dh % 3) return POLYLLA_ELAYOUT;
+    if (dh >= ((int64_t)1 << 31) - 64 || dv >= ((int64_t)1 << 31)) return POLYLLA_EINVAL;
   }
-  return launched();
-}
-
-int polylla_rebase(int32_t* twin, int32_t* origin, int64_t n_meshes, const int64_t* he_off, const int64_t* vtx_off,
-                   hipStream_t s) {
-  if (n_meshes < 0 || (n_meshes > 0 && (!twin || !origin || !he_off || !vtx_off))) return POLYLLA_EINVAL;
-  if (n_meshes == 0) return POLYLLA_OK;
-  hipLaunchKernelGGL(k_rebase, dim3(4096), dim3(256), 0, s, twin, origin, n_meshes, he_off, vtx_off);
+  if (ho[n] > 0 && (!b->xy || !b->twin || !b->origin)) return POLYLLA_EINVAL;
+  // groups of consecutive meshes [first[k], first[k + 1]) of at most group_he
+  // half-edges (a larger mesh alone) and fewer than 2^31 vertices
+  std::vector<int64_t> first;
+  int64_t max_he = 0, max_v = 0, max_m = 1;
+  for (int64_t m = 0; m < n;) {
+    first.push_back(m);
+    int64_t e = m + 1;
+    while (e < n && ho[e + 1] - ho[m] <= c->group_he && vo[e + 1] - vo[m] < ((int64_t)1 << 31)) ++e;
+    max_he = std::max(max_he, ho[e] - ho[m]);
+    max_v = std::max(max_v, vo[e] - vo[m]);
+    max_m = std::max(max_m, e - m);
+    m = e;
+  }
+  first.push_back(n);
+  int rc = ensure(c, max_he / 3, max_v);
+  if (rc) return rc;
+  if ((rc = ensure_group(c, max_he, max_m))) return rc;
+  if (hipSetDevice(c->device) != hipSuccess) return POLYLLA_EHIP;
+  c->last_batched = true;
+  {
+    Prof p(c, s, KR_BATCH);
+    hipLaunchKernelGGL(k_batch_begin, dim3(1), dim3(64), 0, s, c->g_base);
+  }
+  const size_t ng = first.size() - 1;
+  if (ng == 0) {  // no meshes: F = 0, offsets[0] = 0, poly_off[0] = 0
+    reset(c, s, nullptr);
+    hipLaunchKernelGGL(k_group_advance, dim3(1), dim3(64), 0, s, (const int64_t*)c->g_base + 3, c->g_base, true, n,
+                       out->offsets, out->poly_off, out->counts, out->cap_polys, out->cap_verts,
+                       (const Counters*)c->cnt);
+    return launched();
+  }
+  for (size_t k = 0; k < ng; ++k) {
+    const int64_t m0 = first[k], m1 = first[k + 1], nm = m1 - m0;
+    const int64_t h0 = ho[m0], H = ho[m1] - h0, v0 = vo[m0], V = vo[m1] - v0;
+    if (H > 0) {
+      Prof p(c, s, KR_BATCH);
+      hipLaunchKernelGGL(k_group_rebase, dim3(grid_for(H, 256, 1 << 16)), dim3(256), 0, s, b->twin, b->origin,
+                         c->g_twin, c->g_origin, nm, b->he_off + m0, b->vtx_off + m0);
+    }
+    polylla_tri tg{V, H, b->xy + 2 * v0, c->g_twin, nullptr, c->g_origin};
+    polylla_polys pg{c->g_off, c->g_verts, c->g_start, c->g_counts, H / 3, H};
+    uint8_t* he = (l && l->he) ? l->he + h0 : nullptr;
+    uint8_t* tri = (l && l->tri) ? l->tri + h0 / 3 : nullptr;
+    uint8_t* vtx = (l && l->vtx) ? l->vtx + v0 : nullptr;
+    if ((rc = mesh_run(c, &tg, he, tri, vtx, &pg, s, k > 0 ? 1 : 0))) return rc;
+    {
+      Prof p(c, s, KR_BATCH);
+      hipLaunchKernelGGL(k_accumulate, dim3(1), dim3(64), 0, s, c->cnt);
+      hipLaunchKernelGGL(k_batch_offsets, dim3(grid_for(nm + 1, 256, 4096)), dim3(256), 0, s, nm, b->vtx_off + m0,
+                         c->g_off, c->g_verts, c->g_counts, pg.cap_polys, pg.cap_verts, c->g_poly);
+      hipLaunchKernelGGL(k_group_finish, dim3(grid_for(std::max(H / 3, nm), 256, 1 << 16)), dim3(256), 0, s, nm,
+                         b->he_off + m0, b->vtx_off + m0, c->g_off, c->g_verts, c->g_start, c->g_counts, c->g_poly,
+                         c->g_base, out->offsets, out->verts, out->start, out->poly_off + m0, pg.cap_polys,
+                         out->cap_polys, out->cap_verts, c->cnt);
+      hipLaunchKernelGGL(k_group_advance, dim3(1), dim3(64), 0, s, c->g_counts, c->g_base, k + 1 == ng, n,
+                         out->offsets, out->poly_off, out->counts, out->cap_polys, out->cap_verts,
+                         (const Counters*)c->cnt);
+    }
+  }
+  {
+    Prof p(c, s, KR_BATCH);
+    hipLaunchKernelGGL(k_batch_close, dim3(grid_for(n + 1, 256, 4096)), dim3(256), 0, s, c->g_base, n,
+                       out->poly_off);
+  }
   return launched();
 }
 
@@ -555,7 +696,7 @@ int polylla_validate(polylla_ctx* c, const polylla_tri* t, hipStream_t s) {
   if (t->n_halfedges > 0 && !t->next) return POLYLLA_EINVAL;
   if (hipSetDevice(c->device) != hipSuccess) return POLYLLA_EHIP;
   hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, c->cnt, (uint64_t*)nullptr, (int64_t)0,
-                     (const int64_t*)nullptr);
+                     (const int64_t*)nullptr, 0);
   Prof pv(c, s, KR_VALIDATE);
   hipLaunchKernelGGL(k_validate, dim3(grid_for(t->n_halfedges, 256, 1 << 16)), dim3(256), 0, s, t->n_halfedges,
                      t->n_vertices, t->twin, t->next, t->origin, c->cnt);
@@ -579,8 +720,10 @@ int polylla_status(polylla_ctx* c, hipStream_t s) {
 
 int polylla_stats(polylla_ctx* c, int64_t* out, int n) {
   if (!c || !out || n < 0) return POLYLLA_EINVAL;
-  const int64_t v[7] = {c->last.n_seeds,  c->last.n_deferred, c->last.n_tips, c->last.n_splits,
-                        c->last.n_big,    c->last.n_fallback, c->last.n_lane};
+  int64_t v[7] = {c->last.n_seeds, c->last.n_deferred, c->last.n_tips, c->last.n_splits,
+                  c->last.n_big,   c->last.n_fallback, c->last.n_lane};
+  if (c->last_batched)
+    for (int i = 0; i < 7; ++i) v[i] = (int64_t)c->last.acc[i];
   int k = std::min(n, 7);
   for (int i = 0; i < k; ++i) out[i] = v[i];
   return k;
@@ -608,6 +751,10 @@ int polylla_set_param(polylla_ctx* c, int param, int64_t value) {
     case POLYLLA_PARAM_REGION_MEM_MAX:
       if (value < 32 || value > kMemRegionMax) return POLYLLA_EINVAL;
       c->mem_max = (int32_t)value;
+      return POLYLLA_OK;
+    case POLYLLA_PARAM_BATCH_GROUP_HE:
+      if (value < 3 || value > kGroupHeMax) return POLYLLA_EINVAL;
+      c->group_he = value;
       return POLYLLA_OK;
     default:
       return POLYLLA_EINVAL;

@@ -2800,30 +2800,125 @@ __global__ __launch_bounds__(256) void k_scan_emit(PolyState ps, uint64_t* statu
   }
 }
 
-// Packing helper: local indices of meshes copied one after another become
-// the global indices of the packed batch (mesh of a half-edge by binary
-// search over he_off).
-__global__ __launch_bounds__(256) void k_rebase(int32_t* __restrict__ twin, int32_t* __restrict__ origin,
-                                                int64_t n_meshes, const int64_t* __restrict__ he_off,
-                                                const int64_t* __restrict__ vtx_off) {
-  const int64_t H = he_off[n_meshes];
-  for (int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; h < H; h += (int64_t)gridDim.x * blockDim.x) {
-    int64_t lo = 0, hi = n_meshes;  // last mesh with he_off <= h
-    while (hi - lo > 1) {
-      const int64_t mid = (lo + hi) >> 1;
-      if (he_off[mid] <= h) lo = mid;
-      else hi = mid;
-    }
-    origin[h] += (int32_t)vtx_off[lo];
-    const int32_t tw = twin[h];
-    if (tw != -1) twin[h] = tw + (int32_t)he_off[lo];
+// ---------------------------------------------------------------------------
+// Batches (CSR of meshes with mesh-local indices). A group of consecutive
+// meshes runs through the single-mesh kernels with indices over the group:
+// k_group_rebase writes the group's twin and origin into scratch, the
+// group's polygons come out in scratch CSR, and k_group_finish writes them
+// into the caller's int64 CSR with the mesh-local ids restored.
+
+// Mesh of position x: the last m in [0, n) with off[m] <= x (off[0] <= x).
+__device__ __forceinline__ int64_t mesh_of(const int64_t* __restrict__ off, int64_t n, int64_t x) {
+  int64_t lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (off[mid] <= x) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Group indices of the meshes [0, nm) of he_off / vtx_off (pointers at the
+// group's first mesh). Local indices out of their mesh's range become
+// out-of-range group indices, which the label kernels report as ETOPO
+// (instead of silently naming a half-edge or vertex of a neighbouring mesh).
+__global__ __launch_bounds__(256) void k_group_rebase(const int32_t* __restrict__ twin,
+                                                      const int32_t* __restrict__ origin,
+                                                      int32_t* __restrict__ tw_g, int32_t* __restrict__ or_g,
+                                                      int64_t nm, const int64_t* __restrict__ he_off,
+                                                      const int64_t* __restrict__ vtx_off) {
+  const int64_t h0 = he_off[0], v0 = vtx_off[0];
+  const int64_t H = he_off[nm] - h0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (h >= H) return;
+  int64_t m = mesh_of(he_off, nm, h0 + h);
+  for (; h < H; h += stride) {
+    while (m + 1 < nm && he_off[m + 1] <= h0 + h) ++m;  // meshes ahead of the last one (usually none)
+    const int64_t hb = he_off[m] - h0, hn = he_off[m + 1] - he_off[m];
+    const int64_t vb = vtx_off[m] - v0, vn = vtx_off[m + 1] - vtx_off[m];
+    const int32_t tw = twin[h0 + h], og = origin[h0 + h];
+    tw_g[h] = tw == -1 ? -1 : ((tw >= 0 && tw < hn) ? (int32_t)(tw + hb) : INT32_MIN);
+    or_g[h] = (og >= 0 && og < vn) ? (int32_t)(og + vb) : -1;
   }
 }
 
-// First output polygon of every mesh of a batch: polygons come in mesh order
+// base: {polygons, vertices} written by earlier groups, then a capacity
+// failure flag. Cleared by k_batch_begin at the start of a call.
+__global__ void k_batch_begin(int64_t* __restrict__ base) {
+  if (threadIdx.x < 4) base[threadIdx.x] = 0;
+}
+
+// One thread per polygon of the group: the caller's CSR entries at the
+// running offsets, vertex and half-edge ids made local to the polygon's mesh
+// (found by binary search over the group's first-polygon offsets), and the
+// first polygon of every mesh of the group.
+__global__ __launch_bounds__(256) void k_group_finish(
+    int64_t nm, const int64_t* __restrict__ he_off, const int64_t* __restrict__ vtx_off,
+    const int32_t* __restrict__ off_g, const int32_t* __restrict__ verts_g, const int32_t* __restrict__ start_g,
+    const int64_t* __restrict__ counts_g, const int64_t* __restrict__ poly_g, const int64_t* __restrict__ base,
+    int64_t* __restrict__ offsets, int32_t* __restrict__ verts, int32_t* __restrict__ start,
+    int64_t* __restrict__ poly_off, int64_t g_cap_polys, int64_t cap_polys, int64_t cap_verts, Counters* cnt) {
+  const int64_t F = counts_g[0], S = counts_g[1];
+  const int64_t P0 = base[0], S0 = base[1];
+  // nothing is written after an error in this or an earlier group (the
+  // group's CSR may then be incomplete) or a capacity failure
+  if (cnt->error || base[2] || F < 0 || F > g_cap_polys || S < 0 || S > 3 * g_cap_polys || poly_g[0] < 0) return;
+  if (P0 + F > cap_polys || S0 + S > cap_verts) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) set_error(cnt, POLYLLA_ECAPACITY);
+    return;
+  }
+  const int64_t h0 = he_off[0], v0 = vtx_off[0];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < nm; m += stride) poly_off[m] = P0 + poly_g[m];
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= F) return;
+  int64_t m = mesh_of(poly_g, nm, p);
+  for (; p < F; p += stride) {
+    while (m + 1 < nm && poly_g[m + 1] <= p) ++m;
+    const int32_t vb = (int32_t)(vtx_off[m] - v0), hb = (int32_t)(he_off[m] - h0);
+    const int32_t a = off_g[p], b = off_g[p + 1];
+    offsets[P0 + p] = S0 + a;
+    if (start) start[P0 + p] = start_g[p] - hb;
+    for (int32_t k = a; k < b; ++k) verts[S0 + k] = verts_g[k] - vb;
+  }
+}
+
+// After a group: running totals; after the last group, the closing offset,
+// the counts and the end of poly_off.
+__global__ void k_group_advance(const int64_t* __restrict__ counts_g, int64_t* __restrict__ base, bool last,
+                                int64_t n_meshes, int64_t* __restrict__ offsets, int64_t* __restrict__ poly_off,
+                                int64_t* __restrict__ counts, int64_t cap_polys, int64_t cap_verts,
+                                const Counters* cnt) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int64_t F = counts_g[0], S = counts_g[1];
+  if (!base[2]) {
+    if (cnt->error || F < 0 || base[0] + F > cap_polys || base[1] + S > cap_verts) base[2] = 1;
+    base[0] += F;
+    base[1] += S;
+  }
+  if (last) {
+    counts[0] = base[0];
+    counts[1] = base[1];
+    if (!base[2]) {
+      offsets[base[0]] = base[1];
+      poly_off[n_meshes] = base[0];
+    }
+  }
+}
+
+// After a failed call (capacity or a device error): every first-polygon offset is -1.
+__global__ __launch_bounds__(256) void k_batch_close(const int64_t* __restrict__ base, int64_t n_meshes,
+                                                     int64_t* __restrict__ poly_off) {
+  if (!base[2]) return;
+  for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m <= n_meshes; m += (int64_t)gridDim.x * blockDim.x)
+    poly_off[m] = -1;
+}
+
+// First output polygon of every mesh of a group: polygons come in mesh order
 // and each starts at its smallest vertex, which lies in its mesh's vertex
 // range, so the first polygon of mesh m is the first polygon whose first
-// vertex is at least vtx_off[m] (binary search).
+// vertex is at least vtx_off[m] - vtx_off[0] (binary search).
 __global__ __launch_bounds__(256) void k_batch_offsets(int64_t n_meshes, const int64_t* __restrict__ vtx_off,
                                                        const int32_t* __restrict__ offsets,
                                                        const int32_t* __restrict__ verts,
@@ -2832,6 +2927,7 @@ __global__ __launch_bounds__(256) void k_batch_offsets(int64_t n_meshes, const i
   const int64_t F = counts[0];
   // after a capacity error the CSR arrays are not filled: report -1
   const bool ok = F <= cap_polys && counts[1] <= cap_verts;
+  const int64_t vbase = vtx_off[0];
   for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m <= n_meshes;
        m += (int64_t)gridDim.x * blockDim.x) {
     if (!ok) {
@@ -2842,7 +2938,7 @@ __global__ __launch_bounds__(256) void k_batch_offsets(int64_t n_meshes, const i
       poly_off[m] = F;
       continue;
     }
-    const int64_t v0 = vtx_off[m];
+    const int64_t v0 = vtx_off[m] - vbase;
     int64_t lo = 0, hi = F;
     while (lo < hi) {
       const int64_t mid = (lo + hi) >> 1;

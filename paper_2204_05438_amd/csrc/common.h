@@ -42,6 +42,10 @@ struct Counters {
   alignas(256) uint32_t big_ticket;  // work counter of the one-wave workgroup path
   alignas(256) uint32_t over_ticket; // work counter of the 1024-thread workgroup path
   alignas(256) uint32_t xcd_ticket[8 * 64];  // walk work queues, one per XCD (xcd_ticket[64 x])
+  // Sums of the path counters over the groups of a batched call (n_seeds,
+  // n_deferred, n_tips, n_splits, n_big, n_fallback, n_lane); a reset that
+  // keeps them also keeps the error word.
+  uint64_t acc[7];
 };
 
 // Per-polygon results of the walk / general path, in seed order: one 16-byte

@@ -43,16 +43,27 @@ __device__ __forceinline__ int32_t edge_key(const int32_t* __restrict__ twin, in
   return (tw < 0 || h < tw) ? h : tw;
 }
 
-__global__ void k_reset(Counters* cnt, uint64_t* status, int64_t n_status, const int64_t* n_from) {
+__global__ void k_reset(Counters* cnt, uint64_t* status, int64_t n_status, const int64_t* n_from, int keep) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t k = i; k < n_status; k += stride) status[k] = 0;
   if (blockIdx.x == 0) {
+    // keep != 0: the error word and the batch sums survive (later groups of a batched call)
     int32_t* w = reinterpret_cast<int32_t*>(cnt);
-    for (size_t k = threadIdx.x; k < sizeof(Counters) / 4; k += blockDim.x) w[k] = 0;
+    const size_t acc_lo = offsetof(Counters, acc) / 4, acc_hi = acc_lo + sizeof(cnt->acc) / 4;
+    for (size_t k = threadIdx.x; k < sizeof(Counters) / 4; k += blockDim.x)
+      if (!keep || (k != 0 && (k < acc_lo || k >= acc_hi))) w[k] = 0;
     __syncthreads();
     if (threadIdx.x == 0 && n_from) cnt->n_seeds = (uint32_t)(*n_from);
   }
+}
+
+// Adds the path counters of the group just run to the batch sums.
+__global__ void k_accumulate(Counters* cnt) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const uint32_t v[7] = {cnt->n_seeds, cnt->n_deferred, cnt->n_tips, cnt->n_splits,
+                         cnt->n_big, cnt->n_fallback, cnt->n_lane};
+  for (int k = 0; k < 7; ++k) cnt->acc[k] += v[k];
 }
 
 __global__ __launch_bounds__(256) void k_longest(int64_t nt, int64_t nv, const double* __restrict__ xy,

@@ -23,6 +23,7 @@ PARAM_WALK_BLOCKS = 2
 PARAM_GEN_WAVE_MAX = 3
 PARAM_REGION_LDS_MAX = 4
 PARAM_REGION_MEM_MAX = 5
+PARAM_BATCH_GROUP_HE = 6
 PROFILE_OFF, PROFILE_ALL, PROFILE_WALK = 0, 1, 2
 
 
@@ -47,6 +48,18 @@ class _Polys(ctypes.Structure):
                 ("counts", ctypes.c_void_p), ("cap_polys", ctypes.c_int64), ("cap_verts", ctypes.c_int64)]
 
 
+class _Batch(ctypes.Structure):
+    _fields_ = [("n_meshes", ctypes.c_int64), ("vtx_off", ctypes.c_void_p), ("he_off", ctypes.c_void_p),
+                ("vtx_off_host", ctypes.c_void_p), ("he_off_host", ctypes.c_void_p), ("xy", ctypes.c_void_p),
+                ("twin", ctypes.c_void_p), ("origin", ctypes.c_void_p)]
+
+
+class _BatchOut(ctypes.Structure):
+    _fields_ = [("offsets", ctypes.c_void_p), ("verts", ctypes.c_void_p), ("start", ctypes.c_void_p),
+                ("poly_off", ctypes.c_void_p), ("counts", ctypes.c_void_p), ("cap_polys", ctypes.c_int64),
+                ("cap_verts", ctypes.c_int64)]
+
+
 _lib = None
 
 
@@ -63,15 +76,15 @@ def load() -> ctypes.CDLL:
         lib.polylla_ctx_destroy.argtypes = [P]
         lib.polylla_ctx_destroy.restype = None
         lib.polylla_reserve.argtypes = [P, ctypes.c_int64, ctypes.c_int64]
+        lib.polylla_reserve_batch.argtypes = [P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64]
         lib.polylla_label.argtypes = [P, ctypes.POINTER(_Tri), ctypes.POINTER(_Labels), P]
         lib.polylla_build.argtypes = [P, ctypes.POINTER(_Tri), ctypes.POINTER(_Labels), ctypes.POINTER(_Polys), P]
         lib.polylla_repair.argtypes = [P, ctypes.POINTER(_Tri), ctypes.POINTER(_Labels), ctypes.POINTER(_Polys),
                                        ctypes.POINTER(_Polys), P]
         lib.polylla_mesh.argtypes = [P, ctypes.POINTER(_Tri), ctypes.POINTER(_Labels), ctypes.POINTER(_Polys), P]
         lib.polylla_validate.argtypes = [P, ctypes.POINTER(_Tri), P]
-        lib.polylla_mesh_batched.argtypes = [P, ctypes.POINTER(_Tri), ctypes.c_int64, P, ctypes.POINTER(_Labels),
-                                             ctypes.POINTER(_Polys), P, P]
-        lib.polylla_rebase.argtypes = [P, P, ctypes.c_int64, P, P, P]
+        lib.polylla_mesh_batched.argtypes = [P, ctypes.POINTER(_Batch), ctypes.POINTER(_Labels),
+                                             ctypes.POINTER(_BatchOut), P]
         lib.polylla_status.argtypes = [P, P]
         lib.polylla_stats.argtypes = [P, ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
         lib.polylla_set_param.argtypes = [P, ctypes.c_int, ctypes.c_int64]
@@ -80,8 +93,8 @@ def load() -> ctypes.CDLL:
                                              ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
         lib.polylla_strerror.argtypes = [ctypes.c_int]
         lib.polylla_strerror.restype = ctypes.c_char_p
-        for f in ("polylla_ctx_create", "polylla_reserve", "polylla_label", "polylla_build", "polylla_repair",
-                  "polylla_mesh", "polylla_mesh_batched", "polylla_rebase", "polylla_validate", "polylla_status",
+        for f in ("polylla_ctx_create", "polylla_reserve", "polylla_reserve_batch", "polylla_label", "polylla_build", "polylla_repair",
+                  "polylla_mesh", "polylla_mesh_batched", "polylla_validate", "polylla_status",
                   "polylla_stats", "polylla_set_param", "polylla_profile", "polylla_profile_read"):
             getattr(lib, f).restype = ctypes.c_int
         _lib = lib
@@ -187,17 +200,101 @@ class Polys:
                 None if self.start is None else self.start[:F])
 
 
-def rebase(twin: torch.Tensor, origin: torch.Tensor, he_off: torch.Tensor, vtx_off: torch.Tensor):
-    """polylla_rebase on torch's current stream: meshes copied one after
-    another with local indices get the global indices of the packed batch."""
-    for t in (he_off, vtx_off):
-        if t.dtype != torch.int64 or not t.is_cuda:
-            raise TypeError("he_off and vtx_off must be int64 device tensors")
-    for t in (twin, origin):
-        if t.dtype != torch.int32 or not t.is_cuda or not t.is_contiguous():
-            raise TypeError("twin and origin must be contiguous int32 device tensors")
-    _check(load().polylla_rebase(_ptr(twin), _ptr(origin), int(he_off.shape[0]) - 1, _ptr(he_off), _ptr(vtx_off),
-                                 ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)), "polylla_rebase")
+@dataclass
+class Batch:
+    """A batch of triangulations on the device, one after another with
+    mesh-local indices (see polylla_batch in polylla.h)."""
+    xy: torch.Tensor       # float64 [sum V, 2]
+    twin: torch.Tensor     # int32 [sum H], local to each mesh
+    origin: torch.Tensor   # int32 [sum H], local to each mesh
+    vtx_off: torch.Tensor  # int64 [M + 1] on the device
+    he_off: torch.Tensor   # int64 [M + 1] on the device
+    vtx_off_host: torch.Tensor  # the same offsets on the host (int64, contiguous)
+    he_off_host: torch.Tensor
+
+    @property
+    def n_meshes(self):
+        return int(self.he_off_host.shape[0]) - 1
+
+    @property
+    def n_halfedges(self):
+        return int(self.he_off_host[-1])
+
+    @property
+    def n_vertices(self):
+        return int(self.vtx_off_host[-1])
+
+    @property
+    def n_tri(self):
+        return self.n_halfedges // 3
+
+    def c(self) -> _Batch:
+        for name in ("xy", "twin", "origin", "vtx_off", "he_off"):
+            t = getattr(self, name)
+            if not t.is_cuda or not t.is_contiguous():
+                raise ValueError(f"{name} must be a contiguous device tensor")
+        for name in ("vtx_off_host", "he_off_host"):
+            t = getattr(self, name)
+            if t.is_cuda or not t.is_contiguous() or t.dtype != torch.int64:
+                raise ValueError(f"{name} must be a contiguous int64 host tensor")
+        if self.vtx_off.dtype != torch.int64 or self.he_off.dtype != torch.int64:
+            raise TypeError("vtx_off and he_off must be int64")
+        if self.xy.dtype != torch.float64 or self.twin.dtype != torch.int32 or self.origin.dtype != torch.int32:
+            raise TypeError("xy must be float64 and twin/origin int32")
+        return _Batch(self.n_meshes, self.vtx_off.data_ptr(), self.he_off.data_ptr(),
+                      self.vtx_off_host.data_ptr(), self.he_off_host.data_ptr(), self.xy.data_ptr(),
+                      self.twin.data_ptr(), self.origin.data_ptr())
+
+    @staticmethod
+    def from_meshes(meshes, device="cuda") -> "Batch":
+        """Copy meshgen meshes (numpy, local indices) into one device batch."""
+        import numpy as np
+        V = np.array([m.n_vertices for m in meshes], np.int64)
+        H = np.array([m.n_halfedges for m in meshes], np.int64)
+        vo = np.zeros(len(meshes) + 1, np.int64)
+        ho = np.zeros(len(meshes) + 1, np.int64)
+        np.cumsum(V, out=vo[1:])
+        np.cumsum(H, out=ho[1:])
+        xy = np.concatenate([m.xy for m in meshes]) if meshes else np.zeros((0, 2))
+        tw = np.concatenate([m.twin for m in meshes]) if meshes else np.zeros(0, np.int32)
+        og = np.concatenate([m.origin for m in meshes]) if meshes else np.zeros(0, np.int32)
+        vh, hh = torch.from_numpy(vo), torch.from_numpy(ho)
+        return Batch(xy=torch.from_numpy(np.ascontiguousarray(xy)).to(device),
+                     twin=torch.from_numpy(tw).to(device), origin=torch.from_numpy(og).to(device),
+                     vtx_off=vh.to(device), he_off=hh.to(device), vtx_off_host=vh, he_off_host=hh)
+
+
+@dataclass
+class BatchOut:
+    offsets: torch.Tensor   # int64 [cap_polys + 1]
+    verts: torch.Tensor     # int32 [cap_verts], mesh-local vertex ids
+    start: torch.Tensor | None  # int32 [cap_polys], mesh-local half-edge ids
+    poly_off: torch.Tensor  # int64 [M + 1]
+    counts: torch.Tensor    # int64 [2]
+
+    @staticmethod
+    def empty(batch: Batch, cap_polys: int | None = None, cap_verts: int | None = None,
+              with_start=True) -> "BatchOut":
+        dev = batch.twin.device
+        T = batch.n_tri
+        cp = T if cap_polys is None else cap_polys
+        cv = 3 * T if cap_verts is None else cap_verts
+        return BatchOut(offsets=torch.empty(cp + 1, dtype=torch.int64, device=dev),
+                        verts=torch.empty(max(cv, 1), dtype=torch.int32, device=dev),
+                        start=torch.empty(max(cp, 1), dtype=torch.int32, device=dev) if with_start else None,
+                        poly_off=torch.empty(batch.n_meshes + 1, dtype=torch.int64, device=dev),
+                        counts=torch.zeros(2, dtype=torch.int64, device=dev))
+
+    def c(self) -> _BatchOut:
+        return _BatchOut(self.offsets.data_ptr(), self.verts.data_ptr(),
+                         None if self.start is None else self.start.data_ptr(), self.poly_off.data_ptr(),
+                         self.counts.data_ptr(), self.offsets.shape[0] - 1, self.verts.shape[0])
+
+    def trimmed(self):
+        """(offsets, verts, start, poly_off) cut to the produced sizes (synchronises)."""
+        F, S = (int(x) for x in self.counts.tolist())
+        return (self.offsets[:F + 1], self.verts[:S], None if self.start is None else self.start[:F],
+                self.poly_off)
 
 
 class Context:
@@ -228,6 +325,10 @@ class Context:
     def reserve(self, n_halfedges: int, n_vertices: int):
         _check(load().polylla_reserve(self._h, int(n_halfedges), int(n_vertices)), "polylla_reserve")
 
+    def reserve_batch(self, n_halfedges: int, n_vertices: int, n_meshes: int):
+        _check(load().polylla_reserve_batch(self._h, int(n_halfedges), int(n_vertices), int(n_meshes)),
+               "polylla_reserve_batch")
+
     def label(self, tri: Tri, labels: Labels | None = None) -> Labels:
         labels = labels or Labels.empty(tri)
         t, l = tri.c(), labels.c()
@@ -255,21 +356,14 @@ class Context:
         _check(load().polylla_mesh(self._h, ctypes.byref(t), lp, ctypes.byref(o), self._stream()), "polylla_mesh")
         return out
 
-    def mesh_batched(self, tri: Tri, vtx_off: torch.Tensor, labels: Labels | None = None,
-                     out: Polys | None = None, poly_off: torch.Tensor | None = None):
-        """Packed batch of meshes (global indices, see polylla_mesh_batched);
-        returns (polys, poly_off) with poly_off int64 [n_meshes + 1] on the device."""
-        n = int(vtx_off.shape[0]) - 1
-        out = out or Polys.empty(tri)
-        if poly_off is None:
-            poly_off = torch.empty(n + 1, dtype=torch.int64, device=tri.origin.device)
-        if vtx_off.dtype != torch.int64 or not vtx_off.is_cuda:
-            raise TypeError("vtx_off must be an int64 device tensor")
-        t, o = tri.c(), out.c()
+    def mesh_batched(self, batch: Batch, labels: Labels | None = None, out: BatchOut | None = None) -> BatchOut:
+        """polylla_mesh_batched over a Batch (mesh-local indices, int64 offsets)."""
+        out = out or BatchOut.empty(batch)
+        b, o = batch.c(), out.c()
         lp = ctypes.byref(labels.c()) if labels is not None else None
-        _check(load().polylla_mesh_batched(self._h, ctypes.byref(t), n, _ptr(vtx_off), lp, ctypes.byref(o),
-                                           _ptr(poly_off), self._stream()), "polylla_mesh_batched")
-        return out, poly_off
+        _check(load().polylla_mesh_batched(self._h, ctypes.byref(b), lp, ctypes.byref(o), self._stream()),
+               "polylla_mesh_batched")
+        return out
 
     def validate(self, tri: Tri) -> int:
         t = tri.c()

@@ -9,10 +9,13 @@ arrive over time. The loop
   * keeps `slots` independent contexts, each with its own stream and packed
     buffers; whenever a slot is idle it takes every admitted request not yet
     started (up to its triangle and mesh capacity), packs them on the device
-    (device-to-device copies plus polylla_rebase) and runs ONE
+    (device-to-device copies; indices stay local to each mesh) and runs ONE
     polylla_mesh_batched over the batch, so requests that arrive while other
     batches are on the GPU join the next free slot and their work overlaps
     with the running batches on the device;
+  * checks the batch's device status once it is done: a batch with an error
+    (a request that is not a valid triangulation) is served again one request
+    at a time, so only the bad request fails (`error` set, no polygons);
   * copies each batch's polygons back (sizes first, then exactly the produced
     CSR) and splits them per request.
 Latency of a request = results on the host - arrival, split into admission
@@ -42,6 +45,8 @@ class Request:
     done: float | None = None
     offsets: np.ndarray | None = None  # result: local CSR
     verts: np.ndarray | None = None
+    error: int = 0                     # library error code of a request that could not be served
+    alone: bool = False                # served in a batch of its own (after its batch failed)
     _dev: tuple | None = None
     _ready: torch.cuda.Event | None = None
 
@@ -74,24 +79,34 @@ class _Slot:
         self.ctx = lib.Context(device)
         self.stream = torch.cuda.Stream(dev)
         self.max_tri, self.max_vert, self.max_meshes = max_tri, max_vert, max_meshes
-        self.ctx.reserve(3 * max_tri, max_vert)
         self.xy = torch.empty((max_vert, 2), dtype=torch.float64, device=dev)
         self.twin = torch.empty(3 * max_tri, dtype=torch.int32, device=dev)
         self.origin = torch.empty(3 * max_tri, dtype=torch.int32, device=dev)
-        self.offsets = torch.empty(max_tri + 1, dtype=torch.int32, device=dev)
+        self.offsets = torch.empty(max_tri + 1, dtype=torch.int64, device=dev)
         self.verts = torch.empty(3 * max_tri, dtype=torch.int32, device=dev)
         self.counts = torch.zeros(2, dtype=torch.int64, device=dev)
         self.poly_off = torch.empty(max_meshes + 1, dtype=torch.int64, device=dev)
-        self.he_off = torch.empty(max_meshes + 1, dtype=torch.int64, device=dev)
-        self.vtx_off = torch.empty(max_meshes + 1, dtype=torch.int64, device=dev)
+        self.offs = torch.empty((2, max_meshes + 1), dtype=torch.int64, device=dev)  # he_off, vtx_off
         self.h_offs = torch.empty((2, max_meshes + 1), dtype=torch.int64).pin_memory()
         self.h_counts = torch.empty(2, dtype=torch.int64).pin_memory()
         self.h_poly_off = torch.empty(max_meshes + 1, dtype=torch.int64).pin_memory()
-        self.h_offsets = torch.empty(max_tri + 1, dtype=torch.int32).pin_memory()
+        self.h_offsets = torch.empty(max_tri + 1, dtype=torch.int64).pin_memory()
         self.h_verts = torch.empty(3 * max_tri, dtype=torch.int32).pin_memory()
         self.state = _Slot.IDLE
         self.batch: list[Request] = []
         self.event = None
+        self.failed = 0
+        # scratch for a full slot, so that batches allocate nothing
+        self.ctx.reserve_batch(3 * max_tri, max_vert, max_meshes)
+
+    def _run(self, n: int, Ht: int, Vt: int):
+        offs = self.h_offs
+        batch = lib.Batch(xy=self.xy[:Vt], twin=self.twin[:Ht], origin=self.origin[:Ht],
+                          vtx_off=self.offs[1, :n + 1], he_off=self.offs[0, :n + 1],
+                          vtx_off_host=offs[1, :n + 1], he_off_host=offs[0, :n + 1])
+        out = lib.BatchOut(offsets=self.offsets[:Ht // 3 + 1], verts=self.verts[:Ht], start=None,
+                           poly_off=self.poly_off[:n + 1], counts=self.counts)
+        self.ctx.mesh_batched(batch, None, out)
 
     def launch(self, batch: list[Request]):
         n = len(batch)
@@ -105,19 +120,14 @@ class _Slot:
         with torch.cuda.stream(self.stream):
             for r in batch:
                 self.stream.wait_event(r._ready)
-            self.he_off[:n + 1].copy_(self.h_offs[0, :n + 1], non_blocking=True)
-            self.vtx_off[:n + 1].copy_(self.h_offs[1, :n + 1], non_blocking=True)
+            self.offs[:, :n + 1].copy_(self.h_offs[:, :n + 1], non_blocking=True)
             for k, r in enumerate(batch):
                 dxy, dtw, dor = r._dev
                 a, b, va, vb = int(offs[0, k]), int(offs[0, k + 1]), int(offs[1, k]), int(offs[1, k + 1])
                 self.xy[va:vb].copy_(dxy)
                 self.twin[a:b].copy_(dtw)
                 self.origin[a:b].copy_(dor)
-            lib.rebase(self.twin[:Ht], self.origin[:Ht], self.he_off[:n + 1], self.vtx_off[:n + 1])
-            tri = lib.Tri(xy=self.xy[:Vt], twin=self.twin[:Ht], next=None, origin=self.origin[:Ht])
-            out = lib.Polys(offsets=self.offsets[:Ht // 3 + 1], verts=self.verts[:Ht], start=None,
-                            counts=self.counts)
-            self.ctx.mesh_batched(tri, self.vtx_off[:n + 1], None, out, self.poly_off[:n + 1])
+            self._run(n, Ht, Vt)
             self.h_counts.copy_(self.counts, non_blocking=True)
             self.h_poly_off[:n + 1].copy_(self.poly_off[:n + 1], non_blocking=True)
             self.event = torch.cuda.Event()
@@ -126,28 +136,42 @@ class _Slot:
         self.state = _Slot.COMPUTE
 
     def copy_back(self):
-        """Sizes are on the host: copy exactly the produced polygons back."""
+        """The batch is done: read its device status, then copy exactly the
+        produced polygons back. Returns False (nothing copied) when the
+        batch failed; its requests are then in self.batch with the code in
+        self.failed."""
+        code = self.ctx.status(raise_on_error=False)
+        n = len(self.batch)
+        if code == lib.OK and int(self.h_poly_off[0]) < 0:
+            code = lib.ECAPACITY  # every first-polygon offset is -1 after a capacity failure
+        if code != lib.OK:
+            self.failed = code
+            return False
         F, S = (int(x) for x in self.h_counts.tolist())
-        if F < 0 or S < 0:
-            raise lib.PolyllaError(lib.ECAPACITY, "batch output capacity")
+        assert int(self.h_poly_off[n]) == F
         with torch.cuda.stream(self.stream):
             self.h_offsets[:F + 1].copy_(self.offsets[:F + 1], non_blocking=True)
             self.h_verts[:S].copy_(self.verts[:S], non_blocking=True)
             self.event = torch.cuda.Event()
             self.event.record(self.stream)
         self.state = _Slot.COPY
+        return True
+
+    def take_failed(self):
+        batch, self.batch = self.batch, []
+        self.state = _Slot.IDLE
+        return batch
 
     def finish(self, now: float):
         n = len(self.batch)
         po = self.h_poly_off.numpy()[:n + 1]
         offs = self.h_offsets.numpy()
         verts = self.h_verts.numpy()
-        voff = self.h_offs.numpy()[1]
         for k, r in enumerate(self.batch):
             a, b = int(po[k]), int(po[k + 1])
             o = offs[a:b + 1]
-            r.offsets = (o - o[0]).copy()
-            r.verts = verts[int(o[0]):int(o[-1])] - np.int32(voff[k])
+            r.offsets = (o - o[0]).astype(np.int32)
+            r.verts = verts[int(o[0]):int(o[-1])].copy()
             r.done = now
             r._dev = None
         batch, self.batch = self.batch, []
@@ -155,7 +179,7 @@ class _Slot:
         return batch
 
     def close(self):
-        self.ctx.status()
+        self.ctx.status(raise_on_error=False)
         self.ctx.close()
 
 
@@ -209,7 +233,17 @@ class Server:
                 progressed = True
             for slot in self.slots:
                 if slot.state == _Slot.COMPUTE and slot.event.query():
-                    slot.copy_back()
+                    if not slot.copy_back():
+                        bad = slot.take_failed()
+                        if len(bad) == 1 and bad[0].alone:
+                            r = bad[0]  # fails on its own: answered with the error, no polygons
+                            r.error, r.done, r._dev = slot.failed, time.perf_counter() - t0, None
+                            used -= r.input_bytes()
+                            finished.append(r)
+                        else:
+                            for r in reversed(bad):  # served again, one request per batch
+                                r.alone = True
+                                resident.appendleft(r)
                     progressed = True
                 if slot.state == _Slot.COPY and slot.event.query():
                     done = slot.finish(time.perf_counter() - t0)
@@ -221,7 +255,8 @@ class Server:
                     batch, tri, verts = [], 0, 0
                     while resident and len(batch) < self.max_meshes and \
                             tri + resident[0].n_tri <= self.max_tri and \
-                            verts + resident[0].n_vertices <= self.max_vert:
+                            verts + resident[0].n_vertices <= self.max_vert and \
+                            not (batch and (batch[0].alone or resident[0].alone)):
                         r = resident.popleft()
                         tri += r.n_tri
                         verts += r.n_vertices
@@ -231,12 +266,11 @@ class Server:
                     progressed = True
             if not progressed:
                 time.sleep(20e-6)
-        for slot in self.slots:
-            slot.ctx.status()
         return summarize(finished)
 
 
 def summarize(done: list[Request]) -> dict:
+    failed = sum(1 for r in done if r.error)
     lat = np.array([r.done - r.arrival for r in done])
     adm = np.array([r.admitted - r.arrival for r in done])
     que = np.array([r.started - r.admitted for r in done])
@@ -247,7 +281,7 @@ def summarize(done: list[Request]) -> dict:
     def q(x, p):
         return round(float(np.percentile(x, p)) * 1e3, 3)
 
-    return {"requests": len(done), "span_s": round(span, 4),
+    return {"requests": len(done), "failed": failed, "span_s": round(span, 4),
             "meshes_per_s": round(len(done) / span, 2), "triangles_per_s": round(tri / span, 1),
             "latency_ms": {"p50": q(lat, 50), "p99": q(lat, 99), "mean": round(float(lat.mean()) * 1e3, 3)},
             "breakdown_ms_p50": {"admission_wait": q(adm, 50), "queued": q(que, 50), "service": q(svc, 50)},

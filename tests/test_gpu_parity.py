@@ -294,91 +294,197 @@ def test_layout_errors(ctx):
     assert ctx.status(raise_on_error=False) == lib.ETOPO
 
 
-@pytest.mark.parametrize("walk_cap,lds_max,mem_max", [(4, 4096, 65536), (24, 4096, 65536), (24, 32, 65536),
-                                                     (24, 32, 32), (4, 32, 32)])
-def test_batched_equals_per_mesh(ctx, walk_cap, lds_max, mem_max):
-    """A packed batch of uneven meshes gives each mesh's own polygons (also
-    with the region limits lowered, so that regions of the batch take the
-    global-memory and the one-lane paths)."""
-    _say(f"batched 40 meshes walk_cap {walk_cap} lds_max {lds_max} mem_max {mem_max}")
-    from meshgen.gen import pack_meshes
+def check_batch_against_oracle(meshes, out, labels=None, he_off=None, oracle_outputs=None):
+    """Every mesh's polygons in a batched output (mesh-local ids) equal the
+    oracle's for that mesh alone."""
+    off, verts, start, po = (x.cpu().numpy() if x is not None else None for x in out.trimmed())
+    he = labels.he.cpu().numpy() if labels is not None else None
+    assert po[0] == 0 and po[-1] == off.size - 1
+    for k, m in enumerate(meshes):
+        o = oracle_outputs[k] if oracle_outputs is not None else oracle.oracle_on(m)
+        a, b = int(po[k]), int(po[k + 1])
+        got_off = off[a:b + 1] - off[a]
+        assert np.array_equal(got_off, o["offsets"]), k
+        assert np.array_equal(verts[off[a]:off[b]], o["verts"]), k
+        if start is not None:
+            assert np.array_equal(start[a:b], o["start"]), k
+        if he is not None:
+            assert np.array_equal(he[he_off[k]:he_off[k + 1]], o["he"]), k
+
+
+@pytest.mark.parametrize("walk_cap,lds_max,mem_max,group", [(4, 4096, 65536, 0), (24, 4096, 65536, 0),
+                                                            (24, 32, 65536, 0), (24, 32, 32, 0), (4, 32, 32, 0),
+                                                            (24, 4096, 65536, 3), (24, 4096, 65536, 30000)])
+def test_batched_equals_per_mesh(ctx, walk_cap, lds_max, mem_max, group):
+    """A batch of uneven meshes (mesh-local indices) gives each mesh its own
+    polygons, also with the region limits lowered (regions of the batch take
+    the global-memory and one-lane paths) and with the batch cut into groups
+    of one mesh each (group 3) or of about 30000 half-edges."""
+    _say(f"batched 40 meshes walk_cap {walk_cap} lds_max {lds_max} mem_max {mem_max} group {group}")
     from paper_2204_05438_amd import lib
     rng = np.random.default_rng(11)
     meshes = [random_mesh(300 + k, int(n), ["uniform", "cluster", "grid", "lattice"][k % 4])
               for k, n in enumerate(np.rint(10 ** rng.uniform(0.8, 3.6, 40)))]
-    packed, vtx_off, he_off = pack_meshes(meshes)
+    meshes.insert(7, empty_mesh())
     ctx.set_param(lib.PARAM_WALK_CAP, walk_cap)
     ctx.set_param(lib.PARAM_REGION_LDS_MAX, lds_max)
     ctx.set_param(lib.PARAM_REGION_MEM_MAX, mem_max)
+    if group:
+        ctx.set_param(lib.PARAM_BATCH_GROUP_HE, group)
     try:
-        tri = lib.Tri.from_mesh(packed)
-        labels = lib.Labels.empty(tri)
-        out, poly_off = ctx.mesh_batched(tri, torch.from_numpy(vtx_off).cuda(), labels)
+        batch = lib.Batch.from_meshes(meshes)
+        labels = lib.Labels.empty(batch)
+        out = ctx.mesh_batched(batch, labels)
         ctx.status()
         _say(f"  stats {ctx.stats()}")
     finally:
         ctx.set_param(lib.PARAM_WALK_CAP, 24)
         ctx.set_param(lib.PARAM_REGION_LDS_MAX, 4096)
         ctx.set_param(lib.PARAM_REGION_MEM_MAX, 65536)
-    off, verts, start = (x.cpu().numpy() for x in out.trimmed())
-    po = poly_off.cpu().numpy()
-    he = labels.he.cpu().numpy()
-    assert po[0] == 0 and po[-1] == off.size - 1
-    for k, m in enumerate(meshes):
-        o = oracle.oracle_on(m)
-        a, b = int(po[k]), int(po[k + 1])
-        got_off = off[a:b + 1] - off[a]
-        got_verts = verts[off[a]:off[b]] - vtx_off[k]
-        assert np.array_equal(got_off, o["offsets"]), k
-        assert np.array_equal(got_verts, o["verts"]), k
-        assert np.array_equal(start[a:b] - he_off[k], o["start"]), k
-        assert np.array_equal(he[he_off[k]:he_off[k + 1]], o["he"]), k
+        ctx.set_param(lib.PARAM_BATCH_GROUP_HE, (1 << 30) - (1 << 24))
+    check_batch_against_oracle(meshes, out, labels, batch.he_off_host.numpy())
+    st = ctx.stats()
+    assert st["seeds"] == sum(oracle.oracle_on(m)["stats"]["seeds"] for m in meshes)
+
+
+def test_batched_recipe_against_oracle(ctx):
+    """120 meshes of the batched workload's recipe (uniform points, sizes
+    log-uniform, here in [1e3, 2e4]) in one call, each against the oracle."""
+    _say("batched recipe, 120 meshes")
+    from meshgen.gen import batch_points, mesh_from_points
+    from paper_2204_05438_amd import lib
+    sizes = np.rint(10 ** np.random.default_rng(4).uniform(3.0, 4.3, 120)).astype(int)
+    meshes = [mesh_from_points(batch_points(m, int(n))) for m, n in enumerate(sizes)]
+    batch = lib.Batch.from_meshes(meshes)
+    labels = lib.Labels.empty(batch)
+    out = ctx.mesh_batched(batch, labels)
+    ctx.status()
+    check_batch_against_oracle(meshes, out, labels, batch.he_off_host.numpy())
+
+
+def test_batched_bad_mesh_reported(ctx):
+    """A local twin or origin outside its own mesh is reported (ETOPO), not
+    taken as an index into a neighbouring mesh."""
+    _say("batched: out-of-range local index")
+    from paper_2204_05438_amd import lib
+    meshes = [random_mesh(40 + k, 200, "uniform") for k in range(3)]
+    for field, value in (("twin", None), ("origin", None)):
+        batch = lib.Batch.from_meshes(meshes)
+        H0 = meshes[0].n_halfedges
+        arr = getattr(batch, field)
+        if field == "twin":
+            arr[H0 + 5] = meshes[1].n_halfedges + 2   # a half-edge of mesh 2 in global numbering
+        else:
+            arr[H0 + 5] = meshes[1].n_vertices + 1
+        ctx.mesh_batched(batch)
+        assert ctx.status(raise_on_error=False) == lib.ETOPO, field
+    batch = lib.Batch.from_meshes(meshes)
+    out = ctx.mesh_batched(batch)
+    ctx.status()
+    check_batch_against_oracle(meshes, out)
+
+
+def test_batched_capacity_error(ctx):
+    """Too small an output: ECAPACITY and every poly_off entry -1."""
+    _say("batched: capacity error")
+    from paper_2204_05438_amd import lib
+    meshes = [random_mesh(60 + k, 300, "uniform") for k in range(4)]
+    batch = lib.Batch.from_meshes(meshes)
+    for group in (0, 3):
+        if group:
+            ctx.set_param(lib.PARAM_BATCH_GROUP_HE, group)
+        try:
+            out = lib.BatchOut.empty(batch, cap_polys=50, cap_verts=200)
+            ctx.mesh_batched(batch, None, out)
+            assert ctx.status(raise_on_error=False) == lib.ECAPACITY
+            assert (out.poly_off.cpu().numpy() == -1).all()
+        finally:
+            ctx.set_param(lib.PARAM_BATCH_GROUP_HE, (1 << 30) - (1 << 24))
+    out = ctx.mesh_batched(batch)
+    ctx.status()
+    check_batch_against_oracle(meshes, out)
 
 
 def test_batched_graph_replay(ctx):
     """polylla_mesh_batched captured in a HIP graph: every replay, with eager
-    work and synchronisation between replays, equals the eager call."""
+    work and synchronisation between replays, equals the eager call (also
+    with the batch cut into several groups)."""
     _say("batched graph replay, 24 meshes")
-    from meshgen.gen import pack_meshes
     from paper_2204_05438_amd import lib
     rng = np.random.default_rng(21)
     kinds = ["uniform", "cluster", "grid", "lattice"]
     meshes = [random_mesh(600 + k, int(n), kinds[k % 4])
               for k, n in enumerate(np.rint(10 ** rng.uniform(1.0, 3.7, 24)))]
-    packed, vtx_off, _ = pack_meshes(meshes)
-    tri = lib.Tri.from_mesh(packed, with_next=False)
-    voff = torch.from_numpy(vtx_off).cuda()
-    ctx.reserve(tri.n_halfedges, tri.n_vertices)
-    labels = lib.Labels.empty(tri)
-    out = lib.Polys.empty(tri)
-    poly_off = torch.empty(len(meshes) + 1, dtype=torch.int64, device="cuda")
+    batch = lib.Batch.from_meshes(meshes)
+    for group in (0, 20000):
+        if group:
+            ctx.set_param(lib.PARAM_BATCH_GROUP_HE, group)
+        labels = lib.Labels.empty(batch)
+        out = lib.BatchOut.empty(batch)
 
-    def snapshot():
-        off, verts, start = (x.cpu().numpy().copy() for x in out.trimmed())
-        return off, verts, start, poly_off.cpu().numpy().copy(), labels.he.cpu().numpy().copy()
+        def snapshot():
+            off, verts, start, po = (x.cpu().numpy().copy() for x in out.trimmed())
+            return off, verts, start, po, labels.he.cpu().numpy().copy()
 
-    ctx.mesh_batched(tri, voff, labels, out, poly_off)
+        try:
+            ctx.mesh_batched(batch, labels, out)
+            ctx.status()
+            ref = snapshot()
+            side = torch.cuda.Stream()
+            side.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(side):
+                ctx.mesh_batched(batch, labels, out)
+            torch.cuda.current_stream().wait_stream(side)
+            torch.cuda.synchronize()
+            graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(graph):
+                ctx.mesh_batched(batch, labels, out)
+            for rep in range(3):
+                out.verts.fill_(-1)
+                out.offsets.fill_(-1)
+                out.poly_off.fill_(-7)
+                labels.he.zero_()
+                torch.cuda.synchronize()
+                graph.replay()
+                torch.cuda.synchronize()
+                assert ctx.status(raise_on_error=False) == lib.OK, rep
+                got = snapshot()
+                for a, b, name in zip(got, ref, ["offsets", "verts", "start", "poly_off", "he"]):
+                    assert np.array_equal(a, b), (group, rep, name)
+            del graph
+        finally:
+            ctx.set_param(lib.PARAM_BATCH_GROUP_HE, (1 << 30) - (1 << 24))
+    check_batch_against_oracle(meshes, out)
+
+
+def test_batched_beyond_2e31_halfedges(ctx):
+    """One mesh replicated on the device until the batch holds more than 2^31
+    half-edges (int64 offsets, several groups): every copy's polygons equal
+    that mesh's oracle output."""
+    from paper_2204_05438_amd import lib
+    mesh = config_mesh("mixed200k")
+    H, V = mesh.n_halfedges, mesh.n_vertices
+    n = (1 << 31) // H + 2
+    _say(f"batched: {n} copies of mixed200k, {n * H} half-edges")
+    o = oracle.oracle_on(mesh)
+    dev = torch.device("cuda")
+    ho = torch.arange(n + 1, dtype=torch.int64) * H
+    vo = torch.arange(n + 1, dtype=torch.int64) * V
+    batch = lib.Batch(xy=torch.from_numpy(mesh.xy).to(dev).repeat(n, 1),
+                      twin=torch.from_numpy(mesh.twin).to(dev).repeat(n),
+                      origin=torch.from_numpy(mesh.origin).to(dev).repeat(n),
+                      vtx_off=vo.to(dev), he_off=ho.to(dev), vtx_off_host=vo, he_off_host=ho)
+    F1, S1 = o["offsets"].size - 1, o["verts"].size
+    out = lib.BatchOut.empty(batch, cap_polys=n * F1, cap_verts=n * S1, with_start=False)
+    ctx.mesh_batched(batch, None, out)
     ctx.status()
-    ref = snapshot()
-    side = torch.cuda.Stream()
-    side.wait_stream(torch.cuda.current_stream())
-    with torch.cuda.stream(side):
-        ctx.mesh_batched(tri, voff, labels, out, poly_off)
-    torch.cuda.current_stream().wait_stream(side)
-    torch.cuda.synchronize()
-    graph = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(graph):
-        ctx.mesh_batched(tri, voff, labels, out, poly_off)
-    for rep in range(3):
-        out.verts.fill_(-1)
-        out.offsets.fill_(-1)
-        poly_off.fill_(-7)
-        labels.he.zero_()
-        torch.cuda.synchronize()
-        graph.replay()
-        torch.cuda.synchronize()
-        assert ctx.status(raise_on_error=False) == lib.OK, rep
-        got = snapshot()
-        for a, b, name in zip(got, ref, ["offsets", "verts", "start", "poly_off", "he"]):
-            assert np.array_equal(a, b), (rep, name)
-    del graph
+    _say(f"  stats {ctx.stats()}")
+    assert out.counts.tolist() == [n * F1, n * S1]
+    po = out.poly_off
+    assert torch.equal(po, torch.arange(n + 1, dtype=torch.int64, device=dev) * F1)
+    ref_off = torch.from_numpy(o["offsets"].astype(np.int64)).to(dev)
+    ref_verts = torch.from_numpy(o["verts"]).to(dev)
+    for k in range(n):
+        got_off = out.offsets[k * F1:(k + 1) * F1 + 1] - k * S1
+        assert torch.equal(got_off, ref_off), k
+        assert torch.equal(out.verts[k * S1:(k + 1) * S1], ref_verts), k

@@ -65,12 +65,24 @@ def test_binding_constants_match_header():
         "EINTERNAL": lib.EINTERNAL,
         "LONGEST": lib.LONGEST, "FRONTIER": lib.FRONTIER, "TERMINAL": lib.TERMINAL, "BORDER": lib.BORDER,
         "BARRIER": lib.BARRIER, "REPAIRED": lib.REPAIRED, "SEED": lib.SEED, "TIP": lib.TIP,
-        "PARAM_WALK_CAP": lib.PARAM_WALK_CAP, "PARAM_WALK_BLOCKS": lib.PARAM_WALK_BLOCKS,
-        "PARAM_GEN_WAVE_MAX": lib.PARAM_GEN_WAVE_MAX, "PARAM_REGION_LDS_MAX": lib.PARAM_REGION_LDS_MAX,
-        "PARAM_REGION_MEM_MAX": lib.PARAM_REGION_MEM_MAX,
         "PROFILE_OFF": lib.PROFILE_OFF, "PROFILE_ALL": lib.PROFILE_ALL, "PROFILE_WALK": lib.PROFILE_WALK,
     }
     for name, val in pairs.items():
         assert h[name] == val, (name, h.get(name), val)
-    params = {k for k in h if k.startswith("PARAM_")}
-    assert params == {k for k in pairs if k.startswith("PARAM_")}, params
+    params = [k for k in h if k.startswith("PARAM_")]
+    assert len(params) >= 6
+    for k in params:  # every tuning parameter of the header, with its value
+        assert getattr(lib, k) == h[k], k
+
+
+def test_batch_struct_layout():
+    """The ctypes mirrors of polylla_batch and polylla_batch_out have the
+    header's field order and the C layout (all fields 8 bytes wide)."""
+    from paper_2204_05438_amd import lib
+    src = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    for cname, pyt in (("polylla_batch", lib._Batch), ("polylla_batch_out", lib._BatchOut)):
+        body = re.search(r"typedef struct \{([^}]*)\}\s*" + cname + ";", src).group(1)
+        fields = [f for decl in body.split(";") if decl.strip()
+                  for f in re.findall(r"\*?\s*([a-z_]+)\s*(?:,|$)", decl.strip().split(None, 2)[-1])]
+        assert [f for f, _ in pyt._fields_] == fields, (cname, fields)
+        assert ctypes.sizeof(pyt) == 8 * len(fields)

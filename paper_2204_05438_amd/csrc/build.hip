@@ -1194,6 +1194,18 @@ __global__ __launch_bounds__(64) void k_tip(int32_t nhe, int64_t nv, const int32
         }
       }
       fast = ntip == 1;
+      if (fast) {
+        // The cycle may repeat vertices only along the slit ending at the tip
+        // (v[m-k-1] == v[m+k+1], k < K): then the slit's K edges are all its
+        // barrier edges. Any other repeated vertex (a lobe hanging off a
+        // barrier edge, a region touching itself) goes to the region path.
+        int K = 0;
+        while (2 * K + 2 < L && v[(m - K - 1 + L) % L] == v[(m + K + 1) % L]) ++K;
+        int pairs = 0;
+        for (int a = 0; a < L; ++a)
+          for (int b = a + 1; b < L; ++b) pairs += v[a] == v[b] ? 1 : 0;
+        fast = pairs == K;
+      }
     }
     int32_t e = -1, te = -1, x = -1;
     int q = -1;

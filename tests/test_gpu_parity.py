@@ -228,6 +228,21 @@ def test_permuted_layout_mixed1m(ctx, block):
     assert sorted(csr_cycles(r["offsets"], r["verts"])) == sorted(csr_cycles(base["offsets"], base["verts"]))
 
 
+def test_single_tip_polygon_with_a_lobe(ctx):
+    """Mesh 32 of the batched workload (656,631 uniform points) has a short
+    polygon with one barrier-edge tip whose cycle also runs twice along a
+    barrier edge away from the tip's slit (a lobe of the region hangs off
+    that edge). The single-tip path must leave it to the region path, which
+    marks that edge BARRIER like the oracle."""
+    _say("batched mesh 32: single-tip polygon with a lobe")
+    from meshgen.gen import batch_points, batch_sizes, mesh_from_points
+    mesh = mesh_from_points(batch_points(32, int(batch_sizes(2000)[32])))
+    r = gpu_mesh(ctx, mesh)
+    o = oracle.oracle_on(mesh)
+    assert o["stats"]["nonsimple_final"] >= 1
+    assert_same(r, o, FULL)
+
+
 def test_uniform5m_large_regions(ctx):
     """5M uniform points: two regions exceed the LDS of the 1024-thread
     kernel at the default limits and are built by the global-memory path."""

@@ -180,10 +180,13 @@ def generate(pool, fn, jobs, n):
     """Run generation jobs largest first; returns meshes, digests, oracle seconds."""
     from meshgen.gen import Mesh
     meshes, digests, secs = [None] * n, [None] * n, 0.0
-    for k, xy, origin, twin, (dg, dt, _) in pool.imap_unordered(fn, jobs):
+    t0 = time.time()
+    for done, (k, xy, origin, twin, (dg, dt, _)) in enumerate(pool.imap_unordered(fn, jobs), 1):
         meshes[k] = Mesh(xy=xy, origin=origin, twin=twin, next=None)
         digests[k] = dg
         secs += dt
+        if done % 250 == 0:
+            log(f"  {done}/{n} meshes generated ({time.time() - t0:.0f}s)")
     return meshes, digests, secs
 
 

@@ -140,12 +140,13 @@ constexpr int64_t kBigArenaTails = 2 * (int64_t)kBigGrid64 * kBigArenaChunk64 + 
 
 enum KernelId {
   KR_RESET, KR_LONGEST, KR_LABEL, KR_COMPACT, KR_PACK, KR_WALK, KR_GENERAL, KR_BIG, KR_HUGE, KR_SCAN, KR_VALIDATE,
-  KR_BATCH, KR_BIGW, KR_TIP, KR_SEEDS, KR_GENW, KR_N
+  KR_BATCH, KR_BIGW, KR_TIP, KR_SEEDS, KR_GENW, KR_GREBASE, KR_GFINISH, KR_N
 };
 const char* kKernelNames[KR_N] = {"k_reset",         "k_longest",       "k_label",          "k_compact_seeds",
                                   "k_pack_walk",     "k_walk",          "k_general_small",  "k_general_big",
                                   "k_general_huge",  "k_scan_emit",     "k_validate",       "k_batch_offsets",
-                                  "k_general_big_wg", "k_tip",           "k_seeds",          "k_general_wave"};
+                                  "k_general_big_wg", "k_tip",           "k_seeds",          "k_general_wave",
+                                  "k_group_rebase",  "k_group_finish"};
 
 // Event pair around one kernel launch when profiling is on.
 struct Prof {
@@ -657,7 +658,7 @@ int polylla_mesh_batched(polylla_ctx* c, const polylla_batch* b, polylla_labels*
     const int64_t m0 = first[k], m1 = first[k + 1], nm = m1 - m0;
     const int64_t h0 = ho[m0], H = ho[m1] - h0, v0 = vo[m0], V = vo[m1] - v0;
     if (H > 0) {
-      Prof p(c, s, KR_BATCH);
+      Prof p(c, s, KR_GREBASE);
       hipLaunchKernelGGL(k_group_rebase, dim3(grid_for(H, 256, 1 << 16)), dim3(256), 0, s, b->twin, b->origin,
                          c->g_twin, c->g_origin, nm, b->he_off + m0, b->vtx_off + m0);
     }
@@ -672,10 +673,17 @@ int polylla_mesh_batched(polylla_ctx* c, const polylla_batch* b, polylla_labels*
       hipLaunchKernelGGL(k_accumulate, dim3(1), dim3(64), 0, s, c->cnt);
       hipLaunchKernelGGL(k_batch_offsets, dim3(grid_for(nm + 1, 256, 4096)), dim3(256), 0, s, nm, b->vtx_off + m0,
                          c->g_off, c->g_verts, c->g_counts, pg.cap_polys, pg.cap_verts, c->g_poly);
-      hipLaunchKernelGGL(k_group_finish, dim3(grid_for(std::max(H / 3, nm), 256, 1 << 16)), dim3(256), 0, s, nm,
+    }
+    {
+      // one block per 2048 output slots of the group (at most 3 per triangle)
+      Prof p(c, s, KR_GFINISH);
+      hipLaunchKernelGGL(k_group_finish, dim3(std::max<int64_t>(H / 2048 + 1, (nm + 255) / 256)), dim3(256), 0, s, nm,
                          b->he_off + m0, b->vtx_off + m0, c->g_off, c->g_verts, c->g_start, c->g_counts, c->g_poly,
                          c->g_base, out->offsets, out->verts, out->start, out->poly_off + m0, pg.cap_polys,
                          out->cap_polys, out->cap_verts, c->cnt);
+    }
+    {
+      Prof p(c, s, KR_BATCH);
       hipLaunchKernelGGL(k_group_advance, dim3(1), dim3(64), 0, s, c->g_counts, c->g_base, k + 1 == ng, n,
                          out->offsets, out->poly_off, out->counts, out->cap_polys, out->cap_verts,
                          (const Counters*)c->cnt);

@@ -2841,12 +2841,15 @@ __global__ __launch_bounds__(256) void k_group_rebase(const int32_t* __restrict_
                                                       const int64_t* __restrict__ vtx_off) {
   const int64_t h0 = he_off[0], v0 = vtx_off[0];
   const int64_t H = he_off[nm] - h0;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (h >= H) return;
+  // each block takes one contiguous chunk, so a thread's mesh index only
+  // moves forward over the few meshes the chunk spans
+  const int64_t chunk = ((H + gridDim.x - 1) / gridDim.x + 255) / 256 * 256;
+  const int64_t c0 = (int64_t)blockIdx.x * chunk, c1 = min(H, c0 + chunk);
+  int64_t h = c0 + threadIdx.x;
+  if (h >= c1) return;
   int64_t m = mesh_of(he_off, nm, h0 + h);
-  for (; h < H; h += stride) {
-    while (m + 1 < nm && he_off[m + 1] <= h0 + h) ++m;  // meshes ahead of the last one (usually none)
+  for (; h < c1; h += blockDim.x) {
+    while (m + 1 < nm && he_off[m + 1] <= h0 + h) ++m;
     const int64_t hb = he_off[m] - h0, hn = he_off[m + 1] - he_off[m];
     const int64_t vb = vtx_off[m] - v0, vn = vtx_off[m + 1] - vtx_off[m];
     const int32_t tw = twin[h0 + h], og = origin[h0 + h];
@@ -2861,16 +2864,36 @@ __global__ void k_batch_begin(int64_t* __restrict__ base) {
   if (threadIdx.x < 4) base[threadIdx.x] = 0;
 }
 
-// One thread per polygon of the group: the caller's CSR entries at the
-// running offsets, vertex and half-edge ids made local to the polygon's mesh
-// (found by binary search over the group's first-polygon offsets), and the
-// first polygon of every mesh of the group.
+// The group's CSR into the caller's at the running offsets, vertex and
+// half-edge ids made local to each polygon's mesh. A block takes 2048
+// consecutive output slots: the offsets of the polygons they belong to go to
+// LDS with each polygon's vertex base (its mesh found by binary search over
+// the group's first-polygon offsets), every slot finds its polygon by binary
+// search in LDS, and slots, offsets and start half-edges are stored
+// coalesced. Blocks beyond the group's vertices only write first-polygon
+// offsets.
+constexpr int kFinTile = 2048;
+
+__device__ __forceinline__ int64_t first_above(const int32_t* __restrict__ a, int64_t n, int64_t x) {
+  int64_t lo = 0, hi = n;  // first index in [0, n) with a[idx] > x (n if none)
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (a[mid] > x) hi = mid;
+    else lo = mid + 1;
+  }
+  return lo;
+}
+
 __global__ __launch_bounds__(256) void k_group_finish(
     int64_t nm, const int64_t* __restrict__ he_off, const int64_t* __restrict__ vtx_off,
     const int32_t* __restrict__ off_g, const int32_t* __restrict__ verts_g, const int32_t* __restrict__ start_g,
     const int64_t* __restrict__ counts_g, const int64_t* __restrict__ poly_g, const int64_t* __restrict__ base,
     int64_t* __restrict__ offsets, int32_t* __restrict__ verts, int32_t* __restrict__ start,
     int64_t* __restrict__ poly_off, int64_t g_cap_polys, int64_t cap_polys, int64_t cap_verts, Counters* cnt) {
+  __shared__ int32_t s_off[kFinTile + 2];
+  __shared__ int32_t s_vb[kFinTile + 1];
+  __shared__ int64_t s_p0;
+  __shared__ int32_t s_np;
   const int64_t F = counts_g[0], S = counts_g[1];
   const int64_t P0 = base[0], S0 = base[1];
   // nothing is written after an error in this or an earlier group (the
@@ -2880,19 +2903,44 @@ __global__ __launch_bounds__(256) void k_group_finish(
     if (blockIdx.x == 0 && threadIdx.x == 0) set_error(cnt, POLYLLA_ECAPACITY);
     return;
   }
+  for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < nm; m += (int64_t)gridDim.x * blockDim.x)
+    poly_off[m] = P0 + poly_g[m];
+  const int64_t k0 = (int64_t)blockIdx.x * kFinTile;
+  if (k0 >= S) return;
+  const int64_t k1 = min(S, k0 + kFinTile);
+  if (threadIdx.x == 0) {
+    // polygons [p0, p1) cover slots [k0, k1): p0 is the polygon of slot k0
+    const int64_t p0 = first_above(off_g, F + 1, k0) - 1;
+    const int64_t p1 = first_above(off_g, F + 1, k1 - 1);
+    s_p0 = p0;
+    s_np = (int32_t)(p1 - p0);
+  }
+  __syncthreads();
+  const int64_t p0 = s_p0;
+  const int np = s_np;  // at most kFinTile (every polygon has a vertex)
   const int64_t h0 = he_off[0], v0 = vtx_off[0];
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < nm; m += stride) poly_off[m] = P0 + poly_g[m];
-  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= F) return;
-  int64_t m = mesh_of(poly_g, nm, p);
-  for (; p < F; p += stride) {
-    while (m + 1 < nm && poly_g[m + 1] <= p) ++m;
-    const int32_t vb = (int32_t)(vtx_off[m] - v0), hb = (int32_t)(he_off[m] - h0);
-    const int32_t a = off_g[p], b = off_g[p + 1];
-    offsets[P0 + p] = S0 + a;
-    if (start) start[P0 + p] = start_g[p] - hb;
-    for (int32_t k = a; k < b; ++k) verts[S0 + k] = verts_g[k] - vb;
+  for (int j = threadIdx.x; j <= np; j += 256) {
+    const int64_t p = p0 + j;
+    s_off[j] = off_g[p];
+    if (j < np) {
+      const int64_t m = mesh_of(poly_g, nm, p);
+      s_vb[j] = (int32_t)(vtx_off[m] - v0);
+      // each polygon's offset and start are written by the block of its first slot
+      if (off_g[p] >= k0) {
+        offsets[P0 + p] = S0 + off_g[p];
+        if (start) start[P0 + p] = start_g[p] - (int32_t)(he_off[m] - h0);
+      }
+    }
+  }
+  __syncthreads();
+  for (int64_t k = k0 + threadIdx.x; k < k1; k += 256) {
+    int lo = 0, hi = np;  // last polygon j with s_off[j] <= k
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (s_off[mid] <= k) lo = mid;
+      else hi = mid;
+    }
+    verts[S0 + k] = verts_g[k] - s_vb[lo];
   }
 }
 

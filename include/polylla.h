@@ -82,6 +82,7 @@ extern "C" {
 #define POLYLLA_EHIP (-6)      /* a HIP runtime call failed */
 #define POLYLLA_EDEGEN (-7)    /* walk bound exceeded: input not a valid triangulation */
 #define POLYLLA_EINTERNAL (-8) /* a device-wide scan did not complete (library bug) */
+#define POLYLLA_ETOOBIG (-9)   /* mesh larger than polylla_mesh_noalloc takes */
 
 /* label bits */
 #define POLYLLA_LONGEST 1u
@@ -152,6 +153,21 @@ int polylla_repair(polylla_ctx *ctx, const polylla_tri *tri, polylla_labels *lab
  * (then labels live in context scratch). Same result as the three calls. */
 int polylla_mesh(polylla_ctx *ctx, const polylla_tri *tri, polylla_labels *labels,
                  polylla_polys *out, hipStream_t stream);
+
+/* polylla_mesh for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same result as polylla_mesh (same kernels) with all scratch in a static
+ * device array of the library (64 MiB per GPU, held from the library's load
+ * until the process ends) instead of the context's scratch. The call itself
+ * allocates nothing; `ctx` supplies the device, the counters read by
+ * polylla_status, the tuning parameters and its second stream. Meshes of up
+ * to 262144 triangles and 262144 vertices; larger ones return POLYLLA_ETOOBIG
+ * at once. `labels` may be NULL (labels then live in the static array too).
+ * Every call on a GPU shares that GPU's array and it keeps the last call's
+ * contents, so calls that overlap on one GPU (other streams or contexts)
+ * race; order them. Event profiling is off during the call. */
+int polylla_mesh_noalloc(polylla_ctx *ctx, const polylla_tri *tri, polylla_labels *labels, polylla_polys *out,
+                         hipStream_t stream);
 
 /* A batch of independent triangulations stored one after another (CSR of
  * meshes, each mesh in the layout of polylla_tri). Mesh m owns vertices

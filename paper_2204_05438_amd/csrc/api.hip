@@ -4,6 +4,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
+#include <type_traits>
 #include <vector>
 
 #include "common.h"
@@ -58,15 +60,33 @@ __global__ void k_batch_close(const int64_t*, int64_t, int64_t*);
 
 using namespace polylla;
 
+// Scratch of polylla_mesh_noalloc: one static array per device, never
+// allocated by a call. Host code reaches it only through the device address
+// hipGetSymbolAddress returns for each device (taken once per device when a
+// context is created on it); the array's name itself is not a device address
+// in host code.
+constexpr size_t kNoallocBytes = (size_t)64 << 20;
+constexpr int64_t kNoallocMaxTri = 262144;  // triangles of the largest mesh it takes
+constexpr int64_t kNoallocMaxVtx = 262144;  // vertices
+constexpr int kNoallocWalkGrid = 64, kNoallocGrid64 = 256, kNoallocGrid1024 = 16;  // launch grids it is sized for
+constexpr int64_t kNoallocMemKm = 4096;     // store of the global-memory region path (triangles)
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) uint8_t scratch[kNoallocBytes];
+static std::mutex g_noalloc_mu;
+static void* g_noalloc_ptr[kMaxDevices] = {};
+
 // default number of declined short polygons up to which each gets a wave
 constexpr uint32_t kGenWaveMax = 2 * polylla::kBigGrid64;
 // most half-edges of one group of a batched call: keeps every int32 offset of
 // the scratch arrays (arena 6T, staging 5T plus chunk tails) below 2^31
 constexpr int64_t kGroupHeMax = ((int64_t)1 << 30) - ((int64_t)1 << 24);
 
-struct polylla_ctx {
-  int device = 0;
-  Counters* cnt = nullptr;
+// Device scratch of one call sequence: every array is a 256-byte aligned
+// slice of one block of device memory (the context's own allocation, or the
+// library's static array for polylla_mesh_noalloc). The caps are the sizes the
+// slices were carved for; the grids are the launch sizes whose chunk tails the
+// staging and arena capacities include.
+struct Scratch {
   int64_t cap_t = 0;  // triangles
   int64_t cap_v = 0;  // vertices
   uint8_t* lg = nullptr;
@@ -91,6 +111,15 @@ struct polylla_ctx {
   uint8_t* he_s = nullptr;
   uint8_t* tri_s = nullptr;
   uint8_t* vtx_s = nullptr;
+  int walk_grid = 0, grid64 = 0, grid1024 = 0;
+  void* block = nullptr;  // the owned allocation (null for a view)
+};
+
+struct polylla_ctx {
+  int device = 0;
+  Counters* cnt = nullptr;
+  Scratch own;         // scratch owned by the context (one device allocation)
+  Scratch* sc = &own;  // the scratch the calls use (own, or a view of the library's static array)
   Counters last{};
   bool last_batched = false;  // polylla_stats reports the sums over the groups of the last batched call
   // batched calls: a group's twin and origin with indices over the group, its
@@ -133,10 +162,6 @@ constexpr int64_t kScanTileHost = 2048;   // polygons per tile of k_scan_emit
 constexpr int64_t kWalkBlocks = 2048;     // persistent grid of k_walk
 constexpr int64_t kWalkWaves = kWalkBlocks * 4;
 constexpr int64_t kStageChunkHost = 4096; // staging ints a walk wave reserves at a time
-// unused tails of the staging and arena chunks of the region workgroups (two
-// launches of the one-wave instance, one of the 1024-thread instance)
-constexpr int64_t kBigStageTails = 2 * (int64_t)kBigGrid64 * kBigStageChunk64 + (int64_t)kBigGrid1024 * kBigStageChunk1024;
-constexpr int64_t kBigArenaTails = 2 * (int64_t)kBigGrid64 * kBigArenaChunk64 + (int64_t)kBigGrid1024 * kBigArenaChunk1024;
 
 enum KernelId {
   KR_RESET, KR_LONGEST, KR_LABEL, KR_COMPACT, KR_PACK, KR_WALK, KR_GENERAL, KR_BIG, KR_HUGE, KR_SCAN, KR_VALIDATE,
@@ -187,23 +212,65 @@ void dfree(T** p) {
 }
 
 void free_scratch(polylla_ctx* c) {
-  dfree(&c->lg);
-  dfree(&c->wk);
-  dfree(&c->seeds);
-  dfree(&c->deferred);
-  dfree(&c->huge);
-  dfree(&c->lane);
-  dfree(&c->mem_store);
-  dfree(&c->over);
-  dfree(&c->rest);
-  dfree(&c->poly_arrays);
-  dfree(&c->stage);
-  dfree(&c->arena);
-  dfree(&c->status);
-  dfree(&c->he_s);
-  dfree(&c->tri_s);
-  dfree(&c->vtx_s);
-  c->cap_t = c->cap_v = 0;
+  if (c->own.block) (void)hipFree(c->own.block);
+  c->own = Scratch{};
+}
+
+// Staging and arena chunk tails of the launch grids (the walk's waves, two
+// launches of the one-wave region kernel, one of the 1024-thread kernel).
+int64_t stage_tails(int walk_grid, int g64, int g1024) {
+  return 4 * (int64_t)walk_grid * kStageChunkHost + 2 * (int64_t)g64 * kBigStageChunk64 +
+         (int64_t)g1024 * kBigStageChunk1024 + ((int64_t)1 << 20);
+}
+int64_t arena_tails(int g64, int g1024) {
+  return 2 * (int64_t)g64 * kBigArenaChunk64 + (int64_t)g1024 * kBigArenaChunk1024 + 4096;
+}
+
+// Carves the scratch arrays for meshes of up to T triangles and V vertices
+// out of `base` (every slice 256-byte aligned) and returns the bytes used;
+// with base == nullptr only the size is computed. Offsets into the staging
+// and arena arrays stay below 2^31.
+size_t carve(Scratch& S, uint8_t* base, int64_t T, int64_t V, int walk_grid, int g64, int g1024,
+             int64_t mem_km_max) {
+  size_t off = 0;
+  auto take = [&](auto*& ptr, int64_t n) {
+    using E = std::remove_reference_t<decltype(*ptr)>;
+    off = (off + 255) & ~(size_t)255;
+    ptr = base ? reinterpret_cast<E*>(base + off) : nullptr;
+    off += sizeof(E) * (size_t)std::max<int64_t>(n, 1);
+  };
+  S.cap_t = T;
+  S.cap_v = V;
+  S.walk_grid = walk_grid;
+  S.grid64 = g64;
+  S.grid1024 = g1024;
+  const int64_t ntiles = (T + kTile - 1) / kTile + 1;
+  // polygon vertices (<= 3T) and the general paths' staging, plus chunk tails
+  S.stage_cap = std::min<int64_t>(5 * T + stage_tails(walk_grid, g64, g1024), ((int64_t)1 << 31) - 1);
+  S.arena_cap = std::min<int64_t>(6 * T + arena_tails(g64, g1024), ((int64_t)1 << 31) - 1);
+  S.n_status = 2 * ntiles;
+  S.huge_cap = 3 * T / 32 + 64;
+  S.lane_cap = 3 * T / 32 + 64;
+  S.over_cap = T / 32 + 64;
+  S.rest_cap = T / 3 + 64;
+  S.mem_km = std::min<int64_t>(T, mem_km_max);
+  take(S.status, S.n_status);
+  take(S.lg, T);
+  take(S.wk, 3 * T);
+  take(S.seeds, T);
+  take(S.deferred, T);
+  take(S.huge, S.huge_cap);
+  take(S.lane, S.lane_cap);
+  take(S.mem_store, kMemGrid * mem_words(S.mem_km));
+  take(S.over, S.over_cap);
+  take(S.rest, S.rest_cap);
+  take(S.poly_arrays, 5 * T);
+  take(S.stage, S.stage_cap);
+  take(S.arena, S.arena_cap);
+  take(S.he_s, 3 * T);
+  take(S.tri_s, T);
+  take(S.vtx_s, V);
+  return (off + 255) & ~(size_t)255;
 }
 
 void free_group(polylla_ctx* c) {
@@ -239,41 +306,31 @@ int ensure_group(polylla_ctx* c, int64_t n_he, int64_t n_m) {
 }
 
 int ensure(polylla_ctx* c, int64_t nt, int64_t nv) {
-  if (nt <= c->cap_t && nv <= c->cap_v && c->lg) return POLYLLA_OK;
-  int64_t T = std::max(nt, c->cap_t), V = std::max(nv, c->cap_v);
+  if (c->sc != &c->own) return POLYLLA_EINTERNAL;  // a no-alloc call never reaches here
+  if (nt <= c->own.cap_t && nv <= c->own.cap_v && c->own.block) return POLYLLA_OK;
+  int64_t T = std::max(nt, c->own.cap_t), V = std::max(nv, c->own.cap_v);
   if (hipSetDevice(c->device) != hipSuccess) return POLYLLA_EHIP;
   (void)hipDeviceSynchronize();
   free_scratch(c);
   T = std::max<int64_t>(T, 1024);
   V = std::max<int64_t>(V, 1024);
-  int rc = POLYLLA_OK;
-  const int64_t ntiles = (T + kTile - 1) / kTile + 1;
-  // polygon vertices (<= 3T) and the general paths' staging, plus the unused
-  // tail of the last staging chunk of every walk wave. Offsets stay int32.
-  c->stage_cap = std::min<int64_t>(5 * T + kWalkWaves * kStageChunkHost + kBigStageTails + ((int64_t)1 << 20),
-                                   ((int64_t)1 << 31) - 1);
-  c->arena_cap = std::min<int64_t>(6 * T + kBigArenaTails + 4096, ((int64_t)1 << 31) - 1);  // offsets stay int32
-  c->n_status = 2 * ntiles;
-  if ((rc = dalloc(&c->lg, T)) || (rc = dalloc(&c->wk, 3 * T)) || (rc = dalloc(&c->seeds, T)) || (rc = dalloc(&c->deferred, T)) || (rc = dalloc(&c->huge, c->huge_cap = 3 * T / 32 + 64)) ||
-      (rc = dalloc(&c->lane, c->lane_cap = 3 * T / 32 + 64)) ||
-      (rc = dalloc(&c->mem_store, kMemGrid * mem_words(c->mem_km = std::min<int64_t>(T, kMemRegionMax)))) ||
-      (rc = dalloc(&c->over, c->over_cap = T / 32 + 64)) ||
-      (rc = dalloc(&c->rest, c->rest_cap = T / 3 + 64)) ||
-      (rc = dalloc(&c->poly_arrays, 5 * T)) || (rc = dalloc(&c->stage, c->stage_cap)) ||
-      (rc = dalloc(&c->arena, c->arena_cap)) || (rc = dalloc(&c->status, c->n_status)) ||
-      (rc = dalloc(&c->he_s, 3 * T)) || (rc = dalloc(&c->tri_s, T)) || (rc = dalloc(&c->vtx_s, V))) {
-    free_scratch(c);
-    return rc;
+  Scratch S;
+  const size_t bytes = carve(S, nullptr, T, V, (int)kWalkBlocks, kBigGrid64, kBigGrid1024, kMemRegionMax);
+  void* block = nullptr;
+  if (hipMalloc(&block, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return POLYLLA_ENOMEM;
   }
-  c->cap_t = T;
-  c->cap_v = V;
+  carve(S, static_cast<uint8_t*>(block), T, V, (int)kWalkBlocks, kBigGrid64, kBigGrid1024, kMemRegionMax);
+  S.block = block;
+  c->own = S;
   return POLYLLA_OK;
 }
 
 PolyState poly_state(polylla_ctx* c) {
   PolyState ps;
-  ps.rec = reinterpret_cast<int4*>(c->poly_arrays);
-  ps.prec = c->poly_arrays + 4 * c->cap_t;
+  ps.rec = reinterpret_cast<int4*>(c->sc->poly_arrays);
+  ps.prec = c->sc->poly_arrays + 4 * c->sc->cap_t;
   return ps;
 }
 
@@ -303,20 +360,20 @@ int grid_for(int64_t n, int64_t per_block, int64_t cap) {
 
 void reset(polylla_ctx* c, hipStream_t s, const int64_t* n_from, int keep = 0) {
   Prof p(c, s, KR_RESET);
-  hipLaunchKernelGGL(k_reset, dim3(grid_for(c->n_status, 256, 4096)), dim3(256), 0, s, c->cnt, c->status,
-                     c->n_status, n_from, keep);
+  hipLaunchKernelGGL(k_reset, dim3(grid_for(c->sc->n_status, 256, 4096)), dim3(256), 0, s, c->cnt, c->sc->status,
+                     c->sc->n_status, n_from, keep);
 }
 
 // Seed counts per label tile (first ntiles words of the status array) and
 // their sums per group of 64 tiles (the next ntiles / 64 + 1 words, zeroed by
 // k_reset).
-uint32_t* tile_counts(polylla_ctx* c) { return reinterpret_cast<uint32_t*>(c->status); }
+uint32_t* tile_counts(polylla_ctx* c) { return reinterpret_cast<uint32_t*>(c->sc->status); }
 uint32_t* tile_groups(polylla_ctx* c, int64_t T) { return tile_counts(c) + (T + kTile - 1) / kTile; }
 
 void launch_seeds(polylla_ctx* c, int64_t T, const uint8_t* tri, hipStream_t s) {
   Prof p(c, s, KR_SEEDS);
   hipLaunchKernelGGL(k_seeds, dim3((T + kTile - 1) / kTile), dim3(256), 0, s, T, tri, tile_counts(c),
-                     tile_groups(c, T), c->seeds, c->cnt);
+                     tile_groups(c, T), c->sc->seeds, c->cnt);
 }
 
 int run_label(polylla_ctx* c, const polylla_tri* t, uint8_t* he, uint8_t* tri, uint8_t* vtx, hipStream_t s) {
@@ -325,15 +382,15 @@ int run_label(polylla_ctx* c, const polylla_tri* t, uint8_t* he, uint8_t* tri, u
     Prof p(c, s, KR_LONGEST);
     // two triangles per thread (and one vertex to clear)
     hipLaunchKernelGGL(k_longest, dim3(grid_for(std::max((T + 1) / 2, t->n_vertices), 256, 1 << 20)), dim3(256), 0,
-                       s, T, t->n_vertices, t->xy, t->origin, t->twin, c->lg, vtx, c->cnt);
+                       s, T, t->n_vertices, t->xy, t->origin, t->twin, c->sc->lg, vtx, c->cnt);
   }
   if (T > 0) {
     Prof p(c, s, KR_LABEL);
     // 16-byte loads of twin and 4-byte label stores need aligned arrays
     const bool vec = ((uintptr_t)t->twin % 16 == 0) && ((uintptr_t)t->origin % 16 == 0) && ((uintptr_t)he % 4 == 0) &&
                      ((uintptr_t)tri % 4 == 0);
-    hipLaunchKernelGGL(k_label<true>, dim3((T + kTile - 1) / kTile), dim3(256), 0, s, T, t->twin, c->lg, he, tri,
-                       t->origin, c->wk, tile_counts(c), tile_groups(c, T), c->cnt, vec);
+    hipLaunchKernelGGL(k_label<true>, dim3((T + kTile - 1) / kTile), dim3(256), 0, s, T, t->twin, c->sc->lg, he, tri,
+                       t->origin, c->sc->wk, tile_counts(c), tile_groups(c, T), c->cnt, vec);
   }
   if (T > 0) launch_seeds(c, T, tri, s);
   return launched();
@@ -348,13 +405,13 @@ int run_build(polylla_ctx* c, const polylla_tri* t, const int32_t* list, bool fr
   PolyState ps = poly_state(c);
   {
     Prof p(c, s, KR_WALK);
-    const int gw = c->walk_blocks;  // persistent: waves take seeds from per-XCD queues
+    const int gw = std::min(c->walk_blocks, c->sc->walk_grid);  // persistent: waves take seeds from per-XCD queues
     if (from_seeds)
-      hipLaunchKernelGGL(k_walk<true>, dim3(gw), dim3(256), 0, s, list, nhe, c->wk, c->stage,
-                         c->stage_cap, ps, c->deferred, c->cap_t, c->walk_cap, c->cnt);
+      hipLaunchKernelGGL(k_walk<true>, dim3(gw), dim3(256), 0, s, list, nhe, c->sc->wk, c->sc->stage,
+                         c->sc->stage_cap, ps, c->sc->deferred, c->sc->cap_t, c->walk_cap, c->cnt);
     else
-      hipLaunchKernelGGL(k_walk<false>, dim3(gw), dim3(256), 0, s, list, nhe, c->wk, c->stage,
-                         c->stage_cap, ps, c->deferred, c->cap_t, c->walk_cap, c->cnt);
+      hipLaunchKernelGGL(k_walk<false>, dim3(gw), dim3(256), 0, s, list, nhe, c->sc->wk, c->sc->stage,
+                         c->sc->stage_cap, ps, c->sc->deferred, c->sc->cap_t, c->walk_cap, c->cnt);
   }
   // the long regions (workgroup kernel, side stream) and the short ones
   // (per-lane kernel, caller's stream) in parallel
@@ -367,33 +424,33 @@ int run_build(polylla_ctx* c, const polylla_tri* t, const int32_t* list, bool fr
   {
     Prof p(c, c->side, KR_BIG);
     Counters* k = c->cnt;
-    const int gm = kBigGrid64;  // persistent: one-wave blocks take regions round-robin
+    const int gm = c->sc->grid64;  // persistent: one-wave blocks take regions round-robin
     if (repair)
       hipLaunchKernelGGL((k_general_big<true, 64, 128, 128, 8>), dim3(gm), dim3(64), 0, c->side, list, from_seeds, nhe,
-                         t->n_vertices, t->twin, t->origin, c->wk, he, vtx, c->stage, c->stage_cap, c->arena,
-                         c->arena_cap, ps, c->deferred, true, c->cap_t, &k->n_big, &k->big_ticket, c->over,
-                         c->over_cap, &k->n_over, nullptr, (int64_t)0, &k->n_big, few, UINT32_MAX, 128, k);
+                         t->n_vertices, t->twin, t->origin, c->sc->wk, he, vtx, c->sc->stage, c->sc->stage_cap, c->sc->arena,
+                         c->sc->arena_cap, ps, c->sc->deferred, true, c->sc->cap_t, &k->n_big, &k->big_ticket, c->sc->over,
+                         c->sc->over_cap, &k->n_over, nullptr, (int64_t)0, &k->n_big, few, UINT32_MAX, 128, k);
     else
       hipLaunchKernelGGL((k_general_big<false, 64, 128, 128, 8>), dim3(gm), dim3(64), 0, c->side, list, from_seeds,
-                         nhe, t->n_vertices, t->twin, t->origin, c->wk, he, vtx, c->stage, c->stage_cap, c->arena,
-                         c->arena_cap, ps, c->deferred, true, c->cap_t, &k->n_big, &k->big_ticket, c->over,
-                         c->over_cap, &k->n_over, nullptr, (int64_t)0, &k->n_big, few, UINT32_MAX, 128, k);
+                         nhe, t->n_vertices, t->twin, t->origin, c->sc->wk, he, vtx, c->sc->stage, c->sc->stage_cap, c->sc->arena,
+                         c->sc->arena_cap, ps, c->sc->deferred, true, c->sc->cap_t, &k->n_big, &k->big_ticket, c->sc->over,
+                         c->sc->over_cap, &k->n_over, nullptr, (int64_t)0, &k->n_big, few, UINT32_MAX, 128, k);
   }
   {
     Prof p(c, c->side, KR_BIGW);
     Counters* k = c->cnt;
-    const int gb = kBigGrid1024;  // persistent: blocks take the remaining long regions by ticket
+    const int gb = c->sc->grid1024;  // persistent: blocks take the remaining long regions by ticket
     if (repair)
       hipLaunchKernelGGL((k_general_big<true, 1024, 4096, 4096, 13>), dim3(gb), dim3(1024), 0, c->side, list,
-                         from_seeds, nhe, t->n_vertices, t->twin, t->origin, c->wk, he, vtx, c->stage, c->stage_cap,
-                         c->arena, c->arena_cap, ps, c->over, false, (int64_t)0, &k->n_over, &k->over_ticket, c->huge,
-                         c->huge_cap, &k->n_fallback, c->deferred, c->cap_t, &k->n_big, few, UINT32_MAX,
+                         from_seeds, nhe, t->n_vertices, t->twin, t->origin, c->sc->wk, he, vtx, c->sc->stage, c->sc->stage_cap,
+                         c->sc->arena, c->sc->arena_cap, ps, c->sc->over, false, (int64_t)0, &k->n_over, &k->over_ticket, c->sc->huge,
+                         c->sc->huge_cap, &k->n_fallback, c->sc->deferred, c->sc->cap_t, &k->n_big, few, UINT32_MAX,
                          c->lds_max, k);
     else
       hipLaunchKernelGGL((k_general_big<false, 1024, 4096, 4096, 13>), dim3(gb), dim3(1024), 0, c->side, list,
-                         from_seeds, nhe, t->n_vertices, t->twin, t->origin, c->wk, he, vtx, c->stage, c->stage_cap,
-                         c->arena, c->arena_cap, ps, c->over, false, (int64_t)0, &k->n_over, &k->over_ticket, c->huge,
-                         c->huge_cap, &k->n_fallback, c->deferred, c->cap_t, &k->n_big, few, UINT32_MAX,
+                         from_seeds, nhe, t->n_vertices, t->twin, t->origin, c->sc->wk, he, vtx, c->sc->stage, c->sc->stage_cap,
+                         c->sc->arena, c->sc->arena_cap, ps, c->sc->over, false, (int64_t)0, &k->n_over, &k->over_ticket, c->sc->huge,
+                         c->sc->huge_cap, &k->n_fallback, c->sc->deferred, c->sc->cap_t, &k->n_big, few, UINT32_MAX,
                          c->lds_max, k);
   }
   if (hipEventRecord(c->join, c->side) != hipSuccess) return POLYLLA_EHIP;
@@ -402,11 +459,11 @@ int run_build(polylla_ctx* c, const polylla_tri* t, const int32_t* list, bool fr
     const int gt = 2048;  // one lane per short polygon with a repeat, grid-stride
     if (repair)
       hipLaunchKernelGGL(k_tip<true>, dim3(gt), dim3(64), 0, s, nhe, t->n_vertices, t->twin, t->origin, he, vtx,
-                         c->stage, c->stage_cap, c->arena, c->arena_cap, ps, c->deferred, c->rest, c->rest_cap,
+                         c->sc->stage, c->sc->stage_cap, c->sc->arena, c->sc->arena_cap, ps, c->sc->deferred, c->sc->rest, c->sc->rest_cap,
                          c->cnt);
     else
       hipLaunchKernelGGL(k_tip<false>, dim3(gt), dim3(64), 0, s, nhe, t->n_vertices, t->twin, t->origin, he, vtx,
-                         c->stage, c->stage_cap, c->arena, c->arena_cap, ps, c->deferred, c->rest, c->rest_cap,
+                         c->sc->stage, c->sc->stage_cap, c->sc->arena, c->sc->arena_cap, ps, c->sc->deferred, c->sc->rest, c->sc->rest_cap,
                          c->cnt);
   }
   // short polygons the tip path declines: up to gen_wave_max of them one wave
@@ -416,14 +473,14 @@ int run_build(polylla_ctx* c, const polylla_tri* t, const int32_t* list, bool fr
     Prof p(c, s, KR_GENW);
     Counters* k = c->cnt;
     if (repair)
-      hipLaunchKernelGGL((k_general_big<true, 64, 128, 128, 8>), dim3(kBigGrid64), dim3(64), 0, s, list, from_seeds,
-                         nhe, t->n_vertices, t->twin, t->origin, c->wk, he, vtx, c->stage, c->stage_cap, c->arena,
-                         c->arena_cap, ps, c->rest, false, (int64_t)0, &k->n_gen, nullptr, c->huge, c->huge_cap,
+      hipLaunchKernelGGL((k_general_big<true, 64, 128, 128, 8>), dim3(c->sc->grid64), dim3(64), 0, s, list, from_seeds,
+                         nhe, t->n_vertices, t->twin, t->origin, c->sc->wk, he, vtx, c->sc->stage, c->sc->stage_cap, c->sc->arena,
+                         c->sc->arena_cap, ps, c->sc->rest, false, (int64_t)0, &k->n_gen, nullptr, c->sc->huge, c->sc->huge_cap,
                          &k->n_fallback, nullptr, (int64_t)0, nullptr, 0u, c->gen_wave_max, 128, k);
     else
-      hipLaunchKernelGGL((k_general_big<false, 64, 128, 128, 8>), dim3(kBigGrid64), dim3(64), 0, s, list, from_seeds,
-                         nhe, t->n_vertices, t->twin, t->origin, c->wk, he, vtx, c->stage, c->stage_cap, c->arena,
-                         c->arena_cap, ps, c->rest, false, (int64_t)0, &k->n_gen, nullptr, c->huge, c->huge_cap,
+      hipLaunchKernelGGL((k_general_big<false, 64, 128, 128, 8>), dim3(c->sc->grid64), dim3(64), 0, s, list, from_seeds,
+                         nhe, t->n_vertices, t->twin, t->origin, c->sc->wk, he, vtx, c->sc->stage, c->sc->stage_cap, c->sc->arena,
+                         c->sc->arena_cap, ps, c->sc->rest, false, (int64_t)0, &k->n_gen, nullptr, c->sc->huge, c->sc->huge_cap,
                          &k->n_fallback, nullptr, (int64_t)0, nullptr, 0u, c->gen_wave_max, 128, k);
   }
   {
@@ -431,36 +488,36 @@ int run_build(polylla_ctx* c, const polylla_tri* t, const int32_t* list, bool fr
     const int gg = 2048;
     if (repair)
       hipLaunchKernelGGL(k_general_small<true>, dim3(gg), dim3(64), 0, s, list, from_seeds, nhe, t->n_vertices,
-                         t->twin, t->origin, c->wk, he, vtx, c->stage, c->stage_cap, c->arena, c->arena_cap, ps,
-                         c->rest, &c->cnt->n_gen, c->gen_wave_max, c->cnt);
+                         t->twin, t->origin, c->sc->wk, he, vtx, c->sc->stage, c->sc->stage_cap, c->sc->arena, c->sc->arena_cap, ps,
+                         c->sc->rest, &c->cnt->n_gen, c->gen_wave_max, c->cnt);
     else
       hipLaunchKernelGGL(k_general_small<false>, dim3(gg), dim3(64), 0, s, list, from_seeds, nhe, t->n_vertices,
-                         t->twin, t->origin, c->wk, he, vtx, c->stage, c->stage_cap, c->arena, c->arena_cap, ps,
-                         c->rest, &c->cnt->n_gen, c->gen_wave_max, c->cnt);
+                         t->twin, t->origin, c->sc->wk, he, vtx, c->sc->stage, c->sc->stage_cap, c->sc->arena, c->sc->arena_cap, ps,
+                         c->sc->rest, &c->cnt->n_gen, c->gen_wave_max, c->cnt);
   }
   if (hipStreamWaitEvent(s, c->join, 0) != hipSuccess) return POLYLLA_EHIP;
   {
     Prof p(c, s, KR_HUGE);
     // regions beyond the LDS instance: a workgroup each with the region in
     // global memory; beyond that, one lane each
-    const int32_t kcap = (int32_t)std::min<int64_t>(c->mem_km, c->mem_max);
+    const int32_t kcap = (int32_t)std::min<int64_t>(c->sc->mem_km, c->mem_max);
     const int32_t lcap = 2 * kcap;
     if (repair)
       hipLaunchKernelGGL(k_general_huge<true>, dim3(kMemGrid), dim3(1024), 0, s, list, from_seeds, nhe,
-                         t->n_vertices, t->twin, t->origin, c->wk, he, vtx, c->stage, c->stage_cap, c->arena,
-                         c->arena_cap, ps, c->huge, c->huge_cap, c->lane, c->lane_cap, c->mem_store, c->mem_km,
+                         t->n_vertices, t->twin, t->origin, c->sc->wk, he, vtx, c->sc->stage, c->sc->stage_cap, c->sc->arena,
+                         c->sc->arena_cap, ps, c->sc->huge, c->sc->huge_cap, c->sc->lane, c->sc->lane_cap, c->sc->mem_store, c->sc->mem_km,
                          kcap, lcap, c->cnt);
     else
       hipLaunchKernelGGL(k_general_huge<false>, dim3(kMemGrid), dim3(1024), 0, s, list, from_seeds, nhe,
-                         t->n_vertices, t->twin, t->origin, c->wk, he, vtx, c->stage, c->stage_cap, c->arena,
-                         c->arena_cap, ps, c->huge, c->huge_cap, c->lane, c->lane_cap, c->mem_store, c->mem_km,
+                         t->n_vertices, t->twin, t->origin, c->sc->wk, he, vtx, c->sc->stage, c->sc->stage_cap, c->sc->arena,
+                         c->sc->arena_cap, ps, c->sc->huge, c->sc->huge_cap, c->sc->lane, c->sc->lane_cap, c->sc->mem_store, c->sc->mem_km,
                          kcap, lcap, c->cnt);
   }
   {
     Prof p(c, s, KR_SCAN);
     const int64_t ntiles = (T + kScanTileHost - 1) / kScanTileHost + 1;
-    hipLaunchKernelGGL(k_scan_emit, dim3(ntiles), dim3(256), 0, s, ps, c->status + c->n_status / 2, c->stage,
-                       c->arena, out->offsets, out->verts, out->start, out->counts, out->cap_polys,
+    hipLaunchKernelGGL(k_scan_emit, dim3(ntiles), dim3(256), 0, s, ps, c->sc->status + c->sc->n_status / 2, c->sc->stage,
+                       c->sc->arena, out->offsets, out->verts, out->start, out->counts, out->cap_polys,
                        out->cap_verts, c->cnt);
   }
   return launched();
@@ -470,13 +527,13 @@ int run_build(polylla_ctx* c, const polylla_tri* t, const int32_t* list, bool fr
 // keep != 0 keeps the error word and batch sums of earlier groups.
 int mesh_run(polylla_ctx* c, const polylla_tri* t, uint8_t* he, uint8_t* tri, uint8_t* vtx, polylla_polys* out,
              hipStream_t s, int keep) {
-  he = he ? he : c->he_s;
-  tri = tri ? tri : c->tri_s;
-  vtx = vtx ? vtx : c->vtx_s;
+  he = he ? he : c->sc->he_s;
+  tri = tri ? tri : c->sc->tri_s;
+  vtx = vtx ? vtx : c->sc->vtx_s;
   reset(c, s, nullptr, keep);
   int rc = run_label(c, t, he, tri, vtx, s);
   if (rc) return rc;
-  return run_build(c, t, c->seeds, true, true, he, vtx, out, s);
+  return run_build(c, t, c->sc->seeds, true, true, he, vtx, out, s);
 }
 
 }  // namespace
@@ -489,6 +546,19 @@ int polylla_ctx_create(polylla_ctx** out, int device) {
   int n = 0;
   if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return POLYLLA_EINVAL;
   if (hipSetDevice(device) != hipSuccess) return POLYLLA_EHIP;
+  if (device >= kMaxDevices) return POLYLLA_EINVAL;
+  {
+    // the device address of this device's no-alloc scratch, once per device
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (!g_noalloc_ptr[device]) {
+      void* p = nullptr;
+      if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+        (void)hipGetLastError();
+        return POLYLLA_EHIP;
+      }
+      g_noalloc_ptr[device] = p;
+    }
+  }
   polylla_ctx* c = new polylla_ctx();
   c->device = device;
   if (dalloc(&c->cnt, 1)) {
@@ -563,16 +633,16 @@ int polylla_build(polylla_ctx* c, const polylla_tri* t, polylla_labels* l, polyl
   reset(c, s, nullptr);
   if (T > 0) {
     Prof p(c, s, KR_COMPACT);
-    hipLaunchKernelGGL(k_label<false>, dim3((T + kTile - 1) / kTile), dim3(256), 0, s, T, t->twin, c->lg, l->he,
-                       l->tri, t->origin, c->wk, tile_counts(c), tile_groups(c, T), c->cnt, false);
+    hipLaunchKernelGGL(k_label<false>, dim3((T + kTile - 1) / kTile), dim3(256), 0, s, T, t->twin, c->sc->lg, l->he,
+                       l->tri, t->origin, c->sc->wk, tile_counts(c), tile_groups(c, T), c->cnt, false);
   }
   if (T > 0) launch_seeds(c, T, l->tri, s);
   if (T > 0) {
     Prof p(c, s, KR_PACK);
     hipLaunchKernelGGL(k_pack_walk, dim3(grid_for(3 * T, 256, 1 << 16)), dim3(256), 0, s, 3 * T, l->he, t->twin,
-                       t->origin, c->wk);
+                       t->origin, c->sc->wk);
   }
-  return run_build(c, t, c->seeds, true, false, l->he, l->vtx, out, s);
+  return run_build(c, t, c->sc->seeds, true, false, l->he, l->vtx, out, s);
 }
 
 int polylla_repair(polylla_ctx* c, const polylla_tri* t, polylla_labels* l, const polylla_polys* in,
@@ -589,7 +659,7 @@ int polylla_repair(polylla_ctx* c, const polylla_tri* t, polylla_labels* l, cons
   if (T > 0) {
     Prof p(c, s, KR_PACK);
     hipLaunchKernelGGL(k_pack_walk, dim3(grid_for(3 * T, 256, 1 << 16)), dim3(256), 0, s, 3 * T, l->he, t->twin,
-                       t->origin, c->wk);
+                       t->origin, c->sc->wk);
   }
   return run_build(c, t, in->start, false, true, l->he, l->vtx, out, s);
 }
@@ -604,6 +674,41 @@ int polylla_mesh(polylla_ctx* c, const polylla_tri* t, polylla_labels* l, polyll
   if (hipSetDevice(c->device) != hipSuccess) return POLYLLA_EHIP;
   c->last_batched = false;
   return mesh_run(c, t, l ? l->he : nullptr, l ? l->tri : nullptr, l ? l->vtx : nullptr, out, s, 0);
+}
+
+int polylla_mesh_noalloc(polylla_ctx* c, const polylla_tri* t, polylla_labels* l, polylla_polys* out,
+                         hipStream_t s) {
+  if (!c) return POLYLLA_EINVAL;
+  int rc = check_tri(t);
+  if (rc) return rc;
+  if ((rc = check_polys(out, false))) return rc;
+  const int64_t T = t->n_halfedges / 3;
+  if (T > kNoallocMaxTri || t->n_vertices > kNoallocMaxVtx) return POLYLLA_ETOOBIG;
+  void* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    base = g_noalloc_ptr[c->device];
+  }
+  if (!base) return POLYLLA_EHIP;
+  // the scratch arrays as slices of this device's static array (the same
+  // layout as a context's own scratch, sized for this mesh and the smaller
+  // launch grids used here)
+  Scratch view;
+  const int64_t Tv = std::max<int64_t>(T, 1024), Vv = std::max<int64_t>(t->n_vertices, 1024);
+  if (carve(view, nullptr, Tv, Vv, kNoallocWalkGrid, kNoallocGrid64, kNoallocGrid1024, kNoallocMemKm) >
+      kNoallocBytes)
+    return POLYLLA_ETOOBIG;
+  carve(view, static_cast<uint8_t*>(base), Tv, Vv, kNoallocWalkGrid, kNoallocGrid64, kNoallocGrid1024,
+        kNoallocMemKm);
+  if (hipSetDevice(c->device) != hipSuccess) return POLYLLA_EHIP;
+  const int prof = c->prof;  // event records would grow a host vector
+  c->prof = POLYLLA_PROFILE_OFF;
+  c->sc = &view;
+  c->last_batched = false;
+  rc = mesh_run(c, t, l ? l->he : nullptr, l ? l->tri : nullptr, l ? l->vtx : nullptr, out, s, 0);
+  c->sc = &c->own;
+  c->prof = prof;
+  return rc;
 }
 
 int polylla_mesh_batched(polylla_ctx* c, const polylla_batch* b, polylla_labels* l, polylla_batch_out* out,
@@ -820,6 +925,7 @@ const char* polylla_strerror(int code) {
     case POLYLLA_EHIP: return "HIP runtime error";
     case POLYLLA_EDEGEN: return "walk bound exceeded (not a valid triangulation)";
     case POLYLLA_EINTERNAL: return "internal error: device scan did not complete";
+    case POLYLLA_ETOOBIG: return "mesh larger than the no-alloc scratch (262144 triangles, 262144 vertices)";
     default: return "unknown error";
   }
 }

@@ -15,7 +15,7 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpolylla.so")
 
-OK, EINVAL, ELAYOUT, ETOPO, ECAPACITY, ENOMEM, EHIP, EDEGEN, EINTERNAL = 0, -1, -2, -3, -4, -5, -6, -7, -8
+OK, EINVAL, ELAYOUT, ETOPO, ECAPACITY, ENOMEM, EHIP, EDEGEN, EINTERNAL, ETOOBIG = 0, -1, -2, -3, -4, -5, -6, -7, -8, -9
 LONGEST, FRONTIER, TERMINAL, BORDER, BARRIER, REPAIRED = 1, 2, 4, 8, 16, 32
 SEED, TIP = 1, 1
 PARAM_WALK_CAP = 1
@@ -82,6 +82,8 @@ def load() -> ctypes.CDLL:
         lib.polylla_repair.argtypes = [P, ctypes.POINTER(_Tri), ctypes.POINTER(_Labels), ctypes.POINTER(_Polys),
                                        ctypes.POINTER(_Polys), P]
         lib.polylla_mesh.argtypes = [P, ctypes.POINTER(_Tri), ctypes.POINTER(_Labels), ctypes.POINTER(_Polys), P]
+        lib.polylla_mesh_noalloc.argtypes = [P, ctypes.POINTER(_Tri), ctypes.POINTER(_Labels),
+                                             ctypes.POINTER(_Polys), P]
         lib.polylla_validate.argtypes = [P, ctypes.POINTER(_Tri), P]
         lib.polylla_mesh_batched.argtypes = [P, ctypes.POINTER(_Batch), ctypes.POINTER(_Labels),
                                              ctypes.POINTER(_BatchOut), P]
@@ -94,7 +96,7 @@ def load() -> ctypes.CDLL:
         lib.polylla_strerror.argtypes = [ctypes.c_int]
         lib.polylla_strerror.restype = ctypes.c_char_p
         for f in ("polylla_ctx_create", "polylla_reserve", "polylla_reserve_batch", "polylla_label", "polylla_build", "polylla_repair",
-                  "polylla_mesh", "polylla_mesh_batched", "polylla_validate", "polylla_status",
+                  "polylla_mesh", "polylla_mesh_noalloc", "polylla_mesh_batched", "polylla_validate", "polylla_status",
                   "polylla_stats", "polylla_set_param", "polylla_profile", "polylla_profile_read"):
             getattr(lib, f).restype = ctypes.c_int
         _lib = lib
@@ -354,6 +356,15 @@ class Context:
         t, o = tri.c(), out.c()
         lp = ctypes.byref(labels.c()) if labels is not None else None
         _check(load().polylla_mesh(self._h, ctypes.byref(t), lp, ctypes.byref(o), self._stream()), "polylla_mesh")
+        return out
+
+    def mesh_noalloc(self, tri: Tri, labels: Labels | None, out: Polys) -> Polys:
+        """polylla_mesh_noalloc: scratch in the library's static array; `out`
+        must be given (nothing is allocated)."""
+        t, o = tri.c(), out.c()
+        lp = ctypes.byref(labels.c()) if labels is not None else None
+        _check(load().polylla_mesh_noalloc(self._h, ctypes.byref(t), lp, ctypes.byref(o), self._stream()),
+               "polylla_mesh_noalloc")
         return out
 
     def mesh_batched(self, batch: Batch, labels: Labels | None = None, out: BatchOut | None = None) -> BatchOut:

@@ -62,7 +62,7 @@ def test_binding_constants_match_header():
     pairs = {
         "OK": lib.OK, "EINVAL": lib.EINVAL, "ELAYOUT": lib.ELAYOUT, "ETOPO": lib.ETOPO,
         "ECAPACITY": lib.ECAPACITY, "ENOMEM": lib.ENOMEM, "EHIP": lib.EHIP, "EDEGEN": lib.EDEGEN,
-        "EINTERNAL": lib.EINTERNAL,
+        "EINTERNAL": lib.EINTERNAL, "ETOOBIG": lib.ETOOBIG,
         "LONGEST": lib.LONGEST, "FRONTIER": lib.FRONTIER, "TERMINAL": lib.TERMINAL, "BORDER": lib.BORDER,
         "BARRIER": lib.BARRIER, "REPAIRED": lib.REPAIRED, "SEED": lib.SEED, "TIP": lib.TIP,
         "PROFILE_OFF": lib.PROFILE_OFF, "PROFILE_ALL": lib.PROFILE_ALL, "PROFILE_WALK": lib.PROFILE_WALK,

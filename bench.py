@@ -283,11 +283,28 @@ def bench_single(args, pool, workload: str):
                    "paper_GBps": round(pb.get(k, 0) / (v / 1e6) / 1e9, 1),
                    "design_GBps": round(db.get(k, 0) / (v / 1e6) / 1e9, 1)} for k, v in us.items()}
 
+    # the paper's mixed configuration on the same mesh: label and traversal
+    # on the GPU, the reparation phase sequentially on one host core
+    off_g, verts_g, _ = (x.cpu().numpy() for x in out.trimmed())
+    he_g = labels.he.cpu().numpy()
+    mixed_runs = []
+    for _ in range(3):
+        w0 = time.perf_counter()
+        m_off, m_verts, _, m_he, secs = ctx.mesh_mixed(tri, mesh.twin, mesh.origin)
+        mixed_runs.append((time.perf_counter() - w0, secs))
+    mixed_runs.sort(key=lambda r: r[0])
+    wall_m, secs_m = mixed_runs[1]
+    mixed = {"wall_ms_median": round(wall_m * 1e3, 3), "triangles_per_s": round(T / wall_m, 1),
+             "phases_ms": {k[:-2] + "_ms": round(v * 1e3, 3) for k, v in secs_m.items()},
+             "runs": 3, "vs_all_gpu": round(wall_m * 1e3 / ms_step, 2),
+             "identical_to_all_gpu": bool(np.array_equal(m_off, off_g) and np.array_equal(m_verts, verts_g)
+                                          and np.array_equal(m_he, he_g))}
+    log(f"mixed (GPU label + build, host repair): {mixed}")
+
     cpu, identical = None, None
     if not args.no_cpu:
         import oracle
-        off, verts, _ = (x.cpu().numpy() for x in out.trimmed())
-        gpu_dg = digest(off, verts, labels.he.cpu().numpy())
+        gpu_dg = digest(off_g, verts_g, he_g)
         # the CPU baseline: the oracle alone on one core, median of 3, on a
         # bounded sample of the same recipe (a 1000 x 1000 jittered grid)
         sample = config_mesh("grid1000x")
@@ -321,6 +338,7 @@ def bench_single(args, pool, workload: str):
                    "polygons": F, "seeds": stats["seeds"], "tips": stats["tips"], "splits": stats["splits"],
                    "general_small": stats["general_small"], "general_big": stats["general_big"]},
         "roofline": roofline, "kernels": kernels, "cpu_baseline": cpu, "oracle_identical": identical,
+        "mixed": mixed,
     }
 
 
@@ -553,7 +571,8 @@ def main():
             single = bench_single(args, pool, "grid10m" if wl == "all" else wl)
             line.update(value=single["value"], ms_per_step=single["ms_per_step"], config=single["config"],
                         steps_ms=single["steps_ms"], roofline=single["roofline"], kernels=single["kernels"],
-                        cpu_baseline=single["cpu_baseline"], oracle_identical=single["oracle_identical"])
+                        cpu_baseline=single["cpu_baseline"], oracle_identical=single["oracle_identical"],
+                        mixed=single["mixed"])
         if wl == "all" or wl.startswith("batched"):
             nb = args.batched if wl == "all" else int(wl[len("batched"):] or 2000)
             b = bench_batched(args, pool, nb)

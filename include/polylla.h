@@ -154,6 +154,23 @@ int polylla_repair(polylla_ctx *ctx, const polylla_tri *tri, polylla_labels *lab
 int polylla_mesh(polylla_ctx *ctx, const polylla_tri *tri, polylla_labels *labels,
                  polylla_polys *out, hipStream_t stream);
 
+/* Algorithm 1 in the paper's "mixed" configuration (section "GPU parallel
+ * algorithm": the reparation phase gains little in parallel, so the sequential
+ * version of it is used): label and traversal run on the device as in
+ * polylla_label + polylla_build, then the polygons before repair and the edge
+ * labels are copied to the host, where the polygons with barrier-edge tips are
+ * repaired one by one (Algorithm 4 repeated until no tip is left, in the
+ * repair reading above). The result equals polylla_mesh's. Synchronous: waits
+ * for `stream`. tri holds device arrays; twin_host and origin_host are host
+ * copies of tri->twin and tri->origin; he_host (host, [n_halfedges]) receives
+ * the final half-edge labels; `out` holds HOST arrays (offsets, verts, start
+ * may be NULL, counts). seconds (host, [3], may be NULL) receives the time of
+ * the device part, of the copies to the host and of the host repair. Returns
+ * host errors, device errors of the device part (as polylla_status), or
+ * ECAPACITY / EDEGEN from the host repair. */
+int polylla_mesh_mixed(polylla_ctx *ctx, const polylla_tri *tri, const int32_t *twin_host, const int32_t *origin_host,
+                       uint8_t *he_host, polylla_polys *out, double *seconds, hipStream_t stream);
+
 /* polylla_mesh for callers that cannot allocate device memory (code under HIP
  * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
  * same result as polylla_mesh (same kernels) with all scratch in a static

@@ -4,6 +4,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <mutex>
 #include <type_traits>
 #include <vector>
@@ -55,6 +56,8 @@ __global__ void k_group_finish(int64_t, const int64_t*, const int64_t*, const in
 __global__ void k_group_advance(const int64_t*, int64_t*, bool, int64_t, int64_t*, int64_t*, int64_t*, int64_t,
                                 int64_t, const Counters*);
 __global__ void k_batch_close(const int64_t*, int64_t, int64_t*);
+int host_repair(int64_t, const int32_t*, const int32_t*, uint8_t*, int64_t, const int32_t*, const int32_t*,
+                const int32_t*, int32_t*, int32_t*, int32_t*, int64_t, int64_t, int64_t*, int64_t*);
 
 }  // namespace polylla
 
@@ -674,6 +677,51 @@ int polylla_mesh(polylla_ctx* c, const polylla_tri* t, polylla_labels* l, polyll
   if (hipSetDevice(c->device) != hipSuccess) return POLYLLA_EHIP;
   c->last_batched = false;
   return mesh_run(c, t, l ? l->he : nullptr, l ? l->tri : nullptr, l ? l->vtx : nullptr, out, s, 0);
+}
+
+int polylla_mesh_mixed(polylla_ctx* c, const polylla_tri* t, const int32_t* twin_host, const int32_t* origin_host,
+                       uint8_t* he_host, polylla_polys* out, double* seconds, hipStream_t s) {
+  using clock = std::chrono::steady_clock;
+  const auto t0 = clock::now();
+  if (!c || !he_host || !twin_host || !origin_host) return POLYLLA_EINVAL;
+  int rc = check_tri(t);
+  if (rc) return rc;
+  if ((rc = check_polys(out, false))) return rc;
+  const int64_t H = t->n_halfedges, T = H / 3;
+  if ((rc = ensure(c, T, t->n_vertices))) return rc;
+  if ((rc = ensure_group(c, std::max<int64_t>(H, 3), 1))) return rc;
+  if (hipSetDevice(c->device) != hipSuccess) return POLYLLA_EHIP;
+  c->last_batched = false;
+  // label and traversal on the device, the polygons before repair into scratch CSR
+  Scratch* S = c->sc;
+  polylla_polys pre{c->g_off, c->g_verts, c->g_start, c->g_counts, std::max<int64_t>(T, 1),
+                    std::max<int64_t>(H, 3)};
+  reset(c, s, nullptr);
+  if ((rc = run_label(c, t, S->he_s, S->tri_s, S->vtx_s, s))) return rc;
+  if ((rc = run_build(c, t, S->seeds, true, false, S->he_s, S->vtx_s, &pre, s))) return rc;
+  if ((rc = polylla_status(c, s))) return rc;
+  const auto t1 = clock::now();
+  int64_t cnt[2] = {0, 0};
+  if (hipMemcpy(cnt, c->g_counts, sizeof(cnt), hipMemcpyDeviceToHost) != hipSuccess) return POLYLLA_EHIP;
+  const int64_t F = cnt[0], Sv = cnt[1];
+  std::vector<int32_t> off((size_t)F + 1), verts((size_t)std::max<int64_t>(Sv, 1)), start((size_t)std::max<int64_t>(F, 1));
+  if (hipMemcpy(he_host, S->he_s, (size_t)H, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(off.data(), c->g_off, sizeof(int32_t) * (size_t)(F + 1), hipMemcpyDeviceToHost) != hipSuccess ||
+      (Sv > 0 && hipMemcpy(verts.data(), c->g_verts, sizeof(int32_t) * (size_t)Sv, hipMemcpyDeviceToHost) != hipSuccess) ||
+      (F > 0 && hipMemcpy(start.data(), c->g_start, sizeof(int32_t) * (size_t)F, hipMemcpyDeviceToHost) != hipSuccess))
+    return POLYLLA_EHIP;
+  const auto t2 = clock::now();
+  // the reparation phase, sequential on the host
+  int64_t st[2];
+  rc = host_repair(H, twin_host, origin_host, he_host, F, off.data(), verts.data(), start.data(), out->offsets,
+                   out->verts, out->start, out->cap_polys, out->cap_verts, out->counts, st);
+  const auto t3 = clock::now();
+  if (seconds) {
+    seconds[0] = std::chrono::duration<double>(t1 - t0).count();
+    seconds[1] = std::chrono::duration<double>(t2 - t1).count();
+    seconds[2] = std::chrono::duration<double>(t3 - t2).count();
+  }
+  return rc;
 }
 
 int polylla_mesh_noalloc(polylla_ctx* c, const polylla_tri* t, polylla_labels* l, polylla_polys* out,

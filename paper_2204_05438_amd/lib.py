@@ -82,6 +82,8 @@ def load() -> ctypes.CDLL:
         lib.polylla_repair.argtypes = [P, ctypes.POINTER(_Tri), ctypes.POINTER(_Labels), ctypes.POINTER(_Polys),
                                        ctypes.POINTER(_Polys), P]
         lib.polylla_mesh.argtypes = [P, ctypes.POINTER(_Tri), ctypes.POINTER(_Labels), ctypes.POINTER(_Polys), P]
+        lib.polylla_mesh_mixed.argtypes = [P, ctypes.POINTER(_Tri), P, P, P, ctypes.POINTER(_Polys),
+                                           ctypes.POINTER(ctypes.c_double), P]
         lib.polylla_mesh_noalloc.argtypes = [P, ctypes.POINTER(_Tri), ctypes.POINTER(_Labels),
                                              ctypes.POINTER(_Polys), P]
         lib.polylla_validate.argtypes = [P, ctypes.POINTER(_Tri), P]
@@ -96,7 +98,7 @@ def load() -> ctypes.CDLL:
         lib.polylla_strerror.argtypes = [ctypes.c_int]
         lib.polylla_strerror.restype = ctypes.c_char_p
         for f in ("polylla_ctx_create", "polylla_reserve", "polylla_reserve_batch", "polylla_label", "polylla_build", "polylla_repair",
-                  "polylla_mesh", "polylla_mesh_noalloc", "polylla_mesh_batched", "polylla_validate", "polylla_status",
+                  "polylla_mesh", "polylla_mesh_mixed", "polylla_mesh_noalloc", "polylla_mesh_batched", "polylla_validate", "polylla_status",
                   "polylla_stats", "polylla_set_param", "polylla_profile", "polylla_profile_read"):
             getattr(lib, f).restype = ctypes.c_int
         _lib = lib
@@ -357,6 +359,32 @@ class Context:
         lp = ctypes.byref(labels.c()) if labels is not None else None
         _check(load().polylla_mesh(self._h, ctypes.byref(t), lp, ctypes.byref(o), self._stream()), "polylla_mesh")
         return out
+
+    def mesh_mixed(self, tri: Tri, twin_host, origin_host):
+        """polylla_mesh_mixed: label and traversal on the device, repair on the
+        host. twin_host/origin_host: host int32 arrays (numpy) equal to the
+        device ones. Returns (offsets, verts, start, he, seconds) as numpy
+        arrays and a dict of the three phase times."""
+        import numpy as np
+        H, T = tri.n_halfedges, tri.n_tri
+        tw = np.ascontiguousarray(twin_host, dtype=np.int32)
+        og = np.ascontiguousarray(origin_host, dtype=np.int32)
+        if tw.size != H or og.size != H:
+            raise ValueError("host twin/origin must match the device triangulation")
+        he = np.empty(max(H, 1), np.uint8)
+        off = np.empty(T + 1, np.int32)
+        verts = np.empty(max(3 * T, 1), np.int32)
+        start = np.empty(max(T, 1), np.int32)
+        counts = np.zeros(2, np.int64)
+        secs = (ctypes.c_double * 3)()
+        out = _Polys(off.ctypes.data, verts.ctypes.data, start.ctypes.data, counts.ctypes.data, T, 3 * T)
+        t = tri.c()
+        _check(load().polylla_mesh_mixed(self._h, ctypes.byref(t), ctypes.c_void_p(tw.ctypes.data),
+                                         ctypes.c_void_p(og.ctypes.data), ctypes.c_void_p(he.ctypes.data),
+                                         ctypes.byref(out), secs, self._stream()), "polylla_mesh_mixed")
+        F, S = int(counts[0]), int(counts[1])
+        return (off[:F + 1], verts[:S], start[:F], he[:H],
+                {"device_s": secs[0], "copy_s": secs[1], "host_repair_s": secs[2]})
 
     def mesh_noalloc(self, tri: Tri, labels: Labels | None, out: Polys) -> Polys:
         """polylla_mesh_noalloc: scratch in the library's static array; `out`

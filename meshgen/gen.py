@@ -72,6 +72,7 @@ class Mesh:
     next: np.ndarray        # int32 [H]
     lattice: np.ndarray | None = None   # int64 [V, 2] lattice coordinates (None for hand meshes)
     meta: dict = field(default_factory=dict)
+    fixed: np.ndarray | None = None     # uint8 [H], nonzero on both half-edges of a PSLG segment
 
     @property
     def n_vertices(self) -> int:

@@ -37,7 +37,13 @@
  *     in seed-triangle order, and the pieces of a repaired polygon, which
  *     take its place, by ascending first and second vertex;
  *   - a barrier edge is a frontier edge whose two half-edges lie on the same
- *     polygon before repair.
+ *     polygon before repair;
+ *   - a segment of a planar straight-line graph (a constrained edge of the
+ *     input, the paper's guinea-pig example) bounds the domain on both of its
+ *     sides, so each side is labelled like a boundary edge: always a frontier
+ *     edge, and a boundary terminal edge with its own seed triangle on each
+ *     side where it is the longest edge of that side's triangle. Holes are
+ *     triangles absent from the input, their rims boundary edges.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -50,6 +56,7 @@
 #define OR_BORDER 8u
 #define OR_BARRIER 16u
 #define OR_REPAIRED 32u
+#define OR_CONSTRAINED 64u
 /* triangle / vertex label bits */
 #define OR_SEED 1u
 #define OR_TIP 1u
@@ -81,6 +88,7 @@ typedef struct {
   int64_t nv, nhe, nt;
   const double *xy;
   const int32_t *twin, *next, *origin;
+  const uint8_t *fixed;  /* nonzero: the edge is a segment of the input PSLG (may be NULL) */
   uint8_t *he, *tri, *vtx;
   int32_t *maxe;  /* the paper's Max array: local index of the longest edge */
 } mesh_t;
@@ -97,12 +105,16 @@ static int validate(const mesh_t *m) {
     if (t >= 0) {
       if (m->twin[t] != h) return OR_ETOPO;
       if (m->origin[t] != m->origin[m->next[h]]) return OR_ETOPO;
+      if (m->fixed && (m->fixed[h] != 0) != (m->fixed[t] != 0)) return OR_ETOPO;
     }
   }
   return OR_OK;
 }
 
 static int is_frontier(const mesh_t *m, int32_t h) { return (m->he[h] & OR_FRONTIER) != 0; }
+
+/* a boundary side: a hull or hole edge, or a segment of the input PSLG */
+static int is_bounding(const mesh_t *m, int32_t h) { return m->twin[h] < 0 || (m->fixed && m->fixed[h]); }
 
 /* squared length of half-edge h, rounded after every operation */
 static double sq_length(const mesh_t *m, int32_t h) {
@@ -139,19 +151,20 @@ static void label_max(mesh_t *m) {
 }
 
 /* LabelSeed: terminal edges and their seed triangle (lower index); a hull edge
- * that is the longest edge of its triangle is a border terminal edge. */
+ * (or a side of a PSLG segment) that is the longest edge of its triangle is a
+ * border terminal edge. */
 static void label_seed(mesh_t *m) {
   for (int64_t h = 0; h < m->nhe; ++h) {
     int32_t tw = m->twin[h];
-    if (tw >= 0 && tw < h) continue; /* visit each edge once */
     int64_t ta = h / 3;
-    if (tw < 0) {
+    if (is_bounding(m, (int32_t)h)) { /* each side on its own */
       if (m->maxe[ta] == h % 3) {
         m->he[h] |= OR_TERMINAL;
         m->tri[ta] |= OR_SEED;
       }
       continue;
     }
+    if (tw < h) continue; /* visit each interior edge once */
     int64_t tb = tw / 3;
     if (m->maxe[ta] == h % 3 && m->maxe[tb] == tw % 3) {
       m->he[h] |= OR_TERMINAL;
@@ -161,14 +174,19 @@ static void label_seed(mesh_t *m) {
   }
 }
 
-/* LabelFrontier: an edge is a frontier edge when it is a hull edge or the
- * longest edge of neither adjacent triangle. */
+/* LabelFrontier: an edge is a frontier edge when it is a hull edge, a PSLG
+ * segment or the longest edge of neither adjacent triangle. */
 static void label_frontier(mesh_t *m) {
   for (int64_t h = 0; h < m->nhe; ++h) {
     int32_t tw = m->twin[h];
     if (tw >= 0 && tw < h) continue;
     if (tw < 0) {
       m->he[h] |= OR_FRONTIER | OR_BORDER;
+      continue;
+    }
+    if (m->fixed && m->fixed[h]) {
+      m->he[h] |= OR_FRONTIER | OR_CONSTRAINED;
+      m->he[tw] |= OR_FRONTIER | OR_CONSTRAINED;
       continue;
     }
     int64_t ta = h / 3, tb = tw / 3;
@@ -329,7 +347,7 @@ static int emit(const mesh_t *m, const plist_t *p, int32_t *off, int32_t *verts,
 /* ------------------------------ Algorithm 1 ------------------------------ */
 
 int oracle_mesh(int64_t nv, int64_t nhe, const double *xy, const int32_t *twin,
-                const int32_t *next, const int32_t *origin,
+                const int32_t *next, const int32_t *origin, const uint8_t *fixed,
                 uint8_t *he_labels, uint8_t *tri_labels, uint8_t *vtx_labels,
                 int32_t *pre_off, int32_t *pre_verts, int32_t *pre_start, int64_t *pre_counts,
                 int32_t *off, int32_t *verts, int32_t *start, int64_t *counts,
@@ -341,7 +359,7 @@ int oracle_mesh(int64_t nv, int64_t nhe, const double *xy, const int32_t *twin,
   if (nhe >= INT32_MAX || nv >= INT32_MAX) return OR_EINVAL;
   mesh_t m;
   m.nv = nv; m.nhe = nhe; m.nt = nhe / 3;
-  m.xy = xy; m.twin = twin; m.next = next; m.origin = origin;
+  m.xy = xy; m.twin = twin; m.next = next; m.origin = origin; m.fixed = fixed;
   m.he = he_labels; m.tri = tri_labels; m.vtx = vtx_labels;
   for (int i = 0; i < ST_COUNT; ++i) stats[i] = 0;
   int rc = validate(&m);

@@ -15,7 +15,7 @@ _lib = None
 _lock = threading.Lock()
 
 # label bits (the documented output layout)
-HE = {"LONGEST": 1, "FRONTIER": 2, "TERMINAL": 4, "BORDER": 8, "BARRIER": 16, "REPAIRED": 32}
+HE = {"LONGEST": 1, "FRONTIER": 2, "TERMINAL": 4, "BORDER": 8, "BARRIER": 16, "REPAIRED": 32, "CONSTRAINED": 64}
 TRI = {"SEED": 1}
 VTX = {"TIP": 1}
 STATS = ["seeds", "tip_polygons", "tips", "splits", "passes", "nonsimple_final",
@@ -42,7 +42,7 @@ def _load():
             P = ctypes.c_void_p
             I = ctypes.c_int64
             lib.oracle_mesh.restype = ctypes.c_int
-            lib.oracle_mesh.argtypes = [I, I, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, I, I, P]
+            lib.oracle_mesh.argtypes = [I, I, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, I, I, P]
             _lib = lib
     return _lib
 
@@ -51,19 +51,24 @@ def _ptr(a):
     return a.ctypes.data if a is not None and a.size else None
 
 
-def oracle_mesh(xy, twin, next_, origin, check: bool = True):
+def oracle_mesh(xy, twin, next_, origin, check: bool = True, fixed=None):
     """Run label -> traversal -> repair on one triangulation.
 
-    Returns a dict with he/tri/vtx labels (uint8), the polygons before repair
-    (pre_offsets, pre_verts, pre_start) and after (offsets, verts, start) as
-    CSR int32 arrays of canonical CCW cycles, and a stats dict. Raises
-    RuntimeError with the oracle's code when `check` and the call fails.
+    `fixed` (uint8 per half-edge, nonzero on both half-edges of a segment of
+    the input PSLG) may be None. Returns a dict with he/tri/vtx labels
+    (uint8), the polygons before repair (pre_offsets, pre_verts, pre_start)
+    and after (offsets, verts, start) as CSR int32 arrays of canonical CCW
+    cycles, and a stats dict. Raises RuntimeError with the oracle's code when
+    `check` and the call fails.
     """
     lib = _load()
     xy = np.ascontiguousarray(xy, dtype=np.float64)
     twin = np.ascontiguousarray(twin, dtype=np.int32)
     next_ = np.ascontiguousarray(next_, dtype=np.int32)
     origin = np.ascontiguousarray(origin, dtype=np.int32)
+    fixed = None if fixed is None else np.ascontiguousarray(fixed, dtype=np.uint8)
+    if fixed is not None and fixed.shape[0] != origin.shape[0]:
+        raise ValueError("fixed must hold one byte per half-edge")
     nv = xy.shape[0]
     nhe = origin.shape[0]
     nt = nhe // 3
@@ -81,7 +86,7 @@ def oracle_mesh(xy, twin, next_, origin, check: bool = True):
     start = np.zeros(cap_p, np.int32)
     counts = np.zeros(2, np.int64)
     stats = np.zeros(len(STATS), np.int64)
-    rc = lib.oracle_mesh(nv, nhe, _ptr(xy), _ptr(twin), _ptr(next_), _ptr(origin),
+    rc = lib.oracle_mesh(nv, nhe, _ptr(xy), _ptr(twin), _ptr(next_), _ptr(origin), _ptr(fixed),
                          he.ctypes.data, tri.ctypes.data, vtx.ctypes.data,
                          pre_off.ctypes.data, pre_verts.ctypes.data, pre_start.ctypes.data,
                          pre_counts.ctypes.data, off.ctypes.data, verts.ctypes.data,
@@ -100,4 +105,5 @@ def oracle_mesh(xy, twin, next_, origin, check: bool = True):
 
 
 def oracle_on(mesh, check: bool = True):
-    return oracle_mesh(mesh.xy, mesh.twin, mesh.next, mesh.origin, check=check)
+    return oracle_mesh(mesh.xy, mesh.twin, mesh.next, mesh.origin, check=check,
+                       fixed=getattr(mesh, "fixed", None))

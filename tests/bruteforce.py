@@ -13,7 +13,7 @@ from collections import defaultdict
 
 import numpy as np
 
-LONGEST, FRONTIER, TERMINAL, BORDER, BARRIER, REPAIRED = 1, 2, 4, 8, 16, 32
+LONGEST, FRONTIER, TERMINAL, BORDER, BARRIER, REPAIRED, CONSTRAINED = 1, 2, 4, 8, 16, 32, 64
 
 
 def _tris(mesh):
@@ -37,6 +37,14 @@ class Brute:
         for t, (a, b, c) in enumerate(self.tris):
             for i, (u, v) in enumerate(((a, b), (b, c), (c, a))):
                 self.dedge[(u, v)] = (t, i)
+        # segments of the input PSLG, as undirected vertex pairs
+        fx = getattr(mesh, "fixed", None)
+        self.segments = set()
+        if fx is not None:
+            for t, tri in enumerate(self.tris):
+                for i in range(3):
+                    if fx[3 * t + i]:
+                        self.segments.add(frozenset((tri[i], tri[(i + 1) % 3])))
 
     # ---- labels by definition -------------------------------------------------
     def mate(self, t, i):
@@ -65,13 +73,14 @@ class Brute:
         lg = self.longest()
         he = np.zeros(3 * self.T, np.uint8)
         seed = np.zeros(self.T, np.uint8)
-        for t in range(self.T):
+        for t, tri in enumerate(self.tris):
             he[3 * t + lg[t]] |= LONGEST
             for i in range(3):
                 m = self.mate(t, i)
                 mine = lg[t] == i
-                if m is None:
-                    he[3 * t + i] |= BORDER | FRONTIER
+                if m is None or frozenset((tri[i], tri[(i + 1) % 3])) in self.segments:
+                    # a hull edge, or a side of a segment: bounds the domain
+                    he[3 * t + i] |= (BORDER if m is None else CONSTRAINED) | FRONTIER
                     if mine:
                         he[3 * t + i] |= TERMINAL
                         seed[t] = 1

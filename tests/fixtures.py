@@ -20,7 +20,19 @@ def golden(name):
     with open(os.path.join(GOLDEN, name + ".json")) as f:
         g = json.load(f)
     mesh = mesh_from_triangles(np.array(g["xy"], dtype=np.float64), np.array(g["tris"]))
+    if g.get("fixed"):
+        mesh.fixed = fixed_from_pairs(mesh, g["fixed"])
     return mesh, g
+
+
+def fixed_from_pairs(mesh, pairs):
+    """Segment flags per half-edge (both half-edges of every listed vertex pair)."""
+    want = {frozenset((int(a), int(b))) for a, b in pairs}
+    o = mesh.origin
+    h = np.arange(o.size)
+    nxt = o[h - h % 3 + (h + 1) % 3]
+    fixed = np.array([frozenset((int(a), int(b))) in want for a, b in zip(o, nxt)], dtype=np.uint8)
+    return fixed
 
 
 def random_mesh(seed: int, n: int, kind: str = "uniform"):

@@ -48,8 +48,8 @@ def test_layout_errors():
 def _compare_with_brute(mesh):
     o = run(mesh)
     b = Brute(mesh).mesh_pipeline()
-    # labels before repair: LONGEST, FRONTIER, TERMINAL, BORDER, SEED
-    pre_mask = 1 | 2 | 4 | 8
+    # labels before repair: LONGEST, FRONTIER, TERMINAL, BORDER, CONSTRAINED, SEED
+    pre_mask = 1 | 2 | 4 | 8 | 64
     he_pre = o["he"] & pre_mask
     he_pre = np.where(o["he"] & REPAIRED, he_pre & np.uint8(0xFF ^ FRONTIER), he_pre)
     assert np.array_equal(he_pre, b["he"])
@@ -70,6 +70,32 @@ def _compare_with_brute(mesh):
     assert np.array_equal(o["he"] & BARRIER, b["barrier"])
     assert set(np.nonzero(o["vtx"] & 1)[0].tolist()) == b["tips"]
     return o
+
+
+def with_segments(mesh, seed, frac):
+    """The mesh with a seeded random subset of its interior edges made
+    segments of the input (both half-edges flagged)."""
+    rng = np.random.default_rng(seed)
+    o, tw = mesh.origin, mesh.twin
+    h = np.arange(o.size)
+    inner = np.nonzero((tw >= 0) & (h < tw))[0]
+    pick = inner[rng.random(inner.size) < frac]
+    fixed = np.zeros(o.size, np.uint8)
+    fixed[pick] = 1
+    fixed[tw[pick]] = 1
+    mesh.fixed = fixed
+    return mesh
+
+
+@pytest.mark.parametrize("kind", ["uniform", "cluster", "grid", "lattice"])
+@pytest.mark.parametrize("seed", range(8))
+def test_oracle_vs_bruteforce_segments(kind, seed):
+    """Input segments (a planar straight-line graph): each side of a segment
+    is labelled like a boundary edge; labels, regions, barrier edges, tips
+    and the repair against the brute force."""
+    n = [8, 15, 30, 50, 80, 120, 200, 300][seed]
+    frac = [0.05, 0.1, 0.2, 0.35][seed % 4]
+    _compare_with_brute(with_segments(random_mesh(3000 + 17 * seed, n, kind), 5 + seed, frac))
 
 
 @pytest.mark.parametrize("kind", ["uniform", "cluster", "grid", "lattice"])

@@ -41,6 +41,13 @@
  *         bit 16 BARRIER : frontier edge whose two half-edges lie on the same
  *                           polygon before repair (set by build / repair / mesh).
  *         bit 32 REPAIRED: frontier edge opened by the repair.
+ *         bit 64 CONSTRAINED: a side of a segment of the input (polylla_tri.fixed).
+ *                           A segment bounds the domain on both of its sides,
+ *                           so each side is labelled like a boundary edge:
+ *                           FRONTIER always, TERMINAL (and its triangle a
+ *                           SEED) where it is the longest edge of its triangle.
+ *                           The paper meshes such inputs (its guinea-pig PSLG);
+ *                           holes are triangles absent from the input.
  *  tri[t] bit 1 SEED     : t is the lower-index triangle of a terminal edge (or
  *                           the triangle of a boundary terminal edge).
  *  vtx[v] bit 1 TIP      : v is a barrier-edge tip before repair.
@@ -91,6 +98,7 @@ extern "C" {
 #define POLYLLA_BORDER 8u
 #define POLYLLA_BARRIER 16u
 #define POLYLLA_REPAIRED 32u
+#define POLYLLA_CONSTRAINED 64u
 #define POLYLLA_SEED 1u
 #define POLYLLA_TIP 1u
 
@@ -103,6 +111,8 @@ typedef struct {
   const int32_t *twin;    /* [n_halfedges], -1 on the boundary */
   const int32_t *next;    /* [n_halfedges], grouped (see above); may be NULL except for polylla_validate */
   const int32_t *origin;  /* [n_halfedges] */
+  const uint8_t *fixed;   /* [n_halfedges] or NULL: nonzero on both half-edges of a segment of an input
+                             planar straight-line graph (see CONSTRAINED below) */
 } polylla_tri;
 
 typedef struct {
@@ -206,6 +216,7 @@ typedef struct {
   const double *xy;             /* device [2 * vtx_off[n_meshes]] */
   const int32_t *twin;          /* device [he_off[n_meshes]], local, -1 on the boundary */
   const int32_t *origin;        /* device [he_off[n_meshes]], local */
+  const uint8_t *fixed;         /* device [he_off[n_meshes]] or NULL: segment flags as in polylla_tri */
 } polylla_batch;
 
 /* Polygons of a batch: one CSR over all meshes, meshes in order, each mesh's

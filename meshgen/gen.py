@@ -111,14 +111,20 @@ def snap(points: np.ndarray) -> np.ndarray:
     return np.clip(q, 0, _SCALE).astype(np.int64)
 
 
-def mesh_from_points(points: np.ndarray, meta: dict | None = None) -> Mesh:
-    """Snap, deduplicate, Morton-number and Delaunay-triangulate a point set."""
+def mesh_from_points(points: np.ndarray, meta: dict | None = None, vertex_of: list | None = None) -> Mesh:
+    """Snap, deduplicate, Morton-number and Delaunay-triangulate a point set.
+    If `vertex_of` is a list, the vertex id of every input point (after
+    deduplication: the id of the kept copy) is appended to it as an array."""
     lat = snap(points)
     code = (_part1by1(lat[:, 0]) << np.uint64(1)) | _part1by1(lat[:, 1])
     order = np.argsort(code, kind="stable")
     code_s = code[order]
     keep = np.ones(order.shape[0], dtype=bool)
     keep[1:] = code_s[1:] != code_s[:-1]
+    if vertex_of is not None:
+        vid = np.empty(order.shape[0], np.int64)
+        vid[order] = np.cumsum(keep) - 1
+        vertex_of.append(vid)
     lat = np.ascontiguousarray(lat[order[keep]])
     n = lat.shape[0]
     X = np.ascontiguousarray(lat[:, 0])
@@ -203,6 +209,8 @@ def config_points(name: str) -> np.ndarray:
         u = _uniform(rng, n // 2)
         c = _clusters(rng, n - n // 2, 8, 0.02)
         return np.concatenate([u, c], axis=0)
+    if name.startswith("pslg"):
+        raise KeyError("pslg workloads are meshes with segments: use config_mesh")
     if name.startswith("grid"):
         spec = name[len("grid"):]
         g = 3163 if spec == "10m" else int(spec.rstrip("x"))
@@ -226,6 +234,10 @@ def _parse_count(s: str) -> int:
 
 
 def config_mesh(name: str) -> Mesh:
+    if name.startswith("pslg"):
+        # pslg<N>: N uniform points, 8 holes, 6 cracks (seed 6)
+        n = _parse_count(name[len("pslg"):])
+        return pslg_mesh(n, 8, 6, seed=6)
     pts = config_points(name)
     return mesh_from_points(pts, meta={"workload": name})
 
@@ -261,6 +273,118 @@ def request_points(n: int, kind: str, seed: int) -> np.ndarray:
     if kind == "uniform":
         return _uniform(rng, n)
     return _clusters(rng, n, 4, 0.05)
+
+
+def pslg_mesh(n: int, n_holes: int, n_cracks: int, seed: int) -> Mesh:
+    """A triangulation of a planar straight-line graph in [0,1]^2: n points
+    uniform in the square, n_holes circular holes (radius U(0.03, 0.08)) and
+    n_cracks straight segments (length U(0.1, 0.3)) inside the domain, all
+    seeded. The holes' rims and the cracks are sampled at the mean point
+    spacing s = 1/sqrt(n), and uniform points within s of them (or inside a
+    hole) are dropped, so that consecutive samples have an empty diametral
+    disk and their edge is in the Delaunay triangulation (a conforming
+    triangulation, no edge insertion needed). Triangles with their centroid
+    in a hole are removed (the rim becomes boundary); the crack edges are
+    marked as segments in `fixed` (both half-edges)."""
+    rng = np.random.default_rng(seed)
+    sp = 1.0 / math.sqrt(max(n, 1))
+    holes = []
+    tries = 0
+    while len(holes) < n_holes and tries < 10000:
+        tries += 1
+        c = rng.uniform(0.12, 0.88, 2)
+        r = rng.uniform(0.03, 0.08)
+        if all(np.hypot(*(c - c2)) > r + r2 + 6 * sp for c2, r2 in holes):
+            holes.append((c, r))
+    cracks = []
+    tries = 0
+
+    def seg_dist(p, a, b):
+        ab = b - a
+        t = np.clip(((p - a) @ ab) / (ab @ ab), 0.0, 1.0)
+        return np.hypot(*((a + np.outer(t, ab) if p.ndim > 1 else a + t * ab) - p).T)
+
+    while len(cracks) < n_cracks and tries < 10000:
+        tries += 1
+        a = rng.uniform(0.08, 0.92, 2)
+        ang = rng.uniform(0, 2 * math.pi)
+        L = rng.uniform(0.1, 0.3)
+        b = a + L * np.array([math.cos(ang), math.sin(ang)])
+        if not (0.05 < b[0] < 0.95 and 0.05 < b[1] < 0.95):
+            continue
+        samples = a + np.outer(np.linspace(0, 1, 64), b - a)
+        if any(np.min(np.abs(np.hypot(*(samples - c).T) - r)) < 6 * sp or np.min(np.hypot(*(samples - c).T)) < r
+               for c, r in holes):
+            continue
+        if any(np.min(seg_dist(samples, a2, b2)) < 6 * sp for a2, b2 in cracks):
+            continue
+        cracks.append((a, b))
+    P = rng.random((n, 2))
+    keep = np.ones(n, bool)
+    for c, r in holes:
+        keep &= np.hypot(*(P - c).T) > r + sp
+    for a, b in cracks:
+        keep &= seg_dist(P, a, b) > sp
+    feats, chains = [P[keep]], []
+    base = int(keep.sum())
+    for c, r in holes:
+        k = max(8, int(math.ceil(2 * math.pi * r / sp)))
+        ang = 2 * math.pi * np.arange(k) / k
+        feats.append(c + r * np.stack([np.cos(ang), np.sin(ang)], 1))
+        chains.append((base, k, True))
+        base += k
+    for a, b in cracks:
+        k = int(math.ceil(np.hypot(*(b - a)) / sp)) + 1
+        feats.append(a + np.outer(np.linspace(0, 1, k), b - a))
+        chains.append((base, k, False))
+        base += k
+    pts = np.concatenate(feats)
+    vid_l = []
+    mesh = mesh_from_points(pts, meta={"workload": f"pslg n={n} holes={len(holes)} cracks={len(cracks)} seed={seed}"},
+                            vertex_of=vid_l)
+    vid = vid_l[0]
+    T = mesh.n_tri
+    o = mesh.origin.astype(np.int64)
+    h = np.arange(3 * T)
+    nx = o[h - h % 3 + (h + 1) % 3]
+    V = mesh.n_vertices
+    key = o * V + nx
+    order = np.argsort(key)
+    skey = key[order]
+
+    def half_edge(u, v):
+        i = np.searchsorted(skey, u * V + v)
+        if i >= skey.size or skey[i] != u * V + v:
+            raise RuntimeError(f"PSLG edge ({u}, {v}) is missing from the triangulation")
+        return int(order[i])
+
+    seg_he = []
+    for b0, k, closed in chains:
+        ids = vid[b0:b0 + k]
+        for j in range(k if closed else k - 1):
+            u, v = int(ids[j]), int(ids[(j + 1) % k])
+            seg_he.append((half_edge(u, v), half_edge(v, u), closed))
+    # remove the triangles inside the holes, keeping triangle order
+    cen = (mesh.xy[o[0::3]] + mesh.xy[o[1::3]] + mesh.xy[o[2::3]]) / 3.0
+    inside = np.zeros(T, bool)
+    for c, r in holes:
+        inside |= np.hypot(*(cen - c).T) < r
+    newt = np.cumsum(~inside) - 1
+    hmap = np.where(np.repeat(~inside, 3), 3 * np.repeat(newt, 3) + h % 3, -1)
+    kept = np.repeat(~inside, 3)
+    origin = mesh.origin[kept]
+    tw_old = mesh.twin[kept]
+    twin = np.where(tw_old >= 0, hmap[np.maximum(tw_old, 0)], -1).astype(np.int32)
+    fixed = np.zeros(3 * T, np.uint8)
+    for h1, h2, closed in seg_he:
+        if not closed:
+            fixed[h1] = fixed[h2] = 1
+    fixed = fixed[kept]
+    T2 = int((~inside).sum())
+    meta = dict(mesh.meta)
+    meta.update(holes=len(holes), cracks=len(cracks), triangles_removed=int(inside.sum()))
+    return Mesh(xy=mesh.xy, origin=np.ascontiguousarray(origin), twin=twin, next=_grouped_next(3 * T2),
+                lattice=mesh.lattice, meta=meta, fixed=fixed)
 
 
 def pack_meshes(meshes, with_next: bool = True):

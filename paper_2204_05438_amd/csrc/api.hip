@@ -19,7 +19,7 @@ __global__ void k_longest(int64_t, int64_t, const double*, const int32_t*, const
                           Counters*);
 template <bool COMPUTE>
 __global__ void k_label(int64_t, const int32_t*, const uint8_t*, uint8_t*, uint8_t*, const int32_t*, int32_t*,
-                        uint32_t*, uint32_t*, Counters*, bool);
+                        uint32_t*, uint32_t*, Counters*, bool, const uint8_t*);
 __global__ void k_seeds(int64_t, const uint8_t*, const uint32_t*, const uint32_t*, int32_t*, Counters*);
 __global__ void k_pack_walk(int64_t, const uint8_t*, const int32_t*, const int32_t*, int32_t*);
 template <bool FROM_SEEDS>
@@ -44,7 +44,8 @@ __global__ void k_general_huge(const int32_t*, bool, int32_t, int64_t, const int
                                Counters*);
 __global__ void k_scan_emit(PolyState, uint64_t*, const int32_t*, const int32_t*, int32_t*, int32_t*, int32_t*,
                             int64_t*, int64_t, int64_t, Counters*);
-__global__ void k_validate(int64_t, int64_t, const int32_t*, const int32_t*, const int32_t*, Counters*);
+__global__ void k_validate(int64_t, int64_t, const int32_t*, const int32_t*, const int32_t*, const uint8_t*,
+                           Counters*);
 __global__ void k_batch_offsets(int64_t, const int64_t*, const int32_t*, const int32_t*, const int64_t*, int64_t,
                                 int64_t, int64_t*);
 __global__ void k_group_rebase(const int32_t*, const int32_t*, int32_t*, int32_t*, int64_t, const int64_t*,
@@ -393,7 +394,7 @@ int run_label(polylla_ctx* c, const polylla_tri* t, uint8_t* he, uint8_t* tri, u
     const bool vec = ((uintptr_t)t->twin % 16 == 0) && ((uintptr_t)t->origin % 16 == 0) && ((uintptr_t)he % 4 == 0) &&
                      ((uintptr_t)tri % 4 == 0);
     hipLaunchKernelGGL(k_label<true>, dim3((T + kTile - 1) / kTile), dim3(256), 0, s, T, t->twin, c->sc->lg, he, tri,
-                       t->origin, c->sc->wk, tile_counts(c), tile_groups(c, T), c->cnt, vec);
+                       t->origin, c->sc->wk, tile_counts(c), tile_groups(c, T), c->cnt, vec, t->fixed);
   }
   if (T > 0) launch_seeds(c, T, tri, s);
   return launched();
@@ -637,7 +638,8 @@ int polylla_build(polylla_ctx* c, const polylla_tri* t, polylla_labels* l, polyl
   if (T > 0) {
     Prof p(c, s, KR_COMPACT);
     hipLaunchKernelGGL(k_label<false>, dim3((T + kTile - 1) / kTile), dim3(256), 0, s, T, t->twin, c->sc->lg, l->he,
-                       l->tri, t->origin, c->sc->wk, tile_counts(c), tile_groups(c, T), c->cnt, false);
+                       l->tri, t->origin, c->sc->wk, tile_counts(c), tile_groups(c, T), c->cnt, false,
+                       (const uint8_t*)nullptr);
   }
   if (T > 0) launch_seeds(c, T, l->tri, s);
   if (T > 0) {
@@ -815,7 +817,7 @@ int polylla_mesh_batched(polylla_ctx* c, const polylla_batch* b, polylla_labels*
       hipLaunchKernelGGL(k_group_rebase, dim3(grid_for(H, 256, 1 << 16)), dim3(256), 0, s, b->twin, b->origin,
                          c->g_twin, c->g_origin, nm, b->he_off + m0, b->vtx_off + m0);
     }
-    polylla_tri tg{V, H, b->xy + 2 * v0, c->g_twin, nullptr, c->g_origin};
+    polylla_tri tg{V, H, b->xy + 2 * v0, c->g_twin, nullptr, c->g_origin, b->fixed ? b->fixed + h0 : nullptr};
     polylla_polys pg{c->g_off, c->g_verts, c->g_start, c->g_counts, H / 3, H};
     uint8_t* he = (l && l->he) ? l->he + h0 : nullptr;
     uint8_t* tri = (l && l->tri) ? l->tri + h0 / 3 : nullptr;
@@ -860,7 +862,7 @@ int polylla_validate(polylla_ctx* c, const polylla_tri* t, hipStream_t s) {
                      (const int64_t*)nullptr, 0);
   Prof pv(c, s, KR_VALIDATE);
   hipLaunchKernelGGL(k_validate, dim3(grid_for(t->n_halfedges, 256, 1 << 16)), dim3(256), 0, s, t->n_halfedges,
-                     t->n_vertices, t->twin, t->next, t->origin, c->cnt);
+                     t->n_vertices, t->twin, t->next, t->origin, t->fixed, c->cnt);
   if ((rc = launched())) return rc;
   return polylla_status(c, s);
 }

@@ -17,6 +17,7 @@ constexpr uint8_t kTerminal = POLYLLA_TERMINAL;
 constexpr uint8_t kBorder = POLYLLA_BORDER;
 constexpr uint8_t kBarrier = POLYLLA_BARRIER;
 constexpr uint8_t kRepaired = POLYLLA_REPAIRED;
+constexpr uint8_t kConstrained = POLYLLA_CONSTRAINED;
 constexpr uint8_t kSeed = POLYLLA_SEED;
 constexpr uint8_t kTip = POLYLLA_TIP;
 

@@ -145,10 +145,12 @@ struct LgView {
   }
 };
 
-// Labels of the three half-edges of triangle t and whether t is a seed.
+// Labels of the three half-edges of triangle t and whether t is a seed. Bit
+// i of fx: half-edge i is a side of an input segment, labelled like a
+// boundary edge (frontier; a boundary terminal edge where it is the longest).
 template <class LG>
 __device__ __forceinline__ uint32_t label_triangle(int64_t t, int m, const int32_t tw[3], const LG& lg, int32_t nhe,
-                                                   Counters* cnt, bool* seed) {
+                                                   Counters* cnt, bool* seed, uint32_t fx = 0) {
   uint32_t packed = 0;
   bool s = false;
 #pragma unroll
@@ -156,7 +158,13 @@ __device__ __forceinline__ uint32_t label_triangle(int64_t t, int m, const int32
     const bool mine = (m == i);
     uint32_t lab = mine ? kLongest : 0u;
     int32_t u = tw[i];
-    if (u < 0) {
+    if (((fx >> i) & 1u) && u >= 0) {
+      lab |= kFrontier | kConstrained;
+      if (mine) {
+        lab |= kTerminal;
+        s = true;
+      }
+    } else if (u < 0) {
       lab |= kFrontier | kBorder;
       if (mine) {
         lab |= kTerminal;
@@ -216,12 +224,19 @@ constexpr int kLgWin = 256 * kLabelItems + 2 * kLgMargin;
 
 // COMPUTE = true : labels from twin + Max, then seed compaction.
 // COMPUTE = false: seed compaction only, from existing triangle labels.
+// Segment bits of triangle t (bit i: half-edge 3t+i is a side of an input segment).
+__device__ __forceinline__ uint32_t seg_bits(const uint8_t* __restrict__ fixed, int64_t t) {
+  if (!fixed) return 0u;
+  return (fixed[3 * t] ? 1u : 0u) | (fixed[3 * t + 1] ? 2u : 0u) | (fixed[3 * t + 2] ? 4u : 0u);
+}
+
 template <bool COMPUTE>
 __global__ __launch_bounds__(256) void k_label(int64_t nt, const int32_t* __restrict__ twin,
                                                const uint8_t* __restrict__ lg, uint8_t* __restrict__ he,
                                                uint8_t* __restrict__ tri, const int32_t* __restrict__ origin,
                                                int32_t* __restrict__ wk, uint32_t* __restrict__ tcount,
-                                               uint32_t* __restrict__ tsuper, Counters* cnt, bool vec) {
+                                               uint32_t* __restrict__ tsuper, Counters* cnt, bool vec,
+                                               const uint8_t* __restrict__ fixed) {
   constexpr int ITEMS = kLabelItems;
   const uint32_t tile = xcd_block(blockIdx.x, gridDim.x);
   const int64_t t0 = ((int64_t)tile * 256 + threadIdx.x) * ITEMS;
@@ -274,7 +289,7 @@ __global__ __launch_bounds__(256) void k_label(int64_t nt, const int32_t* __rest
       int32_t tw[3] = {tw3[k].x, tw3[k].y, tw3[k].z};
       const int32_t og[3] = {og3[k].x, og3[k].y, og3[k].z};
       const uint32_t lab = label_triangle(t, reinterpret_cast<const uint8_t*>(s_lg4)[kLgMargin + lt], tw, lgv, nhe,
-                                          cnt, &sd[k]);
+                                          cnt, &sd[k], seg_bits(fixed, t));
       walk_words(lab, tw, og);
       Int3 w3;
       w3.x = tw[0];
@@ -308,7 +323,7 @@ __global__ __launch_bounds__(256) void k_label(int64_t nt, const int32_t* __rest
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           lab[j] = label_triangle(t0 + 4 * g + j, (mm[g] >> (8 * j)) & 0xFF, tw + 3 * (4 * g + j),
-                                  LgView{lg, nullptr, 0, 0}, nhe, cnt, &sd[4 * g + j]);
+                                  LgView{lg, nullptr, 0, 0}, nhe, cnt, &sd[4 * g + j], seg_bits(fixed, t0 + 4 * g + j));
           walk_words(lab[j], tw + 3 * (4 * g + j), og + 3 * (4 * g + j));
         }
         // 12 label bytes of 4 triangles -> three 32-bit words
@@ -327,7 +342,7 @@ __global__ __launch_bounds__(256) void k_label(int64_t nt, const int32_t* __rest
         if (t >= nt) continue;
         int32_t tw[3] = {twin[3 * t], twin[3 * t + 1], twin[3 * t + 2]};
         const int32_t og[3] = {origin[3 * t], origin[3 * t + 1], origin[3 * t + 2]};
-        uint32_t lab = label_triangle(t, lg[t], tw, LgView{lg, nullptr, 0, 0}, nhe, cnt, &sd[j]);
+        uint32_t lab = label_triangle(t, lg[t], tw, LgView{lg, nullptr, 0, 0}, nhe, cnt, &sd[j], seg_bits(fixed, t));
         walk_words(lab, tw, og);
         wk[3 * t] = tw[0];
         wk[3 * t + 1] = tw[1];
@@ -404,7 +419,8 @@ __global__ __launch_bounds__(256) void k_seeds(int64_t nt, const uint8_t* __rest
 // and matching endpoints.
 __global__ __launch_bounds__(256) void k_validate(int64_t nhe, int64_t nv, const int32_t* __restrict__ twin,
                                                   const int32_t* __restrict__ next,
-                                                  const int32_t* __restrict__ origin, Counters* cnt) {
+                                                  const int32_t* __restrict__ origin,
+                                                  const uint8_t* __restrict__ fixed, Counters* cnt) {
   for (int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; h < nhe; h += (int64_t)gridDim.x * blockDim.x) {
     const int32_t hh = (int32_t)h;
     if (next[h] != he_next(hh)) {
@@ -419,14 +435,15 @@ __global__ __launch_bounds__(256) void k_validate(int64_t nhe, int64_t nv, const
     if (tw >= 0) {
       const int32_t on = origin[he_next(hh)];
       if (twin[tw] != hh || origin[tw] != on) set_error(cnt, POLYLLA_ETOPO);
+      if (fixed && (fixed[h] != 0) != (fixed[tw] != 0)) set_error(cnt, POLYLLA_ETOPO);
     }
   }
 }
 
 template __global__ void k_label<true>(int64_t, const int32_t*, const uint8_t*, uint8_t*, uint8_t*, const int32_t*,
-                                       int32_t*, uint32_t*, uint32_t*, Counters*, bool);
+                                       int32_t*, uint32_t*, uint32_t*, Counters*, bool, const uint8_t*);
 template __global__ void k_label<false>(int64_t, const int32_t*, const uint8_t*, uint8_t*, uint8_t*, const int32_t*,
-                                        int32_t*, uint32_t*, uint32_t*, Counters*, bool);
+                                        int32_t*, uint32_t*, uint32_t*, Counters*, bool, const uint8_t*);
 
 // Walk words from existing half-edge labels, for calls that start from them.
 __global__ __launch_bounds__(256) void k_pack_walk(int64_t nhe, const uint8_t* __restrict__ he,

@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpolylla.so")
 
 OK, EINVAL, ELAYOUT, ETOPO, ECAPACITY, ENOMEM, EHIP, EDEGEN, EINTERNAL, ETOOBIG = 0, -1, -2, -3, -4, -5, -6, -7, -8, -9
-LONGEST, FRONTIER, TERMINAL, BORDER, BARRIER, REPAIRED = 1, 2, 4, 8, 16, 32
+LONGEST, FRONTIER, TERMINAL, BORDER, BARRIER, REPAIRED, CONSTRAINED = 1, 2, 4, 8, 16, 32, 64
 SEED, TIP = 1, 1
 PARAM_WALK_CAP = 1
 PARAM_WALK_BLOCKS = 2
@@ -36,7 +36,7 @@ class PolyllaError(RuntimeError):
 class _Tri(ctypes.Structure):
     _fields_ = [("n_vertices", ctypes.c_int64), ("n_halfedges", ctypes.c_int64),
                 ("xy", ctypes.c_void_p), ("twin", ctypes.c_void_p),
-                ("next", ctypes.c_void_p), ("origin", ctypes.c_void_p)]
+                ("next", ctypes.c_void_p), ("origin", ctypes.c_void_p), ("fixed", ctypes.c_void_p)]
 
 
 class _Labels(ctypes.Structure):
@@ -51,7 +51,7 @@ class _Polys(ctypes.Structure):
 class _Batch(ctypes.Structure):
     _fields_ = [("n_meshes", ctypes.c_int64), ("vtx_off", ctypes.c_void_p), ("he_off", ctypes.c_void_p),
                 ("vtx_off_host", ctypes.c_void_p), ("he_off_host", ctypes.c_void_p), ("xy", ctypes.c_void_p),
-                ("twin", ctypes.c_void_p), ("origin", ctypes.c_void_p)]
+                ("twin", ctypes.c_void_p), ("origin", ctypes.c_void_p), ("fixed", ctypes.c_void_p)]
 
 
 class _BatchOut(ctypes.Structure):
@@ -114,6 +114,11 @@ def _check(code: int, what: str):
         raise PolyllaError(code, what)
 
 
+def np_u8(a):
+    import numpy as np
+    return np.ascontiguousarray(a, dtype=np.uint8)
+
+
 def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
@@ -125,6 +130,7 @@ class Tri:
     twin: torch.Tensor     # int32 [H]
     next: torch.Tensor | None  # int32 [H]; only polylla_validate reads it
     origin: torch.Tensor   # int32 [H]
+    fixed: torch.Tensor | None = None  # uint8 [H]: segments of an input planar straight-line graph
 
     @property
     def n_vertices(self):
@@ -145,16 +151,22 @@ class Tri:
                 raise ValueError(f"{name} must be contiguous")
         if self.xy.dtype != torch.float64 or any(getattr(self, n).dtype != torch.int32 for n in names[1:]):
             raise TypeError("xy must be float64 and twin/next/origin int32")
+        if self.fixed is not None and (self.fixed.dtype != torch.uint8 or not self.fixed.is_contiguous()
+                                       or self.fixed.shape[0] != self.n_halfedges):
+            raise TypeError("fixed must be a contiguous uint8 tensor with one entry per half-edge")
         return _Tri(self.n_vertices, self.n_halfedges, self.xy.data_ptr(), self.twin.data_ptr(),
-                    None if self.next is None else self.next.data_ptr(), self.origin.data_ptr())
+                    None if self.next is None else self.next.data_ptr(), self.origin.data_ptr(),
+                    None if self.fixed is None else self.fixed.data_ptr())
 
     @staticmethod
     def from_mesh(mesh, device="cuda", with_next: bool = True) -> "Tri":
         """Copy a meshgen.Mesh (numpy arrays) to the device."""
+        fx = getattr(mesh, "fixed", None)
         return Tri(xy=torch.from_numpy(mesh.xy).to(device).contiguous(),
                    twin=torch.from_numpy(mesh.twin).to(device),
                    next=torch.from_numpy(mesh.next).to(device) if with_next else None,
-                   origin=torch.from_numpy(mesh.origin).to(device))
+                   origin=torch.from_numpy(mesh.origin).to(device),
+                   fixed=None if fx is None else torch.from_numpy(np_u8(fx)).to(device))
 
 
 @dataclass
@@ -215,6 +227,7 @@ class Batch:
     he_off: torch.Tensor   # int64 [M + 1] on the device
     vtx_off_host: torch.Tensor  # the same offsets on the host (int64, contiguous)
     he_off_host: torch.Tensor
+    fixed: torch.Tensor | None = None  # uint8 [sum H]: segments of input planar straight-line graphs
 
     @property
     def n_meshes(self):
@@ -245,9 +258,13 @@ class Batch:
             raise TypeError("vtx_off and he_off must be int64")
         if self.xy.dtype != torch.float64 or self.twin.dtype != torch.int32 or self.origin.dtype != torch.int32:
             raise TypeError("xy must be float64 and twin/origin int32")
+        if self.fixed is not None and (self.fixed.dtype != torch.uint8 or not self.fixed.is_contiguous()
+                                       or self.fixed.shape[0] != self.n_halfedges):
+            raise TypeError("fixed must be a contiguous uint8 tensor with one entry per half-edge")
         return _Batch(self.n_meshes, self.vtx_off.data_ptr(), self.he_off.data_ptr(),
                       self.vtx_off_host.data_ptr(), self.he_off_host.data_ptr(), self.xy.data_ptr(),
-                      self.twin.data_ptr(), self.origin.data_ptr())
+                      self.twin.data_ptr(), self.origin.data_ptr(),
+                      None if self.fixed is None else self.fixed.data_ptr())
 
     @staticmethod
     def from_meshes(meshes, device="cuda") -> "Batch":
@@ -263,9 +280,14 @@ class Batch:
         tw = np.concatenate([m.twin for m in meshes]) if meshes else np.zeros(0, np.int32)
         og = np.concatenate([m.origin for m in meshes]) if meshes else np.zeros(0, np.int32)
         vh, hh = torch.from_numpy(vo), torch.from_numpy(ho)
+        fixed = None
+        if any(getattr(m, "fixed", None) is not None for m in meshes):
+            fixed = np.concatenate([np_u8(m.fixed) if getattr(m, "fixed", None) is not None
+                                    else np.zeros(m.n_halfedges, np.uint8) for m in meshes])
         return Batch(xy=torch.from_numpy(np.ascontiguousarray(xy)).to(device),
                      twin=torch.from_numpy(tw).to(device), origin=torch.from_numpy(og).to(device),
-                     vtx_off=vh.to(device), he_off=hh.to(device), vtx_off_host=vh, he_off_host=hh)
+                     vtx_off=vh.to(device), he_off=hh.to(device), vtx_off_host=vh, he_off_host=hh,
+                     fixed=None if fixed is None else torch.from_numpy(fixed).to(device))
 
 
 @dataclass

@@ -47,7 +47,7 @@ def test_mixed_random(ctx, kind):
         _check(ctx, random_mesh(2100 + seed, [50, 400, 3000, 20000][seed], kind))
 
 
-@pytest.mark.parametrize("name", ["uniform10k", "mixed200k"])
+@pytest.mark.parametrize("name", ["uniform10k", "mixed200k", "pslg20k"])
 def test_mixed_workloads(ctx, name):
     print(f"[gpu-case] mixed workload {name}", flush=True)
     secs = _check(ctx, config_mesh(name))

@@ -243,6 +243,55 @@ def test_single_tip_polygon_with_a_lobe(ctx):
     assert_same(r, o, FULL)
 
 
+@pytest.mark.parametrize("name", ["pslg20k", "pslg200k"])
+def test_pslg_workloads(ctx, name):
+    """Triangulations of planar straight-line graphs (8 circular holes, 6
+    cracks): segment sides labelled like boundary edges, regions never
+    crossing a segment, cracks as barrier edges with tips at their ends."""
+    _say(f"workload {name}")
+    mesh = config_mesh(name)
+    o = oracle.oracle_on(mesh)
+    r = gpu_mesh(ctx, mesh)
+    assert_same(r, o, FULL)
+    assert r["stats"]["splits"] == o["stats"]["splits"] > 0
+
+
+def test_pslg_segment_flags_validated(ctx):
+    """Segment flags on one half-edge of an edge only: polylla_validate
+    reports ETOPO."""
+    _say("pslg: asymmetric segment flags")
+    from paper_2204_05438_amd import lib
+    mesh = config_mesh("pslg20k")
+    tri = lib.Tri.from_mesh(mesh)
+    assert ctx.validate(tri) == lib.OK
+    h = int(np.nonzero((mesh.fixed > 0) & (mesh.twin >= 0))[0][0])
+    tri.fixed[h] = 0
+    assert ctx.validate(tri) == lib.ETOPO
+
+
+def test_batched_pslg(ctx):
+    """A batch mixing PSLG meshes (segments) and plain meshes (no segments),
+    cut into several groups, each mesh against the oracle."""
+    _say("batched: PSLG and plain meshes")
+    from meshgen.gen import pslg_mesh
+    from paper_2204_05438_amd import lib
+    meshes = []
+    for k in range(12):
+        if k % 3 == 2:
+            meshes.append(random_mesh(4000 + k, 500 + 300 * k, "uniform"))
+        else:
+            meshes.append(pslg_mesh(800 + 700 * k, 2 + k % 3, 1 + k % 4, 60 + k))
+    batch = lib.Batch.from_meshes(meshes)
+    labels = lib.Labels.empty(batch)
+    ctx.set_param(lib.PARAM_BATCH_GROUP_HE, 40000)
+    try:
+        out = ctx.mesh_batched(batch, labels)
+        ctx.status()
+    finally:
+        ctx.set_param(lib.PARAM_BATCH_GROUP_HE, (1 << 30) - (1 << 24))
+    check_batch_against_oracle(meshes, out, labels, batch.he_off_host.numpy())
+
+
 def test_uniform5m_large_regions(ctx):
     """5M uniform points: two regions exceed the LDS of the 1024-thread
     kernel at the default limits and are built by the global-memory path."""

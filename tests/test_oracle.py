@@ -234,3 +234,42 @@ def test_rotation_and_relabel_invariance():
     m2 = mesh_from_triangles(mesh.xy, tris)
     o2 = run(m2)
     assert sorted(csr_cycles(o1["offsets"], o1["verts"])) == sorted(csr_cycles(o2["offsets"], o2["verts"]))
+
+
+@pytest.mark.parametrize("n,seed", [(600, 1), (1500, 2), (3000, 3)])
+def test_oracle_vs_bruteforce_pslg(n, seed):
+    """Triangulations of planar straight-line graphs (holes and cracks, the
+    generator's recipe at small sizes) against the brute force."""
+    from meshgen.gen import pslg_mesh, validate
+    mesh = pslg_mesh(n, 3, 3, seed)
+    validate(mesh)
+    assert mesh.meta["holes"] == 3 and mesh.meta["cracks"] == 3
+    o = _compare_with_brute(mesh)
+    assert o["stats"]["splits"] > 0
+
+
+def test_pslg_regions_stay_inside_the_domain():
+    """Every polygon of a PSLG mesh lies inside the domain: its vertex cycle
+    never runs along a segment's two sides except as a barrier edge, every
+    triangle is in one region, and the polygons' areas add up to the
+    triangulation's (holes excluded)."""
+    from meshgen.gen import config_mesh
+    mesh = config_mesh("pslg20k")
+    o = run(mesh)
+    he = o["he"]
+    fx = mesh.fixed.astype(bool)
+    assert np.all((he[fx & (mesh.twin >= 0)] & FRONTIER) > 0)
+    assert np.array_equal((he & 64) > 0, fx & (mesh.twin >= 0))
+    T = mesh.n_tri
+    P = mesh.origin.reshape(T, 3)
+    xy = mesh.xy
+    a, b, c = xy[P[:, 0]], xy[P[:, 1]], xy[P[:, 2]]
+    tri_area = 0.5 * ((b[:, 0] - a[:, 0]) * (c[:, 1] - a[:, 1]) - (b[:, 1] - a[:, 1]) * (c[:, 0] - a[:, 0]))
+    off, v = o["offsets"], o["verts"]
+    x, y = xy[v, 0], xy[v, 1]
+    nxt = np.arange(v.size) + 1
+    nxt[off[1:] - 1] = off[:-1]
+    areas = 0.5 * np.add.reduceat(x * y[nxt] - x[nxt] * y, off[:-1])
+    assert np.all(areas > 0)
+    assert math.isclose(areas.sum(), tri_area.sum(), rel_tol=1e-9)
+    assert v.size == T + 2 * (off.size - 1)

@@ -491,3 +491,49 @@ done0:
   free(m.maxe);
   return rc;
 }
+
+/* ------------------------------- Lepp ------------------------------- */
+
+/* Longest-edge propagation path of every triangle (the paper names Lepp-based
+ * algorithms as the next use of its label kernels; Lepp as defined by Rivara):
+ * Lepp(t) = t_0 = t, t_1, ..., t_n where t_{i+1} is the neighbour of t_i across
+ * the longest edge of t_i, ending when that edge is also the longest edge of
+ * t_{i+1} (a terminal edge shared by t_{n-1} and t_n) or is a boundary edge
+ * (or a side of an input segment) of t_n. terminal[t] = the edge key (smaller
+ * half-edge, or the boundary half-edge) of the terminal edge; length[t] = n + 1
+ * triangles. Longest edges use the same (length, edge key) order as LabelMax. */
+int oracle_lepp(int64_t nv, int64_t nhe, const double *xy, const int32_t *twin, const int32_t *next,
+                const int32_t *origin, const uint8_t *fixed, int32_t *terminal, int32_t *length) {
+  if (nv < 0 || nhe < 0 || (nhe > 0 && (!xy || !twin || !next || !origin || !terminal || !length)))
+    return OR_EINVAL;
+  if (nhe >= INT32_MAX || nv >= INT32_MAX) return OR_EINVAL;
+  mesh_t m;
+  memset(&m, 0, sizeof(m));
+  m.nv = nv; m.nhe = nhe; m.nt = nhe / 3;
+  m.xy = xy; m.twin = twin; m.next = next; m.origin = origin; m.fixed = fixed;
+  int rc = validate(&m);
+  if (rc) return rc;
+  uint8_t *he = (uint8_t *)calloc((size_t)nhe + 1, 1);
+  m.maxe = (int32_t *)malloc(sizeof(int32_t) * (size_t)(m.nt + 1));
+  if (!he || !m.maxe) { free(he); free(m.maxe); return OR_ENOMEM; }
+  m.he = he;
+  label_max(&m);
+  for (int64_t t = 0; t < m.nt; ++t) {
+    int64_t cur = t, n = 1;
+    for (;;) {
+      int32_t h = (int32_t)(3 * cur + m.maxe[cur]);
+      if (is_bounding(&m, h)) { terminal[t] = h; break; }
+      int32_t u = twin[h];
+      int64_t nb = u / 3;
+      ++n;
+      if (m.maxe[nb] == u % 3) { terminal[t] = h < u ? h : u; break; }
+      cur = nb;
+      if (n > m.nt + 1) { rc = OR_EDEGEN; goto out; }
+    }
+    length[t] = (int32_t)n;
+  }
+out:
+  free(he);
+  free(m.maxe);
+  return rc;
+}

@@ -41,6 +41,8 @@ def _load():
             lib = ctypes.CDLL(_LIB)
             P = ctypes.c_void_p
             I = ctypes.c_int64
+            lib.oracle_lepp.restype = ctypes.c_int
+            lib.oracle_lepp.argtypes = [I, I, P, P, P, P, P, P, P]
             lib.oracle_mesh.restype = ctypes.c_int
             lib.oracle_mesh.argtypes = [I, I, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, I, I, P]
             _lib = lib
@@ -107,3 +109,23 @@ def oracle_mesh(xy, twin, next_, origin, check: bool = True, fixed=None):
 def oracle_on(mesh, check: bool = True):
     return oracle_mesh(mesh.xy, mesh.twin, mesh.next, mesh.origin, check=check,
                        fixed=getattr(mesh, "fixed", None))
+
+
+def oracle_lepp(mesh, check: bool = True):
+    """Longest-edge propagation path of every triangle: (terminal edge key,
+    number of triangles) per triangle, as int32 arrays."""
+    lib = _load()
+    xy = np.ascontiguousarray(mesh.xy, dtype=np.float64)
+    twin = np.ascontiguousarray(mesh.twin, dtype=np.int32)
+    next_ = np.ascontiguousarray(mesh.next, dtype=np.int32)
+    origin = np.ascontiguousarray(mesh.origin, dtype=np.int32)
+    fixed = getattr(mesh, "fixed", None)
+    fixed = None if fixed is None else np.ascontiguousarray(fixed, dtype=np.uint8)
+    nt = origin.shape[0] // 3
+    terminal = np.zeros(max(nt, 1), np.int32)
+    length = np.zeros(max(nt, 1), np.int32)
+    rc = lib.oracle_lepp(xy.shape[0], origin.shape[0], _ptr(xy), _ptr(twin), _ptr(next_), _ptr(origin),
+                         _ptr(fixed), terminal.ctypes.data, length.ctypes.data)
+    if rc != 0 and check:
+        raise RuntimeError(f"oracle_lepp failed with code {rc}")
+    return terminal[:nt], length[:nt]

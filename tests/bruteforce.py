@@ -94,6 +94,27 @@ class Brute:
                     he[3 * t + i] |= FRONTIER
         return lg, he, seed
 
+    def lepp(self):
+        """Longest-edge propagation path of every triangle, by its definition:
+        (terminal edge key, triangles on the path)."""
+        lg = self.longest()
+        out = []
+        for t in range(self.T):
+            cur, n = t, 1
+            while True:
+                i = lg[cur]
+                a, b = self.tris[cur][i], self.tris[cur][(i + 1) % 3]
+                m = self.mate(cur, i)
+                if m is None or frozenset((a, b)) in self.segments:
+                    out.append((3 * cur + i, n))
+                    break
+                n += 1
+                if lg[m[0]] == m[1]:
+                    out.append((min(3 * cur + i, 3 * m[0] + m[1]), n))
+                    break
+                cur = m[0]
+        return out
+
     # ---- regions: union-find over internal edges ------------------------------
     def regions(self, frontier_of):
         parent = list(range(self.T))

@@ -273,3 +273,35 @@ def test_pslg_regions_stay_inside_the_domain():
     assert np.all(areas > 0)
     assert math.isclose(areas.sum(), tri_area.sum(), rel_tol=1e-9)
     assert v.size == T + 2 * (off.size - 1)
+
+
+
+@pytest.mark.parametrize("name", ["fan7_tip", "square", "square_segment"])
+def test_lepp_golden(name):
+    mesh, g = golden(name)
+    term, length = oracle.oracle_lepp(mesh)
+    assert term.tolist() == g["lepp_terminal"]
+    assert length.tolist() == g["lepp_length"]
+
+
+@pytest.mark.parametrize("kind", ["uniform", "cluster", "grid", "lattice"])
+@pytest.mark.parametrize("seed", range(6))
+def test_lepp_vs_bruteforce(kind, seed):
+    """Lepp of every triangle against the brute force (with and without input
+    segments); every path ends at a terminal edge (TERMINAL bit), and all the
+    triangles of one terminal-edge region end at the same edge."""
+    mesh = random_mesh(5100 + seed, [10, 40, 90, 160, 250, 400][seed], kind)
+    if seed % 2:
+        mesh = with_segments(mesh, seed, 0.15)
+    term, length = oracle.oracle_lepp(mesh)
+    b = Brute(mesh)
+    assert [(int(x), int(y)) for x, y in zip(term, length)] == b.lepp()
+    o = run(mesh)
+    assert np.all(o["he"][term] & TERMINAL)
+    lg, he, seed_flags = b.labels()
+    front = {(t, i) for t in range(b.T) for i in range(3) if he[3 * t + i] & FRONTIER}
+    comp = b.regions(lambda t, i: (t, i) in front)
+    by_region = {}
+    for t, r in enumerate(comp):
+        assert by_region.setdefault(r, term[t]) == term[t]
+    assert len(by_region) == int(o["tri"].sum())

@@ -283,6 +283,20 @@ def bench_single(args, pool, workload: str):
                    "paper_GBps": round(pb.get(k, 0) / (v / 1e6) / 1e9, 1),
                    "design_GBps": round(db.get(k, 0) / (v / 1e6) / 1e9, 1)} for k, v in us.items()}
 
+    # longest-edge propagation paths of every triangle (LabelMax + path kernels)
+    ctx.lepp(tri)
+    torch.cuda.synchronize()
+    le0, le1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    le0.record(stream)
+    for _ in range(5):
+        ctx.lepp(tri)
+    le1.record(stream)
+    torch.cuda.synchronize()
+    ctx.status()
+    lepp_ms = le0.elapsed_time(le1) / 5
+    lepp = {"ms_per_call": round(lepp_ms, 4), "triangles_per_s": round(T / (lepp_ms / 1e3), 1), "calls": 5}
+    log(f"lepp: {lepp}")
+
     # the paper's mixed configuration on the same mesh: label and traversal
     # on the GPU, the reparation phase sequentially on one host core
     off_g, verts_g, _ = (x.cpu().numpy() for x in out.trimmed())
@@ -338,7 +352,7 @@ def bench_single(args, pool, workload: str):
                    "polygons": F, "seeds": stats["seeds"], "tips": stats["tips"], "splits": stats["splits"],
                    "general_small": stats["general_small"], "general_big": stats["general_big"]},
         "roofline": roofline, "kernels": kernels, "cpu_baseline": cpu, "oracle_identical": identical,
-        "mixed": mixed,
+        "mixed": mixed, "lepp": lepp,
     }
 
 
@@ -572,7 +586,7 @@ def main():
             line.update(value=single["value"], ms_per_step=single["ms_per_step"], config=single["config"],
                         steps_ms=single["steps_ms"], roofline=single["roofline"], kernels=single["kernels"],
                         cpu_baseline=single["cpu_baseline"], oracle_identical=single["oracle_identical"],
-                        mixed=single["mixed"])
+                        mixed=single["mixed"], lepp=single["lepp"])
         if wl == "all" or wl.startswith("batched"):
             nb = args.batched if wl == "all" else int(wl[len("batched"):] or 2000)
             b = bench_batched(args, pool, nb)

@@ -164,6 +164,19 @@ int polylla_repair(polylla_ctx *ctx, const polylla_tri *tri, polylla_labels *lab
 int polylla_mesh(polylla_ctx *ctx, const polylla_tri *tri, polylla_labels *labels,
                  polylla_polys *out, hipStream_t stream);
 
+/* Longest-edge propagation path of every triangle (Rivara's Lepp, the basis of
+ * the Lepp-based algorithms the paper's conclusions name as the next use of
+ * its label kernels; it reuses LabelMax, Algorithm 2). Lepp(t) starts at t and
+ * steps to the neighbour across the current triangle's longest edge (the
+ * LONGEST order above) until that edge is also the neighbour's longest edge,
+ * a terminal edge, or is a boundary or segment side. terminal (device
+ * int32 [n_tri]) receives the key of that edge (its smaller half-edge; the
+ * half-edge itself on a boundary or segment side), length (device int32
+ * [n_tri]) the number of triangles on the path. All the triangles of one
+ * terminal-edge region end at its terminal edge. Paths longer than 32
+ * triangles are finished by pointer jumping over the unfinished ones. */
+int polylla_lepp(polylla_ctx *ctx, const polylla_tri *tri, int32_t *terminal, int32_t *length, hipStream_t stream);
+
 /* Algorithm 1 in the paper's "mixed" configuration (section "GPU parallel
  * algorithm": the reparation phase gains little in parallel, so the sequential
  * version of it is used): label and traversal run on the device as in

@@ -15,6 +15,10 @@ namespace polylla {
 
 __global__ void k_reset(Counters*, uint64_t*, int64_t, const int64_t*, int);
 __global__ void k_accumulate(Counters*);
+__global__ void k_lepp_chase(int64_t, const uint8_t*, const int32_t*, const uint8_t*, int32_t*, int32_t*, int4*,
+                             int32_t*, uint32_t*, Counters*);
+__global__ void k_lepp_jump(const int32_t*, const int32_t*, const int4*, int4*, const int32_t*, const uint32_t*);
+__global__ void k_lepp_finish(int32_t*, int32_t*, const int4*, const int32_t*, const uint32_t*, Counters*);
 __global__ void k_longest(int64_t, int64_t, const double*, const int32_t*, const int32_t*, uint8_t*, uint8_t*,
                           Counters*);
 template <bool COMPUTE>
@@ -169,13 +173,13 @@ constexpr int64_t kStageChunkHost = 4096; // staging ints a walk wave reserves a
 
 enum KernelId {
   KR_RESET, KR_LONGEST, KR_LABEL, KR_COMPACT, KR_PACK, KR_WALK, KR_GENERAL, KR_BIG, KR_HUGE, KR_SCAN, KR_VALIDATE,
-  KR_BATCH, KR_BIGW, KR_TIP, KR_SEEDS, KR_GENW, KR_GREBASE, KR_GFINISH, KR_N
+  KR_BATCH, KR_BIGW, KR_TIP, KR_SEEDS, KR_GENW, KR_GREBASE, KR_GFINISH, KR_LEPP, KR_N
 };
 const char* kKernelNames[KR_N] = {"k_reset",         "k_longest",       "k_label",          "k_compact_seeds",
                                   "k_pack_walk",     "k_walk",          "k_general_small",  "k_general_big",
                                   "k_general_huge",  "k_scan_emit",     "k_validate",       "k_batch_offsets",
                                   "k_general_big_wg", "k_tip",           "k_seeds",          "k_general_wave",
-                                  "k_group_rebase",  "k_group_finish"};
+                                  "k_group_rebase",  "k_group_finish",  "k_lepp"};
 
 // Event pair around one kernel launch when profiling is on.
 struct Prof {
@@ -679,6 +683,42 @@ int polylla_mesh(polylla_ctx* c, const polylla_tri* t, polylla_labels* l, polyll
   if (hipSetDevice(c->device) != hipSuccess) return POLYLLA_EHIP;
   c->last_batched = false;
   return mesh_run(c, t, l ? l->he : nullptr, l ? l->tri : nullptr, l ? l->vtx : nullptr, out, s, 0);
+}
+
+int polylla_lepp(polylla_ctx* c, const polylla_tri* t, int32_t* terminal, int32_t* length, hipStream_t s) {
+  if (!c) return POLYLLA_EINVAL;
+  int rc = check_tri(t);
+  if (rc) return rc;
+  const int64_t T = t->n_halfedges / 3;
+  if (T > 0 && (!terminal || !length)) return POLYLLA_EINVAL;
+  if ((rc = ensure(c, T, t->n_vertices))) return rc;
+  if (hipSetDevice(c->device) != hipSuccess) return POLYLLA_EHIP;
+  c->last_batched = false;
+  reset(c, s, nullptr);
+  if (T == 0) return launched();
+  Scratch* S = c->sc;
+  {
+    Prof p(c, s, KR_LONGEST);  // LabelMax: the Max byte of every triangle
+    hipLaunchKernelGGL(k_longest, dim3(grid_for((T + 1) / 2, 256, 1 << 20)), dim3(256), 0, s, T, t->n_vertices,
+                       t->xy, t->origin, t->twin, S->lg, (uint8_t*)nullptr, c->cnt);
+  }
+  // path states in two int4 arrays over the staging (>= 5T ints) and arena
+  // (>= 6T ints) scratch, the unfinished paths listed in the seed array
+  int4* sa = reinterpret_cast<int4*>(S->stage);
+  int4* sb = reinterpret_cast<int4*>(S->arena);
+  uint32_t* n_list = &c->cnt->n_lepp;
+  Prof p(c, s, KR_LEPP);
+  hipLaunchKernelGGL(k_lepp_chase, dim3((T + 255) / 256), dim3(256), 0, s, T, S->lg, t->twin, t->fixed, terminal,
+                     length, sa, S->seeds, n_list, c->cnt);
+  // every round doubles the path length covered: 2^26 * 32 triangles at most
+  constexpr int kRounds = 26;
+  for (int r = 0; r < kRounds; ++r) {
+    hipLaunchKernelGGL(k_lepp_jump, dim3(grid_for(T, 256, 1024)), dim3(256), 0, s, terminal, length,
+                       (const int4*)(r % 2 ? sb : sa), r % 2 ? sa : sb, S->seeds, n_list);
+  }
+  hipLaunchKernelGGL(k_lepp_finish, dim3(grid_for(T, 256, 1024)), dim3(256), 0, s, terminal, length,
+                     (const int4*)(kRounds % 2 ? sb : sa), S->seeds, n_list, c->cnt);
+  return launched();
 }
 
 int polylla_mesh_mixed(polylla_ctx* c, const polylla_tri* t, const int32_t* twin_host, const int32_t* origin_host,

@@ -454,3 +454,107 @@ __global__ __launch_bounds__(256) void k_pack_walk(int64_t nhe, const uint8_t* _
 }
 
 }  // namespace polylla
+
+namespace polylla {
+
+// ---------------------------------------------------------------------------
+// Longest-edge propagation paths (Rivara's Lepp): from triangle t, step to the
+// neighbour across the current triangle's longest edge (the Max bytes of
+// k_longest) until that edge is also the neighbour's longest edge (a terminal
+// edge) or a boundary or segment side. Per triangle: the key of the terminal
+// edge (its smaller half-edge; the half-edge itself on a boundary) and the
+// number of triangles on the path.
+//
+// k_lepp_chase follows each path for up to kLeppSteps triangles; a path not
+// finished by then keeps its state {last triangle reached, triangles so far,
+// -1} in `state` and is listed in `list`. k_lepp_jump then shortens the
+// listed paths by pointer jumping (each round reads one state array and
+// writes the other): a path ending at a finished triangle, or at a listed one
+// whose state is resolved, is resolved; otherwise it jumps to the end of the
+// other path, so every round doubles the length covered.
+constexpr int kLeppSteps = 32;
+
+__device__ __forceinline__ bool lepp_bounding(const int32_t* __restrict__ twin, const uint8_t* __restrict__ fixed,
+                                              int32_t h) {
+  return twin[h] < 0 || (fixed && fixed[h]);
+}
+
+__global__ __launch_bounds__(256) void k_lepp_chase(int64_t nt, const uint8_t* __restrict__ lg,
+                                                    const int32_t* __restrict__ twin,
+                                                    const uint8_t* __restrict__ fixed, int32_t* __restrict__ terminal,
+                                                    int32_t* __restrict__ length, int4* __restrict__ state,
+                                                    int32_t* __restrict__ list, uint32_t* __restrict__ n_list,
+                                                    Counters* cnt) {
+  const int64_t t = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (t >= nt) return;
+  const int32_t nhe = (int32_t)(3 * nt);
+  int32_t cur = (int32_t)t, n = 1, term = -1;
+  for (int k = 0; k < kLeppSteps; ++k) {
+    const uint8_t m = lg[cur];
+    const int32_t h = 3 * cur + (m < 3 ? m : 0);
+    if (lepp_bounding(twin, fixed, h)) {
+      term = h;
+      break;
+    }
+    const int32_t u = twin[h];
+    if (u >= nhe) {
+      set_error(cnt, POLYLLA_ETOPO);
+      term = h;
+      break;
+    }
+    const int32_t nb = u / 3;
+    ++n;
+    if (lg[nb] == (uint8_t)(u - 3 * nb)) {
+      term = h < u ? h : u;
+      break;
+    }
+    cur = nb;
+  }
+  if (term >= 0) {
+    terminal[t] = term;
+    length[t] = n;
+  } else {
+    terminal[t] = -1;
+    state[t] = make_int4(cur, n, -1, 0);
+    list[atomicAdd(n_list, 1u)] = (int32_t)t;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_lepp_jump(const int32_t* __restrict__ terminal,
+                                                   const int32_t* __restrict__ length,
+                                                   const int4* __restrict__ s_in, int4* __restrict__ s_out,
+                                                   const int32_t* __restrict__ list, const uint32_t* n_list) {
+  const uint32_t n = *n_list;
+  for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
+    const int32_t t = list[j];
+    int4 s = s_in[t];
+    if (s.z < 0) {
+      const int32_t cur = s.x;
+      if (terminal[cur] >= 0) {  // the path reached a triangle finished by the chase
+        s = make_int4(cur, s.y - 1 + length[cur], terminal[cur], 0);
+      } else {
+        const int4 o = s_in[cur];
+        s = o.z >= 0 ? make_int4(cur, s.y - 1 + o.y, o.z, 0) : make_int4(o.x, s.y - 1 + o.y, -1, 0);
+      }
+    }
+    s_out[t] = s;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_lepp_finish(int32_t* __restrict__ terminal, int32_t* __restrict__ length,
+                                                     const int4* __restrict__ s_fin, const int32_t* __restrict__ list,
+                                                     const uint32_t* n_list, Counters* cnt) {
+  const uint32_t n = *n_list;
+  for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
+    const int32_t t = list[j];
+    const int4 s = s_fin[t];
+    if (s.z < 0) {
+      set_error(cnt, POLYLLA_EDEGEN);  // more pointer-jumping rounds than the host launched
+      continue;
+    }
+    terminal[t] = s.z;
+    length[t] = s.y;
+  }
+}
+
+}  // namespace polylla

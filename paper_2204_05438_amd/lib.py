@@ -82,6 +82,7 @@ def load() -> ctypes.CDLL:
         lib.polylla_repair.argtypes = [P, ctypes.POINTER(_Tri), ctypes.POINTER(_Labels), ctypes.POINTER(_Polys),
                                        ctypes.POINTER(_Polys), P]
         lib.polylla_mesh.argtypes = [P, ctypes.POINTER(_Tri), ctypes.POINTER(_Labels), ctypes.POINTER(_Polys), P]
+        lib.polylla_lepp.argtypes = [P, ctypes.POINTER(_Tri), P, P, P]
         lib.polylla_mesh_mixed.argtypes = [P, ctypes.POINTER(_Tri), P, P, P, ctypes.POINTER(_Polys),
                                            ctypes.POINTER(ctypes.c_double), P]
         lib.polylla_mesh_noalloc.argtypes = [P, ctypes.POINTER(_Tri), ctypes.POINTER(_Labels),
@@ -98,7 +99,7 @@ def load() -> ctypes.CDLL:
         lib.polylla_strerror.argtypes = [ctypes.c_int]
         lib.polylla_strerror.restype = ctypes.c_char_p
         for f in ("polylla_ctx_create", "polylla_reserve", "polylla_reserve_batch", "polylla_label", "polylla_build", "polylla_repair",
-                  "polylla_mesh", "polylla_mesh_mixed", "polylla_mesh_noalloc", "polylla_mesh_batched", "polylla_validate", "polylla_status",
+                  "polylla_mesh", "polylla_lepp", "polylla_mesh_mixed", "polylla_mesh_noalloc", "polylla_mesh_batched", "polylla_validate", "polylla_status",
                   "polylla_stats", "polylla_set_param", "polylla_profile", "polylla_profile_read"):
             getattr(lib, f).restype = ctypes.c_int
         _lib = lib
@@ -381,6 +382,18 @@ class Context:
         lp = ctypes.byref(labels.c()) if labels is not None else None
         _check(load().polylla_mesh(self._h, ctypes.byref(t), lp, ctypes.byref(o), self._stream()), "polylla_mesh")
         return out
+
+    def lepp(self, tri: Tri):
+        """polylla_lepp: (terminal edge key, triangles on the path) of every
+        triangle's longest-edge propagation path, int32 device tensors."""
+        T = tri.n_tri
+        dev = tri.origin.device
+        terminal = torch.empty(max(T, 1), dtype=torch.int32, device=dev)
+        length = torch.empty(max(T, 1), dtype=torch.int32, device=dev)
+        t = tri.c()
+        _check(load().polylla_lepp(self._h, ctypes.byref(t), _ptr(terminal), _ptr(length), self._stream()),
+               "polylla_lepp")
+        return terminal[:T], length[:T]
 
     def mesh_mixed(self, tri: Tri, twin_host, origin_host):
         """polylla_mesh_mixed: label and traversal on the device, repair on the

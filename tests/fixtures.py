@@ -95,3 +95,16 @@ def permute_mesh(mesh, seed: int, block: int = 0, rotate: bool = True):
     nxt = (h - h % 3 + (h + 1) % 3).astype(np.int32)
     out = Mesh(xy=mesh.xy, origin=origin, twin=twin, next=nxt, lattice=mesh.lattice, meta=dict(mesh.meta))
     return out, tri_map, rot
+
+
+def spiral_fan(n):
+    """n >= 7 triangles around vertex 0, spoke k (to vertex k+1) of length 1 +
+    0.001 k, rims shorter than spokes: triangle i's longest edge is spoke i+1
+    (spoke n-1 for the last),
+    so Lepp(t_i) runs to spoke n-1: n - i triangles (2 for the last one),
+    terminal key 3n - 4 (half-edge n -> 0 of triangle n-2)."""
+    ang = 2 * np.pi * np.arange(n) / n
+    r = 1.0 + 0.001 * np.arange(n)
+    xy = np.concatenate([[[0.0, 0.0]], np.stack([r * np.cos(ang), r * np.sin(ang)], 1)])
+    tris = [(0, i + 1, i + 2) for i in range(n - 1)] + [(0, n, 1)]
+    return mesh_from_triangles(xy, tris)

@@ -5,7 +5,7 @@ import pytest
 
 import oracle
 from bruteforce import csr_cycles
-from fixtures import empty_mesh, golden, golden_names, permute_mesh, random_mesh
+from fixtures import empty_mesh, golden, golden_names, permute_mesh, random_mesh, spiral_fan
 from meshgen.gen import config_mesh as _config_mesh
 
 pytestmark = pytest.mark.gpu
@@ -290,6 +290,46 @@ def test_batched_pslg(ctx):
     finally:
         ctx.set_param(lib.PARAM_BATCH_GROUP_HE, (1 << 30) - (1 << 24))
     check_batch_against_oracle(meshes, out, labels, batch.he_off_host.numpy())
+
+
+def gpu_lepp(ctx, mesh):
+    from paper_2204_05438_amd import lib
+    term, length = ctx.lepp(lib.Tri.from_mesh(mesh))
+    ctx.status()
+    return term.cpu().numpy(), length.cpu().numpy()
+
+
+@pytest.mark.parametrize("name", ["fan7_tip", "square", "square_segment"])
+def test_lepp_golden(ctx, name):
+    _say(f"lepp golden {name}")
+    mesh, g = golden(name)
+    term, length = gpu_lepp(ctx, mesh)
+    assert term.tolist() == g["lepp_terminal"] and length.tolist() == g["lepp_length"]
+
+
+def test_lepp_long_paths(ctx):
+    """Paths far longer than the chase's 32 steps, finished by pointer
+    jumping: the spiral fan's closed-form lengths, and the oracle."""
+    _say("lepp spiral fans")
+    for n in (40, 300, 5000):
+        mesh = spiral_fan(n)
+        term, length = gpu_lepp(ctx, mesh)
+        expect = np.array([n - i for i in range(n - 1)] + [2], np.int32)
+        assert (term == 3 * n - 4).all() and np.array_equal(length, expect), n
+        ot, ol = oracle.oracle_lepp(mesh)
+        assert np.array_equal(term, ot) and np.array_equal(length, ol)
+
+
+@pytest.mark.parametrize("name", ["random", "uniform10k", "pslg20k", "mixed200k", "grid10m"])
+def test_lepp_against_oracle(ctx, name):
+    """Longest-edge propagation paths against the oracle."""
+    _say(f"lepp {name}")
+    meshes = ([random_mesh(6000 + k, [20, 300, 3000][k % 3], ["uniform", "cluster", "lattice"][k % 3])
+               for k in range(6)] if name == "random" else [config_mesh(name)])
+    for mesh in meshes:
+        term, length = gpu_lepp(ctx, mesh)
+        ot, ol = oracle.oracle_lepp(mesh)
+        assert np.array_equal(term, ot) and np.array_equal(length, ol)
 
 
 def test_uniform5m_large_regions(ctx):

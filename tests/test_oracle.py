@@ -7,7 +7,7 @@ import pytest
 
 import oracle
 from bruteforce import BARRIER, FRONTIER, REPAIRED, TERMINAL, Brute, canonical, csr_cycles
-from fixtures import empty_mesh, golden, golden_names, random_mesh
+from fixtures import empty_mesh, golden, golden_names, random_mesh, spiral_fan
 from meshgen.gen import config_mesh, mesh_from_points
 
 
@@ -305,3 +305,12 @@ def test_lepp_vs_bruteforce(kind, seed):
     for t, r in enumerate(comp):
         assert by_region.setdefault(r, term[t]) == term[t]
     assert len(by_region) == int(o["tri"].sum())
+
+
+@pytest.mark.parametrize("n", [7, 40, 300])
+def test_lepp_spiral_fan_closed_form(n):
+    """A fan whose spokes grow by 0.001 per step: every path runs to the last
+    spoke, n - i triangles from triangle i (2 from the last one)."""
+    term, length = oracle.oracle_lepp(spiral_fan(n))
+    assert (term == 3 * n - 4).all()
+    assert length.tolist() == [n - i for i in range(n - 1)] + [2]

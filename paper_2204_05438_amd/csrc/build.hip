@@ -2841,20 +2841,39 @@ __global__ __launch_bounds__(256) void k_group_rebase(const int32_t* __restrict_
                                                       const int64_t* __restrict__ vtx_off) {
   const int64_t h0 = he_off[0], v0 = vtx_off[0];
   const int64_t H = he_off[nm] - h0;
-  // each block takes one contiguous chunk, so a thread's mesh index only
-  // moves forward over the few meshes the chunk spans
-  const int64_t chunk = ((H + gridDim.x - 1) / gridDim.x + 255) / 256 * 256;
+  // each block takes one contiguous chunk, so a thread's mesh only moves
+  // forward over the few meshes the chunk spans; the mesh's bases stay in
+  // registers, and four elements per thread are loaded together
+  constexpr int kU = 4;
+  const int64_t step = (int64_t)blockDim.x * kU;
+  const int64_t chunk = ((H + gridDim.x - 1) / gridDim.x + step - 1) / step * step;
   const int64_t c0 = (int64_t)blockIdx.x * chunk, c1 = min(H, c0 + chunk);
-  int64_t h = c0 + threadIdx.x;
-  if (h >= c1) return;
-  int64_t m = mesh_of(he_off, nm, h0 + h);
-  for (; h < c1; h += blockDim.x) {
-    while (m + 1 < nm && he_off[m + 1] <= h0 + h) ++m;
-    const int64_t hb = he_off[m] - h0, hn = he_off[m + 1] - he_off[m];
-    const int64_t vb = vtx_off[m] - v0, vn = vtx_off[m + 1] - vtx_off[m];
-    const int32_t tw = twin[h0 + h], og = origin[h0 + h];
-    tw_g[h] = tw == -1 ? -1 : ((tw >= 0 && tw < hn) ? (int32_t)(tw + hb) : INT32_MIN);
-    or_g[h] = (og >= 0 && og < vn) ? (int32_t)(og + vb) : -1;
+  if (c0 + threadIdx.x >= c1) return;
+  int64_t m = mesh_of(he_off, nm, h0 + c0 + threadIdx.x);
+  int64_t hb = he_off[m] - h0, he = he_off[m + 1] - h0, vb = vtx_off[m] - v0, vn = vtx_off[m + 1] - vtx_off[m];
+  for (int64_t g = c0 + threadIdx.x; g < c1; g += step) {
+    int32_t tw[kU], og[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int64_t h = g + (int64_t)blockDim.x * u;
+      tw[u] = h < c1 ? twin[h0 + h] : -1;
+      og[u] = h < c1 ? origin[h0 + h] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int64_t h = g + (int64_t)blockDim.x * u;
+      if (h >= c1) break;
+      while (h >= he) {  // the next mesh (rarely more than one step)
+        ++m;
+        hb = he;
+        he = he_off[m + 1] - h0;
+        vb = vtx_off[m] - v0;
+        vn = vtx_off[m + 1] - vtx_off[m];
+      }
+      const int64_t hn = he - hb;
+      tw_g[h] = tw[u] == -1 ? -1 : ((tw[u] >= 0 && tw[u] < hn) ? (int32_t)(tw[u] + hb) : INT32_MIN);
+      or_g[h] = (og[u] >= 0 && og[u] < vn) ? (int32_t)(og[u] + vb) : -1;
+    }
   }
 }
 

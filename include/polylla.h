@@ -265,6 +265,32 @@ typedef struct {
 int polylla_mesh_batched(polylla_ctx *ctx, const polylla_batch *batch, polylla_labels *labels,
                          polylla_batch_out *out, hipStream_t stream);
 
+/* On-device input (so that a caller with no host mesh sends nothing over
+ * PCIe): writes the Delaunay triangulation of a jittered g x g point grid
+ * into device arrays in the layout above. Point of cell (i, j), 0 <= i, j < g:
+ * ((i + 0.5 + jitter (2u - 1)) / g, (j + 0.5 + jitter (2w - 1)) / g), with
+ * u, w in [0, 1) the top 53 bits of SplitMix64 (Steele, Lea and Flood 2014)
+ * at counters 2c and 2c + 1, c = j g + i, seeded by `seed`, then rounded to
+ * the nearest multiple of 2^-28 (so the orientation and in-circle tests are
+ * exact integers). The triangulation is unique for points with no four on a
+ * circle. Vertex ids: 32 x 32 tiles of grid points in tile-row order (row by
+ * row within a tile), so that neighbouring triangles have nearby ids;
+ * triangles: two per grid cell in the same tiled order, then those that fill
+ * the dents of the boundary; the arrays are otherwise what any Delaunay
+ * triangulation of the points in this layout holds, up to the numbering.
+ * Arguments: 2 <= g <= 18000; 0 <= jitter < 0.5 (cells stay convex
+ * quadrilaterals); xy (device, [2 g^2] doubles); twin, origin (device,
+ * [cap_halfedges] int32, cap_halfedges >= 6 g^2, else ECAPACITY);
+ * n_halfedges (host) receives 3 x the triangle count (2 g^2 - 2 - hull
+ * vertices); flip_rounds (host, may be NULL) the number of rounds of parallel
+ * edge flips. Synchronous: waits for `stream` (the flip rounds read a count on
+ * the host). Allocates a work space of about 32 g^2 bytes, kept by the context.
+ * Errors: EINVAL for bad arguments, ENOMEM, EDEGEN if the flips do not end,
+ * EINTERNAL on a work-space overflow. */
+int polylla_gen_grid(polylla_ctx *ctx, int64_t g, double jitter, uint64_t seed, double *xy, int32_t *twin,
+                     int32_t *origin, int64_t cap_halfedges, int64_t *n_halfedges, int32_t *flip_rounds,
+                     hipStream_t stream);
+
 /* Full input check on the device (layout of next, index ranges, twin
  * involution and endpoints). Waits for the stream; returns the first error. */
 int polylla_validate(polylla_ctx *ctx, const polylla_tri *tri, hipStream_t stream);

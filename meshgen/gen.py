@@ -455,3 +455,45 @@ def validate(mesh: Mesh) -> dict:
     h = int(np.count_nonzero(tw < 0))
     nref = int(np.unique(o).shape[0])
     return {"T": T, "hull_edges": h, "referenced_vertices": nref}
+
+
+# --------------------------------------------------------------------------
+# The point grid that polylla_gen_grid draws on the device, drawn on the host
+# from the same counter-based generator (SplitMix64, Steele, Lea and Flood
+# 2014), for checking the on-device triangulation against mesh_from_points.
+# --------------------------------------------------------------------------
+
+_M64 = np.uint64(0xFFFFFFFFFFFFFFFF)
+
+
+def splitmix64(seed: int, k: np.ndarray) -> np.ndarray:
+    """Output k of the SplitMix64 stream that starts at state `seed`."""
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed & 0xFFFFFFFFFFFFFFFF) + (np.asarray(k, dtype=np.uint64) + np.uint64(1)) * np.uint64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        return z ^ (z >> np.uint64(31))
+
+
+def counter_grid_points(g: int, jitter: float, seed: int) -> np.ndarray:
+    """[g*g, 2] points of cell c = j g + i: ((i + 0.5 + jitter (2u - 1)) / g,
+    (j + 0.5 + jitter (2w - 1)) / g), u and w the top 53 bits of outputs 2c
+    and 2c + 1 as fractions in [0, 1)."""
+    c = np.arange(g * g, dtype=np.uint64)
+    u = (splitmix64(seed, 2 * c) >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    w = (splitmix64(seed, 2 * c + np.uint64(1)) >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    j, i = np.divmod(np.arange(g * g, dtype=np.int64), g)
+    x = (i.astype(np.float64) + 0.5 + jitter * (2.0 * u - 1.0)) / g
+    y = (j.astype(np.float64) + 0.5 + jitter * (2.0 * w - 1.0)) / g
+    return np.stack([x, y], axis=1)
+
+
+def tiled_grid_id(i, j, g: int, tile: int = 32):
+    """Vertex id of grid point (i, j) in polylla_gen_grid's numbering: tiles
+    of tile x tile points in row order, points row by row inside a tile."""
+    i = np.asarray(i, dtype=np.int64)
+    j = np.asarray(j, dtype=np.int64)
+    tj, ti = j // tile, i // tile
+    hj = np.minimum(tile, g - tile * tj)
+    wi = np.minimum(tile, g - tile * ti)
+    return tile * g * tj + tile * hj * ti + (j - tile * tj) * wi + (i - tile * ti)

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpolylla.so")
-SOURCES = ["label.hip", "build.hip", "api.hip", "host_repair.hip"]
+SOURCES = ["label.hip", "build.hip", "api.hip", "host_repair.hip", "gen.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("POLYLLA_ARCH", "gfx950")
 

@@ -61,6 +61,9 @@ __global__ void k_group_finish(int64_t, const int64_t*, const int64_t*, const in
 __global__ void k_group_advance(const int64_t*, int64_t*, bool, int64_t, int64_t*, int64_t*, int64_t*, int64_t,
                                 int64_t, const Counters*);
 __global__ void k_batch_close(const int64_t*, int64_t, int64_t*);
+size_t gen_ws_bytes(int64_t g);
+int gen_grid_run(int64_t g, double jitter, uint64_t seed, double* xy, int32_t* twin, int32_t* origin,
+                 int64_t cap_tri, void* ws, Counters* cnt, hipStream_t s, int64_t* n_tri, int* rounds);
 int host_repair(int64_t, const int32_t*, const int32_t*, uint8_t*, int64_t, const int32_t*, const int32_t*,
                 const int32_t*, int32_t*, int32_t*, int32_t*, int64_t, int64_t, int64_t*, int64_t*);
 
@@ -147,6 +150,8 @@ struct polylla_ctx {
   uint32_t gen_wave_max = kGenWaveMax;  // declined short polygons up to which each gets a wave
   int32_t lds_max = 4096;               // region size limit of the 1024-thread LDS workgroup
   int32_t mem_max = (int32_t)kMemRegionMax;  // region size limit of the global-memory workgroup
+  void* gen_ws = nullptr;  // work space of polylla_gen_grid
+  size_t gen_ws_cap = 0;
   int walk_blocks = 640;  // persistent grid of the walk kernel (swept at 10M: 512 851, 640 782, 768 791 us)
   // second stream: the workgroup region kernel runs beside the per-lane one
   // (they touch disjoint regions); fork and join through events
@@ -164,11 +169,11 @@ struct polylla_ctx {
 
 namespace {
 
+constexpr int64_t kGenGridMax = 18000;  // 6 g^2 half-edge ids stay below 2^31
 constexpr int64_t kTile = 2048;  // triangles per tile of k_label
 constexpr size_t kMaxProfiled = 8192;
 constexpr int64_t kScanTileHost = 2048;   // polygons per tile of k_scan_emit
 constexpr int64_t kWalkBlocks = 2048;     // persistent grid of k_walk
-constexpr int64_t kWalkWaves = kWalkBlocks * 4;
 constexpr int64_t kStageChunkHost = 4096; // staging ints a walk wave reserves at a time
 
 enum KernelId {
@@ -594,6 +599,7 @@ void polylla_ctx_destroy(polylla_ctx* c) {
   (void)hipDeviceSynchronize();
   free_scratch(c);
   free_group(c);
+  if (c->gen_ws) (void)hipFree(c->gen_ws);
   dfree(&c->cnt);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   (void)hipEventDestroy(c->join);
@@ -890,6 +896,40 @@ int polylla_mesh_batched(polylla_ctx* c, const polylla_batch* b, polylla_labels*
                        out->poly_off);
   }
   return launched();
+}
+
+int polylla_gen_grid(polylla_ctx* c, int64_t g, double jitter, uint64_t seed, double* xy, int32_t* twin,
+                     int32_t* origin, int64_t cap_halfedges, int64_t* n_halfedges, int32_t* flip_rounds,
+                     hipStream_t s) {
+  if (!c || !xy || !twin || !origin || !n_halfedges) return POLYLLA_EINVAL;
+  if (g < 2 || g > kGenGridMax || !(jitter >= 0.0 && jitter < 0.5)) return POLYLLA_EINVAL;
+  if (cap_halfedges < 6 * g * g) return POLYLLA_ECAPACITY;
+  if (hipSetDevice(c->device) != hipSuccess) return POLYLLA_EHIP;
+  const size_t need = gen_ws_bytes(g);
+  if (need > c->gen_ws_cap) {
+    if (hipStreamSynchronize(s) != hipSuccess) return POLYLLA_EHIP;
+    if (c->gen_ws) (void)hipFree(c->gen_ws);
+    c->gen_ws = nullptr;
+    c->gen_ws_cap = 0;
+    if (hipMalloc(&c->gen_ws, need) != hipSuccess) {
+      (void)hipGetLastError();
+      c->gen_ws = nullptr;
+      return POLYLLA_ENOMEM;
+    }
+    c->gen_ws_cap = need;
+  }
+  c->last_batched = false;
+  hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, c->cnt, (uint64_t*)nullptr, (int64_t)0,
+                     (const int64_t*)nullptr, 0);
+  int64_t T = 0;
+  int rounds = 0;
+  int rc = gen_grid_run(g, jitter, seed, xy, twin, origin, cap_halfedges / 3, c->gen_ws, c->cnt, s, &T, &rounds);
+  const int st = polylla_status(c, s);
+  if (rc == POLYLLA_OK) rc = st;
+  if (rc) return rc;
+  *n_halfedges = 3 * T;
+  if (flip_rounds) *flip_rounds = rounds;
+  return POLYLLA_OK;
 }
 
 int polylla_validate(polylla_ctx* c, const polylla_tri* t, hipStream_t s) {

@@ -88,6 +88,9 @@ def load() -> ctypes.CDLL:
         lib.polylla_mesh_noalloc.argtypes = [P, ctypes.POINTER(_Tri), ctypes.POINTER(_Labels),
                                              ctypes.POINTER(_Polys), P]
         lib.polylla_validate.argtypes = [P, ctypes.POINTER(_Tri), P]
+        lib.polylla_gen_grid.argtypes = [P, ctypes.c_int64, ctypes.c_double, ctypes.c_uint64, P, P, P,
+                                         ctypes.c_int64, ctypes.POINTER(ctypes.c_int64),
+                                         ctypes.POINTER(ctypes.c_int32), P]
         lib.polylla_mesh_batched.argtypes = [P, ctypes.POINTER(_Batch), ctypes.POINTER(_Labels),
                                              ctypes.POINTER(_BatchOut), P]
         lib.polylla_status.argtypes = [P, P]
@@ -99,7 +102,7 @@ def load() -> ctypes.CDLL:
         lib.polylla_strerror.argtypes = [ctypes.c_int]
         lib.polylla_strerror.restype = ctypes.c_char_p
         for f in ("polylla_ctx_create", "polylla_reserve", "polylla_reserve_batch", "polylla_label", "polylla_build", "polylla_repair",
-                  "polylla_mesh", "polylla_lepp", "polylla_mesh_mixed", "polylla_mesh_noalloc", "polylla_mesh_batched", "polylla_validate", "polylla_status",
+                  "polylla_mesh", "polylla_lepp", "polylla_mesh_mixed", "polylla_mesh_noalloc", "polylla_mesh_batched", "polylla_validate", "polylla_gen_grid", "polylla_status",
                   "polylla_stats", "polylla_set_param", "polylla_profile", "polylla_profile_read"):
             getattr(lib, f).restype = ctypes.c_int
         _lib = lib
@@ -438,6 +441,27 @@ class Context:
         _check(load().polylla_mesh_batched(self._h, ctypes.byref(b), lp, ctypes.byref(o), self._stream()),
                "polylla_mesh_batched")
         return out
+
+    def gen_grid(self, g: int, jitter: float = 0.45, seed: int = 3, with_next: bool = False):
+        """polylla_gen_grid: the Delaunay triangulation of a jittered g x g
+        grid, generated on the device. Returns (Tri, flip rounds)."""
+        dev = torch.device("cuda", self.device)
+        n = g * g if 2 <= g <= 18000 else 1  # the library rejects other sizes
+        xy = torch.empty((n, 2), dtype=torch.float64, device=dev)
+        cap = 6 * n
+        twin = torch.empty(cap, dtype=torch.int32, device=dev)
+        origin = torch.empty(cap, dtype=torch.int32, device=dev)
+        n_he = ctypes.c_int64(0)
+        rounds = ctypes.c_int32(0)
+        _check(load().polylla_gen_grid(self._h, int(g), float(jitter), int(seed) & (2 ** 64 - 1), _ptr(xy),
+                                       _ptr(twin), _ptr(origin), cap, ctypes.byref(n_he), ctypes.byref(rounds),
+                                       self._stream()), "polylla_gen_grid")
+        H = n_he.value
+        nxt = None
+        if with_next:
+            h = torch.arange(H, dtype=torch.int32, device=dev)
+            nxt = h - h % 3 + (h + 1) % 3
+        return Tri(xy=xy, twin=twin[:H], next=nxt, origin=origin[:H]), rounds.value
 
     def validate(self, tri: Tri) -> int:
         t = tri.c()

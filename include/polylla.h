@@ -316,9 +316,9 @@ int polylla_stats(polylla_ctx *ctx, int64_t *out, int n);
 #define POLYLLA_PARAM_WALK_CAP 1
 /* POLYLLA_PARAM_WALK_BLOCKS (8..2048, multiple of 8): workgroups of 256
  * threads of the walk kernel; fewer keep the polygons in flight within each
- * XCD's L2, more hide more latency. Default 640; at most three per compute
- * unit are resident (768), so a larger grid only adds workgroups that find no
- * work. */
+ * XCD's L2, more hide more latency. Default 1280; at most six per compute
+ * unit are resident (1536), so a larger grid only adds workgroups that find
+ * no work. */
 #define POLYLLA_PARAM_WALK_BLOCKS 2
 /* POLYLLA_PARAM_GEN_WAVE_MAX (0..2^32-2, default 8192): the short polygons
  * with a repeated vertex that the single-tip path declines are repaired one

@@ -19,7 +19,7 @@ import torch
 
 from . import lib
 
-BLOCKS = (256, 384, 512, 640, 768, 1024)
+BLOCKS = (512, 768, 1024, 1280, 1536)
 CAPS = (12, 16, 20, 24)
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "polylla", "tune.json")
 

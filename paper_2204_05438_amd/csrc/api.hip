@@ -34,7 +34,7 @@ __global__ void k_general_small(const int32_t*, bool, int32_t, int64_t, const in
                                 const int32_t*, uint8_t*, uint8_t*, int32_t*, int64_t, int32_t*, int64_t, PolyState,
                                 const int32_t*, const uint32_t*, uint32_t, Counters*);
 template <bool REPAIR>
-__global__ void k_tip(int32_t, int64_t, const int32_t*, const int32_t*, uint8_t*, uint8_t*, int32_t*, int64_t,
+__global__ void k_tip(int32_t, int64_t, const int32_t*, const int32_t*, const int32_t*, uint8_t*, uint8_t*, int32_t*, int64_t,
                       int32_t*, int64_t, PolyState, const int32_t*, int32_t*, int64_t, Counters*);
 template <bool REPAIR, int NT, int KC, int LC, int HB>
 __global__ void k_general_big(const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*, const int32_t*,
@@ -152,7 +152,7 @@ struct polylla_ctx {
   int32_t mem_max = (int32_t)kMemRegionMax;  // region size limit of the global-memory workgroup
   void* gen_ws = nullptr;  // work space of polylla_gen_grid
   size_t gen_ws_cap = 0;
-  int walk_blocks = 640;  // persistent grid of the walk kernel (swept at 10M: 512 851, 640 782, 768 791 us)
+  int walk_blocks = 1280;  // persistent grid of the walk kernel (swept at 10M: 768 516, 1024 474, 1280 462, 1536 474 us)
   // second stream: the workgroup region kernel runs beside the per-lane one
   // (they touch disjoint regions); fork and join through events
   hipStream_t side = nullptr;
@@ -471,11 +471,11 @@ int run_build(polylla_ctx* c, const polylla_tri* t, const int32_t* list, bool fr
     Prof p(c, s, KR_TIP);
     const int gt = 2048;  // one lane per short polygon with a repeat, grid-stride
     if (repair)
-      hipLaunchKernelGGL(k_tip<true>, dim3(gt), dim3(64), 0, s, nhe, t->n_vertices, t->twin, t->origin, he, vtx,
+      hipLaunchKernelGGL(k_tip<true>, dim3(gt), dim3(64), 0, s, nhe, t->n_vertices, t->twin, t->origin, c->sc->wk, he, vtx,
                          c->sc->stage, c->sc->stage_cap, c->sc->arena, c->sc->arena_cap, ps, c->sc->deferred, c->sc->rest, c->sc->rest_cap,
                          c->cnt);
     else
-      hipLaunchKernelGGL(k_tip<false>, dim3(gt), dim3(64), 0, s, nhe, t->n_vertices, t->twin, t->origin, he, vtx,
+      hipLaunchKernelGGL(k_tip<false>, dim3(gt), dim3(64), 0, s, nhe, t->n_vertices, t->twin, t->origin, c->sc->wk, he, vtx,
                          c->sc->stage, c->sc->stage_cap, c->sc->arena, c->sc->arena_cap, ps, c->sc->deferred, c->sc->rest, c->sc->rest_cap,
                          c->cnt);
   }

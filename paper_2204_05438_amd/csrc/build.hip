@@ -5,14 +5,16 @@
 //                   frontier half-edges of the region from its start
 //                   half-edge with the region on the left (turning about each
 //                   vertex through internal edges), keeping the vertex ids in
-//                   LDS (interleaved [slot][lane]). A cycle with no repeated
-//                   vertex and at most kWalkCap vertices is complete and is
-//                   staged unrotated with the slot of its smallest vertex;
-//                   cycles with a tip or another repeated vertex are queued
-//                   for the tip path, longer ones for the region path.
-// k_tip           : one lane per short polygon with a repeated vertex; a
-//                   single tip is repaired from the staged cycle, other
-//                   cases are left to the region path.
+//                   LDS (interleaved [slot][lane]). A cycle with at most
+//                   kWalkCap vertices that a signature filter finds free of
+//                   repeated vertices is complete and is staged unrotated
+//                   with the slot of its smallest vertex; the cycles it flags
+//                   (every one with a tip or another repeated vertex) are
+//                   queued for the tip path, longer ones for the region path.
+// k_tip           : one lane per flagged short polygon, 64 per wave: walks
+//                   the cycle again from its start half-edge, stages it if it
+//                   has no repeated vertex after all, repairs a single tip,
+//                   and leaves other cases to the region path.
 // k_general_big   : the region path: a breadth-first search gathers the
 //                   region into LDS as links between local edges, then
 //                   barrier marking, tips, the repair and the pieces run
@@ -170,10 +172,22 @@ __global__ __launch_bounds__(256) void k_walk(const int32_t* __restrict__ list, 
                                               const int32_t* __restrict__ wk, int32_t* __restrict__ stage,
                                               int64_t stage_cap, PolyState ps, int32_t* __restrict__ deferred,
                                               int64_t deferred_cap, int walk_cap, Counters* cnt) {
-  __shared__ int32_t buf[kWalkCap][256];   // vertex ids of the cycle, per lane
-  __shared__ int32_t hbuf[kWalkCap][256];  // its half-edges (staged for polygons with a repeat)
+  __shared__ int32_t buf[kWalkCap + 1][256];  // vertex ids of the cycle, per lane (+ a spare row)
   walk_cap = walk_cap < 1 ? 1 : (walk_cap > kWalkCap ? kWalkCap : walk_cap);
   const int lane = threadIdx.x & 63;
+  // per-wave queue of short polygons with a repeated vertex (see below)
+  __shared__ int32_t dq[4][64];
+  const int wv_id = threadIdx.x >> 6;
+  int dq_n = 0;  // wave-uniform
+  auto flush_deferred = [&]() {
+    if (dq_n > 0) {
+      uint32_t b = 0;
+      if (lane == 0) b = atomicAdd(&cnt->n_deferred, (uint32_t)dq_n);
+      b = __shfl(b, 0, 64);
+      if (lane < dq_n) deferred[b + lane] = dq[wv_id][lane];
+      dq_n = 0;
+    }
+  };
   const int32_t R = (int32_t)cnt->n_seeds;
   const int32_t nt = nhe / 3;
   const int xcd = blockIdx.x % kXcds;
@@ -189,7 +203,12 @@ __global__ __launch_bounds__(256) void k_walk(const int32_t* __restrict__ list, 
   // lane state; the cycle's vertices are kept in LDS column buf[.][threadIdx.x]
   int32_t idx = -1;
   int32_t s = -1, t = 0, ci = 0, L = 0, minv = 0, minpos = 0, minhe = -1, steps = 0;
-  uint64_t sig = 0;  // bit (v & 63) of every vertex so far: repeat pre-filter
+  // repeated-vertex filter: two 64-bit signatures of the vertices so far (bit
+  // v & 63 and bit (v ^ v >> 5 ^ v >> 11) & 63). A cycle in which a vertex
+  // finds both its bits set already is flagged and goes to the tip path, which
+  // checks it exactly: every cycle with a repeated vertex is flagged, and
+  // about one in five hundred without one.
+  uint64_t sig = 0, sig2 = 0;
   bool complex = false, pending = false, fresh = false, done = false;
   int result = kSimple;
   WalkRec r, rn;
@@ -247,6 +266,7 @@ __global__ __launch_bounds__(256) void k_walk(const int32_t* __restrict__ list, 
         complex = false;
         done = false;
         sig = 0;
+        sig2 = 0;
         minv = 0x7FFFFFFF;
         minpos = 0;
         minhe = -1;
@@ -262,81 +282,84 @@ __global__ __launch_bounds__(256) void k_walk(const int32_t* __restrict__ list, 
       }
     }
     // ---- advance every busy lane up to its next load
-    if (idx >= 0 && !pending && !done) {
-      if (fresh && FROM_SEEDS) {
-        // seed triangle: its first frontier half-edge, else turn about vertex 0
-        if (r.w0 < 0) ci = 0;
-        else if (r.w1 < 0) ci = 1;
-        else if (r.w2 < 0) ci = 2;
-        else ci = -1;
-        if (ci < 0) {
-          const int32_t tw = r.w0;
-          if ((uint32_t)tw >= (uint32_t)nhe) {
-            result = kInvalid;
-            done = true;
-          } else {
-            t = tw / 3;
-            ci = next_local(tw - 3 * t);
-            pending = true;
-          }
+    const bool busy = idx >= 0 && !pending && !done;
+    if (busy && fresh && FROM_SEEDS) {
+      // seed triangle: its first frontier half-edge, else turn about vertex 0
+      if (r.w0 < 0) ci = 0;
+      else if (r.w1 < 0) ci = 1;
+      else if (r.w2 < 0) ci = 2;
+      else ci = -1;
+      if (ci < 0) {
+        const int32_t tw = r.w0;
+        if ((uint32_t)tw >= (uint32_t)nhe) {
+          result = kInvalid;
+          done = true;
         } else {
-          s = 3 * t + ci;
-        }
-      }
-      fresh = false;
-      // At most three frontier half-edges of one triangle follow each other
-      // (a triangle with three is its own region and closes at the fourth
-      // check), so four unrolled steps take every lane to its next crossing
-      // (a load) or to the end of its cycle; no divergent loop.
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        if (pending || done) continue;
-        const int32_t wv = r.w(ci);
-        if (wv < 0) {
-          // frontier half-edge (a barrier-edge tip shows as a repeated vertex)
-          const int32_t c = 3 * t + ci;
-          if (s < 0) {
-            s = c;  // start found by turning about the seed's vertex 0
-          } else if (L > 0 && c == s) {
-            done = true;
-            continue;
-          }
-          if (L == walk_cap) {
-            result = kLarge;
-            done = true;
-            continue;
-          }
-          const int32_t v = -1 - wv;
-          buf[L][threadIdx.x] = v;
-          hbuf[L][threadIdx.x] = c;
-          if (!complex) {
-            const uint64_t bit = 1ull << (v & 63);
-            bool rep = false;
-            if (sig & bit)
-              for (int j = 0; j < L; ++j) rep |= (buf[j][threadIdx.x] == v);
-            complex = rep;
-            sig |= bit;
-            if (v < minv) {
-              minv = v;
-              minhe = c;
-              minpos = L;
-            }
-          }
-          ++L;
-          ci = next_local(ci);
-        } else {
-          // internal edge: cross it, turning about the current vertex
-          const int32_t tw = wv;
-          if ((uint32_t)tw >= (uint32_t)nhe || ++steps > nhe) {
-            result = kInvalid;
-            done = true;
-            continue;
-          }
           t = tw / 3;
           ci = next_local(tw - 3 * t);
           pending = true;
         }
+      } else {
+        s = 3 * t + ci;
       }
+    }
+    if (busy) fresh = false;
+    const bool act = busy && !pending && !done;
+    {
+      // In the triangle just entered, from local index ci: the frontier
+      // half-edges that follow one another (their origins are the next
+      // vertices of the cycle), then the first internal one, which the lane
+      // crosses (turning about the current vertex). Entered across an edge,
+      // a triangle has at most two such frontier half-edges before that edge
+      // comes round again; the seed triangle of a region of one triangle has
+      // three, and the cycle closes at its start after them. Written as
+      // selects on per-lane predicates (the vertex store goes to a spare row
+      // when the lane emits nothing), so the wave runs it without branches.
+      const int p0 = ci, p1 = next_local(p0), p2 = next_local(p1);
+      const int32_t wa = r.w(p0), wb = r.w(p1), wc = r.w(p2);
+      const int32_t base = t + t + t;
+      bool live = act;
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const int32_t wv = j == 0 ? wa : (j == 1 ? wb : wc);
+        const int32_t c = base + (j == 0 ? p0 : (j == 1 ? p1 : p2));
+        const bool fr = live && wv < 0;
+        const bool first = fr && s < 0;  // start found by turning about the seed's vertex 0
+        const bool close = fr && !first && L > 0 && c == s;
+        const bool over = fr && !close && L == walk_cap;
+        const bool emit = fr && !close && !over;
+        s = first ? c : s;
+        const int32_t v = -1 - wv;
+        buf[emit ? L : kWalkCap][threadIdx.x] = v;
+        const uint64_t bit = 1ull << (v & 63);
+        const uint64_t bit2 = 1ull << ((v ^ (v >> 5) ^ (v >> 11)) & 63);
+        complex = complex || (emit && (sig & bit) != 0 && (sig2 & bit2) != 0);
+        sig |= emit ? bit : 0ull;
+        sig2 |= emit ? bit2 : 0ull;
+        const bool lower = emit && v < minv;
+        minv = lower ? v : minv;
+        minhe = lower ? c : minhe;
+        minpos = lower ? L : minpos;
+        L += emit ? 1 : 0;
+        done = done || close || over;
+        result = over ? kLarge : result;
+        live = emit;
+      }
+      // three emitted: the next check is the start again (a one-triangle region)
+      done = done || live;
+      result = live && base + p0 != s ? kInvalid : result;
+      // the first internal half-edge, crossed
+      const int32_t wx = wa >= 0 ? wa : (wb >= 0 ? wb : wc);
+      const bool cr = act && !done && wx >= 0;
+      steps += cr ? 1 : 0;
+      const bool bad = cr && ((uint32_t)wx >= (uint32_t)nhe || steps > nhe);
+      const bool go = cr && !bad;
+      const int32_t tn = wx / 3;
+      t = go ? tn : t;
+      ci = go ? next_local(wx - (tn + tn + tn)) : ci;
+      pending = pending || go;
+      done = done || bad;
+      result = bad ? kInvalid : result;
     }
     // one load site: the record of the triangle every lane that crossed an
     // edge (or took a new polygon) enters next, consumed next iteration
@@ -346,9 +369,9 @@ __global__ __launch_bounds__(256) void k_walk(const int32_t* __restrict__ list, 
     const bool fin = idx >= 0 && done;
     if (fin && result == kSimple && complex) result = kSmall;
     const bool fin_simple = fin && result == kSimple;
-    const bool fin_small = fin && result == kSmall;  // its vertices and half-edges are staged for the tip path
-    if (__ballot(fin_simple || fin_small)) {
-      const uint32_t need = fin_simple ? (uint32_t)L : (fin_small ? 2u * (uint32_t)L : 0u);
+    if (fin && result == kSmall) ps.set(idx, L, 0, s, -1);  // the tip path walks it again from s
+    if (__ballot(fin_simple)) {
+      const uint32_t need = fin_simple ? (uint32_t)L : 0u;
       const uint32_t incl = wave_incl_sum(need);
       const int32_t tot = __builtin_amdgcn_readlane((int32_t)incl, 63);
       if (tot > sleft) {  // new staging chunk for this wave
@@ -359,16 +382,13 @@ __global__ __launch_bounds__(256) void k_walk(const int32_t* __restrict__ list, 
         sleft = want_ints;
       }
       const bool fits = sbase + tot <= stage_cap;
-      if (fin_simple || fin_small) {
+      if (fin_simple) {
         const int64_t off = sbase + incl - need;
         if (!fits) {
           set_error(cnt, POLYLLA_ENOMEM);
           ps.clear(idx);
-        } else if (fin_simple) {
-          ps.set(idx, L, 1 | (minpos << kRotShift), minhe, (int32_t)off);
         } else {
-          // no output yet (pieces 0): cycle vertices, then its half-edges
-          ps.set(idx, L, 0, -1, (int32_t)off);
+          ps.set(idx, L, 1 | (minpos << kRotShift), minhe, (int32_t)off);
         }
       }
       // the staged words of all finished lanes, copied by the whole wave with
@@ -385,24 +405,34 @@ __global__ __launch_bounds__(256) void k_walk(const int32_t* __restrict__ list, 
             if (v <= (uint32_t)k) f += step;
           }
           const int32_t start = (int32_t)__shfl(incl - need, f, 64);
-          const int32_t lf = __shfl(L, f, 64);
-          if (k < tot) {
-            const int32_t loc = k - start;
-            stage[sbase + k] = loc < lf ? buf[loc][col0 + f] : hbuf[loc - lf][col0 + f];
-          }
+          if (k < tot) stage[sbase + k] = buf[k - start][col0 + f];
         }
       }
       sbase += tot;
       sleft -= tot;
     }
+    // Queued polygons. Short ones with a repeated vertex collect in a
+    // per-wave LDS queue that goes out 64 at a time with one counter update
+    // (one update per polygon on a single counter queues the waves at its L2
+    // channel); the rare long ones take one update per wave and event.
+    const bool q_small = fin && result == kSmall, q_large = fin && result == kLarge;
+    const uint64_t m_small = __ballot(q_small), m_large = __ballot(q_large);
+    if (m_small) {
+      const int n = __popcll(m_small);
+      if (dq_n + n > 64) {
+        flush_deferred();
+      }
+      if (q_small) dq[wv_id][dq_n + __popcll(m_small & ((1ull << lane) - 1ull))] = idx;
+      dq_n += n;
+    }
+    if (m_large) {
+      uint32_t b = 0;
+      if (lane == 0) b = atomicAdd(&cnt->n_big, (uint32_t)__popcll(m_large));
+      b = __shfl(b, 0, 64);
+      if (q_large) deferred[deferred_cap - 1 - (b + __popcll(m_large & ((1ull << lane) - 1ull)))] = idx;
+    }
     if (fin) {
-      if (result == kSmall) {
-        const uint32_t q = atomicAdd(&cnt->n_deferred, 1u);
-        deferred[q] = idx;
-      } else if (result == kLarge) {
-        const uint32_t q = atomicAdd(&cnt->n_big, 1u);
-        deferred[deferred_cap - 1 - q] = idx;
-      } else if (result == kInvalid) {
+      if (result == kInvalid) {
         set_error(cnt, steps > nhe ? POLYLLA_EDEGEN : POLYLLA_ETOPO);
         ps.clear(idx);
       }
@@ -411,6 +441,7 @@ __global__ __launch_bounds__(256) void k_walk(const int32_t* __restrict__ list, 
     }
     if (!more && __ballot(idx >= 0) == 0ull) break;
   }
+  flush_deferred();
 }
 
 // ---------------------------------------------------------------------------
@@ -1156,7 +1187,8 @@ __device__ int piece_rotation(const LdsCol& v, int L, int a, int len) {
 
 template <bool REPAIR>
 __global__ __launch_bounds__(64) void k_tip(int32_t nhe, int64_t nv, const int32_t* __restrict__ twin,
-                                            const int32_t* __restrict__ origin, uint8_t* __restrict__ he,
+                                            const int32_t* __restrict__ origin, const int32_t* __restrict__ wk,
+                                            uint8_t* __restrict__ he,
                                             uint8_t* __restrict__ vtx, int32_t* __restrict__ stage,
                                             int64_t stage_cap, int32_t* __restrict__ arena, int64_t arena_cap,
                                             PolyState ps, const int32_t* __restrict__ deferred,
@@ -1164,27 +1196,60 @@ __global__ __launch_bounds__(64) void k_tip(int32_t nhe, int64_t nv, const int32
   __shared__ int32_t s_v[kWalkCap * 64];
   __shared__ int32_t s_h[kWalkCap * 64];
   __shared__ int32_t s_f[kWalkCap * 64];
-  const LdsCol v{s_v + threadIdx.x}, h{s_h + threadIdx.x}, f{s_f + threadIdx.x};
+  const int lane = threadIdx.x;
+  const LdsCol v{s_v + lane}, h{s_h + lane}, f{s_f + lane};
   const uint32_t nd = cnt->n_deferred;
-  for (uint32_t j = blockIdx.x * 64 + threadIdx.x; j < nd; j += gridDim.x * 64) {
-    const int32_t i = deferred[j];
-    const int4 rc = ps.rec[i];
+  uint32_t n_rep = 0;  // tips repaired by this lane
+  // the wave takes 64 queued polygons at a time (the loop is wave-uniform, so
+  // the staging, arena and queue space of all 64 is reserved with one counter
+  // update each)
+  for (uint32_t j0 = blockIdx.x * 64; j0 < nd; j0 += gridDim.x * 64) {
+    const uint32_t j = j0 + lane;
+    const bool valid = j < nd;
+    const int32_t i = valid ? deferred[j] : 0;
+    const int4 rc = valid ? ps.rec[i] : make_int4(0, 0, -1, 0);
     const int L = rc.x;
-    bool fast = REPAIR && rc.y == 0 && L >= 4 && L <= kWalkCap;
+    bool ok = valid && rc.y == 0 && L >= 3 && L <= kWalkCap && (uint32_t)rc.z < (uint32_t)nhe;
+    if (ok) {
+      // the cycle again from its start half-edge over the walk words (which
+      // the repair does not change): its frontier half-edges and vertices
+      const int32_t s0 = rc.z;
+      int32_t c = s0, w = wk[s0];
+      int k = 0;
+      while (ok) {
+        if (w >= 0 || k == L) {
+          ok = false;
+          break;
+        }
+        v[k] = -1 - w;
+        h[k] = c;
+        ++k;
+        // next frontier half-edge: turn about the vertex across internal edges
+        int32_t x = he_next(c), steps = 0;
+        for (;;) {
+          w = wk[x];
+          if (w < 0) break;
+          if ((uint32_t)w >= (uint32_t)nhe || ++steps > kWalkCap * 3) {
+            ok = false;
+            break;
+          }
+          x = he_next(w);
+        }
+        c = x;
+        if (c == s0) break;
+      }
+      ok = ok && k == L;
+    }
+    int pairs = 0;
+    if (ok)
+      for (int a = 0; a < L; ++a)
+        for (int b = a + 1; b < L; ++b) pairs += v[a] == v[b] ? 1 : 0;
+    // no repeated vertex after all (the walk's filter flags a few such
+    // cycles): a complete polygon, staged like the walk stages one
+    const bool simple = ok && pairs == 0;
+    bool fast = ok && !simple && REPAIR && L >= 4;
     int m = -1;
     if (fast) {
-      // every load of the staged cycle issued before the first LDS store
-      int32_t rv[kWalkCap], rh[kWalkCap];
-#pragma unroll
-      for (int k = 0; k < kWalkCap; ++k) {
-        rv[k] = k < L ? stage[rc.w + k] : 0;
-        rh[k] = k < L ? stage[rc.w + L + k] : 0;
-      }
-#pragma unroll
-      for (int k = 0; k < kWalkCap; ++k) {
-        v[k] = rv[k];
-        h[k] = rh[k];
-      }
       int ntip = 0;
       for (int k = 0; k < L; ++k) {
         const int32_t vp = v[k == 0 ? L - 1 : k - 1], vn = v[k + 1 == L ? 0 : k + 1];
@@ -1201,9 +1266,6 @@ __global__ __launch_bounds__(64) void k_tip(int32_t nhe, int64_t nv, const int32
         // barrier edge, a region touching itself) goes to the region path.
         int K = 0;
         while (2 * K + 2 < L && v[(m - K - 1 + L) % L] == v[(m + K + 1) % L]) ++K;
-        int pairs = 0;
-        for (int a = 0; a < L; ++a)
-          for (int b = a + 1; b < L; ++b) pairs += v[a] == v[b] ? 1 : 0;
         fast = pairs == K;
       }
     }
@@ -1243,12 +1305,42 @@ __global__ __launch_bounds__(64) void k_tip(int32_t nhe, int64_t nv, const int32
         fast = occ == 1 && q != m && (uint32_t)te < (uint32_t)nhe;
       }
     }
-    if (!fast) {
-      const uint32_t r = atomicAdd(&cnt->n_gen, 1u);
+    // space for the whole wave: staging words, arena words, declined entries
+    const bool declined = valid && !simple && !fast;
+    const uint32_t ns = simple ? (uint32_t)L : (fast ? (uint32_t)(L + 2) : 0u);
+    const uint32_t na = fast ? 8u : 0u;
+    const uint32_t is = wave_incl_sum(ns), ia = wave_incl_sum(na);
+    const uint64_t md = __ballot(declined);
+    const uint32_t ts = (uint32_t)__builtin_amdgcn_readlane((int32_t)is, 63);
+    const uint32_t ta = (uint32_t)__builtin_amdgcn_readlane((int32_t)ia, 63);
+    uint32_t bs = 0, ba = 0, bd = 0;
+    if (lane == 0) {
+      if (ts) bs = atomicAdd(&cnt->stage_top, ts);
+      if (ta) ba = atomicAdd(&cnt->arena_top, ta);
+      if (md) bd = atomicAdd(&cnt->n_gen, (uint32_t)__popcll(md));
+    }
+    bs = __shfl(bs, 0, 64);
+    ba = __shfl(ba, 0, 64);
+    bd = __shfl(bd, 0, 64);
+    const int64_t off = (int64_t)bs + is - ns, r0 = (int64_t)ba + ia - na;
+    if (declined) {
+      const uint32_t r = bd + (uint32_t)__popcll(md & ((1ull << lane) - 1ull));
       if ((int64_t)r < rest_cap) rest[r] = i;
       else set_error(cnt, POLYLLA_EINTERNAL);
+    }
+    if ((simple || fast) && (off + ns > stage_cap || r0 + na > arena_cap)) {
+      set_error(cnt, POLYLLA_ENOMEM);
+      ps.clear(i);
       continue;
     }
+    if (simple) {
+      int mp = 0;
+      for (int k = 1; k < L; ++k)
+        if (v[k] < v[mp]) mp = k;
+      for (int k = 0; k < L; ++k) stage[off + k] = v[k];
+      ps.set(i, L, 1 | (mp << kRotShift), h[mp], (int32_t)off);
+    }
+    if (!fast) continue;
     // labels: barrier edges, the tip, the opened edge. The barrier edges of a
     // region form a forest inside it whose leaves are tips, so with one tip
     // they are the path v[m-k-1] = v[m+k+1] read outwards from the tip.
@@ -1262,8 +1354,7 @@ __global__ __launch_bounds__(64) void k_tip(int32_t nhe, int64_t nv, const int32
     if ((uint64_t)(uint32_t)vt < (uint64_t)nv) or_bits(vtx, vt, kTip);
     or_bits(he, e, kFrontier | kRepaired);
     or_bits(he, te, kFrontier | kRepaired);
-    atomicAdd(&cnt->n_tips, 1u);
-    atomicAdd(&cnt->n_splits, 1u);
+    ++n_rep;
     // pieces: A = positions m..q (x last, leaving by te), B = q..m (v[m] last, leaving by e)
     const int lenA = (q - m + L) % L + 1, lenB = (m - q + L) % L + 1;
     const int ra = piece_rotation(v, L, m, lenA), rb = piece_rotation(v, L, q, lenB);
@@ -1272,13 +1363,6 @@ __global__ __launch_bounds__(64) void k_tip(int32_t nhe, int64_t nv, const int32
     const int32_t sa = ra == lenA - 1 ? te : h[(m + ra) % L];
     const int32_t sb = rb == lenB - 1 ? e : h[(q + rb) % L];
     const bool a_first = a0 < b0 || (a0 == b0 && a1 < b1);
-    const uint32_t off = atomicAdd(&cnt->stage_top, (uint32_t)(L + 2));
-    const uint32_t r0 = atomicAdd(&cnt->arena_top, 8u);
-    if ((int64_t)off + L + 2 > stage_cap || (int64_t)r0 + 8 > arena_cap) {
-      set_error(cnt, POLYLLA_ENOMEM);
-      ps.clear(i);
-      continue;
-    }
     const int oa = a_first ? 0 : lenB, ob = a_first ? lenA : 0;
     for (int k = 0; k < lenA; ++k) stage[off + oa + k] = piece_vertex(v, L, m, (ra + k) % lenA);
     for (int k = 0; k < lenB; ++k) stage[off + ob + k] = piece_vertex(v, L, q, (rb + k) % lenB);
@@ -1293,6 +1377,12 @@ __global__ __launch_bounds__(64) void k_tip(int32_t nhe, int64_t nv, const int32
     arena[r0 + 4 * pb + 3] = lenB;
     ps.set(i, L + 2, 2, -1, (int32_t)off);
     ps.prec[i] = (int32_t)r0;
+  }
+  // repair counts: one update per wave
+  const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int32_t)wave_incl_sum(n_rep), 63);
+  if (lane == 0 && tot) {
+    atomicAdd(&cnt->n_tips, tot);
+    atomicAdd(&cnt->n_splits, tot);
   }
 }
 
@@ -3042,10 +3132,10 @@ template __global__ void k_general_small<false>(const int32_t*, bool, int32_t, i
                                                 const int32_t*, const int32_t*, uint8_t*, uint8_t*, int32_t*,
                                                 int64_t, int32_t*, int64_t, PolyState, const int32_t*,
                                                 const uint32_t*, uint32_t, Counters*);
-template __global__ void k_tip<true>(int32_t, int64_t, const int32_t*, const int32_t*, uint8_t*, uint8_t*, int32_t*,
+template __global__ void k_tip<true>(int32_t, int64_t, const int32_t*, const int32_t*, const int32_t*, uint8_t*, uint8_t*, int32_t*,
                                      int64_t, int32_t*, int64_t, PolyState, const int32_t*, int32_t*, int64_t,
                                      Counters*);
-template __global__ void k_tip<false>(int32_t, int64_t, const int32_t*, const int32_t*, uint8_t*, uint8_t*, int32_t*,
+template __global__ void k_tip<false>(int32_t, int64_t, const int32_t*, const int32_t*, const int32_t*, uint8_t*, uint8_t*, int32_t*,
                                       int64_t, int32_t*, int64_t, PolyState, const int32_t*, int32_t*, int64_t,
                                       Counters*);
 template __global__ void k_general_big<true, 64, 128, 128, 8>(

@@ -426,56 +426,24 @@ int run_build(polylla_ctx* c, const polylla_tri* t, const int32_t* list, bool fr
       hipLaunchKernelGGL(k_walk<false>, dim3(gw), dim3(256), 0, s, list, nhe, c->sc->wk, c->sc->stage,
                          c->sc->stage_cap, ps, c->sc->deferred, c->sc->cap_t, c->walk_cap, c->cnt);
   }
-  // the long regions (workgroup kernel, side stream) and the short ones
-  // (per-lane kernel, caller's stream) in parallel
+  // the long regions (workgroup kernels, caller's stream) and the flagged
+  // short polygons (tip path and per-lane kernels, second stream) in
+  // parallel. The long regions stay on the caller's stream: the 1024-thread
+  // region kernel needs a whole compute unit (all its LDS and registers), and
+  // its few workgroups are dispatched before the tip path's blocks spread
+  // over every compute unit only when it does not wait for the fork event.
+  hipStream_t sl = s, ss = c->side;
   if (hipEventRecord(c->fork, s) != hipSuccess || hipStreamWaitEvent(c->side, c->fork, 0) != hipSuccess)
     return POLYLLA_EHIP;
-  // long regions: one wave per region first (regions of up to 128 triangles
-  // and frontier half-edges), then 1024 threads per region for the rest; when
-  // there are at most `few` of them, all go to the 1024-thread instance
-  const uint32_t few = 128;
   {
-    Prof p(c, c->side, KR_BIG);
-    Counters* k = c->cnt;
-    const int gm = c->sc->grid64;  // persistent: one-wave blocks take regions round-robin
-    if (repair)
-      hipLaunchKernelGGL((k_general_big<true, 64, 128, 128, 8>), dim3(gm), dim3(64), 0, c->side, list, from_seeds, nhe,
-                         t->n_vertices, t->twin, t->origin, c->sc->wk, he, vtx, c->sc->stage, c->sc->stage_cap, c->sc->arena,
-                         c->sc->arena_cap, ps, c->sc->deferred, true, c->sc->cap_t, &k->n_big, &k->big_ticket, c->sc->over,
-                         c->sc->over_cap, &k->n_over, nullptr, (int64_t)0, &k->n_big, few, UINT32_MAX, 128, k);
-    else
-      hipLaunchKernelGGL((k_general_big<false, 64, 128, 128, 8>), dim3(gm), dim3(64), 0, c->side, list, from_seeds,
-                         nhe, t->n_vertices, t->twin, t->origin, c->sc->wk, he, vtx, c->sc->stage, c->sc->stage_cap, c->sc->arena,
-                         c->sc->arena_cap, ps, c->sc->deferred, true, c->sc->cap_t, &k->n_big, &k->big_ticket, c->sc->over,
-                         c->sc->over_cap, &k->n_over, nullptr, (int64_t)0, &k->n_big, few, UINT32_MAX, 128, k);
-  }
-  {
-    Prof p(c, c->side, KR_BIGW);
-    Counters* k = c->cnt;
-    const int gb = c->sc->grid1024;  // persistent: blocks take the remaining long regions by ticket
-    if (repair)
-      hipLaunchKernelGGL((k_general_big<true, 1024, 4096, 4096, 13>), dim3(gb), dim3(1024), 0, c->side, list,
-                         from_seeds, nhe, t->n_vertices, t->twin, t->origin, c->sc->wk, he, vtx, c->sc->stage, c->sc->stage_cap,
-                         c->sc->arena, c->sc->arena_cap, ps, c->sc->over, false, (int64_t)0, &k->n_over, &k->over_ticket, c->sc->huge,
-                         c->sc->huge_cap, &k->n_fallback, c->sc->deferred, c->sc->cap_t, &k->n_big, few, UINT32_MAX,
-                         c->lds_max, k);
-    else
-      hipLaunchKernelGGL((k_general_big<false, 1024, 4096, 4096, 13>), dim3(gb), dim3(1024), 0, c->side, list,
-                         from_seeds, nhe, t->n_vertices, t->twin, t->origin, c->sc->wk, he, vtx, c->sc->stage, c->sc->stage_cap,
-                         c->sc->arena, c->sc->arena_cap, ps, c->sc->over, false, (int64_t)0, &k->n_over, &k->over_ticket, c->sc->huge,
-                         c->sc->huge_cap, &k->n_fallback, c->sc->deferred, c->sc->cap_t, &k->n_big, few, UINT32_MAX,
-                         c->lds_max, k);
-  }
-  if (hipEventRecord(c->join, c->side) != hipSuccess) return POLYLLA_EHIP;
-  {
-    Prof p(c, s, KR_TIP);
+    Prof p(c, ss, KR_TIP);
     const int gt = 2048;  // one lane per short polygon with a repeat, grid-stride
     if (repair)
-      hipLaunchKernelGGL(k_tip<true>, dim3(gt), dim3(64), 0, s, nhe, t->n_vertices, t->twin, t->origin, c->sc->wk, he, vtx,
+      hipLaunchKernelGGL(k_tip<true>, dim3(gt), dim3(64), 0, ss, nhe, t->n_vertices, t->twin, t->origin, c->sc->wk, he, vtx,
                          c->sc->stage, c->sc->stage_cap, c->sc->arena, c->sc->arena_cap, ps, c->sc->deferred, c->sc->rest, c->sc->rest_cap,
                          c->cnt);
     else
-      hipLaunchKernelGGL(k_tip<false>, dim3(gt), dim3(64), 0, s, nhe, t->n_vertices, t->twin, t->origin, c->sc->wk, he, vtx,
+      hipLaunchKernelGGL(k_tip<false>, dim3(gt), dim3(64), 0, ss, nhe, t->n_vertices, t->twin, t->origin, c->sc->wk, he, vtx,
                          c->sc->stage, c->sc->stage_cap, c->sc->arena, c->sc->arena_cap, ps, c->sc->deferred, c->sc->rest, c->sc->rest_cap,
                          c->cnt);
   }
@@ -483,30 +451,67 @@ int run_build(polylla_ctx* c, const polylla_tri* t, const int32_t* list, bool fr
   // each (latency), more one lane each (throughput); each kernel reads the
   // count and the one not meant for it returns at once
   {
-    Prof p(c, s, KR_GENW);
+    Prof p(c, ss, KR_GENW);
     Counters* k = c->cnt;
     if (repair)
-      hipLaunchKernelGGL((k_general_big<true, 64, 128, 128, 8>), dim3(c->sc->grid64), dim3(64), 0, s, list, from_seeds,
+      hipLaunchKernelGGL((k_general_big<true, 64, 128, 128, 8>), dim3(c->sc->grid64), dim3(64), 0, ss, list, from_seeds,
                          nhe, t->n_vertices, t->twin, t->origin, c->sc->wk, he, vtx, c->sc->stage, c->sc->stage_cap, c->sc->arena,
                          c->sc->arena_cap, ps, c->sc->rest, false, (int64_t)0, &k->n_gen, nullptr, c->sc->huge, c->sc->huge_cap,
                          &k->n_fallback, nullptr, (int64_t)0, nullptr, 0u, c->gen_wave_max, 128, k);
     else
-      hipLaunchKernelGGL((k_general_big<false, 64, 128, 128, 8>), dim3(c->sc->grid64), dim3(64), 0, s, list, from_seeds,
+      hipLaunchKernelGGL((k_general_big<false, 64, 128, 128, 8>), dim3(c->sc->grid64), dim3(64), 0, ss, list, from_seeds,
                          nhe, t->n_vertices, t->twin, t->origin, c->sc->wk, he, vtx, c->sc->stage, c->sc->stage_cap, c->sc->arena,
                          c->sc->arena_cap, ps, c->sc->rest, false, (int64_t)0, &k->n_gen, nullptr, c->sc->huge, c->sc->huge_cap,
                          &k->n_fallback, nullptr, (int64_t)0, nullptr, 0u, c->gen_wave_max, 128, k);
   }
   {
-    Prof p(c, s, KR_GENERAL);
+    Prof p(c, ss, KR_GENERAL);
     const int gg = 2048;
     if (repair)
-      hipLaunchKernelGGL(k_general_small<true>, dim3(gg), dim3(64), 0, s, list, from_seeds, nhe, t->n_vertices,
+      hipLaunchKernelGGL(k_general_small<true>, dim3(gg), dim3(64), 0, ss, list, from_seeds, nhe, t->n_vertices,
                          t->twin, t->origin, c->sc->wk, he, vtx, c->sc->stage, c->sc->stage_cap, c->sc->arena, c->sc->arena_cap, ps,
                          c->sc->rest, &c->cnt->n_gen, c->gen_wave_max, c->cnt);
     else
-      hipLaunchKernelGGL(k_general_small<false>, dim3(gg), dim3(64), 0, s, list, from_seeds, nhe, t->n_vertices,
+      hipLaunchKernelGGL(k_general_small<false>, dim3(gg), dim3(64), 0, ss, list, from_seeds, nhe, t->n_vertices,
                          t->twin, t->origin, c->sc->wk, he, vtx, c->sc->stage, c->sc->stage_cap, c->sc->arena, c->sc->arena_cap, ps,
                          c->sc->rest, &c->cnt->n_gen, c->gen_wave_max, c->cnt);
+  }
+  if (hipEventRecord(c->join, ss) != hipSuccess) return POLYLLA_EHIP;
+  // long regions: one wave per region first (regions of up to 128 triangles
+  // and frontier half-edges), then 1024 threads per region for the rest; when
+  // there are at most `few` of them, all go to the 1024-thread instance
+  const uint32_t few = 128;
+  {
+    Prof p(c, sl, KR_BIG);
+    Counters* k = c->cnt;
+    const int gm = c->sc->grid64;  // persistent: one-wave blocks take regions round-robin
+    if (repair)
+      hipLaunchKernelGGL((k_general_big<true, 64, 128, 128, 8>), dim3(gm), dim3(64), 0, sl, list, from_seeds, nhe,
+                         t->n_vertices, t->twin, t->origin, c->sc->wk, he, vtx, c->sc->stage, c->sc->stage_cap, c->sc->arena,
+                         c->sc->arena_cap, ps, c->sc->deferred, true, c->sc->cap_t, &k->n_big, &k->big_ticket, c->sc->over,
+                         c->sc->over_cap, &k->n_over, nullptr, (int64_t)0, &k->n_big, few, UINT32_MAX, 128, k);
+    else
+      hipLaunchKernelGGL((k_general_big<false, 64, 128, 128, 8>), dim3(gm), dim3(64), 0, sl, list, from_seeds,
+                         nhe, t->n_vertices, t->twin, t->origin, c->sc->wk, he, vtx, c->sc->stage, c->sc->stage_cap, c->sc->arena,
+                         c->sc->arena_cap, ps, c->sc->deferred, true, c->sc->cap_t, &k->n_big, &k->big_ticket, c->sc->over,
+                         c->sc->over_cap, &k->n_over, nullptr, (int64_t)0, &k->n_big, few, UINT32_MAX, 128, k);
+  }
+  {
+    Prof p(c, sl, KR_BIGW);
+    Counters* k = c->cnt;
+    const int gb = c->sc->grid1024;  // persistent: blocks take the remaining long regions by ticket
+    if (repair)
+      hipLaunchKernelGGL((k_general_big<true, 1024, 4096, 4096, 13>), dim3(gb), dim3(1024), 0, sl, list,
+                         from_seeds, nhe, t->n_vertices, t->twin, t->origin, c->sc->wk, he, vtx, c->sc->stage, c->sc->stage_cap,
+                         c->sc->arena, c->sc->arena_cap, ps, c->sc->over, false, (int64_t)0, &k->n_over, &k->over_ticket, c->sc->huge,
+                         c->sc->huge_cap, &k->n_fallback, c->sc->deferred, c->sc->cap_t, &k->n_big, few, UINT32_MAX,
+                         c->lds_max, k);
+    else
+      hipLaunchKernelGGL((k_general_big<false, 1024, 4096, 4096, 13>), dim3(gb), dim3(1024), 0, sl, list,
+                         from_seeds, nhe, t->n_vertices, t->twin, t->origin, c->sc->wk, he, vtx, c->sc->stage, c->sc->stage_cap,
+                         c->sc->arena, c->sc->arena_cap, ps, c->sc->over, false, (int64_t)0, &k->n_over, &k->over_ticket, c->sc->huge,
+                         c->sc->huge_cap, &k->n_fallback, c->sc->deferred, c->sc->cap_t, &k->n_big, few, UINT32_MAX,
+                         c->lds_max, k);
   }
   if (hipStreamWaitEvent(s, c->join, 0) != hipSuccess) return POLYLLA_EHIP;
   {

@@ -428,11 +428,31 @@ int run_build(polylla_ctx* c, const polylla_tri* t, const int32_t* list, bool fr
   }
   // the long regions (workgroup kernels, caller's stream) and the flagged
   // short polygons (tip path and per-lane kernels, second stream) in
-  // parallel. The long regions stay on the caller's stream: the 1024-thread
-  // region kernel needs a whole compute unit (all its LDS and registers), and
-  // its few workgroups are dispatched before the tip path's blocks spread
-  // over every compute unit only when it does not wait for the fork event.
+  // parallel. The 1024-thread region kernel needs whole compute units (all
+  // their LDS and registers): it stays on the caller's stream and the second
+  // stream forks only after the one-wave instance before it, so that its few
+  // workgroups are dispatched before the tip path's blocks spread over every
+  // compute unit.
   hipStream_t sl = s, ss = c->side;
+  // long regions: one wave per region first (regions of up to 128 triangles
+  // and frontier half-edges), then 1024 threads per region for the rest; when
+  // there are at most `few` of them, all go to the 1024-thread instance
+  const uint32_t few = 128;
+  {
+    Prof p(c, sl, KR_BIG);
+    Counters* k = c->cnt;
+    const int gm = c->sc->grid64;  // persistent: one-wave blocks take regions round-robin
+    if (repair)
+      hipLaunchKernelGGL((k_general_big<true, 64, 128, 128, 8>), dim3(gm), dim3(64), 0, sl, list, from_seeds, nhe,
+                         t->n_vertices, t->twin, t->origin, c->sc->wk, he, vtx, c->sc->stage, c->sc->stage_cap, c->sc->arena,
+                         c->sc->arena_cap, ps, c->sc->deferred, true, c->sc->cap_t, &k->n_big, &k->big_ticket, c->sc->over,
+                         c->sc->over_cap, &k->n_over, nullptr, (int64_t)0, &k->n_big, few, UINT32_MAX, 128, k);
+    else
+      hipLaunchKernelGGL((k_general_big<false, 64, 128, 128, 8>), dim3(gm), dim3(64), 0, sl, list, from_seeds,
+                         nhe, t->n_vertices, t->twin, t->origin, c->sc->wk, he, vtx, c->sc->stage, c->sc->stage_cap, c->sc->arena,
+                         c->sc->arena_cap, ps, c->sc->deferred, true, c->sc->cap_t, &k->n_big, &k->big_ticket, c->sc->over,
+                         c->sc->over_cap, &k->n_over, nullptr, (int64_t)0, &k->n_big, few, UINT32_MAX, 128, k);
+  }
   if (hipEventRecord(c->fork, s) != hipSuccess || hipStreamWaitEvent(c->side, c->fork, 0) != hipSuccess)
     return POLYLLA_EHIP;
   {
@@ -477,25 +497,6 @@ int run_build(polylla_ctx* c, const polylla_tri* t, const int32_t* list, bool fr
                          c->sc->rest, &c->cnt->n_gen, c->gen_wave_max, c->cnt);
   }
   if (hipEventRecord(c->join, ss) != hipSuccess) return POLYLLA_EHIP;
-  // long regions: one wave per region first (regions of up to 128 triangles
-  // and frontier half-edges), then 1024 threads per region for the rest; when
-  // there are at most `few` of them, all go to the 1024-thread instance
-  const uint32_t few = 128;
-  {
-    Prof p(c, sl, KR_BIG);
-    Counters* k = c->cnt;
-    const int gm = c->sc->grid64;  // persistent: one-wave blocks take regions round-robin
-    if (repair)
-      hipLaunchKernelGGL((k_general_big<true, 64, 128, 128, 8>), dim3(gm), dim3(64), 0, sl, list, from_seeds, nhe,
-                         t->n_vertices, t->twin, t->origin, c->sc->wk, he, vtx, c->sc->stage, c->sc->stage_cap, c->sc->arena,
-                         c->sc->arena_cap, ps, c->sc->deferred, true, c->sc->cap_t, &k->n_big, &k->big_ticket, c->sc->over,
-                         c->sc->over_cap, &k->n_over, nullptr, (int64_t)0, &k->n_big, few, UINT32_MAX, 128, k);
-    else
-      hipLaunchKernelGGL((k_general_big<false, 64, 128, 128, 8>), dim3(gm), dim3(64), 0, sl, list, from_seeds,
-                         nhe, t->n_vertices, t->twin, t->origin, c->sc->wk, he, vtx, c->sc->stage, c->sc->stage_cap, c->sc->arena,
-                         c->sc->arena_cap, ps, c->sc->deferred, true, c->sc->cap_t, &k->n_big, &k->big_ticket, c->sc->over,
-                         c->sc->over_cap, &k->n_over, nullptr, (int64_t)0, &k->n_big, few, UINT32_MAX, 128, k);
-  }
   {
     Prof p(c, sl, KR_BIGW);
     Counters* k = c->cnt;

@@ -399,9 +399,9 @@ int run_label(polylla_ctx* c, const polylla_tri* t, uint8_t* he, uint8_t* tri, u
   }
   if (T > 0) {
     Prof p(c, s, KR_LABEL);
-    // 16-byte loads of twin and 4-byte label stores need aligned arrays
-    const bool vec = ((uintptr_t)t->twin % 16 == 0) && ((uintptr_t)t->origin % 16 == 0) && ((uintptr_t)he % 4 == 0) &&
-                     ((uintptr_t)tri % 4 == 0);
+    // 16-byte loads of twin and origin need aligned arrays (the label stores
+    // adapt to the alignment of he and tri)
+    const bool vec = ((uintptr_t)t->twin % 16 == 0) && ((uintptr_t)t->origin % 16 == 0);
     hipLaunchKernelGGL(k_label<true>, dim3((T + kTile - 1) / kTile), dim3(256), 0, s, T, t->twin, c->sc->lg, he, tri,
                        t->origin, c->sc->wk, tile_counts(c), tile_groups(c, T), c->cnt, vec, t->fixed);
   }

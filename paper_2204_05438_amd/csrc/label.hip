@@ -246,9 +246,7 @@ __global__ __launch_bounds__(256) void k_label(int64_t nt, const int32_t* __rest
   // 16-byte stores.
   __shared__ uint4 s_w4[256 * ITEMS / 4];  // he words, then tri words of the tile
   const int64_t tile_t0 = (int64_t)tile * 256 * ITEMS;
-  const bool full = COMPUTE && vec && tile_t0 + 256 * ITEMS <= nt &&
-                    ((reinterpret_cast<uintptr_t>(he) | reinterpret_cast<uintptr_t>(tri) |
-                      reinterpret_cast<uintptr_t>(wk)) & 15) == 0;
+  const bool full = COMPUTE && vec && tile_t0 + 256 * ITEMS <= nt && (reinterpret_cast<uintptr_t>(wk) & 15) == 0;
   __shared__ uint4 s_lg4[kLgWin / 16];
   if (full) {
     // Max bytes of the tile and its margins (16-byte aligned: tiles and
@@ -302,12 +300,20 @@ __global__ __launch_bounds__(256) void k_label(int64_t nt, const int32_t* __rest
       s_trib[lt] = sd[k] ? kSeed : 0;
     }
     __syncthreads();
-    uint4* ghe = reinterpret_cast<uint4*>(he + 3 * tile_t0);
-    uint4* gtri = reinterpret_cast<uint4*>(tri + tile_t0);
-    for (int k = threadIdx.x; k < 256 * ITEMS * 3 / 16; k += 256) ghe[k] = s_w4[k];
-    for (int k = threadIdx.x; k < 256 * ITEMS / 16; k += 256) gtri[k] = s_w4[256 * ITEMS * 3 / 16 + k];
+    if (((reinterpret_cast<uintptr_t>(he) | reinterpret_cast<uintptr_t>(tri)) & 15) == 0) {
+      uint4* ghe = reinterpret_cast<uint4*>(he + 3 * tile_t0);
+      uint4* gtri = reinterpret_cast<uint4*>(tri + tile_t0);
+      for (int k = threadIdx.x; k < 256 * ITEMS * 3 / 16; k += 256) ghe[k] = s_w4[k];
+      for (int k = threadIdx.x; k < 256 * ITEMS / 16; k += 256) gtri[k] = s_w4[256 * ITEMS * 3 / 16 + k];
+    } else {
+      // label arrays at any byte offset (a group of a batch starts at an
+      // arbitrary half-edge): byte stores, contiguous over each wave
+      for (int k = threadIdx.x; k < 256 * ITEMS * 3; k += 256) he[3 * tile_t0 + k] = s_heb[k];
+      for (int k = threadIdx.x; k < 256 * ITEMS; k += 256) tri[tile_t0 + k] = s_trib[k];
+    }
   } else if (COMPUTE) {
-    if (vec && t0 + ITEMS <= nt) {
+    if (vec && t0 + ITEMS <= nt &&
+        ((reinterpret_cast<uintptr_t>(he) | reinterpret_cast<uintptr_t>(tri)) & 3) == 0) {
       // ITEMS triangles: twins and origins as int4, ITEMS Max bytes and labels as words
       int32_t tw[3 * ITEMS], og[3 * ITEMS];
       load_words<ITEMS>(twin + 3 * t0, tw);

@@ -168,6 +168,17 @@ def _job_request(job):
     return j, mesh.xy, mesh.origin, mesh.twin, dg
 
 
+def _job_arrays_oracle(job):
+    """The oracle's digest (polygons only) of a mesh given as arrays (a grid
+    generated on the device and copied back)."""
+    import numpy as np
+    from meshgen.gen import Mesh
+    k, xy, origin, twin = job
+    h = np.arange(origin.shape[0])
+    mesh = Mesh(xy=xy, origin=origin, twin=twin, next=(h - h % 3 + (h + 1) % 3).astype(np.int32))
+    return k, _oracle_digest(mesh, with_labels=False)[0]
+
+
 def _job_workload_oracle(name):
     """The oracle on a whole single-mesh workload (identity check of the
     timed GPU output)."""
@@ -531,18 +542,64 @@ def bench_serve(args, pool, n_requests: int):
         runs[f"{f}x"] = res
         log(f"serve: {f}x capacity ({rate:.1f}/s): p50 {res['latency_ms']['p50']} ms, "
             f"p99 {res['latency_ms']['p99']} ms, {res['meshes_per_s']} meshes/s")
+    gen = bench_serve_generated(args, pool, server, base, n_requests)
     server.close()
     out = {"workload": f"serve{n_requests}: Poisson arrivals (seed 5), points round(10^U(3, log10 2e6)), uniform "
                        f"or 4-cluster (sigma 0.05) with probability 1/2, request j seeded 50000+j; {T_all} "
                        f"triangles; 64 GB admission budget; {args.slots} slots",
            "requests": n_requests, "triangles": T_all, "runs": runs,
-           "oracle_identical_requests": checked}
+           "oracle_identical_requests": checked, "generated_on_device": gen}
     if not args.no_cpu and oracle_s > 0:
         out["cpu_pool"] = {"value": round(T_all / (oracle_s / pool._processes), 1), "unit": "triangles/s",
                            "cores": pool._processes, "kind": "oracle",
                            "sample": f"every request of serve{n_requests}, one oracle per request, "
                                      f"{pool._processes} processes", "oracle_process_seconds": round(oracle_s, 1)}
     return out
+
+
+def bench_serve_generated(args, pool, server, base, n_requests: int):
+    """The same request stream with inputs named instead of sent: request j
+    is the jittered g x g grid with g = round(sqrt(points of request j)),
+    triangulated on the device at admission (no host-to-device copy).
+    Capacity and 0.9x of it; every 64th request checked against the oracle
+    on its generated mesh (copied back after the runs)."""
+    import numpy as np
+    from paper_2204_05438_amd import lib, serve
+    grids = [(max(4, int(round(float(np.sqrt(base[j][1]))))), 0.45, 70_000 + j) for j in range(n_requests)]
+
+    def requests(scale):
+        return [serve.Request.from_grid(j, base[j][0] * scale, *grids[j]) for j in range(n_requests)]
+
+    server.run(requests(0.0)[: min(32, n_requests)])  # warm-up (and the generation context)
+    runs = {}
+    cap_reqs = requests(0.0)
+    runs["saturated"] = server.run(cap_reqs)
+    cap = runs["saturated"]["meshes_per_s"]
+    T_all = sum(r.n_tri for r in cap_reqs)
+    log(f"serve (on-device input): capacity {cap} meshes/s, {runs['saturated']['triangles_per_s']:.4g} triangles/s")
+    rate = 0.9 * cap
+    res = server.run(requests(1.0 / rate))
+    res["rate_meshes_per_s"] = round(rate, 2)
+    runs["0.9x"] = res
+    log(f"serve (on-device input): 0.9x capacity ({rate:.1f}/s): p50 {res['latency_ms']['p50']} ms, "
+        f"p99 {res['latency_ms']['p99']} ms")
+    checked = None
+    if not args.no_cpu:
+        ctx = lib.Context(0)
+        jobs = []
+        for j in range(0, n_requests, 64):
+            tri, _ = ctx.gen_grid(*grids[j])
+            jobs.append((j, tri.xy.cpu().numpy(), tri.origin.cpu().numpy(), tri.twin.cpu().numpy()))
+            del tri
+        ctx.close()
+        got = {r.rid: digest(r.offsets, r.verts, np.zeros(0, np.uint8)) for r in cap_reqs if r.error == 0}
+        checked = sum(1 for k, dg in pool.imap_unordered(_job_arrays_oracle, jobs) if got.get(k) == dg)
+        checked = f"{checked}/{len(jobs)}"
+        log(f"serve (on-device input): oracle-identical sampled requests {checked}")
+    return {"workload": f"the same {n_requests} arrivals, request j = jittered g x g grid (jitter 0.45, SplitMix64 "
+                        f"seed 70000+j), g = round(sqrt(points of request j)), generated on the device at admission; "
+                        f"{T_all} triangles",
+            "triangles": T_all, "runs": runs, "oracle_identical_sampled_requests": checked}
 
 
 def main():

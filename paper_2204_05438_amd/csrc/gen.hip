@@ -27,6 +27,7 @@
 // then the triangles filling the boundary dents; a tile of cells is 2048
 // triangles, the label kernels' tile.
 #include <algorithm>
+#include <vector>
 
 #include "common.h"
 
@@ -56,8 +57,32 @@ __device__ __forceinline__ int64_t orient(int64_t ax, int64_t ay, int64_t bx, in
   return (bx - ax) * (cy - ay) - (by - ay) * (cx - ax);  // |terms| < 2^57
 }
 
-// > 0 when d lies inside the circle through a, b, c (counter-clockwise)
+// > 0 when d lies inside the circle through a, b, c (counter-clockwise):
+// first in binary64 with the static error bound of Shewchuk's incircle
+// predicate (Adaptive Precision Floating-Point Arithmetic and Fast Robust
+// Geometric Predicates, 1997: |error| <= (10 + 96 eps) eps x the permanent;
+// the coordinate differences here are exact), then exactly in 128-bit
+// integers when the rounded value is within the bound.
+__device__ int incircle_exact(const int64_t* p, int32_t a, int32_t b, int32_t c, int32_t d);
+
 __device__ __forceinline__ int incircle(const int64_t* p, int32_t a, int32_t b, int32_t c, int32_t d) {
+  const double adx = (double)(p[2 * a] - p[2 * d]), ady = (double)(p[2 * a + 1] - p[2 * d + 1]);
+  const double bdx = (double)(p[2 * b] - p[2 * d]), bdy = (double)(p[2 * b + 1] - p[2 * d + 1]);
+  const double cdx = (double)(p[2 * c] - p[2 * d]), cdy = (double)(p[2 * c + 1] - p[2 * d + 1]);
+  const double bdxcdy = bdx * cdy, cdxbdy = cdx * bdy, cdxady = cdx * ady, adxcdy = adx * cdy;
+  const double adxbdy = adx * bdy, bdxady = bdx * ady;
+  const double alift = adx * adx + ady * ady, blift = bdx * bdx + bdy * bdy, clift = cdx * cdx + cdy * cdy;
+  const double det = alift * (bdxcdy - cdxbdy) + blift * (cdxady - adxcdy) + clift * (adxbdy - bdxady);
+  const double perm = (fabs(bdxcdy) + fabs(cdxbdy)) * alift + (fabs(cdxady) + fabs(adxcdy)) * blift +
+                      (fabs(adxbdy) + fabs(bdxady)) * clift;
+  const double eps = 0x1.0p-53;
+  const double bound = (10.0 + 96.0 * eps) * eps * perm;
+  if (det > bound) return 1;
+  if (-det > bound) return -1;
+  return incircle_exact(p, a, b, c, d);
+}
+
+__device__ int incircle_exact(const int64_t* p, int32_t a, int32_t b, int32_t c, int32_t d) {
   const int64_t adx = p[2 * a] - p[2 * d], ady = p[2 * a + 1] - p[2 * d + 1];
   const int64_t bdx = p[2 * b] - p[2 * d], bdy = p[2 * b + 1] - p[2 * d + 1];
   const int64_t cdx = p[2 * c] - p[2 * d], cdy = p[2 * c + 1] - p[2 * d + 1];
@@ -232,6 +257,7 @@ struct Pockets {
 __device__ int64_t fill_chain(int32_t* S, int32_t* E, const int32_t* v, const int32_t* ve, int64_t n,
                               const int64_t* lat, int32_t* twin, const Pockets& P, int seg, Counters* cnt) {
   int64_t m = 0;
+  uint32_t used = 0;  // the segment's triangles (one thread owns the segment)
   for (int64_t k = 0; k < n; ++k) {
     const int32_t c = v[k];
     if (k > 0) {
@@ -239,9 +265,10 @@ __device__ int64_t fill_chain(int32_t* S, int32_t* E, const int32_t* v, const in
       while (m >= 2) {
         const int32_t a = S[m - 2], b = S[m - 1];
         if (orient(lat[2 * a], lat[2 * a + 1], lat[2 * b], lat[2 * b + 1], lat[2 * c], lat[2 * c + 1]) >= 0) break;
-        const uint32_t q = P.count[seg]++;
+        const uint32_t q = used++;
         if ((int64_t)q >= P.seg_cap) {
           set_error(cnt, POLYLLA_EINTERNAL);
+          P.count[seg] = used;
           return m;
         }
         const int64_t slot = seg * P.seg_cap + q;
@@ -261,7 +288,162 @@ __device__ int64_t fill_chain(int32_t* S, int32_t* E, const int32_t* v, const in
     }
     S[m++] = c;
   }
+  P.count[seg] = used;
   return m;
+}
+
+// k_gen_sides with the side in LDS (g <= kGenSideLds): the points' lattice
+// coordinates (< 2^29, int32), the boundary half-edges and the scans' stacks
+// (side positions and hull half-edges) live in LDS. The side is cut into
+// chunks of kGenChunk edges; one thread per chunk runs the scan on it, then
+// one thread runs it again over the chunks' hulls in order (the hull of the
+// whole chain is the hull of its chunks' hulls, and the second scan fills the
+// dents between them), writing its stack in place over the chunks' stacks it
+// has already read. The two points on top of a stack stay in registers.
+constexpr int64_t kGenSideLds = 3200;  // 5 int32 per point and 2 per chunk: < 64 KB of LDS
+constexpr int32_t kGenChunk = 64;
+
+__device__ __forceinline__ int32_t side_vertex(int s, int64_t k, int64_t g) {
+  int64_t i, j;
+  ring_pos(s, k, g, &i, &j);
+  return (int32_t)grid_id(i, j, g);
+}
+
+// one pop of the scan: point b = S[m-1] lies in a dent of the chain a -> b -> c
+// (a = S[m-2], c at position pc, ec the half-edge b -> c): triangle (a, c, b)
+// fills it (see fill_chain); returns its a -> c half-edge, or -1 when the
+// segment is full
+__device__ __forceinline__ int32_t side_pop(int s, int64_t g, int32_t pa, int32_t pb, int32_t pc, int32_t ec,
+                                            int32_t eab, uint32_t q, int32_t* twin, const Pockets& P,
+                                            Counters* cnt) {
+  if ((int64_t)q >= P.seg_cap) {
+    set_error(cnt, POLYLLA_EINTERNAL);
+    return -1;
+  }
+  const int64_t slot = s * P.seg_cap + q;
+  const int32_t h = P.vbase + (int32_t)(3 * slot);
+  P.origin[3 * slot] = side_vertex(s, pa, g);
+  P.origin[3 * slot + 1] = side_vertex(s, pc, g);
+  P.origin[3 * slot + 2] = side_vertex(s, pb, g);
+  P.twin[3 * slot] = -1;
+  P.twin[3 * slot + 1] = ec;
+  P.set_twin(twin, ec, h + 1);
+  P.twin[3 * slot + 2] = eab;
+  P.set_twin(twin, eab, h + 2);
+  return h;
+}
+
+__global__ __launch_bounds__(256) void k_gen_sides_lds(int64_t g, const int64_t* __restrict__ lat,
+                                                       const uint8_t* __restrict__ diag,
+                                                       int32_t* __restrict__ twin, int32_t* __restrict__ wsp,
+                                                       int64_t* __restrict__ hull_len, Pockets P, Counters* cnt) {
+  extern __shared__ int32_t sm[];
+  const int s = blockIdx.x;
+  if (s >= 4) return;
+  const int32_t nch = (int32_t)((g - 1 + kGenChunk - 1) / kGenChunk);  // chunks of kGenChunk edges
+  int32_t* px = sm;
+  int32_t* py = px + g;
+  int32_t* ve = py + g;
+  int32_t* S = ve + g;                          // stacks: side positions, chunk c at c (kGenChunk + 1)
+  int32_t* E = S + nch * (kGenChunk + 1);       // and hull half-edges
+  int32_t* mc = E + nch * (kGenChunk + 1);      // hull length of each chunk
+  __shared__ uint32_t s_used;
+  __shared__ int32_t s_m;
+  if (threadIdx.x == 0) s_used = 0;
+  for (int64_t k = threadIdx.x; k < g; k += blockDim.x) {
+    const int32_t v = side_vertex(s, k, g);
+    px[k] = (int32_t)lat[2 * v];
+    py[k] = (int32_t)lat[2 * v + 1];
+    if (k + 1 < g) ve[k] = ring_he(s, k, g, diag);
+  }
+  __syncthreads();
+  // level 1: one thread per chunk (positions c C .. min(c C + C, g - 1))
+  for (int32_t c = threadIdx.x; c < nch; c += blockDim.x) {
+    int32_t* Sc = S + c * (kGenChunk + 1);
+    int32_t* Ec = E + c * (kGenChunk + 1);
+    const int32_t k0 = c * kGenChunk, k1 = (int32_t)min<int64_t>(k0 + kGenChunk, g - 1);
+    int32_t m = 0;
+    int64_t ax = 0, ay = 0, bx = 0, by = 0;  // points Sc[m-2], Sc[m-1]
+    bool ok = true;
+    for (int32_t k = k0; k <= k1 && ok; ++k) {
+      const int64_t cx = px[k], cy = py[k];
+      if (k > k0) {
+        int32_t ec = ve[k - 1];
+        while (m >= 2 && orient(ax, ay, bx, by, cx, cy) < 0) {
+          ec = side_pop(s, g, Sc[m - 2], Sc[m - 1], k, ec, Ec[m - 2], atomicAdd(&s_used, 1u), twin, P, cnt);
+          if (ec < 0) {
+            ok = false;
+            break;
+          }
+          --m;
+          bx = ax;
+          by = ay;
+          if (m >= 2) {
+            ax = px[Sc[m - 2]];
+            ay = py[Sc[m - 2]];
+          }
+        }
+        Ec[m - 1] = ec;
+      }
+      Sc[m++] = k;
+      ax = bx;
+      ay = by;
+      bx = cx;
+      by = cy;
+    }
+    mc[c] = m;
+  }
+  __syncthreads();
+  // level 2: the chunks' hulls in order (a chunk's first point is the
+  // previous chunk's last), the stack written in place from the start
+  if (threadIdx.x == 0) {
+    uint32_t used = s_used;
+    int32_t m = 0;
+    int64_t ax = 0, ay = 0, bx = 0, by = 0;
+    bool ok = true;
+    for (int32_t c = 0; c < nch && ok; ++c) {
+      const int32_t base = c * (kGenChunk + 1), mcc = mc[c];
+      for (int32_t kk = c == 0 ? 0 : 1; kk < mcc && ok; ++kk) {
+        const int32_t pk = S[base + kk];
+        const int64_t cx = px[pk], cy = py[pk];
+        if (m > 0) {
+          int32_t ec = E[base + kk - 1];
+          while (m >= 2 && orient(ax, ay, bx, by, cx, cy) < 0) {
+            ec = side_pop(s, g, S[m - 2], S[m - 1], pk, ec, E[m - 2], used++, twin, P, cnt);
+            if (ec < 0) {
+              ok = false;
+              break;
+            }
+            --m;
+            bx = ax;
+            by = ay;
+            if (m >= 2) {
+              ax = px[S[m - 2]];
+              ay = py[S[m - 2]];
+            }
+          }
+          E[m - 1] = ec;
+        }
+        S[m++] = pk;
+        ax = bx;
+        ay = by;
+        bx = cx;
+        by = cy;
+      }
+    }
+    P.count[s] = used;
+    s_m = m;
+    hull_len[s] = m;
+  }
+  __syncthreads();
+  // the hull chain for the corner scan: vertex ids and half-edges
+  const int32_t m = s_m;
+  int32_t* hs = wsp + (int64_t)s * 4 * g + 2 * g;
+  int32_t* he = hs + g;
+  for (int32_t k = threadIdx.x; k < m; k += blockDim.x) {
+    hs[k] = side_vertex(s, S[k], g);
+    if (k + 1 < m) he[k] = E[k];
+  }
 }
 
 __global__ void k_gen_sides(int64_t g, const int64_t* __restrict__ lat, const uint8_t* __restrict__ diag,
@@ -364,11 +546,13 @@ __global__ __launch_bounds__(256) void k_gen_pack(Pockets P, int64_t tri_base, i
 
 // Structural check before the flips (which index through twin): twins are an
 // involution between half-edges of opposite direction, origins are vertex
-// ids, triangles are counter-clockwise.
-__global__ __launch_bounds__(256) void k_gen_check(int64_t nt, int64_t nv, const int32_t* __restrict__ twin,
+// ids, triangles are counter-clockwise. The triangle count is read on the
+// device (the launch covers its bound).
+__global__ __launch_bounds__(256) void k_gen_check(const int64_t* __restrict__ n_tri, int64_t nv,
+                                                   const int32_t* __restrict__ twin,
                                                    const int32_t* __restrict__ origin,
                                                    const int64_t* __restrict__ lat, Counters* cnt) {
-  const int64_t nh = 3 * nt;
+  const int64_t nh = 3 * *n_tri;
   for (int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; h < nh; h += (int64_t)gridDim.x * blockDim.x) {
     const int32_t hn = he_next((int32_t)h);
     const int32_t a = origin[h], b = origin[hn], c = origin[he_next(hn)];
@@ -386,50 +570,86 @@ __global__ __launch_bounds__(256) void k_gen_check(int64_t nt, int64_t nv, const
 }
 
 // ---- parallel Lawson flips
+//
+// Round r: every failing edge joins the round's list and claims its two
+// triangles and their (up to) four neighbours with a priority whose top bits
+// are the round (so claims of earlier rounds never win and the claims need no
+// clearing); the listed edges that hold all six claims flip. An edge is
+// tested in round r only if one of its triangles was changed by a flip of
+// round r - 1, or held an edge that failed and did not flip (their stamp is
+// r; round 0 tests every edge), and only from one of its triangles. Each kernel returns at once after an error or
+// once a round has found no failing edge, so the host launches rounds in
+// batches and reads the counts once per batch.
 
 __device__ __forceinline__ uint64_t flip_priority(int32_t h, uint32_t round) {
-  return (splitmix64(0x5DEECE66Dull + round, (uint64_t)h) & ~0xFFFFFFFFull) | (uint32_t)h;
+  const uint64_t mix = splitmix64(0x5DEECE66Dull + round, (uint64_t)h) >> 44;  // 20 random bits
+  return ((uint64_t)round << 52) | (mix << 32) | (uint32_t)h;
 }
 
 // the half-edge h (h < twin) fails the in-circle test: the apex of its twin's
 // triangle lies inside the circle of h's triangle
-__device__ __forceinline__ bool bad_edge(int32_t h, const int32_t* twin, const int32_t* origin,
-                                         const int64_t* lat) {
-  const int32_t ht = twin[h];
-  if (ht < 0 || ht < h) return false;
+__device__ __forceinline__ bool fails_incircle(int32_t h, int32_t ht, const int32_t* origin, const int64_t* lat) {
   const int32_t a = origin[h], b = origin[he_next(h)], c = origin[he_next(he_next(h))];
   const int32_t d = origin[he_next(he_next(ht))];
   return incircle(lat, a, b, c, d) > 0;
 }
 
-__global__ __launch_bounds__(256) void k_gen_claim(int64_t nt, const int32_t* __restrict__ twin,
+// the rounds before r all found failing edges and no error is recorded
+__device__ __forceinline__ bool round_live(const uint32_t* bad, uint32_t r, const Counters* cnt) {
+  return cnt->error == 0 && (r == 0 || bad[r - 1] != 0u);
+}
+
+__global__ __launch_bounds__(256) void k_gen_claim(const int64_t* __restrict__ n_tri, const int32_t* __restrict__ twin,
                                                    const int32_t* __restrict__ origin,
-                                                   const int64_t* __restrict__ lat, unsigned long long* claim,
-                                                   uint32_t round, uint32_t* n_bad) {
-  const int64_t nh = 3 * nt;
-  for (int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; h < nh; h += (int64_t)gridDim.x * blockDim.x) {
-    if (!bad_edge((int32_t)h, twin, origin, lat)) continue;
-    atomicAdd(n_bad, 1u);
-    const unsigned long long pr = flip_priority((int32_t)h, round);
-    const int32_t ht = twin[h];
-    const int32_t hs[6] = {(int32_t)h, ht, he_next((int32_t)h), he_next(he_next((int32_t)h)), he_next(ht),
-                           he_next(he_next(ht))};
+                                                   const int64_t* __restrict__ lat,
+                                                   const uint16_t* __restrict__ stamp, unsigned long long* claim,
+                                                   int32_t* __restrict__ list, uint32_t* bad, uint32_t round,
+                                                   const Counters* cnt) {
+  if (!round_live(bad, round, cnt)) return;
+  const int64_t nh = 3 * *n_tri;
+  const int lane = threadIdx.x & 63;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  // wave-uniform loop: the failing edges of a wave join the list with one counter update
+  for (int64_t h0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); h0 < nh; h0 += stride) {
+    const int64_t hh = h0 + lane;
+    bool fail = false;
+    int32_t ht = -1;
+    // an edge is tested from a stamped triangle, from the smaller one when both are
+    if (hh < nh && stamp[hh / 3] == round) {
+      ht = twin[hh];
+      if (ht >= 0) {
+        const int64_t t = hh / 3, u = ht / 3;
+        if (stamp[u] != round || u > t) fail = fails_incircle((int32_t)hh, ht, origin, lat);
+      }
+    }
+    const uint64_t m = __ballot(fail);
+    if (m == 0ull) continue;
+    uint32_t base = 0;
+    if (lane == 0) base = atomicAdd(&bad[round], (uint32_t)__popcll(m));
+    base = __shfl(base, 0, 64);
+    if (!fail) continue;
+    const int32_t h = (int32_t)hh;
+    list[base + __popcll(m & ((1ull << lane) - 1ull))] = h;
+    const unsigned long long pr = flip_priority(h, round);
+    const int32_t hs[4] = {he_next(h), he_next(he_next(h)), he_next(ht), he_next(he_next(ht))};
     atomicMax(&claim[h / 3], pr);
     atomicMax(&claim[ht / 3], pr);
-    for (int k = 2; k < 6; ++k) {
+    for (int k = 0; k < 4; ++k) {
       const int32_t nb = twin[hs[k]];
       if (nb >= 0) atomicMax(&claim[nb / 3], pr);
     }
   }
 }
 
-__global__ __launch_bounds__(256) void k_gen_flip(int64_t nt, int32_t* __restrict__ twin, int32_t* __restrict__ origin,
-                                                  const int64_t* __restrict__ lat,
-                                                  const unsigned long long* __restrict__ claim, uint32_t round) {
-  const int64_t nh = 3 * nt;
-  for (int64_t hh = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; hh < nh; hh += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t h = (int32_t)hh;
-    if (!bad_edge(h, twin, origin, lat)) continue;
+__global__ __launch_bounds__(256) void k_gen_flip(int32_t* __restrict__ twin, int32_t* __restrict__ origin,
+                                                  const unsigned long long* __restrict__ claim,
+                                                  const int32_t* __restrict__ list, uint16_t* __restrict__ stamp,
+                                                  const uint32_t* bad, uint32_t round, const Counters* cnt) {
+  if (cnt->error != 0) return;
+  const uint32_t n = bad[round];
+  const uint16_t next = (uint16_t)(round + 1);
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int32_t h = list[i];
     const unsigned long long pr = flip_priority(h, round);
     const int32_t ht = twin[h];
     const int32_t hn = he_next(h), hp = he_next(hn), tn = he_next(ht), tp = he_next(tn);
@@ -437,7 +657,10 @@ __global__ __launch_bounds__(256) void k_gen_flip(int64_t nt, int32_t* __restric
     bool mine = claim[h / 3] == pr && claim[ht / 3] == pr;
     for (int k = 0; k < 4; ++k)
       if (nbs[k] >= 0) mine = mine && claim[nbs[k] / 3] == pr;
-    if (!mine) continue;
+    if (!mine) {
+      stamp[h / 3] = next;  // still failing: tested again next round
+      continue;
+    }
     // h = a->b in (a, b, c), ht = b->a in (b, a, d): new (c, a, d) in h's
     // triangle and (d, b, c) in ht's
     const int32_t a = origin[h], b = origin[hn], c = origin[hp], d = origin[tp];
@@ -459,38 +682,38 @@ __global__ __launch_bounds__(256) void k_gen_flip(int64_t nt, int32_t* __restric
     if (ta_d >= 0) twin[ta_d] = t1 + 1;
     if (td_b >= 0) twin[td_b] = t2;
     if (tb_c >= 0) twin[tb_c] = t2 + 1;
+    stamp[h / 3] = next;
+    stamp[ht / 3] = next;
   }
-}
-
-__global__ __launch_bounds__(256) void k_gen_clear(unsigned long long* claim, int64_t n, uint32_t* n_bad) {
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
-    claim[k] = 0ull;
-  if (blockIdx.x == 0 && threadIdx.x == 0) *n_bad = 0u;
 }
 
 }  // namespace polylla
 
 namespace polylla {
 
-__global__ void k_gen_zero(uint32_t* a, int n) {
-  if (blockIdx.x == 0 && (int)threadIdx.x < n) a[threadIdx.x] = 0u;
-}
 
 // Host driver (called by polylla_gen_grid). ws: device work space of
 // gen_ws_bytes(g) bytes. Returns a polylla code; *n_tri receives the number
 // of triangles.
+constexpr int kGenMaxRounds = 4095;  // flip rounds before EDEGEN (the round is 12 bits of a claim)
+constexpr int kGenFirstRounds = 12;  // rounds launched before the first read of the counts
+constexpr int kGenMoreRounds = 4;    // then between reads
+
 size_t gen_ws_bytes(int64_t g) {
   const int64_t V = g * g, Tmax = 2 * V;
   const int64_t seg = 4 * g + 8;
   size_t b = 0;
   auto add = [&](size_t n) { b += (n + 255) & ~(size_t)255; };
-  add(sizeof(int64_t) * 2 * V);        // lattice coordinates
-  add((size_t)V);                      // cell diagonals
+  add(sizeof(int64_t) * 2 * V);            // lattice coordinates
+  add((size_t)V);                          // cell diagonals
   add(sizeof(unsigned long long) * Tmax);  // flip claims
-  add(sizeof(int32_t) * 44 * g + 64);  // side and corner scans
+  add(sizeof(int32_t) * 44 * g + 64);      // side and corner scans
   add(sizeof(int32_t) * 2 * 3 * 5 * seg);  // pocket store
-  add(sizeof(uint32_t) * 16);          // pocket counts, bad-edge count
-  add(sizeof(int64_t) * 8);            // hull lengths, triangle count
+  add(sizeof(uint32_t) * 16);              // pocket counts
+  add(sizeof(int64_t) * 8);                // hull lengths, triangle count
+  add(sizeof(uint32_t) * kGenMaxRounds);   // failing edges per flip round
+  add(sizeof(uint16_t) * Tmax);            // round stamps of the triangles
+  add(sizeof(int32_t) * (3 * Tmax / 2 + 64));  // the round's failing edges
   return b;
 }
 
@@ -511,54 +734,71 @@ int gen_grid_run(int64_t g, double jitter, uint64_t seed, double* xy, int32_t* t
   int32_t* porg = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * 2 * 3 * 5 * seg));
   uint32_t* u32 = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * 16));
   int64_t* i64 = reinterpret_cast<int64_t*>(take(sizeof(int64_t) * 8));
+  uint32_t* bad = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kGenMaxRounds));
+  uint16_t* stamp = reinterpret_cast<uint16_t*>(take(sizeof(uint16_t) * Tmax));
+  int32_t* list = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * (3 * Tmax / 2 + 64)));
   const int64_t tri_base = 2 * (g - 1) * (g - 1);
   Pockets P{porg, porg + 3 * 5 * seg, u32, seg, (int32_t)(3 * (tri_base + 8 * g + 64))};
-  uint32_t* n_bad = u32 + 8;
+  const int64_t* d_tri = i64 + 4;
+  const int64_t cap = std::min(cap_tri, Tmax);
   const int grid = (int)std::min<int64_t>((V + 255) / 256, 1 << 16);
-  hipLaunchKernelGGL(k_gen_zero, dim3(1), dim3(64), 0, s, u32, 16);
+  const int hgrid = (int)std::min<int64_t>((3 * Tmax + 255) / 256, 1 << 16);
+  if (hipMemsetAsync(u32, 0, sizeof(uint32_t) * 16, s) != hipSuccess ||
+      hipMemsetAsync(bad, 0, sizeof(uint32_t) * kGenMaxRounds, s) != hipSuccess ||
+      hipMemsetAsync(claim, 0, sizeof(unsigned long long) * Tmax, s) != hipSuccess ||
+      hipMemsetAsync(stamp, 0, sizeof(uint16_t) * Tmax, s) != hipSuccess)
+    return POLYLLA_EHIP;
   hipLaunchKernelGGL(k_gen_points, dim3(grid), dim3(256), 0, s, g, jitter, seed, xy, lat);
   hipLaunchKernelGGL(k_gen_cells, dim3(grid), dim3(256), 0, s, g, (const int64_t*)lat, origin, diag, cnt);
   hipLaunchKernelGGL(k_gen_twins, dim3(grid), dim3(256), 0, s, g, (const uint8_t*)diag, twin);
-  hipLaunchKernelGGL(k_gen_sides, dim3(4), dim3(64), 0, s, g, (const int64_t*)lat, (const uint8_t*)diag, twin, wsp,
-                     i64, P, cnt);
+  const int64_t nch = (g - 1 + kGenChunk - 1) / kGenChunk;
+  const size_t side_lds = sizeof(int32_t) * (size_t)(3 * g + 2 * nch * (kGenChunk + 1) + nch);
+  if (g <= kGenSideLds)
+    hipLaunchKernelGGL(k_gen_sides_lds, dim3(4), dim3(256), side_lds, s, g, (const int64_t*)lat,
+                       (const uint8_t*)diag, twin, wsp, i64, P, cnt);
+  else
+    hipLaunchKernelGGL(k_gen_sides, dim3(4), dim3(64), 0, s, g, (const int64_t*)lat, (const uint8_t*)diag, twin,
+                       wsp, i64, P, cnt);
   hipLaunchKernelGGL(k_gen_corners, dim3(1), dim3(64), 0, s, g, (const int64_t*)lat, twin, wsp,
                      (const int64_t*)i64, P, cnt);
-  hipLaunchKernelGGL(k_gen_pack, dim3(64), dim3(256), 0, s, P, tri_base, std::min(cap_tri, Tmax), origin, twin,
-                     i64 + 4, cnt);
+  hipLaunchKernelGGL(k_gen_pack, dim3(64), dim3(256), 0, s, P, tri_base, cap, origin, twin, i64 + 4, cnt);
+  hipLaunchKernelGGL(k_gen_check, dim3(hgrid), dim3(256), 0, s, d_tri, V, (const int32_t*)twin,
+                     (const int32_t*)origin, (const int64_t*)lat, cnt);
   if (hipGetLastError() != hipSuccess) return POLYLLA_EHIP;
-  int64_t T = 0;
-  if (hipMemcpyAsync(&T, i64 + 4, sizeof(T), hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipStreamSynchronize(s) != hipSuccess)
-    return POLYLLA_EHIP;
-  if (T <= 0 || T > cap_tri || T > Tmax) return POLYLLA_EINTERNAL;
-  hipLaunchKernelGGL(k_gen_check, dim3((int)std::min<int64_t>((3 * T + 255) / 256, 1 << 16)), dim3(256), 0, s, T,
-                     V, (const int32_t*)twin, (const int32_t*)origin, (const int64_t*)lat, cnt);
-  {
-    Counters h;
-    if (hipMemcpyAsync(&h, cnt, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
-      return POLYLLA_EHIP;
-    if (h.error) return h.error;
-  }
-  // Lawson flips until every edge passes the in-circle test
-  const int fgrid = (int)std::min<int64_t>((3 * T + 255) / 256, 1 << 16);
+  // Lawson flips until every edge passes the in-circle test, rounds launched
+  // in batches (a converged or failed round makes the rest return at once)
+  struct {
+    int64_t nt;
+    uint32_t last;
+    int32_t err;
+  } h{};
   int r = 0;
-  for (;; ++r) {
-    if (r > 4096) return POLYLLA_EDEGEN;
-    hipLaunchKernelGGL(k_gen_clear, dim3((int)std::min<int64_t>((T + 255) / 256, 1 << 16)), dim3(256), 0, s, claim,
-                       T, n_bad);
-    hipLaunchKernelGGL(k_gen_claim, dim3(fgrid), dim3(256), 0, s, T, (const int32_t*)twin, (const int32_t*)origin,
-                       (const int64_t*)lat, claim, (uint32_t)r, n_bad);
-    uint32_t bad = 0;
-    if (hipMemcpyAsync(&bad, n_bad, sizeof(bad), hipMemcpyDeviceToHost, s) != hipSuccess ||
+  for (int batch = kGenFirstRounds;; batch = kGenMoreRounds) {
+    for (int k = 0; k < batch; ++k, ++r) {
+      hipLaunchKernelGGL(k_gen_claim, dim3(hgrid), dim3(256), 0, s, d_tri, (const int32_t*)twin,
+                         (const int32_t*)origin, (const int64_t*)lat, (const uint16_t*)stamp, claim, list, bad,
+                         (uint32_t)r, (const Counters*)cnt);
+      hipLaunchKernelGGL(k_gen_flip, dim3(hgrid), dim3(256), 0, s, twin, origin, (const unsigned long long*)claim,
+                         (const int32_t*)list, stamp, (const uint32_t*)bad, (uint32_t)r, (const Counters*)cnt);
+    }
+    if (hipMemcpyAsync(&h.nt, d_tri, sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(&h.last, bad + r - 1, sizeof(uint32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(&h.err, &cnt->error, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
       return POLYLLA_EHIP;
-    if (bad == 0) break;
-    hipLaunchKernelGGL(k_gen_flip, dim3(fgrid), dim3(256), 0, s, T, twin, origin, (const int64_t*)lat,
-                       (const unsigned long long*)claim, (uint32_t)r);
+    if (h.err) return h.err;
+    if (h.last == 0) break;
+    if (r + kGenMoreRounds > kGenMaxRounds) return POLYLLA_EDEGEN;
   }
-  *n_tri = T;
-  if (rounds) *rounds = r;
+  if (h.nt <= 0 || h.nt > cap) return POLYLLA_EINTERNAL;
+  // rounds that found failing edges (the first round without one ends the flips)
+  std::vector<uint32_t> counts((size_t)r);
+  if (hipMemcpy(counts.data(), bad, sizeof(uint32_t) * (size_t)r, hipMemcpyDeviceToHost) != hipSuccess)
+    return POLYLLA_EHIP;
+  int done = 0;
+  while (done < r && counts[(size_t)done] != 0u) ++done;
+  *n_tri = h.nt;
+  if (rounds) *rounds = done;
   return hipGetLastError() == hipSuccess ? POLYLLA_OK : POLYLLA_EHIP;
 }
 

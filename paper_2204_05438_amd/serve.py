@@ -18,6 +18,11 @@ arrive over time. The loop
     at a time, so only the bad request fails (`error` set, no polygons);
   * copies each batch's polygons back (sizes first, then exactly the produced
     CSR) and splits them per request.
+A request may also name its input instead of carrying it: a jittered g x g
+grid (g, jitter, seed) is triangulated on the device after admission
+(polylla_gen_grid, by a generator thread with its own context and stream, so
+the loop keeps dispatching batches meanwhile), and nothing crosses PCIe on
+the way in.
 Latency of a request = results on the host - arrival, split into admission
 wait, queueing after admission and service (pack + mesh + copy back).
 """
@@ -25,6 +30,8 @@ from __future__ import annotations
 
 import collections
 import dataclasses
+import queue
+import threading
 import time
 
 import numpy as np
@@ -37,9 +44,10 @@ from . import lib
 class Request:
     rid: int
     arrival: float        # seconds after the start of the run
-    xy: torch.Tensor      # float64 [V, 2], pinned host memory
-    twin: torch.Tensor    # int32 [H], pinned, local indices
-    origin: torch.Tensor  # int32 [H], pinned, local indices
+    xy: torch.Tensor | None      # float64 [V, 2], pinned host memory (None: generated on the device)
+    twin: torch.Tensor | None    # int32 [H], pinned, local indices
+    origin: torch.Tensor | None  # int32 [H], pinned, local indices
+    gen: tuple | None = None     # (g, jitter, seed): input generated on the device at admission
     admitted: float | None = None
     started: float | None = None
     done: float | None = None
@@ -49,14 +57,21 @@ class Request:
     alone: bool = False                # served in a batch of its own (after its batch failed)
     _dev: tuple | None = None
     _ready: torch.cuda.Event | None = None
+    _charged: int = 0                  # bytes charged to the admission budget
+    _size: tuple | None = None         # (vertices, half-edges) of a generated input
 
     @property
     def n_vertices(self) -> int:
-        return int(self.xy.shape[0])
+        if self.xy is not None:
+            return int(self.xy.shape[0])
+        return self._size[0] if self._size else self.gen[0] * self.gen[0]
 
     @property
     def n_halfedges(self) -> int:
-        return int(self.origin.shape[0])
+        if self.origin is not None:
+            return int(self.origin.shape[0])
+        # a grid not generated yet: its bound, 3 (2 g^2 - 5) < 6 g^2
+        return self._size[1] if self._size else 6 * self.gen[0] * self.gen[0]
 
     @property
     def n_tri(self) -> int:
@@ -69,6 +84,12 @@ class Request:
     def from_mesh(rid: int, arrival: float, mesh) -> "Request":
         return Request(rid, arrival, torch.from_numpy(mesh.xy).pin_memory(),
                        torch.from_numpy(mesh.twin).pin_memory(), torch.from_numpy(mesh.origin).pin_memory())
+
+    @staticmethod
+    def from_grid(rid: int, arrival: float, g: int, jitter: float = 0.45, seed: int = 0) -> "Request":
+        """A request whose input is the Delaunay triangulation of a jittered
+        g x g grid, generated on the device when it is admitted."""
+        return Request(rid, arrival, None, None, None, gen=(int(g), float(jitter), int(seed)))
 
 
 class _Slot:
@@ -194,10 +215,56 @@ class Server:
         self.slots = [_Slot(device, max_batch_tri, mv, max_batch_meshes) for _ in range(slots)]
         self.max_tri, self.max_meshes, self.max_vert = max_batch_tri, max_batch_meshes, mv
         self.admit_stream = torch.cuda.Stream(torch.device("cuda", device))
+        # generator thread for requests that name a grid (started on first use)
+        self._gen_q: queue.Queue = queue.Queue()
+        self._gen_done: collections.deque = collections.deque()
+        self._gen_thread = None
 
     def close(self):
         for s in self.slots:
             s.close()
+        if self._gen_thread is not None:
+            self._gen_q.put(None)
+            self._gen_thread.join()
+            self._gen_thread = None
+
+    def _generator(self):
+        """Generator thread: triangulates the named grids in admission order on
+        its own context and stream; the library call waits for the stream with
+        the interpreter lock released."""
+        ctx = lib.Context(self.device)
+        stream = torch.cuda.Stream(torch.device("cuda", self.device))
+        try:
+            while True:
+                r = self._gen_q.get()
+                if r is None:
+                    return
+                try:
+                    with torch.cuda.stream(stream):
+                        tri, _ = ctx.gen_grid(*r.gen)
+                        r._dev = (tri.xy, tri.twin, tri.origin)
+                        r._size = (tri.n_vertices, tri.n_halfedges)
+                        r._ready = torch.cuda.Event()
+                        r._ready.record(stream)
+                except lib.PolyllaError as e:
+                    r.error = e.code
+                self._gen_done.append(r)
+        finally:
+            ctx.close()
+
+    def _admit(self, r: Request, dev, resident):
+        if r.gen is not None:
+            if self._gen_thread is None:
+                self._gen_thread = threading.Thread(target=self._generator, daemon=True)
+                self._gen_thread.start()
+            self._gen_q.put(r)
+            return
+        with torch.cuda.stream(self.admit_stream):
+            r._dev = (r.xy.to(dev, non_blocking=True), r.twin.to(dev, non_blocking=True),
+                      r.origin.to(dev, non_blocking=True))
+            r._ready = torch.cuda.Event()
+            r._ready.record(self.admit_stream)
+        resident.append(r)
 
     def run(self, requests: list[Request]) -> dict:
         """Serve `requests` (sorted by arrival) in real time; returns throughput
@@ -222,15 +289,21 @@ class Server:
                 waiting.append(pending.popleft())
             while waiting and used + waiting[0].input_bytes() <= self.budget:
                 r = waiting.popleft()
-                used += r.input_bytes()
+                r._charged = r.input_bytes()
+                used += r._charged
                 r.admitted = now
-                with torch.cuda.stream(self.admit_stream):
-                    r._dev = (r.xy.to(dev, non_blocking=True), r.twin.to(dev, non_blocking=True),
-                              r.origin.to(dev, non_blocking=True))
-                    r._ready = torch.cuda.Event()
-                    r._ready.record(self.admit_stream)
-                resident.append(r)
+                self._admit(r, dev, resident)
                 progressed = True
+            while self._gen_done:  # generated inputs join the resident requests
+                r = self._gen_done.popleft()
+                progressed = True
+                if r.error:
+                    r.done = time.perf_counter() - t0
+                    r.started = r.done
+                    used -= r._charged
+                    finished.append(r)
+                else:
+                    resident.append(r)
             for slot in self.slots:
                 if slot.state == _Slot.COMPUTE and slot.event.query():
                     if not slot.copy_back():
@@ -238,7 +311,7 @@ class Server:
                         if len(bad) == 1 and bad[0].alone:
                             r = bad[0]  # fails on its own: answered with the error, no polygons
                             r.error, r.done, r._dev = slot.failed, time.perf_counter() - t0, None
-                            used -= r.input_bytes()
+                            used -= r._charged
                             finished.append(r)
                         else:
                             for r in reversed(bad):  # served again, one request per batch
@@ -248,7 +321,7 @@ class Server:
                 if slot.state == _Slot.COPY and slot.event.query():
                     done = slot.finish(time.perf_counter() - t0)
                     for r in done:
-                        used -= r.input_bytes()
+                        used -= r._charged
                     finished.extend(done)
                     progressed = True
                 if slot.state == _Slot.IDLE and resident:

@@ -62,3 +62,38 @@ def test_bad_request_fails_alone():
         assert r.error == 0
         assert np.array_equal(r.offsets, o["offsets"]), r.rid
         assert np.array_equal(r.verts, o["verts"]), r.rid
+
+
+def test_generated_requests_equal_oracle():
+    """Requests that name a jittered grid are triangulated on the device at
+    admission (no host input), served in the mix with ordinary requests, and
+    give the oracle's polygons on the same generated mesh."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    print("[gpu-case] serve 24 generated + 8 host requests, 2 slots", flush=True)
+    from paper_2204_05438_amd import lib, serve
+    from meshgen import gen as mg
+    meshes, arrivals = _requests(51, 8)
+    rng = np.random.default_rng(52)
+    grids = [(int(g), 0.45, 900 + j) for j, g in enumerate(rng.integers(4, 90, 24))]
+    server = serve.Server(0, slots=2, budget_bytes=8 << 20, max_batch_tri=1 << 16, max_batch_meshes=8)
+    reqs = [serve.Request.from_mesh(j, float(arrivals[j]), m) for j, m in enumerate(meshes)]
+    reqs += [serve.Request.from_grid(100 + j, 0.001 * j, *gr) for j, gr in enumerate(grids)]
+    stats = server.run(reqs)
+    server.close()
+    assert stats["requests"] == len(reqs) and stats["failed"] == 0
+    ctx = lib.Context(0)
+    for r in reqs:
+        assert r.error == 0
+        if r.gen is None:
+            o = oracle.oracle_on(meshes[r.rid])
+        else:
+            tri, _ = ctx.gen_grid(*r.gen)
+            xy, origin, twin = (x.cpu().numpy() for x in (tri.xy, tri.origin, tri.twin))
+            h = np.arange(origin.shape[0])
+            m = mg.Mesh(xy=xy, origin=origin, twin=twin, next=(h - h % 3 + (h + 1) % 3).astype(np.int32))
+            assert r.n_tri == m.n_tri
+            o = oracle.oracle_on(m)
+        assert np.array_equal(r.offsets, o["offsets"]), r.rid
+        assert np.array_equal(r.verts, o["verts"]), r.rid
+    ctx.close()

@@ -283,8 +283,9 @@ int polylla_mesh_batched(polylla_ctx *ctx, const polylla_batch *batch, polylla_l
  * [cap_halfedges] int32, cap_halfedges >= 6 g^2, else ECAPACITY);
  * n_halfedges (host) receives 3 x the triangle count (2 g^2 - 2 - hull
  * vertices); flip_rounds (host, may be NULL) the number of rounds of parallel
- * edge flips. Synchronous: waits for `stream` (the flip rounds read a count on
- * the host). Allocates a work space of about 32 g^2 bytes, kept by the context.
+ * edge flips. Synchronous: waits for `stream` (the flip rounds are launched in
+ * batches and a count is read on the host after each). Allocates a work space
+ * of about 50 g^2 bytes, kept by the context.
  * Errors: EINVAL for bad arguments, ENOMEM, EDEGEN if the flips do not end,
  * EINTERNAL on a work-space overflow. */
 int polylla_gen_grid(polylla_ctx *ctx, int64_t g, double jitter, uint64_t seed, double *xy, int32_t *twin,

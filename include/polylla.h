@@ -155,7 +155,8 @@ int polylla_build(polylla_ctx *ctx, const polylla_tri *tri, polylla_labels *labe
 /* Reparation phase (Algorithm 4, run until no barrier-edge tip remains):
  * `in` must be the output of polylla_build on the same labels, which must not
  * have been repaired before. Adds FRONTIER | REPAIRED on the opened edges.
- * `in` and `out` must not overlap. */
+ * Polygons of `in` without a tip are copied as they are; only those with one
+ * are walked again. `in` and `out` must not overlap. */
 int polylla_repair(polylla_ctx *ctx, const polylla_tri *tri, polylla_labels *labels,
                    const polylla_polys *in, polylla_polys *out, hipStream_t stream);
 

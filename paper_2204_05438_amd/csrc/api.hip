@@ -26,6 +26,8 @@ __global__ void k_label(int64_t, const int32_t*, const uint8_t*, uint8_t*, uint8
                         uint32_t*, uint32_t*, Counters*, bool, const uint8_t*);
 __global__ void k_seeds(int64_t, const uint8_t*, const uint32_t*, const uint32_t*, int32_t*, Counters*);
 __global__ void k_pack_walk(int64_t, const uint8_t*, const int32_t*, const int32_t*, int32_t*);
+__global__ void k_repair_prep(const int32_t*, const int32_t*, const int32_t*, int32_t*, int64_t, PolyState, int32_t*,
+                              int64_t, int, Counters*);
 template <bool FROM_SEEDS>
 __global__ void k_walk(const int32_t*, int32_t, const int32_t*, int32_t*, int64_t, PolyState, int32_t*, int64_t, int,
                        Counters*);
@@ -178,13 +180,13 @@ constexpr int64_t kStageChunkHost = 4096; // staging ints a walk wave reserves a
 
 enum KernelId {
   KR_RESET, KR_LONGEST, KR_LABEL, KR_COMPACT, KR_PACK, KR_WALK, KR_GENERAL, KR_BIG, KR_HUGE, KR_SCAN, KR_VALIDATE,
-  KR_BATCH, KR_BIGW, KR_TIP, KR_SEEDS, KR_GENW, KR_GREBASE, KR_GFINISH, KR_LEPP, KR_N
+  KR_BATCH, KR_BIGW, KR_TIP, KR_SEEDS, KR_GENW, KR_GREBASE, KR_GFINISH, KR_LEPP, KR_PREP, KR_N
 };
 const char* kKernelNames[KR_N] = {"k_reset",         "k_longest",       "k_label",          "k_compact_seeds",
                                   "k_pack_walk",     "k_walk",          "k_general_small",  "k_general_big",
                                   "k_general_huge",  "k_scan_emit",     "k_validate",       "k_batch_offsets",
                                   "k_general_big_wg", "k_tip",           "k_seeds",          "k_general_wave",
-                                  "k_group_rebase",  "k_group_finish",  "k_lepp"};
+                                  "k_group_rebase",  "k_group_finish",  "k_lepp",           "k_repair_prep"};
 
 // Event pair around one kernel launch when profiling is on.
 struct Prof {
@@ -412,19 +414,22 @@ int run_label(polylla_ctx* c, const polylla_tri* t, uint8_t* he, uint8_t* tri, u
 // Walk + general path + scan + emit over the list `list` of seeds (from_seeds)
 // or start half-edges; n (device) polygons already in cnt->n_seeds.
 int run_build(polylla_ctx* c, const polylla_tri* t, const int32_t* list, bool from_seeds, bool repair,
-              uint8_t* he, uint8_t* vtx, polylla_polys* out, hipStream_t s) {
+              uint8_t* he, uint8_t* vtx, polylla_polys* out, hipStream_t s, const polylla_polys* prep_in = nullptr) {
   const int64_t T = t->n_halfedges / 3;
   const int32_t nhe = (int32_t)t->n_halfedges;
   PolyState ps = poly_state(c);
-  {
+  if (prep_in) {
+    // repair of built polygons: only those with a tip are walked again
+    Prof p(c, s, KR_PREP);
+    hipLaunchKernelGGL(k_repair_prep, dim3(grid_for(T, 256, 4096)), dim3(256), 0, s, prep_in->offsets, prep_in->verts,
+                       prep_in->start, c->sc->stage, c->sc->stage_cap, ps, c->sc->deferred, c->sc->cap_t, c->walk_cap,
+                       c->cnt);
+  } else {
     Prof p(c, s, KR_WALK);
     const int gw = std::min(c->walk_blocks, c->sc->walk_grid);  // persistent: waves take seeds from per-XCD queues
-    if (from_seeds)
-      hipLaunchKernelGGL(k_walk<true>, dim3(gw), dim3(256), 0, s, list, nhe, c->sc->wk, c->sc->stage,
-                         c->sc->stage_cap, ps, c->sc->deferred, c->sc->cap_t, c->walk_cap, c->cnt);
-    else
-      hipLaunchKernelGGL(k_walk<false>, dim3(gw), dim3(256), 0, s, list, nhe, c->sc->wk, c->sc->stage,
-                         c->sc->stage_cap, ps, c->sc->deferred, c->sc->cap_t, c->walk_cap, c->cnt);
+    if (!from_seeds) return POLYLLA_EINTERNAL;  // a list of start half-edges is only repaired (prep_in)
+    hipLaunchKernelGGL(k_walk<true>, dim3(gw), dim3(256), 0, s, list, nhe, c->sc->wk, c->sc->stage,
+                       c->sc->stage_cap, ps, c->sc->deferred, c->sc->cap_t, c->walk_cap, c->cnt);
   }
   // the long regions (workgroup kernels, caller's stream) and the flagged
   // short polygons (tip path and per-lane kernels, second stream) in
@@ -682,7 +687,7 @@ int polylla_repair(polylla_ctx* c, const polylla_tri* t, polylla_labels* l, cons
     hipLaunchKernelGGL(k_pack_walk, dim3(grid_for(3 * T, 256, 1 << 16)), dim3(256), 0, s, 3 * T, l->he, t->twin,
                        t->origin, c->sc->wk);
   }
-  return run_build(c, t, in->start, false, true, l->he, l->vtx, out, s);
+  return run_build(c, t, in->start, false, true, l->he, l->vtx, out, s, in);
 }
 
 int polylla_mesh(polylla_ctx* c, const polylla_tri* t, polylla_labels* l, polylla_polys* out, hipStream_t s) {

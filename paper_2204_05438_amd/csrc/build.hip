@@ -444,6 +444,59 @@ __global__ __launch_bounds__(256) void k_walk(const int32_t* __restrict__ list, 
   flush_deferred();
 }
 
+// Reparation phase on the polygons of polylla_build (their vertices, start
+// half-edges and count in the input CSR): a polygon without a barrier-edge tip
+// (no cyclic v[k-1] == v[k+1]) is final as it is (already canonical) and its
+// vertices are staged at its input offset; the others are queued, from their
+// start half-edges, for the tip path or, longer than the walk cap, for the
+// long-region path, so only they are walked again. Queue slots are reserved
+// once per wave.
+__global__ __launch_bounds__(256) void k_repair_prep(const int32_t* __restrict__ offsets,
+                                                     const int32_t* __restrict__ verts,
+                                                     const int32_t* __restrict__ start, int32_t* __restrict__ stage,
+                                                     int64_t stage_cap, PolyState ps, int32_t* __restrict__ deferred,
+                                                     int64_t deferred_cap, int walk_cap, Counters* cnt) {
+  const uint32_t R = cnt->n_seeds;
+  const int lane = threadIdx.x & 63;
+  if (blockIdx.x == 0 && threadIdx.x == 0) cnt->stage_top = (uint32_t)offsets[R];  // the staged copies come first
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); i0 < R; i0 += stride) {
+    const int64_t i = i0 + lane;
+    const bool valid = i < R;
+    int32_t o = 0, L = 0;
+    bool tip = false;
+    if (valid) {
+      o = offsets[i];
+      L = offsets[i + 1] - o;
+      if (L >= 3)
+        for (int32_t k = 0; k < L && !tip; ++k) tip = verts[o + (k == 0 ? L - 1 : k - 1)] == verts[o + (k + 1 == L ? 0 : k + 1)];
+      if (!tip) {
+        if ((int64_t)o + L > stage_cap) {
+          set_error(cnt, POLYLLA_ENOMEM);
+          ps.clear(i);
+        } else {
+          for (int32_t k = 0; k < L; ++k) stage[o + k] = verts[o + k];
+          ps.set(i, L, 1, start[i], o);
+        }
+      } else {
+        ps.set(i, L, 0, start[i], -1);
+      }
+    }
+    const bool q_small = tip && L <= walk_cap, q_large = tip && L > walk_cap;
+    const uint64_t m_small = __ballot(q_small), m_large = __ballot(q_large);
+    uint32_t b_small = 0, b_large = 0;
+    if (lane == 0) {
+      if (m_small) b_small = atomicAdd(&cnt->n_deferred, (uint32_t)__popcll(m_small));
+      if (m_large) b_large = atomicAdd(&cnt->n_big, (uint32_t)__popcll(m_large));
+    }
+    b_small = __shfl(b_small, 0, 64);
+    b_large = __shfl(b_large, 0, 64);
+    const uint64_t below = (1ull << lane) - 1ull;
+    if (q_small) deferred[b_small + __popcll(m_small & below)] = (int32_t)i;
+    if (q_large) deferred[deferred_cap - 1 - (b_large + __popcll(m_large & below))] = (int32_t)i;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // general path
 
@@ -3122,8 +3175,6 @@ __global__ __launch_bounds__(256) void k_batch_offsets(int64_t n_meshes, const i
 
 template __global__ void k_walk<true>(const int32_t*, int32_t, const int32_t*,
                                       int32_t*, int64_t, PolyState, int32_t*, int64_t, int, Counters*);
-template __global__ void k_walk<false>(const int32_t*, int32_t, const int32_t*,
-                                       int32_t*, int64_t, PolyState, int32_t*, int64_t, int, Counters*);
 template __global__ void k_general_small<true>(const int32_t*, bool, int32_t, int64_t, const int32_t*,
                                                const int32_t*, const int32_t*, uint8_t*, uint8_t*, int32_t*,
                                                int64_t, int32_t*, int64_t, PolyState, const int32_t*,

@@ -343,6 +343,10 @@ int polylla_stats(polylla_ctx *ctx, int64_t *out, int n);
  * meshes (a larger mesh forms a group of its own). Lower values split a
  * batch into more groups (used by tests). */
 #define POLYLLA_PARAM_BATCH_GROUP_HE 6
+/* POLYLLA_PARAM_LONGEST_ITEMS (1, 2 or 4, default 2): triangles per thread of
+ * the longest-edge kernel (LabelMax): each thread issues the loads of that many
+ * triangles before it uses any. */
+#define POLYLLA_PARAM_LONGEST_ITEMS 7
 int polylla_set_param(polylla_ctx *ctx, int param, int64_t value);
 
 /* Per-kernel GPU timing with HIP events, for benchmarks (off by default).

@@ -19,6 +19,7 @@ __global__ void k_lepp_chase(int64_t, const uint8_t*, const int32_t*, const uint
                              int32_t*, uint32_t*, Counters*);
 __global__ void k_lepp_jump(const int32_t*, const int32_t*, const int4*, int4*, const int32_t*, const uint32_t*);
 __global__ void k_lepp_finish(int32_t*, int32_t*, const int4*, const int32_t*, const uint32_t*, Counters*);
+template <int kK>
 __global__ void k_longest(int64_t, int64_t, const double*, const int32_t*, const int32_t*, uint8_t*, uint8_t*,
                           Counters*);
 template <bool COMPUTE>
@@ -149,6 +150,7 @@ struct polylla_ctx {
   int64_t g_cap_he = 0, g_cap_m = 0;
   int64_t group_he = kGroupHeMax;
   int walk_cap = 24;  // vertices a lane walks before handing a polygon to a workgroup
+  int longest_items = 2;  // triangles per thread of k_longest (1, 2 or 4)
   uint32_t gen_wave_max = kGenWaveMax;  // declined short polygons up to which each gets a wave
   int32_t lds_max = 4096;               // region size limit of the 1024-thread LDS workgroup
   int32_t mem_max = (int32_t)kMemRegionMax;  // region size limit of the global-memory workgroup
@@ -391,13 +393,27 @@ void launch_seeds(polylla_ctx* c, int64_t T, const uint8_t* tri, hipStream_t s) 
                      tile_groups(c, T), c->sc->seeds, c->cnt);
 }
 
+// LabelMax with the context's triangles per thread; the grid also covers the
+// vertex labels it clears
+void launch_longest(polylla_ctx* c, const polylla_tri* t, int64_t T, uint8_t* vtx, hipStream_t s) {
+  const int k = c->longest_items;
+  const int grid = grid_for(std::max((T + k - 1) / k, vtx ? t->n_vertices : (int64_t)0), 256, 1 << 20);
+  if (k == 1)
+    hipLaunchKernelGGL(k_longest<1>, dim3(grid), dim3(256), 0, s, T, t->n_vertices, t->xy, t->origin, t->twin,
+                       c->sc->lg, vtx, c->cnt);
+  else if (k == 4)
+    hipLaunchKernelGGL(k_longest<4>, dim3(grid), dim3(256), 0, s, T, t->n_vertices, t->xy, t->origin, t->twin,
+                       c->sc->lg, vtx, c->cnt);
+  else
+    hipLaunchKernelGGL(k_longest<2>, dim3(grid), dim3(256), 0, s, T, t->n_vertices, t->xy, t->origin, t->twin,
+                       c->sc->lg, vtx, c->cnt);
+}
+
 int run_label(polylla_ctx* c, const polylla_tri* t, uint8_t* he, uint8_t* tri, uint8_t* vtx, hipStream_t s) {
   const int64_t T = t->n_halfedges / 3;
   {
     Prof p(c, s, KR_LONGEST);
-    // two triangles per thread (and one vertex to clear)
-    hipLaunchKernelGGL(k_longest, dim3(grid_for(std::max((T + 1) / 2, t->n_vertices), 256, 1 << 20)), dim3(256), 0,
-                       s, T, t->n_vertices, t->xy, t->origin, t->twin, c->sc->lg, vtx, c->cnt);
+    launch_longest(c, t, T, vtx, s);
   }
   if (T > 0) {
     Prof p(c, s, KR_LABEL);
@@ -716,8 +732,7 @@ int polylla_lepp(polylla_ctx* c, const polylla_tri* t, int32_t* terminal, int32_
   Scratch* S = c->sc;
   {
     Prof p(c, s, KR_LONGEST);  // LabelMax: the Max byte of every triangle
-    hipLaunchKernelGGL(k_longest, dim3(grid_for((T + 1) / 2, 256, 1 << 20)), dim3(256), 0, s, T, t->n_vertices,
-                       t->xy, t->origin, t->twin, S->lg, (uint8_t*)nullptr, c->cnt);
+    launch_longest(c, t, T, nullptr, s);
   }
   // path states in two int4 arrays over the staging (>= 5T ints) and arena
   // (>= 6T ints) scratch, the unfinished paths listed in the seed array
@@ -1009,6 +1024,10 @@ int polylla_set_param(polylla_ctx* c, int param, int64_t value) {
     case POLYLLA_PARAM_BATCH_GROUP_HE:
       if (value < 3 || value > kGroupHeMax) return POLYLLA_EINVAL;
       c->group_he = value;
+      return POLYLLA_OK;
+    case POLYLLA_PARAM_LONGEST_ITEMS:
+      if (value != 1 && value != 2 && value != 4) return POLYLLA_EINVAL;
+      c->longest_items = (int)value;
       return POLYLLA_OK;
     default:
       return POLYLLA_EINVAL;

@@ -66,6 +66,7 @@ __global__ void k_accumulate(Counters* cnt) {
   for (int k = 0; k < 7; ++k) cnt->acc[k] += v[k];
 }
 
+template <int kK>
 __global__ __launch_bounds__(256) void k_longest(int64_t nt, int64_t nv, const double* __restrict__ xy,
                                                  const int32_t* __restrict__ origin,
                                                  const int32_t* __restrict__ twin, uint8_t* __restrict__ lg,
@@ -76,10 +77,9 @@ __global__ __launch_bounds__(256) void k_longest(int64_t nt, int64_t nv, const d
     for (int64_t v = gid; v < nv; v += stride) vtx[v] = 0;
   const int32_t nhe = (int32_t)(3 * nt);
   const double2* __restrict__ p = reinterpret_cast<const double2*>(xy);
-  // two triangles per thread, 64 apart within the wave's span of 128: both
-  // origin triples, then all six vertex loads, are issued before first use
-  // (four per thread were slower: 105 -> 95 -> 135 us at 10M for 1, 2, 4)
-  constexpr int kK = 2;
+  // kK triangles per thread, 64 apart within the wave's span of 64 kK: all
+  // origin triples, then all vertex loads, are issued before first use (at
+  // 10M: 105, 95 and 135 us for 1, 2 and 4; the autotuner can choose)
   const int64_t wbase = (gid & ~(int64_t)63) * kK + (gid & 63);
   const int64_t wstride = stride * kK;
   for (int64_t t0 = wbase; t0 < nt; t0 += wstride) {
@@ -446,6 +446,13 @@ __global__ __launch_bounds__(256) void k_validate(int64_t nhe, int64_t nv, const
   }
 }
 
+#define POLYLLA_LONGEST(K)                                                                                  \
+  template __global__ void k_longest<K>(int64_t, int64_t, const double*, const int32_t*, const int32_t*, uint8_t*, \
+                                        uint8_t*, Counters*);
+POLYLLA_LONGEST(1)
+POLYLLA_LONGEST(2)
+POLYLLA_LONGEST(4)
+#undef POLYLLA_LONGEST
 template __global__ void k_label<true>(int64_t, const int32_t*, const uint8_t*, uint8_t*, uint8_t*, const int32_t*,
                                        int32_t*, uint32_t*, uint32_t*, Counters*, bool, const uint8_t*);
 template __global__ void k_label<false>(int64_t, const int32_t*, const uint8_t*, uint8_t*, uint8_t*, const int32_t*,

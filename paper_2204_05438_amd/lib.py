@@ -24,6 +24,7 @@ PARAM_GEN_WAVE_MAX = 3
 PARAM_REGION_LDS_MAX = 4
 PARAM_REGION_MEM_MAX = 5
 PARAM_BATCH_GROUP_HE = 6
+PARAM_LONGEST_ITEMS = 7
 PROFILE_OFF, PROFILE_ALL, PROFILE_WALK = 0, 1, 2
 
 

@@ -592,3 +592,20 @@ def test_batched_beyond_2e31_halfedges(ctx):
         got_off = out.offsets[k * F1:(k + 1) * F1 + 1] - k * S1
         assert torch.equal(got_off, ref_off), k
         assert torch.equal(out.verts[k * S1:(k + 1) * S1], ref_verts), k
+
+
+@pytest.mark.parametrize("items", [1, 2, 4])
+def test_longest_items_param(ctx, items):
+    """Each triangles-per-thread setting of the longest-edge kernel gives the
+    oracle's labels and polygons (sizes that leave ragged tails)."""
+    from paper_2204_05438_amd import lib
+    ctx.set_param(lib.PARAM_LONGEST_ITEMS, items)
+    try:
+        for n, kind in ((37, "uniform"), (1001, "lattice"), (4097, "cluster")):
+            _say(f"longest items {items} {kind} n {n}")
+            mesh = random_mesh(5100 + n, n, kind)
+            assert_same(gpu_mesh(ctx, mesh), oracle.oracle_on(mesh), FULL)
+        with pytest.raises(lib.PolyllaError):
+            ctx.set_param(lib.PARAM_LONGEST_ITEMS, 3)
+    finally:
+        ctx.set_param(lib.PARAM_LONGEST_ITEMS, 2)

@@ -6,8 +6,9 @@ polygons are in flight per XCD against the L2 they share), the walk cap
 (POLYLLA_PARAM_WALK_CAP: the longest cycle a lane walks before the polygon is
 queued for the workgroup kernel, i.e. the depth of that queue) and the
 triangles per thread of the longest-edge kernel (POLYLLA_PARAM_LONGEST_ITEMS:
-the loads a thread has in flight). `tune` times a grid of the first two on the
-caller's own input with HIP events, then the third at the best of them, keeps
+the loads a thread has in flight). `tune` times them one after the other on the
+caller's own input with HIP events (walk grid, then walk cap at the best grid,
+then the items at both), keeps
 the fastest, leaves it set on the context and caches it in a JSON file keyed
 by device and input size class, so later calls on inputs of the same class
 skip the sweep.
@@ -86,11 +87,18 @@ def tune(ctx: lib.Context, run, n_halfedges: int, *, batched: bool = False, bloc
         times.sort()
         return times[len(times) // 2]
 
+    # walk grid at the default cap, then the cap at the best grid, then the
+    # longest-edge items at both
     results = []
     ctx.set_param(lib.PARAM_LONGEST_ITEMS, 2)
+    ctx.set_param(lib.PARAM_WALK_CAP, 24)
     for wb in blocks:
-        for cap in caps:
-            ctx.set_param(lib.PARAM_WALK_BLOCKS, wb)
+        ctx.set_param(lib.PARAM_WALK_BLOCKS, wb)
+        results.append((median_ms(), wb, 24, 2))
+    ms, wb, cap, it = min(results)
+    ctx.set_param(lib.PARAM_WALK_BLOCKS, wb)
+    for cap in caps:
+        if cap != 24:
             ctx.set_param(lib.PARAM_WALK_CAP, cap)
             results.append((median_ms(), wb, cap, 2))
     ms, wb, cap, it = min(results)

@@ -172,6 +172,8 @@ __global__ __launch_bounds__(256) void k_walk(const int32_t* __restrict__ list, 
                                               const int32_t* __restrict__ wk, int32_t* __restrict__ stage,
                                               int64_t stage_cap, PolyState ps, int32_t* __restrict__ deferred,
                                               int64_t deferred_cap, int walk_cap, Counters* cnt) {
+  // (the two emission steps per triangle below rely on seed starts)
+  static_assert(FROM_SEEDS, "the walk starts from seed triangles");
   __shared__ int32_t buf[kWalkCap + 1][256];  // vertex ids of the cycle, per lane (+ a spare row)
   walk_cap = walk_cap < 1 ? 1 : (walk_cap > kWalkCap ? kWalkCap : walk_cap);
   const int lane = threadIdx.x & 63;
@@ -289,7 +291,23 @@ __global__ __launch_bounds__(256) void k_walk(const int32_t* __restrict__ list, 
       else if (r.w1 < 0) ci = 1;
       else if (r.w2 < 0) ci = 2;
       else ci = -1;
-      if (ci < 0) {
+      if (r.w0 < 0 && r.w1 < 0 && r.w2 < 0) {
+        // a region of one triangle: its three vertices are the whole cycle
+        s = 3 * t;
+        if (walk_cap < 3) {
+          result = kLarge;
+        } else {
+          const int32_t v0 = -1 - r.w0, v1 = -1 - r.w1, v2 = -1 - r.w2;
+          buf[0][threadIdx.x] = v0;
+          buf[1][threadIdx.x] = v1;
+          buf[2][threadIdx.x] = v2;
+          L = 3;
+          minpos = v1 < v0 ? (v2 < v1 ? 2 : 1) : (v2 < v0 ? 2 : 0);
+          minhe = s + minpos;
+          complex = v0 == v1 || v1 == v2 || v0 == v2;  // (not a triangulation)
+        }
+        done = true;
+      } else if (ci < 0) {
         const int32_t tw = r.w0;
         if ((uint32_t)tw >= (uint32_t)nhe) {
           result = kInvalid;
@@ -311,8 +329,8 @@ __global__ __launch_bounds__(256) void k_walk(const int32_t* __restrict__ list, 
       // vertices of the cycle), then the first internal one, which the lane
       // crosses (turning about the current vertex). Entered across an edge,
       // a triangle has at most two such frontier half-edges before that edge
-      // comes round again; the seed triangle of a region of one triangle has
-      // three, and the cycle closes at its start after them. Written as
+      // comes round again, and a seed triangle with three (a region of one
+      // triangle) was taken whole above, so two steps suffice. Written as
       // selects on per-lane predicates (the vertex store goes to a spare row
       // when the lane emits nothing), so the wave runs it without branches.
       const int p0 = ci, p1 = next_local(p0), p2 = next_local(p1);
@@ -320,9 +338,9 @@ __global__ __launch_bounds__(256) void k_walk(const int32_t* __restrict__ list, 
       const int32_t base = t + t + t;
       bool live = act;
 #pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        const int32_t wv = j == 0 ? wa : (j == 1 ? wb : wc);
-        const int32_t c = base + (j == 0 ? p0 : (j == 1 ? p1 : p2));
+      for (int j = 0; j < 2; ++j) {
+        const int32_t wv = j == 0 ? wa : wb;
+        const int32_t c = base + (j == 0 ? p0 : p1);
         const bool fr = live && wv < 0;
         const bool first = fr && s < 0;  // start found by turning about the seed's vertex 0
         const bool close = fr && !first && L > 0 && c == s;
@@ -345,11 +363,12 @@ __global__ __launch_bounds__(256) void k_walk(const int32_t* __restrict__ list, 
         result = over ? kLarge : result;
         live = emit;
       }
-      // three emitted: the next check is the start again (a one-triangle region)
-      done = done || live;
-      result = live && base + p0 != s ? kInvalid : result;
-      // the first internal half-edge, crossed
+      // the first internal half-edge, crossed (none after two frontier ones
+      // outside a seed triangle: not a triangulation)
       const int32_t wx = wa >= 0 ? wa : (wb >= 0 ? wb : wc);
+      const bool stuck = act && !done && wx < 0;
+      done = done || stuck;
+      result = stuck ? kInvalid : result;
       const bool cr = act && !done && wx >= 0;
       steps += cr ? 1 : 0;
       const bool bad = cr && ((uint32_t)wx >= (uint32_t)nhe || steps > nhe);

@@ -478,13 +478,13 @@ int run_build(polylla_ctx* c, const polylla_tri* t, const int32_t* list, bool fr
     return POLYLLA_EHIP;
   {
     Prof p(c, ss, KR_TIP);
-    const int gt = 2048;  // one lane per short polygon with a repeat, grid-stride
+    const int gt = 2048;  // two waves per 64 short polygons with a repeat, grid-stride
     if (repair)
-      hipLaunchKernelGGL(k_tip<true>, dim3(gt), dim3(64), 0, ss, nhe, t->n_vertices, t->twin, t->origin, c->sc->wk, he, vtx,
+      hipLaunchKernelGGL(k_tip<true>, dim3(gt), dim3(128), 0, ss, nhe, t->n_vertices, t->twin, t->origin, c->sc->wk, he, vtx,
                          c->sc->stage, c->sc->stage_cap, c->sc->arena, c->sc->arena_cap, ps, c->sc->deferred, c->sc->rest, c->sc->rest_cap,
                          c->cnt);
     else
-      hipLaunchKernelGGL(k_tip<false>, dim3(gt), dim3(64), 0, ss, nhe, t->n_vertices, t->twin, t->origin, c->sc->wk, he, vtx,
+      hipLaunchKernelGGL(k_tip<false>, dim3(gt), dim3(128), 0, ss, nhe, t->n_vertices, t->twin, t->origin, c->sc->wk, he, vtx,
                          c->sc->stage, c->sc->stage_cap, c->sc->arena, c->sc->arena_cap, ps, c->sc->deferred, c->sc->rest, c->sc->rest_cap,
                          c->cnt);
   }

@@ -1257,8 +1257,154 @@ __device__ int piece_rotation(const LdsCol& v, int L, int a, int len) {
   return best;
 }
 
+// The rest of the tip path for one queued polygon whose cycle (vertices v,
+// half-edges h) is in the lane's LDS columns; called by a whole wave (the
+// space reservations are wave-wide).
 template <bool REPAIR>
-__global__ __launch_bounds__(64) void k_tip(int32_t nhe, int64_t nv, const int32_t* __restrict__ twin,
+__device__ void tip_rest(bool ok, bool valid, int32_t i, int L, int32_t nhe, int64_t nv,
+                         const int32_t* __restrict__ twin, const int32_t* __restrict__ origin,
+                         uint8_t* __restrict__ he, uint8_t* __restrict__ vtx, int32_t* __restrict__ stage,
+                         int64_t stage_cap, int32_t* __restrict__ arena, int64_t arena_cap, PolyState ps,
+                         int32_t* __restrict__ rest, int64_t rest_cap, const LdsCol& v, const LdsCol& h,
+                         const LdsCol& f, uint32_t& n_rep, Counters* cnt) {
+  const int lane = threadIdx.x & 63;
+  int pairs = 0;
+  if (ok)
+    for (int a = 0; a < L; ++a)
+      for (int b = a + 1; b < L; ++b) pairs += v[a] == v[b] ? 1 : 0;
+  // no repeated vertex after all (the walk's filter flags a few such
+  // cycles): a complete polygon, staged like the walk stages one
+  const bool simple = ok && pairs == 0;
+  bool fast = ok && !simple && REPAIR && L >= 4;
+  int m = -1;
+  if (fast) {
+    int ntip = 0;
+    for (int k = 0; k < L; ++k) {
+      const int32_t vp = v[k == 0 ? L - 1 : k - 1], vn = v[k + 1 == L ? 0 : k + 1];
+      if (vp == vn) {
+        ++ntip;
+        m = k;
+      }
+    }
+    fast = ntip == 1;
+    if (fast) {
+      // The cycle may repeat vertices only along the slit ending at the tip
+      // (v[m-k-1] == v[m+k+1], k < K): then the slit's K edges are all its
+      // barrier edges. Any other repeated vertex (a lobe hanging off a
+      // barrier edge, a region touching itself) goes to the region path.
+      int K = 0;
+      while (2 * K + 2 < L && v[(m - K - 1 + L) % L] == v[(m + K + 1) % L]) ++K;
+      fast = pairs == K;
+    }
+  }
+  int32_t e = -1, te = -1, x = -1;
+  int q = -1;
+  if (fast) {
+    // middle internal edge c_{floor(d/2)} turning clockwise about v[m] from
+    // c0 = h[m] (c_{j+1} = next(twin(c_j))): twin(c0) is h[m-1], so c1 is
+    // next(h[m-1]), and the d - 1 internal edges of the fan are the ones the
+    // walk crossed about v[m] (f[m])
+    const int32_t d = f[m] + 1;
+    fast = d >= 2;
+    if (fast) {
+      e = he_next(h[m == 0 ? L - 1 : m - 1]);
+      for (int32_t k = 1; k < d / 2; ++k) {
+        const int32_t tw = twin[e];
+        if ((uint32_t)tw >= (uint32_t)nhe) {
+          fast = false;
+          break;
+        }
+        e = he_next(tw);
+      }
+    }
+    if (fast) {
+      te = twin[e];
+      x = origin[he_next(e)];
+      int occ = 0;
+      for (int k = 0; k < L; ++k)
+        if (v[k] == x) {
+          ++occ;
+          q = k;
+        }
+      fast = occ == 1 && q != m && (uint32_t)te < (uint32_t)nhe;
+    }
+  }
+  // space for the whole wave: staging words, arena words, declined entries
+  const bool declined = valid && !simple && !fast;
+  const uint32_t ns = simple ? (uint32_t)L : (fast ? (uint32_t)(L + 2) : 0u);
+  const uint32_t na = fast ? 8u : 0u;
+  const uint32_t is = wave_incl_sum(ns), ia = wave_incl_sum(na);
+  const uint64_t md = __ballot(declined);
+  const uint32_t ts = (uint32_t)__builtin_amdgcn_readlane((int32_t)is, 63);
+  const uint32_t ta = (uint32_t)__builtin_amdgcn_readlane((int32_t)ia, 63);
+  uint32_t bs = 0, ba = 0, bd = 0;
+  if (lane == 0) {
+    if (ts) bs = atomicAdd(&cnt->stage_top, ts);
+    if (ta) ba = atomicAdd(&cnt->arena_top, ta);
+    if (md) bd = atomicAdd(&cnt->n_gen, (uint32_t)__popcll(md));
+  }
+  bs = __shfl(bs, 0, 64);
+  ba = __shfl(ba, 0, 64);
+  bd = __shfl(bd, 0, 64);
+  const int64_t off = (int64_t)bs + is - ns, r0 = (int64_t)ba + ia - na;
+  if (declined) {
+    const uint32_t r = bd + (uint32_t)__popcll(md & ((1ull << lane) - 1ull));
+    if ((int64_t)r < rest_cap) rest[r] = i;
+    else set_error(cnt, POLYLLA_EINTERNAL);
+  }
+  if ((simple || fast) && (off + ns > stage_cap || r0 + na > arena_cap)) {
+    set_error(cnt, POLYLLA_ENOMEM);
+    ps.clear(i);
+    return;
+  }
+  if (simple) {
+    int mp = 0;
+    for (int k = 1; k < L; ++k)
+      if (v[k] < v[mp]) mp = k;
+    for (int k = 0; k < L; ++k) stage[off + k] = v[k];
+    ps.set(i, L, 1 | (mp << kRotShift), h[mp], (int32_t)off);
+  }
+  if (!fast) return;
+  // labels: barrier edges, the tip, the opened edge. The barrier edges of a
+  // region form a forest inside it whose leaves are tips, so with one tip
+  // they are the path v[m-k-1] = v[m+k+1] read outwards from the tip.
+  for (int k = 0; 2 * k + 2 < L; ++k) {
+    const int lo = (m - k - 1 + L) % L, hi = (m + k + 1) % L;
+    if (v[lo] != v[hi]) break;
+    or_bits(he, h[lo], kBarrier);             // v[lo] -> v[lo + 1]
+    or_bits(he, h[(m + k) % L], kBarrier);    // v[m + k] -> v[hi]
+  }
+  const int32_t vt = v[m];
+  if ((uint64_t)(uint32_t)vt < (uint64_t)nv) or_bits(vtx, vt, kTip);
+  or_bits(he, e, kFrontier | kRepaired);
+  or_bits(he, te, kFrontier | kRepaired);
+  ++n_rep;
+  // pieces: A = positions m..q (x last, leaving by te), B = q..m (v[m] last, leaving by e)
+  const int lenA = (q - m + L) % L + 1, lenB = (m - q + L) % L + 1;
+  const int ra = piece_rotation(v, L, m, lenA), rb = piece_rotation(v, L, q, lenB);
+  const int32_t a0 = piece_vertex(v, L, m, ra), a1 = piece_vertex(v, L, m, (ra + 1) % lenA);
+  const int32_t b0 = piece_vertex(v, L, q, rb), b1 = piece_vertex(v, L, q, (rb + 1) % lenB);
+  const int32_t sa = ra == lenA - 1 ? te : h[(m + ra) % L];
+  const int32_t sb = rb == lenB - 1 ? e : h[(q + rb) % L];
+  const bool a_first = a0 < b0 || (a0 == b0 && a1 < b1);
+  const int oa = a_first ? 0 : lenB, ob = a_first ? lenA : 0;
+  for (int k = 0; k < lenA; ++k) stage[off + oa + k] = piece_vertex(v, L, m, (ra + k) % lenA);
+  for (int k = 0; k < lenB; ++k) stage[off + ob + k] = piece_vertex(v, L, q, (rb + k) % lenB);
+  const int pa = a_first ? 0 : 1, pb = 1 - pa;
+  arena[r0 + 4 * pa] = a0;
+  arena[r0 + 4 * pa + 1] = a1;
+  arena[r0 + 4 * pa + 2] = sa;
+  arena[r0 + 4 * pa + 3] = lenA;
+  arena[r0 + 4 * pb] = b0;
+  arena[r0 + 4 * pb + 1] = b1;
+  arena[r0 + 4 * pb + 2] = sb;
+  arena[r0 + 4 * pb + 3] = lenB;
+  ps.set(i, L + 2, 2, -1, (int32_t)off);
+  ps.prec[i] = (int32_t)r0;
+}
+
+template <bool REPAIR>
+__global__ __launch_bounds__(128) void k_tip(int32_t nhe, int64_t nv, const int32_t* __restrict__ twin,
                                             const int32_t* __restrict__ origin, const int32_t* __restrict__ wk,
                                             uint8_t* __restrict__ he,
                                             uint8_t* __restrict__ vtx, int32_t* __restrict__ stage,
@@ -1268,13 +1414,24 @@ __global__ __launch_bounds__(64) void k_tip(int32_t nhe, int64_t nv, const int32
   __shared__ int32_t s_v[kWalkCap * 64];
   __shared__ int32_t s_h[kWalkCap * 64];
   __shared__ int32_t s_f[kWalkCap * 64];
-  const int lane = threadIdx.x;
+  __shared__ uint8_t s_bok[64];
+  // Two waves per 64 queued polygons: wave 0 walks each cycle forwards from
+  // its start half-edge over its first half, wave 1 backwards from the start
+  // over its second half (turning the other way about each vertex: the
+  // previous frontier half-edge is the first frontier one met going to
+  // prev(h) and across internal edges), so the chain of dependent loads is
+  // half as long. Both count the internal edges crossed about each vertex
+  // (f[k]: about v[k], between h[k-1] and h[k]). Wave 0 also takes the step
+  // into the second half and checks that it meets wave 1 there, then does
+  // the rest alone.
+  const int lane = threadIdx.x & 63;
+  const bool back = threadIdx.x >= 64;
   const LdsCol v{s_v + lane}, h{s_h + lane}, f{s_f + lane};
   const uint32_t nd = cnt->n_deferred;
   uint32_t n_rep = 0;  // tips repaired by this lane
-  // the wave takes 64 queued polygons at a time (the loop is wave-uniform, so
-  // the staging, arena and queue space of all 64 is reserved with one counter
-  // update each)
+  // the block takes 64 queued polygons at a time (the loop is block-uniform,
+  // and wave 0 reserves the staging, arena and queue space of all 64 with one
+  // counter update each)
   for (uint32_t j0 = blockIdx.x * 64; j0 < nd; j0 += gridDim.x * 64) {
     const uint32_t j = j0 + lane;
     const bool valid = j < nd;
@@ -1282,15 +1439,21 @@ __global__ __launch_bounds__(64) void k_tip(int32_t nhe, int64_t nv, const int32
     const int4 rc = valid ? ps.rec[i] : make_int4(0, 0, -1, 0);
     const int L = rc.x;
     bool ok = valid && rc.y == 0 && L >= 3 && L <= kWalkCap && (uint32_t)rc.z < (uint32_t)nhe;
-    if (ok) {
-      // the cycle again from its start half-edge over the walk words (which
-      // the repair does not change): its frontier half-edges and vertices
+    const int half = (L + 1) >> 1;  // wave 0: positions [0, half); wave 1: [half, L)
+    int32_t hm = -1;                 // wave 0: its half-edge at position half
+    if (ok && !back) {
+      // the first half again over the walk words (which the repair does not
+      // change): frontier half-edges and their vertices
       const int32_t s0 = rc.z;
       int32_t c = s0, w = wk[s0];
       int k = 0;
       while (ok) {
-        if (w >= 0 || k == L) {
+        if (w >= 0) {
           ok = false;
+          break;
+        }
+        if (k == half) {
+          hm = c;
           break;
         }
         v[k] = -1 - w;
@@ -1307,148 +1470,42 @@ __global__ __launch_bounds__(64) void k_tip(int32_t nhe, int64_t nv, const int32
           }
           x = he_next(w);
         }
+        f[k] = steps;
         c = x;
-        if (c == s0) break;
-      }
-      ok = ok && k == L;
-    }
-    int pairs = 0;
-    if (ok)
-      for (int a = 0; a < L; ++a)
-        for (int b = a + 1; b < L; ++b) pairs += v[a] == v[b] ? 1 : 0;
-    // no repeated vertex after all (the walk's filter flags a few such
-    // cycles): a complete polygon, staged like the walk stages one
-    const bool simple = ok && pairs == 0;
-    bool fast = ok && !simple && REPAIR && L >= 4;
-    int m = -1;
-    if (fast) {
-      int ntip = 0;
-      for (int k = 0; k < L; ++k) {
-        const int32_t vp = v[k == 0 ? L - 1 : k - 1], vn = v[k + 1 == L ? 0 : k + 1];
-        if (vp == vn) {
-          ++ntip;
-          m = k;
-        }
-      }
-      fast = ntip == 1;
-      if (fast) {
-        // The cycle may repeat vertices only along the slit ending at the tip
-        // (v[m-k-1] == v[m+k+1], k < K): then the slit's K edges are all its
-        // barrier edges. Any other repeated vertex (a lobe hanging off a
-        // barrier edge, a region touching itself) goes to the region path.
-        int K = 0;
-        while (2 * K + 2 < L && v[(m - K - 1 + L) % L] == v[(m + K + 1) % L]) ++K;
-        fast = pairs == K;
+        if (c == s0) ok = false;  // closed too early
       }
     }
-    int32_t e = -1, te = -1, x = -1;
-    int q = -1;
-    if (fast) {
-      // middle internal edge c_{floor(d/2)} turning clockwise about v[m] from c0 = h[m]
-      // (the fan's half-edges are kept, so the middle one needs no second walk)
-      const int32_t c0 = h[m];
-      int32_t d = 0, c = c0;
-      do {
-        if (d < kWalkCap) f[d] = c;
-        const int32_t tw = twin[c];
-        if ((uint32_t)tw >= (uint32_t)nhe) {
-          d = -1;
-          break;
-        }
-        c = he_next(tw);
-        ++d;
-      } while (c != c0 && d <= nhe);
-      fast = d >= 2 && c == c0;
-      if (fast) {
-        if (d / 2 < kWalkCap) {
-          e = f[d / 2];
-        } else {
-          e = c0;
-          for (int32_t k = 0; k < d / 2; ++k) e = he_next(twin[e]);
-        }
-        te = twin[e];
-        x = origin[he_next(e)];
-        int occ = 0;
-        for (int k = 0; k < L; ++k)
-          if (v[k] == x) {
-            ++occ;
-            q = k;
+    if (ok && back) {
+      const int32_t s0 = rc.z;
+      int32_t c = s0;
+      for (int k = L - 1; ok && k >= half; --k) {
+        // previous frontier half-edge: turn the other way about the origin of c
+        int32_t x = he_next(he_next(c)), steps = 0, w;
+        for (;;) {
+          w = wk[x];
+          if (w < 0) break;
+          if ((uint32_t)w >= (uint32_t)nhe || ++steps > kWalkCap * 3) {
+            ok = false;
+            break;
           }
-        fast = occ == 1 && q != m && (uint32_t)te < (uint32_t)nhe;
+          x = he_next(he_next(w));
+        }
+        f[k + 1 == L ? 0 : k + 1] = steps;
+        c = x;
+        if (c == s0) ok = false;  // closed too early
+        v[k] = -1 - w;
+        h[k] = c;
       }
     }
-    // space for the whole wave: staging words, arena words, declined entries
-    const bool declined = valid && !simple && !fast;
-    const uint32_t ns = simple ? (uint32_t)L : (fast ? (uint32_t)(L + 2) : 0u);
-    const uint32_t na = fast ? 8u : 0u;
-    const uint32_t is = wave_incl_sum(ns), ia = wave_incl_sum(na);
-    const uint64_t md = __ballot(declined);
-    const uint32_t ts = (uint32_t)__builtin_amdgcn_readlane((int32_t)is, 63);
-    const uint32_t ta = (uint32_t)__builtin_amdgcn_readlane((int32_t)ia, 63);
-    uint32_t bs = 0, ba = 0, bd = 0;
-    if (lane == 0) {
-      if (ts) bs = atomicAdd(&cnt->stage_top, ts);
-      if (ta) ba = atomicAdd(&cnt->arena_top, ta);
-      if (md) bd = atomicAdd(&cnt->n_gen, (uint32_t)__popcll(md));
+    if (back) s_bok[lane] = ok ? 1 : 0;
+    __syncthreads();
+    if (!back) {
+      // the halves meet
+      ok = ok && s_bok[lane] != 0 && hm == h[half];
+      tip_rest<REPAIR>(ok, valid, i, L, nhe, nv, twin, origin, he, vtx, stage, stage_cap, arena, arena_cap, ps,
+                       rest, rest_cap, v, h, f, n_rep, cnt);
     }
-    bs = __shfl(bs, 0, 64);
-    ba = __shfl(ba, 0, 64);
-    bd = __shfl(bd, 0, 64);
-    const int64_t off = (int64_t)bs + is - ns, r0 = (int64_t)ba + ia - na;
-    if (declined) {
-      const uint32_t r = bd + (uint32_t)__popcll(md & ((1ull << lane) - 1ull));
-      if ((int64_t)r < rest_cap) rest[r] = i;
-      else set_error(cnt, POLYLLA_EINTERNAL);
-    }
-    if ((simple || fast) && (off + ns > stage_cap || r0 + na > arena_cap)) {
-      set_error(cnt, POLYLLA_ENOMEM);
-      ps.clear(i);
-      continue;
-    }
-    if (simple) {
-      int mp = 0;
-      for (int k = 1; k < L; ++k)
-        if (v[k] < v[mp]) mp = k;
-      for (int k = 0; k < L; ++k) stage[off + k] = v[k];
-      ps.set(i, L, 1 | (mp << kRotShift), h[mp], (int32_t)off);
-    }
-    if (!fast) continue;
-    // labels: barrier edges, the tip, the opened edge. The barrier edges of a
-    // region form a forest inside it whose leaves are tips, so with one tip
-    // they are the path v[m-k-1] = v[m+k+1] read outwards from the tip.
-    for (int k = 0; 2 * k + 2 < L; ++k) {
-      const int lo = (m - k - 1 + L) % L, hi = (m + k + 1) % L;
-      if (v[lo] != v[hi]) break;
-      or_bits(he, h[lo], kBarrier);             // v[lo] -> v[lo + 1]
-      or_bits(he, h[(m + k) % L], kBarrier);    // v[m + k] -> v[hi]
-    }
-    const int32_t vt = v[m];
-    if ((uint64_t)(uint32_t)vt < (uint64_t)nv) or_bits(vtx, vt, kTip);
-    or_bits(he, e, kFrontier | kRepaired);
-    or_bits(he, te, kFrontier | kRepaired);
-    ++n_rep;
-    // pieces: A = positions m..q (x last, leaving by te), B = q..m (v[m] last, leaving by e)
-    const int lenA = (q - m + L) % L + 1, lenB = (m - q + L) % L + 1;
-    const int ra = piece_rotation(v, L, m, lenA), rb = piece_rotation(v, L, q, lenB);
-    const int32_t a0 = piece_vertex(v, L, m, ra), a1 = piece_vertex(v, L, m, (ra + 1) % lenA);
-    const int32_t b0 = piece_vertex(v, L, q, rb), b1 = piece_vertex(v, L, q, (rb + 1) % lenB);
-    const int32_t sa = ra == lenA - 1 ? te : h[(m + ra) % L];
-    const int32_t sb = rb == lenB - 1 ? e : h[(q + rb) % L];
-    const bool a_first = a0 < b0 || (a0 == b0 && a1 < b1);
-    const int oa = a_first ? 0 : lenB, ob = a_first ? lenA : 0;
-    for (int k = 0; k < lenA; ++k) stage[off + oa + k] = piece_vertex(v, L, m, (ra + k) % lenA);
-    for (int k = 0; k < lenB; ++k) stage[off + ob + k] = piece_vertex(v, L, q, (rb + k) % lenB);
-    const int pa = a_first ? 0 : 1, pb = 1 - pa;
-    arena[r0 + 4 * pa] = a0;
-    arena[r0 + 4 * pa + 1] = a1;
-    arena[r0 + 4 * pa + 2] = sa;
-    arena[r0 + 4 * pa + 3] = lenA;
-    arena[r0 + 4 * pb] = b0;
-    arena[r0 + 4 * pb + 1] = b1;
-    arena[r0 + 4 * pb + 2] = sb;
-    arena[r0 + 4 * pb + 3] = lenB;
-    ps.set(i, L + 2, 2, -1, (int32_t)off);
-    ps.prec[i] = (int32_t)r0;
+    __syncthreads();  // (the columns are reused)
   }
   // repair counts: one update per wave
   const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int32_t)wave_incl_sum(n_rep), 63);

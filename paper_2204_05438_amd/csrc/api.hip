@@ -122,6 +122,7 @@ struct Scratch {
   int64_t arena_cap = 0;
   uint64_t* status = nullptr;
   int64_t n_status = 0;
+  int64_t n_status_label = 0;  // the label tiles' part; the emitter's follows
   uint8_t* he_s = nullptr;
   uint8_t* tri_s = nullptr;
   uint8_t* vtx_s = nullptr;
@@ -176,7 +177,7 @@ namespace {
 constexpr int64_t kGenGridMax = 18000;  // 6 g^2 half-edge ids stay below 2^31
 constexpr int64_t kTile = 2048;  // triangles per tile of k_label
 constexpr size_t kMaxProfiled = 8192;
-constexpr int64_t kScanTileHost = 2048;   // polygons per tile of k_scan_emit
+constexpr int64_t kScanTileHost = 1024;   // polygons per tile of k_scan_emit
 constexpr int64_t kWalkBlocks = 2048;     // persistent grid of k_walk
 constexpr int64_t kStageChunkHost = 4096; // staging ints a walk wave reserves at a time
 
@@ -265,7 +266,8 @@ size_t carve(Scratch& S, uint8_t* base, int64_t T, int64_t V, int walk_grid, int
   // polygon vertices (<= 3T) and the general paths' staging, plus chunk tails
   S.stage_cap = std::min<int64_t>(5 * T + stage_tails(walk_grid, g64, g1024), ((int64_t)1 << 31) - 1);
   S.arena_cap = std::min<int64_t>(6 * T + arena_tails(g64, g1024), ((int64_t)1 << 31) - 1);
-  S.n_status = 2 * ntiles;
+  S.n_status_label = ntiles;
+  S.n_status = ntiles + (T + kScanTileHost - 1) / kScanTileHost + 1;
   S.huge_cap = 3 * T / 32 + 64;
   S.lane_cap = 3 * T / 32 + 64;
   S.over_cap = T / 32 + 64;
@@ -556,7 +558,7 @@ int run_build(polylla_ctx* c, const polylla_tri* t, const int32_t* list, bool fr
   {
     Prof p(c, s, KR_SCAN);
     const int64_t ntiles = (T + kScanTileHost - 1) / kScanTileHost + 1;
-    hipLaunchKernelGGL(k_scan_emit, dim3(ntiles), dim3(256), 0, s, ps, c->sc->status + c->sc->n_status / 2, c->sc->stage,
+    hipLaunchKernelGGL(k_scan_emit, dim3(ntiles), dim3(256), 0, s, ps, c->sc->status + c->sc->n_status_label, c->sc->stage,
                        c->sc->arena, out->offsets, out->verts, out->start, out->counts, out->cap_polys,
                        out->cap_verts, c->cnt);
   }

@@ -2866,9 +2866,9 @@ __global__ __launch_bounds__(1024) void k_general_huge(
 // vertex range of the whole tile with all threads, each output slot finding
 // its polygon by binary search in LDS so that the stores are coalesced.
 // Blocks beyond the tile count exit before taking a ticket.
-constexpr int kScanItems = 8;
+constexpr int kScanItems = 4;
 constexpr int kScanTile = 256 * kScanItems;
-constexpr int kScanLog = 11;            // log2(kScanTile)
+constexpr int kScanLog = 10;            // log2(kScanTile)
 constexpr int kScanOut = kScanTile + 512;  // output polygons of a tile staged in LDS (else direct stores)
 static_assert((1 << kScanLog) == kScanTile, "binary search depth");
 

@@ -11,10 +11,11 @@
 //                   with the slot of its smallest vertex; the cycles it flags
 //                   (every one with a tip or another repeated vertex) are
 //                   queued for the tip path, longer ones for the region path.
-// k_tip           : one lane per flagged short polygon, 64 per wave: walks
-//                   the cycle again from its start half-edge, stages it if it
-//                   has no repeated vertex after all, repairs a single tip,
-//                   and leaves other cases to the region path.
+// k_tip           : 64 flagged short polygons per workgroup of two waves:
+//                   walks each cycle again from its start half-edge (one
+//                   wave forwards, one backwards, half the cycle each),
+//                   stages it if it has no repeated vertex after all, repairs
+//                   a single tip, and leaves other cases to the region path.
 // k_general_big   : the region path: a breadth-first search gathers the
 //                   region into LDS as links between local edges, then
 //                   barrier marking, tips, the repair and the pieces run

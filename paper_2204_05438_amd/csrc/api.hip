@@ -39,6 +39,10 @@ __global__ void k_general_small(const int32_t*, bool, int32_t, int64_t, const in
 template <bool REPAIR>
 __global__ void k_tip(int32_t, int64_t, const int32_t*, const int32_t*, const int32_t*, uint8_t*, uint8_t*, int32_t*, int64_t,
                       int32_t*, int64_t, PolyState, const int32_t*, int32_t*, int64_t, Counters*);
+template <bool REPAIR>
+__global__ void k_tip_long(int32_t, int64_t, const int32_t*, const int32_t*, const int32_t*, uint8_t*, uint8_t*,
+                           int32_t*, int64_t, int32_t*, int64_t, PolyState, const int32_t*, int64_t, const uint32_t*,
+                           uint32_t, int32_t*, int64_t, uint32_t*, Counters*);
 template <bool REPAIR, int NT, int KC, int LC, int HB>
 __global__ void k_general_big(const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*, const int32_t*,
                               uint8_t*, uint8_t*, int32_t*, int64_t, int32_t*, int64_t, PolyState, const int32_t*,
@@ -115,6 +119,8 @@ struct Scratch {
   int64_t mem_km = 0;            // triangles of capacity of one store
   int32_t* rest = nullptr;  // short polygons the tip path leaves to the region path
   int64_t rest_cap = 0;
+  int32_t* lrest = nullptr;  // long cycles the long-cycle tip path leaves to the region path
+  int64_t lrest_cap = 0;
   int32_t* poly_arrays = nullptr;  // per-polygon records: 4 ints + 1 int per polygon (PolyState)
   int32_t* stage = nullptr;
   int64_t stage_cap = 0;
@@ -183,13 +189,14 @@ constexpr int64_t kStageChunkHost = 4096; // staging ints a walk wave reserves a
 
 enum KernelId {
   KR_RESET, KR_LONGEST, KR_LABEL, KR_COMPACT, KR_PACK, KR_WALK, KR_GENERAL, KR_BIG, KR_HUGE, KR_SCAN, KR_VALIDATE,
-  KR_BATCH, KR_BIGW, KR_TIP, KR_SEEDS, KR_GENW, KR_GREBASE, KR_GFINISH, KR_LEPP, KR_PREP, KR_N
+  KR_BATCH, KR_BIGW, KR_TIP, KR_SEEDS, KR_GENW, KR_GREBASE, KR_GFINISH, KR_LEPP, KR_PREP, KR_TIPL, KR_N
 };
 const char* kKernelNames[KR_N] = {"k_reset",         "k_longest",       "k_label",          "k_compact_seeds",
                                   "k_pack_walk",     "k_walk",          "k_general_small",  "k_general_big",
                                   "k_general_huge",  "k_scan_emit",     "k_validate",       "k_batch_offsets",
                                   "k_general_big_wg", "k_tip",           "k_seeds",          "k_general_wave",
-                                  "k_group_rebase",  "k_group_finish",  "k_lepp",           "k_repair_prep"};
+                                  "k_group_rebase",  "k_group_finish",  "k_lepp",           "k_repair_prep",
+                                  "k_tip_long"};
 
 // Event pair around one kernel launch when profiling is on.
 struct Prof {
@@ -272,6 +279,7 @@ size_t carve(Scratch& S, uint8_t* base, int64_t T, int64_t V, int walk_grid, int
   S.lane_cap = 3 * T / 32 + 64;
   S.over_cap = T / 32 + 64;
   S.rest_cap = T / 3 + 64;
+  S.lrest_cap = T / 8 + 64;  // cycles of more than 24 frontier half-edges: under 3T / 25
   S.mem_km = std::min<int64_t>(T, mem_km_max);
   take(S.status, S.n_status);
   take(S.lg, T);
@@ -283,6 +291,7 @@ size_t carve(Scratch& S, uint8_t* base, int64_t T, int64_t V, int walk_grid, int
   take(S.mem_store, kMemGrid * mem_words(S.mem_km));
   take(S.over, S.over_cap);
   take(S.rest, S.rest_cap);
+  take(S.lrest, S.lrest_cap);
   take(S.poly_arrays, 5 * T);
   take(S.stage, S.stage_cap);
   take(S.arena, S.arena_cap);
@@ -457,10 +466,25 @@ int run_build(polylla_ctx* c, const polylla_tri* t, const int32_t* list, bool fr
   // workgroups are dispatched before the tip path's blocks spread over every
   // compute unit.
   hipStream_t sl = s, ss = c->side;
-  // long regions: one wave per region first (regions of up to 128 triangles
-  // and frontier half-edges), then 1024 threads per region for the rest; when
-  // there are at most `few` of them, all go to the 1024-thread instance
+  // long regions: the long-cycle tip path first (cycles of up to 32 frontier
+  // half-edges with no repeated vertex or one tip), one wave per region next
+  // (regions of up to 128 triangles and frontier half-edges), then 1024
+  // threads per region for the rest; when there are at most `few` of them,
+  // all go to the 1024-thread instance
   const uint32_t few = 128;
+  {
+    Prof p(c, sl, KR_TIPL);
+    Counters* k = c->cnt;
+    const int gl = 1536;  // (six workgroups of 24 KB of LDS per compute unit), grid-stride
+    if (repair)
+      hipLaunchKernelGGL(k_tip_long<true>, dim3(gl), dim3(64), 0, sl, nhe, t->n_vertices, t->twin, t->origin, c->sc->wk,
+                         he, vtx, c->sc->stage, c->sc->stage_cap, c->sc->arena, c->sc->arena_cap, ps, c->sc->deferred,
+                         c->sc->cap_t, &k->n_big, few, c->sc->lrest, c->sc->lrest_cap, &k->n_lrest, k);
+    else
+      hipLaunchKernelGGL(k_tip_long<false>, dim3(gl), dim3(64), 0, sl, nhe, t->n_vertices, t->twin, t->origin, c->sc->wk,
+                         he, vtx, c->sc->stage, c->sc->stage_cap, c->sc->arena, c->sc->arena_cap, ps, c->sc->deferred,
+                         c->sc->cap_t, &k->n_big, few, c->sc->lrest, c->sc->lrest_cap, &k->n_lrest, k);
+  }
   {
     Prof p(c, sl, KR_BIG);
     Counters* k = c->cnt;
@@ -468,12 +492,12 @@ int run_build(polylla_ctx* c, const polylla_tri* t, const int32_t* list, bool fr
     if (repair)
       hipLaunchKernelGGL((k_general_big<true, 64, 128, 128, 8>), dim3(gm), dim3(64), 0, sl, list, from_seeds, nhe,
                          t->n_vertices, t->twin, t->origin, c->sc->wk, he, vtx, c->sc->stage, c->sc->stage_cap, c->sc->arena,
-                         c->sc->arena_cap, ps, c->sc->deferred, true, c->sc->cap_t, &k->n_big, &k->big_ticket, c->sc->over,
+                         c->sc->arena_cap, ps, c->sc->lrest, false, c->sc->lrest_cap, &k->n_lrest, &k->big_ticket, c->sc->over,
                          c->sc->over_cap, &k->n_over, nullptr, (int64_t)0, &k->n_big, few, UINT32_MAX, 128, k);
     else
       hipLaunchKernelGGL((k_general_big<false, 64, 128, 128, 8>), dim3(gm), dim3(64), 0, sl, list, from_seeds,
                          nhe, t->n_vertices, t->twin, t->origin, c->sc->wk, he, vtx, c->sc->stage, c->sc->stage_cap, c->sc->arena,
-                         c->sc->arena_cap, ps, c->sc->deferred, true, c->sc->cap_t, &k->n_big, &k->big_ticket, c->sc->over,
+                         c->sc->arena_cap, ps, c->sc->lrest, false, c->sc->lrest_cap, &k->n_lrest, &k->big_ticket, c->sc->over,
                          c->sc->over_cap, &k->n_over, nullptr, (int64_t)0, &k->n_big, few, UINT32_MAX, 128, k);
   }
   if (hipEventRecord(c->fork, s) != hipSuccess || hipStreamWaitEvent(c->side, c->fork, 0) != hipSuccess)

@@ -390,6 +390,7 @@ __global__ __launch_bounds__(256) void k_walk(const int32_t* __restrict__ list, 
     if (fin && result == kSimple && complex) result = kSmall;
     const bool fin_simple = fin && result == kSimple;
     if (fin && result == kSmall) ps.set(idx, L, 0, s, -1);  // the tip path walks it again from s
+    if (fin && result == kLarge) ps.set(idx, 0, 0, s, -1);  // (and the long-cycle tip path)
     if (__ballot(fin_simple)) {
       const uint32_t need = fin_simple ? (uint32_t)L : 0u;
       const uint32_t incl = wave_incl_sum(need);
@@ -1266,8 +1267,8 @@ __device__ void tip_rest(bool ok, bool valid, int32_t i, int L, int32_t nhe, int
                          const int32_t* __restrict__ twin, const int32_t* __restrict__ origin,
                          uint8_t* __restrict__ he, uint8_t* __restrict__ vtx, int32_t* __restrict__ stage,
                          int64_t stage_cap, int32_t* __restrict__ arena, int64_t arena_cap, PolyState ps,
-                         int32_t* __restrict__ rest, int64_t rest_cap, const LdsCol& v, const LdsCol& h,
-                         const LdsCol& f, uint32_t& n_rep, Counters* cnt) {
+                         int32_t* __restrict__ rest, int64_t rest_cap, uint32_t* rest_count, const LdsCol& v,
+                         const LdsCol& h, const LdsCol& f, uint32_t& n_rep, Counters* cnt) {
   const int lane = threadIdx.x & 63;
   int pairs = 0;
   if (ok)
@@ -1342,7 +1343,7 @@ __device__ void tip_rest(bool ok, bool valid, int32_t i, int L, int32_t nhe, int
   if (lane == 0) {
     if (ts) bs = atomicAdd(&cnt->stage_top, ts);
     if (ta) ba = atomicAdd(&cnt->arena_top, ta);
-    if (md) bd = atomicAdd(&cnt->n_gen, (uint32_t)__popcll(md));
+    if (md) bd = atomicAdd(rest_count, (uint32_t)__popcll(md));
   }
   bs = __shfl(bs, 0, 64);
   ba = __shfl(ba, 0, 64);
@@ -1504,9 +1505,92 @@ __global__ __launch_bounds__(128) void k_tip(int32_t nhe, int64_t nv, const int3
       // the halves meet
       ok = ok && s_bok[lane] != 0 && hm == h[half];
       tip_rest<REPAIR>(ok, valid, i, L, nhe, nv, twin, origin, he, vtx, stage, stage_cap, arena, arena_cap, ps,
-                       rest, rest_cap, v, h, f, n_rep, cnt);
+                       rest, rest_cap, &cnt->n_gen, v, h, f, n_rep, cnt);
     }
     __syncthreads();  // (the columns are reused)
+  }
+  // repair counts: one update per wave
+  const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int32_t)wave_incl_sum(n_rep), 63);
+  if (lane == 0 && tot) {
+    atomicAdd(&cnt->n_tips, tot);
+    atomicAdd(&cnt->n_splits, tot);
+  }
+}
+
+// Long-cycle tip path: the cycles the walk gave up on (longer than its cap,
+// listed from the back of `in`), one lane each, 64 per wave, walked again
+// from their start half-edges up to kLongCap frontier half-edges. A cycle
+// that closes within that is finished as the tip path finishes a short one
+// (staged, or repaired at its one tip); the others (longer, several tips,
+// other repeated vertices) are listed in `rest` for the region kernels. With
+// at most few_max such cycles in all it does nothing: the 1024-thread region
+// kernel then takes them all from the walk's list.
+constexpr int kLongCap = 32;
+template <bool REPAIR>
+__global__ __launch_bounds__(64) void k_tip_long(int32_t nhe, int64_t nv, const int32_t* __restrict__ twin,
+                                                 const int32_t* __restrict__ origin, const int32_t* __restrict__ wk,
+                                                 uint8_t* __restrict__ he, uint8_t* __restrict__ vtx,
+                                                 int32_t* __restrict__ stage, int64_t stage_cap,
+                                                 int32_t* __restrict__ arena, int64_t arena_cap, PolyState ps,
+                                                 const int32_t* __restrict__ in, int64_t in_cap,
+                                                 const uint32_t* in_count, uint32_t few_max,
+                                                 int32_t* __restrict__ rest, int64_t rest_cap, uint32_t* rest_count,
+                                                 Counters* cnt) {
+  __shared__ int32_t s_v[kLongCap * 64];
+  __shared__ int32_t s_h[kLongCap * 64];
+  __shared__ int32_t s_f[kLongCap * 64];
+  const int lane = threadIdx.x;
+  const LdsCol v{s_v + lane}, h{s_h + lane}, f{s_f + lane};
+  const uint32_t n = (uint32_t)min((int64_t)*in_count, in_cap);
+  if (n <= few_max) return;
+  uint32_t n_rep = 0;
+  for (uint32_t j0 = blockIdx.x * 64; j0 < n; j0 += gridDim.x * 64) {
+    const uint32_t j = j0 + lane;
+    const bool valid = j < n;
+    const int32_t i = valid ? in[in_cap - 1 - j] : 0;
+    const int4 rc = valid ? ps.rec[i] : make_int4(0, 0, -1, 0);
+    bool ok = valid && (uint32_t)rc.z < (uint32_t)nhe;
+    int L = 0;
+    if (ok) {
+      // the cycle from its start half-edge over the walk words: frontier
+      // half-edges, their vertices, and the internal edges crossed about
+      // each vertex (f[k]: about v[k], between h[k-1] and h[k])
+      const int32_t s0 = rc.z;
+      int32_t c = s0, w = wk[s0];
+      for (;;) {
+        if (w >= 0) {
+          ok = false;
+          break;
+        }
+        v[L] = -1 - w;
+        h[L] = c;
+        ++L;
+        int32_t x = he_next(c), steps = 0;
+        for (;;) {
+          w = wk[x];
+          if (w < 0) break;
+          if ((uint32_t)w >= (uint32_t)nhe || ++steps > kLongCap * 3) {
+            ok = false;
+            break;
+          }
+          x = he_next(w);
+        }
+        if (!ok) break;
+        c = x;
+        if (c == s0) {
+          f[0] = steps;
+          break;
+        }
+        if (L == kLongCap) {  // longer: the region kernels
+          ok = false;
+          break;
+        }
+        f[L] = steps;
+      }
+      ok = ok && L >= 3;
+    }
+    tip_rest<REPAIR>(ok, valid, i, L, nhe, nv, twin, origin, he, vtx, stage, stage_cap, arena, arena_cap, ps, rest,
+                     rest_cap, rest_count, v, h, f, n_rep, cnt);
   }
   // repair counts: one update per wave
   const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int32_t)wave_incl_sum(n_rep), 63);
@@ -3266,6 +3350,12 @@ template __global__ void k_tip<true>(int32_t, int64_t, const int32_t*, const int
 template __global__ void k_tip<false>(int32_t, int64_t, const int32_t*, const int32_t*, const int32_t*, uint8_t*, uint8_t*, int32_t*,
                                       int64_t, int32_t*, int64_t, PolyState, const int32_t*, int32_t*, int64_t,
                                       Counters*);
+template __global__ void k_tip_long<true>(int32_t, int64_t, const int32_t*, const int32_t*, const int32_t*, uint8_t*,
+                                           uint8_t*, int32_t*, int64_t, int32_t*, int64_t, PolyState, const int32_t*,
+                                           int64_t, const uint32_t*, uint32_t, int32_t*, int64_t, uint32_t*, Counters*);
+template __global__ void k_tip_long<false>(int32_t, int64_t, const int32_t*, const int32_t*, const int32_t*, uint8_t*,
+                                           uint8_t*, int32_t*, int64_t, int32_t*, int64_t, PolyState, const int32_t*,
+                                           int64_t, const uint32_t*, uint32_t, int32_t*, int64_t, uint32_t*, Counters*);
 template __global__ void k_general_big<true, 64, 128, 128, 8>(
     const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*, const int32_t*, uint8_t*, uint8_t*,
     int32_t*, int64_t, int32_t*, int64_t, PolyState, const int32_t*, bool, int64_t, const uint32_t*, uint32_t*,

@@ -36,6 +36,7 @@ struct Counters {
   uint32_t mem_done;      // workgroups of that path that have finished
   uint32_t n_over;        // polygons too large for the one-wave workgroup's LDS
   uint32_t n_gen;         // short polygons the tip path leaves to the region path
+  uint32_t n_lrest;       // long cycles the long-cycle tip path leaves to the region path
   uint32_t n_lepp;        // longest-edge paths left to pointer jumping
   alignas(256) uint32_t n_deferred;  // polygons handled by the general path
   alignas(256) uint32_t n_big;       // polygons longer than the walk cap (one-wave workgroup path)

@@ -491,7 +491,7 @@ class Context:
 
     def profile_read(self) -> dict:
         """{kernel name: (summed ms, launches)} of the recorded launches."""
-        n = 16
+        n = 32
         names = ctypes.create_string_buffer(32 * n)
         ms = (ctypes.c_double * n)()
         cnt = (ctypes.c_int64 * n)()

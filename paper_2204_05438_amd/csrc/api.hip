@@ -53,18 +53,15 @@ __global__ void k_general_huge(const int32_t*, bool, int32_t, int64_t, const int
                                const int32_t*, uint8_t*, uint8_t*, int32_t*, int64_t, int32_t*, int64_t, PolyState,
                                const int32_t*, int64_t, int32_t*, int64_t, int32_t*, int64_t, int32_t, int32_t,
                                Counters*);
+template <bool BATCH>
 __global__ void k_scan_emit(PolyState, uint64_t*, const int32_t*, const int32_t*, int32_t*, int32_t*, int32_t*,
-                            int64_t*, int64_t, int64_t, Counters*);
+                            int64_t*, int64_t, int64_t, Counters*, BatchEmit);
 __global__ void k_validate(int64_t, int64_t, const int32_t*, const int32_t*, const int32_t*, const uint8_t*,
                            Counters*);
-__global__ void k_batch_offsets(int64_t, const int64_t*, const int32_t*, const int32_t*, const int64_t*, int64_t,
-                                int64_t, int64_t*);
+__global__ void k_batch_empty(int64_t, const int64_t*, const int64_t*, const int64_t*, int64_t*, const Counters*);
 __global__ void k_group_rebase(const int32_t*, const int32_t*, int32_t*, int32_t*, int64_t, const int64_t*,
                                const int64_t*);
 __global__ void k_batch_begin(int64_t*);
-__global__ void k_group_finish(int64_t, const int64_t*, const int64_t*, const int32_t*, const int32_t*,
-                               const int32_t*, const int64_t*, const int64_t*, const int64_t*, int64_t*, int32_t*,
-                               int32_t*, int64_t*, int64_t, int64_t, int64_t, Counters*);
 __global__ void k_group_advance(const int64_t*, int64_t*, bool, int64_t, int64_t*, int64_t*, int64_t*, int64_t,
                                 int64_t, const Counters*);
 __global__ void k_batch_close(const int64_t*, int64_t, int64_t*);
@@ -189,13 +186,13 @@ constexpr int64_t kStageChunkHost = 4096; // staging ints a walk wave reserves a
 
 enum KernelId {
   KR_RESET, KR_LONGEST, KR_LABEL, KR_COMPACT, KR_PACK, KR_WALK, KR_GENERAL, KR_BIG, KR_HUGE, KR_SCAN, KR_VALIDATE,
-  KR_BATCH, KR_BIGW, KR_TIP, KR_SEEDS, KR_GENW, KR_GREBASE, KR_GFINISH, KR_LEPP, KR_PREP, KR_TIPL, KR_N
+  KR_BATCH, KR_BIGW, KR_TIP, KR_SEEDS, KR_GENW, KR_GREBASE, KR_LEPP, KR_PREP, KR_TIPL, KR_N
 };
 const char* kKernelNames[KR_N] = {"k_reset",         "k_longest",       "k_label",          "k_compact_seeds",
                                   "k_pack_walk",     "k_walk",          "k_general_small",  "k_general_big",
-                                  "k_general_huge",  "k_scan_emit",     "k_validate",       "k_batch_offsets",
+                                  "k_general_huge",  "k_scan_emit",     "k_validate",       "k_batch",
                                   "k_general_big_wg", "k_tip",           "k_seeds",          "k_general_wave",
-                                  "k_group_rebase",  "k_group_finish",  "k_lepp",           "k_repair_prep",
+                                  "k_group_rebase",  "k_lepp",          "k_repair_prep",
                                   "k_tip_long"};
 
 // Event pair around one kernel launch when profiling is on.
@@ -441,7 +438,8 @@ int run_label(polylla_ctx* c, const polylla_tri* t, uint8_t* he, uint8_t* tri, u
 // Walk + general path + scan + emit over the list `list` of seeds (from_seeds)
 // or start half-edges; n (device) polygons already in cnt->n_seeds.
 int run_build(polylla_ctx* c, const polylla_tri* t, const int32_t* list, bool from_seeds, bool repair,
-              uint8_t* he, uint8_t* vtx, polylla_polys* out, hipStream_t s, const polylla_polys* prep_in = nullptr) {
+              uint8_t* he, uint8_t* vtx, polylla_polys* out, hipStream_t s, const polylla_polys* prep_in = nullptr,
+              const BatchEmit* be = nullptr) {
   const int64_t T = t->n_halfedges / 3;
   const int32_t nhe = (int32_t)t->n_halfedges;
   PolyState ps = poly_state(c);
@@ -582,9 +580,14 @@ int run_build(polylla_ctx* c, const polylla_tri* t, const int32_t* list, bool fr
   {
     Prof p(c, s, KR_SCAN);
     const int64_t ntiles = (T + kScanTileHost - 1) / kScanTileHost + 1;
-    hipLaunchKernelGGL(k_scan_emit, dim3(ntiles), dim3(256), 0, s, ps, c->sc->status + c->sc->n_status_label, c->sc->stage,
-                       c->sc->arena, out->offsets, out->verts, out->start, out->counts, out->cap_polys,
-                       out->cap_verts, c->cnt);
+    if (be)
+      hipLaunchKernelGGL(k_scan_emit<true>, dim3(ntiles), dim3(256), 0, s, ps, c->sc->status + c->sc->n_status_label,
+                         c->sc->stage, c->sc->arena, (int32_t*)nullptr, (int32_t*)nullptr, (int32_t*)nullptr,
+                         (int64_t*)nullptr, (int64_t)0, (int64_t)0, c->cnt, *be);
+    else
+      hipLaunchKernelGGL(k_scan_emit<false>, dim3(ntiles), dim3(256), 0, s, ps, c->sc->status + c->sc->n_status_label,
+                         c->sc->stage, c->sc->arena, out->offsets, out->verts, out->start, out->counts, out->cap_polys,
+                         out->cap_verts, c->cnt, BatchEmit{});
   }
   return launched();
 }
@@ -592,14 +595,14 @@ int run_build(polylla_ctx* c, const polylla_tri* t, const int32_t* list, bool fr
 // Label, build and repair of one mesh (label arrays NULL: context scratch);
 // keep != 0 keeps the error word and batch sums of earlier groups.
 int mesh_run(polylla_ctx* c, const polylla_tri* t, uint8_t* he, uint8_t* tri, uint8_t* vtx, polylla_polys* out,
-             hipStream_t s, int keep) {
+             hipStream_t s, int keep, const BatchEmit* be = nullptr) {
   he = he ? he : c->sc->he_s;
   tri = tri ? tri : c->sc->tri_s;
   vtx = vtx ? vtx : c->sc->vtx_s;
   reset(c, s, nullptr, keep);
   int rc = run_label(c, t, he, tri, vtx, s);
   if (rc) return rc;
-  return run_build(c, t, c->sc->seeds, true, true, he, vtx, out, s);
+  return run_build(c, t, c->sc->seeds, true, true, he, vtx, out, s, nullptr, be);
 }
 
 }  // namespace
@@ -916,24 +919,19 @@ int polylla_mesh_batched(polylla_ctx* c, const polylla_batch* b, polylla_labels*
                          c->g_twin, c->g_origin, nm, b->he_off + m0, b->vtx_off + m0);
     }
     polylla_tri tg{V, H, b->xy + 2 * v0, c->g_twin, nullptr, c->g_origin, b->fixed ? b->fixed + h0 : nullptr};
-    polylla_polys pg{c->g_off, c->g_verts, c->g_start, c->g_counts, H / 3, H};
+    polylla_polys pg{nullptr, nullptr, nullptr, c->g_counts, H / 3, H};
     uint8_t* he = (l && l->he) ? l->he + h0 : nullptr;
     uint8_t* tri = (l && l->tri) ? l->tri + h0 / 3 : nullptr;
     uint8_t* vtx = (l && l->vtx) ? l->vtx + v0 : nullptr;
-    if ((rc = mesh_run(c, &tg, he, tri, vtx, &pg, s, k > 0 ? 1 : 0))) return rc;
+    // the emitter writes the group's polygons into the caller's CSR itself
+    const BatchEmit be{c->sc->seeds, nm, b->he_off + m0, b->vtx_off + m0, c->g_base, out->offsets, out->verts,
+                       out->start, out->poly_off + m0, out->cap_polys, out->cap_verts, c->g_counts};
+    if ((rc = mesh_run(c, &tg, he, tri, vtx, &pg, s, k > 0 ? 1 : 0, &be))) return rc;
     {
       Prof p(c, s, KR_BATCH);
       hipLaunchKernelGGL(k_accumulate, dim3(1), dim3(64), 0, s, c->cnt);
-      hipLaunchKernelGGL(k_batch_offsets, dim3(grid_for(nm + 1, 256, 4096)), dim3(256), 0, s, nm, b->vtx_off + m0,
-                         c->g_off, c->g_verts, c->g_counts, pg.cap_polys, pg.cap_verts, c->g_poly);
-    }
-    {
-      // one block per 2048 output slots of the group (at most 3 per triangle)
-      Prof p(c, s, KR_GFINISH);
-      hipLaunchKernelGGL(k_group_finish, dim3(std::max<int64_t>(H / 2048 + 1, (nm + 255) / 256)), dim3(256), 0, s, nm,
-                         b->he_off + m0, b->vtx_off + m0, c->g_off, c->g_verts, c->g_start, c->g_counts, c->g_poly,
-                         c->g_base, out->offsets, out->verts, out->start, out->poly_off + m0, pg.cap_polys,
-                         out->cap_polys, out->cap_verts, c->cnt);
+      hipLaunchKernelGGL(k_batch_empty, dim3(grid_for(nm, 256, 4096)), dim3(256), 0, s, nm, b->he_off + m0, c->g_base,
+                         c->g_counts, out->poly_off + m0, (const Counters*)c->cnt);
     }
     {
       Prof p(c, s, KR_BATCH);

@@ -2951,30 +2951,56 @@ __global__ __launch_bounds__(1024) void k_general_huge(
 // vertex range of the whole tile with all threads, each output slot finding
 // its polygon by binary search in LDS so that the stores are coalesced.
 // Blocks beyond the tile count exit before taking a ticket.
+// BATCH: the group of a batched call writes the caller's output directly
+// (`be`): int64 offsets after the earlier groups' totals, vertex ids and
+// start half-edges less the base of the polygon's mesh (the mesh of its seed
+// triangle), and the first output polygon of every mesh that has one.
 constexpr int kScanItems = 4;
 constexpr int kScanTile = 256 * kScanItems;
 constexpr int kScanLog = 10;            // log2(kScanTile)
 constexpr int kScanOut = kScanTile + 512;  // output polygons of a tile staged in LDS (else direct stores)
 static_assert((1 << kScanLog) == kScanTile, "binary search depth");
 
+// Mesh of group triangle t among meshes [lo, hi] of a batch group: the last
+// m with he_off[m] - he_off[0] <= 3t.
+__device__ __forceinline__ int64_t mesh_of_tri(const int64_t* __restrict__ he_off, int64_t lo, int64_t hi,
+                                               int64_t t) {
+  const int64_t x = 3 * t + he_off[0];
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (he_off[mid] <= x) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <bool BATCH>
 __global__ __launch_bounds__(256) void k_scan_emit(PolyState ps, uint64_t* status, const int32_t* __restrict__ stage,
                                                    const int32_t* __restrict__ arena, int32_t* __restrict__ offsets,
                                                    int32_t* __restrict__ verts, int32_t* __restrict__ start,
                                                    int64_t* __restrict__ counts, int64_t cap_polys,
-                                                   int64_t cap_verts, Counters* cnt) {
+                                                   int64_t cap_verts, Counters* cnt, BatchEmit be) {
   __shared__ int32_t s_voff[kScanTile + 1];
   __shared__ int32_t s_src[kScanTile];
   __shared__ uint8_t s_rot[kScanTile];
   __shared__ int32_t s_po[kScanOut];  // offsets of the tile's output polygons
   __shared__ int32_t s_ps[kScanOut];  // their start half-edges
+  __shared__ int32_t s_vb[BATCH ? kScanTile : 1];  // vertex base of each polygon's mesh
+  __shared__ int64_t s_mesh[2];                    // meshes of the tile's first and last polygon
   __shared__ int32_t s_ok;
   const uint32_t R = cnt->n_seeds;
   const uint32_t ntiles = (R + kScanTile - 1) / kScanTile;
+  if (BATCH && be.base[2]) return;  // an earlier group failed: nothing more is written
   if (ntiles == 0) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-      counts[0] = 0;
-      counts[1] = 0;
-      offsets[0] = 0;
+      if constexpr (BATCH) {
+        be.counts_g[0] = 0;
+        be.counts_g[1] = 0;
+      } else {
+        counts[0] = 0;
+        counts[1] = 0;
+        offsets[0] = 0;
+      }
     }
     return;
   }
@@ -2990,9 +3016,26 @@ __global__ __launch_bounds__(256) void k_scan_emit(PolyState ps, uint64_t* statu
     a += (uint32_t)(rc[j].y & kPiecesMask);
     b += (uint32_t)rc[j].x;
   }
+
   uint2 total;
+  if (BATCH && threadIdx.x == 0) {
+    // meshes of the tile's first and last polygon (meshes are contiguous in
+    // seed order); published by the scan's barriers
+    const int64_t t0 = (int64_t)tile * kScanTile;
+    const int64_t t1 = min((int64_t)R, t0 + kScanTile) - 1;
+    s_mesh[0] = mesh_of_tri(be.he_off, 0, be.nm - 1, be.seeds[t0]);
+    s_mesh[1] = mesh_of_tri(be.he_off, s_mesh[0], be.nm - 1, be.seeds[t1]);
+  }
   const uint2 pre = block_exclusive_scan<256>(a, b, &total);
   tile_publish(status, tile, total);
+  // BATCH: the mesh of polygon i, its half-edge base, and whether it is the
+  // first polygon of its mesh
+  const int64_t mlo = BATCH ? s_mesh[0] : 0, mhi = BATCH ? s_mesh[1] : 0;
+  const int64_t bh0 = BATCH ? be.he_off[0] : 0, bv0 = BATCH ? be.vtx_off[0] : 0;
+  auto mesh_at = [&](int64_t i) -> int64_t {
+    return mlo == mhi ? mlo : mesh_of_tri(be.he_off, mlo, mhi, be.seeds[i]);
+  };
+  uint32_t first_mask = 0;  // items that start their mesh
   // Tile-local staging before the look-back (so that it overlaps the wait
   // for earlier tiles): per input polygon its first vertex slot, staging
   // offset and rotation; per output polygon its tile-local vertex offset and
@@ -3008,16 +3051,28 @@ __global__ __launch_bounds__(256) void k_scan_emit(PolyState ps, uint64_t* statu
       s_voff[k] = (int32_t)rb;
       s_src[k] = nl > 0 ? rc[j].w : 0;
       s_rot[k] = rot;
+      int32_t hbj = 0;
+      if constexpr (BATCH) {
+        int32_t vbj = 0;
+        if (i < R) {
+          const int64_t m = mesh_at(i);
+          const int64_t hm = be.he_off[m] - bh0;
+          hbj = (int32_t)hm;
+          vbj = (int32_t)(be.vtx_off[m] - bv0);
+          if (i == 0 || 3 * (int64_t)be.seeds[i - 1] < hm) first_mask |= 1u << j;
+        }
+        s_vb[k] = vbj;
+      }
       if (fit && i < R && np > 0) {
         if (np == 1) {
           s_po[ra] = (int32_t)rb;
-          s_ps[ra] = rc[j].z;
+          s_ps[ra] = rc[j].z - hbj;
         } else {
           const int32_t* rec = arena + ps.prec[i];
           int32_t acc = 0;
           for (int32_t q = 0; q < np; ++q) {
             s_po[ra + q] = (int32_t)rb + acc;
-            s_ps[ra + q] = rec[4 * q + 2];
+            s_ps[ra + q] = rec[4 * q + 2] - hbj;
             acc += rec[4 * q + 3];
           }
         }
@@ -3030,20 +3085,46 @@ __global__ __launch_bounds__(256) void k_scan_emit(PolyState ps, uint64_t* statu
   const uint2 ex = tile_lookback(status, tile, total, cnt, true);  // (its barriers publish the staging)
   const int64_t tile_v0 = ex.y, tile_v1 = (int64_t)ex.y + total.y;
   const int64_t tile_p1 = (int64_t)ex.x + total.x;
-  if (threadIdx.x == 0) s_ok = (tile_p1 <= cap_polys && tile_v1 <= cap_verts) ? 1 : 0;
+  // BATCH: positions in the caller's output (after the earlier groups)
+  const int64_t P0 = BATCH ? be.base[0] : 0, S0 = BATCH ? be.base[1] : 0;
+  int64_t* const off64 = be.offsets;
+  int32_t* const vout = BATCH ? be.verts : verts;
+  int32_t* const sout = BATCH ? be.start : start;
+  if (threadIdx.x == 0) {
+    if constexpr (BATCH)
+      s_ok = (P0 + tile_p1 <= be.cap_polys && S0 + tile_v1 <= be.cap_verts && !cnt->error) ? 1 : 0;
+    else
+      s_ok = (tile_p1 <= cap_polys && tile_v1 <= cap_verts) ? 1 : 0;
+  }
   if (tile == ntiles - 1 && threadIdx.x == 0) {
-    counts[0] = tile_p1;
-    counts[1] = tile_v1;
-    if (tile_p1 <= cap_polys) offsets[tile_p1] = (int32_t)tile_v1;
+    if constexpr (BATCH) {
+      be.counts_g[0] = tile_p1;  // (the closing offset: the next group, or the end of the call)
+      be.counts_g[1] = tile_v1;
+    } else {
+      counts[0] = tile_p1;
+      counts[1] = tile_v1;
+      if (tile_p1 <= cap_polys) offsets[tile_p1] = (int32_t)tile_v1;
+    }
   }
   __syncthreads();
   const bool ok = s_ok != 0;
-  if (!ok && threadIdx.x == 0) set_error(cnt, POLYLLA_ECAPACITY);
+  if (!ok && threadIdx.x == 0 && (!BATCH || !cnt->error)) set_error(cnt, POLYLLA_ECAPACITY);
   if (!ok) return;
+  if constexpr (BATCH) {
+    // first output polygon of each mesh whose first polygon is in this tile
+    uint32_t ra = ex.x + pre.x;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+      const int32_t np = rc[j].y & kPiecesMask;
+      if ((first_mask >> j) & 1u) be.poly_off[mesh_at(i0 + j)] = P0 + ra;
+      ra += (uint32_t)np;
+    }
+  }
   if (fit) {
     for (uint32_t k = threadIdx.x; k < total.x; k += 256) {
-      offsets[ex.x + k] = (int32_t)(tile_v0 + s_po[k]);
-      if (start) start[ex.x + k] = s_ps[k];
+      if constexpr (BATCH) off64[P0 + ex.x + k] = S0 + tile_v0 + s_po[k];
+      else offsets[ex.x + k] = (int32_t)(tile_v0 + s_po[k]);
+      if (sout) sout[P0 + ex.x + k] = s_ps[k];
     }
   } else {
     // more output polygons than the LDS staging holds: direct stores
@@ -3052,17 +3133,20 @@ __global__ __launch_bounds__(256) void k_scan_emit(PolyState ps, uint64_t* statu
     for (int j = 0; j < kScanItems; ++j) {
       const int64_t i = i0 + j;
       const int32_t nl = rc[j].x, np = rc[j].y & kPiecesMask;
+      const int32_t hbj = (BATCH && i < R) ? (int32_t)(be.he_off[mesh_at(i)] - bh0) : 0;
       if (i < R && np > 0) {
-        const int32_t vg = (int32_t)(tile_v0 + rb);
+        const int64_t vg = tile_v0 + rb;
         if (np == 1) {
-          offsets[ra] = vg;
-          if (start) start[ra] = rc[j].z;
+          if constexpr (BATCH) off64[P0 + ra] = S0 + vg;
+          else offsets[ra] = (int32_t)vg;
+          if (sout) sout[P0 + ra] = rc[j].z - hbj;
         } else {
           const int32_t* rec = arena + ps.prec[i];
           int32_t acc = 0;
           for (int32_t q = 0; q < np; ++q) {
-            offsets[ra + q] = vg + acc;
-            if (start) start[ra + q] = rec[4 * q + 2];
+            if constexpr (BATCH) off64[P0 + ra + q] = S0 + vg + acc;
+            else offsets[ra + q] = (int32_t)(vg + acc);
+            if (sout) sout[P0 + ra + q] = rec[4 * q + 2] - hbj;
             acc += rec[4 * q + 3];
           }
         }
@@ -3076,7 +3160,7 @@ __global__ __launch_bounds__(256) void k_scan_emit(PolyState ps, uint64_t* statu
   // the searches of the next eight slots run while the staging words of the
   // current ones are being loaded
   const int32_t nv_tile = (int32_t)total.y;
-  auto locate = [&](int32_t k0, int32_t (&src)[8]) {
+  auto locate = [&](int32_t k0, int32_t (&src)[8], int32_t (&vbs)[8]) {
     int lo[8], hi[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
@@ -3099,19 +3183,20 @@ __global__ __launch_bounds__(256) void k_scan_emit(PolyState ps, uint64_t* statu
       int32_t off = k - s_voff[lo[u]] + s_rot[lo[u]];
       off = off >= len ? off - len : off;
       src[u] = k < nv_tile ? s_src[lo[u]] + off : -1;
+      vbs[u] = BATCH ? s_vb[lo[u]] : 0;
     }
   };
-  int32_t src[8], v[8];
+  int32_t src[8], vbs[8], v[8];
   int32_t k0 = threadIdx.x;
-  if (k0 < nv_tile) locate(k0, src);
+  if (k0 < nv_tile) locate(k0, src, vbs);
   while (k0 < nv_tile) {
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = src[u] >= 0 ? stage[src[u]] : 0;
+    for (int u = 0; u < 8; ++u) v[u] = src[u] >= 0 ? stage[src[u]] - vbs[u] : 0;
     const int32_t k1 = k0 + 8 * 256;
-    if (k1 < nv_tile) locate(k1, src);
+    if (k1 < nv_tile) locate(k1, src, vbs);
 #pragma unroll
     for (int u = 0; u < 8; ++u)
-      if (k0 + 256 * u < nv_tile) verts[tile_v0 + k0 + 256 * u] = v[u];
+      if (k0 + 256 * u < nv_tile) vout[S0 + tile_v0 + k0 + 256 * u] = v[u];
     k0 = k1;
   }
 }
@@ -3119,9 +3204,9 @@ __global__ __launch_bounds__(256) void k_scan_emit(PolyState ps, uint64_t* statu
 // ---------------------------------------------------------------------------
 // Batches (CSR of meshes with mesh-local indices). A group of consecutive
 // meshes runs through the single-mesh kernels with indices over the group:
-// k_group_rebase writes the group's twin and origin into scratch, the
-// group's polygons come out in scratch CSR, and k_group_finish writes them
-// into the caller's int64 CSR with the mesh-local ids restored.
+// k_group_rebase writes the group's twin and origin into scratch, and the
+// emitter writes the group's polygons into the caller's int64 CSR with the
+// mesh-local ids restored.
 
 // Mesh of position x: the last m in [0, n) with off[m] <= x (off[0] <= x).
 __device__ __forceinline__ int64_t mesh_of(const int64_t* __restrict__ off, int64_t n, int64_t x) {
@@ -3187,86 +3272,6 @@ __global__ void k_batch_begin(int64_t* __restrict__ base) {
   if (threadIdx.x < 4) base[threadIdx.x] = 0;
 }
 
-// The group's CSR into the caller's at the running offsets, vertex and
-// half-edge ids made local to each polygon's mesh. A block takes 2048
-// consecutive output slots: the offsets of the polygons they belong to go to
-// LDS with each polygon's vertex base (its mesh found by binary search over
-// the group's first-polygon offsets), every slot finds its polygon by binary
-// search in LDS, and slots, offsets and start half-edges are stored
-// coalesced. Blocks beyond the group's vertices only write first-polygon
-// offsets.
-constexpr int kFinTile = 2048;
-
-__device__ __forceinline__ int64_t first_above(const int32_t* __restrict__ a, int64_t n, int64_t x) {
-  int64_t lo = 0, hi = n;  // first index in [0, n) with a[idx] > x (n if none)
-  while (lo < hi) {
-    const int64_t mid = (lo + hi) >> 1;
-    if (a[mid] > x) hi = mid;
-    else lo = mid + 1;
-  }
-  return lo;
-}
-
-__global__ __launch_bounds__(256) void k_group_finish(
-    int64_t nm, const int64_t* __restrict__ he_off, const int64_t* __restrict__ vtx_off,
-    const int32_t* __restrict__ off_g, const int32_t* __restrict__ verts_g, const int32_t* __restrict__ start_g,
-    const int64_t* __restrict__ counts_g, const int64_t* __restrict__ poly_g, const int64_t* __restrict__ base,
-    int64_t* __restrict__ offsets, int32_t* __restrict__ verts, int32_t* __restrict__ start,
-    int64_t* __restrict__ poly_off, int64_t g_cap_polys, int64_t cap_polys, int64_t cap_verts, Counters* cnt) {
-  __shared__ int32_t s_off[kFinTile + 2];
-  __shared__ int32_t s_vb[kFinTile + 1];
-  __shared__ int64_t s_p0;
-  __shared__ int32_t s_np;
-  const int64_t F = counts_g[0], S = counts_g[1];
-  const int64_t P0 = base[0], S0 = base[1];
-  // nothing is written after an error in this or an earlier group (the
-  // group's CSR may then be incomplete) or a capacity failure
-  if (cnt->error || base[2] || F < 0 || F > g_cap_polys || S < 0 || S > 3 * g_cap_polys || poly_g[0] < 0) return;
-  if (P0 + F > cap_polys || S0 + S > cap_verts) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) set_error(cnt, POLYLLA_ECAPACITY);
-    return;
-  }
-  for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < nm; m += (int64_t)gridDim.x * blockDim.x)
-    poly_off[m] = P0 + poly_g[m];
-  const int64_t k0 = (int64_t)blockIdx.x * kFinTile;
-  if (k0 >= S) return;
-  const int64_t k1 = min(S, k0 + kFinTile);
-  if (threadIdx.x == 0) {
-    // polygons [p0, p1) cover slots [k0, k1): p0 is the polygon of slot k0
-    const int64_t p0 = first_above(off_g, F + 1, k0) - 1;
-    const int64_t p1 = first_above(off_g, F + 1, k1 - 1);
-    s_p0 = p0;
-    s_np = (int32_t)(p1 - p0);
-  }
-  __syncthreads();
-  const int64_t p0 = s_p0;
-  const int np = s_np;  // at most kFinTile (every polygon has a vertex)
-  const int64_t h0 = he_off[0], v0 = vtx_off[0];
-  for (int j = threadIdx.x; j <= np; j += 256) {
-    const int64_t p = p0 + j;
-    s_off[j] = off_g[p];
-    if (j < np) {
-      const int64_t m = mesh_of(poly_g, nm, p);
-      s_vb[j] = (int32_t)(vtx_off[m] - v0);
-      // each polygon's offset and start are written by the block of its first slot
-      if (off_g[p] >= k0) {
-        offsets[P0 + p] = S0 + off_g[p];
-        if (start) start[P0 + p] = start_g[p] - (int32_t)(he_off[m] - h0);
-      }
-    }
-  }
-  __syncthreads();
-  for (int64_t k = k0 + threadIdx.x; k < k1; k += 256) {
-    int lo = 0, hi = np;  // last polygon j with s_off[j] <= k
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (s_off[mid] <= k) lo = mid;
-      else hi = mid;
-    }
-    verts[S0 + k] = verts_g[k] - s_vb[lo];
-  }
-}
-
 // After a group: running totals; after the last group, the closing offset,
 // the counts and the end of poly_off.
 __global__ void k_group_advance(const int64_t* __restrict__ counts_g, int64_t* __restrict__ base, bool last,
@@ -3298,42 +3303,32 @@ __global__ __launch_bounds__(256) void k_batch_close(const int64_t* __restrict__
     poly_off[m] = -1;
 }
 
-// First output polygon of every mesh of a group: polygons come in mesh order
-// and each starts at its smallest vertex, which lies in its mesh's vertex
-// range, so the first polygon of mesh m is the first polygon whose first
-// vertex is at least vtx_off[m] - vtx_off[0] (binary search).
-__global__ __launch_bounds__(256) void k_batch_offsets(int64_t n_meshes, const int64_t* __restrict__ vtx_off,
-                                                       const int32_t* __restrict__ offsets,
-                                                       const int32_t* __restrict__ verts,
-                                                       const int64_t* __restrict__ counts, int64_t cap_polys,
-                                                       int64_t cap_verts, int64_t* __restrict__ poly_off) {
-  const int64_t F = counts[0];
-  // after a capacity error the CSR arrays are not filled: report -1
-  const bool ok = F <= cap_polys && counts[1] <= cap_verts;
-  const int64_t vbase = vtx_off[0];
-  for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m <= n_meshes;
-       m += (int64_t)gridDim.x * blockDim.x) {
-    if (!ok) {
-      poly_off[m] = -1;
-      continue;
-    }
-    if (m == n_meshes) {
-      poly_off[m] = F;
-      continue;
-    }
-    const int64_t v0 = vtx_off[m] - vbase;
-    int64_t lo = 0, hi = F;
+// First output polygon of the meshes of a group without triangles (the
+// emitter writes it for the others): that of the next mesh with triangles,
+// or the end of the group's polygons.
+__global__ __launch_bounds__(256) void k_batch_empty(int64_t n_meshes, const int64_t* __restrict__ he_off,
+                                                     const int64_t* __restrict__ base,
+                                                     const int64_t* __restrict__ counts_g,
+                                                     int64_t* __restrict__ poly_off, const Counters* cnt) {
+  if (base[2] || cnt->error) return;  // (the call's end marks every first-polygon offset -1)
+  for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < n_meshes; m += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t h = he_off[m];
+    if (he_off[m + 1] != h) continue;
+    // the first j > m with he_off[j] > h: mesh j - 1 is the next with triangles
+    int64_t lo = m + 1, hi = n_meshes + 1;
     while (lo < hi) {
       const int64_t mid = (lo + hi) >> 1;
-      const int32_t o = offsets[mid];
-      const int64_t first = (o >= 0 && o < cap_verts) ? (int64_t)verts[o] : v0;
-      if (first < v0) lo = mid + 1;
-      else hi = mid;
+      if (he_off[mid] > h) hi = mid;
+      else lo = mid + 1;
     }
-    poly_off[m] = lo;
+    poly_off[m] = lo <= n_meshes ? poly_off[lo - 1] : base[0] + counts_g[0];
   }
 }
 
+template __global__ void k_scan_emit<false>(PolyState, uint64_t*, const int32_t*, const int32_t*, int32_t*, int32_t*,
+                                            int32_t*, int64_t*, int64_t, int64_t, Counters*, BatchEmit);
+template __global__ void k_scan_emit<true>(PolyState, uint64_t*, const int32_t*, const int32_t*, int32_t*, int32_t*,
+                                           int32_t*, int64_t*, int64_t, int64_t, Counters*, BatchEmit);
 template __global__ void k_walk<true>(const int32_t*, int32_t, const int32_t*,
                                       int32_t*, int64_t, PolyState, int32_t*, int64_t, int, Counters*);
 template __global__ void k_general_small<true>(const int32_t*, bool, int32_t, int64_t, const int32_t*,

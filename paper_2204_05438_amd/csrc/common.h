@@ -57,6 +57,23 @@ struct Counters {
 // arena offset of the piece records, read only for polygons of more than one
 // piece. The rotation is the slot of the staged cycle that the output starts
 // at (the walk stages cycles unrotated; the general paths stage them rotated).
+// Output of one group of a batched call, written by the emitter itself: the
+// caller's int64 offsets, mesh-local vertex ids and start half-edges, and the
+// first output polygon of each mesh, after the totals of the earlier groups.
+struct BatchEmit {
+  const int32_t* seeds;   // seed triangle of each polygon record (group indices)
+  int64_t nm;             // meshes of the group
+  const int64_t* he_off;  // their half-edge offsets (at the group's first mesh)
+  const int64_t* vtx_off; // their vertex offsets (at the group's first mesh)
+  const int64_t* base;    // {polygons, vertices, failure} of the earlier groups
+  int64_t* offsets;       // the caller's CSR
+  int32_t* verts;
+  int32_t* start;         // or null
+  int64_t* poly_off;      // first output polygon of each mesh (at the group's first mesh)
+  int64_t cap_polys, cap_verts;
+  int64_t* counts_g;      // the group's {polygons, vertices}
+};
+
 constexpr int kRotShift = 24;
 constexpr int32_t kPiecesMask = (1 << kRotShift) - 1;
 

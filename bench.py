@@ -92,8 +92,9 @@ def kernel_sources_digest() -> str:
 
 
 def measured_traffic(kernel: str, workload: str):
-    """HBM bytes per launch of `kernel` from the committed counter summary,
-    or None when it is missing or was taken on other kernel sources."""
+    """HBM bytes per launch of `kernel` (or, with kernel None, per step) from
+    the committed counter summary, or None when it is missing or was taken on
+    other kernel sources."""
     path = os.path.join(ROOT, "profiles", f"hbm_traffic.{workload}.md")
     try:
         lines = open(path).read().splitlines()
@@ -102,8 +103,10 @@ def measured_traffic(kernel: str, workload: str):
     if f"sources sha256: {kernel_sources_digest()}" not in lines:
         return None
     for ln in lines:
+        if kernel is None and ln.startswith("per-step total MB:"):
+            return int(float(ln.split(":", 1)[1]) * 1e6)
         cells = [c.strip() for c in ln.strip("|").split("|")]
-        if len(cells) == 6 and cells[0].split("<")[0] == kernel:
+        if kernel is not None and len(cells) == 6 and cells[0].split("<")[0] == kernel:
             return int(float(cells[5]) * 1e6)
     return None
 
@@ -282,12 +285,16 @@ def bench_single(args, pool, workload: str):
     dom_us = us[dominant]
     achieved = pb.get(dominant, 0) / (dom_us / 1e6) / 1e9
     step_gbs = pb["step"] / (ms_step / 1e3) / 1e9
+    step_traffic = measured_traffic(None, workload)  # calibrated counter bytes of a whole step
     roofline = {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": measured_traffic(dominant, workload),
                 "avg_launch_us": round(dom_us, 1), "algorithmic_bytes": pb.get(dominant, 0),
                 "whole_step": {"algorithmic_bytes": pb["step"], "achieved": round(step_gbs, 1),
-                               "frac": round(step_gbs / HBM_PEAK_GBS, 4)},
+                               "frac": round(step_gbs / HBM_PEAK_GBS, 4), "traffic_bytes": step_traffic,
+                               "traffic_GBps": None if step_traffic is None else round(step_traffic / (ms_step / 1e3) / 1e9, 1),
+                               "traffic_frac": None if step_traffic is None else
+                               round(step_traffic / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4)},
                 "design_bytes": {"bytes": db.get(dominant, 0),
                                  "achieved": round(db.get(dominant, 0) / (dom_us / 1e6) / 1e9, 1)}}
     kernels = {k: {"us_per_launch": round(v, 1),

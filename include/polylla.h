@@ -347,6 +347,13 @@ int polylla_stats(polylla_ctx *ctx, int64_t *out, int n);
  * the longest-edge kernel (LabelMax): each thread issues the loads of that many
  * triangles before it uses any. */
 #define POLYLLA_PARAM_LONGEST_ITEMS 7
+/* POLYLLA_PARAM_LONG_TIP_MIN (0..2^32-2, default 4096, the one-wave region
+ * workgroups): with more cycles longer than the walk cap than this, the
+ * long-cycle tip path walks each again (up to 32 frontier half-edges) and
+ * finishes those without a repeated vertex or with one tip; with at most this
+ * many, every long cycle gets a one-wave region workgroup at once, which is
+ * sooner. Lower values exercise the long-cycle path (used by tests). */
+#define POLYLLA_PARAM_LONG_TIP_MIN 8
 int polylla_set_param(polylla_ctx *ctx, int param, int64_t value);
 
 /* Per-kernel GPU timing with HIP events, for benchmarks (off by default).

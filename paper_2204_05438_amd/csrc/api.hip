@@ -42,7 +42,7 @@ __global__ void k_tip(int32_t, int64_t, const int32_t*, const int32_t*, const in
 template <bool REPAIR>
 __global__ void k_tip_long(int32_t, int64_t, const int32_t*, const int32_t*, const int32_t*, uint8_t*, uint8_t*,
                            int32_t*, int64_t, int32_t*, int64_t, PolyState, const int32_t*, int64_t, const uint32_t*,
-                           uint32_t, int32_t*, int64_t, uint32_t*, Counters*);
+                           uint32_t, uint32_t, int32_t*, int64_t, uint32_t*, Counters*);
 template <bool REPAIR, int NT, int KC, int LC, int HB>
 __global__ void k_general_big(const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*, const int32_t*,
                               uint8_t*, uint8_t*, int32_t*, int64_t, int32_t*, int64_t, PolyState, const int32_t*,
@@ -155,6 +155,7 @@ struct polylla_ctx {
   int64_t group_he = kGroupHeMax;
   int walk_cap = 24;  // vertices a lane walks before handing a polygon to a workgroup
   int longest_items = 2;  // triangles per thread of k_longest (1, 2 or 4)
+  uint32_t long_tip_min = kBigGrid64;  // long cycles up to which the long-cycle path only copies its list
   uint32_t gen_wave_max = kGenWaveMax;  // declined short polygons up to which each gets a wave
   int32_t lds_max = 4096;               // region size limit of the 1024-thread LDS workgroup
   int32_t mem_max = (int32_t)kMemRegionMax;  // region size limit of the global-memory workgroup
@@ -276,7 +277,7 @@ size_t carve(Scratch& S, uint8_t* base, int64_t T, int64_t V, int walk_grid, int
   S.lane_cap = 3 * T / 32 + 64;
   S.over_cap = T / 32 + 64;
   S.rest_cap = T / 3 + 64;
-  S.lrest_cap = T / 8 + 64;  // cycles of more than 24 frontier half-edges: under 3T / 25
+  S.lrest_cap = T + 64;  // long cycles: at most one per triangle (the walk cap may be as low as 1)
   S.mem_km = std::min<int64_t>(T, mem_km_max);
   take(S.status, S.n_status);
   take(S.lg, T);
@@ -465,7 +466,8 @@ int run_build(polylla_ctx* c, const polylla_tri* t, const int32_t* list, bool fr
   // compute unit.
   hipStream_t sl = s, ss = c->side;
   // long regions: the long-cycle tip path first (cycles of up to 32 frontier
-  // half-edges with no repeated vertex or one tip), one wave per region next
+  // half-edges with no repeated vertex or one tip, when there are more long
+  // cycles than one-wave workgroups), one wave per region next
   // (regions of up to 128 triangles and frontier half-edges), then 1024
   // threads per region for the rest; when there are at most `few` of them,
   // all go to the 1024-thread instance
@@ -473,15 +475,18 @@ int run_build(polylla_ctx* c, const polylla_tri* t, const int32_t* list, bool fr
   {
     Prof p(c, sl, KR_TIPL);
     Counters* k = c->cnt;
+    // up to one long cycle per one-wave workgroup (the default): those
+    // workgroups take them all at once (the long-cycle path only copies the list)
+    const uint32_t tipl_min = c->long_tip_min;
     const int gl = 1536;  // (six workgroups of 24 KB of LDS per compute unit), grid-stride
     if (repair)
       hipLaunchKernelGGL(k_tip_long<true>, dim3(gl), dim3(64), 0, sl, nhe, t->n_vertices, t->twin, t->origin, c->sc->wk,
                          he, vtx, c->sc->stage, c->sc->stage_cap, c->sc->arena, c->sc->arena_cap, ps, c->sc->deferred,
-                         c->sc->cap_t, &k->n_big, few, c->sc->lrest, c->sc->lrest_cap, &k->n_lrest, k);
+                         c->sc->cap_t, &k->n_big, few, tipl_min, c->sc->lrest, c->sc->lrest_cap, &k->n_lrest, k);
     else
       hipLaunchKernelGGL(k_tip_long<false>, dim3(gl), dim3(64), 0, sl, nhe, t->n_vertices, t->twin, t->origin, c->sc->wk,
                          he, vtx, c->sc->stage, c->sc->stage_cap, c->sc->arena, c->sc->arena_cap, ps, c->sc->deferred,
-                         c->sc->cap_t, &k->n_big, few, c->sc->lrest, c->sc->lrest_cap, &k->n_lrest, k);
+                         c->sc->cap_t, &k->n_big, few, tipl_min, c->sc->lrest, c->sc->lrest_cap, &k->n_lrest, k);
   }
   {
     Prof p(c, sl, KR_BIG);
@@ -1052,6 +1057,10 @@ int polylla_set_param(polylla_ctx* c, int param, int64_t value) {
     case POLYLLA_PARAM_LONGEST_ITEMS:
       if (value != 1 && value != 2 && value != 4) return POLYLLA_EINVAL;
       c->longest_items = (int)value;
+      return POLYLLA_OK;
+    case POLYLLA_PARAM_LONG_TIP_MIN:
+      if (value < 0 || value > UINT32_MAX - 1) return POLYLLA_EINVAL;
+      c->long_tip_min = (uint32_t)value;
       return POLYLLA_OK;
     default:
       return POLYLLA_EINVAL;

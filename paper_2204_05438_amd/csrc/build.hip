@@ -1524,7 +1524,10 @@ __global__ __launch_bounds__(128) void k_tip(int32_t nhe, int64_t nv, const int3
 // (staged, or repaired at its one tip); the others (longer, several tips,
 // other repeated vertices) are listed in `rest` for the region kernels. With
 // at most few_max such cycles in all it does nothing: the 1024-thread region
-// kernel then takes them all from the walk's list.
+// kernel then takes them all from the walk's list. With at most pass_max it
+// only copies the list to `rest`: the one-wave region kernel then gives every
+// cycle a wave of its own at once, which is sooner than this path's walk of
+// up to kLongCap dependent steps; it pays when cycles queue for those waves.
 constexpr int kLongCap = 32;
 template <bool REPAIR>
 __global__ __launch_bounds__(64) void k_tip_long(int32_t nhe, int64_t nv, const int32_t* __restrict__ twin,
@@ -1533,7 +1536,7 @@ __global__ __launch_bounds__(64) void k_tip_long(int32_t nhe, int64_t nv, const 
                                                  int32_t* __restrict__ stage, int64_t stage_cap,
                                                  int32_t* __restrict__ arena, int64_t arena_cap, PolyState ps,
                                                  const int32_t* __restrict__ in, int64_t in_cap,
-                                                 const uint32_t* in_count, uint32_t few_max,
+                                                 const uint32_t* in_count, uint32_t few_max, uint32_t pass_max,
                                                  int32_t* __restrict__ rest, int64_t rest_cap, uint32_t* rest_count,
                                                  Counters* cnt) {
   __shared__ int32_t s_v[kLongCap * 64];
@@ -1543,6 +1546,15 @@ __global__ __launch_bounds__(64) void k_tip_long(int32_t nhe, int64_t nv, const 
   const LdsCol v{s_v + lane}, h{s_h + lane}, f{s_f + lane};
   const uint32_t n = (uint32_t)min((int64_t)*in_count, in_cap);
   if (n <= few_max) return;
+  if (n <= pass_max) {
+    for (uint32_t j = blockIdx.x * 64 + lane; j < n && (int64_t)j < rest_cap; j += gridDim.x * 64)
+      rest[j] = in[in_cap - 1 - j];
+    if (blockIdx.x == 0 && lane == 0) {
+      *rest_count = (uint32_t)min((int64_t)n, rest_cap);
+      if ((int64_t)n > rest_cap) set_error(cnt, POLYLLA_EINTERNAL);
+    }
+    return;
+  }
   uint32_t n_rep = 0;
   for (uint32_t j0 = blockIdx.x * 64; j0 < n; j0 += gridDim.x * 64) {
     const uint32_t j = j0 + lane;
@@ -3347,10 +3359,12 @@ template __global__ void k_tip<false>(int32_t, int64_t, const int32_t*, const in
                                       Counters*);
 template __global__ void k_tip_long<true>(int32_t, int64_t, const int32_t*, const int32_t*, const int32_t*, uint8_t*,
                                            uint8_t*, int32_t*, int64_t, int32_t*, int64_t, PolyState, const int32_t*,
-                                           int64_t, const uint32_t*, uint32_t, int32_t*, int64_t, uint32_t*, Counters*);
+                                           int64_t, const uint32_t*, uint32_t, uint32_t, int32_t*, int64_t, uint32_t*,
+                                           Counters*);
 template __global__ void k_tip_long<false>(int32_t, int64_t, const int32_t*, const int32_t*, const int32_t*, uint8_t*,
                                            uint8_t*, int32_t*, int64_t, int32_t*, int64_t, PolyState, const int32_t*,
-                                           int64_t, const uint32_t*, uint32_t, int32_t*, int64_t, uint32_t*, Counters*);
+                                           int64_t, const uint32_t*, uint32_t, uint32_t, int32_t*, int64_t, uint32_t*,
+                                           Counters*);
 template __global__ void k_general_big<true, 64, 128, 128, 8>(
     const int32_t*, bool, int32_t, int64_t, const int32_t*, const int32_t*, const int32_t*, uint8_t*, uint8_t*,
     int32_t*, int64_t, int32_t*, int64_t, PolyState, const int32_t*, bool, int64_t, const uint32_t*, uint32_t*,

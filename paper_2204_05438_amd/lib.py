@@ -25,6 +25,7 @@ PARAM_REGION_LDS_MAX = 4
 PARAM_REGION_MEM_MAX = 5
 PARAM_BATCH_GROUP_HE = 6
 PARAM_LONGEST_ITEMS = 7
+PARAM_LONG_TIP_MIN = 8
 PROFILE_OFF, PROFILE_ALL, PROFILE_WALK = 0, 1, 2
 
 

@@ -123,6 +123,26 @@ def test_cooperative_path(ctx, kind, walk_cap):
             assert r["stats"]["general_big"] > 0
 
 
+@pytest.mark.parametrize("walk_cap", [3, 8, 16, 24])
+@pytest.mark.parametrize("kind", ["uniform", "cluster", "grid", "lattice"])
+def test_long_cycle_tip_path(ctx, kind, walk_cap):
+    """With the long-cycle threshold at 0, every cycle longer than the walk cap
+    (more than 128 of them) is walked again by the long-cycle tip path, which
+    stages or repairs those of up to 32 frontier half-edges and passes the
+    rest to the region kernels; the result is the oracle's."""
+    from paper_2204_05438_amd import lib
+    _say(f"long-cycle tip path {kind} walk_cap {walk_cap}")
+    ctx.set_param(lib.PARAM_LONG_TIP_MIN, 0)
+    try:
+        for seed in range(2):
+            n = {3: 3000, 8: 3000, 16: 8000, 24: 100000}[walk_cap]
+            mesh = random_mesh(1300 + seed, n, kind)
+            r = gpu_mesh(ctx, mesh, walk_cap)
+            assert_same(r, oracle.oracle_on(mesh), FULL)
+    finally:
+        ctx.set_param(lib.PARAM_LONG_TIP_MIN, 4096)
+
+
 @pytest.mark.parametrize("wave_max", [0, 1 << 20])
 @pytest.mark.parametrize("kind", ["uniform", "cluster"])
 def test_declined_short_polygon_paths(ctx, kind, wave_max):

@@ -409,12 +409,14 @@ __global__ __launch_bounds__(256) void k_walk(const int32_t* __restrict__ list, 
           set_error(cnt, POLYLLA_ENOMEM);
           ps.clear(idx);
         } else {
-          ps.set(idx, L, 1 | (minpos << kRotShift), minhe, (int32_t)off);
+          ps.set_stream(idx, L, 1 | (minpos << kRotShift), minhe, (int32_t)off);
         }
       }
       // the staged words of all finished lanes, copied by the whole wave with
       // coalesced stores: word k belongs to the first lane whose inclusive
-      // offset exceeds k (binary search over the 64 offsets by lane shuffles)
+      // offset exceeds k (binary search over the 64 offsets by lane shuffles).
+      // Staged words and records are not read again here: streaming stores,
+      // so that they leave the L2 to the walk words first.
       if (fits) {
         const int col0 = threadIdx.x & ~63;
         for (int32_t k0 = 0; k0 < tot; k0 += 64) {
@@ -426,7 +428,7 @@ __global__ __launch_bounds__(256) void k_walk(const int32_t* __restrict__ list, 
             if (v <= (uint32_t)k) f += step;
           }
           const int32_t start = (int32_t)__shfl(incl - need, f, 64);
-          if (k < tot) stage[sbase + k] = buf[k - start][col0 + f];
+          if (k < tot) __builtin_nontemporal_store(buf[k - start][col0 + f], &stage[sbase + k]);
         }
       }
       sbase += tot;

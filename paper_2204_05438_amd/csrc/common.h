@@ -83,6 +83,13 @@ struct PolyState {
   __device__ __forceinline__ void set(int64_t i, int32_t len, int32_t pieces, int32_t start, int32_t stage) const {
     rec[i] = make_int4(len, pieces, start, stage);
   }
+  // the same with a streaming (non-temporal) store
+  __device__ __forceinline__ void set_stream(int64_t i, int32_t len, int32_t pieces, int32_t start,
+                                             int32_t stage) const {
+    typedef int32_t v4 __attribute__((ext_vector_type(4)));
+    const v4 r = {len, pieces, start, stage};
+    __builtin_nontemporal_store(r, reinterpret_cast<v4*>(rec + i));
+  }
   __device__ __forceinline__ void clear(int64_t i) const { rec[i] = make_int4(0, 0, -1, 0); }
   __device__ __forceinline__ void set_len(int64_t i, int32_t len) const { reinterpret_cast<int32_t*>(rec + i)[0] = len; }
   __device__ __forceinline__ int32_t len(int64_t i) const { return reinterpret_cast<const int32_t*>(rec + i)[0]; }

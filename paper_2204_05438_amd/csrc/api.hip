@@ -273,11 +273,14 @@ size_t carve(Scratch& S, uint8_t* base, int64_t T, int64_t V, int walk_grid, int
   S.arena_cap = std::min<int64_t>(6 * T + arena_tails(g64, g1024), ((int64_t)1 << 31) - 1);
   S.n_status_label = ntiles;
   S.n_status = ntiles + (T + kScanTileHost - 1) / kScanTileHost + 1;
-  S.huge_cap = 3 * T / 32 + 64;
-  S.lane_cap = 3 * T / 32 + 64;
-  S.over_cap = T / 32 + 64;
-  S.rest_cap = T / 3 + 64;
-  S.lrest_cap = T + 64;  // long cycles: at most one per triangle (the walk cap may be as low as 1)
+  // region lists, each sized for the most regions that can reach it on a
+  // valid mesh (a region's cycle holds distinct frontier half-edges, at most
+  // 3T in all, and its triangles are its own):
+  S.huge_cap = 3 * T / 32 + 64;  // beyond the LDS limit (>= 32 triangles or half-edges)
+  S.lane_cap = 3 * T / 32 + 64;  // beyond the global-memory limit (>= 32)
+  S.over_cap = T / 32 + 64;      // beyond 128 triangles or half-edges: under 3T / 128 + T / 128
+  S.rest_cap = 3 * T / 4 + 64;   // declined short cycles: a repeated vertex needs 4 half-edges
+  S.lrest_cap = T + 64;          // long cycles: at most one per triangle (the walk cap may be as low as 1)
   S.mem_km = std::min<int64_t>(T, mem_km_max);
   take(S.status, S.n_status);
   take(S.lg, T);

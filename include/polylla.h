@@ -354,6 +354,11 @@ int polylla_stats(polylla_ctx *ctx, int64_t *out, int n);
  * many, every long cycle gets a one-wave region workgroup at once, which is
  * sooner. Lower values exercise the long-cycle path (used by tests). */
 #define POLYLLA_PARAM_LONG_TIP_MIN 8
+/* POLYLLA_PARAM_EMIT_LDS_MAX (0..1536, default 1536): the most output
+ * polygons of one emitter tile (1024 polygon records) whose offsets and start
+ * half-edges are staged in LDS and stored coalesced; a tile with more writes
+ * them directly. Lower values exercise the direct path (used by tests). */
+#define POLYLLA_PARAM_EMIT_LDS_MAX 9
 int polylla_set_param(polylla_ctx *ctx, int param, int64_t value);
 
 /* Per-kernel GPU timing with HIP events, for benchmarks (off by default).

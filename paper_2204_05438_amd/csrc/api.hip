@@ -55,7 +55,7 @@ __global__ void k_general_huge(const int32_t*, bool, int32_t, int64_t, const int
                                Counters*);
 template <bool BATCH>
 __global__ void k_scan_emit(PolyState, uint64_t*, const int32_t*, const int32_t*, int32_t*, int32_t*, int32_t*,
-                            int64_t*, int64_t, int64_t, Counters*, BatchEmit);
+                            int64_t*, int64_t, int64_t, Counters*, BatchEmit, int32_t);
 __global__ void k_validate(int64_t, int64_t, const int32_t*, const int32_t*, const int32_t*, const uint8_t*,
                            Counters*);
 __global__ void k_batch_empty(int64_t, const int64_t*, const int64_t*, const int64_t*, int64_t*, const Counters*);
@@ -156,6 +156,7 @@ struct polylla_ctx {
   int walk_cap = 24;  // vertices a lane walks before handing a polygon to a workgroup
   int longest_items = 2;  // triangles per thread of k_longest (1, 2 or 4)
   uint32_t long_tip_min = kBigGrid64;  // long cycles up to which the long-cycle path only copies its list
+  int32_t emit_lds_max = 1536;  // output polygons of an emitter tile staged in LDS (its tile + 512)
   uint32_t gen_wave_max = kGenWaveMax;  // declined short polygons up to which each gets a wave
   int32_t lds_max = 4096;               // region size limit of the 1024-thread LDS workgroup
   int32_t mem_max = (int32_t)kMemRegionMax;  // region size limit of the global-memory workgroup
@@ -591,11 +592,11 @@ int run_build(polylla_ctx* c, const polylla_tri* t, const int32_t* list, bool fr
     if (be)
       hipLaunchKernelGGL(k_scan_emit<true>, dim3(ntiles), dim3(256), 0, s, ps, c->sc->status + c->sc->n_status_label,
                          c->sc->stage, c->sc->arena, (int32_t*)nullptr, (int32_t*)nullptr, (int32_t*)nullptr,
-                         (int64_t*)nullptr, (int64_t)0, (int64_t)0, c->cnt, *be);
+                         (int64_t*)nullptr, (int64_t)0, (int64_t)0, c->cnt, *be, c->emit_lds_max);
     else
       hipLaunchKernelGGL(k_scan_emit<false>, dim3(ntiles), dim3(256), 0, s, ps, c->sc->status + c->sc->n_status_label,
                          c->sc->stage, c->sc->arena, out->offsets, out->verts, out->start, out->counts, out->cap_polys,
-                         out->cap_verts, c->cnt, BatchEmit{});
+                         out->cap_verts, c->cnt, BatchEmit{}, c->emit_lds_max);
   }
   return launched();
 }
@@ -1064,6 +1065,10 @@ int polylla_set_param(polylla_ctx* c, int param, int64_t value) {
     case POLYLLA_PARAM_LONG_TIP_MIN:
       if (value < 0 || value > UINT32_MAX - 1) return POLYLLA_EINVAL;
       c->long_tip_min = (uint32_t)value;
+      return POLYLLA_OK;
+    case POLYLLA_PARAM_EMIT_LDS_MAX:
+      if (value < 0 || value > kScanTileHost + 512) return POLYLLA_EINVAL;
+      c->emit_lds_max = (int32_t)value;
       return POLYLLA_OK;
     default:
       return POLYLLA_EINVAL;

@@ -2993,7 +2993,8 @@ __global__ __launch_bounds__(256) void k_scan_emit(PolyState ps, uint64_t* statu
                                                    const int32_t* __restrict__ arena, int32_t* __restrict__ offsets,
                                                    int32_t* __restrict__ verts, int32_t* __restrict__ start,
                                                    int64_t* __restrict__ counts, int64_t cap_polys,
-                                                   int64_t cap_verts, Counters* cnt, BatchEmit be) {
+                                                   int64_t cap_verts, Counters* cnt, BatchEmit be,
+                                                   int32_t out_lds_max) {
   __shared__ int32_t s_voff[kScanTile + 1];
   __shared__ int32_t s_src[kScanTile];
   __shared__ uint8_t s_rot[kScanTile];
@@ -3054,7 +3055,7 @@ __global__ __launch_bounds__(256) void k_scan_emit(PolyState ps, uint64_t* statu
   // for earlier tiles): per input polygon its first vertex slot, staging
   // offset and rotation; per output polygon its tile-local vertex offset and
   // start half-edge.
-  const bool fit = total.x <= (uint32_t)kScanOut;
+  const bool fit = total.x <= (uint32_t)min(kScanOut, max(out_lds_max, 0));
   {
     uint32_t ra = pre.x, rb = pre.y;
 #pragma unroll
@@ -3340,9 +3341,9 @@ __global__ __launch_bounds__(256) void k_batch_empty(int64_t n_meshes, const int
 }
 
 template __global__ void k_scan_emit<false>(PolyState, uint64_t*, const int32_t*, const int32_t*, int32_t*, int32_t*,
-                                            int32_t*, int64_t*, int64_t, int64_t, Counters*, BatchEmit);
+                                            int32_t*, int64_t*, int64_t, int64_t, Counters*, BatchEmit, int32_t);
 template __global__ void k_scan_emit<true>(PolyState, uint64_t*, const int32_t*, const int32_t*, int32_t*, int32_t*,
-                                           int32_t*, int64_t*, int64_t, int64_t, Counters*, BatchEmit);
+                                           int32_t*, int64_t*, int64_t, int64_t, Counters*, BatchEmit, int32_t);
 template __global__ void k_walk<true>(const int32_t*, int32_t, const int32_t*,
                                       int32_t*, int64_t, PolyState, int32_t*, int64_t, int, Counters*);
 template __global__ void k_general_small<true>(const int32_t*, bool, int32_t, int64_t, const int32_t*,

@@ -26,6 +26,7 @@ PARAM_REGION_MEM_MAX = 5
 PARAM_BATCH_GROUP_HE = 6
 PARAM_LONGEST_ITEMS = 7
 PARAM_LONG_TIP_MIN = 8
+PARAM_EMIT_LDS_MAX = 9
 PROFILE_OFF, PROFILE_ALL, PROFILE_WALK = 0, 1, 2
 
 

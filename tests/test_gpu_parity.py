@@ -471,6 +471,33 @@ def test_batched_equals_per_mesh(ctx, walk_cap, lds_max, mem_max, group):
     assert st["seeds"] == sum(oracle.oracle_on(m)["stats"]["seeds"] for m in meshes)
 
 
+@pytest.mark.parametrize("emit_max", [0, 1030])
+def test_emitter_direct_stores(ctx, emit_max):
+    """Emitter tiles with more output polygons than the LDS staging holds
+    write offsets and start half-edges directly: with the limit lowered to
+    0 (every tile) or 1030 (a full tile of 1024 polygon records with more
+    than 6 splits goes direct, the others stay in LDS), single meshes and a
+    batch (int64 CSR, mesh-local ids) still equal the oracle."""
+    from paper_2204_05438_amd import lib
+    _say(f"emitter direct stores emit_max {emit_max}")
+    ctx.set_param(lib.PARAM_EMIT_LDS_MAX, emit_max)
+    try:
+        for k, kind in enumerate(["uniform", "cluster", "lattice"]):
+            mesh = random_mesh(2100 + k, 20000, kind)
+            assert_same(gpu_mesh(ctx, mesh), oracle.oracle_on(mesh), FULL)
+        rng = np.random.default_rng(12)
+        meshes = [random_mesh(2200 + k, int(n), ["uniform", "cluster", "lattice"][k % 3])
+                  for k, n in enumerate(np.rint(10 ** rng.uniform(1.0, 3.8, 24)))]
+        meshes.insert(5, empty_mesh())
+        batch = lib.Batch.from_meshes(meshes)
+        labels = lib.Labels.empty(batch)
+        out = ctx.mesh_batched(batch, labels)
+        ctx.status()
+    finally:
+        ctx.set_param(lib.PARAM_EMIT_LDS_MAX, 1536)
+    check_batch_against_oracle(meshes, out, labels, batch.he_off_host.numpy())
+
+
 def test_batched_recipe_against_oracle(ctx):
     """120 meshes of the batched workload's recipe (uniform points, sizes
     log-uniform, here in [1e3, 2e4]) in one call, each against the oracle."""

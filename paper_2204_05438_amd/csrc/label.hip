@@ -446,13 +446,13 @@ __global__ __launch_bounds__(256) void k_validate(int64_t nhe, int64_t nv, const
   }
 }
 
-#define POLYLLA_LONGEST(K)                                                                                  \
+#define INSTANTIATE_K_LONGEST(K)                                                                            \
   template __global__ void k_longest<K>(int64_t, int64_t, const double*, const int32_t*, const int32_t*, uint8_t*, \
                                         uint8_t*, Counters*);
-POLYLLA_LONGEST(1)
-POLYLLA_LONGEST(2)
-POLYLLA_LONGEST(4)
-#undef POLYLLA_LONGEST
+INSTANTIATE_K_LONGEST(1)
+INSTANTIATE_K_LONGEST(2)
+INSTANTIATE_K_LONGEST(4)
+#undef INSTANTIATE_K_LONGEST
 template __global__ void k_label<true>(int64_t, const int32_t*, const uint8_t*, uint8_t*, uint8_t*, const int32_t*,
                                        int32_t*, uint32_t*, uint32_t*, Counters*, bool, const uint8_t*);
 template __global__ void k_label<false>(int64_t, const int32_t*, const uint8_t*, uint8_t*, uint8_t*, const int32_t*,
